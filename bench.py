@@ -1,0 +1,219 @@
+#!/usr/bin/env python
+"""QAOA MaxCut energy evaluations per second on one GPU.
+
+Workload: random 3-regular graph, N=30 (45 edges, one light-cone network per
+edge), QAOA depth p=4 -- the benchmark shape of Sec. II-E -- with seeded
+angle sets gamma ~ U[0, pi), beta ~ U[0, pi/2).  One step is one full energy
+evaluation: angle upload, every bucket of every light cone, the per-edge
+scalars, the FP64 energy and the read-back of |E|+1 doubles.  The plan
+(light cones, orders, merged groups, memory layout) is built once, before the
+timed region, as a caller sweeping angles would.
+
+Prints one JSON line.  `roofline` reports the dominant kernel class measured
+with HIP events around each of its launches; `cpu_baseline` times the FP64
+CPU oracle on a bounded sample of the same workload.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "QAOA energy evals/s and bucket-contraction HBM GB/s, 3-reg N=30 p=4, 1 MI355X"
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
+FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector
+FP32_PEAK_TFLOPS = 157.3     # MI355X FP32 (matrix / packed vector)
+PAPER_SECONDS_PER_EVAL = 1.4  # Tab. II, NumPy_Merged + CuPy_Merged, V100 + CPU
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_rows(Q, torch, inst, prec, levels, streams, steps, warmup):
+    n, edges = inst["n"], inst["edges"]
+    angles = inst["angles"]
+    net = Q.Network(n, edges, *angles[0], max_levels=levels, n_streams=streams)
+    t0 = time.perf_counter()
+    net.plan(prec)
+    plan_s = time.perf_counter() - t0
+    ws = net.workspace()
+    for i in range(warmup):
+        net.set_angles(*angles[i % len(angles)])
+        net.contract(ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    last = None
+    for i in range(steps):
+        net.set_angles(*angles[(warmup + i) % len(angles)])
+        last = net.contract(ws)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return net, dt, plan_s, last
+
+
+def roofline_of(timing, prec):
+    """Dominant kernel class (most device time) against its bound."""
+    dom = max(("block", "wide"), key=lambda k: timing[k]["ms"])
+    t = timing[dom]
+    sec = t["ms"] / 1e3
+    gbs = t["bytes"] / sec / 1e9 if sec > 0 else 0.0
+    tflops = t["flops"] / sec / 1e12 if sec > 0 else 0.0
+    fpeak = FP64_PEAK_TFLOPS if prec == 0 else FP32_PEAK_TFLOPS
+    hbm_frac, fp_frac = gbs / HBM_PEAK_GBS, tflops / fpeak
+    kernel = f"k_{'wide_group' if dom == 'wide' else 'block_groups'}<{'double2' if prec == 0 else 'float2'}>"
+    common = {"kernel": kernel, "launches": t["launches"],
+              "bytes_per_launch": t["bytes"] / max(1, t["launches"]),
+              "avg_launch_ms": t["ms"] / max(1, t["launches"]),
+              "hbm_gbs": gbs, "hbm_frac": hbm_frac,
+              "fp_tflops": tflops, "fp_frac": fp_frac, "traffic": None}
+    if hbm_frac >= fp_frac:
+        return {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": hbm_frac, **common}
+    return {"bound": "alu", "achieved": tflops, "peak": fpeak, "unit": "TFLOP/s",
+            "frac": fp_frac, **common}
+
+
+def cpu_baseline(inst, seconds):
+    """FP64 oracle on a bounded sample of light cones, scaled by cost."""
+    import oracle
+    n, edges, p = inst["n"], inst["edges"], inst["p"]
+    g, b = inst["angles"][0]
+    m = len(edges)
+    cost = [sum(2.0 ** int(w) for w in oracle.edge_widths(n, edges, k, p) if w)
+            for k in range(m)]
+    total = sum(cost)
+    cheapest = min(range(m), key=lambda k: cost[k])
+    t0 = time.perf_counter()
+    oracle.energy(n, edges, g, b, threads=1, edge_list=[cheapest])
+    rate = cost[cheapest] / max(time.perf_counter() - t0, 1e-6)  # ops/s/thread
+    threads = max(1, min(os.cpu_count() or 1, 16))
+    import qaoa_synth as qs
+    r = qs.Rng(2024)
+    order = list(range(m))
+    for i in range(m - 1, 0, -1):
+        j = r.below(i + 1)
+        order[i], order[j] = order[j], order[i]
+    sample, acc = [], 0.0
+    for k in order:
+        if cost[k] / rate > seconds / 2:
+            continue
+        if acc + cost[k] > seconds * rate * threads and sample:
+            break
+        sample.append(k)
+        acc += cost[k]
+    t0 = time.perf_counter()
+    oracle.energy(n, edges, g, b, threads=threads, edge_list=sample)
+    wall = time.perf_counter() - t0
+    frac = acc / total
+    return {"value": frac / wall, "unit": "evals/s", "cores": threads, "kind": "oracle",
+            "sample": (f"{len(sample)} of {m} light cones ({100 * frac:.2f}% of the "
+                       f"evaluation's sum of 2^width) on {threads} threads in "
+                       f"{wall:.1f} s, scaled to one full evaluation by that cost share")}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--precision", choices=("c128", "c64"), default="c128")
+    ap.add_argument("--levels", type=int, default=8, help="merged indices per group (1 = plain)")
+    ap.add_argument("--streams", type=int, default=4)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--angle-sets", type=int, default=32)
+    ap.add_argument("--variants", type=int, default=1, help="also time the other rows")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(light cones shard across GPUs without communication; only the "
+              "one-GPU share is built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2204_06045_amd as Q
+    import qaoa_synth as qs
+
+    torch.cuda.set_device(0)
+    inst = qs.instance(30, 3, 4, args.seed, args.angle_sets)
+    prec = Q.QTN_C128 if args.precision == "c128" else Q.QTN_C64
+    log(f"main row: {args.precision} levels={args.levels} streams={args.streams}")
+    net, dt, plan_s, last = run_rows(Q, torch, inst, prec, args.levels, args.streams,
+                                     args.steps, args.warmup)
+    evals = args.steps / dt
+    stats = net.stats()
+    log(f"  {evals:.2f} evals/s, plan {plan_s:.2f} s")
+    _, _, timing = net.contract_timed()
+    roof = roofline_of(timing, prec)
+    log(f"  roofline {roof['kernel']}: {roof['hbm_gbs']:.0f} GB/s, "
+        f"{roof['fp_tflops']:.2f} TFLOP/s")
+    net.close()
+
+    variants = {}
+    if args.variants:
+        for name, pr, lv in (("c64_merged", Q.QTN_C64, 8), ("c128_plain", Q.QTN_C128, 1),
+                             ("c64_plain", Q.QTN_C64, 1)):
+            if pr == prec and lv == args.levels:
+                continue
+            log(f"variant {name}")
+            vnet, vdt, _, _ = run_rows(Q, torch, inst, pr, lv, args.streams,
+                                       max(3, args.steps // 4), 2)
+            vst = vnet.stats()
+            variants[name] = {"evals_per_s": max(3, args.steps // 4) / vdt,
+                              "alg_bytes_per_eval": vst["bytes"],
+                              "n_groups": vst["n_groups"]}
+            vnet.close()
+            torch.cuda.empty_cache()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        cpu = cpu_baseline(inst, args.cpu_seconds)
+
+    line = {
+        "metric": METRIC,
+        "value": evals,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * dt / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": evals * PAPER_SECONDS_PER_EVAL,
+        "vs_baseline_note": ("paper Tab. II best: 1.4 s per evaluation (NumPy_Merged + "
+                             "CuPy_Merged, V100 + host CPU, its own graph instance); context"),
+        "dtype": "complex128" if prec == 0 else "complex64",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"QAOA MaxCut energy, random 3-regular N=30 (45 edges), p=4, graph "
+                         f"seed {args.seed}, {args.angle_sets} seeded angle sets"),
+            "precision": args.precision, "max_levels": args.levels,
+            "streams": args.streams, "max_width": stats["max_width"],
+            "buckets": stats["n_buckets"], "groups": stats["n_groups"],
+        },
+        "alg_bytes_per_eval": stats["bytes"],
+        "alg_flops_per_eval": stats["flops"],
+        "eval_hbm_gbs": stats["bytes"] * evals / 1e9,
+        "plan_seconds": plan_s,
+        "roofline": roof,
+        "kernel_timing": timing,
+        "variants": variants,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,189 @@
+/*
+ * qtn.h — C ABI of the MI355X bucket-elimination library for the QAOA MaxCut
+ * energy expectation (arXiv 2204.06045, "Performance Evaluation and
+ * Acceleration of the QTensor Quantum Circuit Simulator on GPUs").
+ *
+ * What it computes (Sec. II-A, Eq. 1 and Eq. 2; Sec. II-B):
+ *   |gamma,beta>_p = prod_{l=1..p} exp(-i beta_l B) exp(-i gamma_l C) |+>^N,
+ *   C = 1/2 sum_{(jk) in E} (1 - Z_j Z_k),  B = sum_i X_i,
+ *   e_jk = <gamma,beta| Z_j Z_k |gamma,beta>,
+ *   E    = <C> = |E|/2 - 1/2 sum_jk e_jk.
+ * Each e_jk is the scalar of one light-cone tensor network (Sec. II-B),
+ * contracted by bucket elimination (Sec. II-B): buckets are taken in the
+ * elimination order, the tensors of a bucket are multiplied over the union of
+ * their binary indices and the bucket index is summed out.  Consecutive
+ * buckets whose index sets nest are merged and summed in one pass (merged
+ * indices, Sec. II-C).
+ *
+ * Conventions for every call:
+ *   - returns QTN_OK (0) or a negative QTN_E* code; qtn_last_error() gives a
+ *     message for the calling thread, valid until its next call;
+ *   - no C++ exception crosses this boundary;
+ *   - on error, caller-owned output buffers are left untouched;
+ *   - arrays passed in are copied; the caller keeps ownership;
+ *   - a qtn_network is owned by the library and released by
+ *     qtn_network_free; calls on one network are not thread-safe.
+ */
+#ifndef QTN_H
+#define QTN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define QTN_OK 0
+#define QTN_EINVAL (-1)  /* bad graph, angle, order or argument            */
+#define QTN_ERANGE (-2)  /* bucket width or memory over the configured cap */
+#define QTN_ENOMEM (-3)  /* workspace too small or host allocation failed  */
+#define QTN_EDEVICE (-4) /* HIP runtime error (message has the HIP string) */
+#define QTN_ESTATE (-5)  /* call order (e.g. contract before plan)        */
+
+/* Arithmetic of the contraction. */
+#define QTN_C128 0 /* complex128 throughout                              */
+#define QTN_C64 1  /* complex64 buckets, FP64 scalars and energy         */
+
+typedef struct qtn_network qtn_network;
+
+/* Tunables; zero fields take the defaults given in brackets. */
+typedef struct qtn_config {
+    int32_t max_levels;  /* bucket indices summed per fused group, 1..8 [8];
+                            1 = plain per-bucket contraction (no merging)   */
+    int32_t small_width; /* groups of union width <= this run inside one
+                            workgroup, many per launch [12]                */
+    int32_t max_width;   /* refuse plans with a bucket wider than this [32] */
+    int32_t n_streams;   /* HIP streams the light cones are spread over [4] */
+    int32_t eager;       /* 1: launch eagerly instead of replaying a
+                            captured HIP graph [0]                          */
+    int32_t reserved[11];
+} qtn_config;
+
+/*
+ * Build the per-edge light-cone networks (Sec. II-B) of graph G for depth p.
+ *   n_vertices  N >= 2
+ *   n_edges     |E| >= 1
+ *   edges       [n_edges][2] vertex ids, 0 <= u,v < N, u != v, no repeats
+ *   gamma,beta  [p] angles in radians, finite (Eq. 2)
+ *   cfg         NULL for defaults
+ *   out         receives the network handle
+ * The light cone of edge (j,k) keeps, at layer l, the mixers on vertices
+ * within graph distance p-l of {j,k} and the cost gates on edges with an
+ * endpoint there; every other gate cancels against its conjugate.
+ * Errors: QTN_EINVAL for a bad graph or angle; QTN_ENOMEM.
+ */
+int qtn_network_build(int32_t n_vertices, int64_t n_edges, const int32_t *edges,
+                      int32_t p, const double *gamma, const double *beta,
+                      const qtn_config *cfg, qtn_network **out);
+
+/* Size of the light cone of one edge: variables, tensors and the width of the
+ * widest bucket under the greedy min-fill order. */
+int qtn_network_info(const qtn_network *net, int64_t edge, int32_t *n_vars,
+                     int32_t *n_tensors, int32_t *width_minfill);
+
+/*
+ * Greedy min-fill elimination order of one light cone (Sec. II-B orders the
+ * buckets; the paper leaves the heuristic open).  Ties go to the fewest
+ * remaining neighbours, then the smallest variable id; variables are numbered
+ * in creation order: starting variables by vertex, then per layer the new
+ * ket variables by vertex, then the bra variables from layer p down to 1.
+ *   order_out  [n_vars] receives a permutation of 0..n_vars-1
+ */
+int qtn_order_minfill(const qtn_network *net, int64_t edge, int32_t *order_out);
+
+/*
+ * Plan the contraction: symbolic bucket elimination, merged-index groups
+ * (Sec. II-C), memory plan and kernel schedule.
+ *   orders     NULL (min-fill for every edge) or [n_edges] pointers, each NULL
+ *              (min-fill) or a permutation of that light cone's variables
+ *   precision  QTN_C128 or QTN_C64
+ *   workspace_bytes_out  device bytes qtn_contract needs
+ * Errors: QTN_EINVAL (order not a permutation), QTN_ERANGE (width over cap).
+ */
+int qtn_plan(qtn_network *net, const int32_t *const *orders, int32_t precision,
+             size_t *workspace_bytes_out);
+
+/* Replace the angles (values only; the plan is kept). */
+int qtn_set_angles(qtn_network *net, const double *gamma, const double *beta);
+
+/*
+ * Contract every light cone on the GPU.
+ *   d_workspace  device memory of at least the planned size, owned by the
+ *                caller, 256-byte aligned, live until this call returns
+ *   hip_stream   hipStream_t to order the work after (NULL = null stream)
+ *   zz_out       [n_edges] Re e_jk
+ *   zz_imag_out  [n_edges] Im e_jk (zero up to rounding) or NULL
+ *   energy_out   <C> = |E|/2 - 1/2 sum Re e_jk, accumulated in FP64
+ * Blocks until the results are on the host.
+ * Errors: QTN_ESTATE (no plan), QTN_ENOMEM (workspace too small),
+ *         QTN_EDEVICE.
+ */
+int qtn_contract(qtn_network *net, void *d_workspace, size_t bytes,
+                 void *hip_stream, double *zz_out, double *zz_imag_out,
+                 double *energy_out);
+
+/*
+ * Contract several planned networks in one batch: all of their light cones
+ * share one workspace and one launch sequence.
+ *   nets         [n] planned networks of one precision
+ *   d_workspace  at least qtn_batch_workspace() bytes
+ *   zz_out       concatenated [sum n_edges] Re e_jk, network by network
+ *   energy_out   [n]
+ */
+int qtn_contract_batch(qtn_network *const *nets, int32_t n, void *d_workspace,
+                       size_t bytes, void *hip_stream, double *zz_out,
+                       double *energy_out);
+
+/* Workspace bytes qtn_contract_batch needs for these networks. */
+int qtn_batch_workspace(qtn_network *const *nets, int32_t n,
+                        size_t *workspace_bytes_out);
+
+/* Per-kernel-class timing of one eager evaluation, for the roofline report. */
+#define QTN_NKERNELS 4
+#define QTN_K_FILL 0   /* gate-table fill from the angles            */
+#define QTN_K_BLOCK 1  /* small groups, many per workgroup            */
+#define QTN_K_WIDE 2   /* one wide group per launch                   */
+#define QTN_K_REDUCE 3 /* per-edge scalars and the energy             */
+typedef struct qtn_timing {
+    double ms[QTN_NKERNELS];        /* summed launch durations (HIP events) */
+    int64_t launches[QTN_NKERNELS]; /* launches per class                 */
+    double bytes[QTN_NKERNELS];     /* algorithmic HBM bytes per class    */
+    double flops[QTN_NKERNELS];     /* complex-arithmetic FLOPs per class */
+} qtn_timing;
+
+/* Like qtn_contract, but eager, with a HIP event pair around every launch on
+ * its own stream; fills *timing.  Slower than qtn_contract by the event
+ * overhead; the kernels are the same. */
+int qtn_contract_timed(qtn_network *net, void *d_workspace, size_t bytes,
+                       void *hip_stream, double *zz_out, double *energy_out,
+                       qtn_timing *timing);
+
+/* Plan statistics. */
+typedef struct qtn_plan_stats {
+    int64_t n_buckets;    /* non-empty buckets over all light cones      */
+    int64_t n_groups;     /* fused groups (= buckets when max_levels 1)  */
+    int64_t n_wide;       /* groups launched one per kernel             */
+    int32_t max_width;    /* widest bucket                               */
+    int32_t width_hist[40]; /* buckets per width                         */
+    double bytes;         /* algorithmic HBM bytes of one evaluation     */
+    double flops;         /* complex-arithmetic FLOPs of one evaluation  */
+    double paper_flops;   /* 8 * sum 2^width (the paper's Sec. II-E count) */
+    size_t workspace;     /* device bytes                                 */
+} qtn_plan_stats;
+
+int qtn_get_plan_stats(const qtn_network *net, qtn_plan_stats *out);
+
+/* Width of each bucket of one light cone in the planned order, indexed by
+ * elimination position (0 for an empty bucket).  widths_out [n_vars]. */
+int qtn_bucket_widths(const qtn_network *net, int64_t edge, int32_t *widths_out);
+
+void qtn_network_free(qtn_network *net);
+
+const char *qtn_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QTN_H */

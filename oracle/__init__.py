@@ -27,8 +27,10 @@ _lib = None
 
 
 def build(extra_flags=(), out=SO):
-    cmd = ["gcc", *CFLAGS, *extra_flags, SRC, "-o", out, "-lm"]
+    tmp = out + ".tmp"
+    cmd = ["gcc", *CFLAGS, *extra_flags, SRC, "-o", tmp, "-lm"]
     subprocess.run(cmd, check=True)
+    os.replace(tmp, out)
     return out
 
 
@@ -45,6 +47,7 @@ def lib():
         L.qtno_lightcone_size.argtypes = [i, i, ip, i, i, i, ip, ip]
         L.qtno_edge_zz.argtypes = [i, i, ip, i, i, dp, dp, i, i, ip, i, dp, dp, ip]
         L.qtno_edge_order.argtypes = [i, i, ip, i, i, i, ip]
+        L.qtno_edge_widths.argtypes = [i, i, ip, i, i, i, ip]
         L.qtno_edge_zz_bruteforce.argtypes = [i, i, ip, i, i, dp, dp, i, dp, dp]
         L.qtno_statevector_zz.argtypes = [i, i, ip, i, dp, dp, dp]
         L.qtno_p1_closed_form.argtypes = [i, i, ip, d, d, dp]
@@ -91,6 +94,15 @@ def edge_order(n, edges, edge_id, p, mode=0):
     n, m, e, ep = _graph(n, edges)
     out, op = _ints(np.zeros(nv))
     _check(lib().qtno_edge_order(n, m, ep, edge_id, p, mode, op))
+    return out
+
+
+def edge_widths(n, edges, edge_id, p, mode=0):
+    """Bucket widths by elimination position (symbolic, no arithmetic)."""
+    nv, _ = lightcone_size(n, edges, edge_id, p, mode)
+    n, m, e, ep = _graph(n, edges)
+    out, op = _ints(np.zeros(nv))
+    _check(lib().qtno_edge_widths(n, m, ep, edge_id, p, mode, op))
     return out
 
 

@@ -605,6 +605,79 @@ int qtno_edge_order(int n, int m, const int *edges, int edge_id, int p,
     return QTNO_OK;
 }
 
+/* Bucket widths of one light cone under the oracle's min-fill order, from the
+ * index sets alone (no arithmetic): widths_out[i] is the width of the bucket
+ * at elimination position i, 0 when empty.  Used to scale timed samples. */
+int qtno_edge_widths(int n, int m, const int *edges, int edge_id, int p,
+                     int mode, int *widths_out)
+{
+    int rc = check_graph(n, m, edges);
+    if (rc)
+        return rc;
+    double *zero = calloc((size_t)(p > 0 ? p : 1), sizeof(double));
+    onet net;
+    rc = build_network(n, m, edges, edge_id, p, zero, zero, mode, &net);
+    free(zero);
+    if (rc)
+        return rc;
+    int nv = net.n_vars;
+    int *ord = malloc(sizeof(int) * (size_t)nv);
+    int *pos = malloc(sizeof(int) * (size_t)nv);
+    minfill_order(&net, ord);
+    for (int i = 0; i < nv; i++)
+        pos[ord[i]] = i;
+    /* index sets as bitmaps over variables, one per live tensor */
+    int words = (nv + 63) / 64, cap = net.n_tensors + nv + 1, cnt = net.n_tensors;
+    uint64_t *sets = calloc((size_t)cap * (size_t)words, sizeof(uint64_t));
+    int *bucket_of = malloc(sizeof(int) * (size_t)cap);
+    for (int t = 0; t < net.n_tensors; t++) {
+        int b = nv;
+        for (int q = 0; q < net.t[t].rank; q++) {
+            int v = net.t[t].idx[q];
+            sets[(size_t)t * words + v / 64] |= (uint64_t)1 << (v % 64);
+            if (pos[v] < b)
+                b = pos[v];
+        }
+        bucket_of[t] = b;
+    }
+    uint64_t *u = malloc(sizeof(uint64_t) * (size_t)words);
+    for (int i = 0; i < nv; i++) {
+        memset(u, 0, sizeof(uint64_t) * (size_t)words);
+        int any = 0;
+        for (int t = 0; t < cnt; t++)
+            if (bucket_of[t] == i) {
+                any = 1;
+                bucket_of[t] = -1;
+                for (int k = 0; k < words; k++)
+                    u[k] |= sets[(size_t)t * words + k];
+            }
+        widths_out[i] = 0;
+        if (!any)
+            continue;
+        int w = 0, b = nv;
+        for (int k = 0; k < words; k++)
+            w += __builtin_popcountll(u[k]);
+        widths_out[i] = w;
+        int v = ord[i];
+        u[v / 64] &= ~((uint64_t)1 << (v % 64));
+        for (int x = 0; x < nv; x++)
+            if ((u[x / 64] >> (x % 64)) & 1u)
+                if (pos[x] < b)
+                    b = pos[x];
+        if (b < nv) {
+            memcpy(&sets[(size_t)cnt * words], u, sizeof(uint64_t) * (size_t)words);
+            bucket_of[cnt++] = b;
+        }
+    }
+    free(u);
+    free(bucket_of);
+    free(sets);
+    free(pos);
+    free(ord);
+    net_free(&net);
+    return QTNO_OK;
+}
+
 /* The same network summed over every assignment of its variables. */
 int qtno_edge_zz_bruteforce(int n, int m, const int *edges, int edge_id, int p,
                             const double *gamma, const double *beta, int mode,

@@ -1,0 +1,113 @@
+"""ctypes marshalling for ``libqtn.so`` (declarations in ``include/qtn.h``).
+
+Only argument conversion lives here; every step of the contraction runs in
+the library's HIP kernels.  torch is imported before the library is loaded so
+that both share one HIP runtime; torch supplies device memory and streams.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # noqa: F401  (loads the HIP runtime the library binds to)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SO = os.path.join(HERE, "libqtn.so")
+
+QTN_OK = 0
+QTN_EINVAL = -1
+QTN_ERANGE = -2
+QTN_ENOMEM = -3
+QTN_EDEVICE = -4
+QTN_ESTATE = -5
+
+QTN_C128 = 0
+QTN_C64 = 1
+
+NKERNELS = 4
+K_FILL, K_BLOCK, K_WIDE, K_REDUCE = range(4)
+KERNEL_NAMES = ("fill", "block", "wide", "reduce")
+
+# every symbol include/qtn.h declares
+EXPORTS = (
+    "qtn_network_build", "qtn_network_info", "qtn_order_minfill", "qtn_plan",
+    "qtn_set_angles", "qtn_contract", "qtn_contract_batch",
+    "qtn_batch_workspace", "qtn_contract_timed", "qtn_get_plan_stats",
+    "qtn_bucket_widths", "qtn_network_free", "qtn_last_error",
+)
+
+
+class qtn_config(ctypes.Structure):
+    _fields_ = [("max_levels", ctypes.c_int32), ("small_width", ctypes.c_int32),
+                ("max_width", ctypes.c_int32), ("n_streams", ctypes.c_int32),
+                ("eager", ctypes.c_int32), ("reserved", ctypes.c_int32 * 11)]
+
+
+class qtn_timing(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * NKERNELS),
+                ("launches", ctypes.c_int64 * NKERNELS),
+                ("bytes", ctypes.c_double * NKERNELS),
+                ("flops", ctypes.c_double * NKERNELS)]
+
+
+class qtn_plan_stats(ctypes.Structure):
+    _fields_ = [("n_buckets", ctypes.c_int64), ("n_groups", ctypes.c_int64),
+                ("n_wide", ctypes.c_int64), ("max_width", ctypes.c_int32),
+                ("width_hist", ctypes.c_int32 * 40), ("bytes", ctypes.c_double),
+                ("flops", ctypes.c_double), ("paper_flops", ctypes.c_double),
+                ("workspace", ctypes.c_size_t)]
+
+
+class QtnError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"qtn error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(SO):
+            raise ImportError(
+                f"{SO} is missing: build it with paper_2204_06045_amd/build.py "
+                "(or __graft_entry__.build()); there is no fallback path")
+        L = ctypes.CDLL(SO)
+        P = ctypes.c_void_p
+        i32, i64 = ctypes.c_int32, ctypes.c_int64
+        pi32 = ctypes.POINTER(ctypes.c_int32)
+        pd = ctypes.POINTER(ctypes.c_double)
+        L.qtn_last_error.restype = ctypes.c_char_p
+        L.qtn_network_build.argtypes = [i32, i64, pi32, i32, pd, pd,
+                                        ctypes.POINTER(qtn_config), ctypes.POINTER(P)]
+        L.qtn_network_info.argtypes = [P, i64, pi32, pi32, pi32]
+        L.qtn_order_minfill.argtypes = [P, i64, pi32]
+        L.qtn_plan.argtypes = [P, ctypes.POINTER(pi32), i32,
+                               ctypes.POINTER(ctypes.c_size_t)]
+        L.qtn_set_angles.argtypes = [P, pd, pd]
+        L.qtn_contract.argtypes = [P, P, ctypes.c_size_t, P, pd, pd, pd]
+        L.qtn_contract_batch.argtypes = [ctypes.POINTER(P), i32, P, ctypes.c_size_t,
+                                         P, pd, pd]
+        L.qtn_batch_workspace.argtypes = [ctypes.POINTER(P), i32,
+                                          ctypes.POINTER(ctypes.c_size_t)]
+        L.qtn_contract_timed.argtypes = [P, P, ctypes.c_size_t, P, pd, pd,
+                                         ctypes.POINTER(qtn_timing)]
+        L.qtn_get_plan_stats.argtypes = [P, ctypes.POINTER(qtn_plan_stats)]
+        L.qtn_bucket_widths.argtypes = [P, i64, pi32]
+        L.qtn_network_free.argtypes = [P]
+        L.qtn_network_free.restype = None
+        for name in EXPORTS:
+            if name not in ("qtn_network_free", "qtn_last_error"):
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def check(rc):
+    if rc != QTN_OK:
+        raise QtnError(rc, lib().qtn_last_error().decode())
+    return rc

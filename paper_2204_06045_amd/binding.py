@@ -1,0 +1,235 @@
+"""Python binding of the C ABI in ``include/qtn.h``, same names, marshalling only.
+
+Arrays are converted with numpy; device workspaces are torch uint8 tensors on
+the current HIP device and streams are torch streams.  Nothing here computes
+any part of the energy: every call goes to ``libqtn.so``.
+"""
+
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _capi
+from ._capi import (QTN_C128, QTN_C64, QtnError, check, lib, qtn_config,
+                    qtn_plan_stats, qtn_timing)
+
+__all__ = [
+    "QTN_C128", "QTN_C64", "QtnError", "qtn_network_build", "qtn_network_info",
+    "qtn_order_minfill", "qtn_plan", "qtn_set_angles", "qtn_contract",
+    "qtn_contract_timed", "qtn_contract_batch", "qtn_batch_workspace",
+    "qtn_get_plan_stats", "qtn_bucket_widths", "qtn_network_free",
+    "qtn_last_error", "Network", "workspace", "stream_handle",
+]
+
+_pi32 = ctypes.POINTER(ctypes.c_int32)
+_pd = ctypes.POINTER(ctypes.c_double)
+
+
+def _i32(x):
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.int32).ravel())
+    return a, a.ctypes.data_as(_pi32)
+
+
+def _f64(x):
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.float64).ravel())
+    return a, a.ctypes.data_as(_pd)
+
+
+def qtn_last_error() -> str:
+    return lib().qtn_last_error().decode()
+
+
+def qtn_network_build(n_vertices, edges, gamma, beta, max_levels=0,
+                      small_width=0, max_width=0, n_streams=0, eager=False):
+    """Returns an opaque handle (int)."""
+    e, ep = _i32(edges)
+    g, gp = _f64(gamma)
+    b, bp = _f64(beta)
+    if len(g) != len(b):
+        raise ValueError("gamma and beta differ in length")
+    cfg = qtn_config(max_levels, small_width, max_width, n_streams, int(eager))
+    h = ctypes.c_void_p()
+    check(lib().qtn_network_build(int(n_vertices), len(e) // 2, ep, len(g), gp,
+                                  bp, ctypes.byref(cfg), ctypes.byref(h)))
+    return h.value
+
+
+def qtn_network_info(net, edge):
+    nv, nt, w = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    check(lib().qtn_network_info(net, edge, ctypes.byref(nv), ctypes.byref(nt),
+                                 ctypes.byref(w)))
+    return nv.value, nt.value, w.value
+
+
+def qtn_order_minfill(net, edge):
+    nv, _, _ = qtn_network_info(net, edge)
+    out, op = _i32(np.zeros(nv))
+    check(lib().qtn_order_minfill(net, edge, op))
+    return out
+
+
+def qtn_plan(net, orders=None, precision=QTN_C128):
+    """orders: None or a list (one entry per edge) of None / permutations."""
+    ws = ctypes.c_size_t()
+    keep = []
+    if orders is None:
+        arr = None
+    else:
+        arr = (_pi32 * len(orders))()
+        for i, o in enumerate(orders):
+            if o is None:
+                arr[i] = _pi32()
+            else:
+                a, ap = _i32(o)
+                keep.append(a)
+                arr[i] = ap
+    check(lib().qtn_plan(net, arr, int(precision), ctypes.byref(ws)))
+    return ws.value
+
+
+def qtn_set_angles(net, gamma, beta):
+    g, gp = _f64(gamma)
+    b, bp = _f64(beta)
+    check(lib().qtn_set_angles(net, gp, bp))
+
+
+def stream_handle(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def workspace(nbytes, device=None):
+    """Caller-owned device workspace (256-byte aligned by the allocator)."""
+    t = torch.empty(max(int(nbytes), 256), dtype=torch.uint8,
+                    device=device or "cuda")
+    if t.data_ptr() % 256:
+        raise RuntimeError("workspace is not 256-byte aligned")
+    return t
+
+
+def qtn_contract(net, n_edges, ws, stream=None):
+    """Returns (zz real [n_edges], zz imag [n_edges], energy)."""
+    zz = np.zeros(n_edges)
+    zi = np.zeros(n_edges)
+    en = ctypes.c_double()
+    check(lib().qtn_contract(net, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                             stream_handle(stream), zz.ctypes.data_as(_pd),
+                             zi.ctypes.data_as(_pd), ctypes.byref(en)))
+    return zz, zi, en.value
+
+
+def qtn_contract_timed(net, n_edges, ws, stream=None):
+    """Returns (zz real, energy, timing dict)."""
+    zz = np.zeros(n_edges)
+    en = ctypes.c_double()
+    t = qtn_timing()
+    check(lib().qtn_contract_timed(net, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                   stream_handle(stream), zz.ctypes.data_as(_pd),
+                                   ctypes.byref(en), ctypes.byref(t)))
+    timing = {name: {"ms": t.ms[k], "launches": int(t.launches[k]),
+                     "bytes": t.bytes[k], "flops": t.flops[k]}
+              for k, name in enumerate(_capi.KERNEL_NAMES)}
+    return zz, en.value, timing
+
+
+def _net_array(nets):
+    arr = (ctypes.c_void_p * len(nets))(*nets)
+    return arr
+
+
+def qtn_batch_workspace(nets):
+    ws = ctypes.c_size_t()
+    check(lib().qtn_batch_workspace(_net_array(nets), len(nets), ctypes.byref(ws)))
+    return ws.value
+
+
+def qtn_contract_batch(nets, total_edges, ws, stream=None):
+    """Returns (zz real concatenated over networks, energies [n])."""
+    zz = np.zeros(total_edges)
+    en = np.zeros(len(nets))
+    check(lib().qtn_contract_batch(_net_array(nets), len(nets),
+                                   ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                   stream_handle(stream), zz.ctypes.data_as(_pd),
+                                   en.ctypes.data_as(_pd)))
+    return zz, en
+
+
+def qtn_get_plan_stats(net):
+    s = qtn_plan_stats()
+    check(lib().qtn_get_plan_stats(net, ctypes.byref(s)))
+    return {"n_buckets": s.n_buckets, "n_groups": s.n_groups, "n_wide": s.n_wide,
+            "max_width": s.max_width, "width_hist": list(s.width_hist),
+            "bytes": s.bytes, "flops": s.flops, "paper_flops": s.paper_flops,
+            "workspace": s.workspace}
+
+
+def qtn_bucket_widths(net, edge):
+    nv, _, _ = qtn_network_info(net, edge)
+    out, op = _i32(np.zeros(nv))
+    check(lib().qtn_bucket_widths(net, edge, op))
+    return out
+
+
+def qtn_network_free(net):
+    lib().qtn_network_free(net)
+
+
+class Network:
+    """Owning wrapper around one qtn_network handle."""
+
+    def __init__(self, n_vertices, edges, gamma, beta, **cfg):
+        self.n = int(n_vertices)
+        self.edges = [tuple(map(int, e)) for e in edges]
+        self.m = len(self.edges)
+        self.p = len(gamma)
+        self.h = qtn_network_build(self.n, self.edges, gamma, beta, **cfg)
+        self.ws_bytes = None
+        self._ws = None
+
+    def info(self, edge):
+        return qtn_network_info(self.h, edge)
+
+    def order_minfill(self, edge):
+        return qtn_order_minfill(self.h, edge)
+
+    def plan(self, precision=QTN_C128, orders=None):
+        self.ws_bytes = qtn_plan(self.h, orders, precision)
+        return self.ws_bytes
+
+    def set_angles(self, gamma, beta):
+        qtn_set_angles(self.h, gamma, beta)
+
+    def workspace(self):
+        if self._ws is None or self._ws.numel() < self.ws_bytes:
+            self._ws = None
+            self._ws = workspace(self.ws_bytes)
+        return self._ws
+
+    def contract(self, ws=None, stream=None):
+        return qtn_contract(self.h, self.m, ws if ws is not None else self.workspace(),
+                            stream)
+
+    def contract_timed(self, ws=None, stream=None):
+        return qtn_contract_timed(self.h, self.m,
+                                  ws if ws is not None else self.workspace(), stream)
+
+    def stats(self):
+        return qtn_get_plan_stats(self.h)
+
+    def bucket_widths(self, edge):
+        return qtn_bucket_widths(self.h, edge)
+
+    def close(self):
+        if self.h:
+            qtn_network_free(self.h)
+            self.h = None
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

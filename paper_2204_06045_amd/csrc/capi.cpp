@@ -1,0 +1,790 @@
+// C ABI (include/qtn.h): network build, planning, schedule and launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "device.hpp"
+#include "kernels.hpp"
+#include "plan.hpp"
+#include "qtn.h"
+
+using namespace qtn;
+
+namespace {
+
+thread_local std::string g_err;
+
+int set_err(int code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+#define QTN_HIP(expr)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return set_err(QTN_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Runs f(i) for i in [0, n) on up to hardware_concurrency threads.
+template <class F>
+void parallel_for(int n, F f) {
+  int nt = (int)std::min<unsigned>(std::max(1u, std::thread::hardware_concurrency()), 32u);
+  nt = std::min(nt, n);
+  if (nt <= 1) {
+    for (int i = 0; i < n; i++) f(i);
+    return;
+  }
+  std::atomic<int> next{0};
+  std::vector<std::thread> th;
+  for (int t = 0; t < nt; t++)
+    th.emplace_back([&] {
+      for (int i = next++; i < n; i = next++) f(i);
+    });
+  for (auto &x : th) x.join();
+}
+
+struct Task {
+  int kind;        // QTN_K_BLOCK: range index; QTN_K_WIDE: group index
+  int index;
+  uint32_t n_units;
+  double bytes, flops;
+};
+
+// Device layout and launch list of one or more planned networks.
+struct Schedule {
+  int prec = 0, elem = 16;
+  std::vector<DevGroup> groups;
+  std::vector<DevOp> ops;
+  std::vector<int2> ranges;  // first n_cones: each cone's leading small groups
+  std::vector<int> csb, ncb;
+  std::vector<FillDesc> fills;
+  std::vector<std::vector<Task>> cone_tasks;  // after the leading small groups
+  int n_cones = 0, n_nets = 0, n_angles = 0;
+  size_t off_res = 0, off_angles = 0, off_desc = 0, off_fills = 0, off_groups = 0,
+         off_ops = 0, off_ranges = 0, off_csb = 0, off_ncb = 0, off_data = 0, total = 0;
+  int64_t scalar_off = 0;
+  std::vector<char> desc_blob;  // bytes [off_desc, off_data)
+  double bytes[QTN_NKERNELS] = {}, flops[QTN_NKERNELS] = {};
+  double init_bytes = 0, init_flops = 0;
+};
+
+// Streams, events, pinned staging and the captured graph of one schedule.
+struct Runtime {
+  int device = -1;
+  hipStream_t main = nullptr;
+  std::vector<hipStream_t> side;
+  hipEvent_t ev_in = nullptr, ev_fork = nullptr;
+  std::vector<hipEvent_t> ev_join;
+  double *pinned = nullptr;
+  size_t pinned_n = 0;
+  void *ws = nullptr;  // workspace holding the uploaded descriptors
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+
+  void release() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    for (auto s : side) (void)hipStreamDestroy(s);
+    side.clear();
+    for (auto e : ev_join) (void)hipEventDestroy(e);
+    ev_join.clear();
+    if (ev_in) (void)hipEventDestroy(ev_in);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (main) (void)hipStreamDestroy(main);
+    if (pinned) (void)hipHostFree(pinned);
+    ev_in = ev_fork = nullptr;
+    main = nullptr;
+    pinned = nullptr;
+    pinned_n = 0;
+    ws = nullptr;
+    device = -1;
+  }
+  ~Runtime() { release(); }
+};
+
+struct Exec {
+  Schedule sched;
+  Runtime rt;
+};
+
+}  // namespace
+
+struct qtn_network {
+  Graph g;
+  int p = 0;
+  std::vector<double> gamma, beta;
+  PlanOptions opt;
+  int n_streams = 4;
+  bool eager = false;
+  std::vector<LightCone> cones;
+  std::vector<std::vector<int>> minfill;
+  std::mutex minfill_lock;
+  bool planned = false;
+  int precision = 0;
+  uint64_t version = 0;
+  std::vector<ConePlan> plans;
+  std::unique_ptr<Exec> exec;
+};
+
+namespace {
+
+std::mutex g_batch_lock;
+std::map<std::vector<std::pair<const qtn_network *, uint64_t>>, std::unique_ptr<Exec>> g_batch;
+
+void drop_batches_with(const qtn_network *net) {
+  std::lock_guard<std::mutex> lk(g_batch_lock);
+  for (auto it = g_batch.begin(); it != g_batch.end();) {
+    bool has = false;
+    for (auto &kv : it->first) has |= kv.first == net;
+    it = has ? g_batch.erase(it) : std::next(it);
+  }
+}
+
+const std::vector<int> &get_minfill(qtn_network *net, int e) {
+  std::lock_guard<std::mutex> lk(net->minfill_lock);
+  if (net->minfill[e].empty()) net->minfill[e] = minfill_order(net->cones[e]);
+  return net->minfill[e];
+}
+
+int64_t gate_offset(const Gate &gt, bool transposed, int p) {
+  const int t = transposed ? 4 : 0;
+  switch (gt.kind) {
+    case kH: return 32LL * p;
+    case kZ: return 32LL * p + 2;
+    case kP: return 32LL * gt.layer + 0 + t;
+    case kPc: return 32LL * gt.layer + 8 + t;
+    case kR: return 32LL * gt.layer + 16 + t;
+    default: return 32LL * gt.layer + 24 + t;
+  }
+}
+
+int build_schedule(qtn_network *const *nets, int n, Schedule *S) {
+  Schedule &s = *S;
+  s = Schedule();
+  s.prec = nets[0]->precision;
+  s.elem = s.prec == kPrecC128 ? 16 : 8;
+  const int64_t align_el = 256 / s.elem;
+  auto al = [&](int64_t x) { return (x + align_el - 1) / align_el * align_el; };
+  int64_t data = 0;
+  int n_scalars = 0;
+  for (int i = 0; i < n; i++) {
+    if (nets[i]->precision != s.prec) return set_err(QTN_EINVAL, "batched networks differ in precision");
+    s.fills.push_back({(int64_t)s.n_angles, data, nets[i]->p, 0});
+    s.n_angles += 2 * nets[i]->p;
+    data += al(gate_table_elems(nets[i]->p));
+    for (auto &pl : nets[i]->plans) n_scalars += pl.n_scalars;
+  }
+  s.scalar_off = data;
+  data += al(n_scalars);
+  int scalar_next = 0;
+  s.ncb.push_back(0);
+  for (int i = 0; i < n; i++) {
+    const qtn_network *net = nets[i];
+    const int64_t table = s.fills[i].table_off;
+    for (size_t c = 0; c < net->plans.size(); c++) {
+      const ConePlan &pl = net->plans[c];
+      const LightCone &lc = net->cones[c];
+      const int64_t arena = data;
+      data += al(pl.arena_elems);
+      s.csb.push_back(scalar_next);
+      std::vector<Task> tasks;
+      int open_begin = -1;
+      double seg_bytes = 0, seg_flops = 0;
+      auto close_segment = [&](int end) {
+        if (open_begin < 0) return;
+        s.ranges.push_back(make_int2(open_begin, end));
+        tasks.push_back({QTN_K_BLOCK, (int)s.ranges.size() - 1, 0, seg_bytes, seg_flops});
+        open_begin = -1;
+        seg_bytes = seg_flops = 0;
+      };
+      for (const Group &G : pl.groups) {
+        DevGroup dg;
+        std::memset(&dg, 0, sizeof dg);
+        dg.out_off = G.out_tensor >= 0 ? arena + pl.tensors[G.out_tensor].offset
+                                        : s.scalar_off + scalar_next + G.scalar_slot;
+        dg.op_begin = (int32_t)s.ops.size();
+        dg.w = (uint8_t)G.w;
+        dg.L = (uint8_t)G.L;
+        dg.n_ops = (uint8_t)G.ops.size();
+        dg.n_units = G.w > kRegBits + kLaneBits ? 1u << (G.w - kRegBits - kLaneBits) : 1u;
+        if (G.ops.size() > 255) return set_err(QTN_ERANGE, "bucket with more than 255 tensors");
+        double in_el = 0;
+        std::vector<int> per_level(G.L, 0);
+        for (const Operand &o : G.ops) {
+          const Tensor &t = pl.tensors[o.tensor];
+          DevOp d;
+          std::memset(&d, 0, sizeof d);
+          d.off = t.gate >= 0 ? table + gate_offset(lc.gates[t.gate], t.transposed, net->p)
+                              : arena + t.offset;
+          d.mask = o.mask;
+          d.level = (uint8_t)o.level;
+          d.nruns = (uint8_t)mask_runs(o.mask, d.rs, d.rl, d.rd);
+          s.ops.push_back(d);
+          per_level[o.level]++;
+          in_el += std::ldexp(1.0, (int)t.vars.size());
+        }
+        int cum = 0;
+        for (int l = 0; l < kMaxLevels; l++) {
+          if (l < G.L) cum += per_level[l];
+          dg.level_end[l] = (uint8_t)cum;
+        }
+        double gb = s.elem * (in_el + std::ldexp(1.0, G.w - G.L)), gf = 0;
+        for (int l = 0; l < G.L; l++) {
+          int factors = per_level[l] + (l > 0 ? 1 : 0);
+          gf += std::ldexp(1.0, G.w - l) * 6.0 * std::max(0, factors - 1) +
+                std::ldexp(1.0, G.w - l - 1) * 2.0;
+        }
+        const int gid = (int)s.groups.size();
+        s.groups.push_back(dg);
+        if (G.small) {
+          if (open_begin < 0) open_begin = gid;
+          seg_bytes += gb;
+          seg_flops += gf;
+        } else {
+          close_segment(gid);
+          tasks.push_back({QTN_K_WIDE, gid, dg.n_units, gb, gf});
+        }
+      }
+      close_segment((int)s.groups.size());
+      scalar_next += pl.n_scalars;
+      s.cone_tasks.push_back(std::move(tasks));
+      s.n_cones++;
+    }
+    s.ncb.push_back(s.n_cones);
+  }
+  s.csb.push_back(scalar_next);
+  // the first n_cones ranges are the leading small segments (possibly empty)
+  std::vector<int2> lead(s.n_cones, make_int2(0, 0));
+  for (int c = 0; c < s.n_cones; c++) {
+    auto &tk = s.cone_tasks[c];
+    if (!tk.empty() && tk[0].kind == QTN_K_BLOCK) {
+      lead[c] = s.ranges[tk[0].index];
+      s.init_bytes += tk[0].bytes;
+      s.init_flops += tk[0].flops;
+      tk.erase(tk.begin());
+    }
+  }
+  for (auto &tk : s.cone_tasks)
+    for (auto &t : tk)
+      if (t.kind == QTN_K_BLOCK) t.index += s.n_cones;
+  s.ranges.insert(s.ranges.begin(), lead.begin(), lead.end());
+  s.n_nets = n;
+  s.bytes[QTN_K_BLOCK] = s.init_bytes;
+  s.flops[QTN_K_BLOCK] = s.init_flops;
+  for (auto &tk : s.cone_tasks)
+    for (auto &t : tk) {
+      s.bytes[t.kind] += t.bytes;
+      s.flops[t.kind] += t.flops;
+    }
+
+  // workspace layout (bytes)
+  s.off_res = 0;
+  s.off_angles = align_up(8 * (size_t)(2 * s.n_cones + s.n_nets), 256);
+  s.off_desc = align_up(s.off_angles + 8 * (size_t)s.n_angles, 256);
+  s.off_fills = s.off_desc;
+  s.off_groups = align_up(s.off_fills + sizeof(FillDesc) * s.fills.size(), 256);
+  s.off_ops = align_up(s.off_groups + sizeof(DevGroup) * s.groups.size(), 256);
+  s.off_ranges = align_up(s.off_ops + sizeof(DevOp) * s.ops.size(), 256);
+  s.off_csb = align_up(s.off_ranges + sizeof(int2) * s.ranges.size(), 256);
+  s.off_ncb = align_up(s.off_csb + sizeof(int) * s.csb.size(), 256);
+  s.off_data = align_up(s.off_ncb + sizeof(int) * s.ncb.size(), 256);
+  s.total = s.off_data + (size_t)data * s.elem;
+  s.desc_blob.assign(s.off_data - s.off_desc, 0);
+  auto put = [&](size_t off, const void *src, size_t bytes) {
+    if (bytes) std::memcpy(s.desc_blob.data() + (off - s.off_desc), src, bytes);
+  };
+  put(s.off_fills, s.fills.data(), sizeof(FillDesc) * s.fills.size());
+  put(s.off_groups, s.groups.data(), sizeof(DevGroup) * s.groups.size());
+  put(s.off_ops, s.ops.data(), sizeof(DevOp) * s.ops.size());
+  put(s.off_ranges, s.ranges.data(), sizeof(int2) * s.ranges.size());
+  put(s.off_csb, s.csb.data(), sizeof(int) * s.csb.size());
+  put(s.off_ncb, s.ncb.data(), sizeof(int) * s.ncb.size());
+  return QTN_OK;
+}
+
+int ensure_runtime(Runtime &rt, int n_streams, int n_res) {
+  int dev = 0;
+  QTN_HIP(hipGetDevice(&dev));
+  if (rt.device >= 0 && rt.device != dev) rt.release();
+  if (rt.device < 0) {
+    rt.device = dev;
+    QTN_HIP(hipStreamCreateWithFlags(&rt.main, hipStreamNonBlocking));
+    for (int i = 0; i < n_streams; i++) {
+      hipStream_t s;
+      QTN_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+      rt.side.push_back(s);
+      hipEvent_t e;
+      QTN_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      rt.ev_join.push_back(e);
+    }
+    QTN_HIP(hipEventCreateWithFlags(&rt.ev_in, hipEventDisableTiming));
+    QTN_HIP(hipEventCreateWithFlags(&rt.ev_fork, hipEventDisableTiming));
+  }
+  if (rt.pinned_n < (size_t)n_res) {
+    if (rt.pinned) QTN_HIP(hipHostFree(rt.pinned));
+    rt.pinned = nullptr;
+    QTN_HIP(hipHostMalloc((void **)&rt.pinned, sizeof(double) * n_res, hipHostMallocDefault));
+    rt.pinned_n = n_res;
+  }
+  return QTN_OK;
+}
+
+struct Timer {
+  bool on = false;
+  struct Rec {
+    int kind;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  int begin(int kind, hipStream_t s) {
+    if (!on) return QTN_OK;
+    Rec r{kind, nullptr, nullptr};
+    QTN_HIP(hipEventCreate(&r.a));
+    QTN_HIP(hipEventCreate(&r.b));
+    QTN_HIP(hipEventRecord(r.a, s));
+    recs.push_back(r);
+    return QTN_OK;
+  }
+  int end(hipStream_t s) {
+    if (!on) return QTN_OK;
+    QTN_HIP(hipEventRecord(recs.back().b, s));
+    return QTN_OK;
+  }
+  ~Timer() {
+    for (auto &r : recs) {
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+  }
+};
+
+// Every launch of one evaluation, on rt.main and the side streams.
+int enqueue(Exec &X, Timer &tm) {
+  Schedule &s = X.sched;
+  Runtime &rt = X.rt;
+  char *ws = (char *)rt.ws;
+  void *data = ws + s.off_data;
+  auto *groups = (const DevGroup *)(ws + s.off_groups);
+  auto *ops = (const DevOp *)(ws + s.off_ops);
+  auto *ranges = (const int2 *)(ws + s.off_ranges);
+  int rc;
+  if ((rc = tm.begin(QTN_K_FILL, rt.main))) return rc;
+  QTN_HIP(launch_fill(s.prec, data, (const double *)(ws + s.off_angles),
+                      (const FillDesc *)(ws + s.off_fills), s.n_nets, rt.main));
+  if ((rc = tm.end(rt.main))) return rc;
+  if ((rc = tm.begin(QTN_K_BLOCK, rt.main))) return rc;
+  QTN_HIP(launch_block_groups(s.prec, data, groups, ops, ranges, 0, s.n_cones, rt.main));
+  if ((rc = tm.end(rt.main))) return rc;
+  const int K = (int)rt.side.size();
+  bool any = false;
+  for (auto &tk : s.cone_tasks) any |= !tk.empty();
+  if (any) {
+    QTN_HIP(hipEventRecord(rt.ev_fork, rt.main));
+    for (int i = 0; i < K; i++) QTN_HIP(hipStreamWaitEvent(rt.side[i], rt.ev_fork, 0));
+    // heaviest light cones first, dealt round-robin over the side streams
+    std::vector<int> order(s.n_cones);
+    std::vector<double> cost(s.n_cones, 0);
+    for (int c = 0; c < s.n_cones; c++) {
+      order[c] = c;
+      for (auto &t : s.cone_tasks[c]) cost[c] += t.bytes;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    std::vector<double> load(K, 0);
+    for (int c : order) {
+      if (s.cone_tasks[c].empty()) continue;
+      int st = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      load[st] += cost[c];
+      hipStream_t hs = rt.side[st];
+      for (auto &t : s.cone_tasks[c]) {
+        if ((rc = tm.begin(t.kind, hs))) return rc;
+        if (t.kind == QTN_K_BLOCK)
+          QTN_HIP(launch_block_groups(s.prec, data, groups, ops, ranges, t.index, 1, hs));
+        else
+          QTN_HIP(launch_wide_group(s.prec, data, groups, ops, t.index, t.n_units, hs));
+        if ((rc = tm.end(hs))) return rc;
+      }
+    }
+    for (int i = 0; i < K; i++) {
+      QTN_HIP(hipEventRecord(rt.ev_join[i], rt.side[i]));
+      QTN_HIP(hipStreamWaitEvent(rt.main, rt.ev_join[i], 0));
+    }
+  }
+  if ((rc = tm.begin(QTN_K_REDUCE, rt.main))) return rc;
+  QTN_HIP(launch_reduce(s.prec, data, s.scalar_off, (const int *)(ws + s.off_csb),
+                        (const int *)(ws + s.off_ncb), s.n_cones, s.n_nets,
+                        (double *)(ws + s.off_res), rt.main));
+  if ((rc = tm.end(rt.main))) return rc;
+  return QTN_OK;
+}
+
+// Upload descriptors (once per workspace), angles, run, read back.
+int run_exec(Exec &X, const std::vector<const qtn_network *> &nets, void *ws, size_t bytes,
+             void *stream, int n_streams, bool eager, Timer &tm, std::vector<double> &res) {
+  Schedule &s = X.sched;
+  Runtime &rt = X.rt;
+  if (!ws) return set_err(QTN_EINVAL, "workspace is NULL");
+  if (bytes < s.total)
+    return set_err(QTN_ENOMEM, "workspace of " + std::to_string(bytes) + " bytes, plan needs " +
+                                   std::to_string(s.total));
+  if ((uintptr_t)ws % 256) return set_err(QTN_EINVAL, "workspace must be 256-byte aligned");
+  const int n_res = 2 * s.n_cones + s.n_nets;
+  int rc = ensure_runtime(rt, n_streams, std::max(n_res, s.n_angles));
+  if (rc) return rc;
+  QTN_HIP(hipEventRecord(rt.ev_in, (hipStream_t)stream));
+  QTN_HIP(hipStreamWaitEvent(rt.main, rt.ev_in, 0));
+  if (rt.ws != ws) {
+    if (rt.exec) {
+      (void)hipGraphExecDestroy(rt.exec);
+      (void)hipGraphDestroy(rt.graph);
+      rt.exec = nullptr;
+      rt.graph = nullptr;
+    }
+    QTN_HIP(hipMemcpyAsync((char *)ws + s.off_desc, s.desc_blob.data(), s.desc_blob.size(),
+                           hipMemcpyHostToDevice, rt.main));
+    QTN_HIP(hipStreamSynchronize(rt.main));
+    rt.ws = ws;
+  }
+  size_t a = 0;
+  for (auto *net : nets) {
+    for (int l = 0; l < net->p; l++) rt.pinned[a + l] = net->gamma[l];
+    for (int l = 0; l < net->p; l++) rt.pinned[a + net->p + l] = net->beta[l];
+    a += 2 * net->p;
+  }
+  QTN_HIP(hipMemcpyAsync((char *)ws + s.off_angles, rt.pinned, sizeof(double) * s.n_angles,
+                         hipMemcpyHostToDevice, rt.main));
+  if (eager || tm.on) {
+    if ((rc = enqueue(X, tm))) return rc;
+  } else {
+    if (!rt.exec) {
+      QTN_HIP(hipStreamBeginCapture(rt.main, hipStreamCaptureModeThreadLocal));
+      rc = enqueue(X, tm);
+      hipGraph_t graph = nullptr;
+      hipError_t ce = hipStreamEndCapture(rt.main, &graph);
+      if (rc) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+      }
+      if (ce != hipSuccess)
+        return set_err(QTN_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(ce));
+      rt.graph = graph;
+      QTN_HIP(hipGraphInstantiate(&rt.exec, rt.graph, nullptr, nullptr, 0));
+    }
+    QTN_HIP(hipGraphLaunch(rt.exec, rt.main));
+  }
+  QTN_HIP(hipMemcpyAsync(rt.pinned, (char *)ws + s.off_res, sizeof(double) * n_res,
+                         hipMemcpyDeviceToHost, rt.main));
+  QTN_HIP(hipStreamSynchronize(rt.main));
+  res.assign(rt.pinned, rt.pinned + n_res);
+  return QTN_OK;
+}
+
+bool finite_angles(int p, const double *g, const double *b) {
+  for (int l = 0; l < p; l++)
+    if (!std::isfinite(g[l]) || !std::isfinite(b[l])) return false;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *qtn_last_error(void) { return g_err.c_str(); }
+
+int qtn_network_build(int32_t n_vertices, int64_t n_edges, const int32_t *edges, int32_t p,
+                      const double *gamma, const double *beta, const qtn_config *cfg,
+                      qtn_network **out) {
+  try {
+    if (!out) return set_err(QTN_EINVAL, "out is NULL");
+    if (p < 1 || p > 64) return set_err(QTN_EINVAL, "p must be in 1..64");
+    if (!gamma || !beta) return set_err(QTN_EINVAL, "angles are NULL");
+    if (!finite_angles(p, gamma, beta)) return set_err(QTN_EINVAL, "angles must be finite");
+    std::unique_ptr<qtn_network> net(new qtn_network());
+    std::string err = make_graph(n_vertices, n_edges, edges, &net->g);
+    if (!err.empty()) return set_err(QTN_EINVAL, err);
+    net->p = p;
+    net->gamma.assign(gamma, gamma + p);
+    net->beta.assign(beta, beta + p);
+    if (cfg) {
+      if (cfg->max_levels < 0 || cfg->max_levels > kMaxLevels)
+        return set_err(QTN_EINVAL, "max_levels must be in 0..8");
+      if (cfg->max_levels) net->opt.max_levels = cfg->max_levels;
+      if (cfg->small_width < 0 || cfg->small_width > kMaxWidth)
+        return set_err(QTN_EINVAL, "small_width must be in 0..32");
+      if (cfg->small_width) net->opt.small_width = cfg->small_width;
+      if (cfg->max_width < 0 || cfg->max_width > kMaxWidth)
+        return set_err(QTN_EINVAL, "max_width must be in 0..32");
+      if (cfg->max_width) net->opt.max_width = cfg->max_width;
+      if (cfg->n_streams < 0 || cfg->n_streams > 16)
+        return set_err(QTN_EINVAL, "n_streams must be in 0..16");
+      if (cfg->n_streams) net->n_streams = cfg->n_streams;
+      net->eager = cfg->eager != 0;
+    }
+    const int m = (int)n_edges;
+    net->cones.resize(m);
+    net->minfill.resize(m);
+    qtn_network *raw = net.get();
+    parallel_for(m, [&](int e) { raw->cones[e] = build_lightcone(raw->g, e, p); });
+    *out = net.release();
+    return QTN_OK;
+  } catch (const std::bad_alloc &) {
+    return set_err(QTN_ENOMEM, "host allocation failed");
+  } catch (const std::exception &e) {
+    return set_err(QTN_EINVAL, e.what());
+  }
+}
+
+int qtn_network_info(const qtn_network *cnet, int64_t edge, int32_t *n_vars, int32_t *n_tensors,
+                     int32_t *width_minfill) {
+  try {
+    auto *net = const_cast<qtn_network *>(cnet);
+    if (!net) return set_err(QTN_EINVAL, "network is NULL");
+    if (edge < 0 || edge >= (int64_t)net->cones.size())
+      return set_err(QTN_EINVAL, "edge out of range");
+    const LightCone &lc = net->cones[edge];
+    int32_t w = 0;
+    if (width_minfill) {
+      PlanOptions o = net->opt;
+      o.max_levels = 1;
+      o.max_width = 64;
+      ConePlan pl;
+      std::string err = plan_cone(lc, get_minfill(net, (int)edge), o, &pl);
+      if (!err.empty()) return set_err(QTN_EINVAL, err);
+      w = pl.max_width;
+    }
+    if (n_vars) *n_vars = lc.n_vars;
+    if (n_tensors) *n_tensors = (int32_t)lc.gates.size();
+    if (width_minfill) *width_minfill = w;
+    return QTN_OK;
+  } catch (const std::bad_alloc &) {
+    return set_err(QTN_ENOMEM, "host allocation failed");
+  }
+}
+
+int qtn_order_minfill(const qtn_network *cnet, int64_t edge, int32_t *order_out) {
+  try {
+    auto *net = const_cast<qtn_network *>(cnet);
+    if (!net || !order_out) return set_err(QTN_EINVAL, "NULL argument");
+    if (edge < 0 || edge >= (int64_t)net->cones.size())
+      return set_err(QTN_EINVAL, "edge out of range");
+    const auto &o = get_minfill(net, (int)edge);
+    std::copy(o.begin(), o.end(), order_out);
+    return QTN_OK;
+  } catch (const std::bad_alloc &) {
+    return set_err(QTN_ENOMEM, "host allocation failed");
+  }
+}
+
+int qtn_plan(qtn_network *net, const int32_t *const *orders, int32_t precision,
+             size_t *workspace_bytes_out) {
+  try {
+    if (!net) return set_err(QTN_EINVAL, "network is NULL");
+    if (precision != QTN_C128 && precision != QTN_C64)
+      return set_err(QTN_EINVAL, "precision must be QTN_C128 or QTN_C64");
+    const int m = (int)net->cones.size();
+    std::vector<ConePlan> plans(m);
+    std::vector<std::string> errs(m);
+    PlanOptions o = net->opt;
+    o.elem_bytes = precision == QTN_C128 ? 16 : 8;
+    parallel_for(m, [&](int e) {
+      std::vector<int> ord;
+      if (orders && orders[e])
+        ord.assign(orders[e], orders[e] + net->cones[e].n_vars);
+      else
+        ord = get_minfill(net, e);
+      errs[e] = plan_cone(net->cones[e], ord, o, &plans[e]);
+    });
+    for (int e = 0; e < m; e++)
+      if (!errs[e].empty()) {
+        bool range = errs[e].find("exceeds") != std::string::npos;
+        return set_err(range ? QTN_ERANGE : QTN_EINVAL, "edge " + std::to_string(e) + ": " + errs[e]);
+      }
+    auto ex = std::make_unique<Exec>();
+    net->plans.swap(plans);
+    net->precision = precision;
+    qtn_network *one[1] = {net};
+    int rc = build_schedule(one, 1, &ex->sched);
+    if (rc) {
+      net->plans.clear();
+      net->planned = false;
+      return rc;
+    }
+    drop_batches_with(net);
+    net->exec = std::move(ex);
+    net->planned = true;
+    net->version++;
+    if (workspace_bytes_out) *workspace_bytes_out = net->exec->sched.total;
+    return QTN_OK;
+  } catch (const std::bad_alloc &) {
+    return set_err(QTN_ENOMEM, "host allocation failed");
+  }
+}
+
+int qtn_set_angles(qtn_network *net, const double *gamma, const double *beta) {
+  if (!net || !gamma || !beta) return set_err(QTN_EINVAL, "NULL argument");
+  if (!finite_angles(net->p, gamma, beta)) return set_err(QTN_EINVAL, "angles must be finite");
+  net->gamma.assign(gamma, gamma + net->p);
+  net->beta.assign(beta, beta + net->p);
+  return QTN_OK;
+}
+
+static int contract_impl(qtn_network *net, void *ws, size_t bytes, void *stream, double *zz,
+                         double *zz_im, double *energy, qtn_timing *timing) {
+  try {
+    if (!net) return set_err(QTN_EINVAL, "network is NULL");
+    if (!net->planned) return set_err(QTN_ESTATE, "qtn_plan has not been called");
+    Timer tm;
+    tm.on = timing != nullptr;
+    std::vector<double> res;
+    int rc = run_exec(*net->exec, {net}, ws, bytes, stream, net->n_streams, net->eager, tm, res);
+    if (rc) return rc;
+    qtn_timing t;
+    std::memset(&t, 0, sizeof t);
+    if (timing) {
+      for (auto &r : tm.recs) {
+        float ms = 0;
+        QTN_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+        t.ms[r.kind] += ms;
+        t.launches[r.kind]++;
+      }
+      for (int k = 0; k < QTN_NKERNELS; k++) {
+        t.bytes[k] = net->exec->sched.bytes[k];
+        t.flops[k] = net->exec->sched.flops[k];
+      }
+    }
+    const int m = net->exec->sched.n_cones;
+    if (zz) std::copy(res.begin(), res.begin() + m, zz);
+    if (zz_im) std::copy(res.begin() + m, res.begin() + 2 * m, zz_im);
+    if (energy) *energy = res[2 * m];
+    if (timing) *timing = t;
+    return QTN_OK;
+  } catch (const std::bad_alloc &) {
+    return set_err(QTN_ENOMEM, "host allocation failed");
+  }
+}
+
+int qtn_contract(qtn_network *net, void *d_workspace, size_t bytes, void *hip_stream,
+                 double *zz_out, double *zz_imag_out, double *energy_out) {
+  return contract_impl(net, d_workspace, bytes, hip_stream, zz_out, zz_imag_out, energy_out,
+                       nullptr);
+}
+
+int qtn_contract_timed(qtn_network *net, void *d_workspace, size_t bytes, void *hip_stream,
+                       double *zz_out, double *energy_out, qtn_timing *timing) {
+  if (!timing) return set_err(QTN_EINVAL, "timing is NULL");
+  return contract_impl(net, d_workspace, bytes, hip_stream, zz_out, nullptr, energy_out, timing);
+}
+
+static Exec *batch_exec(qtn_network *const *nets, int32_t n, int *rc) {
+  std::vector<std::pair<const qtn_network *, uint64_t>> key;
+  for (int i = 0; i < n; i++) {
+    if (!nets[i]) {
+      *rc = set_err(QTN_EINVAL, "NULL network in batch");
+      return nullptr;
+    }
+    if (!nets[i]->planned) {
+      *rc = set_err(QTN_ESTATE, "network " + std::to_string(i) + " is not planned");
+      return nullptr;
+    }
+    key.push_back({nets[i], nets[i]->version});
+  }
+  std::lock_guard<std::mutex> lk(g_batch_lock);
+  auto it = g_batch.find(key);
+  if (it != g_batch.end()) return it->second.get();
+  auto ex = std::make_unique<Exec>();
+  *rc = build_schedule(nets, n, &ex->sched);
+  if (*rc) return nullptr;
+  Exec *raw = ex.get();
+  g_batch[key] = std::move(ex);
+  return raw;
+}
+
+int qtn_batch_workspace(qtn_network *const *nets, int32_t n, size_t *workspace_bytes_out) {
+  try {
+    if (!nets || n < 1 || !workspace_bytes_out) return set_err(QTN_EINVAL, "bad batch arguments");
+    int rc = QTN_OK;
+    Exec *ex = batch_exec(nets, n, &rc);
+    if (!ex) return rc;
+    *workspace_bytes_out = ex->sched.total;
+    return QTN_OK;
+  } catch (const std::bad_alloc &) {
+    return set_err(QTN_ENOMEM, "host allocation failed");
+  }
+}
+
+int qtn_contract_batch(qtn_network *const *nets, int32_t n, void *d_workspace, size_t bytes,
+                       void *hip_stream, double *zz_out, double *energy_out) {
+  try {
+    if (!nets || n < 1) return set_err(QTN_EINVAL, "bad batch arguments");
+    int rc = QTN_OK;
+    Exec *ex = batch_exec(nets, n, &rc);
+    if (!ex) return rc;
+    std::vector<const qtn_network *> list(nets, nets + n);
+    Timer tm;
+    std::vector<double> res;
+    rc = run_exec(*ex, list, d_workspace, bytes, hip_stream, nets[0]->n_streams, nets[0]->eager,
+                  tm, res);
+    if (rc) return rc;
+    const int m = ex->sched.n_cones;
+    if (zz_out) std::copy(res.begin(), res.begin() + m, zz_out);
+    if (energy_out) std::copy(res.begin() + 2 * m, res.begin() + 2 * m + n, energy_out);
+    return QTN_OK;
+  } catch (const std::bad_alloc &) {
+    return set_err(QTN_ENOMEM, "host allocation failed");
+  }
+}
+
+int qtn_get_plan_stats(const qtn_network *net, qtn_plan_stats *out) {
+  if (!net || !out) return set_err(QTN_EINVAL, "NULL argument");
+  if (!net->planned) return set_err(QTN_ESTATE, "qtn_plan has not been called");
+  qtn_plan_stats st;
+  std::memset(&st, 0, sizeof st);
+  for (const ConePlan &pl : net->plans) {
+    st.n_buckets += pl.n_buckets;
+    st.n_groups += (int64_t)pl.groups.size();
+    for (const Group &G : pl.groups) st.n_wide += G.small ? 0 : 1;
+    st.max_width = std::max(st.max_width, pl.max_width);
+    for (int w : pl.bucket_width)
+      if (w > 0 && w < 40) st.width_hist[w]++;
+    st.paper_flops += pl.paper_flops;
+  }
+  const Schedule &s = net->exec->sched;
+  for (int k = 0; k < QTN_NKERNELS; k++) {
+    st.bytes += s.bytes[k];
+    st.flops += s.flops[k];
+  }
+  st.workspace = s.total;
+  *out = st;
+  return QTN_OK;
+}
+
+int qtn_bucket_widths(const qtn_network *net, int64_t edge, int32_t *widths_out) {
+  if (!net || !widths_out) return set_err(QTN_EINVAL, "NULL argument");
+  if (!net->planned) return set_err(QTN_ESTATE, "qtn_plan has not been called");
+  if (edge < 0 || edge >= (int64_t)net->plans.size()) return set_err(QTN_EINVAL, "edge out of range");
+  const auto &w = net->plans[edge].bucket_width;
+  std::copy(w.begin(), w.end(), widths_out);
+  return QTN_OK;
+}
+
+void qtn_network_free(qtn_network *net) {
+  if (!net) return;
+  drop_batches_with(net);
+  delete net;
+}
+
+}  // extern "C"

@@ -1,0 +1,45 @@
+// Launchers of the HIP kernels (kernels.hip).  Plain pointers and sizes only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "device.hpp"
+
+namespace qtn {
+
+enum Precision : int { kPrecC128 = 0, kPrecC64 = 1 };
+
+// One block per network: fills that network's gate table from its angles.
+struct FillDesc {
+  int64_t angle_off;  // doubles from the angle base: gamma[p] then beta[p]
+  int64_t table_off;  // elements from the data base
+  int32_t p, pad;
+};
+
+hipError_t launch_fill(int prec, void *data, const double *angles,
+                       const FillDesc *fills, int n_nets, hipStream_t s);
+
+// Groups [ranges[b].x, ranges[b].y) run in order inside block b, for
+// b in [range_base, range_base + n_blocks).
+hipError_t launch_block_groups(int prec, void *data, const DevGroup *groups,
+                               const DevOp *ops, const int2 *ranges,
+                               int range_base, int n_blocks, hipStream_t s);
+
+// One group over the whole grid.
+hipError_t launch_wide_group(int prec, void *data, const DevGroup *groups,
+                             const DevOp *ops, int group, uint32_t n_units,
+                             hipStream_t s);
+
+// Per light cone: product of its scalar slots -> e_jk (FP64); per network:
+// E = |E|/2 - 1/2 sum Re e_jk with Neumaier compensation.
+// res: [n_cones] Re, [n_cones] Im, [n_nets] energies.
+hipError_t launch_reduce(int prec, const void *data, int64_t scalar_off,
+                         const int *cone_scalar_begin, const int *net_cone_begin,
+                         int n_cones, int n_nets, double *res, hipStream_t s);
+
+// Grid size used for a wide group.
+int wide_blocks(uint32_t n_units);
+
+}  // namespace qtn

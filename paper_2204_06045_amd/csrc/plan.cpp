@@ -1,0 +1,407 @@
+// Host-side planner.  See plan.hpp for the method references.
+#include "plan.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+namespace qtn {
+
+std::string make_graph(int n, int64_t m, const int32_t *edges, Graph *g) {
+  if (n < 2) return "graph needs at least 2 vertices";
+  if (m < 1) return "graph needs at least 1 edge";
+  if (!edges) return "edge array is NULL";
+  if (m > (int64_t)1 << 26) return "too many edges";
+  g->n = n;
+  g->eu.resize(m);
+  g->ev.resize(m);
+  g->adj.assign(n, {});
+  std::vector<std::vector<int>> seen(n);
+  for (int64_t e = 0; e < m; e++) {
+    int a = edges[2 * e], b = edges[2 * e + 1];
+    if (a < 0 || b < 0 || a >= n || b >= n)
+      return "edge " + std::to_string(e) + " has an endpoint out of range";
+    if (a == b) return "edge " + std::to_string(e) + " is a self-loop";
+    for (int x : seen[a])
+      if (x == b) return "edge " + std::to_string(e) + " is repeated";
+    seen[a].push_back(b);
+    seen[b].push_back(a);
+    g->eu[e] = a;
+    g->ev[e] = b;
+    g->adj[a].push_back((int)e);
+    g->adj[b].push_back((int)e);
+  }
+  return "";
+}
+
+// Sec. II-B: the observable Z_j Z_k commutes with every gate outside its
+// reverse light cone, so those gates cancel against their conjugates.  Walking
+// back from the observable, layer l (1-based) keeps mixers on the vertices
+// within distance p-l of {j,k} and cost gates on edges touching them.
+LightCone build_lightcone(const Graph &g, int e, int p) {
+  LightCone lc;
+  lc.edge = e;
+  lc.j = g.eu[e];
+  lc.k = g.ev[e];
+  std::vector<int> dist(g.n, -1), queue;
+  queue.reserve(g.n);
+  dist[lc.j] = 0;
+  dist[lc.k] = 0;
+  queue.push_back(lc.j);
+  queue.push_back(lc.k);
+  for (size_t h = 0; h < queue.size(); h++) {
+    int u = queue[h];
+    if (dist[u] >= p) continue;
+    for (int f : g.adj[u]) {
+      int w = g.eu[f] == u ? g.ev[f] : g.eu[f];
+      if (dist[w] < 0) {
+        dist[w] = dist[u] + 1;
+        queue.push_back(w);
+      }
+    }
+  }
+  // cone vertices ascending, and the edges touching distance <= p-1 ascending
+  std::vector<int> verts;
+  for (int v = 0; v < g.n; v++)
+    if (dist[v] >= 0) verts.push_back(v);
+  std::vector<int> cone_edges;
+  for (int v : verts)
+    if (dist[v] <= p - 1)
+      for (int f : g.adj[v]) cone_edges.push_back(f);
+  std::sort(cone_edges.begin(), cone_edges.end());
+  cone_edges.erase(std::unique(cone_edges.begin(), cone_edges.end()), cone_edges.end());
+
+  auto within = [&](int v, int r) { return dist[v] >= 0 && dist[v] <= r; };
+  std::vector<int> cur(g.n, -1);
+  int nv = 0;
+  for (int v : verts) {
+    cur[v] = nv++;
+    lc.gates.push_back({kH, 0, 1, {cur[v], -1}});
+  }
+  for (int l = 1; l <= p; l++) {
+    for (int f : cone_edges)
+      if (within(g.eu[f], p - l) || within(g.ev[f], p - l))
+        lc.gates.push_back({kP, (int8_t)(l - 1), 2, {cur[g.eu[f]], cur[g.ev[f]]}});
+    for (int v : verts)
+      if (within(v, p - l)) {
+        int x = nv++;
+        lc.gates.push_back({kR, (int8_t)(l - 1), 2, {x, cur[v]}});
+        cur[v] = x;
+      }
+  }
+  lc.gates.push_back({kZ, 0, 1, {cur[lc.j], -1}});
+  lc.gates.push_back({kZ, 0, 1, {cur[lc.k], -1}});
+  for (int l = p; l >= 1; l--) {
+    for (int v : verts)
+      if (within(v, p - l)) {
+        int y = nv++;
+        lc.gates.push_back({kRc, (int8_t)(l - 1), 2, {cur[v], y}});
+        cur[v] = y;
+      }
+    for (int f : cone_edges)
+      if (within(g.eu[f], p - l) || within(g.ev[f], p - l))
+        lc.gates.push_back({kPc, (int8_t)(l - 1), 2, {cur[g.eu[f]], cur[g.ev[f]]}});
+  }
+  for (int v : verts) lc.gates.push_back({kH, 0, 1, {cur[v], -1}});
+  lc.n_vars = nv;
+  return lc;
+}
+
+// Greedy min-fill over the interaction graph (a vertex per variable, a clique
+// per tensor), with neighbour sets as bitsets.  Eliminating v joins its
+// neighbours into a clique; only the neighbours of v and their neighbours can
+// change fill, so only those are re-scored.
+std::vector<int> minfill_order(const LightCone &lc) {
+  const int n = lc.n_vars, W = (n + 63) / 64;
+  std::vector<uint64_t> adj((size_t)n * W, 0), alive(W, 0);
+  auto row = [&](int v) { return &adj[(size_t)v * W]; };
+  auto setb = [](uint64_t *r, int b) { r[b >> 6] |= 1ull << (b & 63); };
+  auto getb = [](const uint64_t *r, int b) { return (r[b >> 6] >> (b & 63)) & 1; };
+  for (const Gate &gt : lc.gates)
+    if (gt.rank == 2 && gt.var[0] != gt.var[1]) {
+      setb(row(gt.var[0]), gt.var[1]);
+      setb(row(gt.var[1]), gt.var[0]);
+    }
+  for (int v = 0; v < n; v++) setb(alive.data(), v);
+  std::vector<int64_t> fill(n);
+  std::vector<int> deg(n), nb, order;
+  std::vector<uint64_t> tmp(W);
+  auto score = [&](int v) {
+    const uint64_t *r = row(v);
+    nb.clear();
+    for (int w = 0; w < W; w++) {
+      uint64_t x = r[w] & alive[w];
+      while (x) {
+        nb.push_back(w * 64 + __builtin_ctzll(x));
+        x &= x - 1;
+      }
+    }
+    int64_t f = 0;
+    for (int a : nb) {
+      const uint64_t *ra = row(a);
+      for (int w = 0; w < W; w++) tmp[w] = r[w] & alive[w] & ~ra[w];
+      tmp[a >> 6] &= ~(1ull << (a & 63));
+      for (int w = 0; w < W; w++) f += __builtin_popcountll(tmp[w]);
+    }
+    fill[v] = f / 2;
+    deg[v] = (int)nb.size();
+  };
+  for (int v = 0; v < n; v++) score(v);
+  std::vector<char> touched(n);
+  for (int step = 0; step < n; step++) {
+    int best = -1;
+    for (int v = 0; v < n; v++) {
+      if (!getb(alive.data(), v)) continue;
+      if (best < 0 || fill[v] < fill[best] ||
+          (fill[v] == fill[best] && deg[v] < deg[best]))
+        best = v;
+    }
+    order.push_back(best);
+    alive[best >> 6] &= ~(1ull << (best & 63));
+    std::vector<int> nv;
+    const uint64_t *rb = row(best);
+    for (int w = 0; w < W; w++) {
+      uint64_t x = rb[w] & alive[w];
+      while (x) {
+        nv.push_back(w * 64 + __builtin_ctzll(x));
+        x &= x - 1;
+      }
+    }
+    for (int a : nv) {
+      uint64_t *ra = row(a);
+      for (int b : nv)
+        if (b != a) setb(ra, b);
+    }
+    std::fill(touched.begin(), touched.end(), 0);
+    for (int a : nv) {
+      touched[a] = 1;
+      const uint64_t *ra = row(a);
+      for (int w = 0; w < W; w++) {
+        uint64_t x = ra[w] & alive[w];
+        while (x) {
+          touched[w * 64 + __builtin_ctzll(x)] = 1;
+          x &= x - 1;
+        }
+      }
+    }
+    for (int v = 0; v < n; v++)
+      if (touched[v] && getb(alive.data(), v)) score(v);
+  }
+  return order;
+}
+
+int mask_runs(uint32_t mask, uint8_t *src, uint8_t *len, uint8_t *dst) {
+  int nr = 0, d = 0;
+  for (int b = 0; b < 32;) {
+    if (!((mask >> b) & 1)) {
+      b++;
+      continue;
+    }
+    int s = b;
+    while (b < 32 && ((mask >> b) & 1)) b++;
+    src[nr] = (uint8_t)s;
+    len[nr] = (uint8_t)(b - s);
+    dst[nr] = (uint8_t)d;
+    d += b - s;
+    nr++;
+  }
+  return nr;
+}
+
+namespace {
+
+struct BucketRec {
+  int pos;
+  std::vector<int> U;    // union, sorted by elimination position
+  std::vector<int> ops;  // tensor ids in the order they entered the bucket
+  int result = -1;       // tensor id, -1 for a scalar
+  int target = -1;       // record index receiving the result
+  int next = -1, prev = -1;  // merge chain links
+};
+
+// First-fit allocator over element offsets.
+struct Arena {
+  std::vector<std::pair<int64_t, int64_t>> used;  // (offset, size), sorted
+  int64_t peak = 0;
+  int64_t alloc(int64_t size) {
+    int64_t at = 0;
+    size_t i = 0;
+    for (; i < used.size(); i++) {
+      if (used[i].first - at >= size) break;
+      at = used[i].first + used[i].second;
+    }
+    used.insert(used.begin() + i, {at, size});
+    peak = std::max(peak, at + size);
+    return at;
+  }
+  void release(int64_t off) {
+    for (size_t i = 0; i < used.size(); i++)
+      if (used[i].first == off) {
+        used.erase(used.begin() + i);
+        return;
+      }
+  }
+};
+
+}  // namespace
+
+std::string plan_cone(const LightCone &lc, const std::vector<int> &order,
+                      const PlanOptions &opt, ConePlan *out) {
+  const int n = lc.n_vars;
+  if ((int)order.size() != n) return "order length differs from the variable count";
+  std::vector<int> pos(n, -1);
+  for (int i = 0; i < n; i++) {
+    int v = order[i];
+    if (v < 0 || v >= n || pos[v] >= 0) return "order is not a permutation of the variables";
+    pos[v] = i;
+  }
+  ConePlan &P = *out;
+  P = ConePlan();
+  P.order = order;
+  P.bucket_width.assign(n, 0);
+
+  // initial tensors, indices sorted by elimination position
+  for (size_t g = 0; g < lc.gates.size(); g++) {
+    const Gate &gt = lc.gates[g];
+    Tensor t;
+    t.gate = (int)g;
+    if (gt.rank == 1) {
+      t.vars = {gt.var[0]};
+    } else if (pos[gt.var[0]] < pos[gt.var[1]]) {
+      t.vars = {gt.var[0], gt.var[1]};
+      t.transposed = true;
+    } else {
+      t.vars = {gt.var[1], gt.var[0]};
+    }
+    P.tensors.push_back(t);
+  }
+
+  // symbolic bucket elimination (Sec. II-B)
+  std::vector<std::vector<int>> bucket(n);
+  for (size_t t = 0; t < P.tensors.size(); t++)
+    bucket[pos[P.tensors[t].vars[0]]].push_back((int)t);
+  std::vector<BucketRec> recs;
+  std::vector<int> rec_at(n, -1);
+  std::vector<char> mark(n, 0);
+  for (int i = 0; i < n; i++) {
+    if (bucket[i].empty()) continue;
+    BucketRec r;
+    r.pos = i;
+    r.ops = bucket[i];
+    std::vector<int> upos;
+    for (int t : r.ops)
+      for (int v : P.tensors[t].vars)
+        if (!mark[v]) {
+          mark[v] = 1;
+          upos.push_back(pos[v]);
+        }
+    std::sort(upos.begin(), upos.end());
+    for (int q : upos) {
+      r.U.push_back(order[q]);
+      mark[order[q]] = 0;
+    }
+    int w = (int)r.U.size();
+    P.bucket_width[i] = w;
+    P.max_width = std::max(P.max_width, w);
+    P.n_buckets++;
+    P.paper_flops += 8.0 * std::ldexp(1.0, w);
+    if (w > opt.max_width)
+      return "bucket width " + std::to_string(w) + " exceeds the cap " +
+             std::to_string(opt.max_width);
+    if (w > 1) {
+      Tensor res;
+      res.vars.assign(r.U.begin() + 1, r.U.end());
+      r.result = (int)P.tensors.size();
+      P.tensors.push_back(res);
+      bucket[pos[res.vars[0]]].push_back(r.result);
+    }
+    rec_at[i] = (int)recs.size();
+    recs.push_back(std::move(r));
+  }
+  for (auto &r : recs)
+    if (r.result >= 0) r.target = rec_at[pos[P.tensors[r.result].vars[0]]];
+
+  // merged indices (Sec. II-C): bucket r joins its target t when U_t is a
+  // subset of U_r, i.e. |U_t| = |U_r| - 1; one predecessor per target.
+  if (opt.max_levels > 1)
+    for (size_t r = 0; r < recs.size(); r++) {
+      int t = recs[r].target;
+      if (t >= 0 && recs[t].prev < 0 && recs[t].U.size() + 1 == recs[r].U.size()) {
+        recs[t].prev = (int)r;
+        recs[r].next = t;
+      }
+    }
+
+  // chains -> groups of at most max_levels summed indices
+  for (size_t h = 0; h < recs.size(); h++) {
+    if (recs[h].prev >= 0) continue;
+    std::vector<int> chain;
+    for (int r = (int)h; r >= 0; r = recs[r].next) chain.push_back(r);
+    for (size_t s = 0; s < chain.size(); s += opt.max_levels) {
+      size_t e = std::min(chain.size(), s + (size_t)opt.max_levels);
+      Group G;
+      const BucketRec &head = recs[chain[s]];
+      G.w = (int)head.U.size();
+      G.L = (int)(e - s);
+      G.first_pos = head.pos;
+      G.last_pos = recs[chain[e - 1]].pos;
+      std::vector<int> bit(n, -1);
+      for (int q = 0; q < G.w; q++) bit[head.U[q]] = q;
+      for (size_t c = s; c < e; c++) {
+        const BucketRec &r = recs[chain[c]];
+        int internal = (c > s) ? recs[chain[c - 1]].result : -1;
+        for (int t : r.ops) {
+          if (t == internal) continue;
+          uint32_t m = 0;
+          for (int v : P.tensors[t].vars) m |= 1u << bit[v];
+          G.ops.push_back({t, m, (int)(c - s)});
+        }
+      }
+      G.out_tensor = recs[chain[e - 1]].result;
+      G.small = G.w <= opt.small_width;
+      P.groups.push_back(std::move(G));
+    }
+  }
+  std::stable_sort(P.groups.begin(), P.groups.end(),
+                   [](const Group &a, const Group &b) { return a.last_pos < b.last_pos; });
+
+  // producers, consumers, scalar slots, cost counts
+  for (size_t g = 0; g < P.groups.size(); g++) {
+    Group &G = P.groups[g];
+    if (G.out_tensor >= 0)
+      P.tensors[G.out_tensor].producer = (int)g;
+    else
+      G.scalar_slot = P.n_scalars++;
+    double in_elems = 0;
+    std::vector<int> per_level(G.L, 0);
+    for (const Operand &o : G.ops) {
+      per_level[o.level]++;
+      if (P.tensors[o.tensor].gate < 0) P.tensors[o.tensor].consumer = (int)g;
+      in_elems += std::ldexp(1.0, (int)P.tensors[o.tensor].vars.size());
+    }
+    P.bytes += opt.elem_bytes * (in_elems + std::ldexp(1.0, G.w - G.L));
+    for (int l = 0; l < G.L; l++) {
+      int factors = per_level[l] + (l > 0 ? 1 : 0);
+      P.flops += std::ldexp(1.0, G.w - l) * 6.0 * std::max(0, factors - 1) +
+                 std::ldexp(1.0, G.w - l - 1) * 2.0;
+    }
+  }
+
+  // memory plan: outputs are placed before the group's inputs are released
+  Arena A;
+  const int64_t align = std::max<int64_t>(1, 256 / opt.elem_bytes);
+  for (size_t g = 0; g < P.groups.size(); g++) {
+    Group &G = P.groups[g];
+    if (G.out_tensor >= 0) {
+      int64_t sz = (int64_t)1 << (G.w - G.L);
+      sz = (sz + align - 1) / align * align;
+      P.tensors[G.out_tensor].offset = A.alloc(sz);
+    }
+    for (const Operand &o : G.ops)
+      if (P.tensors[o.tensor].gate < 0) A.release(P.tensors[o.tensor].offset);
+  }
+  P.arena_elems = A.peak;
+  return "";
+}
+
+}  // namespace qtn

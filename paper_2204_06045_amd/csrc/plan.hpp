@@ -1,0 +1,115 @@
+// Host-side planner: light cones, tensor networks, elimination orders,
+// symbolic bucket elimination, merged-index groups and the memory plan.
+//
+// Method references (arXiv 2204.06045):
+//   Sec. II-A, Eq. 1-2   QAOA MaxCut ansatz and cost operator
+//   Sec. II-B            light cones, circuit -> tensor network, buckets,
+//                        bucket width, energy as a sum of edge terms
+//   Sec. II-C            merged indices: buckets whose index sets nest are
+//                        summed together in one pass
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace qtn {
+
+constexpr int kMaxWidth = 32;     // union index of a group fits in 32 bits
+constexpr int kMaxLevels = 8;     // summed indices per fused group
+constexpr int kMaxRuns = 16;      // contiguous bit runs of an operand mask
+constexpr int kRegBits = 2;       // union bits held in registers per thread
+constexpr int kLaneBits = 6;      // union bits spread over the 64 lanes
+
+enum GateKind : int8_t { kH = 0, kZ = 1, kP = 2, kPc = 3, kR = 4, kRc = 5 };
+
+// One gate tensor.  Its value table is row-major over (var[0], var[1]):
+//   H  = (1, 1)/sqrt2                     rank 1, |+> amplitude
+//   Z  = (1, -1)                          rank 1, observable factor
+//   P  = exp(-i gamma [x0 != x1])         rank 2, cost phase (Eq. 1)
+//   R  = <x0| exp(-i beta X) |x1>         rank 2, mixer (Eq. 2)
+//   Pc, Rc = complex conjugates (bra side)
+struct Gate {
+  GateKind kind;
+  int8_t layer;  // 0-based QAOA layer of P/Pc/R/Rc
+  int8_t rank;
+  int32_t var[2];
+};
+
+struct LightCone {
+  int edge = -1, j = -1, k = -1;
+  int n_vars = 0;
+  std::vector<Gate> gates;
+};
+
+struct Graph {
+  int n = 0;
+  std::vector<int> eu, ev;   // edge endpoints
+  std::vector<std::vector<int>> adj;
+};
+
+// Validates and stores a graph; returns an error message or "".
+std::string make_graph(int n, int64_t m, const int32_t *edges, Graph *g);
+
+// Light cone of edge e at depth p (Sec. II-B reverse light cone).
+LightCone build_lightcone(const Graph &g, int e, int p);
+
+// Greedy min-fill order (ties: fewest neighbours, then smallest id).
+std::vector<int> minfill_order(const LightCone &lc);
+
+// ---------------------------------------------------------------- plan
+
+struct Tensor {
+  std::vector<int> vars;   // sorted by elimination position (bit 0 first)
+  int gate = -1;           // initial tensor: index into LightCone::gates
+  bool transposed = false; // rank-2 gate stored with var[0] as bit 0
+  int producer = -1;       // group writing this intermediate
+  int consumer = -1;       // group reading it
+  int64_t offset = -1;     // element offset inside the light cone's arena
+};
+
+struct Operand {
+  int tensor;
+  uint32_t mask;  // union bits the operand carries
+  int level;      // 0..L-1: multiplied in after that many indices are summed
+};
+
+struct Group {
+  int w = 0;                 // union width
+  int L = 0;                 // bucket indices summed (merged buckets)
+  int first_pos = 0, last_pos = 0; // elimination positions of the members
+  std::vector<Operand> ops;  // sorted by level
+  int out_tensor = -1;       // -1: scalar output
+  int scalar_slot = -1;      // light cone's scalar slot when out_tensor < 0
+  bool small = false;        // runs inside one workgroup
+};
+
+struct ConePlan {
+  std::vector<int> order;
+  std::vector<int> bucket_width;   // by elimination position, 0 if empty
+  int max_width = 0;
+  int n_buckets = 0;
+  std::vector<Tensor> tensors;
+  std::vector<Group> groups;       // in execution order
+  int n_scalars = 0;
+  int64_t arena_elems = 0;         // peak live elements of intermediates
+  double bytes = 0, flops = 0, paper_flops = 0;  // per evaluation
+};
+
+struct PlanOptions {
+  int max_levels = kMaxLevels;
+  int small_width = 12;
+  int max_width = kMaxWidth;
+  int elem_bytes = 16;
+};
+
+// Symbolic bucket elimination of one light cone along `order`, merged into
+// groups, with the arena laid out.  Returns an error message or "".
+std::string plan_cone(const LightCone &lc, const std::vector<int> &order,
+                      const PlanOptions &opt, ConePlan *out);
+
+// Bit runs of a mask: pext(x, mask) = sum over runs of
+// ((x >> src) & ((1 << len) - 1)) << dst.
+int mask_runs(uint32_t mask, uint8_t *src, uint8_t *len, uint8_t *dst);
+
+}  // namespace qtn

@@ -1,0 +1,170 @@
+"""C ABI without a GPU: exported symbols, planner, orders, widths, error paths.
+
+Nothing here launches a kernel; qtn_contract is only called on paths that
+fail before any HIP call.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import qaoa_synth as qs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    with open(os.path.join(ROOT, "include", "qtn.h")) as f:
+        text = f.read()
+    names = set(re.findall(r"\b(qtn_[a-z_]+)\s*\(", text))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_symbol(qtn):
+    from paper_2204_06045_amd import _capi
+    lib = _capi.lib()
+    names = _declared()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(_capi.EXPORTS)
+
+
+def test_minfill_matches_oracle_rule(qtn, orc):
+    for n, d, p, seed in [(10, 3, 1, 0), (16, 3, 3, 2), (30, 3, 4, 0), (40, 4, 3, 1)]:
+        inst = qs.instance(n, d, p, seed)
+        g, b = inst["angles"][0]
+        net = qtn.Network(n, inst["edges"], g, b)
+        for eid in range(0, len(inst["edges"]), 7):
+            assert np.array_equal(net.order_minfill(eid),
+                                  orc.edge_order(n, inst["edges"], eid, p))
+        net.close()
+
+
+def test_bucket_widths_match_oracle_recount(qtn, orc):
+    inst = qs.instance(16, 3, 3, 4)
+    g, b = inst["angles"][0]
+    net = qtn.Network(16, inst["edges"], g, b, max_levels=1)
+    net.plan(qtn.QTN_C128)
+    for eid in range(0, len(inst["edges"]), 5):
+        _, w_or = orc.edge_zz(16, inst["edges"], eid, g, b, return_widths=True)
+        order = orc.edge_order(16, inst["edges"], eid, 3)
+        w_q = net.bucket_widths(eid)
+        # oracle widths are indexed by elimination position as well
+        assert np.array_equal(np.asarray(w_or), w_q), eid
+        nv, nt, wmax = net.info(eid)
+        assert wmax == max(w_q) and nv == len(order)
+        assert nt == orc.lightcone_size(16, inst["edges"], eid, 3)[1]
+    net.close()
+
+
+def test_plan_stats_consistency(qtn):
+    inst = qs.instance(30, 3, 4, 0)
+    g, b = inst["angles"][0]
+    plain = qtn.Network(30, inst["edges"], g, b, max_levels=1)
+    plain.plan(qtn.QTN_C128)
+    merged = qtn.Network(30, inst["edges"], g, b)
+    merged.plan(qtn.QTN_C128)
+    sp, sm = plain.stats(), merged.stats()
+    assert sp["n_buckets"] == sm["n_buckets"] == sum(sp["width_hist"])
+    assert sp["n_groups"] == sp["n_buckets"]
+    assert sm["n_groups"] < sm["n_buckets"]
+    # merging never widens a bucket and removes intermediate traffic (Sec. II-C)
+    assert sm["max_width"] == sp["max_width"]
+    assert sm["bytes"] < sp["bytes"] / 5
+    assert abs(sp["flops"] - sm["flops"]) / sp["flops"] < 1e-12
+    assert sm["workspace"] < sp["workspace"]
+    plain.close()
+    merged.close()
+
+
+def test_c64_plan_halves_bytes(qtn):
+    inst = qs.instance(20, 3, 3, 1)
+    g, b = inst["angles"][0]
+    n1 = qtn.Network(20, inst["edges"], g, b)
+    n1.plan(qtn.QTN_C128)
+    n2 = qtn.Network(20, inst["edges"], g, b)
+    n2.plan(qtn.QTN_C64)
+    assert abs(n2.stats()["bytes"] * 2 - n1.stats()["bytes"]) < 1e-6 * n1.stats()["bytes"]
+
+
+@pytest.mark.parametrize("edges,msg", [
+    ([(0, 0)], "self-loop"),
+    ([(0, 1), (1, 0)], "repeated"),
+    ([(0, 5)], "out of range"),
+])
+def test_bad_graphs_rejected(qtn, edges, msg):
+    with pytest.raises(qtn.QtnError) as ei:
+        qtn.Network(3, edges, [0.1], [0.2])
+    assert ei.value.code == -1 and msg in str(ei.value)
+
+
+def test_bad_angles_and_depth(qtn):
+    with pytest.raises(qtn.QtnError):
+        qtn.Network(3, [(0, 1)], [float("nan")], [0.2])
+    with pytest.raises(qtn.QtnError):
+        qtn.Network(3, [(0, 1)], [], [])
+
+
+def test_bad_order_and_width_cap(qtn):
+    inst = qs.instance(30, 3, 4, 0)
+    g, b = inst["angles"][0]
+    net = qtn.Network(30, inst["edges"], g, b)
+    nv = net.info(0)[0]
+    bad = [None] * len(inst["edges"])
+    bad[0] = np.zeros(nv, dtype=np.int32)  # not a permutation
+    with pytest.raises(qtn.QtnError) as ei:
+        net.plan(qtn.QTN_C128, orders=bad)
+    assert ei.value.code == -1
+    capped = qtn.Network(30, inst["edges"], g, b, max_width=12)
+    with pytest.raises(qtn.QtnError) as ei:
+        capped.plan(qtn.QTN_C128)
+    assert ei.value.code == -2
+    net.close()
+    capped.close()
+
+
+def test_contract_errors_leave_outputs_untouched(qtn):
+    from paper_2204_06045_amd import _capi
+    lib = _capi.lib()
+    inst = qs.instance(10, 3, 1, 0)
+    g, b = inst["angles"][0]
+    net = qtn.Network(10, inst["edges"], g, b)
+    zz = np.full(15, 7.0)
+    en = ctypes.c_double(7.0)
+    pd = ctypes.POINTER(ctypes.c_double)
+    # before qtn_plan
+    rc = lib.qtn_contract(net.h, ctypes.c_void_p(256), 1 << 20, None,
+                          zz.ctypes.data_as(pd), None, ctypes.byref(en))
+    assert rc == -5
+    need = net.plan(qtn.QTN_C128)
+    # workspace too small
+    rc = lib.qtn_contract(net.h, ctypes.c_void_p(256), need - 1, None,
+                          zz.ctypes.data_as(pd), None, ctypes.byref(en))
+    assert rc == -3 and "workspace" in qtn.qtn_last_error()
+    # NULL workspace
+    rc = lib.qtn_contract(net.h, None, need, None, zz.ctypes.data_as(pd), None,
+                          ctypes.byref(en))
+    assert rc == -1
+    assert np.all(zz == 7.0) and en.value == 7.0
+    net.close()
+
+
+def test_set_angles_validation(qtn):
+    net = qtn.Network(4, [(0, 1), (1, 2), (2, 3)], [0.1, 0.2], [0.3, 0.4])
+    net.set_angles([0.5, 0.6], [0.7, 0.8])
+    with pytest.raises(qtn.QtnError):
+        net.set_angles([float("inf"), 0.0], [0.0, 0.0])
+    net.close()
+
+
+def test_lightcone_sizes_match_oracle(qtn, orc):
+    inst = qs.instance(40, 4, 3, 2)
+    g, b = inst["angles"][0]
+    net = qtn.Network(40, inst["edges"], g, b)
+    for eid in range(0, len(inst["edges"]), 9):
+        nv, nt, _ = net.info(eid)
+        assert (nv, nt) == orc.lightcone_size(40, inst["edges"], eid, 3)
+    net.close()

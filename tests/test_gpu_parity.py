@@ -1,0 +1,178 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Tolerances (per edge |delta e_jk| and |Im e_jk|, and |delta E| / |E|):
+complex128 1e-10, complex64 1e-5.  Every e_jk is bounded by ||Z_j Z_k|| = 1,
+so the per-edge bound is relative to the operator scale.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import qaoa_synth as qs
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TOL = {0: 1e-10, 1: 1e-5}
+
+
+def _check(zz, zi, en, ref_zz, ref_en, prec, what=""):
+    tol = TOL[prec]
+    ref_zz = np.asarray(ref_zz).real
+    err = np.max(np.abs(zz - ref_zz))
+    assert err <= tol, f"{what}: max |delta e| = {err:.3e} > {tol}"
+    if zi is not None:
+        assert np.max(np.abs(zi)) <= tol, f"{what}: |Im e| = {np.max(np.abs(zi)):.3e}"
+    rel = abs(en - ref_en) / max(abs(ref_en), 1e-300)
+    assert rel <= tol, f"{what}: relative energy error {rel:.3e}"
+
+
+def _run(qtn, n, edges, g, b, prec, **cfg):
+    net = qtn.Network(n, edges, g, b, **cfg)
+    net.plan(prec)
+    zz, zi, en = net.contract()
+    net.close()
+    return zz, zi, en
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("levels", [1, 8])
+def test_cfg1_n10_p1(qtn, orc, gpu, prec, levels):
+    for seed in range(10):
+        inst = qs.instance(10, 3, 1, seed)
+        g, b = inst["angles"][0]
+        sv = orc.statevector_zz(10, inst["edges"], g, b)
+        ref_en = len(inst["edges"]) / 2 - 0.5 * np.sum(sv)
+        print(f"cfg1 seed={seed} prec={prec} levels={levels}", flush=True)
+        zz, zi, en = _run(qtn, 10, inst["edges"], g, b, prec, max_levels=levels)
+        _check(zz, zi, en, sv, ref_en, prec, f"seed {seed}")
+
+
+def test_petersen_p1_optimum(qtn, gpu):
+    e = qs.petersen_graph()
+    g, b = math.atan(1 / math.sqrt(2)), math.pi / 8
+    zz, zi, en = _run(qtn, 10, e, [g], [b], 0)
+    assert np.max(np.abs((1 - zz) / 2 - (0.5 + 1 / (3 * math.sqrt(3))))) < 1e-12
+    assert abs(en / 15 - (0.5 + 1 / (3 * math.sqrt(3)))) < 1e-12
+
+
+@pytest.mark.parametrize("n,p", [(12, 2), (16, 3), (16, 4), (20, 3)])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_small_graphs_all_configs(qtn, orc, gpu, n, p, prec):
+    inst = qs.instance(n, 3, p, 7)
+    g, b = inst["angles"][0]
+    ref, ref_en = orc.energy(n, inst["edges"], g, b, threads=8)
+    for cfg in [dict(max_levels=1), dict(max_levels=3), dict(max_levels=8),
+                dict(small_width=4), dict(small_width=20), dict(eager=True),
+                dict(n_streams=1)]:
+        print(f"n={n} p={p} prec={prec} cfg={cfg}", flush=True)
+        zz, zi, en = _run(qtn, n, inst["edges"], g, b, prec, **cfg)
+        _check(zz, zi, en, ref, ref_en, prec, str(cfg))
+
+
+def test_repeat_and_new_angles_replay(qtn, orc, gpu):
+    inst = qs.instance(16, 3, 3, 2, 3)
+    e = inst["edges"]
+    net = qtn.Network(16, e, *inst["angles"][0])
+    net.plan(0)
+    first = net.contract()
+    again = net.contract()
+    assert np.array_equal(first[0], again[0]) and first[2] == again[2]
+    for g, b in inst["angles"][1:]:
+        net.set_angles(g, b)
+        ref, ref_en = orc.energy(16, e, g, b, threads=8)
+        zz, zi, en = net.contract()
+        _check(zz, zi, en, ref, ref_en, 0, "replay with new angles")
+    # a fresh workspace forces a new descriptor upload and capture
+    ws2 = qtn.workspace(net.ws_bytes)
+    zz2, _, _ = net.contract(ws=ws2)
+    assert np.array_equal(zz2, zz)
+    net.close()
+
+
+def test_edge_cases(qtn, orc, gpu):
+    cases = [
+        (2, [(0, 1)], 1), (2, [(0, 1)], 3),                      # single edge
+        (5, [(0, 1), (1, 2), (2, 3), (3, 4)], 2),                 # path
+        (6, [(0, 1), (0, 2), (0, 3), (0, 4), (0, 5)], 3),         # star
+        (6, [(0, 1), (1, 2), (0, 2), (3, 4), (4, 5), (3, 5)], 2), # two triangles
+        (7, [(0, 1), (1, 2), (2, 3), (3, 0), (0, 2)], 2),         # isolated 4,5,6
+        (8, qs.instance(8, 3, 5, 1)["edges"], 5),                 # deep p
+    ]
+    r = qs.Rng(17)
+    for n, e, p in cases:
+        g = [math.pi * r.uniform() for _ in range(p)]
+        b = [0.5 * math.pi * r.uniform() for _ in range(p)]
+        sv = orc.statevector_zz(n, e, g, b)
+        ref_en = len(e) / 2 - 0.5 * np.sum(sv)
+        for prec in (0, 1):
+            print(f"edge case n={n} m={len(e)} p={p} prec={prec}", flush=True)
+            zz, zi, en = _run(qtn, n, e, g, b, prec)
+            _check(zz, zi, en, sv, ref_en, prec, f"n={n} p={p}")
+
+
+def test_given_orders(qtn, orc, gpu):
+    inst = qs.instance(12, 3, 3, 5)
+    e = inst["edges"]
+    g, b = inst["angles"][0]
+    ref, ref_en = orc.energy(12, e, g, b, threads=8)
+    net = qtn.Network(12, e, g, b)
+    r = qs.Rng(8)
+    orders = []
+    for eid in range(len(e)):
+        o = list(net.order_minfill(eid))
+        for _ in range(4):
+            i, j = r.below(len(o)), r.below(len(o))
+            o[i], o[j] = o[j], o[i]
+        orders.append(o)
+    net.plan(0, orders=orders)
+    zz, zi, en = net.contract()
+    _check(zz, zi, en, ref, ref_en, 0, "perturbed orders")
+    net.close()
+
+
+def test_gamma_zero_gives_half_edges(qtn, gpu):
+    inst = qs.instance(30, 3, 4, 0)
+    _, b = inst["angles"][0]
+    zz, zi, en = _run(qtn, 30, inst["edges"], [0.0] * 4, b, 0)
+    assert np.max(np.abs(zz)) < 1e-10 and abs(en - 22.5) < 1e-9
+
+
+def test_batch_matches_single(qtn, orc, gpu):
+    insts = qs.batch_instances(3, 4, 10, 24, (2, 3), d=3)
+    nets, refs = [], []
+    for it in insts:
+        g, b = it["angles"][0]
+        net = qtn.Network(it["n"], it["edges"], g, b)
+        net.plan(1)
+        nets.append(net)
+        refs.append(orc.energy(it["n"], it["edges"], g, b, threads=8))
+    handles = [n.h for n in nets]
+    need = qtn.qtn_batch_workspace(handles)
+    ws = qtn.workspace(need)
+    total = sum(n.m for n in nets)
+    zz, en = qtn.qtn_contract_batch(handles, total, ws)
+    off = 0
+    for net, (rz, re_) in zip(nets, refs):
+        _check(zz[off:off + net.m], None, en[nets.index(net)], rz, re_, 1, "batch")
+        off += net.m
+    for n in nets:
+        n.close()
+
+
+def _golden(name):
+    with open(os.path.join(HERE, "golden", f"{name}_oracle.json")) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("prec,levels", [(0, 8), (1, 8), (0, 1)])
+def test_cfg2_full_size_against_oracle(qtn, gpu, prec, levels):
+    """3-regular N=30, p=4 (Sec. II-E benchmark shape), all 45 light cones."""
+    gd = _golden("cfg2")
+    print(f"cfg2 prec={prec} levels={levels}", flush=True)
+    zz, zi, en = _run(qtn, gd["n"], gd["edges"], gd["gamma"], gd["beta"], prec,
+                      max_levels=levels)
+    _check(zz, zi, en, gd["zz_re"], gd["energy"], prec, "cfg2")

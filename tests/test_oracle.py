@@ -225,3 +225,11 @@ def test_contract_bucket_matches_einsum(orc):
 def test_paper_width27_memory_figure():
     pv = _paper()["width27_c128_bytes"]
     assert abs((1 << 27) * 16 - pv["value"]) / pv["value"] < 0.08
+
+
+def test_symbolic_widths_match_numeric_run(orc):
+    inst = qs.instance(16, 3, 3, 4)
+    g, b = inst["angles"][0]
+    for eid in range(0, 24, 4):
+        _, w = orc.edge_zz(16, inst["edges"], eid, g, b, return_widths=True)
+        assert np.array_equal(w, orc.edge_widths(16, inst["edges"], eid, 3))
