@@ -38,10 +38,10 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_rows(Q, torch, inst, prec, levels, streams, steps, warmup):
+def run_rows(Q, torch, inst, prec, levels, streams, steps, warmup, **cfg):
     n, edges = inst["n"], inst["edges"]
     angles = inst["angles"]
-    net = Q.Network(n, edges, *angles[0], max_levels=levels, n_streams=streams)
+    net = Q.Network(n, edges, *angles[0], max_levels=levels, n_streams=streams, **cfg)
     t0 = time.perf_counter()
     net.plan(prec)
     plan_s = time.perf_counter() - t0
@@ -62,14 +62,15 @@ def run_rows(Q, torch, inst, prec, levels, streams, steps, warmup):
 
 def roofline_of(timing, prec):
     """Dominant kernel class (most device time) against its bound."""
-    dom = max(("block", "wide"), key=lambda k: timing[k]["ms"])
+    dom = max(("block", "wide", "persistent"), key=lambda k: timing[k]["ms"])
     t = timing[dom]
     sec = t["ms"] / 1e3
     gbs = t["bytes"] / sec / 1e9 if sec > 0 else 0.0
     tflops = t["flops"] / sec / 1e12 if sec > 0 else 0.0
     fpeak = FP64_PEAK_TFLOPS if prec == 0 else FP32_PEAK_TFLOPS
     hbm_frac, fp_frac = gbs / HBM_PEAK_GBS, tflops / fpeak
-    kernel = f"k_{'wide_group' if dom == 'wide' else 'block_groups'}<{'double2' if prec == 0 else 'float2'}>"
+    kname = {"wide": "wide", "block": "block_groups", "persistent": "persistent"}[dom]
+    kernel = f"k_{kname}<{'double2' if prec == 0 else 'float2'}>"
     common = {"kernel": kernel, "launches": t["launches"],
               "bytes_per_launch": t["bytes"] / max(1, t["launches"]),
               "avg_launch_ms": t["ms"] / max(1, t["launches"]),
@@ -128,6 +129,11 @@ def main():
     ap.add_argument("--precision", choices=("c128", "c64"), default="c128")
     ap.add_argument("--levels", type=int, default=8, help="merged indices per group (1 = plain)")
     ap.add_argument("--streams", type=int, default=4)
+    ap.add_argument("--variant", type=int, default=0, help="0 auto, 1 generic, 2 streaming")
+    ap.add_argument("--lane-bits", type=int, default=0, help="streaming lane-summed bits")
+    ap.add_argument("--executor", type=int, default=0, help="0 default, 1 launches, 2 persistent")
+    ap.add_argument("--order-trials", type=int, default=64,
+                    help="randomized min-fill orders tried per light cone (0 = greedy)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--angle-sets", type=int, default=32)
     ap.add_argument("--variants", type=int, default=1, help="also time the other rows")
@@ -149,8 +155,10 @@ def main():
     inst = qs.instance(30, 3, 4, args.seed, args.angle_sets)
     prec = Q.QTN_C128 if args.precision == "c128" else Q.QTN_C64
     log(f"main row: {args.precision} levels={args.levels} streams={args.streams}")
+    kcfg = dict(variant=args.variant, lane_sum_bits=args.lane_bits,
+                order_trials=args.order_trials, executor=args.executor)
     net, dt, plan_s, last = run_rows(Q, torch, inst, prec, args.levels, args.streams,
-                                     args.steps, args.warmup)
+                                     args.steps, args.warmup, **kcfg)
     evals = args.steps / dt
     stats = net.stats()
     log(f"  {evals:.2f} evals/s, plan {plan_s:.2f} s")
@@ -168,7 +176,7 @@ def main():
                 continue
             log(f"variant {name}")
             vnet, vdt, _, _ = run_rows(Q, torch, inst, pr, lv, args.streams,
-                                       max(3, args.steps // 4), 2)
+                                       max(3, args.steps // 4), 2, **kcfg)
             vst = vnet.stats()
             variants[name] = {"evals_per_s": max(3, args.steps // 4) / vdt,
                               "alg_bytes_per_eval": vst["bytes"],
@@ -200,7 +208,10 @@ def main():
             "workload": (f"QAOA MaxCut energy, random 3-regular N=30 (45 edges), p=4, graph "
                          f"seed {args.seed}, {args.angle_sets} seeded angle sets"),
             "precision": args.precision, "max_levels": args.levels,
-            "streams": args.streams, "max_width": stats["max_width"],
+            "streams": args.streams, "variant": args.variant,
+            "lane_sum_bits": args.lane_bits, "order_trials": args.order_trials,
+            "executor": args.executor,
+            "max_width": stats["max_width"],
             "buckets": stats["n_buckets"], "groups": stats["n_groups"],
         },
         "alg_bytes_per_eval": stats["bytes"],

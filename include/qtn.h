@@ -57,7 +57,19 @@ typedef struct qtn_config {
     int32_t n_streams;   /* HIP streams the light cones are spread over [4] */
     int32_t eager;       /* 1: launch eagerly instead of replaying a
                             captured HIP graph [0]                          */
-    int32_t reserved[11];
+    int32_t lane_sum_bits; /* streaming kernel: summed indices spread over
+                            lanes, the rest walked serially per lane [2]  */
+    int32_t variant;     /* 0 auto, 1 generic kernel only, 2 streaming
+                            kernel wherever it applies [0]                 */
+    int32_t order_trials; /* >1: plan with the cheapest (sum of 2^width) of
+                            the greedy min-fill order and order_trials-1
+                            min-fill orders with random tie-breaks [0]     */
+    int32_t executor;    /* 0 default (single networks: per-group launches
+                            over n_streams; batches: persistent), 1 per-group
+                            launches, 2 one persistent lockstep launch      */
+    int32_t spin_limit;  /* persistent executor: polls before a grid-barrier
+                            wait gives up with QTN_EDEVICE [2^26]          */
+    int32_t reserved[6];
 } qtn_config;
 
 /*
@@ -104,6 +116,9 @@ int qtn_order_minfill(const qtn_network *net, int64_t edge, int32_t *order_out);
 int qtn_plan(qtn_network *net, const int32_t *const *orders, int32_t precision,
              size_t *workspace_bytes_out);
 
+/* The elimination order qtn_plan used for one light cone. */
+int qtn_plan_order(const qtn_network *net, int64_t edge, int32_t *order_out);
+
 /* Replace the angles (values only; the plan is kept). */
 int qtn_set_angles(qtn_network *net, const double *gamma, const double *beta);
 
@@ -140,11 +155,12 @@ int qtn_batch_workspace(qtn_network *const *nets, int32_t n,
                         size_t *workspace_bytes_out);
 
 /* Per-kernel-class timing of one eager evaluation, for the roofline report. */
-#define QTN_NKERNELS 4
-#define QTN_K_FILL 0   /* gate-table fill from the angles            */
-#define QTN_K_BLOCK 1  /* small groups, many per workgroup            */
-#define QTN_K_WIDE 2   /* one wide group per launch                   */
-#define QTN_K_REDUCE 3 /* per-edge scalars and the energy             */
+#define QTN_NKERNELS 5
+#define QTN_K_FILL 0       /* gate-table fill from the angles            */
+#define QTN_K_BLOCK 1      /* small groups, many per workgroup            */
+#define QTN_K_WIDE 2       /* one wide group per launch                   */
+#define QTN_K_REDUCE 3     /* per-edge scalars and the energy             */
+#define QTN_K_PERSISTENT 4 /* every group in one lockstep launch          */
 typedef struct qtn_timing {
     double ms[QTN_NKERNELS];        /* summed launch durations (HIP events) */
     int64_t launches[QTN_NKERNELS]; /* launches per class                 */
@@ -158,6 +174,25 @@ typedef struct qtn_timing {
 int qtn_contract_timed(qtn_network *net, void *d_workspace, size_t bytes,
                        void *hip_stream, double *zz_out, double *energy_out,
                        qtn_timing *timing);
+
+/* One launch of the last qtn_contract_timed call on this network. */
+typedef struct qtn_launch_rec {
+    int32_t kind;      /* QTN_K_* class                                   */
+    int32_t group;     /* first group of the launch (plan order)          */
+    int32_t n_groups;  /* groups in the launch                            */
+    int32_t w, L;      /* union width and summed indices (first group)    */
+    int32_t n_ops;     /* operands of the first group                     */
+    int32_t variant;   /* kernel mapping of the first group               */
+    int32_t n_units;   /* wave units of the first group                   */
+    double ms;         /* HIP-event duration                              */
+    double bytes;      /* algorithmic bytes of the launch                 */
+    double flops;      /* complex-arithmetic FLOPs of the launch          */
+} qtn_launch_rec;
+
+/* Copies up to `cap` records of the last timed evaluation into `out` and
+ * stores the number available in *n_out. */
+int qtn_launch_log(const qtn_network *net, int64_t cap, qtn_launch_rec *out,
+                   int64_t *n_out);
 
 /* Plan statistics. */
 typedef struct qtn_plan_stats {

@@ -25,23 +25,27 @@ QTN_ESTATE = -5
 QTN_C128 = 0
 QTN_C64 = 1
 
-NKERNELS = 4
-K_FILL, K_BLOCK, K_WIDE, K_REDUCE = range(4)
-KERNEL_NAMES = ("fill", "block", "wide", "reduce")
+NKERNELS = 5
+K_FILL, K_BLOCK, K_WIDE, K_REDUCE, K_PERSISTENT = range(5)
+KERNEL_NAMES = ("fill", "block", "wide", "reduce", "persistent")
 
 # every symbol include/qtn.h declares
 EXPORTS = (
     "qtn_network_build", "qtn_network_info", "qtn_order_minfill", "qtn_plan",
     "qtn_set_angles", "qtn_contract", "qtn_contract_batch",
     "qtn_batch_workspace", "qtn_contract_timed", "qtn_get_plan_stats",
-    "qtn_bucket_widths", "qtn_network_free", "qtn_last_error",
+    "qtn_bucket_widths", "qtn_network_free", "qtn_last_error", "qtn_launch_log",
+    "qtn_plan_order",
 )
 
 
 class qtn_config(ctypes.Structure):
     _fields_ = [("max_levels", ctypes.c_int32), ("small_width", ctypes.c_int32),
                 ("max_width", ctypes.c_int32), ("n_streams", ctypes.c_int32),
-                ("eager", ctypes.c_int32), ("reserved", ctypes.c_int32 * 11)]
+                ("eager", ctypes.c_int32), ("lane_sum_bits", ctypes.c_int32),
+                ("variant", ctypes.c_int32), ("order_trials", ctypes.c_int32),
+                ("executor", ctypes.c_int32), ("spin_limit", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
 
 
 class qtn_timing(ctypes.Structure):
@@ -49,6 +53,14 @@ class qtn_timing(ctypes.Structure):
                 ("launches", ctypes.c_int64 * NKERNELS),
                 ("bytes", ctypes.c_double * NKERNELS),
                 ("flops", ctypes.c_double * NKERNELS)]
+
+
+class qtn_launch_rec(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("group", ctypes.c_int32),
+                ("n_groups", ctypes.c_int32), ("w", ctypes.c_int32), ("L", ctypes.c_int32),
+                ("n_ops", ctypes.c_int32), ("variant", ctypes.c_int32),
+                ("n_units", ctypes.c_int32), ("ms", ctypes.c_double),
+                ("bytes", ctypes.c_double), ("flops", ctypes.c_double)]
 
 
 class qtn_plan_stats(ctypes.Structure):
@@ -98,6 +110,9 @@ def lib():
                                          ctypes.POINTER(qtn_timing)]
         L.qtn_get_plan_stats.argtypes = [P, ctypes.POINTER(qtn_plan_stats)]
         L.qtn_bucket_widths.argtypes = [P, i64, pi32]
+        L.qtn_plan_order.argtypes = [P, i64, pi32]
+        L.qtn_launch_log.argtypes = [P, i64, ctypes.POINTER(qtn_launch_rec),
+                                     ctypes.POINTER(i64)]
         L.qtn_network_free.argtypes = [P]
         L.qtn_network_free.restype = None
         for name in EXPORTS:

@@ -14,14 +14,14 @@ import torch
 
 from . import _capi
 from ._capi import (QTN_C128, QTN_C64, QtnError, check, lib, qtn_config,
-                    qtn_plan_stats, qtn_timing)
+                    qtn_launch_rec, qtn_plan_stats, qtn_timing)
 
 __all__ = [
     "QTN_C128", "QTN_C64", "QtnError", "qtn_network_build", "qtn_network_info",
     "qtn_order_minfill", "qtn_plan", "qtn_set_angles", "qtn_contract",
     "qtn_contract_timed", "qtn_contract_batch", "qtn_batch_workspace",
     "qtn_get_plan_stats", "qtn_bucket_widths", "qtn_network_free",
-    "qtn_last_error", "Network", "workspace", "stream_handle",
+    "qtn_last_error", "qtn_launch_log", "qtn_plan_order", "Network", "workspace", "stream_handle",
 ]
 
 _pi32 = ctypes.POINTER(ctypes.c_int32)
@@ -43,14 +43,17 @@ def qtn_last_error() -> str:
 
 
 def qtn_network_build(n_vertices, edges, gamma, beta, max_levels=0,
-                      small_width=0, max_width=0, n_streams=0, eager=False):
+                      small_width=0, max_width=0, n_streams=0, eager=False,
+                      lane_sum_bits=0, variant=0, order_trials=0, executor=0,
+                      spin_limit=0):
     """Returns an opaque handle (int)."""
     e, ep = _i32(edges)
     g, gp = _f64(gamma)
     b, bp = _f64(beta)
     if len(g) != len(b):
         raise ValueError("gamma and beta differ in length")
-    cfg = qtn_config(max_levels, small_width, max_width, n_streams, int(eager))
+    cfg = qtn_config(max_levels, small_width, max_width, n_streams, int(eager),
+                     lane_sum_bits, variant, order_trials, executor, spin_limit)
     h = ctypes.c_void_p()
     check(lib().qtn_network_build(int(n_vertices), len(e) // 2, ep, len(g), gp,
                                   bp, ctypes.byref(cfg), ctypes.byref(h)))
@@ -166,11 +169,27 @@ def qtn_get_plan_stats(net):
             "workspace": s.workspace}
 
 
+def qtn_plan_order(net, edge):
+    nv, _, _ = qtn_network_info(net, edge)
+    out, op = _i32(np.zeros(nv))
+    check(lib().qtn_plan_order(net, edge, op))
+    return out
+
+
 def qtn_bucket_widths(net, edge):
     nv, _, _ = qtn_network_info(net, edge)
     out, op = _i32(np.zeros(nv))
     check(lib().qtn_bucket_widths(net, edge, op))
     return out
+
+
+def qtn_launch_log(net):
+    """Per-launch records of the last timed evaluation, as dicts."""
+    n = ctypes.c_int64()
+    check(lib().qtn_launch_log(net, 0, None, ctypes.byref(n)))
+    arr = (qtn_launch_rec * max(1, n.value))()
+    check(lib().qtn_launch_log(net, n.value, arr, ctypes.byref(n)))
+    return [{f: getattr(r, f) for f, _ in qtn_launch_rec._fields_} for r in arr[:n.value]]
 
 
 def qtn_network_free(net):
@@ -218,6 +237,12 @@ class Network:
 
     def stats(self):
         return qtn_get_plan_stats(self.h)
+
+    def launch_log(self):
+        return qtn_launch_log(self.h)
+
+    def plan_order(self, edge):
+        return qtn_plan_order(self.h, edge)
 
     def bucket_widths(self, edge):
         return qtn_bucket_widths(self.h, edge)

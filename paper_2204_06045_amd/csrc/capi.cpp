@@ -38,6 +38,13 @@ int set_err(int code, const std::string &msg) {
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+uint32_t pext32(uint32_t x, uint32_t mask) {
+  uint32_t r = 0, d = 0;
+  for (int b = 0; b < 32; b++)
+    if ((mask >> b) & 1u) r |= ((x >> b) & 1u) << d++;
+  return r;
+}
+
 // Runs f(i) for i in [0, n) on up to hardware_concurrency threads.
 template <class F>
 void parallel_for(int n, F f) {
@@ -60,6 +67,7 @@ struct Task {
   int kind;        // QTN_K_BLOCK: range index; QTN_K_WIDE: group index
   int index;
   uint32_t n_units;
+  int variant;     // wide groups: mapping variant
   double bytes, flops;
 };
 
@@ -71,14 +79,22 @@ struct Schedule {
   std::vector<int2> ranges;  // first n_cones: each cone's leading small groups
   std::vector<int> csb, ncb;
   std::vector<FillDesc> fills;
+  std::vector<int32_t> stab;  // serial-offset tables of streaming operands
+  std::vector<uint8_t> uperm; // 32 bytes per group: union bit of each unit bit
   std::vector<std::vector<Task>> cone_tasks;  // after the leading small groups
   int n_cones = 0, n_nets = 0, n_angles = 0;
   size_t off_res = 0, off_angles = 0, off_desc = 0, off_fills = 0, off_groups = 0,
-         off_ops = 0, off_ranges = 0, off_csb = 0, off_ncb = 0, off_data = 0, total = 0;
+         off_ops = 0, off_stab = 0, off_uperm = 0, off_ranges = 0, off_csb = 0, off_ncb = 0, off_data = 0, total = 0;
   int64_t scalar_off = 0;
   std::vector<char> desc_blob;  // bytes [off_desc, off_data)
   double bytes[QTN_NKERNELS] = {}, flops[QTN_NKERNELS] = {};
   double init_bytes = 0, init_flops = 0;
+  // persistent lockstep executor
+  std::vector<int4> items;
+  std::vector<int> step_begin;
+  int n_steps = 0;
+  size_t off_items = 0, off_steps = 0, off_ctl = 0;
+  int n_ctl = 0;
 };
 
 // Streams, events, pinned staging and the captured graph of one schedule.
@@ -93,6 +109,8 @@ struct Runtime {
   void *ws = nullptr;  // workspace holding the uploaded descriptors
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
+  int persist_blocks[2] = {0, 0};
+  uint32_t *pinned_err = nullptr;
 
   void release() {
     if (exec) (void)hipGraphExecDestroy(exec);
@@ -107,6 +125,9 @@ struct Runtime {
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (main) (void)hipStreamDestroy(main);
     if (pinned) (void)hipHostFree(pinned);
+    if (pinned_err) (void)hipHostFree(pinned_err);
+    pinned_err = nullptr;
+    persist_blocks[0] = persist_blocks[1] = 0;
     ev_in = ev_fork = nullptr;
     main = nullptr;
     pinned = nullptr;
@@ -120,6 +141,8 @@ struct Runtime {
 struct Exec {
   Schedule sched;
   Runtime rt;
+  bool persistent = false;
+  uint32_t spin_limit = 1u << 26;
 };
 
 }  // namespace
@@ -131,6 +154,11 @@ struct qtn_network {
   PlanOptions opt;
   int n_streams = 4;
   bool eager = false;
+  int lane_sum_bits = 2;  // streaming: summed bits spread over lanes
+  int order_trials = 0;   // >1: best of this many randomized min-fill orders
+  int executor = 0;       // 0 streams + per-group launches, 1 persistent lockstep
+  uint32_t spin_limit = 1u << 26;
+  int variant = 0;        // 0 auto, 1 generic only, 2 streaming where possible
   std::vector<LightCone> cones;
   std::vector<std::vector<int>> minfill;
   std::mutex minfill_lock;
@@ -139,6 +167,7 @@ struct qtn_network {
   uint64_t version = 0;
   std::vector<ConePlan> plans;
   std::unique_ptr<Exec> exec;
+  std::vector<qtn_launch_rec> launch_log;
 };
 
 namespace {
@@ -208,11 +237,12 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S) {
       auto close_segment = [&](int end) {
         if (open_begin < 0) return;
         s.ranges.push_back(make_int2(open_begin, end));
-        tasks.push_back({QTN_K_BLOCK, (int)s.ranges.size() - 1, 0, seg_bytes, seg_flops});
+        tasks.push_back({QTN_K_BLOCK, (int)s.ranges.size() - 1, 0, 0, seg_bytes, seg_flops});
         open_begin = -1;
         seg_bytes = seg_flops = 0;
       };
       for (const Group &G : pl.groups) {
+        if (G.ops.size() > 255) return set_err(QTN_ERANGE, "bucket with more than 255 tensors");
         DevGroup dg;
         std::memset(&dg, 0, sizeof dg);
         dg.out_off = G.out_tensor >= 0 ? arena + pl.tensors[G.out_tensor].offset
@@ -221,11 +251,92 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S) {
         dg.w = (uint8_t)G.w;
         dg.L = (uint8_t)G.L;
         dg.n_ops = (uint8_t)G.ops.size();
-        dg.n_units = G.w > kRegBits + kLaneBits ? 1u << (G.w - kRegBits - kLaneBits) : 1u;
-        if (G.ops.size() > 255) return set_err(QTN_ERANGE, "bucket with more than 255 tensors");
         double in_el = 0;
         std::vector<int> per_level(G.L, 0);
         for (const Operand &o : G.ops) {
+          per_level[o.level]++;
+          in_el += std::ldexp(1.0, (int)pl.tensors[o.tensor].vars.size());
+        }
+        // streaming mapping unless the group is too large for its LDS tables
+        const int rls = std::min(G.L - 1, net->lane_sum_bits);
+        const int sl = G.L - 1 - rls;
+        const bool stream_ok = (int)G.ops.size() <= kStreamMaxOps && sl <= kStreamMaxSerial;
+        // auto: the streaming mapping pays off once a lane walks >= 2 serial bits
+        const bool stream = stream_ok && (net->variant == 2 || (net->variant == 0 && sl >= 2));
+        std::vector<int> order(G.ops.size());
+        std::vector<int> cls(G.ops.size(), 0);
+        for (size_t k = 0; k < G.ops.size(); k++) order[k] = (int)k;
+        if (stream) {
+          dg.variant = kVarStream;
+          dg.rls = (uint8_t)rls;
+          dg.sl = (uint8_t)sl;
+          dg.lk = (uint8_t)(6 - rls);
+          const uint32_t serial_bits = ((1u << G.L) - 1u) & ~((1u << (1 + rls)) - 1u);
+          const uint32_t lane_bits = (((1u << rls) - 1u) << 1) |
+                                     (uint32_t)((((1ull << dg.lk) - 1ull) << G.L) & 0xFFFFFFFFull);
+          for (size_t k = 0; k < G.ops.size(); k++) {
+            const Operand &o = G.ops[k];
+            if (o.level >= 1 + rls)
+              cls[k] = (o.mask & lane_bits) ? kClsSerial : kClsUniform;
+            else
+              cls[k] = (o.mask & serial_bits) ? kClsStep : kClsUnit;
+          }
+          // step-class operands with bit 0 first: they fill the unrolled slots
+          std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+            if (cls[a] != cls[b]) return cls[a] < cls[b];
+            if (cls[a] == kClsStep) return (G.ops[a].mask & 1u) > (G.ops[b].mask & 1u);
+            return false;
+          });
+          int nu = 0, ns = 0, nun = 0, nse = 0, ns0 = 0;
+          for (int k : order) {
+            if (cls[k] == kClsUnit) nu++;
+            else if (cls[k] == kClsStep) {
+              ns++;
+              ns0 += (G.ops[k].mask & 1u) ? 1 : 0;
+            }
+            else if (cls[k] == kClsUniform) nun++;
+            else nse++;
+          }
+          dg.n_unit = (uint8_t)nu;
+          dg.n_step = (uint8_t)ns;
+          dg.n_step0 = (uint8_t)ns0;
+          dg.n_serial = (uint8_t)(nun + nse);
+          dg.level_end[0] = (uint8_t)nun;
+          const int kept_lanes = G.L + dg.lk;
+          dg.n_units = G.w > kept_lanes ? 1u << (G.w - kept_lanes) : 1u;
+        } else {
+          dg.variant = kVarGeneric;
+          std::stable_sort(order.begin(), order.end(),
+                           [&](int a, int b) { return G.ops[a].level < G.ops[b].level; });
+          int cum = 0;
+          for (int l = 0; l < kMaxLevels; l++) {
+            if (l < G.L) cum += per_level[l];
+            dg.level_end[l] = (uint8_t)cum;
+          }
+          const int bits = kGenRegBits + 6;
+          dg.n_units = G.w > bits ? 1u << (G.w - bits) : 1u;
+        }
+        // wave-unit bits, those that large operands lack first (their data is
+        // then reused by neighbouring units of the same block and XCD)
+        {
+          const int start = stream ? G.L + dg.lk : kGenRegBits + 6;
+          std::vector<std::pair<double, int>> sc;
+          for (int b = start; b < G.w; b++) {
+            double miss = 0;
+            for (const Operand &o : G.ops)
+              if (pl.tensors[o.tensor].gate < 0 && !((o.mask >> b) & 1u))
+                miss += std::ldexp(1.0, (int)pl.tensors[o.tensor].vars.size());
+            sc.push_back({-miss, b});
+          }
+          std::stable_sort(sc.begin(), sc.end());
+          uint8_t up[32];
+          std::memset(up, 0, sizeof up);
+          for (size_t j = 0; j < sc.size(); j++) up[j] = (uint8_t)sc[j].second;
+          dg.n_ubits = (uint8_t)sc.size();
+          s.uperm.insert(s.uperm.end(), up, up + 32);
+        }
+        for (int k : order) {
+          const Operand &o = G.ops[k];
           const Tensor &t = pl.tensors[o.tensor];
           DevOp d;
           std::memset(&d, 0, sizeof d);
@@ -233,15 +344,20 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S) {
                               : arena + t.offset;
           d.mask = o.mask;
           d.level = (uint8_t)o.level;
-          d.nruns = (uint8_t)mask_runs(o.mask, d.rs, d.rl, d.rd);
+          uint8_t rs[32], rl[32], rd[32];
+          const int nr = mask_runs(o.mask, rs, rl, rd);
+          if (nr > kOpRuns) return set_err(QTN_ERANGE, "operand index set too fragmented");
+          d.nruns = (uint8_t)nr;
+          for (int r = 0; r < nr; r++)
+            d.run[r] = (uint16_t)(rs[r] | (rl[r] << 5) | (rd[r] << 11));
+          d.cls = (uint8_t)cls[k];
+          d.stab = -1;
+          if (stream && cls[k] != kClsUnit) {
+            d.stab = (int32_t)s.stab.size();
+            for (uint32_t st = 0; st < (1u << dg.sl); st++)
+              s.stab.push_back((int32_t)pext32(st << (1 + dg.rls), o.mask));
+          }
           s.ops.push_back(d);
-          per_level[o.level]++;
-          in_el += std::ldexp(1.0, (int)t.vars.size());
-        }
-        int cum = 0;
-        for (int l = 0; l < kMaxLevels; l++) {
-          if (l < G.L) cum += per_level[l];
-          dg.level_end[l] = (uint8_t)cum;
         }
         double gb = s.elem * (in_el + std::ldexp(1.0, G.w - G.L)), gf = 0;
         for (int l = 0; l < G.L; l++) {
@@ -257,7 +373,7 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S) {
           seg_flops += gf;
         } else {
           close_segment(gid);
-          tasks.push_back({QTN_K_WIDE, gid, dg.n_units, gb, gf});
+          tasks.push_back({QTN_K_WIDE, gid, dg.n_units, dg.variant, gb, gf});
         }
       }
       close_segment((int)s.groups.size());
@@ -284,6 +400,40 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S) {
       if (t.kind == QTN_K_BLOCK) t.index += s.n_cones;
   s.ranges.insert(s.ranges.begin(), lead.begin(), lead.end());
   s.n_nets = n;
+  // lockstep steps: the j-th task of every cone (leading segment first)
+  {
+    std::vector<std::vector<int4>> per_step;
+    for (int cn = 0; cn < s.n_cones; cn++) {
+      int j = 0;
+      auto put = [&](const int4 &it) {
+        if ((int)per_step.size() <= j) per_step.resize(j + 1);
+        per_step[j].push_back(it);
+      };
+      if (lead[cn].y > lead[cn].x) {
+        put(make_int4(lead[cn].x, lead[cn].y, 0, 0));
+        j++;
+      }
+      for (const Task &t : s.cone_tasks[cn]) {
+        if (t.kind == QTN_K_BLOCK) {
+          const int2 r = s.ranges[t.index];
+          put(make_int4(r.x, r.y, 0, 0));
+        } else {
+          const uint32_t nu = t.n_units;
+          uint32_t chunk = std::max<uint32_t>(4u, nu / 2048u);
+          for (uint32_t u = 0; u < nu; u += chunk)
+            put(make_int4(t.index, -1, (int)u, (int)std::min(nu, u + chunk)));
+        }
+        j++;
+      }
+    }
+    s.step_begin.push_back(0);
+    for (auto &v : per_step) {
+      s.items.insert(s.items.end(), v.begin(), v.end());
+      s.step_begin.push_back((int)s.items.size());
+    }
+    s.n_steps = (int)per_step.size();
+    s.n_ctl = 4 + s.n_steps;
+  }
   s.bytes[QTN_K_BLOCK] = s.init_bytes;
   s.flops[QTN_K_BLOCK] = s.init_flops;
   for (auto &tk : s.cone_tasks)
@@ -299,10 +449,15 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S) {
   s.off_fills = s.off_desc;
   s.off_groups = align_up(s.off_fills + sizeof(FillDesc) * s.fills.size(), 256);
   s.off_ops = align_up(s.off_groups + sizeof(DevGroup) * s.groups.size(), 256);
-  s.off_ranges = align_up(s.off_ops + sizeof(DevOp) * s.ops.size(), 256);
+  s.off_stab = align_up(s.off_ops + sizeof(DevOp) * s.ops.size(), 256);
+  s.off_uperm = align_up(s.off_stab + sizeof(int32_t) * s.stab.size(), 256);
+  s.off_ranges = align_up(s.off_uperm + s.uperm.size(), 256);
   s.off_csb = align_up(s.off_ranges + sizeof(int2) * s.ranges.size(), 256);
   s.off_ncb = align_up(s.off_csb + sizeof(int) * s.csb.size(), 256);
-  s.off_data = align_up(s.off_ncb + sizeof(int) * s.ncb.size(), 256);
+  s.off_items = align_up(s.off_ncb + sizeof(int) * s.ncb.size(), 256);
+  s.off_steps = align_up(s.off_items + sizeof(int4) * s.items.size(), 256);
+  s.off_ctl = align_up(s.off_steps + sizeof(int) * s.step_begin.size(), 256);
+  s.off_data = align_up(s.off_ctl + sizeof(uint32_t) * s.n_ctl, 256);
   s.total = s.off_data + (size_t)data * s.elem;
   s.desc_blob.assign(s.off_data - s.off_desc, 0);
   auto put = [&](size_t off, const void *src, size_t bytes) {
@@ -311,9 +466,13 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S) {
   put(s.off_fills, s.fills.data(), sizeof(FillDesc) * s.fills.size());
   put(s.off_groups, s.groups.data(), sizeof(DevGroup) * s.groups.size());
   put(s.off_ops, s.ops.data(), sizeof(DevOp) * s.ops.size());
+  put(s.off_stab, s.stab.data(), sizeof(int32_t) * s.stab.size());
+  put(s.off_uperm, s.uperm.data(), s.uperm.size());
   put(s.off_ranges, s.ranges.data(), sizeof(int2) * s.ranges.size());
   put(s.off_csb, s.csb.data(), sizeof(int) * s.csb.size());
   put(s.off_ncb, s.ncb.data(), sizeof(int) * s.ncb.size());
+  put(s.off_items, s.items.data(), sizeof(int4) * s.items.size());
+  put(s.off_steps, s.step_begin.data(), sizeof(int) * s.step_begin.size());
   return QTN_OK;
 }
 
@@ -334,6 +493,11 @@ int ensure_runtime(Runtime &rt, int n_streams, int n_res) {
     }
     QTN_HIP(hipEventCreateWithFlags(&rt.ev_in, hipEventDisableTiming));
     QTN_HIP(hipEventCreateWithFlags(&rt.ev_fork, hipEventDisableTiming));
+    QTN_HIP(hipHostMalloc((void **)&rt.pinned_err, 4 * sizeof(uint32_t), hipHostMallocDefault));
+    int n_cu = 0;
+    QTN_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    rt.persist_blocks[0] = persistent_blocks(kPrecC128, n_cu);
+    rt.persist_blocks[1] = persistent_blocks(kPrecC64, n_cu);
   }
   if (rt.pinned_n < (size_t)n_res) {
     if (rt.pinned) QTN_HIP(hipHostFree(rt.pinned));
@@ -349,11 +513,14 @@ struct Timer {
   struct Rec {
     int kind;
     hipEvent_t a, b;
+    int group, n_groups;
+    double bytes, flops;
   };
   std::vector<Rec> recs;
-  int begin(int kind, hipStream_t s) {
+  int begin(int kind, hipStream_t s, int group = -1, int n_groups = 0, double bytes = 0,
+            double flops = 0) {
     if (!on) return QTN_OK;
-    Rec r{kind, nullptr, nullptr};
+    Rec r{kind, nullptr, nullptr, group, n_groups, bytes, flops};
     QTN_HIP(hipEventCreate(&r.a));
     QTN_HIP(hipEventCreate(&r.b));
     QTN_HIP(hipEventRecord(r.a, s));
@@ -382,13 +549,30 @@ int enqueue(Exec &X, Timer &tm) {
   auto *groups = (const DevGroup *)(ws + s.off_groups);
   auto *ops = (const DevOp *)(ws + s.off_ops);
   auto *ranges = (const int2 *)(ws + s.off_ranges);
+  auto *stab = (const int32_t *)(ws + s.off_stab);
+  auto *uperm = (const uint8_t *)(ws + s.off_uperm);
   int rc;
   if ((rc = tm.begin(QTN_K_FILL, rt.main))) return rc;
   QTN_HIP(launch_fill(s.prec, data, (const double *)(ws + s.off_angles),
                       (const FillDesc *)(ws + s.off_fills), s.n_nets, rt.main));
   if ((rc = tm.end(rt.main))) return rc;
-  if ((rc = tm.begin(QTN_K_BLOCK, rt.main))) return rc;
-  QTN_HIP(launch_block_groups(s.prec, data, groups, ops, ranges, 0, s.n_cones, rt.main));
+  if (X.persistent) {
+    const int nb = rt.persist_blocks[s.prec == kPrecC128 ? 0 : 1];
+    if (nb < 1) return set_err(QTN_EDEVICE, "persistent kernel does not fit on the device");
+    double b_all = 0, f_all = 0;
+    for (int k = 0; k < QTN_NKERNELS; k++) {
+      b_all += s.bytes[k];
+      f_all += s.flops[k];
+    }
+    if ((rc = tm.begin(QTN_K_PERSISTENT, rt.main, 0, (int)s.groups.size(), b_all, f_all))) return rc;
+    QTN_HIP(launch_persistent(s.prec, data, groups, ops, stab, uperm, (const int4 *)(ws + s.off_items),
+                              (const int *)(ws + s.off_steps), s.n_steps,
+                              (uint32_t *)(ws + s.off_ctl), s.n_ctl, nb, X.spin_limit, rt.main));
+    if ((rc = tm.end(rt.main))) return rc;
+  } else {
+  if ((rc = tm.begin(QTN_K_BLOCK, rt.main, 0, (int)s.groups.size(), s.init_bytes, s.init_flops)))
+    return rc;
+  QTN_HIP(launch_block_groups(s.prec, data, groups, ops, stab, uperm, ranges, 0, s.n_cones, rt.main));
   if ((rc = tm.end(rt.main))) return rc;
   const int K = (int)rt.side.size();
   bool any = false;
@@ -411,11 +595,13 @@ int enqueue(Exec &X, Timer &tm) {
       load[st] += cost[c];
       hipStream_t hs = rt.side[st];
       for (auto &t : s.cone_tasks[c]) {
-        if ((rc = tm.begin(t.kind, hs))) return rc;
+        const int g0 = t.kind == QTN_K_BLOCK ? s.ranges[t.index].x : t.index;
+        const int ng = t.kind == QTN_K_BLOCK ? s.ranges[t.index].y - s.ranges[t.index].x : 1;
+        if ((rc = tm.begin(t.kind, hs, g0, ng, t.bytes, t.flops))) return rc;
         if (t.kind == QTN_K_BLOCK)
-          QTN_HIP(launch_block_groups(s.prec, data, groups, ops, ranges, t.index, 1, hs));
+          QTN_HIP(launch_block_groups(s.prec, data, groups, ops, stab, uperm, ranges, t.index, 1, hs));
         else
-          QTN_HIP(launch_wide_group(s.prec, data, groups, ops, t.index, t.n_units, hs));
+          QTN_HIP(launch_wide_group(s.prec, t.variant, data, groups, ops, stab, uperm, t.index, t.n_units, hs));
         if ((rc = tm.end(hs))) return rc;
       }
     }
@@ -423,6 +609,7 @@ int enqueue(Exec &X, Timer &tm) {
       QTN_HIP(hipEventRecord(rt.ev_join[i], rt.side[i]));
       QTN_HIP(hipStreamWaitEvent(rt.main, rt.ev_join[i], 0));
     }
+  }
   }
   if ((rc = tm.begin(QTN_K_REDUCE, rt.main))) return rc;
   QTN_HIP(launch_reduce(s.prec, data, s.scalar_off, (const int *)(ws + s.off_csb),
@@ -488,7 +675,12 @@ int run_exec(Exec &X, const std::vector<const qtn_network *> &nets, void *ws, si
   }
   QTN_HIP(hipMemcpyAsync(rt.pinned, (char *)ws + s.off_res, sizeof(double) * n_res,
                          hipMemcpyDeviceToHost, rt.main));
+  if (X.persistent)
+    QTN_HIP(hipMemcpyAsync(rt.pinned_err, (char *)ws + s.off_ctl, 4 * sizeof(uint32_t),
+                           hipMemcpyDeviceToHost, rt.main));
   QTN_HIP(hipStreamSynchronize(rt.main));
+  if (X.persistent && rt.pinned_err[2] != 0)
+    return set_err(QTN_EDEVICE, "persistent executor: a grid barrier wait exceeded its bound");
   res.assign(rt.pinned, rt.pinned + n_res);
   return QTN_OK;
 }
@@ -533,6 +725,17 @@ int qtn_network_build(int32_t n_vertices, int64_t n_edges, const int32_t *edges,
         return set_err(QTN_EINVAL, "n_streams must be in 0..16");
       if (cfg->n_streams) net->n_streams = cfg->n_streams;
       net->eager = cfg->eager != 0;
+      if (cfg->lane_sum_bits < 0 || cfg->lane_sum_bits > 5)
+        return set_err(QTN_EINVAL, "lane_sum_bits must be in 0..5");
+      if (cfg->lane_sum_bits) net->lane_sum_bits = cfg->lane_sum_bits;
+      if (cfg->variant < 0 || cfg->variant > 2) return set_err(QTN_EINVAL, "variant must be 0..2");
+      net->variant = cfg->variant;
+      if (cfg->order_trials < 0 || cfg->order_trials > 4096)
+        return set_err(QTN_EINVAL, "order_trials must be in 0..4096");
+      net->order_trials = cfg->order_trials;
+      if (cfg->executor < 0 || cfg->executor > 2) return set_err(QTN_EINVAL, "executor must be 0..2");
+      net->executor = cfg->executor;
+      if (cfg->spin_limit > 0) net->spin_limit = (uint32_t)cfg->spin_limit;
     }
     const int m = (int)n_edges;
     net->cones.resize(m);
@@ -604,6 +807,8 @@ int qtn_plan(qtn_network *net, const int32_t *const *orders, int32_t precision,
       std::vector<int> ord;
       if (orders && orders[e])
         ord.assign(orders[e], orders[e] + net->cones[e].n_vars);
+      else if (net->order_trials > 1)
+        ord = search_order(net->cones[e], net->order_trials);
       else
         ord = get_minfill(net, e);
       errs[e] = plan_cone(net->cones[e], ord, o, &plans[e]);
@@ -624,6 +829,8 @@ int qtn_plan(qtn_network *net, const int32_t *const *orders, int32_t precision,
       return rc;
     }
     drop_batches_with(net);
+    ex->persistent = net->executor == 2;
+    ex->spin_limit = net->spin_limit;
     net->exec = std::move(ex);
     net->planned = true;
     net->version++;
@@ -655,15 +862,41 @@ static int contract_impl(qtn_network *net, void *ws, size_t bytes, void *stream,
     qtn_timing t;
     std::memset(&t, 0, sizeof t);
     if (timing) {
+      net->launch_log.clear();
+      const Schedule &sc = net->exec->sched;
       for (auto &r : tm.recs) {
         float ms = 0;
         QTN_HIP(hipEventElapsedTime(&ms, r.a, r.b));
         t.ms[r.kind] += ms;
         t.launches[r.kind]++;
+        qtn_launch_rec lr;
+        std::memset(&lr, 0, sizeof lr);
+        lr.kind = r.kind;
+        lr.group = r.group;
+        lr.n_groups = r.n_groups;
+        lr.ms = ms;
+        lr.bytes = r.bytes;
+        lr.flops = r.flops;
+        if (r.group >= 0 && r.group < (int)sc.groups.size()) {
+          const DevGroup &g = sc.groups[r.group];
+          lr.w = g.w;
+          lr.L = g.L;
+          lr.n_ops = g.n_ops;
+          lr.variant = g.variant;
+          lr.n_units = (int32_t)g.n_units;
+        }
+        net->launch_log.push_back(lr);
       }
       for (int k = 0; k < QTN_NKERNELS; k++) {
         t.bytes[k] = net->exec->sched.bytes[k];
         t.flops[k] = net->exec->sched.flops[k];
+      }
+      if (net->exec->persistent) {
+        for (int k = 0; k < QTN_K_PERSISTENT; k++) {
+          t.bytes[QTN_K_PERSISTENT] += t.bytes[k];
+          t.flops[QTN_K_PERSISTENT] += t.flops[k];
+          t.bytes[k] = t.flops[k] = 0;
+        }
       }
     }
     const int m = net->exec->sched.n_cones;
@@ -708,6 +941,8 @@ static Exec *batch_exec(qtn_network *const *nets, int32_t n, int *rc) {
   auto ex = std::make_unique<Exec>();
   *rc = build_schedule(nets, n, &ex->sched);
   if (*rc) return nullptr;
+  ex->persistent = nets[0]->executor != 1;  // batches default to the persistent executor
+  ex->spin_limit = nets[0]->spin_limit;
   Exec *raw = ex.get();
   g_batch[key] = std::move(ex);
   return raw;
@@ -748,6 +983,15 @@ int qtn_contract_batch(qtn_network *const *nets, int32_t n, void *d_workspace, s
   }
 }
 
+int qtn_launch_log(const qtn_network *net, int64_t cap, qtn_launch_rec *out, int64_t *n_out) {
+  if (!net || !n_out || (cap > 0 && !out)) return set_err(QTN_EINVAL, "NULL argument");
+  const auto &lg = net->launch_log;
+  const int64_t n = std::min<int64_t>(cap, (int64_t)lg.size());
+  for (int64_t i = 0; i < n; i++) out[i] = lg[i];
+  *n_out = (int64_t)lg.size();
+  return QTN_OK;
+}
+
 int qtn_get_plan_stats(const qtn_network *net, qtn_plan_stats *out) {
   if (!net || !out) return set_err(QTN_EINVAL, "NULL argument");
   if (!net->planned) return set_err(QTN_ESTATE, "qtn_plan has not been called");
@@ -769,6 +1013,15 @@ int qtn_get_plan_stats(const qtn_network *net, qtn_plan_stats *out) {
   }
   st.workspace = s.total;
   *out = st;
+  return QTN_OK;
+}
+
+int qtn_plan_order(const qtn_network *net, int64_t edge, int32_t *order_out) {
+  if (!net || !order_out) return set_err(QTN_EINVAL, "NULL argument");
+  if (!net->planned) return set_err(QTN_ESTATE, "qtn_plan has not been called");
+  if (edge < 0 || edge >= (int64_t)net->plans.size()) return set_err(QTN_EINVAL, "edge out of range");
+  const auto &o = net->plans[edge].order;
+  std::copy(o.begin(), o.end(), order_out);
   return QTN_OK;
 }
 

@@ -12,28 +12,53 @@
 
 namespace qtn {
 
+constexpr int kOpRuns = 16;
+
+// Operand classes of the streaming mapping (see kernels.hip):
+enum OpClass : uint8_t {
+  kClsUnit = 0,     // leaf level, no serial bit: constant over a unit's walk
+  kClsStep = 1,     // leaf level with serial bits: read at every serial step
+  kClsUniform = 2,  // serial level, no lane bit: one table U(s) per unit
+  kClsSerial = 3,   // serial level with lane bits: read at every serial step
+};
+
 struct DevOp {          // 64 bytes
   int64_t off;          // element offset of the operand from the data base
   uint32_t mask;        // union bits the operand carries
+  int32_t stab;         // first entry of its serial-offset table (streaming)
   uint8_t level;        // multiplied in after `level` indices are summed
   uint8_t nruns;        // contiguous runs of `mask`
-  uint8_t pad[2];
-  uint8_t rs[16];       // run start bit in I
-  uint8_t rl[16];       // run length
-  uint8_t rd[16];       // run start bit in the operand offset
+  uint8_t cls;          // OpClass (streaming)
+  uint8_t pad;
+  uint16_t run[kOpRuns];  // src | len << 5 | dst << 11 : pext by runs
+  uint8_t pad2[12];
 };
 
-struct DevGroup {       // 32 bytes
+struct DevGroup {       // 48 bytes
   int64_t out_off;      // element offset of the output (or scalar slot)
   int32_t op_begin;     // first DevOp of the group
-  uint32_t n_units;     // wave units: 2^max(0, w - units_shift)
-  uint8_t w, L, n_ops, pad;
-  uint8_t level_end[8]; // ops of levels 0..l end at op_begin + level_end[l]
-  uint8_t pad2[4];
+  uint32_t n_units;     // wave units
+  uint8_t w, L, n_ops, variant;   // variant: kVarGeneric / kVarStream
+  uint8_t rls, sl, lk, n_unit;    // streaming: lane-summed bits, serial bits,
+                                  // lane-kept bits, kClsUnit op count
+  uint8_t n_step, n_serial, n_step0, pad;  // n_step0: step-class ops with bit 0
+  uint8_t level_end[8]; // generic: ops of levels <= l end at level_end[l];
+                        // streaming: level_end[0] = uniform-class count; the
+                        // n_serial - level_end[0] serial-class ops follow
+  uint8_t n_ubits;      // wave-unit bits (their union positions: uperm)
+  uint8_t pad2[7];
 };
 
 static_assert(sizeof(DevOp) == 64, "DevOp layout");
-static_assert(sizeof(DevGroup) == 32, "DevGroup layout");
+static_assert(sizeof(DevGroup) == 48, "DevGroup layout");
+
+enum Variant : uint8_t { kVarGeneric = 0, kVarStream = 1 };
+
+// Generic mapping: 2 register bits and 6 lane bits per wave unit.
+constexpr int kGenRegBits = 2;
+// Streaming mapping: at most this many operands per group (LDS lane tables).
+constexpr int kStreamMaxOps = 96;
+constexpr int kStreamMaxSerial = 6;
 
 // Gate table layout (elements): per layer l, 8 blocks of 4 at 32*l:
 // P, P^T, Pc, Pc^T, R, R^T, Rc, Rc^T (row-major over the gate's own axes,

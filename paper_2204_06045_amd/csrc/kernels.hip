@@ -3,15 +3,28 @@
 // Bucket elimination (arXiv 2204.06045, Sec. II-B) contracts a bucket by
 // multiplying its tensors over the union of their binary indices and summing
 // the bucket index; merged indices (Sec. II-C) sum several nested buckets in
-// one pass.  A fused group here is such a chain of L buckets: with the union
-// index I (bit 0 = first bucket index), level-l operands are multiplied in
-// after bits 0..l-1 have been summed, and the group writes out[I >> L].
+// one pass.  A fused group is such a chain of L buckets over the union index I
+// (bit 0 = first bucket index): level-l operands are multiplied in after bits
+// 0..l-1 are summed, and the group writes out[I >> L].  Every operand t is
+// read at pext(I, mask_t).
 //
-// Thread mapping (wave64): a wave evaluates one unit of 2^(RG+6) union points;
-// bits [0, RG) are held in registers by each lane, bits [RG, RG+6) select the
-// lane, the rest select the unit.  Summed bits in registers are added in
-// registers; summed lane bits are added with cross-lane butterflies.  Operand
-// t is read at pext(I, mask_t), computed from the contiguous runs of the mask.
+// Two thread mappings (wave64):
+//
+// Streaming (kVarStream).  Bit 0 lives in registers (two points per lane);
+// the next `rls` summed bits select lanes (contiguous operand runs per lane
+// group, summed at the end with cross-lane butterflies); the remaining `sl`
+// summed bits are walked serially by each lane; the kept bits select the
+// other `lk` lanes and the wave unit.  Operand offsets split into a lane part
+// (pext of the lane bits, staged once per group in LDS), a unit part (pext of
+// the unit bits, wave-uniform, scalar ALU) and a serial part (per-step table
+// built by the planner), so the inner loop is loads and complex FMAs.  The
+// group's sum is taken flat: a level-l operand does not depend on bits 0..l-1,
+// so multiplying it in before those bits are summed gives the same sum; the
+// nesting only decides how often each factor is applied.
+//
+// Generic (kVarGeneric).  2 register bits and 6 lane bits per unit, every
+// level in hierarchical order with register adds and lane butterflies.  Used
+// for groups with more operands than the streaming LDS tables hold.
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -19,8 +32,8 @@
 namespace qtn {
 namespace {
 
-constexpr int RG = 2;  // register bits per lane
 constexpr int kBlock = 256;
+constexpr int kStepOps = 4;  // step-class operands unrolled in the serial loop
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
@@ -50,20 +63,34 @@ template <> __device__ __forceinline__ float2 make_c<float2>(double re, double i
 __device__ __forceinline__ double2 to_d(double2 v) { return v; }
 __device__ __forceinline__ double2 to_d(float2 v) { return make_double2(v.x, v.y); }
 
-// pext over the operand's mask, from its runs (uniform per wave).
+// pext(x, mask) from the operand's packed runs (wave-uniform loop bounds).
 __device__ __forceinline__ uint32_t pext_runs(uint32_t x, const DevOp &o) {
   uint32_t r = 0;
   const int nr = o.nruns;
-  for (int i = 0; i < nr; i++)
-    r |= ((x >> o.rs[i]) & (uint32_t)((1ull << o.rl[i]) - 1ull)) << o.rd[i];
+  for (int i = 0; i < nr; i++) {
+    const uint32_t rr = o.run[i];
+    const uint32_t src = rr & 31u, len = (rr >> 5) & 63u, dst = rr >> 11;
+    r |= ((x >> src) & (uint32_t)((1ull << len) - 1ull)) << dst;
+  }
   return r;
 }
 
-// pext of a register-field value x < 2^RG over the low RG mask bits.
+// Union bits of wave unit u: bit j of u goes to union bit ubit[j] (the
+// planner orders the unit bits so that bits some large operand lacks come
+// first, and units that reuse an operand's data run next to each other).
+__device__ __forceinline__ uint32_t unit_bits(uint32_t u, const uint8_t *__restrict__ ubit,
+                                              int n) {
+  uint32_t I = 0;
+  for (int j = 0; j < n; j++) I |= ((u >> j) & 1u) << ubit[j];
+  return I;
+}
+
+// ------------------------------------------------------------------ generic
+
 __device__ __forceinline__ uint32_t pext_reg(uint32_t x, uint32_t m) {
   uint32_t r = 0, d = 0;
 #pragma unroll
-  for (int b = 0; b < RG; b++)
+  for (int b = 0; b < kGenRegBits; b++)
     if ((m >> b) & 1u) {
       r |= ((x >> b) & 1u) << d;
       d++;
@@ -72,15 +99,13 @@ __device__ __forceinline__ uint32_t pext_reg(uint32_t x, uint32_t m) {
 }
 
 template <class T>
-__device__ __forceinline__ void eval_unit(const DevGroup &G, const DevOp *__restrict__ ops,
-                                          T *__restrict__ data, uint32_t u, int lane) {
-  constexpr int NR = 1 << RG;
-  const uint32_t I0 = (u << (RG + 6)) | ((uint32_t)lane << RG);
+__device__ __forceinline__ void generic_unit(const DevGroup &G, const DevOp *__restrict__ gops,
+                                             const uint8_t *__restrict__ ubit, T *__restrict__ data,
+                                             uint32_t u, int lane) {
+  constexpr int RG = kGenRegBits, NR = 1 << RG;
+  const uint32_t I0 = unit_bits(u, ubit, G.n_ubits) | ((uint32_t)lane << RG);
   const int L = G.L;
-  const DevOp *gops = ops + G.op_begin;
   T v[NR];
-
-  // level 0: product of the first bucket's tensors at the NR register points
   {
     const DevOp &o = gops[0];
     const uint32_t base = pext_runs(I0, o);
@@ -96,8 +121,6 @@ __device__ __forceinline__ void eval_unit(const DevGroup &G, const DevOp *__rest
 #pragma unroll
     for (int r = 0; r < NR; r++) v[r] = cmul(v[r], src[base + pext_reg(r, o.mask)]);
   }
-
-  // summed bits held in registers
 #pragma unroll
   for (int s = 0; s < RG; s++) {
     if (s < L) {
@@ -115,7 +138,6 @@ __device__ __forceinline__ void eval_unit(const DevGroup &G, const DevOp *__rest
       }
     }
   }
-
   T *out = data + G.out_off;
   const uint32_t nout = 1u << (G.w - L);
   if (L <= RG) {
@@ -125,8 +147,6 @@ __device__ __forceinline__ void eval_unit(const DevGroup &G, const DevOp *__rest
       if (r < (NR >> L) && ob + r < nout) out[ob + r] = v[r];
     return;
   }
-
-  // summed bits spread over lanes: butterflies, then the next level's tensors
   T acc = v[0];
   for (int s = RG; s < L; s++) {
     acc = cadd(acc, shfl_xor2(acc, 1 << (s - RG)));
@@ -143,37 +163,357 @@ __device__ __forceinline__ void eval_unit(const DevGroup &G, const DevOp *__rest
   }
 }
 
+// ---------------------------------------------------------------- streaming
+
+// Lane parts of every operand of the group: pext of the lane bits.
+__device__ __forceinline__ void stream_setup(const DevGroup &G, const DevOp *__restrict__ gops,
+                                             uint32_t *s_lane) {
+  const uint32_t rls = G.rls, L = G.L;
+  for (int e = threadIdx.x; e < G.n_ops * 64; e += blockDim.x) {
+    const int k = e >> 6, lane = e & 63;
+    const uint32_t lo = (uint32_t)lane & ((1u << rls) - 1u), hi = (uint32_t)lane >> rls;
+    s_lane[e] = pext_runs((lo << 1) | (hi << L), gops[k]);
+  }
+}
+
+__device__ __forceinline__ double2 readlane2(double2 v, uint32_t l) {
+  const int2 a = make_int2(__builtin_amdgcn_readlane(__double2loint(v.x), l),
+                           __builtin_amdgcn_readlane(__double2hiint(v.x), l));
+  const int2 b = make_int2(__builtin_amdgcn_readlane(__double2loint(v.y), l),
+                           __builtin_amdgcn_readlane(__double2hiint(v.y), l));
+  return make_double2(__hiloint2double(a.y, a.x), __hiloint2double(b.y, b.x));
+}
+__device__ __forceinline__ float2 readlane2(float2 v, uint32_t l) {
+  return make_float2(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.x), l)),
+                     __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.y), l)));
+}
+
+// A wave-uniform pointer, forced into scalar registers.
+__device__ __forceinline__ const char *uniform_ptr(const void *p) {
+  const uint64_t v = (uint64_t)p;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return (const char *)(((uint64_t)hi << 32) | lo);
+}
+
+// Global load at (scalar base + per-lane byte offset), through a global
+// address-space pointer so the compiler emits global (not flat) loads.
+typedef double nd2 __attribute__((ext_vector_type(2)));
+typedef float nf2 __attribute__((ext_vector_type(2)));
+template <class T> __device__ __forceinline__ T gload(const char *base, uint32_t byte_off);
+template <> __device__ __forceinline__ double2 gload<double2>(const char *base, uint32_t byte_off) {
+  typedef const char __attribute__((address_space(1))) gchar;
+  typedef const nd2 __attribute__((address_space(1))) gv;
+  const nd2 v = *(gv *)((gchar *)base + byte_off);
+  return make_double2(v.x, v.y);
+}
+template <> __device__ __forceinline__ float2 gload<float2>(const char *base, uint32_t byte_off) {
+  typedef const char __attribute__((address_space(1))) gchar;
+  typedef const nf2 __attribute__((address_space(1))) gv;
+  const nf2 v = *(gv *)((gchar *)base + byte_off);
+  return make_float2(v.x, v.y);
+}
+
+// One wave unit of the streaming mapping.  With u fixed, every point's value
+// is the product of
+//   unit-class operands      (no serial bit)        -> c0, c1 once per unit
+//   step-class operands      (leaf level, serial bits) -> loaded each step
+//   uniform-class operands   (serial level, no lane bit) -> table U(s), one
+//                            entry per lane, built once per unit
+//   serial-class operands    (serial level, lane bits)  -> loaded each step
+// summed over bit 0 (registers), the serial bits (this loop) and the
+// lane-summed bits (butterflies).  Operands without bit 0 multiply the pair
+// sum once instead of each point.  Serial offsets of the unrolled operands sit
+// one entry per lane and are read with readlane, so a step's loads issue
+// back to back from scalar bases.
+template <class T>
+__device__ __forceinline__ void stream_unit(const DevGroup &G, const DevOp *__restrict__ gops,
+                                            const int32_t *__restrict__ stab,
+                                            const uint8_t *__restrict__ ubit, T *__restrict__ data,
+                                            const uint32_t *s_lane, uint32_t u, int lane) {
+  constexpr uint32_t ES = sizeof(T);
+  const int L = G.L, rls = G.rls, sl = G.sl, lk = G.lk;
+  const uint32_t Iu = unit_bits(u, ubit, G.n_ubits);
+  const uint32_t nsteps = 1u << sl;
+  const bool lane_step = (uint32_t)lane < nsteps;
+  const T one = make_c<T>(1.0, 0.0);
+  T c0 = one, c1 = one;
+  for (int k = 0; k < G.n_unit; k++) {
+    const DevOp &o = gops[k];
+    const char *p = uniform_ptr(data + o.off + pext_runs(Iu, o));
+    const uint32_t lb = s_lane[k * 64 + lane] * ES;
+    const T x0 = gload<T>(p, lb);
+    const T x1 = gload<T>(p, lb + ((o.mask & 1u) ? ES : 0u));
+    c0 = cmul(c0, x0);
+    c1 = cmul(c1, x1);
+  }
+  // U(s) for s = lane: product of the uniform-class operands at step s
+  const int ku = G.n_unit + G.n_step, ks = ku + G.level_end[0];
+  T U = one;
+  for (int k = ku; k < ks; k++) {
+    const DevOp &o = gops[k];
+    const char *p = uniform_ptr(data + o.off + pext_runs(Iu, o));
+    const uint32_t off = lane_step ? (uint32_t)stab[o.stab + lane] * ES : 0u;
+    U = cmul(U, gload<T>(p, off));
+  }
+  // unrolled step-class operands: scalar base, per-lane byte offset, serial
+  // offsets one per lane
+  const int kb = G.n_unit, n_step = G.n_step;
+  const char *pb[kStepOps];
+  uint32_t lb[kStepOps], tb[kStepOps], h0b[kStepOps];
+  bool h0[kStepOps];
+#pragma unroll
+  for (int i = 0; i < kStepOps; i++) {
+    pb[i] = uniform_ptr(data);
+    lb[i] = 0;
+    tb[i] = 0;
+    h0[i] = false;
+    h0b[i] = 0;
+    if (i < n_step) {
+      const DevOp &o = gops[kb + i];
+      pb[i] = uniform_ptr(data + o.off + pext_runs(Iu, o));
+      lb[i] = s_lane[(kb + i) * 64 + lane] * ES;
+      tb[i] = lane_step ? (uint32_t)stab[o.stab + lane] * ES : 0u;
+      h0[i] = (o.mask & 1u) != 0;
+      h0b[i] = h0[i] ? ES : 0u;
+    }
+  }
+  const int ke = ks + G.n_serial - G.level_end[0];  // end of serial-class ops
+  T acc = make_c<T>(0.0, 0.0);
+  for (uint32_t s = 0; s < nsteps; s++) {
+    T e0[kStepOps], e1[kStepOps];
+#pragma unroll
+    for (int i = 0; i < kStepOps; i++) {
+      e0[i] = one;
+      e1[i] = one;
+      if (i < n_step) {
+        const char *p = pb[i] + __builtin_amdgcn_readlane(tb[i], s);
+        e0[i] = gload<T>(p, lb[i]);
+        e1[i] = gload<T>(p, lb[i] + h0b[i]);
+      }
+    }
+    T v0 = c0, v1 = c1;
+#pragma unroll
+    for (int i = 0; i < kStepOps; i++)
+      if (i < n_step && h0[i]) {
+        v0 = cmul(v0, e0[i]);
+        v1 = cmul(v1, e1[i]);
+      }
+    // step operands past the unrolled slots: those with bit 0 come first
+    const int k_extra = kb + kStepOps, k_h0_end = kb + G.n_step0;
+    for (int k = k_extra; k < k_h0_end; k++) {
+      const DevOp &o = gops[k];
+      const char *p = uniform_ptr(data + o.off + pext_runs(Iu, o) + stab[o.stab + s]);
+      const uint32_t l = s_lane[k * 64 + lane] * ES;
+      v0 = cmul(v0, gload<T>(p, l));
+      v1 = cmul(v1, gload<T>(p, l + ES));
+    }
+    T x = cadd(v0, v1);  // bit 0 summed in registers
+#pragma unroll
+    for (int i = 0; i < kStepOps; i++)
+      if (i < n_step && !h0[i]) x = cmul(x, e0[i]);
+    for (int k = max(k_extra, k_h0_end); k < kb + n_step; k++) {
+      const DevOp &o = gops[k];
+      const char *p = uniform_ptr(data + o.off + pext_runs(Iu, o) + stab[o.stab + s]);
+      x = cmul(x, gload<T>(p, s_lane[k * 64 + lane] * ES));
+    }
+    if (sl > 0) x = cmul(x, readlane2(U, s));
+    for (int k = ks; k < ke; k++) {
+      const DevOp &o = gops[k];
+      const char *p = uniform_ptr(data + o.off + pext_runs(Iu, o) + stab[o.stab + s]);
+      x = cmul(x, gload<T>(p, s_lane[k * 64 + lane] * ES));
+    }
+    acc = cadd(acc, x);
+  }
+  // lane-summed bits: butterflies
+  for (int b = 0; b < rls; b++) acc = cadd(acc, shfl_xor2(acc, 1 << b));
+  if ((lane & ((1 << rls) - 1)) == 0) {
+    const uint32_t o = (Iu >> L) | ((uint32_t)lane >> rls);
+    if (o < (1u << (G.w - L))) data[G.out_off + o] = acc;
+  }
+}
+
+// ------------------------------------------------------------------ kernels
+
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_block_groups(T *__restrict__ data,
                                                          const DevGroup *__restrict__ groups,
                                                          const DevOp *__restrict__ ops,
+                                                         const int32_t *__restrict__ stab,
+                                                         const uint8_t *__restrict__ uperm,
                                                          const int2 *__restrict__ ranges,
                                                          int range_base) {
+  __shared__ uint32_t s_lane[kStreamMaxOps * 64];
   const int2 rg = ranges[range_base + blockIdx.x];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int nw = blockDim.x >> 6;
   for (int g = rg.x; g < rg.y; g++) {
-    const DevGroup G = groups[g];
-    for (uint32_t u = wave; u < G.n_units; u += nw) eval_unit<T>(G, ops, data, u, lane);
+    const DevGroup &G = groups[g];
+    const DevOp *gops = ops + G.op_begin;
+    if (G.variant == kVarStream) {
+      stream_setup(G, gops, s_lane);
+      __syncthreads();
+      for (uint32_t u = wave; u < G.n_units; u += nw)
+        stream_unit<T>(G, gops, stab, uperm + 32 * g, data, s_lane, u, lane);
+    } else {
+      for (uint32_t u = wave; u < G.n_units; u += nw)
+        generic_unit<T>(G, gops, uperm + 32 * g, data, u, lane);
+    }
     __syncthreads();  // this group's output is read by the next ones
   }
 }
 
-template <class T>
-__global__ __launch_bounds__(kBlock) void k_wide_group(T *__restrict__ data,
-                                                       const DevGroup *__restrict__ groups,
-                                                       const DevOp *__restrict__ ops, int gid) {
-  const DevGroup G = groups[gid];
-  const int lane = threadIdx.x & 63;
+// Blocks are dealt round-robin to the 8 XCDs; renumber them so that each XCD
+// walks one contiguous slice of the union space (its own L2).
+__device__ __forceinline__ void wide_range(uint32_t n_units, uint32_t *ub, uint32_t *ue) {
   const uint32_t nb = gridDim.x, b = blockIdx.x;
-  // Blocks are dealt round-robin to the 8 XCDs; renumber them so that each
-  // XCD walks one contiguous slice of the union space (its own L2).
   const uint32_t lb = (nb % 8u == 0u) ? (b % 8u) * (nb / 8u) + b / 8u : b;
-  const uint32_t per = (G.n_units + nb - 1) / nb;
-  const uint32_t ub = lb * per;
-  const uint32_t ue = min(G.n_units, ub + per);
+  const uint32_t per = (n_units + nb - 1) / nb;
+  *ub = lb * per;
+  *ue = min(n_units, *ub + per);
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_wide_stream(T *__restrict__ data,
+                                                        const DevGroup *__restrict__ groups,
+                                                        const DevOp *__restrict__ ops,
+                                                        const int32_t *__restrict__ stab,
+                                                        const uint8_t *__restrict__ uperm, int gid) {
+  __shared__ uint32_t s_lane[kStreamMaxOps * 64];
+  const DevGroup &G = groups[gid];
+  const DevOp *gops = ops + G.op_begin;
+  const int lane = threadIdx.x & 63;
+  uint32_t ub, ue;
+  wide_range(G.n_units, &ub, &ue);
   const uint32_t nw = blockDim.x >> 6;
-  for (uint32_t u = ub + (threadIdx.x >> 6); u < ue; u += nw) eval_unit<T>(G, ops, data, u, lane);
+  const uint32_t w0 = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  stream_setup(G, gops, s_lane);
+  __syncthreads();
+  for (uint32_t u = ub + w0; u < ue; u += nw)
+    stream_unit<T>(G, gops, stab, uperm + 32 * gid, data, s_lane, u, lane);
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_wide_generic(T *__restrict__ data,
+                                                         const DevGroup *__restrict__ groups,
+                                                         const DevOp *__restrict__ ops,
+                                                         const int32_t *__restrict__ stab,
+                                                         const uint8_t *__restrict__ uperm,
+                                                         int gid) {
+  const DevGroup &G = groups[gid];
+  const DevOp *gops = ops + G.op_begin;
+  const int lane = threadIdx.x & 63;
+  uint32_t ub, ue;
+  wide_range(G.n_units, &ub, &ue);
+  const uint32_t nw = blockDim.x >> 6;
+  const uint32_t w0 = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  for (uint32_t u = ub + w0; u < ue; u += nw)
+    generic_unit<T>(G, gops, uperm + 32 * gid, data, u, lane);
+}
+
+// ----------------------------------------------------- persistent executor
+
+// Runs one work item with the whole block: a segment of small groups
+// [it.x, it.y) in order, or units [it.z, it.w) of wide group it.x (it.y < 0).
+template <class T>
+__device__ __forceinline__ void run_item(int4 it, T *__restrict__ data,
+                                         const DevGroup *__restrict__ groups,
+                                         const DevOp *__restrict__ ops,
+                                         const int32_t *__restrict__ stab,
+                                         const uint8_t *__restrict__ uperm, uint32_t *s_lane) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  const bool chunk = it.y < 0;
+  const int g_end = chunk ? it.x + 1 : it.y;
+  for (int g = it.x; g < g_end; g++) {
+    const DevGroup &G = groups[g];
+    const DevOp *gops = ops + G.op_begin;
+    const uint32_t u0 = chunk ? (uint32_t)it.z : 0u;
+    const uint32_t u1 = chunk ? min((uint32_t)it.w, G.n_units) : G.n_units;
+    if (G.variant == kVarStream) {
+      stream_setup(G, gops, s_lane);
+      __syncthreads();
+      for (uint32_t u = u0 + wave; u < u1; u += nw)
+        stream_unit<T>(G, gops, stab, uperm + 32 * g, data, s_lane, u, lane);
+    } else {
+      for (uint32_t u = u0 + wave; u < u1; u += nw)
+        generic_unit<T>(G, gops, uperm + 32 * g, data, u, lane);
+    }
+    __syncthreads();
+  }
+}
+
+// Grid-wide barrier over resident blocks.  Block writes are released at agent
+// scope before arriving and acquired after leaving.  The wait is bounded: past
+// `spin_limit` polls the block records an error and the kernel stops early.
+__device__ __forceinline__ bool grid_barrier(uint32_t *ctl, uint32_t spin_limit) {
+  uint32_t *count = ctl, *gen = ctl + 1, *err = ctl + 2;
+  __shared__ int s_ok;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    s_ok = 1;
+    __threadfence();
+    const uint32_t g0 = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t arrived =
+        __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (arrived == gridDim.x - 1) {
+      __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __threadfence();
+      __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      uint32_t polls = 0;
+      while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g0) {
+        __builtin_amdgcn_s_sleep(4);
+        if (++polls > spin_limit ||
+            __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+          __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          s_ok = 0;
+          break;
+        }
+      }
+    }
+    __threadfence();
+  }
+  __syncthreads();
+  return s_ok != 0;
+}
+
+// Every light cone's tasks in lockstep: step s runs the s-th task of every
+// cone (a segment of small groups, or a chunk of a wide group), blocks taking
+// items with an atomic counter; a grid barrier separates steps.  ctl:
+// [barrier count, barrier generation, error flag, pad, per-step counters...],
+// cleared by k_reset before the launch.
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_persistent(T *__restrict__ data,
+                                                       const DevGroup *__restrict__ groups,
+                                                       const DevOp *__restrict__ ops,
+                                                       const int32_t *__restrict__ stab,
+                                                       const uint8_t *__restrict__ uperm,
+                                                       const int4 *__restrict__ items,
+                                                       const int *__restrict__ step_begin,
+                                                       int n_steps, uint32_t *ctl,
+                                                       uint32_t spin_limit) {
+  __shared__ uint32_t s_lane[kStreamMaxOps * 64];
+  __shared__ int s_item;
+  uint32_t *step_ctr = ctl + 4;
+  for (int st = 0; st < n_steps; st++) {
+    const int b = step_begin[st], e = step_begin[st + 1];
+    for (;;) {
+      if (threadIdx.x == 0)
+        s_item = b + (int)__hip_atomic_fetch_add(step_ctr + st, 1u, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+      __syncthreads();
+      const int i = s_item;
+      __syncthreads();
+      if (i >= e) break;
+      run_item<T>(items[i], data, groups, ops, stab, uperm, s_lane);
+    }
+    if (st + 1 < n_steps && !grid_barrier(ctl, spin_limit)) return;
+  }
+}
+
+__global__ void k_reset(uint32_t *ctl, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    ctl[i] = 0u;
 }
 
 // Gate values (Eq. 1-2): P = exp(-i gamma [a != b]), R = exp(-i beta X).
@@ -269,28 +609,69 @@ hipError_t launch_fill(int prec, void *data, const double *angles, const FillDes
 }
 
 hipError_t launch_block_groups(int prec, void *data, const DevGroup *groups, const DevOp *ops,
-                               const int2 *ranges, int range_base, int n_blocks,
-                               hipStream_t s) {
+                               const int32_t *stab, const uint8_t *uperm, const int2 *ranges,
+                               int range_base, int n_blocks, hipStream_t s) {
   if (n_blocks <= 0) return hipSuccess;
   if (prec == kPrecC128)
     hipLaunchKernelGGL(k_block_groups<double2>, dim3(n_blocks), dim3(kBlock), 0, s,
-                       (double2 *)data, groups, ops, ranges, range_base);
+                       (double2 *)data, groups, ops, stab, uperm, ranges, range_base);
   else
     hipLaunchKernelGGL(k_block_groups<float2>, dim3(n_blocks), dim3(kBlock), 0, s,
-                       (float2 *)data, groups, ops, ranges, range_base);
+                       (float2 *)data, groups, ops, stab, uperm, ranges, range_base);
   return hipGetLastError();
 }
 
-hipError_t launch_wide_group(int prec, void *data, const DevGroup *groups, const DevOp *ops,
+hipError_t launch_wide_group(int prec, int variant, void *data, const DevGroup *groups,
+                             const DevOp *ops, const int32_t *stab, const uint8_t *uperm,
                              int group, uint32_t n_units, hipStream_t s) {
   const int nb = wide_blocks(n_units);
-  if (prec == kPrecC128)
-    hipLaunchKernelGGL(k_wide_group<double2>, dim3(nb), dim3(kBlock), 0, s, (double2 *)data,
-                       groups, ops, group);
-  else
-    hipLaunchKernelGGL(k_wide_group<float2>, dim3(nb), dim3(kBlock), 0, s, (float2 *)data,
-                       groups, ops, group);
+  if (variant == kVarStream) {
+    if (prec == kPrecC128)
+      hipLaunchKernelGGL(k_wide_stream<double2>, dim3(nb), dim3(kBlock), 0, s, (double2 *)data,
+                         groups, ops, stab, uperm, group);
+    else
+      hipLaunchKernelGGL(k_wide_stream<float2>, dim3(nb), dim3(kBlock), 0, s, (float2 *)data,
+                         groups, ops, stab, uperm, group);
+  } else {
+    if (prec == kPrecC128)
+      hipLaunchKernelGGL(k_wide_generic<double2>, dim3(nb), dim3(kBlock), 0, s,
+                         (double2 *)data, groups, ops, stab, uperm, group);
+    else
+      hipLaunchKernelGGL(k_wide_generic<float2>, dim3(nb), dim3(kBlock), 0, s, (float2 *)data,
+                         groups, ops, stab, uperm, group);
+  }
   return hipGetLastError();
+}
+
+hipError_t launch_persistent(int prec, void *data, const DevGroup *groups, const DevOp *ops,
+                             const int32_t *stab, const uint8_t *uperm, const int4 *items,
+                             const int *step_begin,
+                             int n_steps, uint32_t *ctl, int n_ctl, int n_blocks,
+                             uint32_t spin_limit, hipStream_t s) {
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(256), 0, s, ctl, n_ctl);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (n_steps <= 0) return hipSuccess;
+  if (prec == kPrecC128)
+    hipLaunchKernelGGL(k_persistent<double2>, dim3(n_blocks), dim3(kBlock), 0, s,
+                       (double2 *)data, groups, ops, stab, uperm, items, step_begin, n_steps,
+                       ctl, spin_limit);
+  else
+    hipLaunchKernelGGL(k_persistent<float2>, dim3(n_blocks), dim3(kBlock), 0, s,
+                       (float2 *)data, groups, ops, stab, uperm, items, step_begin, n_steps,
+                       ctl, spin_limit);
+  return hipGetLastError();
+}
+
+int persistent_blocks(int prec, int n_cu) {
+  int per_cu = 0;
+  hipError_t e = prec == kPrecC128
+                     ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<double2>,
+                                                                    kBlock, 0)
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<float2>,
+                                                                    kBlock, 0);
+  if (e != hipSuccess || per_cu < 1) return 0;
+  return per_cu * n_cu;
 }
 
 hipError_t launch_reduce(int prec, const void *data, int64_t scalar_off, const int *csb,

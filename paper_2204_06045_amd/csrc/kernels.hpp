@@ -22,15 +22,33 @@ hipError_t launch_fill(int prec, void *data, const double *angles,
                        const FillDesc *fills, int n_nets, hipStream_t s);
 
 // Groups [ranges[b].x, ranges[b].y) run in order inside block b, for
-// b in [range_base, range_base + n_blocks).
+// b in [range_base, range_base + n_blocks).  uperm holds 32 bytes per group:
+// the union bit of each wave-unit bit.
 hipError_t launch_block_groups(int prec, void *data, const DevGroup *groups,
-                               const DevOp *ops, const int2 *ranges,
+                               const DevOp *ops, const int32_t *stab,
+                               const uint8_t *uperm, const int2 *ranges,
                                int range_base, int n_blocks, hipStream_t s);
 
-// One group over the whole grid.
-hipError_t launch_wide_group(int prec, void *data, const DevGroup *groups,
-                             const DevOp *ops, int group, uint32_t n_units,
-                             hipStream_t s);
+// One group over the whole grid, with the kernel of its mapping variant.
+hipError_t launch_wide_group(int prec, int variant, void *data,
+                             const DevGroup *groups, const DevOp *ops,
+                             const int32_t *stab, const uint8_t *uperm, int group,
+                             uint32_t n_units, hipStream_t s);
+
+// Clears the control words, then runs every light cone's task list in
+// lockstep inside one persistent launch of n_blocks resident blocks.
+// items: (group_begin, group_end, 0, 0) for a segment of small groups or
+// (group, -1, unit_begin, unit_end) for a chunk of a wide group; step s owns
+// items [step_begin[s], step_begin[s+1]).  ctl needs 4 + n_steps words;
+// ctl[2] != 0 after the launch means a barrier wait exceeded spin_limit.
+hipError_t launch_persistent(int prec, void *data, const DevGroup *groups,
+                             const DevOp *ops, const int32_t *stab,
+                             const uint8_t *uperm, const int4 *items, const int *step_begin, int n_steps,
+                             uint32_t *ctl, int n_ctl, int n_blocks,
+                             uint32_t spin_limit, hipStream_t s);
+
+// Resident blocks of the persistent kernel on n_cu compute units (0 on error).
+int persistent_blocks(int prec, int n_cu);
 
 // Per light cone: product of its scalar slots -> e_jk (FP64); per network:
 // E = |E|/2 - 1/2 sum Re e_jk with Neumaier compensation.

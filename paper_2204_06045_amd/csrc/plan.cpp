@@ -111,8 +111,17 @@ LightCone build_lightcone(const Graph &g, int e, int p) {
 // per tensor), with neighbour sets as bitsets.  Eliminating v joins its
 // neighbours into a clique; only the neighbours of v and their neighbours can
 // change fill, so only those are re-scored.
-std::vector<int> minfill_order(const LightCone &lc) {
+std::vector<int> minfill_order(const LightCone &lc, uint64_t seed) {
   const int n = lc.n_vars, W = (n + 63) / 64;
+  // seed 0: ties by smallest id; otherwise ties broken by a splitmix64 draw
+  uint64_t rs = seed;
+  auto draw = [&rs]() {
+    rs += 0x9E3779B97F4A7C15ull;
+    uint64_t z = rs;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  };
   std::vector<uint64_t> adj((size_t)n * W, 0), alive(W, 0);
   auto row = [&](int v) { return &adj[(size_t)v * W]; };
   auto setb = [](uint64_t *r, int b) { r[b >> 6] |= 1ull << (b & 63); };
@@ -148,6 +157,7 @@ std::vector<int> minfill_order(const LightCone &lc) {
   };
   for (int v = 0; v < n; v++) score(v);
   std::vector<char> touched(n);
+  std::vector<int> ties;
   for (int step = 0; step < n; step++) {
     int best = -1;
     for (int v = 0; v < n; v++) {
@@ -155,6 +165,12 @@ std::vector<int> minfill_order(const LightCone &lc) {
       if (best < 0 || fill[v] < fill[best] ||
           (fill[v] == fill[best] && deg[v] < deg[best]))
         best = v;
+    }
+    if (seed) {
+      ties.clear();
+      for (int v = 0; v < n; v++)
+        if (getb(alive.data(), v) && fill[v] == fill[best] && deg[v] == deg[best]) ties.push_back(v);
+      best = ties[draw() % ties.size()];
     }
     order.push_back(best);
     alive[best >> 6] &= ~(1ull << (best & 63));
@@ -188,6 +204,57 @@ std::vector<int> minfill_order(const LightCone &lc) {
       if (touched[v] && getb(alive.data(), v)) score(v);
   }
   return order;
+}
+
+double order_cost(const LightCone &lc, const std::vector<int> &order) {
+  // sum over buckets of 2^width, from index sets alone
+  const int n = lc.n_vars;
+  std::vector<int> pos(n);
+  for (int i = 0; i < n; i++) pos[order[i]] = i;
+  std::vector<std::vector<int>> bucket(n);
+  auto place = [&](std::vector<int> vars) {
+    int b = n;
+    for (int v : vars) b = std::min(b, pos[v]);
+    bucket[b].insert(bucket[b].end(), vars.begin(), vars.end());
+    bucket[b].push_back(-1);  // tensor separator
+  };
+  for (const Gate &g : lc.gates) {
+    std::vector<int> v = {g.var[0]};
+    if (g.rank == 2) v.push_back(g.var[1]);
+    place(v);
+  }
+  double cost = 0;
+  std::vector<char> mark(n, 0);
+  for (int i = 0; i < n; i++) {
+    if (bucket[i].empty()) continue;
+    std::vector<int> u;
+    for (int v : bucket[i])
+      if (v >= 0 && !mark[v]) {
+        mark[v] = 1;
+        u.push_back(v);
+      }
+    for (int v : u) mark[v] = 0;
+    cost += std::ldexp(1.0, (int)u.size());
+    std::vector<int> rest;
+    for (int v : u)
+      if (v != order[i]) rest.push_back(v);
+    if (!rest.empty()) place(rest);
+  }
+  return cost;
+}
+
+std::vector<int> search_order(const LightCone &lc, int trials) {
+  std::vector<int> best = minfill_order(lc, 0);
+  double best_cost = order_cost(lc, best);
+  for (int t = 1; t < trials; t++) {
+    std::vector<int> o = minfill_order(lc, 0x5EEDull * (uint64_t)t + (uint64_t)lc.edge);
+    const double c = order_cost(lc, o);
+    if (c < best_cost) {
+      best_cost = c;
+      best.swap(o);
+    }
+  }
+  return best;
 }
 
 int mask_runs(uint32_t mask, uint8_t *src, uint8_t *len, uint8_t *dst) {

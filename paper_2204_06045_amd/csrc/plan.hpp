@@ -18,8 +18,6 @@ namespace qtn {
 constexpr int kMaxWidth = 32;     // union index of a group fits in 32 bits
 constexpr int kMaxLevels = 8;     // summed indices per fused group
 constexpr int kMaxRuns = 16;      // contiguous bit runs of an operand mask
-constexpr int kRegBits = 2;       // union bits held in registers per thread
-constexpr int kLaneBits = 6;      // union bits spread over the 64 lanes
 
 enum GateKind : int8_t { kH = 0, kZ = 1, kP = 2, kPc = 3, kR = 4, kRc = 5 };
 
@@ -54,8 +52,16 @@ std::string make_graph(int n, int64_t m, const int32_t *edges, Graph *g);
 // Light cone of edge e at depth p (Sec. II-B reverse light cone).
 LightCone build_lightcone(const Graph &g, int e, int p);
 
-// Greedy min-fill order (ties: fewest neighbours, then smallest id).
-std::vector<int> minfill_order(const LightCone &lc);
+// Greedy min-fill order (ties: fewest neighbours, then smallest id; with a
+// nonzero seed, remaining ties are broken at random).
+std::vector<int> minfill_order(const LightCone &lc, uint64_t seed = 0);
+
+// Sum over buckets of 2^width for an order (index sets only).
+double order_cost(const LightCone &lc, const std::vector<int> &order);
+
+// The cheapest (by order_cost) of the greedy order and trials-1 randomized
+// min-fill orders.
+std::vector<int> search_order(const LightCone &lc, int trials);
 
 // ---------------------------------------------------------------- plan
 

@@ -67,7 +67,12 @@ def test_small_graphs_all_configs(qtn, orc, gpu, n, p, prec):
     ref, ref_en = orc.energy(n, inst["edges"], g, b, threads=8)
     for cfg in [dict(max_levels=1), dict(max_levels=3), dict(max_levels=8),
                 dict(small_width=4), dict(small_width=20), dict(eager=True),
-                dict(n_streams=1)]:
+                dict(n_streams=1), dict(variant=1), dict(variant=1, small_width=4),
+                dict(small_width=4, lane_sum_bits=1), dict(small_width=4, lane_sum_bits=3),
+                dict(small_width=4, lane_sum_bits=5), dict(small_width=4, max_levels=2),
+                dict(order_trials=8), dict(small_width=4, variant=2, lane_sum_bits=4),
+                dict(executor=2), dict(executor=2, small_width=4),
+                dict(executor=2, max_levels=1, variant=1)]:
         print(f"n={n} p={p} prec={prec} cfg={cfg}", flush=True)
         zz, zi, en = _run(qtn, n, inst["edges"], g, b, prec, **cfg)
         _check(zz, zi, en, ref, ref_en, prec, str(cfg))
@@ -163,16 +168,66 @@ def test_batch_matches_single(qtn, orc, gpu):
         n.close()
 
 
+def test_persistent_bounded_wait_reports_error(qtn, gpu):
+    """A spin limit of one poll makes the grid barrier give up at once: every
+    block exits and the call reports QTN_EDEVICE instead of a result."""
+    inst = qs.instance(16, 3, 3, 3)
+    g, b = inst["angles"][0]
+    net = qtn.Network(16, inst["edges"], g, b, executor=2, spin_limit=1)
+    net.plan(0)
+    with pytest.raises(qtn.QtnError) as ei:
+        net.contract()
+    assert ei.value.code == -4 and "barrier" in str(ei.value)
+    net.close()
+    # the same plan with the default bound succeeds afterwards
+    net = qtn.Network(16, inst["edges"], g, b, executor=2)
+    net.plan(0)
+    zz, zi, en = net.contract()
+    assert np.all(np.isfinite(zz))
+    net.close()
+
+
+def test_batch_persistent_and_streams_agree(qtn, orc, gpu):
+    # N in [12, 40], p in {2, 3}: oracle widths stay at or below 18
+    insts = qs.batch_instances(5, 6, 12, 40, (2, 3), d=3)
+    refs = []
+    for it in insts:
+        g, b = it["angles"][0]
+        print(f"oracle n={it['n']} p={it['p']}", flush=True)
+        refs.append(orc.energy(it["n"], it["edges"], g, b, threads=8))
+    for executor in (0, 1):
+        nets = []
+        for it in insts:
+            g, b = it["angles"][0]
+            net = qtn.Network(it["n"], it["edges"], g, b, executor=executor, order_trials=4)
+            net.plan(0)
+            nets.append(net)
+        print(f"batch executor={executor}", flush=True)
+        handles = [n.h for n in nets]
+        ws = qtn.workspace(qtn.qtn_batch_workspace(handles))
+        zz, en = qtn.qtn_contract_batch(handles, sum(n.m for n in nets), ws)
+        off = 0
+        for i, (net, (rz, re_)) in enumerate(zip(nets, refs)):
+            _check(zz[off:off + net.m], None, en[i], rz, re_, 0, f"batch executor {executor}")
+            off += net.m
+        for n in nets:
+            n.close()
+
+
 def _golden(name):
     with open(os.path.join(HERE, "golden", f"{name}_oracle.json")) as f:
         return json.load(f)
 
 
-@pytest.mark.parametrize("prec,levels", [(0, 8), (1, 8), (0, 1)])
-def test_cfg2_full_size_against_oracle(qtn, gpu, prec, levels):
+@pytest.mark.parametrize("prec,levels,variant,trials,executor", [
+    (0, 8, 0, 0, 0), (1, 8, 0, 0, 0), (0, 1, 0, 0, 0), (0, 8, 1, 0, 0), (1, 1, 0, 0, 0),
+    (0, 8, 0, 64, 0), (1, 8, 0, 64, 0), (0, 8, 2, 16, 0), (0, 8, 0, 64, 2), (1, 8, 1, 64, 2)])
+def test_cfg2_full_size_against_oracle(qtn, gpu, prec, levels, variant, trials, executor):
     """3-regular N=30, p=4 (Sec. II-E benchmark shape), all 45 light cones."""
     gd = _golden("cfg2")
-    print(f"cfg2 prec={prec} levels={levels}", flush=True)
+    print(f"cfg2 prec={prec} levels={levels} variant={variant} trials={trials} "
+          f"executor={executor}", flush=True)
     zz, zi, en = _run(qtn, gd["n"], gd["edges"], gd["gamma"], gd["beta"], prec,
-                      max_levels=levels)
+                      max_levels=levels, variant=variant, order_trials=trials,
+                      executor=executor)
     _check(zz, zi, en, gd["zz_re"], gd["energy"], prec, "cfg2")
