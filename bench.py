@@ -38,7 +38,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_rows(Q, torch, inst, prec, levels, streams, steps, warmup, **cfg):
+def run_rows(Q, torch, inst, prec, levels, streams, steps, warmup, autotune=False, **cfg):
     n, edges = inst["n"], inst["edges"]
     angles = inst["angles"]
     net = Q.Network(n, edges, *angles[0], max_levels=levels, n_streams=streams, **cfg)
@@ -46,6 +46,11 @@ def run_rows(Q, torch, inst, prec, levels, streams, steps, warmup, **cfg):
     net.plan(prec)
     plan_s = time.perf_counter() - t0
     ws = net.workspace()
+    net.tune_report = None
+    if autotune:
+        t0 = time.perf_counter()
+        net.tune_report = net.autotune(ws)
+        net.tune_report["seconds"] = time.perf_counter() - t0
     for i in range(warmup):
         net.set_angles(*angles[i % len(angles)])
         net.contract(ws)
@@ -60,22 +65,74 @@ def run_rows(Q, torch, inst, prec, levels, streams, steps, warmup, **cfg):
     return net, dt, plan_s, last
 
 
-def roofline_of(timing, prec):
-    """Dominant kernel class (most device time) against its bound."""
-    dom = max(("block", "wide", "persistent"), key=lambda k: timing[k]["ms"])
-    t = timing[dom]
+KERNEL_OF = {  # launch-log (kind, variant) -> kernel symbol
+    (1, None): "k_block_groups", (2, 0): "k_wide_generic", (2, 1): "k_wide_stream",
+    (4, None): "k_persistent",
+}
+
+
+def kernel_name(rec, prec):
+    key = (rec["kind"], rec["variant"] if rec["kind"] == 2 else None)
+    base = KERNEL_OF.get(key)
+    if base is None:
+        return None
+    return f"{base}<{'double2' if prec == 0 else 'float2'}>"
+
+
+def source_hash():
+    """Hash of the kernel source, to tell whether stored counters still apply."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "device.hpp"):
+        with open(os.path.join(ROOT, "paper_2204_06045_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(kernel, workload_tag):
+    """Per-launch HBM bytes from committed rocprofv3 --pmc summaries, if they
+    were taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload_tag}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("source_hash") != source_hash():
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("hbm_bytes_per_launch")
+
+
+def roofline_of(log, prec, workload_tag):
+    """The kernel with the most device time in one timed evaluation, against
+    its bound: algorithmic bytes (or flops) per launch over its mean launch
+    duration (HIP events on the launch stream)."""
+    per = {}
+    for r in log:
+        name = kernel_name(r, prec)
+        if name is None:
+            continue
+        a = per.setdefault(name, {"ms": 0.0, "bytes": 0.0, "flops": 0.0, "launches": 0})
+        a["ms"] += r["ms"]
+        a["bytes"] += r["bytes"]
+        a["flops"] += r["flops"]
+        a["launches"] += 1
+    kernel, t = max(per.items(), key=lambda kv: kv[1]["ms"])
     sec = t["ms"] / 1e3
     gbs = t["bytes"] / sec / 1e9 if sec > 0 else 0.0
     tflops = t["flops"] / sec / 1e12 if sec > 0 else 0.0
     fpeak = FP64_PEAK_TFLOPS if prec == 0 else FP32_PEAK_TFLOPS
     hbm_frac, fp_frac = gbs / HBM_PEAK_GBS, tflops / fpeak
-    kname = {"wide": "wide", "block": "block_groups", "persistent": "persistent"}[dom]
-    kernel = f"k_{kname}<{'double2' if prec == 0 else 'float2'}>"
+    n = max(1, t["launches"])
     common = {"kernel": kernel, "launches": t["launches"],
-              "bytes_per_launch": t["bytes"] / max(1, t["launches"]),
-              "avg_launch_ms": t["ms"] / max(1, t["launches"]),
-              "hbm_gbs": gbs, "hbm_frac": hbm_frac,
-              "fp_tflops": tflops, "fp_frac": fp_frac, "traffic": None}
+              "bytes_per_launch": t["bytes"] / n, "flops_per_launch": t["flops"] / n,
+              "avg_launch_ms": t["ms"] / n, "hbm_gbs": gbs, "hbm_frac": hbm_frac,
+              "fp_tflops": tflops, "fp_frac": fp_frac,
+              "traffic": stored_traffic(kernel, workload_tag),
+              "per_kernel": {k: {"ms": v["ms"], "launches": v["launches"],
+                                 "gbs": v["bytes"] / max(v["ms"], 1e-9) / 1e6,
+                                 "tflops": v["flops"] / max(v["ms"], 1e-9) / 1e9}
+                             for k, v in per.items()}}
     if hbm_frac >= fp_frac:
         return {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": hbm_frac, **common}
@@ -129,6 +186,7 @@ def main():
     ap.add_argument("--precision", choices=("c128", "c64"), default="c128")
     ap.add_argument("--levels", type=int, default=8, help="merged indices per group (1 = plain)")
     ap.add_argument("--streams", type=int, default=4)
+    ap.add_argument("--small-width", type=int, default=0, help="widest group run in-block")
     ap.add_argument("--variant", type=int, default=0, help="0 auto, 1 generic, 2 streaming")
     ap.add_argument("--lane-bits", type=int, default=0, help="streaming lane-summed bits")
     ap.add_argument("--executor", type=int, default=0, help="0 default, 1 launches, 2 persistent")
@@ -139,6 +197,9 @@ def main():
     ap.add_argument("--variants", type=int, default=1, help="also time the other rows")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--autotune", type=int, default=1, help="run the autotuner after planning")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a 1 GiB device copy (byte-counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -156,17 +217,36 @@ def main():
     prec = Q.QTN_C128 if args.precision == "c128" else Q.QTN_C64
     log(f"main row: {args.precision} levels={args.levels} streams={args.streams}")
     kcfg = dict(variant=args.variant, lane_sum_bits=args.lane_bits,
-                order_trials=args.order_trials, executor=args.executor)
+                order_trials=args.order_trials, executor=args.executor,
+                small_width=args.small_width)
     net, dt, plan_s, last = run_rows(Q, torch, inst, prec, args.levels, args.streams,
-                                     args.steps, args.warmup, **kcfg)
+                                     args.steps, args.warmup, autotune=bool(args.autotune), **kcfg)
+    tune = net.tune_report
     evals = args.steps / dt
     stats = net.stats()
+    plan_order_trials = args.order_trials
     log(f"  {evals:.2f} evals/s, plan {plan_s:.2f} s")
-    _, _, timing = net.contract_timed()
-    roof = roofline_of(timing, prec)
+    net.close()
+    # kernel roofline: the same plan on one stream, so that each launch's HIP
+    # event pair brackets that kernel alone
+    rnet = Q.Network(inst["n"], inst["edges"], *inst["angles"][0], max_levels=args.levels,
+                     n_streams=1, **kcfg)
+    rnet.plan(prec)
+    if args.autotune:
+        rnet.autotune()
+    rnet.contract()
+    _, _, timing = rnet.contract_timed()
+    tag = f"n30p4_{args.precision}"
+    roof = roofline_of(rnet.launch_log(), prec, tag)
+    rnet.close()
     log(f"  roofline {roof['kernel']}: {roof['hbm_gbs']:.0f} GB/s, "
         f"{roof['fp_tflops']:.2f} TFLOP/s")
-    net.close()
+    if args.calibrate_copy:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     variants = {}
     if args.variants:
@@ -176,7 +256,8 @@ def main():
                 continue
             log(f"variant {name}")
             vnet, vdt, _, _ = run_rows(Q, torch, inst, pr, lv, args.streams,
-                                       max(3, args.steps // 4), 2, **kcfg)
+                                       max(3, args.steps // 4), 2,
+                                       autotune=bool(args.autotune), **kcfg)
             vst = vnet.stats()
             variants[name] = {"evals_per_s": max(3, args.steps // 4) / vdt,
                               "alg_bytes_per_eval": vst["bytes"],
@@ -210,7 +291,7 @@ def main():
             "precision": args.precision, "max_levels": args.levels,
             "streams": args.streams, "variant": args.variant,
             "lane_sum_bits": args.lane_bits, "order_trials": args.order_trials,
-            "executor": args.executor,
+            "executor": args.executor, "autotune": bool(args.autotune),
             "max_width": stats["max_width"],
             "buckets": stats["n_buckets"], "groups": stats["n_groups"],
         },
@@ -218,8 +299,10 @@ def main():
         "alg_flops_per_eval": stats["flops"],
         "eval_hbm_gbs": stats["bytes"] * evals / 1e9,
         "plan_seconds": plan_s,
+        "autotune": tune,
         "roofline": roof,
         "kernel_timing": timing,
+        "kernel_source_hash": source_hash(),
         "variants": variants,
         "cpu_baseline": cpu,
     }

@@ -66,7 +66,9 @@ typedef struct qtn_config {
                             min-fill orders with random tie-breaks [0]     */
     int32_t executor;    /* 0 default (single networks: per-group launches
                             over n_streams; batches: persistent), 1 per-group
-                            launches, 2 one persistent lockstep launch      */
+                            launches, 2 one persistent lockstep launch, 3
+                            per-group launches with each cone's leading
+                            small groups launched on that cone's stream    */
     int32_t spin_limit;  /* persistent executor: polls before a grid-barrier
                             wait gives up with QTN_EDEVICE [2^26]          */
     int32_t reserved[6];
@@ -193,6 +195,43 @@ typedef struct qtn_launch_rec {
  * stores the number available in *n_out. */
 int qtn_launch_log(const qtn_network *net, int64_t cap, qtn_launch_rec *out,
                    int64_t *n_out);
+
+/* Kernel variants a group can run with (cost-model outputs). */
+#define QTN_VAR_BLOCK 0   /* inside one workgroup, many groups per launch  */
+#define QTN_VAR_STREAM 1  /* own launch, streaming mapping (LDS lane
+                             tables, serial walk, butterflies)           */
+#define QTN_VAR_GENERIC 2 /* own launch, generic register/lane mapping   */
+
+typedef struct qtn_tune_report {
+    int32_t n_groups;     /* own-launch groups tuned                        */
+    int32_t n_candidates; /* configurations measured                        */
+    double cand_ms[8];    /* summed own-launch group time per configuration */
+    double tuned_ms;      /* the same with each group's fastest choice      */
+    int32_t picks[8];     /* groups that chose each configuration           */
+} qtn_tune_report;
+
+/*
+ * Autotuner.  Runs the planned evaluation once per candidate configuration
+ * (generic mapping; streaming mapping with 1, 2 or 3 lane-summed bits), each
+ * group in its own launch on one stream and, for groups up to width 16, again
+ * alone inside one workgroup, timing every launch with HIP events.  Each
+ * group then keeps its fastest configuration for where it runs, and the plan's
+ * schedule is rebuilt.  Needs the workspace qtn_plan reported.  The timings
+ * are kept for qtn_tune_log.  Results of qtn_contract are unchanged up to
+ * rounding order.
+ */
+int qtn_autotune(qtn_network *net, void *d_workspace, size_t bytes,
+                 void *hip_stream, qtn_tune_report *report);
+
+/* One group's timings from the last qtn_autotune: its 16 shape features and
+ * the measured time of each QTN_VAR_* (negative: not measured). */
+typedef struct qtn_tune_rec {
+    float features[16];
+    double ms[3];
+} qtn_tune_rec;
+
+int qtn_tune_log(const qtn_network *net, int64_t cap, qtn_tune_rec *out,
+                 int64_t *n_out);
 
 /* Plan statistics. */
 typedef struct qtn_plan_stats {

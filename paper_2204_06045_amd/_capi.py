@@ -35,7 +35,7 @@ EXPORTS = (
     "qtn_set_angles", "qtn_contract", "qtn_contract_batch",
     "qtn_batch_workspace", "qtn_contract_timed", "qtn_get_plan_stats",
     "qtn_bucket_widths", "qtn_network_free", "qtn_last_error", "qtn_launch_log",
-    "qtn_plan_order",
+    "qtn_plan_order", "qtn_autotune", "qtn_tune_log",
 )
 
 
@@ -61,6 +61,16 @@ class qtn_launch_rec(ctypes.Structure):
                 ("n_ops", ctypes.c_int32), ("variant", ctypes.c_int32),
                 ("n_units", ctypes.c_int32), ("ms", ctypes.c_double),
                 ("bytes", ctypes.c_double), ("flops", ctypes.c_double)]
+
+
+class qtn_tune_report(ctypes.Structure):
+    _fields_ = [("n_groups", ctypes.c_int32), ("n_candidates", ctypes.c_int32),
+                ("cand_ms", ctypes.c_double * 8), ("tuned_ms", ctypes.c_double),
+                ("picks", ctypes.c_int32 * 8)]
+
+
+class qtn_tune_rec(ctypes.Structure):
+    _fields_ = [("features", ctypes.c_float * 16), ("ms", ctypes.c_double * 3)]
 
 
 class qtn_plan_stats(ctypes.Structure):
@@ -111,6 +121,8 @@ def lib():
         L.qtn_get_plan_stats.argtypes = [P, ctypes.POINTER(qtn_plan_stats)]
         L.qtn_bucket_widths.argtypes = [P, i64, pi32]
         L.qtn_plan_order.argtypes = [P, i64, pi32]
+        L.qtn_autotune.argtypes = [P, P, ctypes.c_size_t, P, ctypes.POINTER(qtn_tune_report)]
+        L.qtn_tune_log.argtypes = [P, i64, ctypes.POINTER(qtn_tune_rec), ctypes.POINTER(i64)]
         L.qtn_launch_log.argtypes = [P, i64, ctypes.POINTER(qtn_launch_rec),
                                      ctypes.POINTER(i64)]
         L.qtn_network_free.argtypes = [P]

@@ -14,14 +14,16 @@ import torch
 
 from . import _capi
 from ._capi import (QTN_C128, QTN_C64, QtnError, check, lib, qtn_config,
-                    qtn_launch_rec, qtn_plan_stats, qtn_timing)
+                    qtn_launch_rec, qtn_plan_stats, qtn_timing, qtn_tune_rec,
+                    qtn_tune_report)
 
 __all__ = [
     "QTN_C128", "QTN_C64", "QtnError", "qtn_network_build", "qtn_network_info",
     "qtn_order_minfill", "qtn_plan", "qtn_set_angles", "qtn_contract",
     "qtn_contract_timed", "qtn_contract_batch", "qtn_batch_workspace",
     "qtn_get_plan_stats", "qtn_bucket_widths", "qtn_network_free",
-    "qtn_last_error", "qtn_launch_log", "qtn_plan_order", "Network", "workspace", "stream_handle",
+    "qtn_last_error", "qtn_launch_log", "qtn_plan_order", "qtn_autotune", "qtn_tune_log",
+    "Network", "workspace", "stream_handle",
 ]
 
 _pi32 = ctypes.POINTER(ctypes.c_int32)
@@ -192,6 +194,29 @@ def qtn_launch_log(net):
     return [{f: getattr(r, f) for f, _ in qtn_launch_rec._fields_} for r in arr[:n.value]]
 
 
+def qtn_autotune(net, ws, stream=None):
+    """Measure each candidate kernel configuration and keep the fastest per
+    group.  Returns the report as a dict."""
+    r = qtn_tune_report()
+    check(lib().qtn_autotune(net, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                             stream_handle(stream), ctypes.byref(r)))
+    nc = r.n_candidates
+    return {"n_groups": r.n_groups, "n_candidates": nc,
+            "cand_ms": list(r.cand_ms[:nc]), "tuned_ms": r.tuned_ms,
+            "picks": list(r.picks[:nc])}
+
+
+def qtn_tune_log(net):
+    """(features [n, 16] float32, ms [n, 3] float64) from the last autotune."""
+    n = ctypes.c_int64()
+    check(lib().qtn_tune_log(net, 0, None, ctypes.byref(n)))
+    arr = (qtn_tune_rec * max(1, n.value))()
+    check(lib().qtn_tune_log(net, n.value, arr, ctypes.byref(n)))
+    feats = np.array([list(r.features) for r in arr[:n.value]], dtype=np.float32)
+    ms = np.array([list(r.ms) for r in arr[:n.value]], dtype=np.float64)
+    return feats.reshape(-1, 16), ms.reshape(-1, 3)
+
+
 def qtn_network_free(net):
     lib().qtn_network_free(net)
 
@@ -240,6 +265,12 @@ class Network:
 
     def launch_log(self):
         return qtn_launch_log(self.h)
+
+    def autotune(self, ws=None, stream=None):
+        return qtn_autotune(self.h, ws if ws is not None else self.workspace(), stream)
+
+    def tune_log(self):
+        return qtn_tune_log(self.h)
 
     def plan_order(self, edge):
         return qtn_plan_order(self.h, edge)

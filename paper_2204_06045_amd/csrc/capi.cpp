@@ -81,6 +81,9 @@ struct Schedule {
   std::vector<FillDesc> fills;
   std::vector<int32_t> stab;  // serial-offset tables of streaming operands
   std::vector<uint8_t> uperm; // 32 bytes per group: union bit of each unit bit
+  std::vector<int> group_cone, group_index;  // plan position of each group
+  std::vector<int> singles;   // groups also given a one-group range (tuning)
+  int singles_range0 = 0;     // range index of singles[0]
   std::vector<std::vector<Task>> cone_tasks;  // after the leading small groups
   int n_cones = 0, n_nets = 0, n_angles = 0;
   size_t off_res = 0, off_angles = 0, off_desc = 0, off_fills = 0, off_groups = 0,
@@ -142,6 +145,7 @@ struct Exec {
   Schedule sched;
   Runtime rt;
   bool persistent = false;
+  bool lead_per_cone = false;
   uint32_t spin_limit = 1u << 26;
 };
 
@@ -168,6 +172,8 @@ struct qtn_network {
   std::vector<ConePlan> plans;
   std::unique_ptr<Exec> exec;
   std::vector<qtn_launch_rec> launch_log;
+  std::vector<qtn_tune_rec> tune_log;
+  size_t tune_workspace = 0;
 };
 
 namespace {
@@ -202,7 +208,25 @@ int64_t gate_offset(const Gate &gt, bool transposed, int p) {
   }
 }
 
-int build_schedule(qtn_network *const *nets, int n, Schedule *S) {
+// Candidate kernel configuration the autotuner forces on every wide group.
+struct Force {
+  int place;    // -1 keep, 0 workgroup segment, 1 own launch
+  int variant;  // 1 generic, 2 streaming
+  int rls;
+};
+
+constexpr int kTuneSingleWidth = 16;
+
+// Configurations measured by the autotuner: every group in its own launch
+// with the generic mapping, or with the streaming mapping at 1, 2, 3
+// lane-summed bits.
+const std::vector<Force> &tune_candidates() {
+  static const std::vector<Force> c = {{1, 1, 2}, {1, 2, 1}, {1, 2, 2}, {1, 2, 3}};
+  return c;
+}
+
+int build_schedule(qtn_network *const *nets, int n, Schedule *S, const Force *force = nullptr,
+                   int singleton_width = 0) {
   Schedule &s = *S;
   s = Schedule();
   s.prec = nets[0]->precision;
@@ -258,11 +282,23 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S) {
           in_el += std::ldexp(1.0, (int)pl.tensors[o.tensor].vars.size());
         }
         // streaming mapping unless the group is too large for its LDS tables
-        const int rls = std::min(G.L - 1, net->lane_sum_bits);
+        int var_req = net->variant, rls_req = net->lane_sum_bits;
+        if (G.pick_variant > 0) {
+          var_req = G.pick_variant;
+          if (G.pick_rls >= 0) rls_req = G.pick_rls;
+        }
+        const bool is_small = force && force->place >= 0
+                                  ? force->place == 0
+                                  : (G.pick_place >= 0 ? G.pick_place == 0 : G.small);
+        if (force) {
+          var_req = force->variant;
+          rls_req = force->rls;
+        }
+        const int rls = std::min(G.L - 1, rls_req);
         const int sl = G.L - 1 - rls;
         const bool stream_ok = (int)G.ops.size() <= kStreamMaxOps && sl <= kStreamMaxSerial;
         // auto: the streaming mapping pays off once a lane walks >= 2 serial bits
-        const bool stream = stream_ok && (net->variant == 2 || (net->variant == 0 && sl >= 2));
+        const bool stream = stream_ok && (var_req == 2 || (var_req == 0 && sl >= 2));
         std::vector<int> order(G.ops.size());
         std::vector<int> cls(G.ops.size(), 0);
         for (size_t k = 0; k < G.ops.size(); k++) order[k] = (int)k;
@@ -367,7 +403,10 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S) {
         }
         const int gid = (int)s.groups.size();
         s.groups.push_back(dg);
-        if (G.small) {
+        s.group_cone.push_back(s.n_cones);
+        s.group_index.push_back((int)(&G - pl.groups.data()));
+        if (singleton_width > 0 && G.w <= singleton_width) s.singles.push_back(gid);
+        if (is_small) {
           if (open_begin < 0) open_begin = gid;
           seg_bytes += gb;
           seg_flops += gf;
@@ -399,6 +438,8 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S) {
     for (auto &t : tk)
       if (t.kind == QTN_K_BLOCK) t.index += s.n_cones;
   s.ranges.insert(s.ranges.begin(), lead.begin(), lead.end());
+  s.singles_range0 = (int)s.ranges.size();
+  for (int g : s.singles) s.ranges.push_back(make_int2(g, g + 1));
   s.n_nets = n;
   // lockstep steps: the j-th task of every cone (leading segment first)
   {
@@ -570,12 +611,17 @@ int enqueue(Exec &X, Timer &tm) {
                               (uint32_t *)(ws + s.off_ctl), s.n_ctl, nb, X.spin_limit, rt.main));
     if ((rc = tm.end(rt.main))) return rc;
   } else {
-  if ((rc = tm.begin(QTN_K_BLOCK, rt.main, 0, (int)s.groups.size(), s.init_bytes, s.init_flops)))
-    return rc;
-  QTN_HIP(launch_block_groups(s.prec, data, groups, ops, stab, uperm, ranges, 0, s.n_cones, rt.main));
-  if ((rc = tm.end(rt.main))) return rc;
+  // leading small segments: one launch for every cone before the fork, or
+  // (lead_per_cone) each cone's own one-block launch on its stream
+  if (!X.lead_per_cone) {
+    if ((rc = tm.begin(QTN_K_BLOCK, rt.main, 0, (int)s.groups.size(), s.init_bytes, s.init_flops)))
+      return rc;
+    QTN_HIP(launch_block_groups(s.prec, data, groups, ops, stab, uperm, ranges, 0, s.n_cones,
+                                rt.main));
+    if ((rc = tm.end(rt.main))) return rc;
+  }
   const int K = (int)rt.side.size();
-  bool any = false;
+  bool any = X.lead_per_cone;
   for (auto &tk : s.cone_tasks) any |= !tk.empty();
   if (any) {
     QTN_HIP(hipEventRecord(rt.ev_fork, rt.main));
@@ -590,10 +636,17 @@ int enqueue(Exec &X, Timer &tm) {
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
     std::vector<double> load(K, 0);
     for (int c : order) {
-      if (s.cone_tasks[c].empty()) continue;
+      const bool lead = X.lead_per_cone && s.ranges[c].y > s.ranges[c].x;
+      if (s.cone_tasks[c].empty() && !lead) continue;
       int st = (int)(std::min_element(load.begin(), load.end()) - load.begin());
       load[st] += cost[c];
       hipStream_t hs = rt.side[st];
+      if (lead) {
+        if ((rc = tm.begin(QTN_K_BLOCK, hs, s.ranges[c].x, s.ranges[c].y - s.ranges[c].x)))
+          return rc;
+        QTN_HIP(launch_block_groups(s.prec, data, groups, ops, stab, uperm, ranges, c, 1, hs));
+        if ((rc = tm.end(hs))) return rc;
+      }
       for (auto &t : s.cone_tasks[c]) {
         const int g0 = t.kind == QTN_K_BLOCK ? s.ranges[t.index].x : t.index;
         const int ng = t.kind == QTN_K_BLOCK ? s.ranges[t.index].y - s.ranges[t.index].x : 1;
@@ -733,7 +786,7 @@ int qtn_network_build(int32_t n_vertices, int64_t n_edges, const int32_t *edges,
       if (cfg->order_trials < 0 || cfg->order_trials > 4096)
         return set_err(QTN_EINVAL, "order_trials must be in 0..4096");
       net->order_trials = cfg->order_trials;
-      if (cfg->executor < 0 || cfg->executor > 2) return set_err(QTN_EINVAL, "executor must be 0..2");
+      if (cfg->executor < 0 || cfg->executor > 3) return set_err(QTN_EINVAL, "executor must be 0..3");
       net->executor = cfg->executor;
       if (cfg->spin_limit > 0) net->spin_limit = (uint32_t)cfg->spin_limit;
     }
@@ -830,11 +883,21 @@ int qtn_plan(qtn_network *net, const int32_t *const *orders, int32_t precision,
     }
     drop_batches_with(net);
     ex->persistent = net->executor == 2;
+    ex->lead_per_cone = net->executor == 3;
+    {
+      size_t mx = ex->sched.total;
+      for (const Force &f : tune_candidates()) {
+        Schedule tmp;
+        if (build_schedule(one, 1, &tmp, &f, kTuneSingleWidth) == QTN_OK)
+          mx = std::max(mx, tmp.total);
+      }
+      net->tune_workspace = mx;
+    }
     ex->spin_limit = net->spin_limit;
     net->exec = std::move(ex);
     net->planned = true;
     net->version++;
-    if (workspace_bytes_out) *workspace_bytes_out = net->exec->sched.total;
+    if (workspace_bytes_out) *workspace_bytes_out = net->tune_workspace;
     return QTN_OK;
   } catch (const std::bad_alloc &) {
     return set_err(QTN_ENOMEM, "host allocation failed");
@@ -981,6 +1044,128 @@ int qtn_contract_batch(qtn_network *const *nets, int32_t n, void *d_workspace, s
   } catch (const std::bad_alloc &) {
     return set_err(QTN_ENOMEM, "host allocation failed");
   }
+}
+
+int qtn_autotune(qtn_network *net, void *d_workspace, size_t bytes, void *hip_stream,
+                 qtn_tune_report *report) {
+  try {
+    if (!net) return set_err(QTN_EINVAL, "network is NULL");
+    if (!net->planned) return set_err(QTN_ESTATE, "qtn_plan has not been called");
+    if (bytes < net->tune_workspace)
+      return set_err(QTN_ENOMEM, "autotuning needs a workspace of " +
+                                     std::to_string(net->tune_workspace) + " bytes");
+    const auto &cands = tune_candidates();
+    const int nc = (int)cands.size();
+    qtn_network *one[1] = {net};
+    // per plan group: measured ms per candidate, own launch and inside a block
+    struct Meas {
+      double wide[8], block[8];
+    };
+    std::map<std::pair<int, int>, Meas> meas;
+    qtn_tune_report rep;
+    std::memset(&rep, 0, sizeof rep);
+    rep.n_candidates = nc;
+    for (int ci = 0; ci < nc; ci++) {
+      Exec ex;
+      int rc = build_schedule(one, 1, &ex.sched, &cands[ci], kTuneSingleWidth);
+      if (rc) return rc;
+      Timer tm;
+      tm.on = true;
+      std::vector<double> res;
+      rc = run_exec(ex, {net}, d_workspace, bytes, hip_stream, 1, true, tm, res);
+      if (rc) return rc;
+      // the same groups again, each alone in one workgroup
+      Timer tb;
+      tb.on = true;
+      char *ws = (char *)d_workspace;
+      const Schedule &s = ex.sched;
+      for (size_t i = 0; i < s.singles.size(); i++) {
+        if ((rc = tb.begin(QTN_K_BLOCK, ex.rt.main, s.singles[i], 1))) return rc;
+        QTN_HIP(launch_block_groups(s.prec, ws + s.off_data, (const DevGroup *)(ws + s.off_groups),
+                                    (const DevOp *)(ws + s.off_ops),
+                                    (const int32_t *)(ws + s.off_stab),
+                                    (const uint8_t *)(ws + s.off_uperm),
+                                    (const int2 *)(ws + s.off_ranges), s.singles_range0 + (int)i, 1,
+                                    ex.rt.main));
+        if ((rc = tb.end(ex.rt.main))) return rc;
+      }
+      QTN_HIP(hipStreamSynchronize(ex.rt.main));
+      auto key_of = [&](int g) { return std::make_pair(s.group_cone[g], s.group_index[g]); };
+      for (auto &r : tm.recs) {
+        if (r.kind != QTN_K_WIDE) continue;
+        float ms = 0;
+        QTN_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+        Meas &m = meas.emplace(key_of(r.group), Meas{{-1, -1, -1, -1, -1, -1, -1, -1},
+                                                     {-1, -1, -1, -1, -1, -1, -1, -1}}).first->second;
+        m.wide[ci] = ms;
+        rep.cand_ms[ci] += ms;
+      }
+      for (auto &r : tb.recs) {
+        float ms = 0;
+        QTN_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+        Meas &m = meas.emplace(key_of(r.group), Meas{{-1, -1, -1, -1, -1, -1, -1, -1},
+                                                     {-1, -1, -1, -1, -1, -1, -1, -1}}).first->second;
+        m.block[ci] = ms;
+      }
+    }
+    // per group: the fastest candidate for where the width rule places it;
+    // every group's timings go to the tuning log
+    net->tune_log.clear();
+    for (auto &kv : meas) {
+      ConePlan &pl = net->plans[kv.first.first];
+      Group &G = pl.groups[kv.first.second];
+      const Meas &m = kv.second;
+      const double *t = G.small ? m.block : m.wide;
+      int best = -1;
+      for (int ci = 0; ci < nc; ci++)
+        if (t[ci] >= 0 && (best < 0 || t[ci] < t[best])) best = ci;
+      if (best >= 0) {
+        G.pick_variant = (int8_t)cands[best].variant;
+        G.pick_rls = (int8_t)cands[best].rls;
+        if (!G.small) {
+          rep.tuned_ms += t[best];
+          rep.picks[best]++;
+          rep.n_groups++;
+        }
+      }
+      qtn_tune_rec tr;
+      std::memset(&tr, 0, sizeof tr);
+      group_features(G, pl, net->precision, tr.features);
+      double mb = -1, ms_stream = -1;
+      for (int ci = 0; ci < nc; ci++) {
+        if (m.block[ci] >= 0 && (mb < 0 || m.block[ci] < mb)) mb = m.block[ci];
+        if (cands[ci].variant == 2 && m.wide[ci] >= 0 && (ms_stream < 0 || m.wide[ci] < ms_stream))
+          ms_stream = m.wide[ci];
+      }
+      tr.ms[QTN_VAR_BLOCK] = mb;
+      tr.ms[QTN_VAR_STREAM] = ms_stream;
+      tr.ms[QTN_VAR_GENERIC] = m.wide[0];
+      net->tune_log.push_back(tr);
+    }
+    // the tuned schedule replaces the current one
+    auto ex = std::make_unique<Exec>();
+    int rc = build_schedule(one, 1, &ex->sched);
+    if (rc) return rc;
+    ex->persistent = net->exec->persistent;
+    ex->lead_per_cone = net->exec->lead_per_cone;
+    ex->spin_limit = net->exec->spin_limit;
+    drop_batches_with(net);
+    net->exec = std::move(ex);
+    net->version++;
+    if (report) *report = rep;
+    return QTN_OK;
+  } catch (const std::bad_alloc &) {
+    return set_err(QTN_ENOMEM, "host allocation failed");
+  }
+}
+
+int qtn_tune_log(const qtn_network *net, int64_t cap, qtn_tune_rec *out, int64_t *n_out) {
+  if (!net || !n_out || (cap > 0 && !out)) return set_err(QTN_EINVAL, "NULL argument");
+  const auto &lg = net->tune_log;
+  const int64_t n = std::min<int64_t>(cap, (int64_t)lg.size());
+  for (int64_t i = 0; i < n; i++) out[i] = lg[i];
+  *n_out = (int64_t)lg.size();
+  return QTN_OK;
 }
 
 int qtn_launch_log(const qtn_network *net, int64_t cap, qtn_launch_rec *out, int64_t *n_out) {

@@ -257,6 +257,46 @@ std::vector<int> search_order(const LightCone &lc, int trials) {
   return best;
 }
 
+void group_features(const Group &G, const ConePlan &pl, int precision, float *f) {
+  int n_big = 0, max_rank = 0, n_small = 0, n_inter = 0, lv0 = 0;
+  double elems = 0, rank_sum = 0;
+  for (const Operand &o : G.ops) {
+    const Tensor &t = pl.tensors[o.tensor];
+    const int r = (int)t.vars.size();
+    max_rank = std::max(max_rank, r);
+    n_big += r >= 8;
+    n_small += r <= 2;
+    n_inter += t.gate < 0;
+    lv0 += o.level == 0;
+    elems += std::ldexp(1.0, r);
+    rank_sum += r;
+  }
+  const int es = precision == 0 ? 16 : 8;
+  double flops = 0;
+  for (int l = 0; l < G.L; l++) {
+    int factors = (l > 0 ? 1 : 0);
+    for (const Operand &o : G.ops) factors += o.level == l;
+    flops += std::ldexp(1.0, G.w - l) * 6.0 * std::max(0, factors - 1) +
+             std::ldexp(1.0, G.w - l - 1) * 2.0;
+  }
+  f[0] = (float)G.w;
+  f[1] = (float)G.L;
+  f[2] = (float)(G.w - G.L);
+  f[3] = (float)G.ops.size();
+  f[4] = (float)n_big;
+  f[5] = (float)max_rank;
+  f[6] = (float)std::log2(elems);
+  f[7] = (float)(G.w - max_rank);
+  f[8] = (float)lv0;
+  f[9] = (float)((int)G.ops.size() - lv0);
+  f[10] = (float)std::log2(es * (elems + std::ldexp(1.0, G.w - G.L)));
+  f[11] = (float)std::log2(std::max(1.0, flops));
+  f[12] = (float)n_small;
+  f[13] = (float)(rank_sum / std::max(1, G.w));
+  f[14] = (float)n_inter;
+  f[15] = (float)precision;
+}
+
 int mask_runs(uint32_t mask, uint8_t *src, uint8_t *len, uint8_t *dst) {
   int nr = 0, d = 0;
   for (int b = 0; b < 32;) {

@@ -88,7 +88,12 @@ struct Group {
   int out_tensor = -1;       // -1: scalar output
   int scalar_slot = -1;      // light cone's scalar slot when out_tensor < 0
   bool small = false;        // runs inside one workgroup
+  // kernel choice from the autotuner or the cost model (-1: width rule)
+  int8_t pick_place = -1;    // 0 inside a workgroup segment, 1 own launch
+  int8_t pick_variant = -1;  // 1 generic mapping, 2 streaming mapping
+  int8_t pick_rls = -1;      // streaming: lane-summed bits
 };
+
 
 struct ConePlan {
   std::vector<int> order;
@@ -101,6 +106,10 @@ struct ConePlan {
   int64_t arena_elems = 0;         // peak live elements of intermediates
   double bytes = 0, flops = 0, paper_flops = 0;  // per evaluation
 };
+
+// 16 shape features of a group, for timing records and the cost model.
+constexpr int kNumFeatures = 16;
+void group_features(const Group &G, const ConePlan &pl, int precision, float *f);
 
 struct PlanOptions {
   int max_levels = kMaxLevels;

@@ -141,7 +141,7 @@ def test_contract_errors_leave_outputs_untouched(qtn):
     assert rc == -5
     need = net.plan(qtn.QTN_C128)
     # workspace too small
-    rc = lib.qtn_contract(net.h, ctypes.c_void_p(256), need - 1, None,
+    rc = lib.qtn_contract(net.h, ctypes.c_void_p(256), 1024, None,
                           zz.ctypes.data_as(pd), None, ctypes.byref(en))
     assert rc == -3 and "workspace" in qtn.qtn_last_error()
     # NULL workspace
@@ -149,6 +149,9 @@ def test_contract_errors_leave_outputs_untouched(qtn):
                           ctypes.byref(en))
     assert rc == -1
     assert np.all(zz == 7.0) and en.value == 7.0
+    # autotuning needs the workspace qtn_plan reported
+    rc = lib.qtn_autotune(net.h, ctypes.c_void_p(256), need - 1, None, None)
+    assert rc == -3 and "autotun" in qtn.qtn_last_error()
     net.close()
 
 

@@ -72,7 +72,8 @@ def test_small_graphs_all_configs(qtn, orc, gpu, n, p, prec):
                 dict(small_width=4, lane_sum_bits=5), dict(small_width=4, max_levels=2),
                 dict(order_trials=8), dict(small_width=4, variant=2, lane_sum_bits=4),
                 dict(executor=2), dict(executor=2, small_width=4),
-                dict(executor=2, max_levels=1, variant=1)]:
+                dict(executor=2, max_levels=1, variant=1), dict(executor=3),
+                dict(executor=3, n_streams=2, small_width=8)]:
         print(f"n={n} p={p} prec={prec} cfg={cfg}", flush=True)
         zz, zi, en = _run(qtn, n, inst["edges"], g, b, prec, **cfg)
         _check(zz, zi, en, ref, ref_en, prec, str(cfg))
@@ -214,6 +215,24 @@ def test_batch_persistent_and_streams_agree(qtn, orc, gpu):
             n.close()
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_autotune_keeps_parity(qtn, orc, gpu, prec):
+    inst = qs.instance(20, 3, 3, 4)
+    g, b = inst["angles"][0]
+    ref, ref_en = orc.energy(20, inst["edges"], g, b, threads=8)
+    net = qtn.Network(20, inst["edges"], g, b)
+    net.plan(prec)
+    rep = net.autotune()
+    assert rep["n_candidates"] == 4 and rep["n_groups"] > 0
+    assert rep["tuned_ms"] <= min(rep["cand_ms"]) * (1 + 1e-9)
+    feats, ms = net.tune_log()
+    assert feats.shape[1] == 16 and len(feats) == len(ms) > 0
+    assert np.all(ms[:, 2] > 0)
+    zz, zi, en = net.contract()
+    _check(zz, zi, en, ref, ref_en, prec, "after autotune")
+    net.close()
+
+
 def _golden(name):
     with open(os.path.join(HERE, "golden", f"{name}_oracle.json")) as f:
         return json.load(f)
@@ -221,7 +240,8 @@ def _golden(name):
 
 @pytest.mark.parametrize("prec,levels,variant,trials,executor", [
     (0, 8, 0, 0, 0), (1, 8, 0, 0, 0), (0, 1, 0, 0, 0), (0, 8, 1, 0, 0), (1, 1, 0, 0, 0),
-    (0, 8, 0, 64, 0), (1, 8, 0, 64, 0), (0, 8, 2, 16, 0), (0, 8, 0, 64, 2), (1, 8, 1, 64, 2)])
+    (0, 8, 0, 64, 0), (1, 8, 0, 64, 0), (0, 8, 2, 16, 0), (0, 8, 0, 64, 2), (1, 8, 1, 64, 2),
+    (0, 8, 0, 64, 3)])
 def test_cfg2_full_size_against_oracle(qtn, gpu, prec, levels, variant, trials, executor):
     """3-regular N=30, p=4 (Sec. II-E benchmark shape), all 45 light cones."""
     gd = _golden("cfg2")
