@@ -71,12 +71,15 @@ KERNEL_OF = {  # launch-log (kind, variant) -> kernel symbol
 }
 
 
-def kernel_name(rec, prec):
+def kernel_name(rec):
     key = (rec["kind"], rec["variant"] if rec["kind"] == 2 else None)
     base = KERNEL_OF.get(key)
     if base is None:
         return None
-    return f"{base}<{'double2' if prec == 0 else 'float2'}>"
+    if rec["kind"] != 2:  # one instantiation serves every precision
+        return base
+    t = "double2" if rec["prec"] == 0 else "float2"
+    return f"{base}<{t}, {'true' if rec['cvt'] else 'false'}>"
 
 
 def source_hash():
@@ -103,17 +106,20 @@ def stored_traffic(kernel, workload_tag):
     return None if k is None else k.get("hbm_bytes_per_launch")
 
 
-def roofline_of(log, prec, workload_tag):
+def roofline_of(log, workload_tag):
     """The kernel with the most device time in one timed evaluation, against
     its bound: algorithmic bytes (or flops) per launch over its mean launch
     duration (HIP events on the launch stream)."""
     per = {}
     for r in log:
-        name = kernel_name(r, prec)
+        name = kernel_name(r)
         if name is None:
             continue
-        a = per.setdefault(name, {"ms": 0.0, "bytes": 0.0, "flops": 0.0, "launches": 0})
+        a = per.setdefault(name, {"ms": 0.0, "bytes": 0.0, "flops": 0.0, "launches": 0,
+                                  "c64_flops": 0.0})
         a["ms"] += r["ms"]
+        if r["prec"] == 1:
+            a["c64_flops"] += r["flops"]
         a["bytes"] += r["bytes"]
         a["flops"] += r["flops"]
         a["launches"] += 1
@@ -121,7 +127,8 @@ def roofline_of(log, prec, workload_tag):
     sec = t["ms"] / 1e3
     gbs = t["bytes"] / sec / 1e9 if sec > 0 else 0.0
     tflops = t["flops"] / sec / 1e12 if sec > 0 else 0.0
-    fpeak = FP64_PEAK_TFLOPS if prec == 0 else FP32_PEAK_TFLOPS
+    # arithmetic peak of the precision the kernel's flops were done in
+    fpeak = FP32_PEAK_TFLOPS if t["c64_flops"] >= 0.5 * t["flops"] else FP64_PEAK_TFLOPS
     hbm_frac, fp_frac = gbs / HBM_PEAK_GBS, tflops / fpeak
     n = max(1, t["launches"])
     common = {"kernel": kernel, "launches": t["launches"],
@@ -178,12 +185,137 @@ def cpu_baseline(inst, seconds):
                        f"{wall:.1f} s, scaled to one full evaluation by that cost share")}
 
 
+def run_batch(Q, torch, steps, warmup, executor=0, autotune=False, order_trials=16,
+              prec=1, master_seed=2204, count=64):
+    """64 random cubic graphs, N uniform over even sizes in [20, 200], p in
+    {2, 3, 4}; all light cones of all graphs in one batched call."""
+    import qaoa_synth as qs
+    insts = qs.batch_instances(master_seed, count, 20, 200, (2, 3, 4), d=3)
+    t0 = time.perf_counter()
+    nets = []
+    for it in insts:
+        g, b = it["angles"][0]
+        net = Q.Network(it["n"], it["edges"], g, b, order_trials=order_trials,
+                        executor=executor)
+        net.plan(prec)
+        nets.append(net)
+    plan_s = time.perf_counter() - t0
+    tune_s = 0.0
+    if autotune:
+        # tune the 16 networks with the most algorithmic bytes
+        t0 = time.perf_counter()
+        heavy = sorted(nets, key=lambda n: -n.stats()["bytes"])[:16]
+        for net in heavy:
+            net.autotune()
+        tune_s = time.perf_counter() - t0
+        for net in nets:
+            net._ws = None
+        torch.cuda.empty_cache()
+    handles = [n.h for n in nets]
+    ws = Q.workspace(Q.qtn_batch_workspace(handles))
+    total = sum(n.m for n in nets)
+    for _ in range(warmup):
+        Q.qtn_contract_batch(handles, total, ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        zz, en = Q.qtn_contract_batch(handles, total, ws)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = [n.stats() for n in nets]
+    row = {"graphs": count, "light_cones": total, "calls_per_s": steps / dt,
+           "energies_per_s": count * steps / dt, "light_cones_per_s": total * steps / dt,
+           "ms_per_call": 1e3 * dt / steps, "plan_seconds": plan_s, "tune_seconds": tune_s,
+           "alg_bytes_per_call": sum(s["bytes"] for s in st),
+           "max_width": max(s["max_width"] for s in st),
+           "executor": "persistent" if executor in (0, 2) else "launches",
+           "precision": "c64" if prec == 1 else "c128", "order_trials": order_trials}
+    for n in nets:
+        n.close()
+    return row
+
+
+def run_costmodel(Q, torch, prec=1, epochs=600, lr=3e-3, reps=3):
+    """Train the cost model on autotuner timings of N=10 p=1, N=30 p=4 and 16
+    of the batched graphs; judge it by measured time on 32 held-out graphs
+    (16 cubic, 16 quartic, N even in [50, 500], p=3) against the width rule."""
+    import numpy as np
+    import qaoa_synth as qs
+    feats, times = [], []
+
+    def collect(n, edges, g, b, trials):
+        net = Q.Network(n, edges, g, b, order_trials=trials)
+        net.plan(prec)
+        net.autotune()
+        f, m = net.tune_log()
+        feats.append(f)
+        times.append(m)
+        net.close()
+
+    t0 = time.perf_counter()
+    for seed in range(3):
+        it = qs.instance(10, 3, 1, seed)
+        collect(10, it["edges"], *it["angles"][0], 0)
+    it = qs.instance(30, 3, 4, 0)
+    collect(30, it["edges"], *it["angles"][0], 64)
+    for it in qs.batch_instances(2204, 64, 20, 200, (2, 3, 4), d=3)[:16]:
+        collect(it["n"], it["edges"], *it["angles"][0], 16)
+    x = np.concatenate(feats)
+    ms = np.concatenate(times)
+    collect_s = time.perf_counter() - t0
+    r = qs.Rng(4242)
+    init = np.array([0.15 * (2 * r.uniform() - 1) for _ in range(Q.CostModel.n_params)],
+                    dtype=np.float32)
+    cm = Q.CostModel(init)
+    t0 = time.perf_counter()
+    hist = cm.train(x, ms, epochs, lr)
+    train_s = time.perf_counter() - t0
+    torch.cuda.empty_cache()
+    rr = qs.Rng(5000)
+    fallback_ms = learned_ms = 0.0
+    picks = np.zeros(3, dtype=np.int64)
+    for i in range(32):
+        d = 3 if i < 16 else 4
+        sizes = [n for n in range(50, 501) if (n * d) % 2 == 0]
+        n = sizes[rr.below(len(sizes))]
+        inst = qs.instance(n, d, 3, 7000 + i)
+        net = Q.Network(n, inst["edges"], *inst["angles"][0], order_trials=4)
+        net.plan(prec)
+        ws = net.workspace()
+        for mode in ("fallback", "learned"):
+            if mode == "learned":
+                picks += Q.qtn_apply_costmodel(net.h, cm)
+            net.contract(ws)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                net.contract(ws)
+            torch.cuda.synchronize()
+            dt = 1e3 * (time.perf_counter() - t0) / reps
+            if mode == "fallback":
+                fallback_ms += dt
+            else:
+                learned_ms += dt
+        net.close()
+        torch.cuda.empty_cache()
+    cm.close()
+    return {"train_samples": int(len(x)), "collect_seconds": collect_s,
+            "train_seconds": train_s, "epochs": epochs, "loss_first": float(hist[0]),
+            "loss_last": float(hist[-1]), "heldout_graphs": 32,
+            "fallback_ms_per_pass": fallback_ms, "learned_ms_per_pass": learned_ms,
+            "gain": fallback_ms / learned_ms if learned_ms > 0 else None,
+            "picks_block_stream_generic": [int(v) for v in picks],
+            "precision": "c64" if prec == 1 else "c128"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--precision", choices=("c128", "c64"), default="c128")
+    ap.add_argument("--precision", choices=("c128", "c64", "mixed"), default="c128")
+    ap.add_argument("--mixed-width", type=int, default=0,
+                    help="mixed: narrowest group run in complex64 (0 = library default)")
     ap.add_argument("--levels", type=int, default=8, help="merged indices per group (1 = plain)")
     ap.add_argument("--streams", type=int, default=4)
     ap.add_argument("--small-width", type=int, default=0, help="widest group run in-block")
@@ -214,11 +346,11 @@ def main():
 
     torch.cuda.set_device(0)
     inst = qs.instance(30, 3, 4, args.seed, args.angle_sets)
-    prec = Q.QTN_C128 if args.precision == "c128" else Q.QTN_C64
+    prec = {"c128": Q.QTN_C128, "c64": Q.QTN_C64, "mixed": Q.QTN_MIXED}[args.precision]
     log(f"main row: {args.precision} levels={args.levels} streams={args.streams}")
     kcfg = dict(variant=args.variant, lane_sum_bits=args.lane_bits,
                 order_trials=args.order_trials, executor=args.executor,
-                small_width=args.small_width)
+                small_width=args.small_width, mixed_width=args.mixed_width)
     net, dt, plan_s, last = run_rows(Q, torch, inst, prec, args.levels, args.streams,
                                      args.steps, args.warmup, autotune=bool(args.autotune), **kcfg)
     tune = net.tune_report
@@ -237,7 +369,7 @@ def main():
     rnet.contract()
     _, _, timing = rnet.contract_timed()
     tag = f"n30p4_{args.precision}"
-    roof = roofline_of(rnet.launch_log(), prec, tag)
+    roof = roofline_of(rnet.launch_log(), tag)
     rnet.close()
     log(f"  roofline {roof['kernel']}: {roof['hbm_gbs']:.0f} GB/s, "
         f"{roof['fp_tflops']:.2f} TFLOP/s")
@@ -250,7 +382,8 @@ def main():
 
     variants = {}
     if args.variants:
-        for name, pr, lv in (("c64_merged", Q.QTN_C64, 8), ("c128_plain", Q.QTN_C128, 1),
+        for name, pr, lv in (("c128_merged", Q.QTN_C128, 8), ("c64_merged", Q.QTN_C64, 8),
+                             ("mixed_merged", Q.QTN_MIXED, 8), ("c128_plain", Q.QTN_C128, 1),
                              ("c64_plain", Q.QTN_C64, 1)):
             if pr == prec and lv == args.levels:
                 continue
@@ -264,6 +397,15 @@ def main():
                               "n_groups": vst["n_groups"]}
             vnet.close()
             torch.cuda.empty_cache()
+
+    if args.variants:
+        log("variant costmodel (learned selector vs width rule, held-out graphs)")
+        variants["costmodel_c64"] = run_costmodel(Q, torch)
+        torch.cuda.empty_cache()
+        log("variant batch64_c64 (persistent)")
+        variants["batch64_c64"] = run_batch(Q, torch, 5, 1, executor=0,
+                                            autotune=bool(args.autotune))
+        torch.cuda.empty_cache()
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -283,7 +425,7 @@ def main():
         "vs_baseline": evals * PAPER_SECONDS_PER_EVAL,
         "vs_baseline_note": ("paper Tab. II best: 1.4 s per evaluation (NumPy_Merged + "
                              "CuPy_Merged, V100 + host CPU, its own graph instance); context"),
-        "dtype": "complex128" if prec == 0 else "complex64",
+        "dtype": {0: "complex128", 1: "complex64", 2: "complex128+complex64"}[prec],
         "data": "synthetic",
         "config": {
             "workload": (f"QAOA MaxCut energy, random 3-regular N=30 (45 edges), p=4, graph "

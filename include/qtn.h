@@ -42,8 +42,12 @@ extern "C" {
 #define QTN_ESTATE (-5)  /* call order (e.g. contract before plan)        */
 
 /* Arithmetic of the contraction. */
-#define QTN_C128 0 /* complex128 throughout                              */
-#define QTN_C64 1  /* complex64 buckets, FP64 scalars and energy         */
+#define QTN_C128 0  /* complex128 throughout                             */
+#define QTN_C64 1   /* complex64 buckets, FP64 scalars and energy        */
+#define QTN_MIXED 2 /* complex64 for groups of union width >= mixed_width
+                       (their outputs stored as complex64), complex128 for
+                       the rest and for every group ending in a scalar;
+                       operands convert on load                          */
 
 typedef struct qtn_network qtn_network;
 
@@ -71,7 +75,8 @@ typedef struct qtn_config {
                             small groups launched on that cone's stream    */
     int32_t spin_limit;  /* persistent executor: polls before a grid-barrier
                             wait gives up with QTN_EDEVICE [2^26]          */
-    int32_t reserved[6];
+    int32_t mixed_width; /* QTN_MIXED: narrowest group run in complex64 [18] */
+    int32_t reserved[5];
 } qtn_config;
 
 /*
@@ -111,7 +116,7 @@ int qtn_order_minfill(const qtn_network *net, int64_t edge, int32_t *order_out);
  * (Sec. II-C), memory plan and kernel schedule.
  *   orders     NULL (min-fill for every edge) or [n_edges] pointers, each NULL
  *              (min-fill) or a permutation of that light cone's variables
- *   precision  QTN_C128 or QTN_C64
+ *   precision  QTN_C128, QTN_C64 or QTN_MIXED
  *   workspace_bytes_out  device bytes qtn_contract needs
  * Errors: QTN_EINVAL (order not a permutation), QTN_ERANGE (width over cap).
  */
@@ -186,6 +191,9 @@ typedef struct qtn_launch_rec {
     int32_t n_ops;     /* operands of the first group                     */
     int32_t variant;   /* kernel mapping of the first group               */
     int32_t n_units;   /* wave units of the first group                   */
+    int32_t prec;      /* arithmetic of the first group: QTN_C128/QTN_C64 */
+    int32_t cvt;       /* 1: some operand of it is stored in the other
+                          precision and converted on load                 */
     double ms;         /* HIP-event duration                              */
     double bytes;      /* algorithmic bytes of the launch                 */
     double flops;      /* complex-arithmetic FLOPs of the launch          */
@@ -232,6 +240,59 @@ typedef struct qtn_tune_rec {
 
 int qtn_tune_log(const qtn_network *net, int64_t cap, qtn_tune_rec *out,
                  int64_t *n_out);
+
+/*
+ * Learned cost model (16 -> 64 -> 64 -> 3 perceptron, ReLU hidden units):
+ * from a group's 16 shape features (those of qtn_tune_rec) it predicts the
+ * natural log of the launch time in milliseconds of each QTN_VAR_* variant.
+ * Forward, backward and Adam run in FP32 HIP kernels on the caller's
+ * stream; parameters live on the host between calls.  Parameter layout
+ * (floats): W1[16][64], b1[64], W2[64][64], b2[64], W3[64][3], b3[3].
+ */
+#define QTN_MLP_PARAMS 5443
+typedef struct qtn_costmodel qtn_costmodel;
+
+/* A model with the given initial parameters (drawn by the caller). */
+int qtn_costmodel_create(const float *params, qtn_costmodel **out);
+int qtn_costmodel_params(const qtn_costmodel *cm, float *params_out);
+/* Feature standardisation fixed by the first training call. */
+int qtn_costmodel_normalization(const qtn_costmodel *cm, float *mean_out,
+                                float *inv_std_out);
+/* Device bytes for a batch of n samples. */
+int qtn_costmodel_workspace(int64_t n, size_t *bytes_out);
+
+/* Full-batch Adam (lr, beta1 0.9, beta2 0.999) for `epochs` steps on
+ * features x[n][16] and times ms[n][3] (targets log ms; entries <= 0 are not
+ * measured and carry no loss).  loss_history [epochs] or NULL. */
+int qtn_costmodel_train(qtn_costmodel *cm, const float *x, const double *ms,
+                        int64_t n, int32_t epochs, float lr, void *d_workspace,
+                        size_t bytes, void *hip_stream, float *loss_history);
+
+/* Predicted log-ms [n][3] for raw features x[n][16]. */
+int qtn_costmodel_predict(const qtn_costmodel *cm, const float *x, int64_t n,
+                          void *d_workspace, size_t bytes, void *hip_stream,
+                          float *y_out);
+
+/* Loss and gradient at the current parameters for inputs already
+ * standardised (x[n][16]), targets t[n][3] and mask m[n][3]. */
+int qtn_costmodel_grad(const qtn_costmodel *cm, const float *x, const float *t,
+                       const float *m, int64_t n, void *d_workspace,
+                       size_t bytes, void *hip_stream, float *loss_out,
+                       float *grad_out);
+
+/* One Adam step with a caller-given gradient. */
+int qtn_costmodel_adam_step(qtn_costmodel *cm, const float *grad, float lr,
+                            void *d_workspace, size_t bytes, void *hip_stream);
+
+/* Picks, for every group of a planned network, the variant with the lowest
+ * predicted time (inside a workgroup only up to width 16) and rebuilds the
+ * schedule.  counts_out [3] or NULL: groups per QTN_VAR_*.  Workspace: the
+ * cost-model bytes for as many samples as the network has groups. */
+int qtn_apply_costmodel(qtn_network *net, const qtn_costmodel *cm,
+                        void *d_workspace, size_t bytes, void *hip_stream,
+                        int32_t *counts_out);
+
+void qtn_costmodel_free(qtn_costmodel *cm);
 
 /* Plan statistics. */
 typedef struct qtn_plan_stats {

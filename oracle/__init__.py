@@ -53,6 +53,9 @@ def lib():
         L.qtno_p1_closed_form.argtypes = [i, i, ip, d, d, dp]
         L.qtno_energy.argtypes = [i, i, ip, i, dp, dp, i, i, ip, i, dp, dp, dp]
         L.qtno_contract_bucket.argtypes = [i, ip, ip, dp, i, ip, i, ip, dp]
+        L.qtno_mlp_forward.argtypes = [dp, dp, i, dp]
+        L.qtno_mlp_loss_grad.argtypes = [dp, dp, dp, dp, i, dp, dp]
+        L.qtno_mlp_adam.argtypes = [dp, dp, dp, dp, i, d, d, d, d]
         _lib = L
     return _lib
 
@@ -199,3 +202,43 @@ def contract_bucket(tensors, sum_vars, out_idx):
         out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
     res = out[0::2] + 1j * out[1::2]
     return res.reshape((2,) * len(out_idx)) if out_idx else res.reshape(())
+
+
+# ------------------------------------------------------------- cost model
+
+MLP_SHAPE = (16, 64, 64, 3)
+
+
+def mlp_nparams():
+    return lib().qtno_mlp_nparams()
+
+
+def mlp_forward(params, x):
+    p, pp = _dbls(params)
+    xx, xp = _dbls(x)
+    n = len(xx) // 16
+    y, yp = _dbls(np.zeros(n * 3))
+    _check(lib().qtno_mlp_forward(pp, xp, n, yp))
+    return y.reshape(n, 3)
+
+
+def mlp_loss_grad(params, x, t, m):
+    p, pp = _dbls(params)
+    xx, xp = _dbls(x)
+    tt, tp = _dbls(t)
+    mm, mp = _dbls(m)
+    n = len(xx) // 16
+    g, gp = _dbls(np.zeros(len(p)))
+    loss = ctypes.c_double()
+    _check(lib().qtno_mlp_loss_grad(pp, xp, tp, mp, n, ctypes.byref(loss), gp))
+    return loss.value, g
+
+
+def mlp_adam(params, m1, m2, grad, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam step; returns new (params, m1, m2)."""
+    p, pp = _dbls(np.array(params, dtype=np.float64))
+    a, ap = _dbls(np.array(m1, dtype=np.float64))
+    b, bp = _dbls(np.array(m2, dtype=np.float64))
+    g, gp = _dbls(grad)
+    _check(lib().qtno_mlp_adam(pp, ap, bp, gp, int(t), lr, beta1, beta2, eps))
+    return p, a, b

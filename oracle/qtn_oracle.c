@@ -957,3 +957,151 @@ int qtno_contract_bucket(int n_tensors, const int *ranks, const int *idx_flat,
     free(doff);
     return QTNO_OK;
 }
+
+/* ------------------------------------------------------------- cost model */
+
+/*
+ * FP64 reference of the cost-model network: 16 inputs, two hidden layers of
+ * 64 rectified-linear units, 3 linear outputs (predicted log launch time of
+ * each kernel variant).  Parameters are packed as
+ *   W1[16][64], b1[64], W2[64][64], b2[64], W3[64][3], b3[3]
+ * (row-major, input index first).  The loss is the mean of the squared
+ * errors over the measured entries:
+ *   loss = sum_{i,k} m_ik (y_ik - t_ik)^2 / sum_{i,k} m_ik.
+ * qtno_mlp_loss_grad returns the loss and d loss / d params; qtno_mlp_adam
+ * takes one Adam step (Kingma & Ba 2015) with bias correction at step t.
+ */
+#define MLP_IN 16
+#define MLP_H 64
+#define MLP_OUT 3
+#define MLP_NPARAM (MLP_IN * MLP_H + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H * MLP_OUT + MLP_OUT)
+
+int qtno_mlp_nparams(void) { return MLP_NPARAM; }
+
+static void mlp_views(const double *p, const double **w1, const double **b1,
+                      const double **w2, const double **b2, const double **w3,
+                      const double **b3)
+{
+    *w1 = p;
+    *b1 = *w1 + MLP_IN * MLP_H;
+    *w2 = *b1 + MLP_H;
+    *b2 = *w2 + MLP_H * MLP_H;
+    *w3 = *b2 + MLP_H;
+    *b3 = *w3 + MLP_H * MLP_OUT;
+}
+
+int qtno_mlp_forward(const double *params, const double *x, int n, double *y)
+{
+    const double *w1, *b1, *w2, *b2, *w3, *b3;
+    mlp_views(params, &w1, &b1, &w2, &b2, &w3, &b3);
+    double h1[MLP_H], h2[MLP_H];
+    for (int i = 0; i < n; i++) {
+        const double *xi = &x[i * MLP_IN];
+        for (int j = 0; j < MLP_H; j++) {
+            double a = b1[j];
+            for (int k = 0; k < MLP_IN; k++)
+                a += xi[k] * w1[k * MLP_H + j];
+            h1[j] = a > 0 ? a : 0;
+        }
+        for (int j = 0; j < MLP_H; j++) {
+            double a = b2[j];
+            for (int k = 0; k < MLP_H; k++)
+                a += h1[k] * w2[k * MLP_H + j];
+            h2[j] = a > 0 ? a : 0;
+        }
+        for (int j = 0; j < MLP_OUT; j++) {
+            double a = b3[j];
+            for (int k = 0; k < MLP_H; k++)
+                a += h2[k] * w3[k * MLP_OUT + j];
+            y[i * MLP_OUT + j] = a;
+        }
+    }
+    return QTNO_OK;
+}
+
+int qtno_mlp_loss_grad(const double *params, const double *x, const double *t,
+                       const double *m, int n, double *loss, double *grad)
+{
+    const double *w1, *b1, *w2, *b2, *w3, *b3;
+    mlp_views(params, &w1, &b1, &w2, &b2, &w3, &b3);
+    double *gw1 = grad, *gb1 = gw1 + MLP_IN * MLP_H, *gw2 = gb1 + MLP_H;
+    double *gb2 = gw2 + MLP_H * MLP_H, *gw3 = gb2 + MLP_H, *gb3 = gw3 + MLP_H * MLP_OUT;
+    for (int q = 0; q < MLP_NPARAM; q++)
+        grad[q] = 0;
+    double msum = 0;
+    for (int q = 0; q < n * MLP_OUT; q++)
+        msum += m[q];
+    if (msum <= 0)
+        return fail(QTNO_EINVAL, "no measured entries");
+    double l = 0;
+    double z1[MLP_H], h1[MLP_H], z2[MLP_H], h2[MLP_H], y[MLP_OUT];
+    double dy[MLP_OUT], dh2[MLP_H], dh1[MLP_H];
+    for (int i = 0; i < n; i++) {
+        const double *xi = &x[i * MLP_IN];
+        for (int j = 0; j < MLP_H; j++) {
+            double a = b1[j];
+            for (int k = 0; k < MLP_IN; k++)
+                a += xi[k] * w1[k * MLP_H + j];
+            z1[j] = a;
+            h1[j] = a > 0 ? a : 0;
+        }
+        for (int j = 0; j < MLP_H; j++) {
+            double a = b2[j];
+            for (int k = 0; k < MLP_H; k++)
+                a += h1[k] * w2[k * MLP_H + j];
+            z2[j] = a;
+            h2[j] = a > 0 ? a : 0;
+        }
+        for (int j = 0; j < MLP_OUT; j++) {
+            double a = b3[j];
+            for (int k = 0; k < MLP_H; k++)
+                a += h2[k] * w3[k * MLP_OUT + j];
+            y[j] = a;
+            const double e = y[j] - t[i * MLP_OUT + j], mm = m[i * MLP_OUT + j];
+            l += mm * e * e;
+            dy[j] = 2.0 * mm * e / msum;
+        }
+        for (int j = 0; j < MLP_OUT; j++) {
+            gb3[j] += dy[j];
+            for (int k = 0; k < MLP_H; k++)
+                gw3[k * MLP_OUT + j] += h2[k] * dy[j];
+        }
+        for (int k = 0; k < MLP_H; k++) {
+            double a = 0;
+            for (int j = 0; j < MLP_OUT; j++)
+                a += w3[k * MLP_OUT + j] * dy[j];
+            dh2[k] = z2[k] > 0 ? a : 0;
+        }
+        for (int j = 0; j < MLP_H; j++) {
+            gb2[j] += dh2[j];
+            for (int k = 0; k < MLP_H; k++)
+                gw2[k * MLP_H + j] += h1[k] * dh2[j];
+        }
+        for (int k = 0; k < MLP_H; k++) {
+            double a = 0;
+            for (int j = 0; j < MLP_H; j++)
+                a += w2[k * MLP_H + j] * dh2[j];
+            dh1[k] = z1[k] > 0 ? a : 0;
+        }
+        for (int j = 0; j < MLP_H; j++) {
+            gb1[j] += dh1[j];
+            for (int k = 0; k < MLP_IN; k++)
+                gw1[k * MLP_H + j] += xi[k] * dh1[j];
+        }
+    }
+    *loss = l / msum;
+    return QTNO_OK;
+}
+
+/* One Adam step on params (moments mom1, mom2 updated in place), step t >= 1. */
+int qtno_mlp_adam(double *params, double *mom1, double *mom2, const double *grad,
+                  int t, double lr, double beta1, double beta2, double eps)
+{
+    const double c1 = 1.0 - pow(beta1, t), c2 = 1.0 - pow(beta2, t);
+    for (int q = 0; q < MLP_NPARAM; q++) {
+        mom1[q] = beta1 * mom1[q] + (1 - beta1) * grad[q];
+        mom2[q] = beta2 * mom2[q] + (1 - beta2) * grad[q] * grad[q];
+        params[q] -= lr * (mom1[q] / c1) / (sqrt(mom2[q] / c2) + eps);
+    }
+    return QTNO_OK;
+}

@@ -6,4 +6,4 @@ The C ABI is ``include/qtn.h``; ``binding`` exposes it under the same names.
 """
 
 from .binding import *  # noqa: F401,F403
-from .binding import Network, QTN_C128, QTN_C64, QtnError  # noqa: F401
+from .binding import Network, QTN_C128, QTN_C64, QTN_MIXED, QtnError  # noqa: F401

@@ -24,6 +24,7 @@ QTN_ESTATE = -5
 
 QTN_C128 = 0
 QTN_C64 = 1
+QTN_MIXED = 2
 
 NKERNELS = 5
 K_FILL, K_BLOCK, K_WIDE, K_REDUCE, K_PERSISTENT = range(5)
@@ -36,7 +37,12 @@ EXPORTS = (
     "qtn_batch_workspace", "qtn_contract_timed", "qtn_get_plan_stats",
     "qtn_bucket_widths", "qtn_network_free", "qtn_last_error", "qtn_launch_log",
     "qtn_plan_order", "qtn_autotune", "qtn_tune_log",
+    "qtn_costmodel_create", "qtn_costmodel_params", "qtn_costmodel_normalization",
+    "qtn_costmodel_workspace", "qtn_costmodel_train", "qtn_costmodel_predict",
+    "qtn_costmodel_grad", "qtn_costmodel_adam_step", "qtn_apply_costmodel",
+    "qtn_costmodel_free",
 )
+MLP_PARAMS = 5443
 
 
 class qtn_config(ctypes.Structure):
@@ -45,7 +51,7 @@ class qtn_config(ctypes.Structure):
                 ("eager", ctypes.c_int32), ("lane_sum_bits", ctypes.c_int32),
                 ("variant", ctypes.c_int32), ("order_trials", ctypes.c_int32),
                 ("executor", ctypes.c_int32), ("spin_limit", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("mixed_width", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
 
 
 class qtn_timing(ctypes.Structure):
@@ -59,7 +65,8 @@ class qtn_launch_rec(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("group", ctypes.c_int32),
                 ("n_groups", ctypes.c_int32), ("w", ctypes.c_int32), ("L", ctypes.c_int32),
                 ("n_ops", ctypes.c_int32), ("variant", ctypes.c_int32),
-                ("n_units", ctypes.c_int32), ("ms", ctypes.c_double),
+                ("n_units", ctypes.c_int32), ("prec", ctypes.c_int32),
+                ("cvt", ctypes.c_int32), ("ms", ctypes.c_double),
                 ("bytes", ctypes.c_double), ("flops", ctypes.c_double)]
 
 
@@ -123,12 +130,25 @@ def lib():
         L.qtn_plan_order.argtypes = [P, i64, pi32]
         L.qtn_autotune.argtypes = [P, P, ctypes.c_size_t, P, ctypes.POINTER(qtn_tune_report)]
         L.qtn_tune_log.argtypes = [P, i64, ctypes.POINTER(qtn_tune_rec), ctypes.POINTER(i64)]
+        pf = ctypes.POINTER(ctypes.c_float)
+        sz = ctypes.c_size_t
+        L.qtn_costmodel_create.argtypes = [pf, ctypes.POINTER(P)]
+        L.qtn_costmodel_params.argtypes = [P, pf]
+        L.qtn_costmodel_normalization.argtypes = [P, pf, pf]
+        L.qtn_costmodel_workspace.argtypes = [i64, ctypes.POINTER(sz)]
+        L.qtn_costmodel_train.argtypes = [P, pf, pd, i64, i32, ctypes.c_float, P, sz, P, pf]
+        L.qtn_costmodel_predict.argtypes = [P, pf, i64, P, sz, P, pf]
+        L.qtn_costmodel_grad.argtypes = [P, pf, pf, pf, i64, P, sz, P, pf, pf]
+        L.qtn_costmodel_adam_step.argtypes = [P, pf, ctypes.c_float, P, sz, P]
+        L.qtn_apply_costmodel.argtypes = [P, P, P, sz, P, pi32]
+        L.qtn_costmodel_free.argtypes = [P]
+        L.qtn_costmodel_free.restype = None
         L.qtn_launch_log.argtypes = [P, i64, ctypes.POINTER(qtn_launch_rec),
                                      ctypes.POINTER(i64)]
         L.qtn_network_free.argtypes = [P]
         L.qtn_network_free.restype = None
         for name in EXPORTS:
-            if name not in ("qtn_network_free", "qtn_last_error"):
+            if name not in ("qtn_network_free", "qtn_last_error", "qtn_costmodel_free"):
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib

@@ -13,17 +13,17 @@ import numpy as np
 import torch
 
 from . import _capi
-from ._capi import (QTN_C128, QTN_C64, QtnError, check, lib, qtn_config,
+from ._capi import (QTN_C128, QTN_C64, QTN_MIXED, QtnError, check, lib, qtn_config,
                     qtn_launch_rec, qtn_plan_stats, qtn_timing, qtn_tune_rec,
                     qtn_tune_report)
 
 __all__ = [
-    "QTN_C128", "QTN_C64", "QtnError", "qtn_network_build", "qtn_network_info",
+    "QTN_C128", "QTN_C64", "QTN_MIXED", "QtnError", "qtn_network_build", "qtn_network_info",
     "qtn_order_minfill", "qtn_plan", "qtn_set_angles", "qtn_contract",
     "qtn_contract_timed", "qtn_contract_batch", "qtn_batch_workspace",
     "qtn_get_plan_stats", "qtn_bucket_widths", "qtn_network_free",
     "qtn_last_error", "qtn_launch_log", "qtn_plan_order", "qtn_autotune", "qtn_tune_log",
-    "Network", "workspace", "stream_handle",
+    "Network", "CostModel", "qtn_apply_costmodel", "workspace", "stream_handle",
 ]
 
 _pi32 = ctypes.POINTER(ctypes.c_int32)
@@ -47,7 +47,7 @@ def qtn_last_error() -> str:
 def qtn_network_build(n_vertices, edges, gamma, beta, max_levels=0,
                       small_width=0, max_width=0, n_streams=0, eager=False,
                       lane_sum_bits=0, variant=0, order_trials=0, executor=0,
-                      spin_limit=0):
+                      spin_limit=0, mixed_width=0):
     """Returns an opaque handle (int)."""
     e, ep = _i32(edges)
     g, gp = _f64(gamma)
@@ -55,7 +55,8 @@ def qtn_network_build(n_vertices, edges, gamma, beta, max_levels=0,
     if len(g) != len(b):
         raise ValueError("gamma and beta differ in length")
     cfg = qtn_config(max_levels, small_width, max_width, n_streams, int(eager),
-                     lane_sum_bits, variant, order_trials, executor, spin_limit)
+                     lane_sum_bits, variant, order_trials, executor, spin_limit,
+                     mixed_width)
     h = ctypes.c_void_p()
     check(lib().qtn_network_build(int(n_vertices), len(e) // 2, ep, len(g), gp,
                                   bp, ctypes.byref(cfg), ctypes.byref(h)))
@@ -289,3 +290,106 @@ class Network:
             self.close()
         except Exception:
             pass
+
+
+_pf = ctypes.POINTER(ctypes.c_float)
+
+
+def _f32(x):
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.float32).ravel())
+    return a, a.ctypes.data_as(_pf)
+
+
+class CostModel:
+    """Owning wrapper of a qtn_costmodel (16-64-64-3 perceptron)."""
+
+    n_params = _capi.MLP_PARAMS
+
+    def __init__(self, params):
+        p, pp = _f32(params)
+        if len(p) != self.n_params:
+            raise ValueError(f"expected {self.n_params} parameters")
+        h = ctypes.c_void_p()
+        check(lib().qtn_costmodel_create(pp, ctypes.byref(h)))
+        self.h = h.value
+
+    @staticmethod
+    def workspace(n):
+        b = ctypes.c_size_t()
+        check(lib().qtn_costmodel_workspace(int(n), ctypes.byref(b)))
+        return workspace(b.value)
+
+    def params(self):
+        out = np.zeros(self.n_params, dtype=np.float32)
+        check(lib().qtn_costmodel_params(self.h, out.ctypes.data_as(_pf)))
+        return out
+
+    def normalization(self):
+        mu = np.zeros(16, dtype=np.float32)
+        inv = np.zeros(16, dtype=np.float32)
+        check(lib().qtn_costmodel_normalization(self.h, mu.ctypes.data_as(_pf),
+                                                inv.ctypes.data_as(_pf)))
+        return mu, inv
+
+    def train(self, x, ms, epochs, lr, stream=None):
+        x, xp = _f32(x)
+        n = len(x) // 16
+        m, mp = _f64(ms)
+        ws = self.workspace(n)
+        hist = np.zeros(epochs, dtype=np.float32)
+        check(lib().qtn_costmodel_train(self.h, xp, mp, n, int(epochs), float(lr),
+                                        ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                        stream_handle(stream), hist.ctypes.data_as(_pf)))
+        return hist
+
+    def predict(self, x, stream=None):
+        x, xp = _f32(x)
+        n = len(x) // 16
+        ws = self.workspace(n)
+        y = np.zeros(n * 3, dtype=np.float32)
+        check(lib().qtn_costmodel_predict(self.h, xp, n, ctypes.c_void_p(ws.data_ptr()),
+                                          ws.numel(), stream_handle(stream),
+                                          y.ctypes.data_as(_pf)))
+        return y.reshape(n, 3)
+
+    def grad(self, x, t, m, stream=None):
+        x, xp = _f32(x)
+        t, tp = _f32(t)
+        m, mp = _f32(m)
+        n = len(x) // 16
+        ws = self.workspace(n)
+        loss = ctypes.c_float()
+        g = np.zeros(self.n_params, dtype=np.float32)
+        check(lib().qtn_costmodel_grad(self.h, xp, tp, mp, n, ctypes.c_void_p(ws.data_ptr()),
+                                       ws.numel(), stream_handle(stream), ctypes.byref(loss),
+                                       g.ctypes.data_as(_pf)))
+        return loss.value, g
+
+    def adam_step(self, grad, lr, stream=None):
+        g, gp = _f32(grad)
+        ws = self.workspace(1)
+        check(lib().qtn_costmodel_adam_step(self.h, gp, float(lr),
+                                            ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                            stream_handle(stream)))
+
+    def close(self):
+        if self.h:
+            lib().qtn_costmodel_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def qtn_apply_costmodel(net, cm, stream=None):
+    """Variant per group from the cost model; returns groups per variant
+    (block, stream, generic)."""
+    n_groups = qtn_get_plan_stats(net)["n_groups"]
+    ws = CostModel.workspace(max(1, n_groups))
+    counts = np.zeros(3, dtype=np.int32)
+    check(lib().qtn_apply_costmodel(net, cm.h, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                    stream_handle(stream), counts.ctypes.data_as(_pi32)))
+    return counts

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 SO = os.path.join(HERE, "libqtn.so")
 
-SOURCES = ["kernels.hip", "plan.cpp", "capi.cpp"]
+SOURCES = ["kernels.hip", "mlp.hip", "plan.cpp", "capi.cpp"]
 
 # Packed FP32 instructions stay off: the compiler must not form them.
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -15,6 +15,7 @@
 
 #include "device.hpp"
 #include "kernels.hpp"
+#include "mlp.hpp"
 #include "plan.hpp"
 #include "qtn.h"
 
@@ -73,7 +74,8 @@ struct Task {
 
 // Device layout and launch list of one or more planned networks.
 struct Schedule {
-  int prec = 0, elem = 16;
+  int prec = 0;        // QTN_C128, QTN_C64 or QTN_MIXED
+  int scalar_prec = 0;  // storage of the scalar slots
   std::vector<DevGroup> groups;
   std::vector<DevOp> ops;
   std::vector<int2> ranges;  // first n_cones: each cone's leading small groups
@@ -112,7 +114,7 @@ struct Runtime {
   void *ws = nullptr;  // workspace holding the uploaded descriptors
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
-  int persist_blocks[2] = {0, 0};
+  int persist_blocks = 0;
   uint32_t *pinned_err = nullptr;
 
   void release() {
@@ -130,7 +132,7 @@ struct Runtime {
     if (pinned) (void)hipHostFree(pinned);
     if (pinned_err) (void)hipHostFree(pinned_err);
     pinned_err = nullptr;
-    persist_blocks[0] = persist_blocks[1] = 0;
+    persist_blocks = 0;
     ev_in = ev_fork = nullptr;
     main = nullptr;
     pinned = nullptr;
@@ -230,30 +232,40 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S, const Force *fo
   Schedule &s = *S;
   s = Schedule();
   s.prec = nets[0]->precision;
-  s.elem = s.prec == kPrecC128 ? 16 : 8;
-  const int64_t align_el = 256 / s.elem;
-  auto al = [&](int64_t x) { return (x + align_el - 1) / align_el * align_el; };
+  s.scalar_prec = s.prec == kPrecC64 ? 1 : 0;
+  auto al = [](int64_t bytes) { return (bytes + 255) / 256 * 256; };
+  auto es = [](int prec) { return prec == 1 ? (int64_t)8 : (int64_t)16; };
+  // every offset below is in bytes from the data base
   int64_t data = 0;
   int n_scalars = 0;
   for (int i = 0; i < n; i++) {
     if (nets[i]->precision != s.prec) return set_err(QTN_EINVAL, "batched networks differ in precision");
-    s.fills.push_back({(int64_t)s.n_angles, data, nets[i]->p, 0});
+    FillDesc f{(int64_t)s.n_angles, -1, -1, nets[i]->p, 0};
+    const int64_t tab = gate_table_elems(nets[i]->p);
+    if (s.prec != kPrecC64) {
+      f.table128 = data;
+      data += al(tab * 16);
+    }
+    if (s.prec != kPrecC128) {
+      f.table64 = data;
+      data += al(tab * 8);
+    }
+    s.fills.push_back(f);
     s.n_angles += 2 * nets[i]->p;
-    data += al(gate_table_elems(nets[i]->p));
     for (auto &pl : nets[i]->plans) n_scalars += pl.n_scalars;
   }
   s.scalar_off = data;
-  data += al(n_scalars);
+  data += al(n_scalars * es(s.scalar_prec));
   int scalar_next = 0;
   s.ncb.push_back(0);
   for (int i = 0; i < n; i++) {
     const qtn_network *net = nets[i];
-    const int64_t table = s.fills[i].table_off;
+    const int64_t table[2] = {s.fills[i].table128, s.fills[i].table64};
     for (size_t c = 0; c < net->plans.size(); c++) {
       const ConePlan &pl = net->plans[c];
       const LightCone &lc = net->cones[c];
       const int64_t arena = data;
-      data += al(pl.arena_elems);
+      data += al(pl.arena_bytes);
       s.csb.push_back(scalar_next);
       std::vector<Task> tasks;
       int open_begin = -1;
@@ -269,17 +281,22 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S, const Force *fo
         if (G.ops.size() > 255) return set_err(QTN_ERANGE, "bucket with more than 255 tensors");
         DevGroup dg;
         std::memset(&dg, 0, sizeof dg);
-        dg.out_off = G.out_tensor >= 0 ? arena + pl.tensors[G.out_tensor].offset
-                                        : s.scalar_off + scalar_next + G.scalar_slot;
+        if (G.out_tensor < 0 && G.prec != s.scalar_prec)
+          return set_err(QTN_EINVAL, "scalar group precision differs from the scalar slots");
+        dg.out_off = G.out_tensor >= 0
+                         ? arena + pl.tensors[G.out_tensor].offset
+                         : s.scalar_off + (int64_t)(scalar_next + G.scalar_slot) * es(s.scalar_prec);
+        dg.prec = (uint8_t)G.prec;
         dg.op_begin = (int32_t)s.ops.size();
         dg.w = (uint8_t)G.w;
         dg.L = (uint8_t)G.L;
         dg.n_ops = (uint8_t)G.ops.size();
-        double in_el = 0;
+        double in_bytes = 0;
         std::vector<int> per_level(G.L, 0);
         for (const Operand &o : G.ops) {
           per_level[o.level]++;
-          in_el += std::ldexp(1.0, (int)pl.tensors[o.tensor].vars.size());
+          const Tensor &t = pl.tensors[o.tensor];
+          in_bytes += std::ldexp(1.0, (int)t.vars.size()) * es(t.gate >= 0 ? G.prec : t.prec);
         }
         // streaming mapping unless the group is too large for its LDS tables
         int var_req = net->variant, rls_req = net->lane_sum_bits;
@@ -376,8 +393,14 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S, const Force *fo
           const Tensor &t = pl.tensors[o.tensor];
           DevOp d;
           std::memset(&d, 0, sizeof d);
-          d.off = t.gate >= 0 ? table + gate_offset(lc.gates[t.gate], t.transposed, net->p)
-                              : arena + t.offset;
+          if (t.gate >= 0) {
+            // gate operands read the table of the group's own precision
+            d.off = table[G.prec] + gate_offset(lc.gates[t.gate], t.transposed, net->p) * es(G.prec);
+            d.dt = (uint8_t)G.prec;
+          } else {
+            d.off = arena + t.offset;
+            d.dt = (uint8_t)t.prec;
+          }
           d.mask = o.mask;
           d.level = (uint8_t)o.level;
           uint8_t rs[32], rl[32], rd[32];
@@ -393,9 +416,10 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S, const Force *fo
             for (uint32_t st = 0; st < (1u << dg.sl); st++)
               s.stab.push_back((int32_t)pext32(st << (1 + dg.rls), o.mask));
           }
+          if (d.dt != dg.prec) dg.cvt = 1;
           s.ops.push_back(d);
         }
-        double gb = s.elem * (in_el + std::ldexp(1.0, G.w - G.L)), gf = 0;
+        double gb = in_bytes + es(G.prec) * std::ldexp(1.0, G.w - G.L), gf = 0;
         for (int l = 0; l < G.L; l++) {
           int factors = per_level[l] + (l > 0 ? 1 : 0);
           gf += std::ldexp(1.0, G.w - l) * 6.0 * std::max(0, factors - 1) +
@@ -499,7 +523,7 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S, const Force *fo
   s.off_steps = align_up(s.off_items + sizeof(int4) * s.items.size(), 256);
   s.off_ctl = align_up(s.off_steps + sizeof(int) * s.step_begin.size(), 256);
   s.off_data = align_up(s.off_ctl + sizeof(uint32_t) * s.n_ctl, 256);
-  s.total = s.off_data + (size_t)data * s.elem;
+  s.total = s.off_data + (size_t)data;
   s.desc_blob.assign(s.off_data - s.off_desc, 0);
   auto put = [&](size_t off, const void *src, size_t bytes) {
     if (bytes) std::memcpy(s.desc_blob.data() + (off - s.off_desc), src, bytes);
@@ -537,8 +561,7 @@ int ensure_runtime(Runtime &rt, int n_streams, int n_res) {
     QTN_HIP(hipHostMalloc((void **)&rt.pinned_err, 4 * sizeof(uint32_t), hipHostMallocDefault));
     int n_cu = 0;
     QTN_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
-    rt.persist_blocks[0] = persistent_blocks(kPrecC128, n_cu);
-    rt.persist_blocks[1] = persistent_blocks(kPrecC64, n_cu);
+    rt.persist_blocks = persistent_blocks(kPrecC128, n_cu);
   }
   if (rt.pinned_n < (size_t)n_res) {
     if (rt.pinned) QTN_HIP(hipHostFree(rt.pinned));
@@ -598,7 +621,7 @@ int enqueue(Exec &X, Timer &tm) {
                       (const FillDesc *)(ws + s.off_fills), s.n_nets, rt.main));
   if ((rc = tm.end(rt.main))) return rc;
   if (X.persistent) {
-    const int nb = rt.persist_blocks[s.prec == kPrecC128 ? 0 : 1];
+    const int nb = rt.persist_blocks;
     if (nb < 1) return set_err(QTN_EDEVICE, "persistent kernel does not fit on the device");
     double b_all = 0, f_all = 0;
     for (int k = 0; k < QTN_NKERNELS; k++) {
@@ -654,7 +677,8 @@ int enqueue(Exec &X, Timer &tm) {
         if (t.kind == QTN_K_BLOCK)
           QTN_HIP(launch_block_groups(s.prec, data, groups, ops, stab, uperm, ranges, t.index, 1, hs));
         else
-          QTN_HIP(launch_wide_group(s.prec, t.variant, data, groups, ops, stab, uperm, t.index, t.n_units, hs));
+          QTN_HIP(launch_wide_group(s.groups[t.index].prec, s.groups[t.index].cvt != 0, t.variant,
+                                    data, groups, ops, stab, uperm, t.index, t.n_units, hs));
         if ((rc = tm.end(hs))) return rc;
       }
     }
@@ -665,7 +689,7 @@ int enqueue(Exec &X, Timer &tm) {
   }
   }
   if ((rc = tm.begin(QTN_K_REDUCE, rt.main))) return rc;
-  QTN_HIP(launch_reduce(s.prec, data, s.scalar_off, (const int *)(ws + s.off_csb),
+  QTN_HIP(launch_reduce(s.scalar_prec == 1 ? kPrecC64 : kPrecC128, data, s.scalar_off, (const int *)(ws + s.off_csb),
                         (const int *)(ws + s.off_ncb), s.n_cones, s.n_nets,
                         (double *)(ws + s.off_res), rt.main));
   if ((rc = tm.end(rt.main))) return rc;
@@ -789,6 +813,9 @@ int qtn_network_build(int32_t n_vertices, int64_t n_edges, const int32_t *edges,
       if (cfg->executor < 0 || cfg->executor > 3) return set_err(QTN_EINVAL, "executor must be 0..3");
       net->executor = cfg->executor;
       if (cfg->spin_limit > 0) net->spin_limit = (uint32_t)cfg->spin_limit;
+      if (cfg->mixed_width < 0 || cfg->mixed_width > 32)
+        return set_err(QTN_EINVAL, "mixed_width must be in 0..32");
+      if (cfg->mixed_width > 0) net->opt.mixed_width = cfg->mixed_width;
     }
     const int m = (int)n_edges;
     net->cones.resize(m);
@@ -849,13 +876,13 @@ int qtn_plan(qtn_network *net, const int32_t *const *orders, int32_t precision,
              size_t *workspace_bytes_out) {
   try {
     if (!net) return set_err(QTN_EINVAL, "network is NULL");
-    if (precision != QTN_C128 && precision != QTN_C64)
-      return set_err(QTN_EINVAL, "precision must be QTN_C128 or QTN_C64");
+    if (precision != QTN_C128 && precision != QTN_C64 && precision != QTN_MIXED)
+      return set_err(QTN_EINVAL, "precision must be QTN_C128, QTN_C64 or QTN_MIXED");
     const int m = (int)net->cones.size();
     std::vector<ConePlan> plans(m);
     std::vector<std::string> errs(m);
     PlanOptions o = net->opt;
-    o.elem_bytes = precision == QTN_C128 ? 16 : 8;
+    o.precision = precision;
     parallel_for(m, [&](int e) {
       std::vector<int> ord;
       if (orders && orders[e])
@@ -947,6 +974,8 @@ static int contract_impl(qtn_network *net, void *ws, size_t bytes, void *stream,
           lr.n_ops = g.n_ops;
           lr.variant = g.variant;
           lr.n_units = (int32_t)g.n_units;
+          lr.prec = g.prec;
+          lr.cvt = g.cvt;
         }
         net->launch_log.push_back(lr);
       }
@@ -1218,6 +1247,270 @@ int qtn_bucket_widths(const qtn_network *net, int64_t edge, int32_t *widths_out)
   std::copy(w.begin(), w.end(), widths_out);
   return QTN_OK;
 }
+
+}  // extern "C"
+
+struct qtn_costmodel {
+  std::vector<float> params, m1, m2;
+  float mean[kMlpIn], inv_std[kMlpIn];
+  bool norm_set = false;
+  int step = 0;
+};
+
+namespace {
+
+int mlp_upload_inputs(const qtn_costmodel *cm, const float *x, int64_t n, const MlpBuffers &b,
+                      bool normalize, hipStream_t s, std::vector<float> &stage) {
+  stage.assign(x, x + n * kMlpIn);
+  if (normalize)
+    for (int64_t i = 0; i < n; i++)
+      for (int k = 0; k < kMlpIn; k++)
+        stage[i * kMlpIn + k] = (stage[i * kMlpIn + k] - cm->mean[k]) * cm->inv_std[k];
+  QTN_HIP(hipMemcpyAsync(b.x, stage.data(), sizeof(float) * n * kMlpIn, hipMemcpyHostToDevice, s));
+  QTN_HIP(hipMemcpyAsync(b.params, cm->params.data(), sizeof(float) * kMlpParams,
+                         hipMemcpyHostToDevice, s));
+  return QTN_OK;
+}
+
+int mlp_check_ws(int64_t n, void *ws, size_t bytes) {
+  if (n < 1) return set_err(QTN_EINVAL, "need at least one sample");
+  if (!ws) return set_err(QTN_EINVAL, "workspace is NULL");
+  if (bytes < mlp_buffers(ws, n).bytes) return set_err(QTN_ENOMEM, "cost-model workspace too small");
+  return QTN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int qtn_costmodel_create(const float *params, qtn_costmodel **out) {
+  if (!params || !out) return set_err(QTN_EINVAL, "NULL argument");
+  try {
+    auto *cm = new qtn_costmodel();
+    cm->params.assign(params, params + kMlpParams);
+    cm->m1.assign(kMlpParams, 0.0f);
+    cm->m2.assign(kMlpParams, 0.0f);
+    for (int k = 0; k < kMlpIn; k++) {
+      cm->mean[k] = 0.0f;
+      cm->inv_std[k] = 1.0f;
+    }
+    *out = cm;
+    return QTN_OK;
+  } catch (const std::bad_alloc &) {
+    return set_err(QTN_ENOMEM, "host allocation failed");
+  }
+}
+
+int qtn_costmodel_params(const qtn_costmodel *cm, float *params_out) {
+  if (!cm || !params_out) return set_err(QTN_EINVAL, "NULL argument");
+  std::copy(cm->params.begin(), cm->params.end(), params_out);
+  return QTN_OK;
+}
+
+int qtn_costmodel_normalization(const qtn_costmodel *cm, float *mean_out, float *inv_std_out) {
+  if (!cm || !mean_out || !inv_std_out) return set_err(QTN_EINVAL, "NULL argument");
+  std::copy(cm->mean, cm->mean + kMlpIn, mean_out);
+  std::copy(cm->inv_std, cm->inv_std + kMlpIn, inv_std_out);
+  return QTN_OK;
+}
+
+int qtn_costmodel_workspace(int64_t n, size_t *bytes_out) {
+  if (n < 1 || !bytes_out) return set_err(QTN_EINVAL, "bad arguments");
+  *bytes_out = mlp_buffers(nullptr, n).bytes;
+  return QTN_OK;
+}
+
+int qtn_costmodel_train(qtn_costmodel *cm, const float *x, const double *ms, int64_t n,
+                        int32_t epochs, float lr, void *d_ws, size_t bytes, void *hip_stream,
+                        float *loss_history) {
+  try {
+    if (!cm || !x || !ms || epochs < 1 || !(lr > 0)) return set_err(QTN_EINVAL, "bad arguments");
+    int rc = mlp_check_ws(n, d_ws, bytes);
+    if (rc) return rc;
+    if (!cm->norm_set) {
+      for (int k = 0; k < kMlpIn; k++) {
+        double s = 0, s2 = 0;
+        for (int64_t i = 0; i < n; i++) {
+          s += x[i * kMlpIn + k];
+          s2 += (double)x[i * kMlpIn + k] * x[i * kMlpIn + k];
+        }
+        const double mu = s / n, var = std::max(0.0, s2 / n - mu * mu);
+        cm->mean[k] = (float)mu;
+        cm->inv_std[k] = (float)(1.0 / std::max(1e-3, std::sqrt(var)));
+      }
+      cm->norm_set = true;
+    }
+    std::vector<float> t(n * kMlpOut), m(n * kMlpOut), stage;
+    for (int64_t q = 0; q < n * kMlpOut; q++) {
+      m[q] = ms[q] > 0 ? 1.0f : 0.0f;
+      t[q] = ms[q] > 0 ? (float)std::log(ms[q]) : 0.0f;
+    }
+    hipStream_t s = (hipStream_t)hip_stream;
+    const MlpBuffers b = mlp_buffers(d_ws, n);
+    if ((rc = mlp_upload_inputs(cm, x, n, b, true, s, stage))) return rc;
+    QTN_HIP(hipMemcpyAsync(b.t, t.data(), sizeof(float) * n * kMlpOut, hipMemcpyHostToDevice, s));
+    QTN_HIP(hipMemcpyAsync(b.m, m.data(), sizeof(float) * n * kMlpOut, hipMemcpyHostToDevice, s));
+    QTN_HIP(hipMemcpyAsync(b.m1, cm->m1.data(), sizeof(float) * kMlpParams, hipMemcpyHostToDevice, s));
+    QTN_HIP(hipMemcpyAsync(b.m2, cm->m2.data(), sizeof(float) * kMlpParams, hipMemcpyHostToDevice, s));
+    float *hist = nullptr;
+    QTN_HIP(hipHostMalloc((void **)&hist, sizeof(float) * epochs, hipHostMallocDefault));
+    int step = cm->step;
+    for (int e = 0; e < epochs; e++) {
+      hipError_t he = mlp_loss_grad(b, (int)n, s);
+      if (he == hipSuccess) he = hipMemcpyAsync(hist + e, b.loss, sizeof(float), hipMemcpyDeviceToHost, s);
+      if (he == hipSuccess) he = mlp_adam(b, ++step, lr, s);
+      if (he != hipSuccess) {
+        (void)hipHostFree(hist);
+        return set_err(QTN_EDEVICE, std::string("cost-model training: ") + hipGetErrorString(he));
+      }
+    }
+    std::vector<float> p(kMlpParams), a(kMlpParams), q2(kMlpParams);
+    hipError_t he = hipMemcpyAsync(p.data(), b.params, sizeof(float) * kMlpParams, hipMemcpyDeviceToHost, s);
+    if (he == hipSuccess) he = hipMemcpyAsync(a.data(), b.m1, sizeof(float) * kMlpParams, hipMemcpyDeviceToHost, s);
+    if (he == hipSuccess) he = hipMemcpyAsync(q2.data(), b.m2, sizeof(float) * kMlpParams, hipMemcpyDeviceToHost, s);
+    if (he == hipSuccess) he = hipStreamSynchronize(s);
+    if (he != hipSuccess) {
+      (void)hipHostFree(hist);
+      return set_err(QTN_EDEVICE, std::string("cost-model training: ") + hipGetErrorString(he));
+    }
+    if (loss_history) std::copy(hist, hist + epochs, loss_history);
+    (void)hipHostFree(hist);
+    cm->params.swap(p);
+    cm->m1.swap(a);
+    cm->m2.swap(q2);
+    cm->step = step;
+    return QTN_OK;
+  } catch (const std::bad_alloc &) {
+    return set_err(QTN_ENOMEM, "host allocation failed");
+  }
+}
+
+int qtn_costmodel_predict(const qtn_costmodel *cm, const float *x, int64_t n, void *d_ws,
+                          size_t bytes, void *hip_stream, float *y_out) {
+  try {
+    if (!cm || !x || !y_out) return set_err(QTN_EINVAL, "NULL argument");
+    int rc = mlp_check_ws(n, d_ws, bytes);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)hip_stream;
+    const MlpBuffers b = mlp_buffers(d_ws, n);
+    std::vector<float> stage, y(n * kMlpOut);
+    if ((rc = mlp_upload_inputs(cm, x, n, b, true, s, stage))) return rc;
+    QTN_HIP(mlp_forward(b, (int)n, s));
+    QTN_HIP(hipMemcpyAsync(y.data(), b.y, sizeof(float) * n * kMlpOut, hipMemcpyDeviceToHost, s));
+    QTN_HIP(hipStreamSynchronize(s));
+    std::copy(y.begin(), y.end(), y_out);
+    return QTN_OK;
+  } catch (const std::bad_alloc &) {
+    return set_err(QTN_ENOMEM, "host allocation failed");
+  }
+}
+
+int qtn_costmodel_grad(const qtn_costmodel *cm, const float *x, const float *t, const float *m,
+                       int64_t n, void *d_ws, size_t bytes, void *hip_stream, float *loss_out,
+                       float *grad_out) {
+  try {
+    if (!cm || !x || !t || !m || !loss_out || !grad_out) return set_err(QTN_EINVAL, "NULL argument");
+    int rc = mlp_check_ws(n, d_ws, bytes);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)hip_stream;
+    const MlpBuffers b = mlp_buffers(d_ws, n);
+    std::vector<float> stage, g(kMlpParams);
+    if ((rc = mlp_upload_inputs(cm, x, n, b, false, s, stage))) return rc;
+    QTN_HIP(hipMemcpyAsync(b.t, t, sizeof(float) * n * kMlpOut, hipMemcpyHostToDevice, s));
+    QTN_HIP(hipMemcpyAsync(b.m, m, sizeof(float) * n * kMlpOut, hipMemcpyHostToDevice, s));
+    QTN_HIP(mlp_loss_grad(b, (int)n, s));
+    float loss = 0;
+    QTN_HIP(hipMemcpyAsync(g.data(), b.grad, sizeof(float) * kMlpParams, hipMemcpyDeviceToHost, s));
+    QTN_HIP(hipMemcpyAsync(&loss, b.loss, sizeof(float), hipMemcpyDeviceToHost, s));
+    QTN_HIP(hipStreamSynchronize(s));
+    *loss_out = loss;
+    std::copy(g.begin(), g.end(), grad_out);
+    return QTN_OK;
+  } catch (const std::bad_alloc &) {
+    return set_err(QTN_ENOMEM, "host allocation failed");
+  }
+}
+
+int qtn_costmodel_adam_step(qtn_costmodel *cm, const float *grad, float lr, void *d_ws,
+                            size_t bytes, void *hip_stream) {
+  try {
+    if (!cm || !grad || !(lr > 0)) return set_err(QTN_EINVAL, "bad arguments");
+    int rc = mlp_check_ws(1, d_ws, bytes);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)hip_stream;
+    const MlpBuffers b = mlp_buffers(d_ws, 1);
+    QTN_HIP(hipMemcpyAsync(b.params, cm->params.data(), sizeof(float) * kMlpParams, hipMemcpyHostToDevice, s));
+    QTN_HIP(hipMemcpyAsync(b.grad, grad, sizeof(float) * kMlpParams, hipMemcpyHostToDevice, s));
+    QTN_HIP(hipMemcpyAsync(b.m1, cm->m1.data(), sizeof(float) * kMlpParams, hipMemcpyHostToDevice, s));
+    QTN_HIP(hipMemcpyAsync(b.m2, cm->m2.data(), sizeof(float) * kMlpParams, hipMemcpyHostToDevice, s));
+    QTN_HIP(mlp_adam(b, cm->step + 1, lr, s));
+    std::vector<float> p(kMlpParams), a(kMlpParams), q2(kMlpParams);
+    QTN_HIP(hipMemcpyAsync(p.data(), b.params, sizeof(float) * kMlpParams, hipMemcpyDeviceToHost, s));
+    QTN_HIP(hipMemcpyAsync(a.data(), b.m1, sizeof(float) * kMlpParams, hipMemcpyDeviceToHost, s));
+    QTN_HIP(hipMemcpyAsync(q2.data(), b.m2, sizeof(float) * kMlpParams, hipMemcpyDeviceToHost, s));
+    QTN_HIP(hipStreamSynchronize(s));
+    cm->params.swap(p);
+    cm->m1.swap(a);
+    cm->m2.swap(q2);
+    cm->step++;
+    return QTN_OK;
+  } catch (const std::bad_alloc &) {
+    return set_err(QTN_ENOMEM, "host allocation failed");
+  }
+}
+
+int qtn_apply_costmodel(qtn_network *net, const qtn_costmodel *cm, void *d_ws, size_t bytes,
+                        void *hip_stream, int32_t *counts_out) {
+  try {
+    if (!net || !cm) return set_err(QTN_EINVAL, "NULL argument");
+    if (!net->planned) return set_err(QTN_ESTATE, "qtn_plan has not been called");
+    std::vector<float> feats;
+    std::vector<Group *> gs;
+    for (ConePlan &pl : net->plans)
+      for (Group &G : pl.groups) {
+        float f[kNumFeatures];
+        group_features(G, pl, net->precision, f);
+        feats.insert(feats.end(), f, f + kNumFeatures);
+        gs.push_back(&G);
+      }
+    const int64_t n = (int64_t)gs.size();
+    std::vector<float> y(n * kMlpOut);
+    int rc = qtn_costmodel_predict(cm, feats.data(), n, d_ws, bytes, hip_stream, y.data());
+    if (rc) return rc;
+    int32_t counts[3] = {0, 0, 0};
+    for (int64_t i = 0; i < n; i++) {
+      Group &G = *gs[i];
+      const float *p = &y[i * kMlpOut];
+      // inside a workgroup only where that was ever measured (width <= 16)
+      int best = p[QTN_VAR_STREAM] <= p[QTN_VAR_GENERIC] ? QTN_VAR_STREAM : QTN_VAR_GENERIC;
+      if (G.w <= 16 && p[QTN_VAR_BLOCK] < p[best]) best = QTN_VAR_BLOCK;
+      counts[best]++;
+      G.pick_place = best == QTN_VAR_BLOCK ? 0 : 1;
+      if (best == QTN_VAR_BLOCK) {
+        G.pick_variant = -1;
+        G.pick_rls = -1;
+      } else {
+        G.pick_variant = best == QTN_VAR_STREAM ? 2 : 1;
+        G.pick_rls = 2;
+      }
+    }
+    qtn_network *one[1] = {net};
+    auto ex = std::make_unique<Exec>();
+    if ((rc = build_schedule(one, 1, &ex->sched))) return rc;
+    ex->persistent = net->exec->persistent;
+    ex->lead_per_cone = net->exec->lead_per_cone;
+    ex->spin_limit = net->exec->spin_limit;
+    drop_batches_with(net);
+    net->exec = std::move(ex);
+    net->version++;
+    if (counts_out) std::copy(counts, counts + 3, counts_out);
+    return QTN_OK;
+  } catch (const std::bad_alloc &) {
+    return set_err(QTN_ENOMEM, "host allocation failed");
+  }
+}
+
+void qtn_costmodel_free(qtn_costmodel *cm) { delete cm; }
 
 void qtn_network_free(qtn_network *net) {
   if (!net) return;

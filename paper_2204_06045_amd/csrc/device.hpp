@@ -23,19 +23,19 @@ enum OpClass : uint8_t {
 };
 
 struct DevOp {          // 64 bytes
-  int64_t off;          // element offset of the operand from the data base
+  int64_t off;          // byte offset of the operand from the data base
   uint32_t mask;        // union bits the operand carries
   int32_t stab;         // first entry of its serial-offset table (streaming)
   uint8_t level;        // multiplied in after `level` indices are summed
   uint8_t nruns;        // contiguous runs of `mask`
   uint8_t cls;          // OpClass (streaming)
-  uint8_t pad;
+  uint8_t dt;           // storage: 0 complex128, 1 complex64
   uint16_t run[kOpRuns];  // src | len << 5 | dst << 11 : pext by runs
   uint8_t pad2[12];
 };
 
 struct DevGroup {       // 48 bytes
-  int64_t out_off;      // element offset of the output (or scalar slot)
+  int64_t out_off;      // byte offset of the output (or scalar slot)
   int32_t op_begin;     // first DevOp of the group
   uint32_t n_units;     // wave units
   uint8_t w, L, n_ops, variant;   // variant: kVarGeneric / kVarStream
@@ -46,7 +46,9 @@ struct DevGroup {       // 48 bytes
                         // streaming: level_end[0] = uniform-class count; the
                         // n_serial - level_end[0] serial-class ops follow
   uint8_t n_ubits;      // wave-unit bits (their union positions: uperm)
-  uint8_t pad2[7];
+  uint8_t prec;         // arithmetic and output storage: 0 complex128, 1 complex64
+  uint8_t cvt;          // 1: some operand is stored in the other precision
+  uint8_t pad2[5];
 };
 
 static_assert(sizeof(DevOp) == 64, "DevOp layout");
@@ -60,7 +62,8 @@ constexpr int kGenRegBits = 2;
 constexpr int kStreamMaxOps = 96;
 constexpr int kStreamMaxSerial = 6;
 
-// Gate table layout (elements): per layer l, 8 blocks of 4 at 32*l:
+// Gate table layout (elements; one table per precision in use): per layer l,
+// 8 blocks of 4 at 32*l:
 // P, P^T, Pc, Pc^T, R, R^T, Rc, Rc^T (row-major over the gate's own axes,
 // ^T = the other axis as bit 0); then H (2) at 32*p and Z (2) at 32*p + 2.
 inline int64_t gate_table_elems(int p) { return 32LL * p + 4; }

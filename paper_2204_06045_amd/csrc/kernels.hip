@@ -63,6 +63,31 @@ template <> __device__ __forceinline__ float2 make_c<float2>(double re, double i
 __device__ __forceinline__ double2 to_d(double2 v) { return v; }
 __device__ __forceinline__ double2 to_d(float2 v) { return make_double2(v.x, v.y); }
 
+// Element storage: dt 0 = complex128 (double2), 1 = complex64 (float2).  With
+// CVT false every operand of the group is stored as T and dt is not read.
+template <class T, bool CVT> __device__ __forceinline__ uint32_t esize(int dt) {
+  return CVT ? (dt ? 8u : 16u) : (uint32_t)sizeof(T);
+}
+
+// Element `idx` of an operand stored as dt at p, converted to T.
+template <class T, bool CVT> __device__ __forceinline__ T ld_elem(const char *p, uint64_t idx, int dt);
+template <> __device__ __forceinline__ double2 ld_elem<double2, false>(const char *p, uint64_t idx, int) {
+  return *(const double2 *)(p + idx * 16u);
+}
+template <> __device__ __forceinline__ float2 ld_elem<float2, false>(const char *p, uint64_t idx, int) {
+  return *(const float2 *)(p + idx * 8u);
+}
+template <> __device__ __forceinline__ double2 ld_elem<double2, true>(const char *p, uint64_t idx, int dt) {
+  if (dt == 0) return *(const double2 *)(p + idx * 16u);
+  const float2 v = *(const float2 *)(p + idx * 8u);
+  return make_double2(v.x, v.y);
+}
+template <> __device__ __forceinline__ float2 ld_elem<float2, true>(const char *p, uint64_t idx, int dt) {
+  if (dt == 1) return *(const float2 *)(p + idx * 8u);
+  const double2 v = *(const double2 *)(p + idx * 16u);
+  return make_float2((float)v.x, (float)v.y);
+}
+
 // pext(x, mask) from the operand's packed runs (wave-uniform loop bounds).
 __device__ __forceinline__ uint32_t pext_runs(uint32_t x, const DevOp &o) {
   uint32_t r = 0;
@@ -98,9 +123,9 @@ __device__ __forceinline__ uint32_t pext_reg(uint32_t x, uint32_t m) {
   return r;
 }
 
-template <class T>
+template <class T, bool CVT>
 __device__ __forceinline__ void generic_unit(const DevGroup &G, const DevOp *__restrict__ gops,
-                                             const uint8_t *__restrict__ ubit, T *__restrict__ data,
+                                             const uint8_t *__restrict__ ubit, char *__restrict__ data,
                                              uint32_t u, int lane) {
   constexpr int RG = kGenRegBits, NR = 1 << RG;
   const uint32_t I0 = unit_bits(u, ubit, G.n_ubits) | ((uint32_t)lane << RG);
@@ -109,17 +134,18 @@ __device__ __forceinline__ void generic_unit(const DevGroup &G, const DevOp *__r
   {
     const DevOp &o = gops[0];
     const uint32_t base = pext_runs(I0, o);
-    const T *src = data + o.off;
+    const char *src = data + o.off;
 #pragma unroll
-    for (int r = 0; r < NR; r++) v[r] = src[base + pext_reg(r, o.mask)];
+    for (int r = 0; r < NR; r++) v[r] = ld_elem<T, CVT>(src, base + pext_reg(r, o.mask), o.dt);
   }
   int k = 1;
   for (; k < G.level_end[0]; k++) {
     const DevOp &o = gops[k];
     const uint32_t base = pext_runs(I0, o);
-    const T *src = data + o.off;
+    const char *src = data + o.off;
 #pragma unroll
-    for (int r = 0; r < NR; r++) v[r] = cmul(v[r], src[base + pext_reg(r, o.mask)]);
+    for (int r = 0; r < NR; r++)
+      v[r] = cmul(v[r], ld_elem<T, CVT>(src, base + pext_reg(r, o.mask), o.dt));
   }
 #pragma unroll
   for (int s = 0; s < RG; s++) {
@@ -130,15 +156,15 @@ __device__ __forceinline__ void generic_unit(const DevGroup &G, const DevOp *__r
         for (; k < G.level_end[s + 1]; k++) {
           const DevOp &o = gops[k];
           const uint32_t base = pext_runs(I0, o);
-          const T *src = data + o.off;
+          const char *src = data + o.off;
 #pragma unroll
           for (int r = 0; r < (NR >> (s + 1)); r++)
-            v[r] = cmul(v[r], src[base + pext_reg((uint32_t)r << (s + 1), o.mask)]);
+            v[r] = cmul(v[r], ld_elem<T, CVT>(src, base + pext_reg((uint32_t)r << (s + 1), o.mask), o.dt));
         }
       }
     }
   }
-  T *out = data + G.out_off;
+  T *out = (T *)(data + G.out_off);
   const uint32_t nout = 1u << (G.w - L);
   if (L <= RG) {
     const uint32_t ob = I0 >> L;
@@ -153,7 +179,7 @@ __device__ __forceinline__ void generic_unit(const DevGroup &G, const DevOp *__r
     if (s + 1 < L) {
       for (; k < G.level_end[s + 1]; k++) {
         const DevOp &o = gops[k];
-        acc = cmul(acc, data[o.off + pext_runs(I0, o)]);
+        acc = cmul(acc, ld_elem<T, CVT>(data + o.off, pext_runs(I0, o), o.dt));
       }
     }
   }
@@ -214,6 +240,19 @@ template <> __device__ __forceinline__ float2 gload<float2>(const char *base, ui
   return make_float2(v.x, v.y);
 }
 
+// The same with the operand stored as dt (CVT) or as T, converted to T.
+template <class T, bool CVT>
+__device__ __forceinline__ T gload_dt(const char *base, uint32_t off, int dt) {
+  if (!CVT) return gload<T>(base, off);
+  if (dt == (sizeof(T) == 16 ? 0 : 1)) return gload<T>(base, off);
+  if (sizeof(T) == 16) {
+    const float2 v = gload<float2>(base, off);
+    return make_c<T>(v.x, v.y);
+  }
+  const double2 v = gload<double2>(base, off);
+  return make_c<T>(v.x, v.y);
+}
+
 // One wave unit of the streaming mapping.  With u fixed, every point's value
 // is the product of
 //   unit-class operands      (no serial bit)        -> c0, c1 once per unit
@@ -226,13 +265,12 @@ template <> __device__ __forceinline__ float2 gload<float2>(const char *base, ui
 // sum once instead of each point.  Serial offsets of the unrolled operands sit
 // one entry per lane and are read with readlane, so a step's loads issue
 // back to back from scalar bases.
-template <class T>
+template <class T, bool CVT>
 __device__ __forceinline__ void stream_unit(const DevGroup &G, const DevOp *__restrict__ gops,
                                             const int32_t *__restrict__ stab,
-                                            const uint8_t *__restrict__ ubit, T *__restrict__ data,
+                                            const uint8_t *__restrict__ ubit, char *__restrict__ data,
                                             const uint32_t *s_lane, uint32_t u, int lane) {
-  constexpr uint32_t ES = sizeof(T);
-  const int L = G.L, rls = G.rls, sl = G.sl, lk = G.lk;
+  const int L = G.L, rls = G.rls, sl = G.sl;
   const uint32_t Iu = unit_bits(u, ubit, G.n_ubits);
   const uint32_t nsteps = 1u << sl;
   const bool lane_step = (uint32_t)lane < nsteps;
@@ -240,10 +278,11 @@ __device__ __forceinline__ void stream_unit(const DevGroup &G, const DevOp *__re
   T c0 = one, c1 = one;
   for (int k = 0; k < G.n_unit; k++) {
     const DevOp &o = gops[k];
-    const char *p = uniform_ptr(data + o.off + pext_runs(Iu, o));
+    const uint32_t ES = esize<T, CVT>(o.dt);
+    const char *p = uniform_ptr(data + o.off + (uint64_t)pext_runs(Iu, o) * ES);
     const uint32_t lb = s_lane[k * 64 + lane] * ES;
-    const T x0 = gload<T>(p, lb);
-    const T x1 = gload<T>(p, lb + ((o.mask & 1u) ? ES : 0u));
+    const T x0 = gload_dt<T, CVT>(p, lb, o.dt);
+    const T x1 = gload_dt<T, CVT>(p, lb + ((o.mask & 1u) ? ES : 0u), o.dt);
     c0 = cmul(c0, x0);
     c1 = cmul(c1, x1);
   }
@@ -252,9 +291,10 @@ __device__ __forceinline__ void stream_unit(const DevGroup &G, const DevOp *__re
   T U = one;
   for (int k = ku; k < ks; k++) {
     const DevOp &o = gops[k];
-    const char *p = uniform_ptr(data + o.off + pext_runs(Iu, o));
+    const uint32_t ES = esize<T, CVT>(o.dt);
+    const char *p = uniform_ptr(data + o.off + (uint64_t)pext_runs(Iu, o) * ES);
     const uint32_t off = lane_step ? (uint32_t)stab[o.stab + lane] * ES : 0u;
-    U = cmul(U, gload<T>(p, off));
+    U = cmul(U, gload_dt<T, CVT>(p, off, o.dt));
   }
   // unrolled step-class operands: scalar base, per-lane byte offset, serial
   // offsets one per lane
@@ -262,6 +302,7 @@ __device__ __forceinline__ void stream_unit(const DevGroup &G, const DevOp *__re
   const char *pb[kStepOps];
   uint32_t lb[kStepOps], tb[kStepOps], h0b[kStepOps];
   bool h0[kStepOps];
+  int dt[kStepOps];
 #pragma unroll
   for (int i = 0; i < kStepOps; i++) {
     pb[i] = uniform_ptr(data);
@@ -269,9 +310,12 @@ __device__ __forceinline__ void stream_unit(const DevGroup &G, const DevOp *__re
     tb[i] = 0;
     h0[i] = false;
     h0b[i] = 0;
+    dt[i] = 0;
     if (i < n_step) {
       const DevOp &o = gops[kb + i];
-      pb[i] = uniform_ptr(data + o.off + pext_runs(Iu, o));
+      const uint32_t ES = esize<T, CVT>(o.dt);
+      dt[i] = o.dt;
+      pb[i] = uniform_ptr(data + o.off + (uint64_t)pext_runs(Iu, o) * ES);
       lb[i] = s_lane[(kb + i) * 64 + lane] * ES;
       tb[i] = lane_step ? (uint32_t)stab[o.stab + lane] * ES : 0u;
       h0[i] = (o.mask & 1u) != 0;
@@ -288,8 +332,8 @@ __device__ __forceinline__ void stream_unit(const DevGroup &G, const DevOp *__re
       e1[i] = one;
       if (i < n_step) {
         const char *p = pb[i] + __builtin_amdgcn_readlane(tb[i], s);
-        e0[i] = gload<T>(p, lb[i]);
-        e1[i] = gload<T>(p, lb[i] + h0b[i]);
+        e0[i] = gload_dt<T, CVT>(p, lb[i], dt[i]);
+        e1[i] = gload_dt<T, CVT>(p, lb[i] + h0b[i], dt[i]);
       }
     }
     T v0 = c0, v1 = c1;
@@ -303,10 +347,12 @@ __device__ __forceinline__ void stream_unit(const DevGroup &G, const DevOp *__re
     const int k_extra = kb + kStepOps, k_h0_end = kb + G.n_step0;
     for (int k = k_extra; k < k_h0_end; k++) {
       const DevOp &o = gops[k];
-      const char *p = uniform_ptr(data + o.off + pext_runs(Iu, o) + stab[o.stab + s]);
+      const uint32_t ES = esize<T, CVT>(o.dt);
+      const char *p = uniform_ptr(data + o.off +
+                                  ((uint64_t)pext_runs(Iu, o) + (uint32_t)stab[o.stab + s]) * ES);
       const uint32_t l = s_lane[k * 64 + lane] * ES;
-      v0 = cmul(v0, gload<T>(p, l));
-      v1 = cmul(v1, gload<T>(p, l + ES));
+      v0 = cmul(v0, gload_dt<T, CVT>(p, l, o.dt));
+      v1 = cmul(v1, gload_dt<T, CVT>(p, l + ES, o.dt));
     }
     T x = cadd(v0, v1);  // bit 0 summed in registers
 #pragma unroll
@@ -314,14 +360,18 @@ __device__ __forceinline__ void stream_unit(const DevGroup &G, const DevOp *__re
       if (i < n_step && !h0[i]) x = cmul(x, e0[i]);
     for (int k = max(k_extra, k_h0_end); k < kb + n_step; k++) {
       const DevOp &o = gops[k];
-      const char *p = uniform_ptr(data + o.off + pext_runs(Iu, o) + stab[o.stab + s]);
-      x = cmul(x, gload<T>(p, s_lane[k * 64 + lane] * ES));
+      const uint32_t ES = esize<T, CVT>(o.dt);
+      const char *p = uniform_ptr(data + o.off +
+                                  ((uint64_t)pext_runs(Iu, o) + (uint32_t)stab[o.stab + s]) * ES);
+      x = cmul(x, gload_dt<T, CVT>(p, s_lane[k * 64 + lane] * ES, o.dt));
     }
     if (sl > 0) x = cmul(x, readlane2(U, s));
     for (int k = ks; k < ke; k++) {
       const DevOp &o = gops[k];
-      const char *p = uniform_ptr(data + o.off + pext_runs(Iu, o) + stab[o.stab + s]);
-      x = cmul(x, gload<T>(p, s_lane[k * 64 + lane] * ES));
+      const uint32_t ES = esize<T, CVT>(o.dt);
+      const char *p = uniform_ptr(data + o.off +
+                                  ((uint64_t)pext_runs(Iu, o) + (uint32_t)stab[o.stab + s]) * ES);
+      x = cmul(x, gload_dt<T, CVT>(p, s_lane[k * 64 + lane] * ES, o.dt));
     }
     acc = cadd(acc, x);
   }
@@ -329,14 +379,44 @@ __device__ __forceinline__ void stream_unit(const DevGroup &G, const DevOp *__re
   for (int b = 0; b < rls; b++) acc = cadd(acc, shfl_xor2(acc, 1 << b));
   if ((lane & ((1 << rls) - 1)) == 0) {
     const uint32_t o = (Iu >> L) | ((uint32_t)lane >> rls);
-    if (o < (1u << (G.w - L))) data[G.out_off + o] = acc;
+    if (o < (1u << (G.w - L))) ((T *)(data + G.out_off))[o] = acc;
   }
+}
+
+// One group's wave units [u0, u1) over the block's waves, in the group's
+// own precision.
+__device__ __forceinline__ void run_group(const DevGroup &G, int g, const DevOp *__restrict__ ops,
+                                          const int32_t *__restrict__ stab,
+                                          const uint8_t *__restrict__ uperm, char *__restrict__ data,
+                                          uint32_t *s_lane, uint32_t u0, uint32_t u1) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  const DevOp *gops = ops + G.op_begin;
+  const uint8_t *ub = uperm + 32 * g;
+#define QTN_UNITS(F, ...)                                                          \
+  do {                                                                             \
+    if (G.prec == 0 && !G.cvt)                                                     \
+      for (uint32_t u = u0 + wave; u < u1; u += nw) F<double2, false>(__VA_ARGS__); \
+    else if (G.prec == 0)                                                          \
+      for (uint32_t u = u0 + wave; u < u1; u += nw) F<double2, true>(__VA_ARGS__);  \
+    else if (!G.cvt)                                                               \
+      for (uint32_t u = u0 + wave; u < u1; u += nw) F<float2, false>(__VA_ARGS__);  \
+    else                                                                           \
+      for (uint32_t u = u0 + wave; u < u1; u += nw) F<float2, true>(__VA_ARGS__);   \
+  } while (0)
+  if (G.variant == kVarStream) {
+    stream_setup(G, gops, s_lane);
+    __syncthreads();
+    QTN_UNITS(stream_unit, G, gops, stab, ub, data, s_lane, u, lane);
+  } else {
+    QTN_UNITS(generic_unit, G, gops, ub, data, u, lane);
+  }
+#undef QTN_UNITS
+  __syncthreads();
 }
 
 // ------------------------------------------------------------------ kernels
 
-template <class T>
-__global__ __launch_bounds__(kBlock) void k_block_groups(T *__restrict__ data,
+__global__ __launch_bounds__(kBlock) void k_block_groups(char *__restrict__ data,
                                                          const DevGroup *__restrict__ groups,
                                                          const DevOp *__restrict__ ops,
                                                          const int32_t *__restrict__ stab,
@@ -345,21 +425,9 @@ __global__ __launch_bounds__(kBlock) void k_block_groups(T *__restrict__ data,
                                                          int range_base) {
   __shared__ uint32_t s_lane[kStreamMaxOps * 64];
   const int2 rg = ranges[range_base + blockIdx.x];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int nw = blockDim.x >> 6;
   for (int g = rg.x; g < rg.y; g++) {
     const DevGroup &G = groups[g];
-    const DevOp *gops = ops + G.op_begin;
-    if (G.variant == kVarStream) {
-      stream_setup(G, gops, s_lane);
-      __syncthreads();
-      for (uint32_t u = wave; u < G.n_units; u += nw)
-        stream_unit<T>(G, gops, stab, uperm + 32 * g, data, s_lane, u, lane);
-    } else {
-      for (uint32_t u = wave; u < G.n_units; u += nw)
-        generic_unit<T>(G, gops, uperm + 32 * g, data, u, lane);
-    }
-    __syncthreads();  // this group's output is read by the next ones
+    run_group(G, g, ops, stab, uperm, data, s_lane, 0u, G.n_units);
   }
 }
 
@@ -373,8 +441,8 @@ __device__ __forceinline__ void wide_range(uint32_t n_units, uint32_t *ub, uint3
   *ue = min(n_units, *ub + per);
 }
 
-template <class T>
-__global__ __launch_bounds__(kBlock) void k_wide_stream(T *__restrict__ data,
+template <class T, bool CVT>
+__global__ __launch_bounds__(kBlock) void k_wide_stream(char *__restrict__ data,
                                                         const DevGroup *__restrict__ groups,
                                                         const DevOp *__restrict__ ops,
                                                         const int32_t *__restrict__ stab,
@@ -390,11 +458,11 @@ __global__ __launch_bounds__(kBlock) void k_wide_stream(T *__restrict__ data,
   stream_setup(G, gops, s_lane);
   __syncthreads();
   for (uint32_t u = ub + w0; u < ue; u += nw)
-    stream_unit<T>(G, gops, stab, uperm + 32 * gid, data, s_lane, u, lane);
+    stream_unit<T, CVT>(G, gops, stab, uperm + 32 * gid, data, s_lane, u, lane);
 }
 
-template <class T>
-__global__ __launch_bounds__(kBlock) void k_wide_generic(T *__restrict__ data,
+template <class T, bool CVT>
+__global__ __launch_bounds__(kBlock) void k_wide_generic(char *__restrict__ data,
                                                          const DevGroup *__restrict__ groups,
                                                          const DevOp *__restrict__ ops,
                                                          const int32_t *__restrict__ stab,
@@ -408,37 +476,25 @@ __global__ __launch_bounds__(kBlock) void k_wide_generic(T *__restrict__ data,
   const uint32_t nw = blockDim.x >> 6;
   const uint32_t w0 = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   for (uint32_t u = ub + w0; u < ue; u += nw)
-    generic_unit<T>(G, gops, uperm + 32 * gid, data, u, lane);
+    generic_unit<T, CVT>(G, gops, uperm + 32 * gid, data, u, lane);
 }
 
 // ----------------------------------------------------- persistent executor
 
 // Runs one work item with the whole block: a segment of small groups
 // [it.x, it.y) in order, or units [it.z, it.w) of wide group it.x (it.y < 0).
-template <class T>
-__device__ __forceinline__ void run_item(int4 it, T *__restrict__ data,
+__device__ __forceinline__ void run_item(int4 it, char *__restrict__ data,
                                          const DevGroup *__restrict__ groups,
                                          const DevOp *__restrict__ ops,
                                          const int32_t *__restrict__ stab,
                                          const uint8_t *__restrict__ uperm, uint32_t *s_lane) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
   const bool chunk = it.y < 0;
   const int g_end = chunk ? it.x + 1 : it.y;
   for (int g = it.x; g < g_end; g++) {
     const DevGroup &G = groups[g];
-    const DevOp *gops = ops + G.op_begin;
     const uint32_t u0 = chunk ? (uint32_t)it.z : 0u;
     const uint32_t u1 = chunk ? min((uint32_t)it.w, G.n_units) : G.n_units;
-    if (G.variant == kVarStream) {
-      stream_setup(G, gops, s_lane);
-      __syncthreads();
-      for (uint32_t u = u0 + wave; u < u1; u += nw)
-        stream_unit<T>(G, gops, stab, uperm + 32 * g, data, s_lane, u, lane);
-    } else {
-      for (uint32_t u = u0 + wave; u < u1; u += nw)
-        generic_unit<T>(G, gops, uperm + 32 * g, data, u, lane);
-    }
-    __syncthreads();
+    run_group(G, g, ops, stab, uperm, data, s_lane, u0, u1);
   }
 }
 
@@ -482,8 +538,7 @@ __device__ __forceinline__ bool grid_barrier(uint32_t *ctl, uint32_t spin_limit)
 // items with an atomic counter; a grid barrier separates steps.  ctl:
 // [barrier count, barrier generation, error flag, pad, per-step counters...],
 // cleared by k_reset before the launch.
-template <class T>
-__global__ __launch_bounds__(kBlock) void k_persistent(T *__restrict__ data,
+__global__ __launch_bounds__(kBlock) void k_persistent(char *__restrict__ data,
                                                        const DevGroup *__restrict__ groups,
                                                        const DevOp *__restrict__ ops,
                                                        const int32_t *__restrict__ stab,
@@ -505,7 +560,7 @@ __global__ __launch_bounds__(kBlock) void k_persistent(T *__restrict__ data,
       const int i = s_item;
       __syncthreads();
       if (i >= e) break;
-      run_item<T>(items[i], data, groups, ops, stab, uperm, s_lane);
+      run_item(items[i], data, groups, ops, stab, uperm, s_lane);
     }
     if (st + 1 < n_steps && !grid_barrier(ctl, spin_limit)) return;
   }
@@ -531,12 +586,8 @@ __device__ void put2x2(T *t, double2 m00, double2 m01, double2 m10, double2 m11)
 }
 
 template <class T>
-__global__ void k_fill(T *__restrict__ data, const double *__restrict__ angles,
-                       const FillDesc *__restrict__ fills) {
-  const FillDesc f = fills[blockIdx.x];
-  T *table = data + f.table_off;
-  const double *gamma = angles + f.angle_off, *beta = gamma + f.p;
-  for (int l = threadIdx.x; l < f.p; l += blockDim.x) {
+__device__ void fill_table(T *table, const double *gamma, const double *beta, int p) {
+  for (int l = threadIdx.x; l < p; l += blockDim.x) {
     double sg, cg, sb, cb;
     sincos(gamma[l], &sg, &cg);
     sincos(beta[l], &sb, &cb);
@@ -552,12 +603,20 @@ __global__ void k_fill(T *__restrict__ data, const double *__restrict__ angles,
   }
   if (threadIdx.x == 0) {
     const double r2 = 0.70710678118654752440;
-    T *t = table + 32 * f.p;
+    T *t = table + 32 * p;
     t[0] = make_c<T>(r2, 0.0);  // H
     t[1] = make_c<T>(r2, 0.0);
     t[2] = make_c<T>(1.0, 0.0);  // Z
     t[3] = make_c<T>(-1.0, 0.0);
   }
+}
+
+__global__ void k_fill(char *__restrict__ data, const double *__restrict__ angles,
+                       const FillDesc *__restrict__ fills) {
+  const FillDesc f = fills[blockIdx.x];
+  const double *gamma = angles + f.angle_off, *beta = gamma + f.p;
+  if (f.table128 >= 0) fill_table<double2>((double2 *)(data + f.table128), gamma, beta, f.p);
+  if (f.table64 >= 0) fill_table<float2>((float2 *)(data + f.table64), gamma, beta, f.p);
 }
 
 template <class T>
@@ -599,89 +658,79 @@ int wide_blocks(uint32_t n_units) {
 
 hipError_t launch_fill(int prec, void *data, const double *angles, const FillDesc *fills,
                        int n_nets, hipStream_t s) {
-  if (prec == kPrecC128)
-    hipLaunchKernelGGL(k_fill<double2>, dim3(n_nets), dim3(64), 0, s, (double2 *)data, angles,
-                       fills);
-  else
-    hipLaunchKernelGGL(k_fill<float2>, dim3(n_nets), dim3(64), 0, s, (float2 *)data, angles,
-                       fills);
+  (void)prec;
+  hipLaunchKernelGGL(k_fill, dim3(n_nets), dim3(64), 0, s, (char *)data, angles, fills);
   return hipGetLastError();
 }
 
 hipError_t launch_block_groups(int prec, void *data, const DevGroup *groups, const DevOp *ops,
                                const int32_t *stab, const uint8_t *uperm, const int2 *ranges,
                                int range_base, int n_blocks, hipStream_t s) {
+  (void)prec;
   if (n_blocks <= 0) return hipSuccess;
-  if (prec == kPrecC128)
-    hipLaunchKernelGGL(k_block_groups<double2>, dim3(n_blocks), dim3(kBlock), 0, s,
-                       (double2 *)data, groups, ops, stab, uperm, ranges, range_base);
-  else
-    hipLaunchKernelGGL(k_block_groups<float2>, dim3(n_blocks), dim3(kBlock), 0, s,
-                       (float2 *)data, groups, ops, stab, uperm, ranges, range_base);
+  hipLaunchKernelGGL(k_block_groups, dim3(n_blocks), dim3(kBlock), 0, s, (char *)data, groups,
+                     ops, stab, uperm, ranges, range_base);
   return hipGetLastError();
 }
 
-hipError_t launch_wide_group(int prec, int variant, void *data, const DevGroup *groups,
+template <class T, bool CVT>
+void launch_wide_t(int variant, int nb, char *d, const DevGroup *groups, const DevOp *ops,
+                   const int32_t *stab, const uint8_t *uperm, int group, hipStream_t s) {
+  if (variant == kVarStream)
+    hipLaunchKernelGGL((k_wide_stream<T, CVT>), dim3(nb), dim3(kBlock), 0, s, d, groups, ops, stab,
+                       uperm, group);
+  else
+    hipLaunchKernelGGL((k_wide_generic<T, CVT>), dim3(nb), dim3(kBlock), 0, s, d, groups, ops,
+                       stab, uperm, group);
+}
+
+hipError_t launch_wide_group(int prec, bool cvt, int variant, void *data, const DevGroup *groups,
                              const DevOp *ops, const int32_t *stab, const uint8_t *uperm,
                              int group, uint32_t n_units, hipStream_t s) {
   const int nb = wide_blocks(n_units);
-  if (variant == kVarStream) {
-    if (prec == kPrecC128)
-      hipLaunchKernelGGL(k_wide_stream<double2>, dim3(nb), dim3(kBlock), 0, s, (double2 *)data,
-                         groups, ops, stab, uperm, group);
-    else
-      hipLaunchKernelGGL(k_wide_stream<float2>, dim3(nb), dim3(kBlock), 0, s, (float2 *)data,
-                         groups, ops, stab, uperm, group);
-  } else {
-    if (prec == kPrecC128)
-      hipLaunchKernelGGL(k_wide_generic<double2>, dim3(nb), dim3(kBlock), 0, s,
-                         (double2 *)data, groups, ops, stab, uperm, group);
-    else
-      hipLaunchKernelGGL(k_wide_generic<float2>, dim3(nb), dim3(kBlock), 0, s, (float2 *)data,
-                         groups, ops, stab, uperm, group);
-  }
+  char *d = (char *)data;
+  if (prec == kPrecC128 && !cvt)
+    launch_wide_t<double2, false>(variant, nb, d, groups, ops, stab, uperm, group, s);
+  else if (prec == kPrecC128)
+    launch_wide_t<double2, true>(variant, nb, d, groups, ops, stab, uperm, group, s);
+  else if (!cvt)
+    launch_wide_t<float2, false>(variant, nb, d, groups, ops, stab, uperm, group, s);
+  else
+    launch_wide_t<float2, true>(variant, nb, d, groups, ops, stab, uperm, group, s);
   return hipGetLastError();
 }
 
 hipError_t launch_persistent(int prec, void *data, const DevGroup *groups, const DevOp *ops,
                              const int32_t *stab, const uint8_t *uperm, const int4 *items,
-                             const int *step_begin,
-                             int n_steps, uint32_t *ctl, int n_ctl, int n_blocks,
-                             uint32_t spin_limit, hipStream_t s) {
+                             const int *step_begin, int n_steps, uint32_t *ctl, int n_ctl,
+                             int n_blocks, uint32_t spin_limit, hipStream_t s) {
+  (void)prec;
   hipLaunchKernelGGL(k_reset, dim3(1), dim3(256), 0, s, ctl, n_ctl);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (n_steps <= 0) return hipSuccess;
-  if (prec == kPrecC128)
-    hipLaunchKernelGGL(k_persistent<double2>, dim3(n_blocks), dim3(kBlock), 0, s,
-                       (double2 *)data, groups, ops, stab, uperm, items, step_begin, n_steps,
-                       ctl, spin_limit);
-  else
-    hipLaunchKernelGGL(k_persistent<float2>, dim3(n_blocks), dim3(kBlock), 0, s,
-                       (float2 *)data, groups, ops, stab, uperm, items, step_begin, n_steps,
-                       ctl, spin_limit);
+  hipLaunchKernelGGL(k_persistent, dim3(n_blocks), dim3(kBlock), 0, s, (char *)data, groups, ops,
+                     stab, uperm, items, step_begin, n_steps, ctl, spin_limit);
   return hipGetLastError();
 }
 
 int persistent_blocks(int prec, int n_cu) {
+  (void)prec;
   int per_cu = 0;
-  hipError_t e = prec == kPrecC128
-                     ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<double2>,
-                                                                    kBlock, 0)
-                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<float2>,
-                                                                    kBlock, 0);
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent, kBlock, 0);
   if (e != hipSuccess || per_cu < 1) return 0;
   return per_cu * n_cu;
 }
 
 hipError_t launch_reduce(int prec, const void *data, int64_t scalar_off, const int *csb,
                          const int *ncb, int n_cones, int n_nets, double *res, hipStream_t s) {
-  if (prec == kPrecC128)
-    hipLaunchKernelGGL(k_reduce<double2>, dim3(1), dim3(256), 0, s,
-                       (const double2 *)data + scalar_off, csb, ncb, n_cones, n_nets, res);
+  const char *sc = (const char *)data + scalar_off;
+  if (prec == kPrecC64)
+    hipLaunchKernelGGL(k_reduce<float2>, dim3(1), dim3(256), 0, s, (const float2 *)sc, csb, ncb,
+                       n_cones, n_nets, res);
   else
-    hipLaunchKernelGGL(k_reduce<float2>, dim3(1), dim3(256), 0, s,
-                       (const float2 *)data + scalar_off, csb, ncb, n_cones, n_nets, res);
+    hipLaunchKernelGGL(k_reduce<double2>, dim3(1), dim3(256), 0, s, (const double2 *)sc, csb, ncb,
+                       n_cones, n_nets, res);
   return hipGetLastError();
 }
 

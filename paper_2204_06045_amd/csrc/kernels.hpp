@@ -9,12 +9,13 @@
 
 namespace qtn {
 
-enum Precision : int { kPrecC128 = 0, kPrecC64 = 1 };
+enum Precision : int { kPrecC128 = 0, kPrecC64 = 1, kPrecMixed = 2 };
 
 // One block per network: fills that network's gate table from its angles.
 struct FillDesc {
   int64_t angle_off;  // doubles from the angle base: gamma[p] then beta[p]
-  int64_t table_off;  // elements from the data base
+  int64_t table128;   // byte offset of the complex128 gate table, or -1
+  int64_t table64;    // byte offset of the complex64 gate table, or -1
   int32_t p, pad;
 };
 
@@ -29,8 +30,9 @@ hipError_t launch_block_groups(int prec, void *data, const DevGroup *groups,
                                const uint8_t *uperm, const int2 *ranges,
                                int range_base, int n_blocks, hipStream_t s);
 
-// One group over the whole grid, with the kernel of its mapping variant.
-hipError_t launch_wide_group(int prec, int variant, void *data,
+// One group over the whole grid, with the kernel of its mapping variant, in
+// precision prec; cvt: some operand is stored in the other precision.
+hipError_t launch_wide_group(int prec, bool cvt, int variant, void *data,
                              const DevGroup *groups, const DevOp *ops,
                              const int32_t *stab, const uint8_t *uperm, int group,
                              uint32_t n_units, hipStream_t s);
@@ -50,6 +52,9 @@ hipError_t launch_persistent(int prec, void *data, const DevGroup *groups,
 // Resident blocks of the persistent kernel on n_cu compute units (0 on error).
 int persistent_blocks(int prec, int n_cu);
 
+// All offsets in descriptors are bytes from the data base `data`.
+// launch_reduce: scalars stored as complex64 when prec is kPrecC64, else as
+// complex128, starting scalar_off bytes into data.
 // Per light cone: product of its scalar slots -> e_jk (FP64); per network:
 // E = |E|/2 - 1/2 sum Re e_jk with Neumaier compensation.
 // res: [n_cones] Re, [n_cones] Im, [n_nets] energies.

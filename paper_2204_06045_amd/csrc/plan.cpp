@@ -271,7 +271,8 @@ void group_features(const Group &G, const ConePlan &pl, int precision, float *f)
     elems += std::ldexp(1.0, r);
     rank_sum += r;
   }
-  const int es = precision == 0 ? 16 : 8;
+  (void)precision;
+  const int es = G.prec == 1 ? 8 : 16;
   double flops = 0;
   for (int l = 0; l < G.L; l++) {
     int factors = (l > 0 ? 1 : 0);
@@ -294,7 +295,7 @@ void group_features(const Group &G, const ConePlan &pl, int precision, float *f)
   f[12] = (float)n_small;
   f[13] = (float)(rank_sum / std::max(1, G.w));
   f[14] = (float)n_inter;
-  f[15] = (float)precision;
+  f[15] = (float)G.prec;
 }
 
 int mask_runs(uint32_t mask, uint8_t *src, uint8_t *len, uint8_t *dst) {
@@ -326,7 +327,7 @@ struct BucketRec {
   int next = -1, prev = -1;  // merge chain links
 };
 
-// First-fit allocator over element offsets.
+// First-fit allocator over byte offsets.
 struct Arena {
   std::vector<std::pair<int64_t, int64_t>> used;  // (offset, size), sorted
   int64_t peak = 0;
@@ -472,6 +473,17 @@ std::string plan_cone(const LightCone &lc, const std::vector<int> &order,
   std::stable_sort(P.groups.begin(), P.groups.end(),
                    [](const Group &a, const Group &b) { return a.last_pos < b.last_pos; });
 
+  // precision per group: in mixed mode wide groups run in complex64, narrow
+  // ones and every final scalar sum-out in complex128
+  for (Group &G : P.groups) {
+    if (opt.precision == 2)
+      G.prec = (G.w >= opt.mixed_width && G.out_tensor >= 0) ? 1 : 0;
+    else
+      G.prec = (int8_t)opt.precision;
+    if (G.out_tensor >= 0) P.tensors[G.out_tensor].prec = G.prec;
+  }
+  auto es = [](int prec) { return prec == 0 ? 16.0 : 8.0; };
+
   // producers, consumers, scalar slots, cost counts
   for (size_t g = 0; g < P.groups.size(); g++) {
     Group &G = P.groups[g];
@@ -479,14 +491,15 @@ std::string plan_cone(const LightCone &lc, const std::vector<int> &order,
       P.tensors[G.out_tensor].producer = (int)g;
     else
       G.scalar_slot = P.n_scalars++;
-    double in_elems = 0;
+    double in_bytes = 0;
     std::vector<int> per_level(G.L, 0);
     for (const Operand &o : G.ops) {
       per_level[o.level]++;
-      if (P.tensors[o.tensor].gate < 0) P.tensors[o.tensor].consumer = (int)g;
-      in_elems += std::ldexp(1.0, (int)P.tensors[o.tensor].vars.size());
+      const Tensor &t = P.tensors[o.tensor];
+      if (t.gate < 0) P.tensors[o.tensor].consumer = (int)g;
+      in_bytes += std::ldexp(1.0, (int)t.vars.size()) * es(t.gate < 0 ? t.prec : G.prec);
     }
-    P.bytes += opt.elem_bytes * (in_elems + std::ldexp(1.0, G.w - G.L));
+    P.bytes += in_bytes + es(G.prec) * std::ldexp(1.0, G.w - G.L);
     for (int l = 0; l < G.L; l++) {
       int factors = per_level[l] + (l > 0 ? 1 : 0);
       P.flops += std::ldexp(1.0, G.w - l) * 6.0 * std::max(0, factors - 1) +
@@ -494,20 +507,20 @@ std::string plan_cone(const LightCone &lc, const std::vector<int> &order,
     }
   }
 
-  // memory plan: outputs are placed before the group's inputs are released
+  // memory plan (bytes, 256-aligned): outputs are placed before the group's
+  // inputs are released
   Arena A;
-  const int64_t align = std::max<int64_t>(1, 256 / opt.elem_bytes);
   for (size_t g = 0; g < P.groups.size(); g++) {
     Group &G = P.groups[g];
     if (G.out_tensor >= 0) {
-      int64_t sz = (int64_t)1 << (G.w - G.L);
-      sz = (sz + align - 1) / align * align;
+      int64_t sz = ((int64_t)1 << (G.w - G.L)) * (int64_t)es(G.prec);
+      sz = (sz + 255) / 256 * 256;
       P.tensors[G.out_tensor].offset = A.alloc(sz);
     }
     for (const Operand &o : G.ops)
       if (P.tensors[o.tensor].gate < 0) A.release(P.tensors[o.tensor].offset);
   }
-  P.arena_elems = A.peak;
+  P.arena_bytes = A.peak;
   return "";
 }
 

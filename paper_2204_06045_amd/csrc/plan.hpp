@@ -71,7 +71,8 @@ struct Tensor {
   bool transposed = false; // rank-2 gate stored with var[0] as bit 0
   int producer = -1;       // group writing this intermediate
   int consumer = -1;       // group reading it
-  int64_t offset = -1;     // element offset inside the light cone's arena
+  int64_t offset = -1;     // byte offset inside the light cone's arena
+  int8_t prec = 0;         // storage: 0 complex128, 1 complex64
 };
 
 struct Operand {
@@ -88,6 +89,7 @@ struct Group {
   int out_tensor = -1;       // -1: scalar output
   int scalar_slot = -1;      // light cone's scalar slot when out_tensor < 0
   bool small = false;        // runs inside one workgroup
+  int8_t prec = 0;           // arithmetic: 0 complex128, 1 complex64
   // kernel choice from the autotuner or the cost model (-1: width rule)
   int8_t pick_place = -1;    // 0 inside a workgroup segment, 1 own launch
   int8_t pick_variant = -1;  // 1 generic mapping, 2 streaming mapping
@@ -103,7 +105,7 @@ struct ConePlan {
   std::vector<Tensor> tensors;
   std::vector<Group> groups;       // in execution order
   int n_scalars = 0;
-  int64_t arena_elems = 0;         // peak live elements of intermediates
+  int64_t arena_bytes = 0;         // peak live bytes of intermediates
   double bytes = 0, flops = 0, paper_flops = 0;  // per evaluation
 };
 
@@ -115,7 +117,8 @@ struct PlanOptions {
   int max_levels = kMaxLevels;
   int small_width = 12;
   int max_width = kMaxWidth;
-  int elem_bytes = 16;
+  int precision = 0;     // 0 complex128, 1 complex64, 2 mixed
+  int mixed_width = 18;  // mixed: groups at least this wide run in complex64
 };
 
 // Symbolic bucket elimination of one light cone along `order`, merged into

@@ -90,6 +90,26 @@ def test_c64_plan_halves_bytes(qtn):
     assert abs(n2.stats()["bytes"] * 2 - n1.stats()["bytes"]) < 1e-6 * n1.stats()["bytes"]
 
 
+def test_mixed_plan_bytes_between_c64_and_c128(qtn):
+    inst = qs.instance(30, 3, 4, 0)
+    g, b = inst["angles"][0]
+    st = {}
+    for name, prec, mw in [("c128", 0, 0), ("c64", 1, 0), ("mixed", 2, 16), ("mixed32", 2, 32)]:
+        net = qtn.Network(30, inst["edges"], g, b, mixed_width=mw)
+        net.plan(prec)
+        st[name] = net.stats()
+        net.close()
+    assert st["c64"]["bytes"] < st["mixed"]["bytes"] < st["c128"]["bytes"]
+    # no group is 32 wide: mixed keeps every group in complex128
+    assert abs(st["mixed32"]["bytes"] - st["c128"]["bytes"]) < 1e-6 * st["c128"]["bytes"]
+    with pytest.raises(qtn.QtnError):
+        qtn.Network(30, inst["edges"], g, b, mixed_width=33)
+    net = qtn.Network(30, inst["edges"], g, b)
+    with pytest.raises(qtn.QtnError):
+        net.plan(3)
+    net.close()
+
+
 @pytest.mark.parametrize("edges,msg", [
     ([(0, 0)], "self-loop"),
     ([(0, 1), (1, 0)], "repeated"),

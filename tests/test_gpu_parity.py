@@ -1,7 +1,7 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
 
 Tolerances (per edge |delta e_jk| and |Im e_jk|, and |delta E| / |E|):
-complex128 1e-10, complex64 1e-5.  Every e_jk is bounded by ||Z_j Z_k|| = 1,
+complex128 1e-10, complex64 and mixed 1e-5.  Every e_jk is bounded by ||Z_j Z_k|| = 1,
 so the per-edge bound is relative to the operator scale.
 """
 import json
@@ -16,7 +16,7 @@ import qaoa_synth as qs
 pytestmark = pytest.mark.gpu
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-TOL = {0: 1e-10, 1: 1e-5}
+TOL = {0: 1e-10, 1: 1e-5, 2: 1e-5}
 
 
 def _check(zz, zi, en, ref_zz, ref_en, prec, what=""):
@@ -233,6 +233,26 @@ def test_autotune_keeps_parity(qtn, orc, gpu, prec):
     net.close()
 
 
+@pytest.mark.parametrize("n,p", [(16, 3), (20, 3)])
+def test_mixed_precision(qtn, orc, gpu, n, p):
+    """Mixed: groups of union width >= mixed_width in complex64, the rest (and
+    every group ending in a scalar) in complex128, converting on load."""
+    inst = qs.instance(n, 3, p, 11)
+    g, b = inst["angles"][0]
+    ref, ref_en = orc.energy(n, inst["edges"], g, b, threads=8)
+    for mw in (1, 4, 8, 12):
+        for cfg in [dict(), dict(small_width=4), dict(variant=1, small_width=4),
+                    dict(variant=2, small_width=4, lane_sum_bits=1), dict(executor=2),
+                    dict(executor=2, small_width=4, max_levels=2)]:
+            print(f"mixed n={n} p={p} mixed_width={mw} cfg={cfg}", flush=True)
+            zz, zi, en = _run(qtn, n, inst["edges"], g, b, 2, mixed_width=mw, **cfg)
+            _check(zz, zi, en, ref, ref_en, 2, f"mixed {mw} {cfg}")
+    # no group reaches width 32: mixed is then the complex128 path exactly
+    full = _run(qtn, n, inst["edges"], g, b, 0, small_width=4)
+    same = _run(qtn, n, inst["edges"], g, b, 2, small_width=4, mixed_width=32)
+    assert np.array_equal(full[0], same[0]) and full[2] == same[2]
+
+
 def _golden(name):
     with open(os.path.join(HERE, "golden", f"{name}_oracle.json")) as f:
         return json.load(f)
@@ -241,7 +261,7 @@ def _golden(name):
 @pytest.mark.parametrize("prec,levels,variant,trials,executor", [
     (0, 8, 0, 0, 0), (1, 8, 0, 0, 0), (0, 1, 0, 0, 0), (0, 8, 1, 0, 0), (1, 1, 0, 0, 0),
     (0, 8, 0, 64, 0), (1, 8, 0, 64, 0), (0, 8, 2, 16, 0), (0, 8, 0, 64, 2), (1, 8, 1, 64, 2),
-    (0, 8, 0, 64, 3)])
+    (0, 8, 0, 64, 3), (2, 8, 0, 64, 0), (2, 8, 0, 64, 2)])
 def test_cfg2_full_size_against_oracle(qtn, gpu, prec, levels, variant, trials, executor):
     """3-regular N=30, p=4 (Sec. II-E benchmark shape), all 45 light cones."""
     gd = _golden("cfg2")

@@ -233,3 +233,41 @@ def test_symbolic_widths_match_numeric_run(orc):
     for eid in range(0, 24, 4):
         _, w = orc.edge_zz(16, inst["edges"], eid, g, b, return_widths=True)
         assert np.array_equal(w, orc.edge_widths(16, inst["edges"], eid, 3))
+
+
+def test_costmodel_oracle_gradient_by_finite_differences(orc):
+    r = np.random.default_rng(11)
+    P = orc.mlp_nparams()
+    assert P == 16 * 64 + 64 + 64 * 64 + 64 + 64 * 3 + 3
+    params = 0.3 * r.standard_normal(P)
+    x = r.standard_normal((9, 16))
+    t = r.standard_normal((9, 3))
+    m = (r.random((9, 3)) > 0.25).astype(float)
+    loss, g = orc.mlp_loss_grad(params, x, t, m)
+    h = 1e-6
+    for q in range(0, P, 53):
+        pp = params.copy()
+        pp[q] += h
+        lp, _ = orc.mlp_loss_grad(pp, x, t, m)
+        pp[q] -= 2 * h
+        lm, _ = orc.mlp_loss_grad(pp, x, t, m)
+        assert abs((lp - lm) / (2 * h) - g[q]) < 1e-6 * max(1.0, abs(g[q]))
+    # the loss is the masked mean of squared errors of the forward pass
+    y = orc.mlp_forward(params, x)
+    assert abs(loss - np.sum(m * (y - t) ** 2) / np.sum(m)) < 1e-12
+
+
+def test_costmodel_oracle_special_cases(orc):
+    P = orc.mlp_nparams()
+    # zero weights: the output is the last bias
+    params = np.zeros(P)
+    params[-3:] = [1.5, -2.0, 0.25]
+    y = orc.mlp_forward(params, np.ones((4, 16)))
+    assert np.allclose(y, [[1.5, -2.0, 0.25]] * 4)
+    # Adam's first step from zero moments moves every parameter by lr*sign(g)
+    g = np.linspace(-1, 1, P)
+    g[P // 2] = 0.3
+    p1, m1, m2 = orc.mlp_adam(np.zeros(P), np.zeros(P), np.zeros(P), g, 1, 0.01)
+    nz = np.abs(g) > 1e-3
+    assert np.allclose(p1[nz], -0.01 * np.sign(g[nz]), rtol=1e-4)
+    assert np.allclose(m1, 0.1 * g) and np.allclose(m2, 0.001 * g * g)
