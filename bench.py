@@ -67,7 +67,7 @@ def run_rows(Q, torch, inst, prec, levels, streams, steps, warmup, autotune=Fals
 
 KERNEL_OF = {  # launch-log (kind, variant) -> kernel symbol
     (1, None): "k_block_groups", (2, 0): "k_wide_generic", (2, 1): "k_wide_stream",
-    (4, None): "k_persistent",
+    (2, 2): "k_wide_mfma", (4, None): "k_persistent",
 }
 
 
@@ -78,6 +78,8 @@ def kernel_name(rec):
         return None
     if rec["kind"] != 2:  # one instantiation serves every precision
         return base
+    if rec["variant"] == 2:  # complex64 only
+        return f"{base}<{'true' if rec['cvt'] else 'false'}>"
     t = "double2" if rec["prec"] == 0 else "float2"
     return f"{base}<{t}, {'true' if rec['cvt'] else 'false'}>"
 
@@ -235,6 +237,43 @@ def run_batch(Q, torch, steps, warmup, executor=0, autotune=False, order_trials=
     return row
 
 
+def run_cfg4(Q, torch, steps=10, autotune=True):
+    """4-regular N=40, p=3 (80 light cones): complex128, complex64 and mixed
+    precision (groups of width >= 18 in complex64, in matrix form on the
+    matrix cores where a group reshapes), each with its per-edge error
+    against the stored FP64 oracle values."""
+    import numpy as np
+    with open(os.path.join(ROOT, "tests", "golden", "cfg4_oracle.json")) as f:
+        gd = json.load(f)
+    ref = np.asarray(gd["zz_re"])
+    rows = {}
+    for name, prec, variant in (("c128", Q.QTN_C128, 0), ("c64", Q.QTN_C64, 0),
+                                ("mixed", Q.QTN_MIXED, 0), ("mixed_matrix", Q.QTN_MIXED, 3)):
+        net = Q.Network(gd["n"], gd["edges"], gd["gamma"], gd["beta"], order_trials=16,
+                        variant=variant)
+        net.plan(prec)
+        ws = net.workspace()
+        if autotune:
+            net.autotune(ws)
+        zz, _, en = net.contract(ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            net.contract(ws)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        err = np.abs(zz - ref)
+        st = net.stats()
+        rows[name] = {"evals_per_s": 1.0 / dt, "edge_err_max": float(err.max()),
+                      "edge_err_median": float(np.median(err)),
+                      "energy_rel_err": abs(en - gd["energy"]) / abs(gd["energy"]),
+                      "alg_bytes_per_eval": st["bytes"], "matrix_groups": st["n_matrix"],
+                      "max_width": st["max_width"]}
+        net.close()
+        torch.cuda.empty_cache()
+    return rows
+
+
 def run_costmodel(Q, torch, prec=1, epochs=600, lr=3e-3, reps=3):
     """Train the cost model on autotuner timings of N=10 p=1, N=30 p=4 and 16
     of the batched graphs; judge it by measured time on 32 held-out graphs
@@ -273,7 +312,7 @@ def run_costmodel(Q, torch, prec=1, epochs=600, lr=3e-3, reps=3):
     torch.cuda.empty_cache()
     rr = qs.Rng(5000)
     fallback_ms = learned_ms = 0.0
-    picks = np.zeros(3, dtype=np.int64)
+    picks = np.zeros(4, dtype=np.int64)
     for i in range(32):
         d = 3 if i < 16 else 4
         sizes = [n for n in range(50, 501) if (n * d) % 2 == 0]
@@ -304,7 +343,7 @@ def run_costmodel(Q, torch, prec=1, epochs=600, lr=3e-3, reps=3):
             "loss_last": float(hist[-1]), "heldout_graphs": 32,
             "fallback_ms_per_pass": fallback_ms, "learned_ms_per_pass": learned_ms,
             "gain": fallback_ms / learned_ms if learned_ms > 0 else None,
-            "picks_block_stream_generic": [int(v) for v in picks],
+            "picks_block_stream_generic_mfma": [int(v) for v in picks],
             "precision": "c64" if prec == 1 else "c128"}
 
 
@@ -399,6 +438,9 @@ def main():
             torch.cuda.empty_cache()
 
     if args.variants:
+        log("variant cfg4 (4-regular N=40 p=3: c128, c64, mixed, mixed + matrix form)")
+        variants["n40d4p3"] = run_cfg4(Q, torch, autotune=bool(args.autotune))
+        torch.cuda.empty_cache()
         log("variant costmodel (learned selector vs width rule, held-out graphs)")
         variants["costmodel_c64"] = run_costmodel(Q, torch)
         torch.cuda.empty_cache()

@@ -64,7 +64,9 @@ typedef struct qtn_config {
     int32_t lane_sum_bits; /* streaming kernel: summed indices spread over
                             lanes, the rest walked serially per lane [2]  */
     int32_t variant;     /* 0 auto, 1 generic kernel only, 2 streaming
-                            kernel wherever it applies [0]                 */
+                            kernel wherever it applies, 3 matrix form for
+                            every complex64 group that has one (others as
+                            auto) [0]                                       */
     int32_t order_trials; /* >1: plan with the cheapest (sum of 2^width) of
                             the greedy min-fill order and order_trials-1
                             min-fill orders with random tie-breaks [0]     */
@@ -209,6 +211,8 @@ int qtn_launch_log(const qtn_network *net, int64_t cap, qtn_launch_rec *out,
 #define QTN_VAR_STREAM 1  /* own launch, streaming mapping (LDS lane
                              tables, serial walk, butterflies)           */
 #define QTN_VAR_GENERIC 2 /* own launch, generic register/lane mapping   */
+#define QTN_VAR_MFMA 3    /* matrix form on the matrix cores (complex64
+                             groups whose operands reduce to two factors) */
 
 typedef struct qtn_tune_report {
     int32_t n_groups;     /* own-launch groups tuned                        */
@@ -220,11 +224,12 @@ typedef struct qtn_tune_report {
 
 /*
  * Autotuner.  Runs the planned evaluation once per candidate configuration
- * (generic mapping; streaming mapping with 1, 2 or 3 lane-summed bits), each
- * group in its own launch on one stream and, for groups up to width 16, again
- * alone inside one workgroup, timing every launch with HIP events.  Each
- * group then keeps its fastest configuration for where it runs, and the plan's
- * schedule is rebuilt.  Needs the workspace qtn_plan reported.  The timings
+ * (generic mapping; streaming mapping with 1, 2 or 3 lane-summed bits; matrix
+ * form, which only complex64 groups that have one take part in), each group in
+ * its own launch on one stream and, for groups up to width 16, again alone
+ * inside one workgroup, timing every launch with HIP events.  Each group then
+ * keeps its fastest configuration for where it runs, and the plan's schedule
+ * is rebuilt.  Needs the workspace qtn_plan reported.  The timings
  * are kept for qtn_tune_log.  Results of qtn_contract are unchanged up to
  * rounding order.
  */
@@ -235,21 +240,21 @@ int qtn_autotune(qtn_network *net, void *d_workspace, size_t bytes,
  * the measured time of each QTN_VAR_* (negative: not measured). */
 typedef struct qtn_tune_rec {
     float features[16];
-    double ms[3];
+    double ms[4];
 } qtn_tune_rec;
 
 int qtn_tune_log(const qtn_network *net, int64_t cap, qtn_tune_rec *out,
                  int64_t *n_out);
 
 /*
- * Learned cost model (16 -> 64 -> 64 -> 3 perceptron, ReLU hidden units):
+ * Learned cost model (16 -> 64 -> 64 -> 4 perceptron, ReLU hidden units):
  * from a group's 16 shape features (those of qtn_tune_rec) it predicts the
  * natural log of the launch time in milliseconds of each QTN_VAR_* variant.
  * Forward, backward and Adam run in FP32 HIP kernels on the caller's
  * stream; parameters live on the host between calls.  Parameter layout
- * (floats): W1[16][64], b1[64], W2[64][64], b2[64], W3[64][3], b3[3].
+ * (floats): W1[16][64], b1[64], W2[64][64], b2[64], W3[64][4], b3[4].
  */
-#define QTN_MLP_PARAMS 5443
+#define QTN_MLP_PARAMS 5508
 typedef struct qtn_costmodel qtn_costmodel;
 
 /* A model with the given initial parameters (drawn by the caller). */
@@ -262,19 +267,19 @@ int qtn_costmodel_normalization(const qtn_costmodel *cm, float *mean_out,
 int qtn_costmodel_workspace(int64_t n, size_t *bytes_out);
 
 /* Full-batch Adam (lr, beta1 0.9, beta2 0.999) for `epochs` steps on
- * features x[n][16] and times ms[n][3] (targets log ms; entries <= 0 are not
+ * features x[n][16] and times ms[n][4] (targets log ms; entries <= 0 are not
  * measured and carry no loss).  loss_history [epochs] or NULL. */
 int qtn_costmodel_train(qtn_costmodel *cm, const float *x, const double *ms,
                         int64_t n, int32_t epochs, float lr, void *d_workspace,
                         size_t bytes, void *hip_stream, float *loss_history);
 
-/* Predicted log-ms [n][3] for raw features x[n][16]. */
+/* Predicted log-ms [n][4] for raw features x[n][16]. */
 int qtn_costmodel_predict(const qtn_costmodel *cm, const float *x, int64_t n,
                           void *d_workspace, size_t bytes, void *hip_stream,
                           float *y_out);
 
 /* Loss and gradient at the current parameters for inputs already
- * standardised (x[n][16]), targets t[n][3] and mask m[n][3]. */
+ * standardised (x[n][16]), targets t[n][4] and mask m[n][4]. */
 int qtn_costmodel_grad(const qtn_costmodel *cm, const float *x, const float *t,
                        const float *m, int64_t n, void *d_workspace,
                        size_t bytes, void *hip_stream, float *loss_out,
@@ -285,8 +290,9 @@ int qtn_costmodel_adam_step(qtn_costmodel *cm, const float *grad, float lr,
                             void *d_workspace, size_t bytes, void *hip_stream);
 
 /* Picks, for every group of a planned network, the variant with the lowest
- * predicted time (inside a workgroup only up to width 16) and rebuilds the
- * schedule.  counts_out [3] or NULL: groups per QTN_VAR_*.  Workspace: the
+ * predicted time (inside a workgroup only up to width 16; the matrix form
+ * only for complex64 groups that have one) and rebuilds the schedule.
+ * counts_out [4] or NULL: groups per QTN_VAR_*.  Workspace: the
  * cost-model bytes for as many samples as the network has groups. */
 int qtn_apply_costmodel(qtn_network *net, const qtn_costmodel *cm,
                         void *d_workspace, size_t bytes, void *hip_stream,
@@ -305,6 +311,7 @@ typedef struct qtn_plan_stats {
     double flops;         /* complex-arithmetic FLOPs of one evaluation  */
     double paper_flops;   /* 8 * sum 2^width (the paper's Sec. II-E count) */
     size_t workspace;     /* device bytes                                 */
+    int64_t n_matrix;     /* groups scheduled in matrix form (QTN_VAR_MFMA) */
 } qtn_plan_stats;
 
 int qtn_get_plan_stats(const qtn_network *net, qtn_plan_stats *out);

@@ -206,7 +206,7 @@ def contract_bucket(tensors, sum_vars, out_idx):
 
 # ------------------------------------------------------------- cost model
 
-MLP_SHAPE = (16, 64, 64, 3)
+MLP_SHAPE = (16, 64, 64, 4)
 
 
 def mlp_nparams():
@@ -217,9 +217,9 @@ def mlp_forward(params, x):
     p, pp = _dbls(params)
     xx, xp = _dbls(x)
     n = len(xx) // 16
-    y, yp = _dbls(np.zeros(n * 3))
+    y, yp = _dbls(np.zeros(n * MLP_SHAPE[3]))
     _check(lib().qtno_mlp_forward(pp, xp, n, yp))
-    return y.reshape(n, 3)
+    return y.reshape(n, MLP_SHAPE[3])
 
 
 def mlp_loss_grad(params, x, t, m):

@@ -962,9 +962,9 @@ int qtno_contract_bucket(int n_tensors, const int *ranks, const int *idx_flat,
 
 /*
  * FP64 reference of the cost-model network: 16 inputs, two hidden layers of
- * 64 rectified-linear units, 3 linear outputs (predicted log launch time of
+ * 64 rectified-linear units, 4 linear outputs (predicted log launch time of
  * each kernel variant).  Parameters are packed as
- *   W1[16][64], b1[64], W2[64][64], b2[64], W3[64][3], b3[3]
+ *   W1[16][64], b1[64], W2[64][64], b2[64], W3[64][4], b3[4]
  * (row-major, input index first).  The loss is the mean of the squared
  * errors over the measured entries:
  *   loss = sum_{i,k} m_ik (y_ik - t_ik)^2 / sum_{i,k} m_ik.
@@ -973,7 +973,7 @@ int qtno_contract_bucket(int n_tensors, const int *ranks, const int *idx_flat,
  */
 #define MLP_IN 16
 #define MLP_H 64
-#define MLP_OUT 3
+#define MLP_OUT 4
 #define MLP_NPARAM (MLP_IN * MLP_H + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H * MLP_OUT + MLP_OUT)
 
 int qtno_mlp_nparams(void) { return MLP_NPARAM; }

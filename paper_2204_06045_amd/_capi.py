@@ -42,7 +42,7 @@ EXPORTS = (
     "qtn_costmodel_grad", "qtn_costmodel_adam_step", "qtn_apply_costmodel",
     "qtn_costmodel_free",
 )
-MLP_PARAMS = 5443
+MLP_PARAMS = 5508
 
 
 class qtn_config(ctypes.Structure):
@@ -77,7 +77,7 @@ class qtn_tune_report(ctypes.Structure):
 
 
 class qtn_tune_rec(ctypes.Structure):
-    _fields_ = [("features", ctypes.c_float * 16), ("ms", ctypes.c_double * 3)]
+    _fields_ = [("features", ctypes.c_float * 16), ("ms", ctypes.c_double * 4)]
 
 
 class qtn_plan_stats(ctypes.Structure):
@@ -85,7 +85,7 @@ class qtn_plan_stats(ctypes.Structure):
                 ("n_wide", ctypes.c_int64), ("max_width", ctypes.c_int32),
                 ("width_hist", ctypes.c_int32 * 40), ("bytes", ctypes.c_double),
                 ("flops", ctypes.c_double), ("paper_flops", ctypes.c_double),
-                ("workspace", ctypes.c_size_t)]
+                ("workspace", ctypes.c_size_t), ("n_matrix", ctypes.c_int64)]
 
 
 class QtnError(RuntimeError):

@@ -169,7 +169,7 @@ def qtn_get_plan_stats(net):
     return {"n_buckets": s.n_buckets, "n_groups": s.n_groups, "n_wide": s.n_wide,
             "max_width": s.max_width, "width_hist": list(s.width_hist),
             "bytes": s.bytes, "flops": s.flops, "paper_flops": s.paper_flops,
-            "workspace": s.workspace}
+            "workspace": s.workspace, "n_matrix": s.n_matrix}
 
 
 def qtn_plan_order(net, edge):
@@ -208,14 +208,14 @@ def qtn_autotune(net, ws, stream=None):
 
 
 def qtn_tune_log(net):
-    """(features [n, 16] float32, ms [n, 3] float64) from the last autotune."""
+    """(features [n, 16] float32, ms [n, 4] float64) from the last autotune."""
     n = ctypes.c_int64()
     check(lib().qtn_tune_log(net, 0, None, ctypes.byref(n)))
     arr = (qtn_tune_rec * max(1, n.value))()
     check(lib().qtn_tune_log(net, n.value, arr, ctypes.byref(n)))
     feats = np.array([list(r.features) for r in arr[:n.value]], dtype=np.float32)
     ms = np.array([list(r.ms) for r in arr[:n.value]], dtype=np.float64)
-    return feats.reshape(-1, 16), ms.reshape(-1, 3)
+    return feats.reshape(-1, 16), ms.reshape(-1, 4)
 
 
 def qtn_network_free(net):
@@ -350,7 +350,7 @@ class CostModel:
         check(lib().qtn_costmodel_predict(self.h, xp, n, ctypes.c_void_p(ws.data_ptr()),
                                           ws.numel(), stream_handle(stream),
                                           y.ctypes.data_as(_pf)))
-        return y.reshape(n, 3)
+        return y.reshape(n, 4)
 
     def grad(self, x, t, m, stream=None):
         x, xp = _f32(x)
@@ -389,7 +389,7 @@ def qtn_apply_costmodel(net, cm, stream=None):
     (block, stream, generic)."""
     n_groups = qtn_get_plan_stats(net)["n_groups"]
     ws = CostModel.workspace(max(1, n_groups))
-    counts = np.zeros(3, dtype=np.int32)
+    counts = np.zeros(4, dtype=np.int32)
     check(lib().qtn_apply_costmodel(net, cm.h, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                                     stream_handle(stream), counts.ctypes.data_as(_pi32)))
     return counts

@@ -220,10 +220,10 @@ struct Force {
 constexpr int kTuneSingleWidth = 16;
 
 // Configurations measured by the autotuner: every group in its own launch
-// with the generic mapping, or with the streaming mapping at 1, 2, 3
-// lane-summed bits.
+// with the generic mapping, with the streaming mapping at 1, 2, 3
+// lane-summed bits, or in matrix form (complex64 groups that have one).
 const std::vector<Force> &tune_candidates() {
-  static const std::vector<Force> c = {{1, 1, 2}, {1, 2, 1}, {1, 2, 2}, {1, 2, 3}};
+  static const std::vector<Force> c = {{1, 1, 2}, {1, 2, 1}, {1, 2, 2}, {1, 2, 3}, {1, 3, 2}};
   return c;
 }
 
@@ -314,12 +314,38 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S, const Force *fo
         const int rls = std::min(G.L - 1, rls_req);
         const int sl = G.L - 1 - rls;
         const bool stream_ok = (int)G.ops.size() <= kStreamMaxOps && sl <= kStreamMaxSerial;
+        // matrix form: complex64 groups in their own launch whose operands
+        // reduce to two factors (requested, or picked by tuning)
+        GemmShape gsh;
+        const bool mfma = var_req == 3 && G.prec == 1 && gemm_shape(G, pl, &gsh);
+        if (var_req == 3 && !mfma) var_req = 0;
         // auto: the streaming mapping pays off once a lane walks >= 2 serial bits
-        const bool stream = stream_ok && (var_req == 2 || (var_req == 0 && sl >= 2));
+        const bool stream = !mfma && stream_ok && (var_req == 2 || (var_req == 0 && sl >= 2));
         std::vector<int> order(G.ops.size());
         std::vector<int> cls(G.ops.size(), 0);
         for (size_t k = 0; k < G.ops.size(); k++) order[k] = (int)k;
-        if (stream) {
+        if (mfma) {
+          dg.variant = kVarMfma;
+          // [a, into At..., b, into Bt..., into Out...]
+          std::vector<int> side[3];
+          side[0].push_back(gsh.a);
+          side[1].push_back(gsh.b);
+          for (int k = 0; k < (int)G.ops.size(); k++)
+            if (k != gsh.a && k != gsh.b) side[gsh.role[k]].push_back(k);
+          order.clear();
+          for (auto &sd : side) order.insert(order.end(), sd.begin(), sd.end());
+          dg.n_unit = (uint8_t)side[0].size();
+          dg.n_step = (uint8_t)side[1].size();
+          dg.n_serial = (uint8_t)side[2].size();
+          dg.n_mb = (uint8_t)gsh.mbits.size();
+          dg.n_nb = (uint8_t)gsh.nbits.size();
+          dg.n_bb = (uint8_t)gsh.bbits.size();
+          const uint64_t mt = ((1ull << dg.n_mb) + kMfmaTM - 1) / kMfmaTM;
+          const uint64_t nt = ((1ull << dg.n_nb) + kMfmaTN - 1) / kMfmaTN;
+          const uint64_t tiles = (1ull << dg.n_bb) * mt * nt;
+          if (tiles > 0xFFFFFFFFull) return set_err(QTN_ERANGE, "matrix-form group too large");
+          dg.n_units = (uint32_t)tiles;
+        } else if (stream) {
           dg.variant = kVarStream;
           dg.rls = (uint8_t)rls;
           dg.sl = (uint8_t)sl;
@@ -369,9 +395,19 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S, const Force *fo
           const int bits = kGenRegBits + 6;
           dg.n_units = G.w > bits ? 1u << (G.w - bits) : 1u;
         }
-        // wave-unit bits, those that large operands lack first (their data is
-        // then reused by neighbouring units of the same block and XCD)
-        {
+        if (mfma) {
+          // matrix form: m bits, then n bits, then batch bits
+          uint8_t up[32];
+          std::memset(up, 0, sizeof up);
+          int j = 0;
+          for (int q : gsh.mbits) up[j++] = (uint8_t)q;
+          for (int q : gsh.nbits) up[j++] = (uint8_t)q;
+          for (int q : gsh.bbits) up[j++] = (uint8_t)q;
+          dg.n_ubits = 0;
+          s.uperm.insert(s.uperm.end(), up, up + 32);
+        } else {
+          // wave-unit bits, those that large operands lack first (their data
+          // is then reused by neighbouring units of the same block and XCD)
           const int start = stream ? G.L + dg.lk : kGenRegBits + 6;
           std::vector<std::pair<double, int>> sc;
           for (int b = start; b < G.w; b++) {
@@ -805,7 +841,7 @@ int qtn_network_build(int32_t n_vertices, int64_t n_edges, const int32_t *edges,
       if (cfg->lane_sum_bits < 0 || cfg->lane_sum_bits > 5)
         return set_err(QTN_EINVAL, "lane_sum_bits must be in 0..5");
       if (cfg->lane_sum_bits) net->lane_sum_bits = cfg->lane_sum_bits;
-      if (cfg->variant < 0 || cfg->variant > 2) return set_err(QTN_EINVAL, "variant must be 0..2");
+      if (cfg->variant < 0 || cfg->variant > 3) return set_err(QTN_EINVAL, "variant must be 0..3");
       net->variant = cfg->variant;
       if (cfg->order_trials < 0 || cfg->order_trials > 4096)
         return set_err(QTN_EINVAL, "order_trials must be in 0..4096");
@@ -1120,8 +1156,12 @@ int qtn_autotune(qtn_network *net, void *d_workspace, size_t bytes, void *hip_st
       }
       QTN_HIP(hipStreamSynchronize(ex.rt.main));
       auto key_of = [&](int g) { return std::make_pair(s.group_cone[g], s.group_index[g]); };
+      // a candidate only counts for the groups that ran its kernel
+      auto ran = [&](int g) {
+        return cands[ci].variant != 3 || s.groups[g].variant == kVarMfma;
+      };
       for (auto &r : tm.recs) {
-        if (r.kind != QTN_K_WIDE) continue;
+        if (r.kind != QTN_K_WIDE || !ran(r.group)) continue;
         float ms = 0;
         QTN_HIP(hipEventElapsedTime(&ms, r.a, r.b));
         Meas &m = meas.emplace(key_of(r.group), Meas{{-1, -1, -1, -1, -1, -1, -1, -1},
@@ -1130,6 +1170,7 @@ int qtn_autotune(qtn_network *net, void *d_workspace, size_t bytes, void *hip_st
         rep.cand_ms[ci] += ms;
       }
       for (auto &r : tb.recs) {
+        if (!ran(r.group)) continue;
         float ms = 0;
         QTN_HIP(hipEventElapsedTime(&ms, r.a, r.b));
         Meas &m = meas.emplace(key_of(r.group), Meas{{-1, -1, -1, -1, -1, -1, -1, -1},
@@ -1160,15 +1201,17 @@ int qtn_autotune(qtn_network *net, void *d_workspace, size_t bytes, void *hip_st
       qtn_tune_rec tr;
       std::memset(&tr, 0, sizeof tr);
       group_features(G, pl, net->precision, tr.features);
-      double mb = -1, ms_stream = -1;
+      double mb = -1, ms_stream = -1, ms_mfma = -1;
       for (int ci = 0; ci < nc; ci++) {
         if (m.block[ci] >= 0 && (mb < 0 || m.block[ci] < mb)) mb = m.block[ci];
         if (cands[ci].variant == 2 && m.wide[ci] >= 0 && (ms_stream < 0 || m.wide[ci] < ms_stream))
           ms_stream = m.wide[ci];
+        if (cands[ci].variant == 3) ms_mfma = m.wide[ci];
       }
       tr.ms[QTN_VAR_BLOCK] = mb;
       tr.ms[QTN_VAR_STREAM] = ms_stream;
       tr.ms[QTN_VAR_GENERIC] = m.wide[0];
+      tr.ms[QTN_VAR_MFMA] = ms_mfma;
       net->tune_log.push_back(tr);
     }
     // the tuned schedule replaces the current one
@@ -1226,6 +1269,7 @@ int qtn_get_plan_stats(const qtn_network *net, qtn_plan_stats *out) {
     st.flops += s.flops[k];
   }
   st.workspace = s.total;
+  for (const DevGroup &g : s.groups) st.n_matrix += g.variant == kVarMfma ? 1 : 0;
   *out = st;
   return QTN_OK;
 }
@@ -1466,23 +1510,28 @@ int qtn_apply_costmodel(qtn_network *net, const qtn_costmodel *cm, void *d_ws, s
     if (!net->planned) return set_err(QTN_ESTATE, "qtn_plan has not been called");
     std::vector<float> feats;
     std::vector<Group *> gs;
+    std::vector<const ConePlan *> gp;
     for (ConePlan &pl : net->plans)
       for (Group &G : pl.groups) {
         float f[kNumFeatures];
         group_features(G, pl, net->precision, f);
         feats.insert(feats.end(), f, f + kNumFeatures);
         gs.push_back(&G);
+        gp.push_back(&pl);
       }
     const int64_t n = (int64_t)gs.size();
     std::vector<float> y(n * kMlpOut);
     int rc = qtn_costmodel_predict(cm, feats.data(), n, d_ws, bytes, hip_stream, y.data());
     if (rc) return rc;
-    int32_t counts[3] = {0, 0, 0};
+    int32_t counts[4] = {0, 0, 0, 0};
     for (int64_t i = 0; i < n; i++) {
       Group &G = *gs[i];
       const float *p = &y[i * kMlpOut];
-      // inside a workgroup only where that was ever measured (width <= 16)
+      // inside a workgroup only where that was ever measured (width <= 16);
+      // the matrix form only where the group has one
       int best = p[QTN_VAR_STREAM] <= p[QTN_VAR_GENERIC] ? QTN_VAR_STREAM : QTN_VAR_GENERIC;
+      if (G.prec == 1 && p[QTN_VAR_MFMA] < p[best] && gemm_shape(G, *gp[i], nullptr))
+        best = QTN_VAR_MFMA;
       if (G.w <= 16 && p[QTN_VAR_BLOCK] < p[best]) best = QTN_VAR_BLOCK;
       counts[best]++;
       G.pick_place = best == QTN_VAR_BLOCK ? 0 : 1;
@@ -1490,7 +1539,7 @@ int qtn_apply_costmodel(qtn_network *net, const qtn_costmodel *cm, void *d_ws, s
         G.pick_variant = -1;
         G.pick_rls = -1;
       } else {
-        G.pick_variant = best == QTN_VAR_STREAM ? 2 : 1;
+        G.pick_variant = best == QTN_VAR_STREAM ? 2 : (best == QTN_VAR_MFMA ? 3 : 1);
         G.pick_rls = 2;
       }
     }
@@ -1503,7 +1552,7 @@ int qtn_apply_costmodel(qtn_network *net, const qtn_costmodel *cm, void *d_ws, s
     drop_batches_with(net);
     net->exec = std::move(ex);
     net->version++;
-    if (counts_out) std::copy(counts, counts + 3, counts_out);
+    if (counts_out) std::copy(counts, counts + 4, counts_out);
     return QTN_OK;
   } catch (const std::bad_alloc &) {
     return set_err(QTN_ENOMEM, "host allocation failed");

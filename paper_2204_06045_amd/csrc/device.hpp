@@ -48,13 +48,21 @@ struct DevGroup {       // 48 bytes
   uint8_t n_ubits;      // wave-unit bits (their union positions: uperm)
   uint8_t prec;         // arithmetic and output storage: 0 complex128, 1 complex64
   uint8_t cvt;          // 1: some operand is stored in the other precision
-  uint8_t pad2[5];
+  uint8_t n_mb, n_nb, n_bb;  // matrix form: m, n and batch bit counts (their
+                             // union positions: uperm, m then n then batch)
+  uint8_t pad2[2];
 };
 
 static_assert(sizeof(DevOp) == 64, "DevOp layout");
 static_assert(sizeof(DevGroup) == 48, "DevGroup layout");
 
-enum Variant : uint8_t { kVarGeneric = 0, kVarStream = 1 };
+enum Variant : uint8_t { kVarGeneric = 0, kVarStream = 1, kVarMfma = 2 };
+
+// Matrix form (kVarMfma): ops are [a, ops into At..., b, ops into Bt...,
+// ops into Out...] with n_unit = |At side|, n_step = |Bt side|, n_serial =
+// |Out side|.  A work unit is one 64 x 16 (m x n) output tile of one batch
+// index; a whole workgroup computes it.
+constexpr int kMfmaTM = 64, kMfmaTN = 16, kMfmaKC = 32, kMfmaLd = kMfmaKC + 1;
 
 // Generic mapping: 2 register bits and 6 lane bits per wave unit.
 constexpr int kGenRegBits = 2;

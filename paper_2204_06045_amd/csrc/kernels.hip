@@ -25,6 +25,10 @@
 // Generic (kVarGeneric).  2 register bits and 6 lane bits per unit, every
 // level in hierarchical order with register adds and lane butterflies.  Used
 // for groups with more operands than the streaming LDS tables hold.
+//
+// Matrix form (kVarMfma, complex64).  A group whose operands reduce to two
+// factors over the summed indices is a batched complex matrix product; it
+// runs as three real FP32 products on the matrix cores (3M).
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -383,6 +387,95 @@ __device__ __forceinline__ void stream_unit(const DevGroup &G, const DevOp *__re
   }
 }
 
+// ------------------------------------------------------------ matrix form
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+static_assert((kMfmaTM + kMfmaTN) * kMfmaLd * 8 <= kStreamMaxOps * 64 * 4,
+              "matrix tiles must fit the streaming LDS tables");
+
+// Product of operands [k0, k1) at union index I, in complex64.
+template <bool CVT>
+__device__ __forceinline__ float2 op_product(const DevOp *__restrict__ gops, int k0, int k1,
+                                             const char *__restrict__ data, uint32_t I) {
+  float2 v = make_float2(1.0f, 0.0f);
+  for (int k = k0; k < k1; k++) {
+    const DevOp &o = gops[k];
+    v = cmul(v, ld_elem<float2, CVT>(data + o.off, pext_runs(I, o), o.dt));
+  }
+  return v;
+}
+
+// One 64 x 16 output tile of a matrix-form group, with the whole workgroup.
+// Per chunk of 32 summed indices, At (64 x 32) and Bt (16 x 32) are gathered
+// into LDS with their absorbed operands multiplied in; then three real
+// products run on the matrix cores (3M: T1 = Ar Br, T2 = Ai Bi,
+// T3 = (Ar + Ai)(Br + Bi); Re = T1 - T2, Im = T3 - T1 - T2), accumulated in
+// FP32.  Wave v owns tile rows 16v..16v+15.  v_mfma_f32_16x16x4_f32 lane
+// layout: A[i][k] and B[k][j] come from lane i + 16k (j + 16k); lane l holds
+// C[4(l/16) + r][l % 16] in element r.
+template <bool CVT>
+__device__ void mfma_tile(const DevGroup &G, const DevOp *__restrict__ gops,
+                          const uint8_t *__restrict__ bits, char *__restrict__ data,
+                          float2 *lds, uint32_t tile) {
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int nM = G.n_mb, nN = G.n_nb, nB = G.n_bb, L = G.L;
+  const uint32_t M = 1u << nM, N = 1u << nN, K = 1u << L;
+  const uint32_t mt = (M + kMfmaTM - 1) / kMfmaTM, nt = (N + kMfmaTN - 1) / kMfmaTN;
+  const uint32_t bt = tile / (mt * nt), rem = tile % (mt * nt);
+  const uint32_t m0 = (rem / nt) * kMfmaTM, n0 = (rem % nt) * kMfmaTN;
+  const uint8_t *mpos = bits, *npos = bits + nM, *bpos = bits + nM + nN;
+  // m0 and n0 are multiples of the tile sizes, so their union bits and those
+  // of a row (col) inside the tile are disjoint
+  const uint32_t Ib = unit_bits(bt, bpos, nB) | unit_bits(m0, mpos, nM) | unit_bits(n0, npos, nN);
+  const int mlo = nM < 6 ? nM : 6, nlo = nN < 4 ? nN : 4;
+  const uint32_t kc = K >= (uint32_t)kMfmaKC ? (uint32_t)kMfmaKC : (K < 4u ? 4u : K);
+  const int na = G.n_unit, nb = G.n_step, no = G.n_serial;
+  float2 *sA = lds, *sB = lds + kMfmaTM * kMfmaLd;
+  f32x4 t1 = {0.0f, 0.0f, 0.0f, 0.0f}, t2 = t1, t3 = t1;
+  for (uint32_t k0 = 0; k0 < K; k0 += kc) {
+    for (uint32_t e = tid; e < kMfmaTM * kc; e += kBlock) {
+      const uint32_t row = e / kc, kk = e % kc, k = k0 + kk;
+      float2 v = make_float2(0.0f, 0.0f);
+      if (m0 + row < M && k < K)
+        v = op_product<CVT>(gops, 0, na, data, Ib | unit_bits(row, mpos, mlo) | k);
+      sA[row * kMfmaLd + kk] = v;
+    }
+    for (uint32_t e = tid; e < kMfmaTN * kc; e += kBlock) {
+      const uint32_t col = e / kc, kk = e % kc, k = k0 + kk;
+      float2 v = make_float2(0.0f, 0.0f);
+      if (n0 + col < N && k < K)
+        v = op_product<CVT>(gops, na, na + nb, data, Ib | unit_bits(col, npos, nlo) | k);
+      sB[col * kMfmaLd + kk] = v;
+    }
+    __syncthreads();
+    const float2 *ra = sA + (wave * 16 + (lane & 15)) * kMfmaLd + (lane >> 4);
+    const float2 *rb = sB + (lane & 15) * kMfmaLd + (lane >> 4);
+    for (uint32_t kk = 0; kk < kc; kk += 4) {
+      const float2 a = ra[kk], b = rb[kk];
+      t1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, t1, 0, 0, 0);
+      t2 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, t2, 0, 0, 0);
+      t3 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x + a.y, b.x + b.y, t3, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  float2 *out = (float2 *)(data + G.out_off);
+  const uint32_t col = lane & 15;
+  if (n0 + col < N) {
+    const uint32_t Ic = Ib | unit_bits(col, npos, nlo);
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+      const uint32_t row = wave * 16 + 4 * (lane >> 4) + i;
+      if (m0 + row < M) {
+        float2 v = make_float2(t1[i] - t2[i], t3[i] - t1[i] - t2[i]);
+        const uint32_t I = Ic | unit_bits(row, mpos, mlo);
+        if (no > 0) v = cmul(v, op_product<CVT>(gops, na + nb, na + nb + no, data, I));
+        out[I >> L] = v;
+      }
+    }
+  }
+}
+
 // One group's wave units [u0, u1) over the block's waves, in the group's
 // own precision.
 __device__ __forceinline__ void run_group(const DevGroup &G, int g, const DevOp *__restrict__ ops,
@@ -403,7 +496,13 @@ __device__ __forceinline__ void run_group(const DevGroup &G, int g, const DevOp 
     else                                                                           \
       for (uint32_t u = u0 + wave; u < u1; u += nw) F<float2, true>(__VA_ARGS__);   \
   } while (0)
-  if (G.variant == kVarStream) {
+  if (G.variant == kVarMfma) {
+    // matrix form: a unit is one output tile, computed by the whole block
+    if (G.cvt)
+      for (uint32_t u = u0; u < u1; u++) mfma_tile<true>(G, gops, ub, data, (float2 *)s_lane, u);
+    else
+      for (uint32_t u = u0; u < u1; u++) mfma_tile<false>(G, gops, ub, data, (float2 *)s_lane, u);
+  } else if (G.variant == kVarStream) {
     stream_setup(G, gops, s_lane);
     __syncthreads();
     QTN_UNITS(stream_unit, G, gops, stab, ub, data, s_lane, u, lane);
@@ -423,7 +522,7 @@ __global__ __launch_bounds__(kBlock) void k_block_groups(char *__restrict__ data
                                                          const uint8_t *__restrict__ uperm,
                                                          const int2 *__restrict__ ranges,
                                                          int range_base) {
-  __shared__ uint32_t s_lane[kStreamMaxOps * 64];
+  __shared__ __align__(16) uint32_t s_lane[kStreamMaxOps * 64];
   const int2 rg = ranges[range_base + blockIdx.x];
   for (int g = rg.x; g < rg.y; g++) {
     const DevGroup &G = groups[g];
@@ -447,7 +546,7 @@ __global__ __launch_bounds__(kBlock) void k_wide_stream(char *__restrict__ data,
                                                         const DevOp *__restrict__ ops,
                                                         const int32_t *__restrict__ stab,
                                                         const uint8_t *__restrict__ uperm, int gid) {
-  __shared__ uint32_t s_lane[kStreamMaxOps * 64];
+  __shared__ __align__(16) uint32_t s_lane[kStreamMaxOps * 64];
   const DevGroup &G = groups[gid];
   const DevOp *gops = ops + G.op_begin;
   const int lane = threadIdx.x & 63;
@@ -477,6 +576,19 @@ __global__ __launch_bounds__(kBlock) void k_wide_generic(char *__restrict__ data
   const uint32_t w0 = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   for (uint32_t u = ub + w0; u < ue; u += nw)
     generic_unit<T, CVT>(G, gops, uperm + 32 * gid, data, u, lane);
+}
+
+template <bool CVT>
+__global__ __launch_bounds__(kBlock) void k_wide_mfma(char *__restrict__ data,
+                                                      const DevGroup *__restrict__ groups,
+                                                      const DevOp *__restrict__ ops,
+                                                      const uint8_t *__restrict__ uperm, int gid) {
+  __shared__ __align__(16) float2 s_tile[(kMfmaTM + kMfmaTN) * kMfmaLd];
+  const DevGroup &G = groups[gid];
+  uint32_t ub, ue;
+  wide_range(G.n_units, &ub, &ue);
+  for (uint32_t t = ub; t < ue; t++)
+    mfma_tile<CVT>(G, ops + G.op_begin, uperm + 32 * gid, data, s_tile, t);
 }
 
 // ----------------------------------------------------- persistent executor
@@ -547,7 +659,7 @@ __global__ __launch_bounds__(kBlock) void k_persistent(char *__restrict__ data,
                                                        const int *__restrict__ step_begin,
                                                        int n_steps, uint32_t *ctl,
                                                        uint32_t spin_limit) {
-  __shared__ uint32_t s_lane[kStreamMaxOps * 64];
+  __shared__ __align__(16) uint32_t s_lane[kStreamMaxOps * 64];
   __shared__ int s_item;
   uint32_t *step_ctr = ctl + 4;
   for (int st = 0; st < n_steps; st++) {
@@ -689,6 +801,16 @@ hipError_t launch_wide_group(int prec, bool cvt, int variant, void *data, const 
                              int group, uint32_t n_units, hipStream_t s) {
   const int nb = wide_blocks(n_units);
   char *d = (char *)data;
+  if (variant == kVarMfma) {
+    if (prec != kPrecC64) return hipErrorInvalidValue;  // complex64 arithmetic only
+    if (cvt)
+      hipLaunchKernelGGL(k_wide_mfma<true>, dim3(nb), dim3(kBlock), 0, s, d, groups, ops, uperm,
+                         group);
+    else
+      hipLaunchKernelGGL(k_wide_mfma<false>, dim3(nb), dim3(kBlock), 0, s, d, groups, ops, uperm,
+                         group);
+    return hipGetLastError();
+  }
   if (prec == kPrecC128 && !cvt)
     launch_wide_t<double2, false>(variant, nb, d, groups, ops, stab, uperm, group, s);
   else if (prec == kPrecC128)

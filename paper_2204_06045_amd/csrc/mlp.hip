@@ -1,11 +1,11 @@
-// Learned cost model: a 16-64-64-3 multilayer perceptron predicting the log
+// Learned cost model: a 16-64-64-4 multilayer perceptron predicting the log
 // launch time of a group under each kernel variant, trained on timings the
 // autotuner measures.  Forward, backward and Adam are hand-written FP32
 // kernels; every reduction runs in a fixed order, so results are
 // deterministic.
 //
 // Parameter layout (floats): W1[16][64], b1[64], W2[64][64], b2[64],
-// W3[64][3], b3[3], row-major with the input index first.
+// W3[64][4], b3[4], row-major with the input index first.
 #include <hip/hip_runtime.h>
 
 #include "mlp.hpp"

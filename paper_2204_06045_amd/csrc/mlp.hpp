@@ -8,7 +8,7 @@
 
 namespace qtn {
 
-constexpr int kMlpIn = 16, kMlpHidden = 64, kMlpOut = 3;
+constexpr int kMlpIn = 16, kMlpHidden = 64, kMlpOut = 4;
 constexpr int kMlpParams = kMlpIn * kMlpHidden + kMlpHidden + kMlpHidden * kMlpHidden +
                            kMlpHidden + kMlpHidden * kMlpOut + kMlpOut;
 

@@ -293,9 +293,72 @@ void group_features(const Group &G, const ConePlan &pl, int precision, float *f)
   f[10] = (float)std::log2(es * (elems + std::ldexp(1.0, G.w - G.L)));
   f[11] = (float)std::log2(std::max(1.0, flops));
   f[12] = (float)n_small;
-  f[13] = (float)(rank_sum / std::max(1, G.w));
+  // matrix form: 1 + its n bits (the smaller side), 0 if the group has none
+  GemmShape gs;
+  f[13] = gemm_shape(G, pl, &gs) ? (float)(1 + gs.nbits.size()) : 0.0f;
+  (void)rank_sum;
   f[14] = (float)n_inter;
   f[15] = (float)G.prec;
+}
+
+bool gemm_shape(const Group &G, const ConePlan &pl, GemmShape *gs) {
+  const int n = (int)G.ops.size();
+  if (n < 2 || G.w > 31) return false;
+  const uint32_t summed = (1u << G.L) - 1u, all = (1u << G.w) - 1u, kept = all & ~summed;
+  std::vector<int> by_rank(n);
+  for (int k = 0; k < n; k++) by_rank[k] = k;
+  auto rank = [&](int k) { return (int)pl.tensors[G.ops[k].tensor].vars.size(); };
+  std::stable_sort(by_rank.begin(), by_rank.end(), [&](int x, int y) { return rank(x) > rank(y); });
+  bool found = false;
+  GemmShape best;
+  int best_m = -1;
+  // a: the largest operand; b: each other operand in order of rank
+  const int a = by_rank[0];
+  for (int bi = 1; bi < n; bi++) {
+    const int b = by_rank[bi];
+    const uint32_t ma = G.ops[a].mask, mb = G.ops[b].mask;
+    GemmShape s;
+    s.a = a;
+    s.b = b;
+    s.role.assign(n, 0);
+    bool ok = true;
+    for (int k = 0; k < n && ok; k++) {
+      const uint32_t mk = G.ops[k].mask;
+      if (k == a || (k != b && (mk & ~ma) == 0)) s.role[k] = 0;
+      else if (k == b || (mk & ~mb) == 0) s.role[k] = 1;
+      else if ((mk & ~kept) == 0) s.role[k] = 2;
+      else ok = false;
+    }
+    if (!ok) continue;
+    for (int q = G.L; q < G.w; q++) {
+      const bool in_a = (ma >> q) & 1u, in_b = (mb >> q) & 1u;
+      if (in_a && in_b) s.bbits.push_back(q);
+      else if (in_b) s.nbits.push_back(q);
+      else s.mbits.push_back(q);
+    }
+    if (s.nbits.size() > s.mbits.size()) {
+      // b has more private kept bits: swap the roles of a and b
+      std::swap(s.a, s.b);
+      for (auto &r : s.role)
+        if (r < 2) r = (int8_t)(1 - r);
+      std::vector<int> mb2, nb2;
+      for (int q = G.L; q < G.w; q++) {
+        const bool in_a = (G.ops[s.a].mask >> q) & 1u, in_b = (G.ops[s.b].mask >> q) & 1u;
+        if (in_a && in_b) continue;
+        if (in_b) nb2.push_back(q);
+        else mb2.push_back(q);
+      }
+      s.mbits.swap(mb2);
+      s.nbits.swap(nb2);
+    }
+    if ((int)s.mbits.size() > best_m) {
+      best_m = (int)s.mbits.size();
+      best = s;
+      found = true;
+    }
+  }
+  if (found && gs) *gs = best;
+  return found;
 }
 
 int mask_runs(uint32_t mask, uint8_t *src, uint8_t *len, uint8_t *dst) {

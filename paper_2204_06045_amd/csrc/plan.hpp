@@ -109,6 +109,24 @@ struct ConePlan {
   double bytes = 0, flops = 0, paper_flops = 0;  // per evaluation
 };
 
+// Matrix form of a group.  The merged contraction of Sec. II-C is a batched
+// complex matrix product when two operands a and b cover every other operand
+// that carries a summed index:
+//   out[bt, m, n] = Out[bt, m, n] * sum_k At[bt, m, k] Bt[bt, k, n]
+// At (Bt) is operand a (b) times the operands whose indices it covers; Out is
+// the product of the operands that carry kept indices only.  k runs over the
+// L summed union bits (0..L-1); m over kept bits of a alone (and kept bits of
+// neither, broadcast); n over kept bits of b alone; bt over kept bits of both.
+struct GemmShape {
+  int a = -1, b = -1;            // operand positions in Group::ops
+  std::vector<int8_t> role;      // per operand: 0 into At, 1 into Bt, 2 into Out
+  std::vector<int> mbits, nbits, bbits;  // union bit positions, low to high
+};
+
+// The matrix form of G, or false when G has none.  Of the valid choices the
+// one with the most rows per batch (m bits) is taken, with |m| >= |n|.
+bool gemm_shape(const Group &G, const ConePlan &pl, GemmShape *gs);
+
 // 16 shape features of a group, for timing records and the cost model.
 constexpr int kNumFeatures = 16;
 void group_features(const Group &G, const ConePlan &pl, int precision, float *f);

@@ -110,6 +110,22 @@ def test_mixed_plan_bytes_between_c64_and_c128(qtn):
     net.close()
 
 
+def test_matrix_form_scheduled_only_in_complex64(qtn):
+    inst = qs.instance(30, 3, 4, 0)
+    g, b = inst["angles"][0]
+    counts = {}
+    for prec in (0, 1, 2):
+        for variant in (0, 3):
+            net = qtn.Network(30, inst["edges"], g, b, variant=variant, mixed_width=16)
+            net.plan(prec)
+            counts[prec, variant] = net.stats()["n_matrix"]
+            net.close()
+    # requested only: never by the default rule, never in complex128 groups
+    assert counts[0, 0] == counts[1, 0] == counts[2, 0] == 0
+    assert counts[0, 3] == 0
+    assert counts[1, 3] > counts[2, 3] > 0
+
+
 @pytest.mark.parametrize("edges,msg", [
     ([(0, 0)], "self-loop"),
     ([(0, 1), (1, 0)], "repeated"),

@@ -12,7 +12,7 @@ pytestmark = pytest.mark.gpu
 
 def _rand_params(seed, scale=0.2):
     r = qs.Rng(seed)
-    n = 5443
+    n = 5508
     # uniform in [-scale, scale) from the shared seeded generator
     return np.array([scale * (2 * r.uniform() - 1) for _ in range(n)], dtype=np.float32)
 
@@ -32,8 +32,8 @@ def test_gradient_matches_oracle(qtn, orc, gpu):
     p = _rand_params(3)
     r = np.random.default_rng(4)
     x = r.standard_normal((257, 16)).astype(np.float32)
-    t = r.standard_normal((257, 3)).astype(np.float32)
-    m = (r.random((257, 3)) > 0.2).astype(np.float32)
+    t = r.standard_normal((257, 4)).astype(np.float32)
+    m = (r.random((257, 4)) > 0.2).astype(np.float32)
     cm = qtn.CostModel(p)
     loss, g = cm.grad(x, t, m)
     rl, rg = orc.mlp_loss_grad(p.astype(np.float64), x.astype(np.float64),
@@ -61,8 +61,9 @@ def test_training_reduces_loss(qtn, gpu):
     x = r.uniform(0, 30, (2000, 16)).astype(np.float32)
     # a smooth synthetic timing law: log ms grows with feature 0 and 10
     ms = np.stack([np.exp(0.2 * x[:, 0] - 4), np.exp(0.1 * x[:, 10] - 3),
-                   np.exp(0.05 * (x[:, 0] + x[:, 10]) - 3)], 1)
+                   np.exp(0.05 * (x[:, 0] + x[:, 10]) - 3), np.exp(0.15 * x[:, 3] - 5)], 1)
     ms[::5, 0] = -1.0  # unmeasured entries
+    ms[::3, 3] = -1.0
     cm = qtn.CostModel(_rand_params(8, 0.1))
     hist = cm.train(x, ms, 400, 3e-3)
     assert hist[-1] < 0.05 * hist[0]

@@ -223,7 +223,7 @@ def test_autotune_keeps_parity(qtn, orc, gpu, prec):
     net = qtn.Network(20, inst["edges"], g, b)
     net.plan(prec)
     rep = net.autotune()
-    assert rep["n_candidates"] == 4 and rep["n_groups"] > 0
+    assert rep["n_candidates"] == 5 and rep["n_groups"] > 0
     assert rep["tuned_ms"] <= min(rep["cand_ms"]) * (1 + 1e-9)
     feats, ms = net.tune_log()
     assert feats.shape[1] == 16 and len(feats) == len(ms) > 0
@@ -253,6 +253,31 @@ def test_mixed_precision(qtn, orc, gpu, n, p):
     assert np.array_equal(full[0], same[0]) and full[2] == same[2]
 
 
+@pytest.mark.parametrize("n,p", [(12, 2), (16, 3), (20, 3)])
+def test_matrix_form_parity(qtn, orc, gpu, n, p):
+    """Matrix form (3M on the matrix cores, FP32) for every complex64 group
+    that has one, in its own launch, inside workgroups and in the persistent
+    executor."""
+    inst = qs.instance(n, 3, p, 5)
+    g, b = inst["angles"][0]
+    ref, ref_en = orc.energy(n, inst["edges"], g, b, threads=8)
+    for prec, cfg in [(1, dict(small_width=4)), (1, dict()), (1, dict(small_width=4, max_levels=1)),
+                      (1, dict(small_width=4, max_levels=2)), (1, dict(executor=2, small_width=4)),
+                      (2, dict(small_width=4, mixed_width=6)), (2, dict(mixed_width=1))]:
+        print(f"matrix form n={n} p={p} prec={prec} cfg={cfg}", flush=True)
+        net = qtn.Network(n, inst["edges"], g, b, variant=3, **cfg)
+        net.plan(prec)
+        assert net.stats()["n_matrix"] > 0
+        zz, zi, en = net.contract()
+        _check(zz, zi, en, ref, ref_en, prec, f"matrix form {cfg}")
+        if cfg.get("executor", 0) != 2:
+            net.contract_timed()
+            log = net.launch_log()
+            if cfg.get("small_width") == 4:
+                assert any(r["kind"] == 2 and r["variant"] == 2 for r in log)
+        net.close()
+
+
 def _golden(name):
     with open(os.path.join(HERE, "golden", f"{name}_oracle.json")) as f:
         return json.load(f)
@@ -261,7 +286,7 @@ def _golden(name):
 @pytest.mark.parametrize("prec,levels,variant,trials,executor", [
     (0, 8, 0, 0, 0), (1, 8, 0, 0, 0), (0, 1, 0, 0, 0), (0, 8, 1, 0, 0), (1, 1, 0, 0, 0),
     (0, 8, 0, 64, 0), (1, 8, 0, 64, 0), (0, 8, 2, 16, 0), (0, 8, 0, 64, 2), (1, 8, 1, 64, 2),
-    (0, 8, 0, 64, 3), (2, 8, 0, 64, 0), (2, 8, 0, 64, 2)])
+    (0, 8, 0, 64, 3), (2, 8, 0, 64, 0), (2, 8, 0, 64, 2), (1, 8, 3, 64, 0), (2, 8, 3, 64, 0)])
 def test_cfg2_full_size_against_oracle(qtn, gpu, prec, levels, variant, trials, executor):
     """3-regular N=30, p=4 (Sec. II-E benchmark shape), all 45 light cones."""
     gd = _golden("cfg2")
@@ -271,3 +296,19 @@ def test_cfg2_full_size_against_oracle(qtn, gpu, prec, levels, variant, trials, 
                       max_levels=levels, variant=variant, order_trials=trials,
                       executor=executor)
     _check(zz, zi, en, gd["zz_re"], gd["energy"], prec, "cfg2")
+
+
+@pytest.mark.parametrize("prec,variant,mixed_width", [
+    (0, 0, 0), (1, 0, 0), (2, 0, 18), (2, 3, 18), (1, 3, 0), (2, 3, 12)])
+def test_cfg4_full_size_against_oracle(qtn, gpu, prec, variant, mixed_width):
+    """4-regular N=40, p=3, all 80 light cones; mixed precision runs groups of
+    width >= mixed_width in complex64 (matrix form where it applies with
+    variant 3) and reports the per-edge error against the FP64 oracle."""
+    gd = _golden("cfg4")
+    print(f"cfg4 prec={prec} variant={variant} mixed_width={mixed_width}", flush=True)
+    zz, zi, en = _run(qtn, gd["n"], gd["edges"], gd["gamma"], gd["beta"], prec,
+                      variant=variant, order_trials=16, mixed_width=mixed_width)
+    err = np.abs(zz - np.asarray(gd["zz_re"]))
+    print(f"  per-edge |delta e|: max {err.max():.3e} median {np.median(err):.3e}; "
+          f"|delta E|/E {abs(en - gd['energy']) / gd['energy']:.3e}", flush=True)
+    _check(zz, zi, en, gd["zz_re"], gd["energy"], prec, "cfg4")

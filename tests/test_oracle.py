@@ -238,11 +238,11 @@ def test_symbolic_widths_match_numeric_run(orc):
 def test_costmodel_oracle_gradient_by_finite_differences(orc):
     r = np.random.default_rng(11)
     P = orc.mlp_nparams()
-    assert P == 16 * 64 + 64 + 64 * 64 + 64 + 64 * 3 + 3
+    assert P == 16 * 64 + 64 + 64 * 64 + 64 + 64 * 4 + 4
     params = 0.3 * r.standard_normal(P)
     x = r.standard_normal((9, 16))
-    t = r.standard_normal((9, 3))
-    m = (r.random((9, 3)) > 0.25).astype(float)
+    t = r.standard_normal((9, 4))
+    m = (r.random((9, 4)) > 0.25).astype(float)
     loss, g = orc.mlp_loss_grad(params, x, t, m)
     h = 1e-6
     for q in range(0, P, 53):
@@ -261,9 +261,9 @@ def test_costmodel_oracle_special_cases(orc):
     P = orc.mlp_nparams()
     # zero weights: the output is the last bias
     params = np.zeros(P)
-    params[-3:] = [1.5, -2.0, 0.25]
+    params[-4:] = [1.5, -2.0, 0.25, 0.75]
     y = orc.mlp_forward(params, np.ones((4, 16)))
-    assert np.allclose(y, [[1.5, -2.0, 0.25]] * 4)
+    assert np.allclose(y, [[1.5, -2.0, 0.25, 0.75]] * 4)
     # Adam's first step from zero moments moves every parameter by lr*sign(g)
     g = np.linspace(-1, 1, P)
     g[P // 2] = 0.3
