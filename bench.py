@@ -230,7 +230,8 @@ def run_batch(Q, torch, steps, warmup, executor=0, autotune=False, order_trials=
            "ms_per_call": 1e3 * dt / steps, "plan_seconds": plan_s, "tune_seconds": tune_s,
            "alg_bytes_per_call": sum(s["bytes"] for s in st),
            "max_width": max(s["max_width"] for s in st),
-           "executor": "persistent" if executor in (0, 2) else "launches",
+           "executor": {0: "persistent lockstep", 2: "persistent lockstep",
+                        4: "persistent dataflow"}.get(executor, "launches"),
            "precision": "c64" if prec == 1 else "c128", "order_trials": order_trials}
     for n in nets:
         n.close()

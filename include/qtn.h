@@ -71,12 +71,15 @@ typedef struct qtn_config {
                             the greedy min-fill order and order_trials-1
                             min-fill orders with random tie-breaks [0]     */
     int32_t executor;    /* 0 default (single networks: per-group launches
-                            over n_streams; batches: persistent), 1 per-group
-                            launches, 2 one persistent lockstep launch, 3
-                            per-group launches with each cone's leading
-                            small groups launched on that cone's stream    */
-    int32_t spin_limit;  /* persistent executor: polls before a grid-barrier
-                            wait gives up with QTN_EDEVICE [2^26]          */
+                            over n_streams; batches: persistent lockstep),
+                            1 per-group launches, 2 one persistent lockstep
+                            launch, 3 per-group launches with each cone's
+                            leading small groups launched on that cone's
+                            stream, 4 one persistent dataflow launch (work
+                            items wait only for the previous task of their
+                            own light cone)                                */
+    int32_t spin_limit;  /* persistent executors: polls before a barrier or
+                            dependency wait gives up with QTN_EDEVICE [2^26] */
     int32_t mixed_width; /* QTN_MIXED: narrowest group run in complex64 [18] */
     int32_t reserved[5];
 } qtn_config;

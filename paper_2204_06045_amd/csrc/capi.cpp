@@ -94,11 +94,14 @@ struct Schedule {
   std::vector<char> desc_blob;  // bytes [off_desc, off_data)
   double bytes[QTN_NKERNELS] = {}, flops[QTN_NKERNELS] = {};
   double init_bytes = 0, init_flops = 0;
-  // persistent lockstep executor
+  // persistent executors: work items in step order; the task (one cone's
+  // segment or wide group) of each item, each task's predecessor in its cone
+  // (-1: none) and its item count
   std::vector<int4> items;
-  std::vector<int> step_begin;
-  int n_steps = 0;
-  size_t off_items = 0, off_steps = 0, off_ctl = 0;
+  std::vector<int> step_begin, item_task, task_dep, task_need;
+  int n_steps = 0, n_tasks = 0;
+  size_t off_items = 0, off_steps = 0, off_item_task = 0, off_task_dep = 0, off_task_need = 0,
+         off_ctl = 0;
   int n_ctl = 0;
 };
 
@@ -147,6 +150,7 @@ struct Exec {
   Schedule sched;
   Runtime rt;
   bool persistent = false;
+  bool dataflow = false;  // persistent: per-task dependencies instead of lockstep
   bool lead_per_cone = false;
   uint32_t spin_limit = 1u << 26;
 };
@@ -501,39 +505,69 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S, const Force *fo
   s.singles_range0 = (int)s.ranges.size();
   for (int g : s.singles) s.ranges.push_back(make_int2(g, g + 1));
   s.n_nets = n;
-  // lockstep steps: the j-th task of every cone (leading segment first)
+  // persistent work items: the j-th task of every cone forms step j (leading
+  // segment first); inside a step the costlier cones come first.  The
+  // lockstep executor runs the steps between grid barriers; the dataflow
+  // executor takes items in the same order and waits only for the previous
+  // task of the item's own cone.
   {
+    std::vector<int> corder(s.n_cones);
+    std::vector<double> ccost(s.n_cones, 0);
+    for (int c = 0; c < s.n_cones; c++) {
+      corder[c] = c;
+      for (auto &t : s.cone_tasks[c]) ccost[c] += t.bytes;
+    }
+    std::stable_sort(corder.begin(), corder.end(), [&](int a, int b) { return ccost[a] > ccost[b]; });
     std::vector<std::vector<int4>> per_step;
-    for (int cn = 0; cn < s.n_cones; cn++) {
-      int j = 0;
-      auto put = [&](const int4 &it) {
-        if ((int)per_step.size() <= j) per_step.resize(j + 1);
+    std::vector<std::vector<int>> per_step_task;
+    for (int cn : corder) {
+      int j = 0, prev = -1;
+      auto put = [&](const int4 &it, int task) {
+        if ((int)per_step.size() <= j) {
+          per_step.resize(j + 1);
+          per_step_task.resize(j + 1);
+        }
         per_step[j].push_back(it);
+        per_step_task[j].push_back(task);
+      };
+      auto new_task = [&]() {
+        s.task_dep.push_back(prev);
+        s.task_need.push_back(0);
+        prev = (int)s.task_dep.size() - 1;
+        return prev;
       };
       if (lead[cn].y > lead[cn].x) {
-        put(make_int4(lead[cn].x, lead[cn].y, 0, 0));
+        const int tk = new_task();
+        put(make_int4(lead[cn].x, lead[cn].y, 0, 0), tk);
+        s.task_need[tk]++;
         j++;
       }
       for (const Task &t : s.cone_tasks[cn]) {
+        const int tk = new_task();
         if (t.kind == QTN_K_BLOCK) {
           const int2 r = s.ranges[t.index];
-          put(make_int4(r.x, r.y, 0, 0));
+          put(make_int4(r.x, r.y, 0, 0), tk);
+          s.task_need[tk]++;
         } else {
           const uint32_t nu = t.n_units;
           uint32_t chunk = std::max<uint32_t>(4u, nu / 2048u);
-          for (uint32_t u = 0; u < nu; u += chunk)
-            put(make_int4(t.index, -1, (int)u, (int)std::min(nu, u + chunk)));
+          for (uint32_t u = 0; u < nu; u += chunk) {
+            put(make_int4(t.index, -1, (int)u, (int)std::min(nu, u + chunk)), tk);
+            s.task_need[tk]++;
+          }
         }
         j++;
       }
     }
     s.step_begin.push_back(0);
-    for (auto &v : per_step) {
-      s.items.insert(s.items.end(), v.begin(), v.end());
+    for (size_t j = 0; j < per_step.size(); j++) {
+      s.items.insert(s.items.end(), per_step[j].begin(), per_step[j].end());
+      s.item_task.insert(s.item_task.end(), per_step_task[j].begin(), per_step_task[j].end());
       s.step_begin.push_back((int)s.items.size());
     }
     s.n_steps = (int)per_step.size();
-    s.n_ctl = 4 + s.n_steps;
+    s.n_tasks = (int)s.task_dep.size();
+    s.n_ctl = 4 + std::max(s.n_steps, s.n_tasks);
   }
   s.bytes[QTN_K_BLOCK] = s.init_bytes;
   s.flops[QTN_K_BLOCK] = s.init_flops;
@@ -557,7 +591,10 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S, const Force *fo
   s.off_ncb = align_up(s.off_csb + sizeof(int) * s.csb.size(), 256);
   s.off_items = align_up(s.off_ncb + sizeof(int) * s.ncb.size(), 256);
   s.off_steps = align_up(s.off_items + sizeof(int4) * s.items.size(), 256);
-  s.off_ctl = align_up(s.off_steps + sizeof(int) * s.step_begin.size(), 256);
+  s.off_item_task = align_up(s.off_steps + sizeof(int) * s.step_begin.size(), 256);
+  s.off_task_dep = align_up(s.off_item_task + sizeof(int) * s.item_task.size(), 256);
+  s.off_task_need = align_up(s.off_task_dep + sizeof(int) * s.task_dep.size(), 256);
+  s.off_ctl = align_up(s.off_task_need + sizeof(int) * s.task_need.size(), 256);
   s.off_data = align_up(s.off_ctl + sizeof(uint32_t) * s.n_ctl, 256);
   s.total = s.off_data + (size_t)data;
   s.desc_blob.assign(s.off_data - s.off_desc, 0);
@@ -574,6 +611,9 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S, const Force *fo
   put(s.off_ncb, s.ncb.data(), sizeof(int) * s.ncb.size());
   put(s.off_items, s.items.data(), sizeof(int4) * s.items.size());
   put(s.off_steps, s.step_begin.data(), sizeof(int) * s.step_begin.size());
+  put(s.off_item_task, s.item_task.data(), sizeof(int) * s.item_task.size());
+  put(s.off_task_dep, s.task_dep.data(), sizeof(int) * s.task_dep.size());
+  put(s.off_task_need, s.task_need.data(), sizeof(int) * s.task_need.size());
   return QTN_OK;
 }
 
@@ -665,9 +705,17 @@ int enqueue(Exec &X, Timer &tm) {
       f_all += s.flops[k];
     }
     if ((rc = tm.begin(QTN_K_PERSISTENT, rt.main, 0, (int)s.groups.size(), b_all, f_all))) return rc;
-    QTN_HIP(launch_persistent(s.prec, data, groups, ops, stab, uperm, (const int4 *)(ws + s.off_items),
-                              (const int *)(ws + s.off_steps), s.n_steps,
-                              (uint32_t *)(ws + s.off_ctl), s.n_ctl, nb, X.spin_limit, rt.main));
+    if (X.dataflow)
+      QTN_HIP(launch_dataflow(data, groups, ops, stab, uperm, (const int4 *)(ws + s.off_items),
+                              (int)s.items.size(), (const int *)(ws + s.off_item_task),
+                              (const int *)(ws + s.off_task_dep),
+                              (const int *)(ws + s.off_task_need), (uint32_t *)(ws + s.off_ctl),
+                              s.n_ctl, nb, X.spin_limit, rt.main));
+    else
+      QTN_HIP(launch_persistent(s.prec, data, groups, ops, stab, uperm,
+                                (const int4 *)(ws + s.off_items), (const int *)(ws + s.off_steps),
+                                s.n_steps, (uint32_t *)(ws + s.off_ctl), s.n_ctl, nb, X.spin_limit,
+                                rt.main));
     if ((rc = tm.end(rt.main))) return rc;
   } else {
   // leading small segments: one launch for every cone before the fork, or
@@ -793,7 +841,9 @@ int run_exec(Exec &X, const std::vector<const qtn_network *> &nets, void *ws, si
                            hipMemcpyDeviceToHost, rt.main));
   QTN_HIP(hipStreamSynchronize(rt.main));
   if (X.persistent && rt.pinned_err[2] != 0)
-    return set_err(QTN_EDEVICE, "persistent executor: a grid barrier wait exceeded its bound");
+    return set_err(QTN_EDEVICE, X.dataflow
+                                    ? "persistent executor: a dependency wait exceeded its bound"
+                                    : "persistent executor: a grid barrier wait exceeded its bound");
   res.assign(rt.pinned, rt.pinned + n_res);
   return QTN_OK;
 }
@@ -846,7 +896,7 @@ int qtn_network_build(int32_t n_vertices, int64_t n_edges, const int32_t *edges,
       if (cfg->order_trials < 0 || cfg->order_trials > 4096)
         return set_err(QTN_EINVAL, "order_trials must be in 0..4096");
       net->order_trials = cfg->order_trials;
-      if (cfg->executor < 0 || cfg->executor > 3) return set_err(QTN_EINVAL, "executor must be 0..3");
+      if (cfg->executor < 0 || cfg->executor > 4) return set_err(QTN_EINVAL, "executor must be 0..4");
       net->executor = cfg->executor;
       if (cfg->spin_limit > 0) net->spin_limit = (uint32_t)cfg->spin_limit;
       if (cfg->mixed_width < 0 || cfg->mixed_width > 32)
@@ -945,7 +995,8 @@ int qtn_plan(qtn_network *net, const int32_t *const *orders, int32_t precision,
       return rc;
     }
     drop_batches_with(net);
-    ex->persistent = net->executor == 2;
+    ex->persistent = net->executor == 2 || net->executor == 4;
+    ex->dataflow = net->executor == 4;
     ex->lead_per_cone = net->executor == 3;
     {
       size_t mx = ex->sched.total;
@@ -1069,7 +1120,9 @@ static Exec *batch_exec(qtn_network *const *nets, int32_t n, int *rc) {
   auto ex = std::make_unique<Exec>();
   *rc = build_schedule(nets, n, &ex->sched);
   if (*rc) return nullptr;
-  ex->persistent = nets[0]->executor != 1;  // batches default to the persistent executor
+  // batches default to the persistent executor
+  ex->persistent = nets[0]->executor != 1 && nets[0]->executor != 3;
+  ex->dataflow = nets[0]->executor == 4;
   ex->spin_limit = nets[0]->spin_limit;
   Exec *raw = ex.get();
   g_batch[key] = std::move(ex);
@@ -1219,6 +1272,7 @@ int qtn_autotune(qtn_network *net, void *d_workspace, size_t bytes, void *hip_st
     int rc = build_schedule(one, 1, &ex->sched);
     if (rc) return rc;
     ex->persistent = net->exec->persistent;
+    ex->dataflow = net->exec->dataflow;
     ex->lead_per_cone = net->exec->lead_per_cone;
     ex->spin_limit = net->exec->spin_limit;
     drop_batches_with(net);
@@ -1547,6 +1601,7 @@ int qtn_apply_costmodel(qtn_network *net, const qtn_costmodel *cm, void *d_ws, s
     auto ex = std::make_unique<Exec>();
     if ((rc = build_schedule(one, 1, &ex->sched))) return rc;
     ex->persistent = net->exec->persistent;
+    ex->dataflow = net->exec->dataflow;
     ex->lead_per_cone = net->exec->lead_per_cone;
     ex->spin_limit = net->exec->spin_limit;
     drop_batches_with(net);

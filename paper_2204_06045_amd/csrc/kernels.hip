@@ -678,6 +678,61 @@ __global__ __launch_bounds__(kBlock) void k_persistent(char *__restrict__ data,
   }
 }
 
+// Dataflow form of the executor: blocks take items in order from ctl[0]; an
+// item first waits for the completion counter of its task's predecessor (the
+// previous task of the same light cone), then runs, then counts itself done.
+// Every item's predecessor items come earlier in the order and were taken by
+// running blocks, so the earliest unfinished item can always proceed.
+// Results are published with an agent-scope release before the count and
+// observed with an agent-scope acquire after the wait, as in grid_barrier.
+__global__ __launch_bounds__(kBlock) void k_dataflow(char *__restrict__ data,
+                                                     const DevGroup *__restrict__ groups,
+                                                     const DevOp *__restrict__ ops,
+                                                     const int32_t *__restrict__ stab,
+                                                     const uint8_t *__restrict__ uperm,
+                                                     const int4 *__restrict__ items, int n_items,
+                                                     const int *__restrict__ item_task,
+                                                     const int *__restrict__ task_dep,
+                                                     const int *__restrict__ task_need,
+                                                     uint32_t *ctl, uint32_t spin_limit) {
+  __shared__ __align__(16) uint32_t s_lane[kStreamMaxOps * 64];
+  __shared__ int s_item, s_ok;
+  uint32_t *head = ctl, *err = ctl + 2, *done = ctl + 4;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      s_item = (int)__hip_atomic_fetch_add(head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s_ok = 1;
+      if (s_item < n_items) {
+        const int d = task_dep[item_task[s_item]];
+        if (d >= 0) {
+          const uint32_t need = (uint32_t)task_need[d];
+          uint32_t polls = 0;
+          while (__hip_atomic_load(done + d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+            __builtin_amdgcn_s_sleep(2);
+            if (++polls > spin_limit ||
+                __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+              __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              s_ok = 0;
+              break;
+            }
+          }
+          __threadfence();
+        }
+      }
+    }
+    __syncthreads();
+    const int i = s_item, ok = s_ok;
+    __syncthreads();
+    if (i >= n_items || !ok) break;
+    run_item(items[i], data, groups, ops, stab, uperm, s_lane);
+    // run_item ends with a barrier: every wave's stores are issued
+    if (threadIdx.x == 0) {
+      __threadfence();
+      __hip_atomic_fetch_add(done + item_task[i], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
 __global__ void k_reset(uint32_t *ctl, int n) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
     ctl[i] = 0u;
@@ -833,6 +888,20 @@ hipError_t launch_persistent(int prec, void *data, const DevGroup *groups, const
   if (n_steps <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_persistent, dim3(n_blocks), dim3(kBlock), 0, s, (char *)data, groups, ops,
                      stab, uperm, items, step_begin, n_steps, ctl, spin_limit);
+  return hipGetLastError();
+}
+
+hipError_t launch_dataflow(void *data, const DevGroup *groups, const DevOp *ops,
+                           const int32_t *stab, const uint8_t *uperm, const int4 *items,
+                           int n_items, const int *item_task, const int *task_dep,
+                           const int *task_need, uint32_t *ctl, int n_ctl, int n_blocks,
+                           uint32_t spin_limit, hipStream_t s) {
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(256), 0, s, ctl, n_ctl);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_dataflow, dim3(n_blocks), dim3(kBlock), 0, s, (char *)data, groups, ops,
+                     stab, uperm, items, n_items, item_task, task_dep, task_need, ctl, spin_limit);
   return hipGetLastError();
 }
 

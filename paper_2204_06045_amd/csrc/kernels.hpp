@@ -49,6 +49,18 @@ hipError_t launch_persistent(int prec, void *data, const DevGroup *groups,
                              uint32_t *ctl, int n_ctl, int n_blocks,
                              uint32_t spin_limit, hipStream_t s);
 
+// Clears the control words, then runs the work items in order inside one
+// persistent launch: blocks take items from an atomic counter; an item of
+// task t first waits until task task_dep[t] (if >= 0) has completed all of
+// its task_need items.  ctl needs 4 + n_tasks words (ctl[0] the item counter,
+// ctl[2] != 0 after the launch means a wait exceeded spin_limit, then one
+// completion counter per task).
+hipError_t launch_dataflow(void *data, const DevGroup *groups, const DevOp *ops,
+                           const int32_t *stab, const uint8_t *uperm, const int4 *items,
+                           int n_items, const int *item_task, const int *task_dep,
+                           const int *task_need, uint32_t *ctl, int n_ctl, int n_blocks,
+                           uint32_t spin_limit, hipStream_t s);
+
 // Resident blocks of the persistent kernel on n_cu compute units (0 on error).
 int persistent_blocks(int prec, int n_cu);
 

@@ -73,7 +73,8 @@ def test_small_graphs_all_configs(qtn, orc, gpu, n, p, prec):
                 dict(order_trials=8), dict(small_width=4, variant=2, lane_sum_bits=4),
                 dict(executor=2), dict(executor=2, small_width=4),
                 dict(executor=2, max_levels=1, variant=1), dict(executor=3),
-                dict(executor=3, n_streams=2, small_width=8)]:
+                dict(executor=3, n_streams=2, small_width=8), dict(executor=4),
+                dict(executor=4, small_width=4), dict(executor=4, max_levels=1, variant=1)]:
         print(f"n={n} p={p} prec={prec} cfg={cfg}", flush=True)
         zz, zi, en = _run(qtn, n, inst["edges"], g, b, prec, **cfg)
         _check(zz, zi, en, ref, ref_en, prec, str(cfg))
@@ -188,6 +189,24 @@ def test_persistent_bounded_wait_reports_error(qtn, gpu):
     net.close()
 
 
+def test_dataflow_bounded_wait_reports_error(qtn, gpu):
+    """A spin limit of one poll makes the first dependency wait give up: every
+    block exits and the call reports QTN_EDEVICE instead of a result."""
+    inst = qs.instance(16, 3, 3, 3)
+    g, b = inst["angles"][0]
+    net = qtn.Network(16, inst["edges"], g, b, executor=4, spin_limit=1)
+    net.plan(0)
+    with pytest.raises(qtn.QtnError) as ei:
+        net.contract()
+    assert ei.value.code == -4 and "dependency" in str(ei.value)
+    net.close()
+    net = qtn.Network(16, inst["edges"], g, b, executor=4)
+    net.plan(0)
+    zz, zi, en = net.contract()
+    assert np.all(np.isfinite(zz))
+    net.close()
+
+
 def test_batch_persistent_and_streams_agree(qtn, orc, gpu):
     # N in [12, 40], p in {2, 3}: oracle widths stay at or below 18
     insts = qs.batch_instances(5, 6, 12, 40, (2, 3), d=3)
@@ -196,7 +215,7 @@ def test_batch_persistent_and_streams_agree(qtn, orc, gpu):
         g, b = it["angles"][0]
         print(f"oracle n={it['n']} p={it['p']}", flush=True)
         refs.append(orc.energy(it["n"], it["edges"], g, b, threads=8))
-    for executor in (0, 1):
+    for executor in (0, 1, 4):
         nets = []
         for it in insts:
             g, b = it["angles"][0]
@@ -263,6 +282,7 @@ def test_matrix_form_parity(qtn, orc, gpu, n, p):
     ref, ref_en = orc.energy(n, inst["edges"], g, b, threads=8)
     for prec, cfg in [(1, dict(small_width=4)), (1, dict()), (1, dict(small_width=4, max_levels=1)),
                       (1, dict(small_width=4, max_levels=2)), (1, dict(executor=2, small_width=4)),
+                      (1, dict(executor=4, small_width=4)),
                       (2, dict(small_width=4, mixed_width=6)), (2, dict(mixed_width=1))]:
         print(f"matrix form n={n} p={p} prec={prec} cfg={cfg}", flush=True)
         net = qtn.Network(n, inst["edges"], g, b, variant=3, **cfg)
@@ -270,7 +290,7 @@ def test_matrix_form_parity(qtn, orc, gpu, n, p):
         assert net.stats()["n_matrix"] > 0
         zz, zi, en = net.contract()
         _check(zz, zi, en, ref, ref_en, prec, f"matrix form {cfg}")
-        if cfg.get("executor", 0) != 2:
+        if cfg.get("executor", 0) not in (2, 4):
             net.contract_timed()
             log = net.launch_log()
             if cfg.get("small_width") == 4:
@@ -286,7 +306,8 @@ def _golden(name):
 @pytest.mark.parametrize("prec,levels,variant,trials,executor", [
     (0, 8, 0, 0, 0), (1, 8, 0, 0, 0), (0, 1, 0, 0, 0), (0, 8, 1, 0, 0), (1, 1, 0, 0, 0),
     (0, 8, 0, 64, 0), (1, 8, 0, 64, 0), (0, 8, 2, 16, 0), (0, 8, 0, 64, 2), (1, 8, 1, 64, 2),
-    (0, 8, 0, 64, 3), (2, 8, 0, 64, 0), (2, 8, 0, 64, 2), (1, 8, 3, 64, 0), (2, 8, 3, 64, 0)])
+    (0, 8, 0, 64, 3), (2, 8, 0, 64, 0), (2, 8, 0, 64, 2), (1, 8, 3, 64, 0), (2, 8, 3, 64, 0),
+    (0, 8, 0, 64, 4), (1, 8, 3, 64, 4)])
 def test_cfg2_full_size_against_oracle(qtn, gpu, prec, levels, variant, trials, executor):
     """3-regular N=30, p=4 (Sec. II-E benchmark shape), all 45 light cones."""
     gd = _golden("cfg2")
