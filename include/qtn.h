@@ -79,7 +79,7 @@ typedef struct qtn_config {
                             items wait only for the previous task of their
                             own light cone)                                */
     int32_t spin_limit;  /* persistent executors: polls before a barrier or
-                            dependency wait gives up with QTN_EDEVICE [2^26] */
+                            dependency wait gives up with QTN_EDEVICE [2^22] */
     int32_t mixed_width; /* QTN_MIXED: narrowest group run in complex64 [18] */
     int32_t reserved[5];
 } qtn_config;

@@ -43,6 +43,7 @@ EXPORTS = (
     "qtn_costmodel_free",
 )
 MLP_PARAMS = 5508
+MLP_OUT = 4  # predicted variants: workgroup, streaming, generic, matrix form
 
 
 class qtn_config(ctypes.Structure):

@@ -301,9 +301,10 @@ def _f32(x):
 
 
 class CostModel:
-    """Owning wrapper of a qtn_costmodel (16-64-64-3 perceptron)."""
+    """Owning wrapper of a qtn_costmodel (16-64-64-4 perceptron)."""
 
     n_params = _capi.MLP_PARAMS
+    n_out = _capi.MLP_OUT
 
     def __init__(self, params):
         p, pp = _f32(params)
@@ -335,6 +336,8 @@ class CostModel:
         x, xp = _f32(x)
         n = len(x) // 16
         m, mp = _f64(ms)
+        if len(x) != 16 * n or len(m) != self.n_out * n:
+            raise ValueError(f"expected x [n, 16] and ms [n, {self.n_out}]")
         ws = self.workspace(n)
         hist = np.zeros(epochs, dtype=np.float32)
         check(lib().qtn_costmodel_train(self.h, xp, mp, n, int(epochs), float(lr),
@@ -345,18 +348,22 @@ class CostModel:
     def predict(self, x, stream=None):
         x, xp = _f32(x)
         n = len(x) // 16
+        if len(x) != 16 * n:
+            raise ValueError("expected x [n, 16]")
         ws = self.workspace(n)
-        y = np.zeros(n * 3, dtype=np.float32)
+        y = np.zeros(n * self.n_out, dtype=np.float32)
         check(lib().qtn_costmodel_predict(self.h, xp, n, ctypes.c_void_p(ws.data_ptr()),
                                           ws.numel(), stream_handle(stream),
                                           y.ctypes.data_as(_pf)))
-        return y.reshape(n, 4)
+        return y.reshape(n, self.n_out)
 
     def grad(self, x, t, m, stream=None):
         x, xp = _f32(x)
         t, tp = _f32(t)
         m, mp = _f32(m)
         n = len(x) // 16
+        if len(x) != 16 * n or len(t) != self.n_out * n or len(m) != self.n_out * n:
+            raise ValueError(f"expected x [n, 16], t and m [n, {self.n_out}]")
         ws = self.workspace(n)
         loss = ctypes.c_float()
         g = np.zeros(self.n_params, dtype=np.float32)
@@ -367,6 +374,8 @@ class CostModel:
 
     def adam_step(self, grad, lr, stream=None):
         g, gp = _f32(grad)
+        if len(g) != self.n_params:
+            raise ValueError(f"expected {self.n_params} gradient entries")
         ws = self.workspace(1)
         check(lib().qtn_costmodel_adam_step(self.h, gp, float(lr),
                                             ctypes.c_void_p(ws.data_ptr()), ws.numel(),
@@ -386,7 +395,7 @@ class CostModel:
 
 def qtn_apply_costmodel(net, cm, stream=None):
     """Variant per group from the cost model; returns groups per variant
-    (block, stream, generic)."""
+    (workgroup, streaming, generic, matrix form)."""
     n_groups = qtn_get_plan_stats(net)["n_groups"]
     ws = CostModel.workspace(max(1, n_groups))
     counts = np.zeros(4, dtype=np.int32)

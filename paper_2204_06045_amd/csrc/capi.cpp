@@ -152,7 +152,7 @@ struct Exec {
   bool persistent = false;
   bool dataflow = false;  // persistent: per-task dependencies instead of lockstep
   bool lead_per_cone = false;
-  uint32_t spin_limit = 1u << 26;
+  uint32_t spin_limit = 1u << 22;
 };
 
 }  // namespace
@@ -167,7 +167,7 @@ struct qtn_network {
   int lane_sum_bits = 2;  // streaming: summed bits spread over lanes
   int order_trials = 0;   // >1: best of this many randomized min-fill orders
   int executor = 0;       // 0 streams + per-group launches, 1 persistent lockstep
-  uint32_t spin_limit = 1u << 26;
+  uint32_t spin_limit = 1u << 22;
   int variant = 0;        // 0 auto, 1 generic only, 2 streaming where possible
   std::vector<LightCone> cones;
   std::vector<std::vector<int>> minfill;

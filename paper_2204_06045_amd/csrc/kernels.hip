@@ -685,6 +685,13 @@ __global__ __launch_bounds__(kBlock) void k_persistent(char *__restrict__ data,
 // running blocks, so the earliest unfinished item can always proceed.
 // Results are published with an agent-scope release before the count and
 // observed with an agent-scope acquire after the wait, as in grid_barrier.
+//
+// The bookkeeping runs in one branch at the top of the loop that is uniform
+// per wave (wave 0; lane 0 alone issues the atomics): a lane-divergent region
+// at the end of the loop body would let the compiler rotate it across the
+// back edge, so that the other lanes of wave 0 met the next barrier before
+// lane 0 had taken the next item.  The completion count of the previous item
+// is therefore issued there too, before the next item is taken.
 __global__ __launch_bounds__(kBlock) void k_dataflow(char *__restrict__ data,
                                                      const DevGroup *__restrict__ groups,
                                                      const DevOp *__restrict__ ops,
@@ -698,38 +705,55 @@ __global__ __launch_bounds__(kBlock) void k_dataflow(char *__restrict__ data,
   __shared__ __align__(16) uint32_t s_lane[kStreamMaxOps * 64];
   __shared__ int s_item, s_ok;
   uint32_t *head = ctl, *err = ctl + 2, *done = ctl + 4;
+  const int lane = threadIdx.x & 63;
+  int prev = -1;  // item this block finished last (block-uniform)
   for (;;) {
-    if (threadIdx.x == 0) {
-      s_item = (int)__hip_atomic_fetch_add(head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      s_ok = 1;
-      if (s_item < n_items) {
-        const int d = task_dep[item_task[s_item]];
+    if (threadIdx.x < 64) {
+      if (prev >= 0) {
+        // release this block's results, then count the item done
+        __threadfence();
+        if (lane == 0)
+          __hip_atomic_fetch_add(done + item_task[prev], 1u, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+      }
+      uint32_t got = 0;
+      if (lane == 0)
+        got = __hip_atomic_fetch_add(head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const int i = __builtin_amdgcn_readfirstlane((int)got);
+      int ok = 1;
+      if (i < n_items) {
+        const int d = task_dep[item_task[i]];
         if (d >= 0) {
           const uint32_t need = (uint32_t)task_need[d];
           uint32_t polls = 0;
-          while (__hip_atomic_load(done + d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+          for (;;) {
+            const uint32_t c = __builtin_amdgcn_readfirstlane(
+                __hip_atomic_load(done + d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            if (c >= need) break;
             __builtin_amdgcn_s_sleep(2);
-            if (++polls > spin_limit ||
-                __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
-              __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-              s_ok = 0;
+            const uint32_t e = __builtin_amdgcn_readfirstlane(
+                __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            if (++polls > spin_limit || e != 0u) {
+              if (lane == 0)
+                __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              ok = 0;
               break;
             }
           }
-          __threadfence();
+          __threadfence();  // acquire the predecessor's results
         }
+      }
+      if (lane == 0) {
+        s_item = i;
+        s_ok = ok;
       }
     }
     __syncthreads();
     const int i = s_item, ok = s_ok;
     __syncthreads();
     if (i >= n_items || !ok) break;
-    run_item(items[i], data, groups, ops, stab, uperm, s_lane);
-    // run_item ends with a barrier: every wave's stores are issued
-    if (threadIdx.x == 0) {
-      __threadfence();
-      __hip_atomic_fetch_add(done + item_task[i], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    run_item(items[i], data, groups, ops, stab, uperm, s_lane);  // ends with a barrier
+    prev = i;
   }
 }
 

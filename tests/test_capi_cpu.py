@@ -207,3 +207,21 @@ def test_lightcone_sizes_match_oracle(qtn, orc):
         nv, nt, _ = net.info(eid)
         assert (nv, nt) == orc.lightcone_size(40, inst["edges"], eid, 3)
     net.close()
+
+
+def test_costmodel_host_side_checks(qtn):
+    from paper_2204_06045_amd import _capi
+    assert _capi.MLP_PARAMS == 16 * 64 + 64 + 64 * 64 + 64 + 64 * _capi.MLP_OUT + _capi.MLP_OUT
+    p = np.linspace(-0.1, 0.1, qtn.CostModel.n_params).astype(np.float32)
+    cm = qtn.CostModel(p)
+    assert np.array_equal(cm.params(), p)
+    # shapes are checked before any device work
+    with pytest.raises(ValueError):
+        cm.train(np.zeros((5, 16)), np.zeros((5, 3)), 1, 1e-3)
+    with pytest.raises(ValueError):
+        cm.predict(np.zeros(17))
+    with pytest.raises(ValueError):
+        cm.grad(np.zeros((2, 16)), np.zeros((2, 3)), np.ones((2, 3)))
+    with pytest.raises(ValueError):
+        qtn.CostModel(p[:-1])
+    cm.close()
