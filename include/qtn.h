@@ -220,7 +220,9 @@ int qtn_launch_log(const qtn_network *net, int64_t cap, qtn_launch_rec *out,
 typedef struct qtn_tune_report {
     int32_t n_groups;     /* own-launch groups tuned                        */
     int32_t n_candidates; /* configurations measured                        */
-    double cand_ms[8];    /* summed own-launch group time per configuration */
+    double cand_ms[8];    /* summed own-launch group time per configuration
+                             (the matrix form: over the groups that have
+                             one; 0 when none has)                          */
     double tuned_ms;      /* the same with each group's fastest choice      */
     int32_t picks[8];     /* groups that chose each configuration           */
 } qtn_tune_report;
