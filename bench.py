@@ -370,6 +370,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", type=int, default=1, help="run the autotuner after planning")
+    ap.add_argument("--eager", action="store_true",
+                    help="launch eagerly instead of replaying the captured HIP graph")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 1 GiB device copy (byte-counter calibration)")
     args = ap.parse_args()
@@ -390,7 +392,7 @@ def main():
     log(f"main row: {args.precision} levels={args.levels} streams={args.streams}")
     kcfg = dict(variant=args.variant, lane_sum_bits=args.lane_bits,
                 order_trials=args.order_trials, executor=args.executor,
-                small_width=args.small_width, mixed_width=args.mixed_width)
+                small_width=args.small_width, mixed_width=args.mixed_width, eager=args.eager)
     net, dt, plan_s, last = run_rows(Q, torch, inst, prec, args.levels, args.streams,
                                      args.steps, args.warmup, autotune=bool(args.autotune), **kcfg)
     tune = net.tune_report
@@ -398,19 +400,13 @@ def main():
     stats = net.stats()
     plan_order_trials = args.order_trials
     log(f"  {evals:.2f} evals/s, plan {plan_s:.2f} s")
-    net.close()
-    # kernel roofline: the same plan on one stream, so that each launch's HIP
-    # event pair brackets that kernel alone
-    rnet = Q.Network(inst["n"], inst["edges"], *inst["angles"][0], max_levels=args.levels,
-                     n_streams=1, **kcfg)
-    rnet.plan(prec)
-    if args.autotune:
-        rnet.autotune()
-    rnet.contract()
-    _, _, timing = rnet.contract_timed()
+    # kernel roofline: the same tuned plan, its launches serialized on one
+    # stream so that each launch's HIP event pair brackets that kernel alone
+    net.contract_timed()
+    _, _, timing = net.contract_timed()
     tag = f"n30p4_{args.precision}"
-    roof = roofline_of(rnet.launch_log(), tag)
-    rnet.close()
+    roof = roofline_of(net.launch_log(), tag)
+    net.close()
     log(f"  roofline {roof['kernel']}: {roof['hbm_gbs']:.0f} GB/s, "
         f"{roof['fp_tflops']:.2f} TFLOP/s")
     if args.calibrate_copy:
@@ -476,7 +472,7 @@ def main():
             "precision": args.precision, "max_levels": args.levels,
             "streams": args.streams, "variant": args.variant,
             "lane_sum_bits": args.lane_bits, "order_trials": args.order_trials,
-            "executor": args.executor, "autotune": bool(args.autotune),
+            "executor": args.executor, "autotune": bool(args.autotune), "eager": args.eager,
             "max_width": stats["max_width"],
             "buckets": stats["n_buckets"], "groups": stats["n_groups"],
         },

@@ -180,9 +180,10 @@ typedef struct qtn_timing {
     double flops[QTN_NKERNELS];     /* complex-arithmetic FLOPs per class */
 } qtn_timing;
 
-/* Like qtn_contract, but eager, with a HIP event pair around every launch on
- * its own stream; fills *timing.  Slower than qtn_contract by the event
- * overhead; the kernels are the same. */
+/* Like qtn_contract, but eager, with every launch serialized on one stream
+ * and bracketed by its own HIP event pair, so that each pair times one kernel
+ * alone; fills *timing.  Slower than qtn_contract by the event overhead and
+ * the lost overlap; the kernels and the schedule are the same. */
 int qtn_contract_timed(qtn_network *net, void *d_workspace, size_t bytes,
                        void *hip_stream, double *zz_out, double *energy_out,
                        qtn_timing *timing);
@@ -294,9 +295,10 @@ int qtn_costmodel_grad(const qtn_costmodel *cm, const float *x, const float *t,
 int qtn_costmodel_adam_step(qtn_costmodel *cm, const float *grad, float lr,
                             void *d_workspace, size_t bytes, void *hip_stream);
 
-/* Picks, for every group of a planned network, the variant with the lowest
- * predicted time (inside a workgroup only up to width 16; the matrix form
- * only for complex64 groups that have one) and rebuilds the schedule.
+/* Picks, for every group of a planned network that the width rule gives its
+ * own launch, the kernel with the lowest predicted time (the matrix form only
+ * for complex64 groups that have one) and rebuilds the schedule; groups the
+ * rule places inside a workgroup stay there (counted as QTN_VAR_BLOCK).
  * counts_out [4] or NULL: groups per QTN_VAR_*.  Workspace: the
  * cost-model bytes for as many samples as the network has groups. */
 int qtn_apply_costmodel(qtn_network *net, const qtn_costmodel *cm,

@@ -143,6 +143,47 @@ struct Runtime {
     ws = nullptr;
     device = -1;
   }
+  // The captured graph and the uploaded descriptors belong to one schedule.
+  void forget_schedule() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    ws = nullptr;
+  }
+  // Takes over o's streams, events and pinned buffers (o is left empty), for
+  // a new schedule of the same network: streams are not torn down and
+  // re-created when a plan is re-tuned.
+  void take(Runtime &o) {
+    if (&o == this) return;
+    release();
+    device = o.device;
+    main = o.main;
+    side.swap(o.side);
+    ev_in = o.ev_in;
+    ev_fork = o.ev_fork;
+    ev_join.swap(o.ev_join);
+    pinned = o.pinned;
+    pinned_n = o.pinned_n;
+    persist_blocks = o.persist_blocks;
+    pinned_err = o.pinned_err;
+    exec = o.exec;
+    graph = o.graph;
+    o.exec = nullptr;
+    o.graph = nullptr;
+    o.main = nullptr;
+    o.ev_in = o.ev_fork = nullptr;
+    o.pinned = nullptr;
+    o.pinned_n = 0;
+    o.pinned_err = nullptr;
+    o.persist_blocks = 0;
+    o.ws = nullptr;
+    o.device = -1;
+    forget_schedule();
+  }
+  Runtime() = default;
+  Runtime(const Runtime &) = delete;
+  Runtime &operator=(const Runtime &) = delete;
   ~Runtime() { release(); }
 };
 
@@ -657,18 +698,22 @@ struct Timer {
     double bytes, flops;
   };
   std::vector<Rec> recs;
+  // on_dispatch: the launch attaches the events to its kernel's dispatch
+  // (t0(), t1()) instead of recording them around it on the stream
   int begin(int kind, hipStream_t s, int group = -1, int n_groups = 0, double bytes = 0,
-            double flops = 0) {
+            double flops = 0, bool on_dispatch = false) {
     if (!on) return QTN_OK;
     Rec r{kind, nullptr, nullptr, group, n_groups, bytes, flops};
     QTN_HIP(hipEventCreate(&r.a));
     QTN_HIP(hipEventCreate(&r.b));
-    QTN_HIP(hipEventRecord(r.a, s));
+    if (!on_dispatch) QTN_HIP(hipEventRecord(r.a, s));
     recs.push_back(r);
     return QTN_OK;
   }
-  int end(hipStream_t s) {
-    if (!on) return QTN_OK;
+  hipEvent_t t0() const { return on ? recs.back().a : nullptr; }
+  hipEvent_t t1() const { return on ? recs.back().b : nullptr; }
+  int end(hipStream_t s, bool on_dispatch = false) {
+    if (!on || on_dispatch) return QTN_OK;
     QTN_HIP(hipEventRecord(recs.back().b, s));
     return QTN_OK;
   }
@@ -704,30 +749,33 @@ int enqueue(Exec &X, Timer &tm) {
       b_all += s.bytes[k];
       f_all += s.flops[k];
     }
-    if ((rc = tm.begin(QTN_K_PERSISTENT, rt.main, 0, (int)s.groups.size(), b_all, f_all))) return rc;
+    if ((rc = tm.begin(QTN_K_PERSISTENT, rt.main, 0, (int)s.groups.size(), b_all, f_all, true)))
+      return rc;
     if (X.dataflow)
       QTN_HIP(launch_dataflow(data, groups, ops, stab, uperm, (const int4 *)(ws + s.off_items),
                               (int)s.items.size(), (const int *)(ws + s.off_item_task),
                               (const int *)(ws + s.off_task_dep),
                               (const int *)(ws + s.off_task_need), (uint32_t *)(ws + s.off_ctl),
-                              s.n_ctl, nb, X.spin_limit, rt.main));
+                              s.n_ctl, nb, X.spin_limit, rt.main, tm.t0(), tm.t1()));
     else
       QTN_HIP(launch_persistent(s.prec, data, groups, ops, stab, uperm,
                                 (const int4 *)(ws + s.off_items), (const int *)(ws + s.off_steps),
                                 s.n_steps, (uint32_t *)(ws + s.off_ctl), s.n_ctl, nb, X.spin_limit,
-                                rt.main));
-    if ((rc = tm.end(rt.main))) return rc;
+                                rt.main, tm.t0(), tm.t1()));
+    if ((rc = tm.end(rt.main, true))) return rc;
   } else {
   // leading small segments: one launch for every cone before the fork, or
   // (lead_per_cone) each cone's own one-block launch on its stream
   if (!X.lead_per_cone) {
-    if ((rc = tm.begin(QTN_K_BLOCK, rt.main, 0, (int)s.groups.size(), s.init_bytes, s.init_flops)))
+    if ((rc = tm.begin(QTN_K_BLOCK, rt.main, 0, (int)s.groups.size(), s.init_bytes, s.init_flops,
+                       true)))
       return rc;
     QTN_HIP(launch_block_groups(s.prec, data, groups, ops, stab, uperm, ranges, 0, s.n_cones,
-                                rt.main));
-    if ((rc = tm.end(rt.main))) return rc;
+                                rt.main, tm.t0(), tm.t1()));
+    if ((rc = tm.end(rt.main, true))) return rc;
   }
-  const int K = (int)rt.side.size();
+  // timed runs serialize on one stream, so each event pair brackets one kernel
+  const int K = tm.on ? 1 : (int)rt.side.size();
   bool any = X.lead_per_cone;
   for (auto &tk : s.cone_tasks) any |= !tk.empty();
   if (any) {
@@ -749,21 +797,25 @@ int enqueue(Exec &X, Timer &tm) {
       load[st] += cost[c];
       hipStream_t hs = rt.side[st];
       if (lead) {
-        if ((rc = tm.begin(QTN_K_BLOCK, hs, s.ranges[c].x, s.ranges[c].y - s.ranges[c].x)))
+        if ((rc = tm.begin(QTN_K_BLOCK, hs, s.ranges[c].x, s.ranges[c].y - s.ranges[c].x, 0, 0,
+                           true)))
           return rc;
-        QTN_HIP(launch_block_groups(s.prec, data, groups, ops, stab, uperm, ranges, c, 1, hs));
-        if ((rc = tm.end(hs))) return rc;
+        QTN_HIP(launch_block_groups(s.prec, data, groups, ops, stab, uperm, ranges, c, 1, hs,
+                                    tm.t0(), tm.t1()));
+        if ((rc = tm.end(hs, true))) return rc;
       }
       for (auto &t : s.cone_tasks[c]) {
         const int g0 = t.kind == QTN_K_BLOCK ? s.ranges[t.index].x : t.index;
         const int ng = t.kind == QTN_K_BLOCK ? s.ranges[t.index].y - s.ranges[t.index].x : 1;
-        if ((rc = tm.begin(t.kind, hs, g0, ng, t.bytes, t.flops))) return rc;
+        if ((rc = tm.begin(t.kind, hs, g0, ng, t.bytes, t.flops, true))) return rc;
         if (t.kind == QTN_K_BLOCK)
-          QTN_HIP(launch_block_groups(s.prec, data, groups, ops, stab, uperm, ranges, t.index, 1, hs));
+          QTN_HIP(launch_block_groups(s.prec, data, groups, ops, stab, uperm, ranges, t.index, 1, hs,
+                                      tm.t0(), tm.t1()));
         else
           QTN_HIP(launch_wide_group(s.groups[t.index].prec, s.groups[t.index].cvt != 0, t.variant,
-                                    data, groups, ops, stab, uperm, t.index, t.n_units, hs));
-        if ((rc = tm.end(hs))) return rc;
+                                    data, groups, ops, stab, uperm, t.index, t.n_units, hs,
+                                    tm.t0(), tm.t1()));
+        if ((rc = tm.end(hs, true))) return rc;
       }
     }
     for (int i = 0; i < K; i++) {
@@ -1008,6 +1060,7 @@ int qtn_plan(qtn_network *net, const int32_t *const *orders, int32_t precision,
       net->tune_workspace = mx;
     }
     ex->spin_limit = net->spin_limit;
+    if (net->exec) ex->rt.take(net->exec->rt);
     net->exec = std::move(ex);
     net->planned = true;
     net->version++;
@@ -1176,6 +1229,7 @@ int qtn_autotune(qtn_network *net, void *d_workspace, size_t bytes, void *hip_st
     const int nc = (int)cands.size();
     qtn_network *one[1] = {net};
     // per plan group: measured ms per candidate, own launch and inside a block
+    // (the fastest of the passes)
     struct Meas {
       double wide[8], block[8];
     };
@@ -1183,65 +1237,101 @@ int qtn_autotune(qtn_network *net, void *d_workspace, size_t bytes, void *hip_st
     qtn_tune_report rep;
     std::memset(&rep, 0, sizeof rep);
     rep.n_candidates = nc;
-    for (int ci = 0; ci < nc; ci++) {
-      Exec ex;
-      int rc = build_schedule(one, 1, &ex.sched, &cands[ci], kTuneSingleWidth);
-      if (rc) return rc;
-      Timer tm;
-      tm.on = true;
-      std::vector<double> res;
-      rc = run_exec(ex, {net}, d_workspace, bytes, hip_stream, 1, true, tm, res);
-      if (rc) return rc;
-      // the same groups again, each alone in one workgroup
-      Timer tb;
-      tb.on = true;
-      char *ws = (char *)d_workspace;
-      const Schedule &s = ex.sched;
-      for (size_t i = 0; i < s.singles.size(); i++) {
-        if ((rc = tb.begin(QTN_K_BLOCK, ex.rt.main, s.singles[i], 1))) return rc;
-        QTN_HIP(launch_block_groups(s.prec, ws + s.off_data, (const DevGroup *)(ws + s.off_groups),
-                                    (const DevOp *)(ws + s.off_ops),
-                                    (const int32_t *)(ws + s.off_stab),
-                                    (const uint8_t *)(ws + s.off_uperm),
-                                    (const int2 *)(ws + s.off_ranges), s.singles_range0 + (int)i, 1,
-                                    ex.rt.main));
-        if ((rc = tb.end(ex.rt.main))) return rc;
+    // one runtime for every candidate: the network's own streams
+    Exec ex;
+    ex.rt.take(net->exec->rt);
+    auto give_back = [&]() { net->exec->rt.take(ex.rt); };
+    constexpr int kPasses = 2;
+    for (int pass = 0; pass < kPasses; pass++)
+      for (int ci = 0; ci < nc; ci++) {
+        int rc = build_schedule(one, 1, &ex.sched, &cands[ci], kTuneSingleWidth);
+        if (rc) {
+          give_back();
+          return rc;
+        }
+        ex.rt.forget_schedule();
+        Timer tm;
+        tm.on = true;
+        std::vector<double> res;
+        rc = run_exec(ex, {net}, d_workspace, bytes, hip_stream, 1, true, tm, res);
+        if (rc) {
+          give_back();
+          return rc;
+        }
+        // the same groups again, each alone in one workgroup
+        Timer tb;
+        tb.on = true;
+        char *ws = (char *)d_workspace;
+        const Schedule &s = ex.sched;
+        for (size_t i = 0; i < s.singles.size(); i++) {
+          if ((rc = tb.begin(QTN_K_BLOCK, ex.rt.main, s.singles[i], 1, 0, 0, true))) {
+            give_back();
+            return rc;
+          }
+          hipError_t he = launch_block_groups(
+              s.prec, ws + s.off_data, (const DevGroup *)(ws + s.off_groups),
+              (const DevOp *)(ws + s.off_ops), (const int32_t *)(ws + s.off_stab),
+              (const uint8_t *)(ws + s.off_uperm), (const int2 *)(ws + s.off_ranges),
+              s.singles_range0 + (int)i, 1, ex.rt.main, tb.t0(), tb.t1());
+          if (he == hipSuccess) rc = tb.end(ex.rt.main, true);
+          if (he != hipSuccess || rc) {
+            give_back();
+            return he != hipSuccess ? set_err(QTN_EDEVICE, hipGetErrorString(he)) : rc;
+          }
+        }
+        hipError_t he = hipStreamSynchronize(ex.rt.main);
+        if (he != hipSuccess) {
+          give_back();
+          return set_err(QTN_EDEVICE, std::string("autotune: ") + hipGetErrorString(he));
+        }
+        auto key_of = [&](int g) { return std::make_pair(s.group_cone[g], s.group_index[g]); };
+        // a candidate only counts for the groups that ran its kernel
+        auto ran = [&](int g) {
+          return cands[ci].variant != 3 || s.groups[g].variant == kVarMfma;
+        };
+        auto slot = [&](int g) -> Meas & {
+          return meas.emplace(key_of(g), Meas{{-1, -1, -1, -1, -1, -1, -1, -1},
+                                              {-1, -1, -1, -1, -1, -1, -1, -1}})
+              .first->second;
+        };
+        auto keep_min = [](double &dst, double v) { dst = dst < 0 ? v : std::min(dst, v); };
+        for (auto &r : tm.recs) {
+          if (r.kind != QTN_K_WIDE || !ran(r.group)) continue;
+          float ms = 0;
+          (void)hipEventElapsedTime(&ms, r.a, r.b);
+          keep_min(slot(r.group).wide[ci], ms);
+        }
+        for (auto &r : tb.recs) {
+          if (!ran(r.group)) continue;
+          float ms = 0;
+          (void)hipEventElapsedTime(&ms, r.a, r.b);
+          keep_min(slot(r.group).block[ci], ms);
+        }
       }
-      QTN_HIP(hipStreamSynchronize(ex.rt.main));
-      auto key_of = [&](int g) { return std::make_pair(s.group_cone[g], s.group_index[g]); };
-      // a candidate only counts for the groups that ran its kernel
-      auto ran = [&](int g) {
-        return cands[ci].variant != 3 || s.groups[g].variant == kVarMfma;
-      };
-      for (auto &r : tm.recs) {
-        if (r.kind != QTN_K_WIDE || !ran(r.group)) continue;
-        float ms = 0;
-        QTN_HIP(hipEventElapsedTime(&ms, r.a, r.b));
-        Meas &m = meas.emplace(key_of(r.group), Meas{{-1, -1, -1, -1, -1, -1, -1, -1},
-                                                     {-1, -1, -1, -1, -1, -1, -1, -1}}).first->second;
-        m.wide[ci] = ms;
-        rep.cand_ms[ci] += ms;
-      }
-      for (auto &r : tb.recs) {
-        if (!ran(r.group)) continue;
-        float ms = 0;
-        QTN_HIP(hipEventElapsedTime(&ms, r.a, r.b));
-        Meas &m = meas.emplace(key_of(r.group), Meas{{-1, -1, -1, -1, -1, -1, -1, -1},
-                                                     {-1, -1, -1, -1, -1, -1, -1, -1}}).first->second;
-        m.block[ci] = ms;
-      }
-    }
+    for (auto &kv : meas)
+      for (int ci = 0; ci < nc; ci++)
+        if (kv.second.wide[ci] > 0) rep.cand_ms[ci] += kv.second.wide[ci];
     // per group: the fastest candidate for where the width rule places it;
-    // every group's timings go to the tuning log
+    // the width rule's own configuration is kept unless another is faster by
+    // more than the tolerance (near-ties are timing noise and would make the
+    // tuned schedule differ from run to run).  Every group's timings go to
+    // the tuning log.
+    constexpr double kSwitchGain = 0.97;
     net->tune_log.clear();
     for (auto &kv : meas) {
       ConePlan &pl = net->plans[kv.first.first];
       Group &G = pl.groups[kv.first.second];
       const Meas &m = kv.second;
       const double *t = G.small ? m.block : m.wide;
+      const int rls = std::min(G.L - 1, net->lane_sum_bits), sl = G.L - 1 - rls;
+      const bool rule_stream = (int)G.ops.size() <= kStreamMaxOps && sl <= kStreamMaxSerial &&
+                               sl >= 2 && net->variant != 1;
       int best = -1;
       for (int ci = 0; ci < nc; ci++)
-        if (t[ci] >= 0 && (best < 0 || t[ci] < t[best])) best = ci;
+        if (cands[ci].variant == (rule_stream ? 2 : 1) && (rule_stream ? cands[ci].rls == rls : true))
+          if (t[ci] >= 0) best = ci;
+      for (int ci = 0; ci < nc; ci++)
+        if (t[ci] >= 0 && (best < 0 || t[ci] < kSwitchGain * t[best])) best = ci;
       if (best >= 0) {
         G.pick_variant = (int8_t)cands[best].variant;
         G.pick_rls = (int8_t)cands[best].rls;
@@ -1267,16 +1357,20 @@ int qtn_autotune(qtn_network *net, void *d_workspace, size_t bytes, void *hip_st
       tr.ms[QTN_VAR_MFMA] = ms_mfma;
       net->tune_log.push_back(tr);
     }
-    // the tuned schedule replaces the current one
-    auto ex = std::make_unique<Exec>();
-    int rc = build_schedule(one, 1, &ex->sched);
-    if (rc) return rc;
-    ex->persistent = net->exec->persistent;
-    ex->dataflow = net->exec->dataflow;
-    ex->lead_per_cone = net->exec->lead_per_cone;
-    ex->spin_limit = net->exec->spin_limit;
+    // the tuned schedule replaces the current one, on the same streams
+    auto tuned = std::make_unique<Exec>();
+    int rc = build_schedule(one, 1, &tuned->sched);
+    if (rc) {
+      give_back();
+      return rc;
+    }
+    tuned->persistent = net->exec->persistent;
+    tuned->dataflow = net->exec->dataflow;
+    tuned->lead_per_cone = net->exec->lead_per_cone;
+    tuned->spin_limit = net->exec->spin_limit;
+    tuned->rt.take(ex.rt);
     drop_batches_with(net);
-    net->exec = std::move(ex);
+    net->exec = std::move(tuned);
     net->version++;
     if (report) *report = rep;
     return QTN_OK;
@@ -1581,25 +1675,29 @@ int qtn_apply_costmodel(qtn_network *net, const qtn_costmodel *cm, void *d_ws, s
     for (int64_t i = 0; i < n; i++) {
       Group &G = *gs[i];
       const float *p = &y[i * kMlpOut];
-      // inside a workgroup only where that was ever measured (width <= 16);
-      // the matrix form only where the group has one
+      // placement stays with the width rule: a group's time inside a
+      // workgroup segment is not the time of the same group alone in a
+      // one-workgroup launch, which is what was measured.  Groups that get
+      // their own launch take the kernel with the lowest predicted time, the
+      // matrix form only where the group has one.
+      G.pick_place = -1;
+      if (G.small) {
+        G.pick_variant = -1;
+        G.pick_rls = -1;
+        counts[QTN_VAR_BLOCK]++;
+        continue;
+      }
       int best = p[QTN_VAR_STREAM] <= p[QTN_VAR_GENERIC] ? QTN_VAR_STREAM : QTN_VAR_GENERIC;
       if (G.prec == 1 && p[QTN_VAR_MFMA] < p[best] && gemm_shape(G, *gp[i], nullptr))
         best = QTN_VAR_MFMA;
-      if (G.w <= 16 && p[QTN_VAR_BLOCK] < p[best]) best = QTN_VAR_BLOCK;
       counts[best]++;
-      G.pick_place = best == QTN_VAR_BLOCK ? 0 : 1;
-      if (best == QTN_VAR_BLOCK) {
-        G.pick_variant = -1;
-        G.pick_rls = -1;
-      } else {
-        G.pick_variant = best == QTN_VAR_STREAM ? 2 : (best == QTN_VAR_MFMA ? 3 : 1);
-        G.pick_rls = 2;
-      }
+      G.pick_variant = best == QTN_VAR_STREAM ? 2 : (best == QTN_VAR_MFMA ? 3 : 1);
+      G.pick_rls = 2;
     }
     qtn_network *one[1] = {net};
     auto ex = std::make_unique<Exec>();
     if ((rc = build_schedule(one, 1, &ex->sched))) return rc;
+    ex->rt.take(net->exec->rt);
     ex->persistent = net->exec->persistent;
     ex->dataflow = net->exec->dataflow;
     ex->lead_per_cone = net->exec->lead_per_cone;

@@ -29,6 +29,7 @@
 // Matrix form (kVarMfma, complex64).  A group whose operands reduce to two
 // factors over the summed indices is a batched complex matrix product; it
 // runs as three real FP32 products on the matrix cores (3M).
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -847,6 +848,23 @@ int wide_blocks(uint32_t n_units) {
   return (int)(b ? b : 1);
 }
 
+// Launch with optional start/stop events attached to the dispatch itself:
+// they time the kernel alone, without queueing or event-packet overhead.
+#define QTN_LAUNCH(t0, t1, K, grid, block, s, ...)                       \
+  do {                                                                  \
+    if (t0)                                                             \
+      hipExtLaunchKernelGGL(K, grid, block, 0, s, t0, t1, 0, __VA_ARGS__); \
+    else                                                                \
+      hipLaunchKernelGGL(K, grid, block, 0, s, __VA_ARGS__);            \
+  } while (0)
+
+// Nothing to launch: the timing events still complete (zero duration).
+inline hipError_t no_launch(hipEvent_t t0, hipEvent_t t1, hipStream_t s) {
+  if (!t0) return hipSuccess;
+  hipError_t e = hipEventRecord(t0, s);
+  return e == hipSuccess ? hipEventRecord(t1, s) : e;
+}
+
 hipError_t launch_fill(int prec, void *data, const double *angles, const FillDesc *fills,
                        int n_nets, hipStream_t s) {
   (void)prec;
@@ -856,62 +874,66 @@ hipError_t launch_fill(int prec, void *data, const double *angles, const FillDes
 
 hipError_t launch_block_groups(int prec, void *data, const DevGroup *groups, const DevOp *ops,
                                const int32_t *stab, const uint8_t *uperm, const int2 *ranges,
-                               int range_base, int n_blocks, hipStream_t s) {
+                               int range_base, int n_blocks, hipStream_t s, hipEvent_t t0,
+                               hipEvent_t t1) {
   (void)prec;
-  if (n_blocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_block_groups, dim3(n_blocks), dim3(kBlock), 0, s, (char *)data, groups,
-                     ops, stab, uperm, ranges, range_base);
+  if (n_blocks <= 0) return no_launch(t0, t1, s);
+  QTN_LAUNCH(t0, t1, k_block_groups, dim3(n_blocks), dim3(kBlock), s, (char *)data, groups, ops,
+             stab, uperm, ranges, range_base);
   return hipGetLastError();
 }
 
 template <class T, bool CVT>
 void launch_wide_t(int variant, int nb, char *d, const DevGroup *groups, const DevOp *ops,
-                   const int32_t *stab, const uint8_t *uperm, int group, hipStream_t s) {
+                   const int32_t *stab, const uint8_t *uperm, int group, hipStream_t s,
+                   hipEvent_t t0, hipEvent_t t1) {
   if (variant == kVarStream)
-    hipLaunchKernelGGL((k_wide_stream<T, CVT>), dim3(nb), dim3(kBlock), 0, s, d, groups, ops, stab,
-                       uperm, group);
+    QTN_LAUNCH(t0, t1, (k_wide_stream<T, CVT>), dim3(nb), dim3(kBlock), s, d, groups, ops, stab,
+               uperm, group);
   else
-    hipLaunchKernelGGL((k_wide_generic<T, CVT>), dim3(nb), dim3(kBlock), 0, s, d, groups, ops,
-                       stab, uperm, group);
+    QTN_LAUNCH(t0, t1, (k_wide_generic<T, CVT>), dim3(nb), dim3(kBlock), s, d, groups, ops, stab,
+               uperm, group);
 }
 
 hipError_t launch_wide_group(int prec, bool cvt, int variant, void *data, const DevGroup *groups,
                              const DevOp *ops, const int32_t *stab, const uint8_t *uperm,
-                             int group, uint32_t n_units, hipStream_t s) {
+                             int group, uint32_t n_units, hipStream_t s, hipEvent_t t0,
+                             hipEvent_t t1) {
   const int nb = wide_blocks(n_units);
   char *d = (char *)data;
   if (variant == kVarMfma) {
     if (prec != kPrecC64) return hipErrorInvalidValue;  // complex64 arithmetic only
     if (cvt)
-      hipLaunchKernelGGL(k_wide_mfma<true>, dim3(nb), dim3(kBlock), 0, s, d, groups, ops, uperm,
-                         group);
+      QTN_LAUNCH(t0, t1, k_wide_mfma<true>, dim3(nb), dim3(kBlock), s, d, groups, ops, uperm,
+                 group);
     else
-      hipLaunchKernelGGL(k_wide_mfma<false>, dim3(nb), dim3(kBlock), 0, s, d, groups, ops, uperm,
-                         group);
+      QTN_LAUNCH(t0, t1, k_wide_mfma<false>, dim3(nb), dim3(kBlock), s, d, groups, ops, uperm,
+                 group);
     return hipGetLastError();
   }
   if (prec == kPrecC128 && !cvt)
-    launch_wide_t<double2, false>(variant, nb, d, groups, ops, stab, uperm, group, s);
+    launch_wide_t<double2, false>(variant, nb, d, groups, ops, stab, uperm, group, s, t0, t1);
   else if (prec == kPrecC128)
-    launch_wide_t<double2, true>(variant, nb, d, groups, ops, stab, uperm, group, s);
+    launch_wide_t<double2, true>(variant, nb, d, groups, ops, stab, uperm, group, s, t0, t1);
   else if (!cvt)
-    launch_wide_t<float2, false>(variant, nb, d, groups, ops, stab, uperm, group, s);
+    launch_wide_t<float2, false>(variant, nb, d, groups, ops, stab, uperm, group, s, t0, t1);
   else
-    launch_wide_t<float2, true>(variant, nb, d, groups, ops, stab, uperm, group, s);
+    launch_wide_t<float2, true>(variant, nb, d, groups, ops, stab, uperm, group, s, t0, t1);
   return hipGetLastError();
 }
 
 hipError_t launch_persistent(int prec, void *data, const DevGroup *groups, const DevOp *ops,
                              const int32_t *stab, const uint8_t *uperm, const int4 *items,
                              const int *step_begin, int n_steps, uint32_t *ctl, int n_ctl,
-                             int n_blocks, uint32_t spin_limit, hipStream_t s) {
+                             int n_blocks, uint32_t spin_limit, hipStream_t s, hipEvent_t t0,
+                             hipEvent_t t1) {
   (void)prec;
   hipLaunchKernelGGL(k_reset, dim3(1), dim3(256), 0, s, ctl, n_ctl);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (n_steps <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_persistent, dim3(n_blocks), dim3(kBlock), 0, s, (char *)data, groups, ops,
-                     stab, uperm, items, step_begin, n_steps, ctl, spin_limit);
+  if (n_steps <= 0) return no_launch(t0, t1, s);
+  QTN_LAUNCH(t0, t1, k_persistent, dim3(n_blocks), dim3(kBlock), s, (char *)data, groups, ops,
+             stab, uperm, items, step_begin, n_steps, ctl, spin_limit);
   return hipGetLastError();
 }
 
@@ -919,13 +941,13 @@ hipError_t launch_dataflow(void *data, const DevGroup *groups, const DevOp *ops,
                            const int32_t *stab, const uint8_t *uperm, const int4 *items,
                            int n_items, const int *item_task, const int *task_dep,
                            const int *task_need, uint32_t *ctl, int n_ctl, int n_blocks,
-                           uint32_t spin_limit, hipStream_t s) {
+                           uint32_t spin_limit, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
   hipLaunchKernelGGL(k_reset, dim3(1), dim3(256), 0, s, ctl, n_ctl);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (n_items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_dataflow, dim3(n_blocks), dim3(kBlock), 0, s, (char *)data, groups, ops,
-                     stab, uperm, items, n_items, item_task, task_dep, task_need, ctl, spin_limit);
+  if (n_items <= 0) return no_launch(t0, t1, s);
+  QTN_LAUNCH(t0, t1, k_dataflow, dim3(n_blocks), dim3(kBlock), s, (char *)data, groups, ops, stab,
+             uperm, items, n_items, item_task, task_dep, task_need, ctl, spin_limit);
   return hipGetLastError();
 }
 

@@ -9,6 +9,9 @@
 
 namespace qtn {
 
+// Launchers taking (t0, t1): when t0 is not null, the two events are attached
+// to the main kernel's dispatch and time that kernel alone.
+
 enum Precision : int { kPrecC128 = 0, kPrecC64 = 1, kPrecMixed = 2 };
 
 // One block per network: fills that network's gate table from its angles.
@@ -28,14 +31,16 @@ hipError_t launch_fill(int prec, void *data, const double *angles,
 hipError_t launch_block_groups(int prec, void *data, const DevGroup *groups,
                                const DevOp *ops, const int32_t *stab,
                                const uint8_t *uperm, const int2 *ranges,
-                               int range_base, int n_blocks, hipStream_t s);
+                               int range_base, int n_blocks, hipStream_t s,
+                               hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 
 // One group over the whole grid, with the kernel of its mapping variant, in
 // precision prec; cvt: some operand is stored in the other precision.
 hipError_t launch_wide_group(int prec, bool cvt, int variant, void *data,
                              const DevGroup *groups, const DevOp *ops,
                              const int32_t *stab, const uint8_t *uperm, int group,
-                             uint32_t n_units, hipStream_t s);
+                             uint32_t n_units, hipStream_t s, hipEvent_t t0 = nullptr,
+                             hipEvent_t t1 = nullptr);
 
 // Clears the control words, then runs every light cone's task list in
 // lockstep inside one persistent launch of n_blocks resident blocks.
@@ -47,7 +52,8 @@ hipError_t launch_persistent(int prec, void *data, const DevGroup *groups,
                              const DevOp *ops, const int32_t *stab,
                              const uint8_t *uperm, const int4 *items, const int *step_begin, int n_steps,
                              uint32_t *ctl, int n_ctl, int n_blocks,
-                             uint32_t spin_limit, hipStream_t s);
+                             uint32_t spin_limit, hipStream_t s, hipEvent_t t0 = nullptr,
+                             hipEvent_t t1 = nullptr);
 
 // Clears the control words, then runs the work items in order inside one
 // persistent launch: blocks take items from an atomic counter; an item of
@@ -59,7 +65,8 @@ hipError_t launch_dataflow(void *data, const DevGroup *groups, const DevOp *ops,
                            const int32_t *stab, const uint8_t *uperm, const int4 *items,
                            int n_items, const int *item_task, const int *task_dep,
                            const int *task_need, uint32_t *ctl, int n_ctl, int n_blocks,
-                           uint32_t spin_limit, hipStream_t s);
+                           uint32_t spin_limit, hipStream_t s, hipEvent_t t0 = nullptr,
+                           hipEvent_t t1 = nullptr);
 
 // Resident blocks of the persistent kernel on n_cu compute units (0 on error).
 int persistent_blocks(int prec, int n_cu);
