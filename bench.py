@@ -38,7 +38,30 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_rows(Q, torch, inst, prec, levels, streams, steps, warmup, autotune=False, **cfg):
+def load_tune(net, path):
+    """Apply stored kernel choices (written by --save-tune on the same plan);
+    None if the file is missing or was made for a different plan."""
+    if not path or not os.path.exists(path):
+        return None
+    with open(path) as f:
+        stored = json.load(f)
+    try:
+        net.set_tune_picks(stored["picks"])
+    except Exception as e:  # a different plan: tune afresh
+        log(f"  stored tuning not applied ({e})")
+        return None
+    return {"source": os.path.relpath(path, ROOT), "n_groups": len(stored["picks"]),
+            "measured_on": stored.get("measured_on")}
+
+
+def save_tune(net, path, report, meta):
+    with open(path, "w") as f:
+        json.dump({**meta, "measured_on": "MI355X (gfx950)", "report": report,
+                   "picks": [list(p) for p in net.tune_picks()]}, f)
+
+
+def run_rows(Q, torch, inst, prec, levels, streams, steps, warmup, autotune=False,
+             tune_file=None, save_tune_file=None, **cfg):
     n, edges = inst["n"], inst["edges"]
     angles = inst["angles"]
     net = Q.Network(n, edges, *angles[0], max_levels=levels, n_streams=streams, **cfg)
@@ -49,7 +72,13 @@ def run_rows(Q, torch, inst, prec, levels, streams, steps, warmup, autotune=Fals
     net.tune_report = None
     if autotune:
         t0 = time.perf_counter()
-        net.tune_report = net.autotune(ws)
+        net.tune_report = load_tune(net, tune_file)
+        if net.tune_report is None:
+            net.tune_report = net.autotune(ws)
+            if save_tune_file:
+                save_tune(net, save_tune_file, dict(net.tune_report),
+                          {"n": n, "edges": len(edges), "precision": prec, "levels": levels,
+                           "config": {k: v for k, v in cfg.items() if k != "eager"}})
         net.tune_report["seconds"] = time.perf_counter() - t0
     for i in range(warmup):
         net.set_angles(*angles[i % len(angles)])
@@ -369,7 +398,13 @@ def main():
     ap.add_argument("--variants", type=int, default=1, help="also time the other rows")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--autotune", type=int, default=1, help="run the autotuner after planning")
+    ap.add_argument("--autotune", type=int, default=1,
+                    help="tune the kernel choice per group after planning (stored choices "
+                         "from --tune-file when they match the plan, else the autotuner)")
+    ap.add_argument("--tune-file", default=None,
+                    help="stored kernel choices to apply (default: profiles/tune_n30p4_<prec>.json)")
+    ap.add_argument("--retune", action="store_true", help="ignore stored choices, measure afresh")
+    ap.add_argument("--save-tune", default=None, help="write the autotuner's choices here")
     ap.add_argument("--eager", action="store_true",
                     help="launch eagerly instead of replaying the captured HIP graph")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -393,8 +428,11 @@ def main():
     kcfg = dict(variant=args.variant, lane_sum_bits=args.lane_bits,
                 order_trials=args.order_trials, executor=args.executor,
                 small_width=args.small_width, mixed_width=args.mixed_width, eager=args.eager)
+    tune_file = None if args.retune else (
+        args.tune_file or os.path.join(ROOT, "profiles", f"tune_n30p4_{args.precision}.json"))
     net, dt, plan_s, last = run_rows(Q, torch, inst, prec, args.levels, args.streams,
-                                     args.steps, args.warmup, autotune=bool(args.autotune), **kcfg)
+                                     args.steps, args.warmup, autotune=bool(args.autotune),
+                                     tune_file=tune_file, save_tune_file=args.save_tune, **kcfg)
     tune = net.tune_report
     evals = args.steps / dt
     stats = net.stats()

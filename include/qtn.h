@@ -252,6 +252,32 @@ typedef struct qtn_tune_rec {
 int qtn_tune_log(const qtn_network *net, int64_t cap, qtn_tune_rec *out,
                  int64_t *n_out);
 
+/* One group's kernel choice, as set by qtn_autotune or qtn_apply_costmodel
+ * (-1 fields: the width rule decides).  `shape` fingerprints the group (width,
+ * summed indices and operand index sets) so that a stored choice is only ever
+ * applied to the same group of the same plan. */
+typedef struct qtn_tune_pick {
+    int32_t edge;     /* light cone */
+    int32_t group;    /* group index inside the light cone's plan */
+    int8_t place;     /* 0 inside a workgroup segment, 1 own launch, -1 rule */
+    int8_t variant;   /* 1 generic, 2 streaming, 3 matrix form, -1 rule */
+    int8_t rls;       /* streaming: lane-summed bits, -1 rule */
+    int8_t pad;
+    uint32_t shape;
+} qtn_tune_pick;
+
+/* Copies up to `cap` picks (one per group, all light cones in order) into
+ * `out` and stores the number of groups in *n_out.  Lets a tuning result be
+ * stored and reapplied to a later plan of the same network, order and
+ * precision without measuring again. */
+int qtn_tune_picks(const qtn_network *net, int64_t cap, qtn_tune_pick *out,
+                   int64_t *n_out);
+
+/* Applies stored picks and rebuilds the schedule.  Every pick must name an
+ * existing group whose shape matches; otherwise nothing is applied and the
+ * call fails with QTN_EINVAL. */
+int qtn_set_tune_picks(qtn_network *net, const qtn_tune_pick *picks, int64_t n);
+
 /*
  * Learned cost model (16 -> 64 -> 64 -> 4 perceptron, ReLU hidden units):
  * from a group's 16 shape features (those of qtn_tune_rec) it predicts the

@@ -36,7 +36,7 @@ EXPORTS = (
     "qtn_set_angles", "qtn_contract", "qtn_contract_batch",
     "qtn_batch_workspace", "qtn_contract_timed", "qtn_get_plan_stats",
     "qtn_bucket_widths", "qtn_network_free", "qtn_last_error", "qtn_launch_log",
-    "qtn_plan_order", "qtn_autotune", "qtn_tune_log",
+    "qtn_plan_order", "qtn_autotune", "qtn_tune_log", "qtn_tune_picks", "qtn_set_tune_picks",
     "qtn_costmodel_create", "qtn_costmodel_params", "qtn_costmodel_normalization",
     "qtn_costmodel_workspace", "qtn_costmodel_train", "qtn_costmodel_predict",
     "qtn_costmodel_grad", "qtn_costmodel_adam_step", "qtn_apply_costmodel",
@@ -75,6 +75,12 @@ class qtn_tune_report(ctypes.Structure):
     _fields_ = [("n_groups", ctypes.c_int32), ("n_candidates", ctypes.c_int32),
                 ("cand_ms", ctypes.c_double * 8), ("tuned_ms", ctypes.c_double),
                 ("picks", ctypes.c_int32 * 8)]
+
+
+class qtn_tune_pick(ctypes.Structure):
+    _fields_ = [("edge", ctypes.c_int32), ("group", ctypes.c_int32), ("place", ctypes.c_int8),
+                ("variant", ctypes.c_int8), ("rls", ctypes.c_int8), ("pad", ctypes.c_int8),
+                ("shape", ctypes.c_uint32)]
 
 
 class qtn_tune_rec(ctypes.Structure):
@@ -131,6 +137,8 @@ def lib():
         L.qtn_plan_order.argtypes = [P, i64, pi32]
         L.qtn_autotune.argtypes = [P, P, ctypes.c_size_t, P, ctypes.POINTER(qtn_tune_report)]
         L.qtn_tune_log.argtypes = [P, i64, ctypes.POINTER(qtn_tune_rec), ctypes.POINTER(i64)]
+        L.qtn_tune_picks.argtypes = [P, i64, ctypes.POINTER(qtn_tune_pick), ctypes.POINTER(i64)]
+        L.qtn_set_tune_picks.argtypes = [P, ctypes.POINTER(qtn_tune_pick), i64]
         pf = ctypes.POINTER(ctypes.c_float)
         sz = ctypes.c_size_t
         L.qtn_costmodel_create.argtypes = [pf, ctypes.POINTER(P)]

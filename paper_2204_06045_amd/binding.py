@@ -14,7 +14,7 @@ import torch
 
 from . import _capi
 from ._capi import (QTN_C128, QTN_C64, QTN_MIXED, QtnError, check, lib, qtn_config,
-                    qtn_launch_rec, qtn_plan_stats, qtn_timing, qtn_tune_rec,
+                    qtn_launch_rec, qtn_plan_stats, qtn_timing, qtn_tune_pick, qtn_tune_rec,
                     qtn_tune_report)
 
 __all__ = [
@@ -23,6 +23,7 @@ __all__ = [
     "qtn_contract_timed", "qtn_contract_batch", "qtn_batch_workspace",
     "qtn_get_plan_stats", "qtn_bucket_widths", "qtn_network_free",
     "qtn_last_error", "qtn_launch_log", "qtn_plan_order", "qtn_autotune", "qtn_tune_log",
+    "qtn_tune_picks", "qtn_set_tune_picks",
     "Network", "CostModel", "qtn_apply_costmodel", "workspace", "stream_handle",
 ]
 
@@ -207,6 +208,23 @@ def qtn_autotune(net, ws, stream=None):
             "picks": list(r.picks[:nc])}
 
 
+def qtn_tune_picks(net):
+    """Kernel choice per group: list of (edge, group, place, variant, rls, shape)."""
+    n = ctypes.c_int64()
+    check(lib().qtn_tune_picks(net, 0, None, ctypes.byref(n)))
+    arr = (qtn_tune_pick * max(1, n.value))()
+    check(lib().qtn_tune_picks(net, n.value, arr, ctypes.byref(n)))
+    return [(r.edge, r.group, r.place, r.variant, r.rls, r.shape) for r in arr[:n.value]]
+
+
+def qtn_set_tune_picks(net, picks):
+    """Apply picks as returned by qtn_tune_picks."""
+    arr = (qtn_tune_pick * max(1, len(picks)))()
+    for k, (e, g, pl, v, r, sh) in enumerate(picks):
+        arr[k] = qtn_tune_pick(int(e), int(g), int(pl), int(v), int(r), 0, int(sh))
+    check(lib().qtn_set_tune_picks(net, arr, len(picks)))
+
+
 def qtn_tune_log(net):
     """(features [n, 16] float32, ms [n, 4] float64) from the last autotune."""
     n = ctypes.c_int64()
@@ -272,6 +290,12 @@ class Network:
 
     def tune_log(self):
         return qtn_tune_log(self.h)
+
+    def tune_picks(self):
+        return qtn_tune_picks(self.h)
+
+    def set_tune_picks(self, picks):
+        qtn_set_tune_picks(self.h, picks)
 
     def plan_order(self, edge):
         return qtn_plan_order(self.h, edge)

@@ -1379,6 +1379,85 @@ int qtn_autotune(qtn_network *net, void *d_workspace, size_t bytes, void *hip_st
   }
 }
 
+// FNV-1a over a group's width, summed count and operand index sets.
+static uint32_t group_shape(const Group &G) {
+  uint32_t h = 2166136261u;
+  auto mix = [&](uint32_t v) {
+    for (int k = 0; k < 4; k++) {
+      h ^= (v >> (8 * k)) & 0xFFu;
+      h *= 16777619u;
+    }
+  };
+  mix((uint32_t)G.w);
+  mix((uint32_t)G.L);
+  mix((uint32_t)G.ops.size());
+  for (const Operand &o : G.ops) {
+    mix(o.mask);
+    mix((uint32_t)o.level);
+  }
+  return h;
+}
+
+int qtn_tune_picks(const qtn_network *net, int64_t cap, qtn_tune_pick *out, int64_t *n_out) {
+  if (!net || !n_out || (cap > 0 && !out)) return set_err(QTN_EINVAL, "NULL argument");
+  if (!net->planned) return set_err(QTN_ESTATE, "qtn_plan has not been called");
+  int64_t n = 0;
+  for (size_t e = 0; e < net->plans.size(); e++)
+    for (size_t g = 0; g < net->plans[e].groups.size(); g++, n++) {
+      if (n >= cap) continue;
+      const Group &G = net->plans[e].groups[g];
+      qtn_tune_pick p;
+      std::memset(&p, 0, sizeof p);
+      p.edge = (int32_t)e;
+      p.group = (int32_t)g;
+      p.place = G.pick_place;
+      p.variant = G.pick_variant;
+      p.rls = G.pick_rls;
+      p.shape = group_shape(G);
+      out[n] = p;
+    }
+  *n_out = n;
+  return QTN_OK;
+}
+
+int qtn_set_tune_picks(qtn_network *net, const qtn_tune_pick *picks, int64_t n) {
+  try {
+    if (!net || (n > 0 && !picks)) return set_err(QTN_EINVAL, "NULL argument");
+    if (!net->planned) return set_err(QTN_ESTATE, "qtn_plan has not been called");
+    for (int64_t i = 0; i < n; i++) {
+      const qtn_tune_pick &p = picks[i];
+      if (p.edge < 0 || p.edge >= (int32_t)net->plans.size() || p.group < 0 ||
+          p.group >= (int32_t)net->plans[p.edge].groups.size())
+        return set_err(QTN_EINVAL, "pick " + std::to_string(i) + " names no group of this plan");
+      if (group_shape(net->plans[p.edge].groups[p.group]) != p.shape)
+        return set_err(QTN_EINVAL, "pick " + std::to_string(i) + " is for a different group");
+      if (p.place < -1 || p.place > 1 || p.variant < -1 || p.variant > 3 || p.rls < -1 || p.rls > 5)
+        return set_err(QTN_EINVAL, "pick " + std::to_string(i) + " is out of range");
+    }
+    for (int64_t i = 0; i < n; i++) {
+      Group &G = net->plans[picks[i].edge].groups[picks[i].group];
+      G.pick_place = picks[i].place;
+      G.pick_variant = picks[i].variant;
+      G.pick_rls = picks[i].rls;
+    }
+    qtn_network *one[1] = {net};
+    auto ex = std::make_unique<Exec>();
+    int rc = build_schedule(one, 1, &ex->sched);
+    if (rc) return rc;
+    ex->rt.take(net->exec->rt);
+    ex->persistent = net->exec->persistent;
+    ex->dataflow = net->exec->dataflow;
+    ex->lead_per_cone = net->exec->lead_per_cone;
+    ex->spin_limit = net->exec->spin_limit;
+    drop_batches_with(net);
+    net->exec = std::move(ex);
+    net->version++;
+    return QTN_OK;
+  } catch (const std::bad_alloc &) {
+    return set_err(QTN_ENOMEM, "host allocation failed");
+  }
+}
+
 int qtn_tune_log(const qtn_network *net, int64_t cap, qtn_tune_rec *out, int64_t *n_out) {
   if (!net || !n_out || (cap > 0 && !out)) return set_err(QTN_EINVAL, "NULL argument");
   const auto &lg = net->tune_log;

@@ -225,3 +225,32 @@ def test_costmodel_host_side_checks(qtn):
     with pytest.raises(ValueError):
         qtn.CostModel(p[:-1])
     cm.close()
+
+
+def test_tune_picks_round_trip_and_validation(qtn):
+    inst = qs.instance(20, 3, 3, 1)
+    g, b = inst["angles"][0]
+    net = qtn.Network(20, inst["edges"], g, b)
+    net.plan(qtn.QTN_C64)
+    picks = net.tune_picks()
+    assert len(picks) == net.stats()["n_groups"]
+    assert all(p[2:5] == (-1, -1, -1) for p in picks)
+    # generic kernel for every group: accepted, read back, and the plan's
+    # matrix-form count stays zero
+    chosen = [(e, gi, 1, 1, 2, sh) for (e, gi, _, _, _, sh) in picks]
+    net.set_tune_picks(chosen)
+    assert net.tune_picks() == chosen
+    # a pick for a different group is refused and changes nothing
+    bad = list(chosen)
+    bad[0] = bad[0][:5] + ((bad[0][5] + 1) % (1 << 32),)
+    with pytest.raises(qtn.QtnError) as ei:
+        net.set_tune_picks(bad)
+    assert ei.value.code == -1 and "different group" in str(ei.value)
+    with pytest.raises(qtn.QtnError):
+        net.set_tune_picks([(999, 0, 1, 1, 2, 0)])
+    assert net.tune_picks() == chosen
+    # matrix form requested through picks on complex64 groups that have one
+    mf = [(e, gi, 1, 3, 2, sh) for (e, gi, _, _, _, sh) in picks]
+    net.set_tune_picks(mf)
+    assert net.stats()["n_matrix"] > 0
+    net.close()

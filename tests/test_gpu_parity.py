@@ -337,3 +337,29 @@ def test_cfg4_full_size_against_oracle(qtn, gpu, prec, variant, mixed_width):
     print(f"  per-edge |delta e|: max {err.max():.3e} median {np.median(err):.3e}; "
           f"|delta E|/E {abs(en - gd['energy']) / gd['energy']:.3e}", flush=True)
     _check(zz, zi, en, gd["zz_re"], gd["energy"], prec, "cfg4")
+
+
+def test_stored_tuning_reapplies(qtn, orc, gpu):
+    """Choices measured on one network reapplied to a fresh plan of the same
+    graph give the same schedule and results."""
+    inst = qs.instance(20, 3, 3, 6)
+    g, b = inst["angles"][0]
+    ref, ref_en = orc.energy(20, inst["edges"], g, b, threads=8)
+    a = qtn.Network(20, inst["edges"], g, b, order_trials=4)
+    a.plan(1)
+    a.autotune()
+    picks = a.tune_picks()
+    za, _, ea = a.contract()
+    a.contract_timed()
+    log_a = [(r["kind"], r["group"], r["variant"]) for r in a.launch_log()]
+    bnet = qtn.Network(20, inst["edges"], g, b, order_trials=4)
+    bnet.plan(1)
+    bnet.set_tune_picks(picks)
+    zb, _, eb = bnet.contract()
+    bnet.contract_timed()
+    log_b = [(r["kind"], r["group"], r["variant"]) for r in bnet.launch_log()]
+    assert log_a == log_b
+    assert np.array_equal(za, zb) and ea == eb
+    _check(zb, None, eb, ref, ref_en, 1, "stored tuning")
+    a.close()
+    bnet.close()
