@@ -680,6 +680,16 @@ int ensure_runtime(Runtime &rt, int n_streams, int n_res) {
     QTN_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
     rt.persist_blocks = persistent_blocks(kPrecC128, n_cu);
   }
+  // a runtime first made for a one-stream pass (autotuning) grows to the
+  // network's stream count
+  while ((int)rt.side.size() < n_streams) {
+    hipStream_t s;
+    QTN_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    rt.side.push_back(s);
+    hipEvent_t e;
+    QTN_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    rt.ev_join.push_back(e);
+  }
   if (rt.pinned_n < (size_t)n_res) {
     if (rt.pinned) QTN_HIP(hipHostFree(rt.pinned));
     rt.pinned = nullptr;
