@@ -98,10 +98,10 @@ struct Schedule {
   // segment or wide group) of each item, each task's predecessor in its cone
   // (-1: none) and its item count
   std::vector<int4> items;
-  std::vector<int> step_begin, item_task, task_dep, task_need;
-  int n_steps = 0, n_tasks = 0;
-  size_t off_items = 0, off_steps = 0, off_item_task = 0, off_task_dep = 0, off_task_need = 0,
-         off_ctl = 0;
+  std::vector<int> step_begin, item_task, task_dep, task_need, task_next, task_first;
+  int n_steps = 0, n_tasks = 0, n_init = 0;
+  size_t off_items = 0, off_steps = 0, off_item_task = 0, off_task_next = 0, off_task_first = 0,
+         off_task_need = 0, off_queue = 0, off_ctl = 0;
   int n_ctl = 0;
 };
 
@@ -591,7 +591,8 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S, const Force *fo
           s.task_need[tk]++;
         } else {
           const uint32_t nu = t.n_units;
-          uint32_t chunk = std::max<uint32_t>(4u, nu / 2048u);
+          // at least four passes of the block's waves per item
+          uint32_t chunk = std::max<uint32_t>(16u, nu / 1024u);
           for (uint32_t u = 0; u < nu; u += chunk) {
             put(make_int4(t.index, -1, (int)u, (int)std::min(nu, u + chunk)), tk);
             s.task_need[tk]++;
@@ -609,6 +610,14 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S, const Force *fo
     s.n_steps = (int)per_step.size();
     s.n_tasks = (int)s.task_dep.size();
     s.n_ctl = 4 + std::max(s.n_steps, s.n_tasks);
+    // ready-queue tables: a task's items are contiguous (one cone's chunks of
+    // one step); the first step holds the first task of every cone
+    s.task_next.assign(s.n_tasks, -1);
+    for (int t = 1; t < s.n_tasks; t++)
+      if (s.task_dep[t] >= 0) s.task_next[s.task_dep[t]] = t;
+    s.task_first.assign(s.n_tasks, -1);
+    for (int i = (int)s.item_task.size() - 1; i >= 0; i--) s.task_first[s.item_task[i]] = i;
+    s.n_init = s.n_steps > 0 ? s.step_begin[1] : 0;
   }
   s.bytes[QTN_K_BLOCK] = s.init_bytes;
   s.flops[QTN_K_BLOCK] = s.init_flops;
@@ -633,9 +642,11 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S, const Force *fo
   s.off_items = align_up(s.off_ncb + sizeof(int) * s.ncb.size(), 256);
   s.off_steps = align_up(s.off_items + sizeof(int4) * s.items.size(), 256);
   s.off_item_task = align_up(s.off_steps + sizeof(int) * s.step_begin.size(), 256);
-  s.off_task_dep = align_up(s.off_item_task + sizeof(int) * s.item_task.size(), 256);
-  s.off_task_need = align_up(s.off_task_dep + sizeof(int) * s.task_dep.size(), 256);
-  s.off_ctl = align_up(s.off_task_need + sizeof(int) * s.task_need.size(), 256);
+  s.off_task_next = align_up(s.off_item_task + sizeof(int) * s.item_task.size(), 256);
+  s.off_task_first = align_up(s.off_task_next + sizeof(int) * s.task_next.size(), 256);
+  s.off_task_need = align_up(s.off_task_first + sizeof(int) * s.task_first.size(), 256);
+  s.off_queue = align_up(s.off_task_need + sizeof(int) * s.task_need.size(), 256);
+  s.off_ctl = align_up(s.off_queue + sizeof(uint32_t) * s.items.size(), 256);
   s.off_data = align_up(s.off_ctl + sizeof(uint32_t) * s.n_ctl, 256);
   s.total = s.off_data + (size_t)data;
   s.desc_blob.assign(s.off_data - s.off_desc, 0);
@@ -653,7 +664,8 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S, const Force *fo
   put(s.off_items, s.items.data(), sizeof(int4) * s.items.size());
   put(s.off_steps, s.step_begin.data(), sizeof(int) * s.step_begin.size());
   put(s.off_item_task, s.item_task.data(), sizeof(int) * s.item_task.size());
-  put(s.off_task_dep, s.task_dep.data(), sizeof(int) * s.task_dep.size());
+  put(s.off_task_next, s.task_next.data(), sizeof(int) * s.task_next.size());
+  put(s.off_task_first, s.task_first.data(), sizeof(int) * s.task_first.size());
   put(s.off_task_need, s.task_need.data(), sizeof(int) * s.task_need.size());
   return QTN_OK;
 }
@@ -763,10 +775,12 @@ int enqueue(Exec &X, Timer &tm) {
       return rc;
     if (X.dataflow)
       QTN_HIP(launch_dataflow(data, groups, ops, stab, uperm, (const int4 *)(ws + s.off_items),
-                              (int)s.items.size(), (const int *)(ws + s.off_item_task),
-                              (const int *)(ws + s.off_task_dep),
-                              (const int *)(ws + s.off_task_need), (uint32_t *)(ws + s.off_ctl),
-                              s.n_ctl, nb, X.spin_limit, rt.main, tm.t0(), tm.t1()));
+                              (int)s.items.size(), s.n_init, (const int *)(ws + s.off_item_task),
+                              (const int *)(ws + s.off_task_next),
+                              (const int *)(ws + s.off_task_first),
+                              (const int *)(ws + s.off_task_need), (uint32_t *)(ws + s.off_queue),
+                              (uint32_t *)(ws + s.off_ctl), s.n_ctl, nb, X.spin_limit, rt.main,
+                              tm.t0(), tm.t1()));
     else
       QTN_HIP(launch_persistent(s.prec, data, groups, ops, stab, uperm,
                                 (const int4 *)(ws + s.off_items), (const int *)(ws + s.off_steps),

@@ -679,20 +679,26 @@ __global__ __launch_bounds__(kBlock) void k_persistent(char *__restrict__ data,
   }
 }
 
-// Dataflow form of the executor: blocks take items in order from ctl[0]; an
-// item first waits for the completion counter of its task's predecessor (the
-// previous task of the same light cone), then runs, then counts itself done.
-// Every item's predecessor items come earlier in the order and were taken by
-// running blocks, so the earliest unfinished item can always proceed.
-// Results are published with an agent-scope release before the count and
-// observed with an agent-scope acquire after the wait, as in grid_barrier.
+// Dataflow form of the executor, with a ready queue.  Work items (a cone's
+// segment of small groups, or a chunk of a wide group) belong to tasks; a
+// cone's tasks form a chain.  queue[] receives item indices (+1; 0 = empty)
+// as their tasks become ready: the first task of every cone before the
+// launch, a task's successor when the last item of the task completes.
+// Blocks claim queue slots in order from ctl[0] and run the item once its
+// slot is filled.  A block only waits when no ready item is left, and the
+// block that completes a task publishes its successor before claiming again,
+// so the earliest unfilled slot is always being worked towards.
+//
+// ctl: [claim counter, fill counter, error flag, pad, done counter per task].
+// Results are released (agent scope) before a done count, acquired by the
+// completing block before it publishes the successor, and acquired again by
+// the block that takes a published item.
 //
 // The bookkeeping runs in one branch at the top of the loop that is uniform
-// per wave (wave 0; lane 0 alone issues the atomics): a lane-divergent region
-// at the end of the loop body would let the compiler rotate it across the
-// back edge, so that the other lanes of wave 0 met the next barrier before
-// lane 0 had taken the next item.  The completion count of the previous item
-// is therefore issued there too, before the next item is taken.
+// per wave (wave 0; lane 0 alone issues the counter atomics): a lane-divergent
+// region at the end of the loop body could be rotated across the back edge,
+// so that the other lanes of wave 0 met the next barrier before lane 0 had
+// taken the next item.
 __global__ __launch_bounds__(kBlock) void k_dataflow(char *__restrict__ data,
                                                      const DevGroup *__restrict__ groups,
                                                      const DevOp *__restrict__ ops,
@@ -700,12 +706,14 @@ __global__ __launch_bounds__(kBlock) void k_dataflow(char *__restrict__ data,
                                                      const uint8_t *__restrict__ uperm,
                                                      const int4 *__restrict__ items, int n_items,
                                                      const int *__restrict__ item_task,
-                                                     const int *__restrict__ task_dep,
+                                                     const int *__restrict__ task_next,
+                                                     const int *__restrict__ task_first,
                                                      const int *__restrict__ task_need,
-                                                     uint32_t *ctl, uint32_t spin_limit) {
+                                                     uint32_t *queue, uint32_t *ctl,
+                                                     uint32_t spin_limit) {
   __shared__ __align__(16) uint32_t s_lane[kStreamMaxOps * 64];
   __shared__ int s_item, s_ok;
-  uint32_t *head = ctl, *err = ctl + 2, *done = ctl + 4;
+  uint32_t *claim = ctl, *fill = ctl + 1, *err = ctl + 2, *done = ctl + 4;
   const int lane = threadIdx.x & 63;
   int prev = -1;  // item this block finished last (block-uniform)
   for (;;) {
@@ -713,36 +721,50 @@ __global__ __launch_bounds__(kBlock) void k_dataflow(char *__restrict__ data,
       if (prev >= 0) {
         // release this block's results, then count the item done
         __threadfence();
+        const int t = item_task[prev];
+        uint32_t old = 0;
         if (lane == 0)
-          __hip_atomic_fetch_add(done + item_task[prev], 1u, __ATOMIC_RELAXED,
-                                 __HIP_MEMORY_SCOPE_AGENT);
-      }
-      uint32_t got = 0;
-      if (lane == 0)
-        got = __hip_atomic_fetch_add(head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      const int i = __builtin_amdgcn_readfirstlane((int)got);
-      int ok = 1;
-      if (i < n_items) {
-        const int d = task_dep[item_task[i]];
-        if (d >= 0) {
-          const uint32_t need = (uint32_t)task_need[d];
-          uint32_t polls = 0;
-          for (;;) {
-            const uint32_t c = __builtin_amdgcn_readfirstlane(
-                __hip_atomic_load(done + d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-            if (c >= need) break;
-            __builtin_amdgcn_s_sleep(2);
-            const uint32_t e = __builtin_amdgcn_readfirstlane(
-                __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-            if (++polls > spin_limit || e != 0u) {
-              if (lane == 0)
-                __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-              ok = 0;
-              break;
-            }
-          }
-          __threadfence();  // acquire the predecessor's results
+          old = __hip_atomic_fetch_add(done + t, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        old = __builtin_amdgcn_readfirstlane(old);
+        const int nt = task_next[t];
+        if (old + 1u == (uint32_t)task_need[t] && nt >= 0) {
+          // the task is complete: acquire every item's results, then publish
+          // the successor's items
+          __threadfence();
+          const uint32_t cnt = (uint32_t)task_need[nt], first = (uint32_t)task_first[nt];
+          uint32_t base = 0;
+          if (lane == 0)
+            base = __hip_atomic_fetch_add(fill, cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          base = __builtin_amdgcn_readfirstlane(base);
+          for (uint32_t k = lane; k < cnt; k += 64)
+            __hip_atomic_store(queue + base + k, first + k + 1u, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
         }
+      }
+      uint32_t h = 0;
+      if (lane == 0)
+        h = __hip_atomic_fetch_add(claim, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      h = __builtin_amdgcn_readfirstlane(h);
+      int i = n_items, ok = 1;
+      if (h < (uint32_t)n_items) {
+        uint32_t polls = 0;
+        for (;;) {
+          const uint32_t v = __builtin_amdgcn_readfirstlane(
+              __hip_atomic_load(queue + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+          if (v != 0u) {
+            i = (int)v - 1;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(8);
+          const uint32_t e = __builtin_amdgcn_readfirstlane(
+              __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+          if (++polls > spin_limit || e != 0u) {
+            if (lane == 0) __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ok = 0;
+            break;
+          }
+        }
+        __threadfence();  // acquire the item's inputs
       }
       if (lane == 0) {
         s_item = i;
@@ -752,10 +774,22 @@ __global__ __launch_bounds__(kBlock) void k_dataflow(char *__restrict__ data,
     __syncthreads();
     const int i = s_item, ok = s_ok;
     __syncthreads();
-    if (i >= n_items || !ok) break;
+    if (i >= n_items || i < 0 || !ok) break;
     run_item(items[i], data, groups, ops, stab, uperm, s_lane);  // ends with a barrier
     prev = i;
   }
+}
+
+// Control words to zero; the queue holds the first n_init items (0..n_init-1,
+// the first task of every cone) and is empty after them; the fill counter
+// starts at n_init.
+__global__ void k_queue_reset(uint32_t *ctl, int n_ctl, uint32_t *queue, int n_items,
+                              int n_init) {
+  const int stride = gridDim.x * blockDim.x;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n_ctl; k += stride)
+    ctl[k] = k == 1 ? (uint32_t)n_init : 0u;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n_items; k += stride)
+    queue[k] = k < n_init ? (uint32_t)k + 1u : 0u;
 }
 
 __global__ void k_reset(uint32_t *ctl, int n) {
@@ -939,15 +973,19 @@ hipError_t launch_persistent(int prec, void *data, const DevGroup *groups, const
 
 hipError_t launch_dataflow(void *data, const DevGroup *groups, const DevOp *ops,
                            const int32_t *stab, const uint8_t *uperm, const int4 *items,
-                           int n_items, const int *item_task, const int *task_dep,
-                           const int *task_need, uint32_t *ctl, int n_ctl, int n_blocks,
-                           uint32_t spin_limit, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
-  hipLaunchKernelGGL(k_reset, dim3(1), dim3(256), 0, s, ctl, n_ctl);
+                           int n_items, int n_init, const int *item_task, const int *task_next,
+                           const int *task_first, const int *task_need, uint32_t *queue,
+                           uint32_t *ctl, int n_ctl, int n_blocks, uint32_t spin_limit,
+                           hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
+  const int span = n_ctl > n_items ? n_ctl : n_items;
+  hipLaunchKernelGGL(k_queue_reset, dim3((span + 255) / 256), dim3(256), 0, s, ctl, n_ctl, queue,
+                     n_items, n_init);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (n_items <= 0) return no_launch(t0, t1, s);
   QTN_LAUNCH(t0, t1, k_dataflow, dim3(n_blocks), dim3(kBlock), s, (char *)data, groups, ops, stab,
-             uperm, items, n_items, item_task, task_dep, task_need, ctl, spin_limit);
+             uperm, items, n_items, item_task, task_next, task_first, task_need, queue, ctl,
+             spin_limit);
   return hipGetLastError();
 }
 

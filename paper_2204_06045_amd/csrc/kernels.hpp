@@ -55,18 +55,19 @@ hipError_t launch_persistent(int prec, void *data, const DevGroup *groups,
                              uint32_t spin_limit, hipStream_t s, hipEvent_t t0 = nullptr,
                              hipEvent_t t1 = nullptr);
 
-// Clears the control words, then runs the work items in order inside one
-// persistent launch: blocks take items from an atomic counter; an item of
-// task t first waits until task task_dep[t] (if >= 0) has completed all of
-// its task_need items.  ctl needs 4 + n_tasks words (ctl[0] the item counter,
-// ctl[2] != 0 after the launch means a wait exceeded spin_limit, then one
-// completion counter per task).
+// Runs every cone's tasks inside one persistent launch with a ready queue:
+// items of task t are items[task_first[t] .. task_first[t] + task_need[t]);
+// task_next[t] is the next task of the same light cone (-1: none); the first
+// n_init items (the first task of every cone) are ready at the start.  A
+// task's successor is queued when the task's last item completes.  queue
+// holds n_items words; ctl needs 4 + n_tasks words (ctl[2] != 0 after the
+// launch means a wait exceeded spin_limit).
 hipError_t launch_dataflow(void *data, const DevGroup *groups, const DevOp *ops,
                            const int32_t *stab, const uint8_t *uperm, const int4 *items,
-                           int n_items, const int *item_task, const int *task_dep,
-                           const int *task_need, uint32_t *ctl, int n_ctl, int n_blocks,
-                           uint32_t spin_limit, hipStream_t s, hipEvent_t t0 = nullptr,
-                           hipEvent_t t1 = nullptr);
+                           int n_items, int n_init, const int *item_task, const int *task_next,
+                           const int *task_first, const int *task_need, uint32_t *queue,
+                           uint32_t *ctl, int n_ctl, int n_blocks, uint32_t spin_limit,
+                           hipStream_t s, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 
 // Resident blocks of the persistent kernel on n_cu compute units (0 on error).
 int persistent_blocks(int prec, int n_cu);
