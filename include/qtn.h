@@ -188,6 +188,25 @@ int qtn_contract_timed(qtn_network *net, void *d_workspace, size_t bytes,
                        void *hip_stream, double *zz_out, double *energy_out,
                        qtn_timing *timing);
 
+/*
+ * Several angle sets on one plan in one pass: every launch of the schedule
+ * covers all sets, so each launch carries n_sets times the work (a parameter
+ * search evaluates many (gamma, beta) on one graph, Sec. II-A).
+ *   n_sets       1..1024
+ *   gamma, beta  [n_sets][p] angles in radians, finite
+ *   zz_out       [n_sets][n_edges] Re e_jk, or NULL
+ *   energy_out   [n_sets] energies, or NULL
+ * The workspace (qtn_angles_workspace) holds one copy of every intermediate
+ * per set.  Runs the per-group launch schedule (executor 0, 1 or 3 behaviour)
+ * on the network's streams; blocks until the results are on the host.
+ * The network's own angles (qtn_set_angles) are not used or changed.
+ * Errors: QTN_EINVAL (n_sets or angles), QTN_ESTATE, QTN_ENOMEM, QTN_EDEVICE.
+ */
+int qtn_angles_workspace(qtn_network *net, int32_t n_sets, size_t *workspace_bytes_out);
+int qtn_contract_angles(qtn_network *net, void *d_workspace, size_t bytes,
+                        void *hip_stream, int32_t n_sets, const double *gamma,
+                        const double *beta, double *zz_out, double *energy_out);
+
 /* One launch of the last qtn_contract_timed call on this network. */
 typedef struct qtn_launch_rec {
     int32_t kind;      /* QTN_K_* class                                   */

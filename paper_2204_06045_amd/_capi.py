@@ -35,6 +35,7 @@ EXPORTS = (
     "qtn_network_build", "qtn_network_info", "qtn_order_minfill", "qtn_plan",
     "qtn_set_angles", "qtn_contract", "qtn_contract_batch",
     "qtn_batch_workspace", "qtn_contract_timed", "qtn_get_plan_stats",
+    "qtn_angles_workspace", "qtn_contract_angles",
     "qtn_bucket_widths", "qtn_network_free", "qtn_last_error", "qtn_launch_log",
     "qtn_plan_order", "qtn_autotune", "qtn_tune_log", "qtn_tune_picks", "qtn_set_tune_picks",
     "qtn_costmodel_create", "qtn_costmodel_params", "qtn_costmodel_normalization",
@@ -137,6 +138,8 @@ def lib():
         L.qtn_plan_order.argtypes = [P, i64, pi32]
         L.qtn_autotune.argtypes = [P, P, ctypes.c_size_t, P, ctypes.POINTER(qtn_tune_report)]
         L.qtn_tune_log.argtypes = [P, i64, ctypes.POINTER(qtn_tune_rec), ctypes.POINTER(i64)]
+        L.qtn_angles_workspace.argtypes = [P, i32, ctypes.POINTER(ctypes.c_size_t)]
+        L.qtn_contract_angles.argtypes = [P, P, ctypes.c_size_t, P, i32, pd, pd, pd, pd]
         L.qtn_tune_picks.argtypes = [P, i64, ctypes.POINTER(qtn_tune_pick), ctypes.POINTER(i64)]
         L.qtn_set_tune_picks.argtypes = [P, ctypes.POINTER(qtn_tune_pick), i64]
         pf = ctypes.POINTER(ctypes.c_float)

@@ -23,7 +23,7 @@ __all__ = [
     "qtn_contract_timed", "qtn_contract_batch", "qtn_batch_workspace",
     "qtn_get_plan_stats", "qtn_bucket_widths", "qtn_network_free",
     "qtn_last_error", "qtn_launch_log", "qtn_plan_order", "qtn_autotune", "qtn_tune_log",
-    "qtn_tune_picks", "qtn_set_tune_picks",
+    "qtn_tune_picks", "qtn_set_tune_picks", "qtn_angles_workspace", "qtn_contract_angles",
     "Network", "CostModel", "qtn_apply_costmodel", "workspace", "stream_handle",
 ]
 
@@ -208,6 +208,28 @@ def qtn_autotune(net, ws, stream=None):
             "picks": list(r.picks[:nc])}
 
 
+def qtn_angles_workspace(net, n_sets):
+    b = ctypes.c_size_t()
+    check(lib().qtn_angles_workspace(net, int(n_sets), ctypes.byref(b)))
+    return b.value
+
+
+def qtn_contract_angles(net, n_edges, gammas, betas, ws, stream=None):
+    """gammas, betas: [n_sets][p].  Returns (zz [n_sets, n_edges], energies [n_sets])."""
+    g = np.ascontiguousarray(np.asarray(gammas, dtype=np.float64))
+    b = np.ascontiguousarray(np.asarray(betas, dtype=np.float64))
+    if g.ndim != 2 or g.shape != b.shape:
+        raise ValueError("gammas and betas must both be [n_sets][p]")
+    n_sets = g.shape[0]
+    zz = np.zeros((n_sets, n_edges))
+    en = np.zeros(n_sets)
+    check(lib().qtn_contract_angles(net, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                    stream_handle(stream), n_sets, g.ctypes.data_as(_pd),
+                                    b.ctypes.data_as(_pd), zz.ctypes.data_as(_pd),
+                                    en.ctypes.data_as(_pd)))
+    return zz, en
+
+
 def qtn_tune_picks(net):
     """Kernel choice per group: list of (edge, group, place, variant, rls, shape)."""
     n = ctypes.c_int64()
@@ -251,6 +273,7 @@ class Network:
         self.h = qtn_network_build(self.n, self.edges, gamma, beta, **cfg)
         self.ws_bytes = None
         self._ws = None
+        self._aws = None
 
     def info(self, edge):
         return qtn_network_info(self.h, edge)
@@ -291,6 +314,19 @@ class Network:
     def tune_log(self):
         return qtn_tune_log(self.h)
 
+    def angles_workspace(self, n_sets):
+        return qtn_angles_workspace(self.h, n_sets)
+
+    def contract_angles(self, gammas, betas, ws=None, stream=None):
+        """Energies of several angle sets in one pass over the plan."""
+        if ws is None:
+            need = qtn_angles_workspace(self.h, len(gammas))
+            if self._aws is None or self._aws.numel() < need:
+                self._aws = None
+                self._aws = workspace(need)
+            ws = self._aws
+        return qtn_contract_angles(self.h, self.m, gammas, betas, ws, stream)
+
     def tune_picks(self):
         return qtn_tune_picks(self.h)
 
@@ -308,6 +344,7 @@ class Network:
             qtn_network_free(self.h)
             self.h = None
         self._ws = None
+        self._aws = None
 
     def __del__(self):
         try:

@@ -90,7 +90,8 @@ struct Schedule {
   int n_cones = 0, n_nets = 0, n_angles = 0;
   size_t off_res = 0, off_angles = 0, off_desc = 0, off_fills = 0, off_groups = 0,
          off_ops = 0, off_stab = 0, off_uperm = 0, off_ranges = 0, off_csb = 0, off_ncb = 0, off_data = 0, total = 0;
-  int64_t scalar_off = 0;
+  int64_t scalar_off = 0, scalar_sstride = 0;
+  int n_sets = 1;  // angle sets evaluated per launch (one copy of the data each)
   std::vector<char> desc_blob;  // bytes [off_desc, off_data)
   double bytes[QTN_NKERNELS] = {}, flops[QTN_NKERNELS] = {};
   double init_bytes = 0, init_flops = 0;
@@ -221,6 +222,11 @@ struct qtn_network {
   std::vector<qtn_launch_rec> launch_log;
   std::vector<qtn_tune_rec> tune_log;
   size_t tune_workspace = 0;
+  // angle-set batches: a schedule with one data copy per set, rebuilt when
+  // the set count or the plan changes
+  std::unique_ptr<Exec> angle_exec;
+  int angle_sets = 0;
+  uint64_t angle_version = 0;
 };
 
 namespace {
@@ -273,9 +279,10 @@ const std::vector<Force> &tune_candidates() {
 }
 
 int build_schedule(qtn_network *const *nets, int n, Schedule *S, const Force *force = nullptr,
-                   int singleton_width = 0) {
+                   int singleton_width = 0, int n_sets = 1) {
   Schedule &s = *S;
   s = Schedule();
+  s.n_sets = n_sets;
   s.prec = nets[0]->precision;
   s.scalar_prec = s.prec == kPrecC64 ? 1 : 0;
   auto al = [](int64_t bytes) { return (bytes + 255) / 256 * 256; };
@@ -285,32 +292,37 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S, const Force *fo
   int n_scalars = 0;
   for (int i = 0; i < n; i++) {
     if (nets[i]->precision != s.prec) return set_err(QTN_EINVAL, "batched networks differ in precision");
-    FillDesc f{(int64_t)s.n_angles, -1, -1, nets[i]->p, 0};
+    // one copy of every table, scalar slot and arena per angle set
+    FillDesc f{(int64_t)s.n_angles, -1, -1, 0, 0, nets[i]->p, 0};
     const int64_t tab = gate_table_elems(nets[i]->p);
     if (s.prec != kPrecC64) {
       f.table128 = data;
-      data += al(tab * 16);
+      f.sstride128 = al(tab * 16);
+      data += n_sets * f.sstride128;
     }
     if (s.prec != kPrecC128) {
       f.table64 = data;
-      data += al(tab * 8);
+      f.sstride64 = al(tab * 8);
+      data += n_sets * f.sstride64;
     }
     s.fills.push_back(f);
     s.n_angles += 2 * nets[i]->p;
     for (auto &pl : nets[i]->plans) n_scalars += pl.n_scalars;
   }
   s.scalar_off = data;
-  data += al(n_scalars * es(s.scalar_prec));
+  s.scalar_sstride = al(n_scalars * es(s.scalar_prec));
+  data += n_sets * s.scalar_sstride;
   int scalar_next = 0;
   s.ncb.push_back(0);
   for (int i = 0; i < n; i++) {
     const qtn_network *net = nets[i];
     const int64_t table[2] = {s.fills[i].table128, s.fills[i].table64};
+    const int64_t table_sstride[2] = {s.fills[i].sstride128, s.fills[i].sstride64};
     for (size_t c = 0; c < net->plans.size(); c++) {
       const ConePlan &pl = net->plans[c];
       const LightCone &lc = net->cones[c];
-      const int64_t arena = data;
-      data += al(pl.arena_bytes);
+      const int64_t arena = data, arena_sstride = al(pl.arena_bytes);
+      data += n_sets * arena_sstride;
       s.csb.push_back(scalar_next);
       std::vector<Task> tasks;
       int open_begin = -1;
@@ -331,6 +343,7 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S, const Force *fo
         dg.out_off = G.out_tensor >= 0
                          ? arena + pl.tensors[G.out_tensor].offset
                          : s.scalar_off + (int64_t)(scalar_next + G.scalar_slot) * es(s.scalar_prec);
+        dg.out_sstride = G.out_tensor >= 0 ? arena_sstride : s.scalar_sstride;
         dg.prec = (uint8_t)G.prec;
         dg.op_begin = (int32_t)s.ops.size();
         dg.w = (uint8_t)G.w;
@@ -477,9 +490,11 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S, const Force *fo
           if (t.gate >= 0) {
             // gate operands read the table of the group's own precision
             d.off = table[G.prec] + gate_offset(lc.gates[t.gate], t.transposed, net->p) * es(G.prec);
+            d.sstride = table_sstride[G.prec];
             d.dt = (uint8_t)G.prec;
           } else {
             d.off = arena + t.offset;
+            d.sstride = arena_sstride;
             d.dt = (uint8_t)t.prec;
           }
           d.mask = o.mask;
@@ -629,8 +644,8 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S, const Force *fo
 
   // workspace layout (bytes)
   s.off_res = 0;
-  s.off_angles = align_up(8 * (size_t)(2 * s.n_cones + s.n_nets), 256);
-  s.off_desc = align_up(s.off_angles + 8 * (size_t)s.n_angles, 256);
+  s.off_angles = align_up(8 * (size_t)(2 * s.n_cones + s.n_nets) * s.n_sets, 256);
+  s.off_desc = align_up(s.off_angles + 8 * (size_t)s.n_angles * s.n_sets, 256);
   s.off_fills = s.off_desc;
   s.off_groups = align_up(s.off_fills + sizeof(FillDesc) * s.fills.size(), 256);
   s.off_ops = align_up(s.off_groups + sizeof(DevGroup) * s.groups.size(), 256);
@@ -761,9 +776,12 @@ int enqueue(Exec &X, Timer &tm) {
   int rc;
   if ((rc = tm.begin(QTN_K_FILL, rt.main))) return rc;
   QTN_HIP(launch_fill(s.prec, data, (const double *)(ws + s.off_angles),
-                      (const FillDesc *)(ws + s.off_fills), s.n_nets, rt.main));
+                      (const FillDesc *)(ws + s.off_fills), s.n_nets, s.n_angles, s.n_sets,
+                      rt.main));
   if ((rc = tm.end(rt.main))) return rc;
+  const int NS = s.n_sets;  // launch records carry the bytes of every set
   if (X.persistent) {
+    if (NS != 1) return set_err(QTN_EINVAL, "the persistent executors run one angle set");
     const int nb = rt.persist_blocks;
     if (nb < 1) return set_err(QTN_EDEVICE, "persistent kernel does not fit on the device");
     double b_all = 0, f_all = 0;
@@ -791,10 +809,10 @@ int enqueue(Exec &X, Timer &tm) {
   // leading small segments: one launch for every cone before the fork, or
   // (lead_per_cone) each cone's own one-block launch on its stream
   if (!X.lead_per_cone) {
-    if ((rc = tm.begin(QTN_K_BLOCK, rt.main, 0, (int)s.groups.size(), s.init_bytes, s.init_flops,
-                       true)))
+    if ((rc = tm.begin(QTN_K_BLOCK, rt.main, 0, (int)s.groups.size(), NS * s.init_bytes,
+                       NS * s.init_flops, true)))
       return rc;
-    QTN_HIP(launch_block_groups(s.prec, data, groups, ops, stab, uperm, ranges, 0, s.n_cones,
+    QTN_HIP(launch_block_groups(s.prec, data, groups, ops, stab, uperm, ranges, 0, s.n_cones, NS,
                                 rt.main, tm.t0(), tm.t1()));
     if ((rc = tm.end(rt.main, true))) return rc;
   }
@@ -824,20 +842,20 @@ int enqueue(Exec &X, Timer &tm) {
         if ((rc = tm.begin(QTN_K_BLOCK, hs, s.ranges[c].x, s.ranges[c].y - s.ranges[c].x, 0, 0,
                            true)))
           return rc;
-        QTN_HIP(launch_block_groups(s.prec, data, groups, ops, stab, uperm, ranges, c, 1, hs,
+        QTN_HIP(launch_block_groups(s.prec, data, groups, ops, stab, uperm, ranges, c, 1, NS, hs,
                                     tm.t0(), tm.t1()));
         if ((rc = tm.end(hs, true))) return rc;
       }
       for (auto &t : s.cone_tasks[c]) {
         const int g0 = t.kind == QTN_K_BLOCK ? s.ranges[t.index].x : t.index;
         const int ng = t.kind == QTN_K_BLOCK ? s.ranges[t.index].y - s.ranges[t.index].x : 1;
-        if ((rc = tm.begin(t.kind, hs, g0, ng, t.bytes, t.flops, true))) return rc;
+        if ((rc = tm.begin(t.kind, hs, g0, ng, NS * t.bytes, NS * t.flops, true))) return rc;
         if (t.kind == QTN_K_BLOCK)
-          QTN_HIP(launch_block_groups(s.prec, data, groups, ops, stab, uperm, ranges, t.index, 1, hs,
-                                      tm.t0(), tm.t1()));
+          QTN_HIP(launch_block_groups(s.prec, data, groups, ops, stab, uperm, ranges, t.index, 1, NS,
+                                      hs, tm.t0(), tm.t1()));
         else
           QTN_HIP(launch_wide_group(s.groups[t.index].prec, s.groups[t.index].cvt != 0, t.variant,
-                                    data, groups, ops, stab, uperm, t.index, t.n_units, hs,
+                                    data, groups, ops, stab, uperm, t.index, t.n_units, NS, hs,
                                     tm.t0(), tm.t1()));
         if ((rc = tm.end(hs, true))) return rc;
       }
@@ -849,16 +867,20 @@ int enqueue(Exec &X, Timer &tm) {
   }
   }
   if ((rc = tm.begin(QTN_K_REDUCE, rt.main))) return rc;
-  QTN_HIP(launch_reduce(s.scalar_prec == 1 ? kPrecC64 : kPrecC128, data, s.scalar_off, (const int *)(ws + s.off_csb),
-                        (const int *)(ws + s.off_ncb), s.n_cones, s.n_nets,
+  QTN_HIP(launch_reduce(s.scalar_prec == 1 ? kPrecC64 : kPrecC128, data, s.scalar_off,
+                        s.scalar_sstride, (const int *)(ws + s.off_csb),
+                        (const int *)(ws + s.off_ncb), s.n_cones, s.n_nets, NS,
                         (double *)(ws + s.off_res), rt.main));
   if ((rc = tm.end(rt.main))) return rc;
   return QTN_OK;
 }
 
 // Upload descriptors (once per workspace), angles, run, read back.
+// set_angles: n_sets * n_angles doubles (per set, per network gamma[p] then
+// beta[p]); NULL: the networks' own angles (one set).
 int run_exec(Exec &X, const std::vector<const qtn_network *> &nets, void *ws, size_t bytes,
-             void *stream, int n_streams, bool eager, Timer &tm, std::vector<double> &res) {
+             void *stream, int n_streams, bool eager, Timer &tm, std::vector<double> &res,
+             const double *set_angles = nullptr) {
   Schedule &s = X.sched;
   Runtime &rt = X.rt;
   if (!ws) return set_err(QTN_EINVAL, "workspace is NULL");
@@ -866,8 +888,9 @@ int run_exec(Exec &X, const std::vector<const qtn_network *> &nets, void *ws, si
     return set_err(QTN_ENOMEM, "workspace of " + std::to_string(bytes) + " bytes, plan needs " +
                                    std::to_string(s.total));
   if ((uintptr_t)ws % 256) return set_err(QTN_EINVAL, "workspace must be 256-byte aligned");
-  const int n_res = 2 * s.n_cones + s.n_nets;
-  int rc = ensure_runtime(rt, n_streams, std::max(n_res, s.n_angles));
+  if (!set_angles && s.n_sets != 1) return set_err(QTN_EINVAL, "angle sets missing");
+  const int n_res = (2 * s.n_cones + s.n_nets) * s.n_sets;
+  int rc = ensure_runtime(rt, n_streams, std::max(n_res, s.n_angles * s.n_sets));
   if (rc) return rc;
   QTN_HIP(hipEventRecord(rt.ev_in, (hipStream_t)stream));
   QTN_HIP(hipStreamWaitEvent(rt.main, rt.ev_in, 0));
@@ -883,14 +906,18 @@ int run_exec(Exec &X, const std::vector<const qtn_network *> &nets, void *ws, si
     QTN_HIP(hipStreamSynchronize(rt.main));
     rt.ws = ws;
   }
-  size_t a = 0;
-  for (auto *net : nets) {
-    for (int l = 0; l < net->p; l++) rt.pinned[a + l] = net->gamma[l];
-    for (int l = 0; l < net->p; l++) rt.pinned[a + net->p + l] = net->beta[l];
-    a += 2 * net->p;
+  if (set_angles) {
+    std::memcpy(rt.pinned, set_angles, sizeof(double) * s.n_angles * s.n_sets);
+  } else {
+    size_t a = 0;
+    for (auto *net : nets) {
+      for (int l = 0; l < net->p; l++) rt.pinned[a + l] = net->gamma[l];
+      for (int l = 0; l < net->p; l++) rt.pinned[a + net->p + l] = net->beta[l];
+      a += 2 * net->p;
+    }
   }
-  QTN_HIP(hipMemcpyAsync((char *)ws + s.off_angles, rt.pinned, sizeof(double) * s.n_angles,
-                         hipMemcpyHostToDevice, rt.main));
+  QTN_HIP(hipMemcpyAsync((char *)ws + s.off_angles, rt.pinned,
+                         sizeof(double) * s.n_angles * s.n_sets, hipMemcpyHostToDevice, rt.main));
   if (eager || tm.on) {
     if ((rc = enqueue(X, tm))) return rc;
   } else {
@@ -1172,6 +1199,78 @@ int qtn_contract(qtn_network *net, void *d_workspace, size_t bytes, void *hip_st
                        nullptr);
 }
 
+constexpr int kMaxAngleSets = 1024;
+
+static Exec *angle_exec(qtn_network *net, int n_sets, int *rc) {
+  if (net->angle_exec && net->angle_sets == n_sets && net->angle_version == net->version)
+    return net->angle_exec.get();
+  auto ex = std::make_unique<Exec>();
+  qtn_network *one[1] = {net};
+  *rc = build_schedule(one, 1, &ex->sched, nullptr, 0, n_sets);
+  if (*rc) return nullptr;
+  // per-group launches (the persistent executors run one set)
+  ex->lead_per_cone = net->executor == 3;
+  ex->spin_limit = net->spin_limit;
+  if (net->angle_exec) ex->rt.take(net->angle_exec->rt);
+  net->angle_exec = std::move(ex);
+  net->angle_sets = n_sets;
+  net->angle_version = net->version;
+  return net->angle_exec.get();
+}
+
+int qtn_angles_workspace(qtn_network *net, int32_t n_sets, size_t *bytes_out) {
+  try {
+    if (!net || !bytes_out) return set_err(QTN_EINVAL, "NULL argument");
+    if (!net->planned) return set_err(QTN_ESTATE, "qtn_plan has not been called");
+    if (n_sets < 1 || n_sets > kMaxAngleSets)
+      return set_err(QTN_EINVAL, "n_sets must be in 1.." + std::to_string(kMaxAngleSets));
+    int rc = QTN_OK;
+    Exec *ex = angle_exec(net, n_sets, &rc);
+    if (!ex) return rc;
+    *bytes_out = ex->sched.total;
+    return QTN_OK;
+  } catch (const std::bad_alloc &) {
+    return set_err(QTN_ENOMEM, "host allocation failed");
+  }
+}
+
+int qtn_contract_angles(qtn_network *net, void *d_workspace, size_t bytes, void *hip_stream,
+                        int32_t n_sets, const double *gamma, const double *beta, double *zz_out,
+                        double *energy_out) {
+  try {
+    if (!net || !gamma || !beta) return set_err(QTN_EINVAL, "NULL argument");
+    if (!net->planned) return set_err(QTN_ESTATE, "qtn_plan has not been called");
+    if (n_sets < 1 || n_sets > kMaxAngleSets)
+      return set_err(QTN_EINVAL, "n_sets must be in 1.." + std::to_string(kMaxAngleSets));
+    const int p = net->p;
+    std::vector<double> ang((size_t)n_sets * 2 * p);
+    for (int k = 0; k < n_sets; k++) {
+      if (!finite_angles(p, gamma + (size_t)k * p, beta + (size_t)k * p))
+        return set_err(QTN_EINVAL, "angles of set " + std::to_string(k) + " are not finite");
+      std::copy(gamma + (size_t)k * p, gamma + (size_t)(k + 1) * p, ang.begin() + (size_t)k * 2 * p);
+      std::copy(beta + (size_t)k * p, beta + (size_t)(k + 1) * p,
+                ang.begin() + (size_t)k * 2 * p + p);
+    }
+    int rc = QTN_OK;
+    Exec *ex = angle_exec(net, n_sets, &rc);
+    if (!ex) return rc;
+    Timer tm;
+    std::vector<double> res;
+    rc = run_exec(*ex, {net}, d_workspace, bytes, hip_stream, net->n_streams, net->eager, tm, res,
+                  ang.data());
+    if (rc) return rc;
+    const int m = (int)net->cones.size(), per = 2 * m + 1;
+    for (int k = 0; k < n_sets; k++) {
+      if (zz_out) std::copy(res.begin() + (size_t)k * per, res.begin() + (size_t)k * per + m,
+                            zz_out + (size_t)k * m);
+      if (energy_out) energy_out[k] = res[(size_t)k * per + 2 * m];
+    }
+    return QTN_OK;
+  } catch (const std::bad_alloc &) {
+    return set_err(QTN_ENOMEM, "host allocation failed");
+  }
+}
+
 int qtn_contract_timed(qtn_network *net, void *d_workspace, size_t bytes, void *hip_stream,
                        double *zz_out, double *energy_out, qtn_timing *timing) {
   if (!timing) return set_err(QTN_EINVAL, "timing is NULL");
@@ -1296,7 +1395,7 @@ int qtn_autotune(qtn_network *net, void *d_workspace, size_t bytes, void *hip_st
               s.prec, ws + s.off_data, (const DevGroup *)(ws + s.off_groups),
               (const DevOp *)(ws + s.off_ops), (const int32_t *)(ws + s.off_stab),
               (const uint8_t *)(ws + s.off_uperm), (const int2 *)(ws + s.off_ranges),
-              s.singles_range0 + (int)i, 1, ex.rt.main, tb.t0(), tb.t1());
+              s.singles_range0 + (int)i, 1, 1, ex.rt.main, tb.t0(), tb.t1());
           if (he == hipSuccess) rc = tb.end(ex.rt.main, true);
           if (he != hipSuccess || rc) {
             give_back();

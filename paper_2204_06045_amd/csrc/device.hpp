@@ -22,8 +22,11 @@ enum OpClass : uint8_t {
   kClsSerial = 3,   // serial level with lane bits: read at every serial step
 };
 
+// Angle sets: one launch may evaluate several (gamma, beta) sets on one
+// plan; every tensor then has one copy per set, sstride bytes apart.
 struct DevOp {          // 64 bytes
-  int64_t off;          // byte offset of the operand from the data base
+  int64_t off;          // byte offset of the operand from the data base (set 0)
+  int64_t sstride;      // bytes from one angle set's copy to the next
   uint32_t mask;        // union bits the operand carries
   int32_t stab;         // first entry of its serial-offset table (streaming)
   uint8_t level;        // multiplied in after `level` indices are summed
@@ -31,11 +34,12 @@ struct DevOp {          // 64 bytes
   uint8_t cls;          // OpClass (streaming)
   uint8_t dt;           // storage: 0 complex128, 1 complex64
   uint16_t run[kOpRuns];  // src | len << 5 | dst << 11 : pext by runs
-  uint8_t pad2[12];
+  uint8_t pad2[4];
 };
 
-struct DevGroup {       // 48 bytes
-  int64_t out_off;      // byte offset of the output (or scalar slot)
+struct DevGroup {       // 64 bytes
+  int64_t out_off;      // byte offset of the output (or scalar slot), set 0
+  int64_t out_sstride;  // bytes from one angle set's output to the next
   int32_t op_begin;     // first DevOp of the group
   uint32_t n_units;     // wave units
   uint8_t w, L, n_ops, variant;   // variant: kVarGeneric / kVarStream
@@ -50,11 +54,11 @@ struct DevGroup {       // 48 bytes
   uint8_t cvt;          // 1: some operand is stored in the other precision
   uint8_t n_mb, n_nb, n_bb;  // matrix form: m, n and batch bit counts (their
                              // union positions: uperm, m then n then batch)
-  uint8_t pad2[2];
+  uint8_t pad2[10];
 };
 
 static_assert(sizeof(DevOp) == 64, "DevOp layout");
-static_assert(sizeof(DevGroup) == 48, "DevGroup layout");
+static_assert(sizeof(DevGroup) == 64, "DevGroup layout");
 
 enum Variant : uint8_t { kVarGeneric = 0, kVarStream = 1, kVarMfma = 2 };
 

@@ -39,6 +39,7 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kStepOps = 4;  // step-class operands unrolled in the serial loop
+constexpr int kGenBatch = 3; // generic mapping: leaf operands loaded together
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
@@ -105,6 +106,14 @@ __device__ __forceinline__ uint32_t pext_runs(uint32_t x, const DevOp &o) {
   return r;
 }
 
+// Operand and output of angle set `set` (each tensor has one copy per set).
+__device__ __forceinline__ const char *opnd(const char *data, const DevOp &o, uint32_t set) {
+  return data + o.off + (int64_t)set * o.sstride;
+}
+__device__ __forceinline__ char *outp(char *data, const DevGroup &G, uint32_t set) {
+  return data + G.out_off + (int64_t)set * G.out_sstride;
+}
+
 // Union bits of wave unit u: bit j of u goes to union bit ubit[j] (the
 // planner orders the unit bits so that bits some large operand lacks come
 // first, and units that reuse an operand's data run next to each other).
@@ -131,7 +140,7 @@ __device__ __forceinline__ uint32_t pext_reg(uint32_t x, uint32_t m) {
 template <class T, bool CVT>
 __device__ __forceinline__ void generic_unit(const DevGroup &G, const DevOp *__restrict__ gops,
                                              const uint8_t *__restrict__ ubit, char *__restrict__ data,
-                                             uint32_t u, int lane) {
+                                             uint32_t u, int lane, uint32_t set) {
   constexpr int RG = kGenRegBits, NR = 1 << RG;
   const uint32_t I0 = unit_bits(u, ubit, G.n_ubits) | ((uint32_t)lane << RG);
   const int L = G.L;
@@ -139,15 +148,33 @@ __device__ __forceinline__ void generic_unit(const DevGroup &G, const DevOp *__r
   {
     const DevOp &o = gops[0];
     const uint32_t base = pext_runs(I0, o);
-    const char *src = data + o.off;
+    const char *src = opnd(data, o, set);
 #pragma unroll
     for (int r = 0; r < NR; r++) v[r] = ld_elem<T, CVT>(src, base + pext_reg(r, o.mask), o.dt);
   }
+  // the other leaf operands, kGenBatch at a time: all of their loads are
+  // issued before the first multiply, so their latencies overlap
   int k = 1;
-  for (; k < G.level_end[0]; k++) {
+  const int e0 = G.level_end[0];
+  for (; k + kGenBatch <= e0; k += kGenBatch) {
+    T x[kGenBatch][NR];
+#pragma unroll
+    for (int j = 0; j < kGenBatch; j++) {
+      const DevOp &o = gops[k + j];
+      const uint32_t base = pext_runs(I0, o);
+      const char *src = opnd(data, o, set);
+#pragma unroll
+      for (int r = 0; r < NR; r++) x[j][r] = ld_elem<T, CVT>(src, base + pext_reg(r, o.mask), o.dt);
+    }
+#pragma unroll
+    for (int j = 0; j < kGenBatch; j++)
+#pragma unroll
+      for (int r = 0; r < NR; r++) v[r] = cmul(v[r], x[j][r]);
+  }
+  for (; k < e0; k++) {
     const DevOp &o = gops[k];
     const uint32_t base = pext_runs(I0, o);
-    const char *src = data + o.off;
+    const char *src = opnd(data, o, set);
 #pragma unroll
     for (int r = 0; r < NR; r++)
       v[r] = cmul(v[r], ld_elem<T, CVT>(src, base + pext_reg(r, o.mask), o.dt));
@@ -161,7 +188,7 @@ __device__ __forceinline__ void generic_unit(const DevGroup &G, const DevOp *__r
         for (; k < G.level_end[s + 1]; k++) {
           const DevOp &o = gops[k];
           const uint32_t base = pext_runs(I0, o);
-          const char *src = data + o.off;
+          const char *src = opnd(data, o, set);
 #pragma unroll
           for (int r = 0; r < (NR >> (s + 1)); r++)
             v[r] = cmul(v[r], ld_elem<T, CVT>(src, base + pext_reg((uint32_t)r << (s + 1), o.mask), o.dt));
@@ -169,7 +196,7 @@ __device__ __forceinline__ void generic_unit(const DevGroup &G, const DevOp *__r
       }
     }
   }
-  T *out = (T *)(data + G.out_off);
+  T *out = (T *)outp(data, G, set);
   const uint32_t nout = 1u << (G.w - L);
   if (L <= RG) {
     const uint32_t ob = I0 >> L;
@@ -184,7 +211,7 @@ __device__ __forceinline__ void generic_unit(const DevGroup &G, const DevOp *__r
     if (s + 1 < L) {
       for (; k < G.level_end[s + 1]; k++) {
         const DevOp &o = gops[k];
-        acc = cmul(acc, ld_elem<T, CVT>(data + o.off, pext_runs(I0, o), o.dt));
+        acc = cmul(acc, ld_elem<T, CVT>(opnd(data, o, set), pext_runs(I0, o), o.dt));
       }
     }
   }
@@ -274,7 +301,8 @@ template <class T, bool CVT>
 __device__ __forceinline__ void stream_unit(const DevGroup &G, const DevOp *__restrict__ gops,
                                             const int32_t *__restrict__ stab,
                                             const uint8_t *__restrict__ ubit, char *__restrict__ data,
-                                            const uint32_t *s_lane, uint32_t u, int lane) {
+                                            const uint32_t *s_lane, uint32_t u, int lane,
+                                            uint32_t set) {
   const int L = G.L, rls = G.rls, sl = G.sl;
   const uint32_t Iu = unit_bits(u, ubit, G.n_ubits);
   const uint32_t nsteps = 1u << sl;
@@ -284,7 +312,7 @@ __device__ __forceinline__ void stream_unit(const DevGroup &G, const DevOp *__re
   for (int k = 0; k < G.n_unit; k++) {
     const DevOp &o = gops[k];
     const uint32_t ES = esize<T, CVT>(o.dt);
-    const char *p = uniform_ptr(data + o.off + (uint64_t)pext_runs(Iu, o) * ES);
+    const char *p = uniform_ptr(opnd(data, o, set) + (uint64_t)pext_runs(Iu, o) * ES);
     const uint32_t lb = s_lane[k * 64 + lane] * ES;
     const T x0 = gload_dt<T, CVT>(p, lb, o.dt);
     const T x1 = gload_dt<T, CVT>(p, lb + ((o.mask & 1u) ? ES : 0u), o.dt);
@@ -297,7 +325,7 @@ __device__ __forceinline__ void stream_unit(const DevGroup &G, const DevOp *__re
   for (int k = ku; k < ks; k++) {
     const DevOp &o = gops[k];
     const uint32_t ES = esize<T, CVT>(o.dt);
-    const char *p = uniform_ptr(data + o.off + (uint64_t)pext_runs(Iu, o) * ES);
+    const char *p = uniform_ptr(opnd(data, o, set) + (uint64_t)pext_runs(Iu, o) * ES);
     const uint32_t off = lane_step ? (uint32_t)stab[o.stab + lane] * ES : 0u;
     U = cmul(U, gload_dt<T, CVT>(p, off, o.dt));
   }
@@ -320,7 +348,7 @@ __device__ __forceinline__ void stream_unit(const DevGroup &G, const DevOp *__re
       const DevOp &o = gops[kb + i];
       const uint32_t ES = esize<T, CVT>(o.dt);
       dt[i] = o.dt;
-      pb[i] = uniform_ptr(data + o.off + (uint64_t)pext_runs(Iu, o) * ES);
+      pb[i] = uniform_ptr(opnd(data, o, set) + (uint64_t)pext_runs(Iu, o) * ES);
       lb[i] = s_lane[(kb + i) * 64 + lane] * ES;
       tb[i] = lane_step ? (uint32_t)stab[o.stab + lane] * ES : 0u;
       h0[i] = (o.mask & 1u) != 0;
@@ -353,7 +381,7 @@ __device__ __forceinline__ void stream_unit(const DevGroup &G, const DevOp *__re
     for (int k = k_extra; k < k_h0_end; k++) {
       const DevOp &o = gops[k];
       const uint32_t ES = esize<T, CVT>(o.dt);
-      const char *p = uniform_ptr(data + o.off +
+      const char *p = uniform_ptr(opnd(data, o, set) +
                                   ((uint64_t)pext_runs(Iu, o) + (uint32_t)stab[o.stab + s]) * ES);
       const uint32_t l = s_lane[k * 64 + lane] * ES;
       v0 = cmul(v0, gload_dt<T, CVT>(p, l, o.dt));
@@ -366,7 +394,7 @@ __device__ __forceinline__ void stream_unit(const DevGroup &G, const DevOp *__re
     for (int k = max(k_extra, k_h0_end); k < kb + n_step; k++) {
       const DevOp &o = gops[k];
       const uint32_t ES = esize<T, CVT>(o.dt);
-      const char *p = uniform_ptr(data + o.off +
+      const char *p = uniform_ptr(opnd(data, o, set) +
                                   ((uint64_t)pext_runs(Iu, o) + (uint32_t)stab[o.stab + s]) * ES);
       x = cmul(x, gload_dt<T, CVT>(p, s_lane[k * 64 + lane] * ES, o.dt));
     }
@@ -374,7 +402,7 @@ __device__ __forceinline__ void stream_unit(const DevGroup &G, const DevOp *__re
     for (int k = ks; k < ke; k++) {
       const DevOp &o = gops[k];
       const uint32_t ES = esize<T, CVT>(o.dt);
-      const char *p = uniform_ptr(data + o.off +
+      const char *p = uniform_ptr(opnd(data, o, set) +
                                   ((uint64_t)pext_runs(Iu, o) + (uint32_t)stab[o.stab + s]) * ES);
       x = cmul(x, gload_dt<T, CVT>(p, s_lane[k * 64 + lane] * ES, o.dt));
     }
@@ -384,7 +412,7 @@ __device__ __forceinline__ void stream_unit(const DevGroup &G, const DevOp *__re
   for (int b = 0; b < rls; b++) acc = cadd(acc, shfl_xor2(acc, 1 << b));
   if ((lane & ((1 << rls) - 1)) == 0) {
     const uint32_t o = (Iu >> L) | ((uint32_t)lane >> rls);
-    if (o < (1u << (G.w - L))) ((T *)(data + G.out_off))[o] = acc;
+    if (o < (1u << (G.w - L))) ((T *)outp(data, G, set))[o] = acc;
   }
 }
 
@@ -398,11 +426,12 @@ static_assert((kMfmaTM + kMfmaTN) * kMfmaLd * 8 <= kStreamMaxOps * 64 * 4,
 // Product of operands [k0, k1) at union index I, in complex64.
 template <bool CVT>
 __device__ __forceinline__ float2 op_product(const DevOp *__restrict__ gops, int k0, int k1,
-                                             const char *__restrict__ data, uint32_t I) {
+                                             const char *__restrict__ data, uint32_t I,
+                                             uint32_t set) {
   float2 v = make_float2(1.0f, 0.0f);
   for (int k = k0; k < k1; k++) {
     const DevOp &o = gops[k];
-    v = cmul(v, ld_elem<float2, CVT>(data + o.off, pext_runs(I, o), o.dt));
+    v = cmul(v, ld_elem<float2, CVT>(opnd(data, o, set), pext_runs(I, o), o.dt));
   }
   return v;
 }
@@ -418,7 +447,7 @@ __device__ __forceinline__ float2 op_product(const DevOp *__restrict__ gops, int
 template <bool CVT>
 __device__ void mfma_tile(const DevGroup &G, const DevOp *__restrict__ gops,
                           const uint8_t *__restrict__ bits, char *__restrict__ data,
-                          float2 *lds, uint32_t tile) {
+                          float2 *lds, uint32_t tile, uint32_t set) {
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int nM = G.n_mb, nN = G.n_nb, nB = G.n_bb, L = G.L;
   const uint32_t M = 1u << nM, N = 1u << nN, K = 1u << L;
@@ -439,14 +468,14 @@ __device__ void mfma_tile(const DevGroup &G, const DevOp *__restrict__ gops,
       const uint32_t row = e / kc, kk = e % kc, k = k0 + kk;
       float2 v = make_float2(0.0f, 0.0f);
       if (m0 + row < M && k < K)
-        v = op_product<CVT>(gops, 0, na, data, Ib | unit_bits(row, mpos, mlo) | k);
+        v = op_product<CVT>(gops, 0, na, data, Ib | unit_bits(row, mpos, mlo) | k, set);
       sA[row * kMfmaLd + kk] = v;
     }
     for (uint32_t e = tid; e < kMfmaTN * kc; e += kBlock) {
       const uint32_t col = e / kc, kk = e % kc, k = k0 + kk;
       float2 v = make_float2(0.0f, 0.0f);
       if (n0 + col < N && k < K)
-        v = op_product<CVT>(gops, na, na + nb, data, Ib | unit_bits(col, npos, nlo) | k);
+        v = op_product<CVT>(gops, na, na + nb, data, Ib | unit_bits(col, npos, nlo) | k, set);
       sB[col * kMfmaLd + kk] = v;
     }
     __syncthreads();
@@ -460,7 +489,7 @@ __device__ void mfma_tile(const DevGroup &G, const DevOp *__restrict__ gops,
     }
     __syncthreads();
   }
-  float2 *out = (float2 *)(data + G.out_off);
+  float2 *out = (float2 *)outp(data, G, set);
   const uint32_t col = lane & 15;
   if (n0 + col < N) {
     const uint32_t Ic = Ib | unit_bits(col, npos, nlo);
@@ -470,19 +499,20 @@ __device__ void mfma_tile(const DevGroup &G, const DevOp *__restrict__ gops,
       if (m0 + row < M) {
         float2 v = make_float2(t1[i] - t2[i], t3[i] - t1[i] - t2[i]);
         const uint32_t I = Ic | unit_bits(row, mpos, mlo);
-        if (no > 0) v = cmul(v, op_product<CVT>(gops, na + nb, na + nb + no, data, I));
+        if (no > 0) v = cmul(v, op_product<CVT>(gops, na + nb, na + nb + no, data, I, set));
         out[I >> L] = v;
       }
     }
   }
 }
 
-// One group's wave units [u0, u1) over the block's waves, in the group's
-// own precision.
+// One group's wave units [u0, u1) of angle set `set` over the block's waves,
+// in the group's own precision.
 __device__ __forceinline__ void run_group(const DevGroup &G, int g, const DevOp *__restrict__ ops,
                                           const int32_t *__restrict__ stab,
                                           const uint8_t *__restrict__ uperm, char *__restrict__ data,
-                                          uint32_t *s_lane, uint32_t u0, uint32_t u1) {
+                                          uint32_t *s_lane, uint32_t u0, uint32_t u1,
+                                          uint32_t set) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
   const DevOp *gops = ops + G.op_begin;
   const uint8_t *ub = uperm + 32 * g;
@@ -500,15 +530,17 @@ __device__ __forceinline__ void run_group(const DevGroup &G, int g, const DevOp 
   if (G.variant == kVarMfma) {
     // matrix form: a unit is one output tile, computed by the whole block
     if (G.cvt)
-      for (uint32_t u = u0; u < u1; u++) mfma_tile<true>(G, gops, ub, data, (float2 *)s_lane, u);
+      for (uint32_t u = u0; u < u1; u++)
+        mfma_tile<true>(G, gops, ub, data, (float2 *)s_lane, u, set);
     else
-      for (uint32_t u = u0; u < u1; u++) mfma_tile<false>(G, gops, ub, data, (float2 *)s_lane, u);
+      for (uint32_t u = u0; u < u1; u++)
+        mfma_tile<false>(G, gops, ub, data, (float2 *)s_lane, u, set);
   } else if (G.variant == kVarStream) {
     stream_setup(G, gops, s_lane);
     __syncthreads();
-    QTN_UNITS(stream_unit, G, gops, stab, ub, data, s_lane, u, lane);
+    QTN_UNITS(stream_unit, G, gops, stab, ub, data, s_lane, u, lane, set);
   } else {
-    QTN_UNITS(generic_unit, G, gops, ub, data, u, lane);
+    QTN_UNITS(generic_unit, G, gops, ub, data, u, lane, set);
   }
 #undef QTN_UNITS
   __syncthreads();
@@ -522,12 +554,14 @@ __global__ __launch_bounds__(kBlock) void k_block_groups(char *__restrict__ data
                                                          const int32_t *__restrict__ stab,
                                                          const uint8_t *__restrict__ uperm,
                                                          const int2 *__restrict__ ranges,
-                                                         int range_base) {
+                                                         int range_base, int n_ranges) {
   __shared__ __align__(16) uint32_t s_lane[kStreamMaxOps * 64];
-  const int2 rg = ranges[range_base + blockIdx.x];
+  // block b runs range b % n_ranges for angle set b / n_ranges
+  const uint32_t set = blockIdx.x / (uint32_t)n_ranges;
+  const int2 rg = ranges[range_base + (int)(blockIdx.x % (uint32_t)n_ranges)];
   for (int g = rg.x; g < rg.y; g++) {
     const DevGroup &G = groups[g];
-    run_group(G, g, ops, stab, uperm, data, s_lane, 0u, G.n_units);
+    run_group(G, g, ops, stab, uperm, data, s_lane, 0u, G.n_units, set);
   }
 }
 
@@ -546,19 +580,24 @@ __global__ __launch_bounds__(kBlock) void k_wide_stream(char *__restrict__ data,
                                                         const DevGroup *__restrict__ groups,
                                                         const DevOp *__restrict__ ops,
                                                         const int32_t *__restrict__ stab,
-                                                        const uint8_t *__restrict__ uperm, int gid) {
+                                                        const uint8_t *__restrict__ uperm, int gid,
+                                                        uint32_t n_sets) {
   __shared__ __align__(16) uint32_t s_lane[kStreamMaxOps * 64];
   const DevGroup &G = groups[gid];
   const DevOp *gops = ops + G.op_begin;
   const int lane = threadIdx.x & 63;
   uint32_t ub, ue;
-  wide_range(G.n_units, &ub, &ue);
+  wide_range(G.n_units * n_sets, &ub, &ue);
   const uint32_t nw = blockDim.x >> 6;
   const uint32_t w0 = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   stream_setup(G, gops, s_lane);
   __syncthreads();
-  for (uint32_t u = ub + w0; u < ue; u += nw)
-    stream_unit<T, CVT>(G, gops, stab, uperm + 32 * gid, data, s_lane, u, lane);
+  // flat unit f: angle set f / n_units, unit f % n_units
+  for (uint32_t f = ub + w0; f < ue; f += nw) {
+    const uint32_t set = f / G.n_units;
+    stream_unit<T, CVT>(G, gops, stab, uperm + 32 * gid, data, s_lane, f - set * G.n_units, lane,
+                        set);
+  }
 }
 
 template <class T, bool CVT>
@@ -567,29 +606,34 @@ __global__ __launch_bounds__(kBlock) void k_wide_generic(char *__restrict__ data
                                                          const DevOp *__restrict__ ops,
                                                          const int32_t *__restrict__ stab,
                                                          const uint8_t *__restrict__ uperm,
-                                                         int gid) {
+                                                         int gid, uint32_t n_sets) {
   const DevGroup &G = groups[gid];
   const DevOp *gops = ops + G.op_begin;
   const int lane = threadIdx.x & 63;
   uint32_t ub, ue;
-  wide_range(G.n_units, &ub, &ue);
+  wide_range(G.n_units * n_sets, &ub, &ue);
   const uint32_t nw = blockDim.x >> 6;
   const uint32_t w0 = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  for (uint32_t u = ub + w0; u < ue; u += nw)
-    generic_unit<T, CVT>(G, gops, uperm + 32 * gid, data, u, lane);
+  for (uint32_t f = ub + w0; f < ue; f += nw) {
+    const uint32_t set = f / G.n_units;
+    generic_unit<T, CVT>(G, gops, uperm + 32 * gid, data, f - set * G.n_units, lane, set);
+  }
 }
 
 template <bool CVT>
 __global__ __launch_bounds__(kBlock) void k_wide_mfma(char *__restrict__ data,
                                                       const DevGroup *__restrict__ groups,
                                                       const DevOp *__restrict__ ops,
-                                                      const uint8_t *__restrict__ uperm, int gid) {
+                                                      const uint8_t *__restrict__ uperm, int gid,
+                                                      uint32_t n_sets) {
   __shared__ __align__(16) float2 s_tile[(kMfmaTM + kMfmaTN) * kMfmaLd];
   const DevGroup &G = groups[gid];
   uint32_t ub, ue;
-  wide_range(G.n_units, &ub, &ue);
-  for (uint32_t t = ub; t < ue; t++)
-    mfma_tile<CVT>(G, ops + G.op_begin, uperm + 32 * gid, data, s_tile, t);
+  wide_range(G.n_units * n_sets, &ub, &ue);
+  for (uint32_t f = ub; f < ue; f++) {
+    const uint32_t set = f / G.n_units;
+    mfma_tile<CVT>(G, ops + G.op_begin, uperm + 32 * gid, data, s_tile, f - set * G.n_units, set);
+  }
 }
 
 // ----------------------------------------------------- persistent executor
@@ -607,7 +651,7 @@ __device__ __forceinline__ void run_item(int4 it, char *__restrict__ data,
     const DevGroup &G = groups[g];
     const uint32_t u0 = chunk ? (uint32_t)it.z : 0u;
     const uint32_t u1 = chunk ? min((uint32_t)it.w, G.n_units) : G.n_units;
-    run_group(G, g, ops, stab, uperm, data, s_lane, u0, u1);
+    run_group(G, g, ops, stab, uperm, data, s_lane, u0, u1, 0u);
   }
 }
 
@@ -837,18 +881,27 @@ __device__ void fill_table(T *table, const double *gamma, const double *beta, in
   }
 }
 
+// Block b fills network b % n_nets for angle set b / n_nets; the angles of
+// set s start at angles + s * n_angles.
 __global__ void k_fill(char *__restrict__ data, const double *__restrict__ angles,
-                       const FillDesc *__restrict__ fills) {
-  const FillDesc f = fills[blockIdx.x];
-  const double *gamma = angles + f.angle_off, *beta = gamma + f.p;
-  if (f.table128 >= 0) fill_table<double2>((double2 *)(data + f.table128), gamma, beta, f.p);
-  if (f.table64 >= 0) fill_table<float2>((float2 *)(data + f.table64), gamma, beta, f.p);
+                       const FillDesc *__restrict__ fills, int n_nets, int n_angles) {
+  const int set = blockIdx.x / n_nets;
+  const FillDesc f = fills[blockIdx.x % n_nets];
+  const double *gamma = angles + (int64_t)set * n_angles + f.angle_off, *beta = gamma + f.p;
+  if (f.table128 >= 0)
+    fill_table<double2>((double2 *)(data + f.table128 + set * f.sstride128), gamma, beta, f.p);
+  if (f.table64 >= 0)
+    fill_table<float2>((float2 *)(data + f.table64 + set * f.sstride64), gamma, beta, f.p);
 }
 
+// Block s reduces angle set s: its scalar slots start scalar_sstride bytes
+// after those of set s - 1, its results 2 n_cones + n_nets doubles after.
 template <class T>
-__global__ void k_reduce(const T *__restrict__ scalars, const int *__restrict__ csb,
-                         const int *__restrict__ ncb, int n_cones, int n_nets,
-                         double *__restrict__ res) {
+__global__ void k_reduce(const char *__restrict__ scalar_base, int64_t scalar_sstride,
+                         const int *__restrict__ csb, const int *__restrict__ ncb, int n_cones,
+                         int n_nets, double *__restrict__ res_base) {
+  const T *scalars = (const T *)(scalar_base + blockIdx.x * scalar_sstride);
+  double *res = res_base + (int64_t)blockIdx.x * (2 * n_cones + n_nets);
   for (int c = threadIdx.x; c < n_cones; c += blockDim.x) {
     double re = 1.0, im = 0.0;
     for (int s = csb[c]; s < csb[c + 1]; s++) {
@@ -900,59 +953,63 @@ inline hipError_t no_launch(hipEvent_t t0, hipEvent_t t1, hipStream_t s) {
 }
 
 hipError_t launch_fill(int prec, void *data, const double *angles, const FillDesc *fills,
-                       int n_nets, hipStream_t s) {
+                       int n_nets, int n_angles, int n_sets, hipStream_t s) {
   (void)prec;
-  hipLaunchKernelGGL(k_fill, dim3(n_nets), dim3(64), 0, s, (char *)data, angles, fills);
+  hipLaunchKernelGGL(k_fill, dim3(n_nets * n_sets), dim3(64), 0, s, (char *)data, angles, fills,
+                     n_nets, n_angles);
   return hipGetLastError();
 }
 
 hipError_t launch_block_groups(int prec, void *data, const DevGroup *groups, const DevOp *ops,
                                const int32_t *stab, const uint8_t *uperm, const int2 *ranges,
-                               int range_base, int n_blocks, hipStream_t s, hipEvent_t t0,
-                               hipEvent_t t1) {
+                               int range_base, int n_blocks, int n_sets, hipStream_t s,
+                               hipEvent_t t0, hipEvent_t t1) {
   (void)prec;
-  if (n_blocks <= 0) return no_launch(t0, t1, s);
-  QTN_LAUNCH(t0, t1, k_block_groups, dim3(n_blocks), dim3(kBlock), s, (char *)data, groups, ops,
-             stab, uperm, ranges, range_base);
+  if (n_blocks <= 0 || n_sets <= 0) return no_launch(t0, t1, s);
+  QTN_LAUNCH(t0, t1, k_block_groups, dim3(n_blocks * n_sets), dim3(kBlock), s, (char *)data,
+             groups, ops, stab, uperm, ranges, range_base, n_blocks);
   return hipGetLastError();
 }
 
 template <class T, bool CVT>
 void launch_wide_t(int variant, int nb, char *d, const DevGroup *groups, const DevOp *ops,
-                   const int32_t *stab, const uint8_t *uperm, int group, hipStream_t s,
-                   hipEvent_t t0, hipEvent_t t1) {
+                   const int32_t *stab, const uint8_t *uperm, int group, uint32_t n_sets,
+                   hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
   if (variant == kVarStream)
     QTN_LAUNCH(t0, t1, (k_wide_stream<T, CVT>), dim3(nb), dim3(kBlock), s, d, groups, ops, stab,
-               uperm, group);
+               uperm, group, n_sets);
   else
     QTN_LAUNCH(t0, t1, (k_wide_generic<T, CVT>), dim3(nb), dim3(kBlock), s, d, groups, ops, stab,
-               uperm, group);
+               uperm, group, n_sets);
 }
 
 hipError_t launch_wide_group(int prec, bool cvt, int variant, void *data, const DevGroup *groups,
                              const DevOp *ops, const int32_t *stab, const uint8_t *uperm,
-                             int group, uint32_t n_units, hipStream_t s, hipEvent_t t0,
-                             hipEvent_t t1) {
-  const int nb = wide_blocks(n_units);
+                             int group, uint32_t n_units, int n_sets, hipStream_t s,
+                             hipEvent_t t0, hipEvent_t t1) {
+  if (n_sets <= 0 || (uint64_t)n_units * (uint64_t)n_sets > 0xFFFFFFFFull)
+    return hipErrorInvalidValue;
+  const uint32_t ns = (uint32_t)n_sets;
+  const int nb = wide_blocks(n_units * ns);
   char *d = (char *)data;
   if (variant == kVarMfma) {
     if (prec != kPrecC64) return hipErrorInvalidValue;  // complex64 arithmetic only
     if (cvt)
       QTN_LAUNCH(t0, t1, k_wide_mfma<true>, dim3(nb), dim3(kBlock), s, d, groups, ops, uperm,
-                 group);
+                 group, ns);
     else
       QTN_LAUNCH(t0, t1, k_wide_mfma<false>, dim3(nb), dim3(kBlock), s, d, groups, ops, uperm,
-                 group);
+                 group, ns);
     return hipGetLastError();
   }
   if (prec == kPrecC128 && !cvt)
-    launch_wide_t<double2, false>(variant, nb, d, groups, ops, stab, uperm, group, s, t0, t1);
+    launch_wide_t<double2, false>(variant, nb, d, groups, ops, stab, uperm, group, ns, s, t0, t1);
   else if (prec == kPrecC128)
-    launch_wide_t<double2, true>(variant, nb, d, groups, ops, stab, uperm, group, s, t0, t1);
+    launch_wide_t<double2, true>(variant, nb, d, groups, ops, stab, uperm, group, ns, s, t0, t1);
   else if (!cvt)
-    launch_wide_t<float2, false>(variant, nb, d, groups, ops, stab, uperm, group, s, t0, t1);
+    launch_wide_t<float2, false>(variant, nb, d, groups, ops, stab, uperm, group, ns, s, t0, t1);
   else
-    launch_wide_t<float2, true>(variant, nb, d, groups, ops, stab, uperm, group, s, t0, t1);
+    launch_wide_t<float2, true>(variant, nb, d, groups, ops, stab, uperm, group, ns, s, t0, t1);
   return hipGetLastError();
 }
 
@@ -997,15 +1054,16 @@ int persistent_blocks(int prec, int n_cu) {
   return per_cu * n_cu;
 }
 
-hipError_t launch_reduce(int prec, const void *data, int64_t scalar_off, const int *csb,
-                         const int *ncb, int n_cones, int n_nets, double *res, hipStream_t s) {
+hipError_t launch_reduce(int prec, const void *data, int64_t scalar_off, int64_t scalar_sstride,
+                         const int *csb, const int *ncb, int n_cones, int n_nets, int n_sets,
+                         double *res, hipStream_t s) {
   const char *sc = (const char *)data + scalar_off;
   if (prec == kPrecC64)
-    hipLaunchKernelGGL(k_reduce<float2>, dim3(1), dim3(256), 0, s, (const float2 *)sc, csb, ncb,
-                       n_cones, n_nets, res);
+    hipLaunchKernelGGL(k_reduce<float2>, dim3(n_sets), dim3(256), 0, s, sc, scalar_sstride, csb,
+                       ncb, n_cones, n_nets, res);
   else
-    hipLaunchKernelGGL(k_reduce<double2>, dim3(1), dim3(256), 0, s, (const double2 *)sc, csb, ncb,
-                       n_cones, n_nets, res);
+    hipLaunchKernelGGL(k_reduce<double2>, dim3(n_sets), dim3(256), 0, s, sc, scalar_sstride, csb,
+                       ncb, n_cones, n_nets, res);
   return hipGetLastError();
 }
 

@@ -16,22 +16,26 @@ enum Precision : int { kPrecC128 = 0, kPrecC64 = 1, kPrecMixed = 2 };
 
 // One block per network: fills that network's gate table from its angles.
 struct FillDesc {
-  int64_t angle_off;  // doubles from the angle base: gamma[p] then beta[p]
-  int64_t table128;   // byte offset of the complex128 gate table, or -1
-  int64_t table64;    // byte offset of the complex64 gate table, or -1
+  int64_t angle_off;  // doubles from an angle set's base: gamma[p] then beta[p]
+  int64_t table128;   // byte offset of the complex128 gate table (set 0), or -1
+  int64_t table64;    // byte offset of the complex64 gate table (set 0), or -1
+  int64_t sstride128, sstride64;  // bytes between angle sets' tables
   int32_t p, pad;
 };
 
+// n_sets angle sets of n_angles doubles each, set after set.
 hipError_t launch_fill(int prec, void *data, const double *angles,
-                       const FillDesc *fills, int n_nets, hipStream_t s);
+                       const FillDesc *fills, int n_nets, int n_angles, int n_sets,
+                       hipStream_t s);
 
-// Groups [ranges[b].x, ranges[b].y) run in order inside block b, for
-// b in [range_base, range_base + n_blocks).  uperm holds 32 bytes per group:
-// the union bit of each wave-unit bit.
+// Groups [ranges[b].x, ranges[b].y) run in order inside one block, for
+// b in [range_base, range_base + n_blocks), once per angle set (n_blocks *
+// n_sets blocks).  uperm holds 32 bytes per group: the union bit of each
+// wave-unit bit.
 hipError_t launch_block_groups(int prec, void *data, const DevGroup *groups,
                                const DevOp *ops, const int32_t *stab,
                                const uint8_t *uperm, const int2 *ranges,
-                               int range_base, int n_blocks, hipStream_t s,
+                               int range_base, int n_blocks, int n_sets, hipStream_t s,
                                hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 
 // One group over the whole grid, with the kernel of its mapping variant, in
@@ -39,8 +43,8 @@ hipError_t launch_block_groups(int prec, void *data, const DevGroup *groups,
 hipError_t launch_wide_group(int prec, bool cvt, int variant, void *data,
                              const DevGroup *groups, const DevOp *ops,
                              const int32_t *stab, const uint8_t *uperm, int group,
-                             uint32_t n_units, hipStream_t s, hipEvent_t t0 = nullptr,
-                             hipEvent_t t1 = nullptr);
+                             uint32_t n_units, int n_sets, hipStream_t s,
+                             hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 
 // Clears the control words, then runs every light cone's task list in
 // lockstep inside one persistent launch of n_blocks resident blocks.
@@ -77,10 +81,11 @@ int persistent_blocks(int prec, int n_cu);
 // complex128, starting scalar_off bytes into data.
 // Per light cone: product of its scalar slots -> e_jk (FP64); per network:
 // E = |E|/2 - 1/2 sum Re e_jk with Neumaier compensation.
-// res: [n_cones] Re, [n_cones] Im, [n_nets] energies.
+// res: per angle set [n_cones] Re, [n_cones] Im, [n_nets] energies.
 hipError_t launch_reduce(int prec, const void *data, int64_t scalar_off,
-                         const int *cone_scalar_begin, const int *net_cone_begin,
-                         int n_cones, int n_nets, double *res, hipStream_t s);
+                         int64_t scalar_sstride, const int *cone_scalar_begin,
+                         const int *net_cone_begin, int n_cones, int n_nets, int n_sets,
+                         double *res, hipStream_t s);
 
 // Grid size used for a wide group.
 int wide_blocks(uint32_t n_units);

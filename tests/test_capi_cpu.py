@@ -254,3 +254,29 @@ def test_tune_picks_round_trip_and_validation(qtn):
     net.set_tune_picks(mf)
     assert net.stats()["n_matrix"] > 0
     net.close()
+
+
+def test_angle_batch_workspace_and_validation(qtn):
+    from paper_2204_06045_amd import _capi
+    inst = qs.instance(16, 3, 3, 2)
+    g, b = inst["angles"][0]
+    net = qtn.Network(16, inst["edges"], g, b)
+    net.plan(qtn.QTN_C128)
+    w1, w4, w8 = (net.angles_workspace(k) for k in (1, 4, 8))
+    # one data copy per set on top of fixed descriptors
+    assert w1 <= net.ws_bytes and w1 < w4 < w8
+    assert abs((w8 - w4) - (w4 - w1) * 4 / 3) < 4096 * 8
+    for bad in (0, 1025):
+        with pytest.raises(qtn.QtnError) as ei:
+            net.angles_workspace(bad)
+        assert ei.value.code == -1
+    lib = _capi.lib()
+    pd = ctypes.POINTER(ctypes.c_double)
+    gs = np.array([[0.1, 0.2, float("nan")]])
+    bs = np.zeros((1, 3))
+    en = np.full(1, 7.0)
+    rc = lib.qtn_contract_angles(net.h, ctypes.c_void_p(256), 1 << 30, None, 1,
+                                 gs.ctypes.data_as(pd), bs.ctypes.data_as(pd), None,
+                                 en.ctypes.data_as(pd))
+    assert rc == -1 and "finite" in qtn.qtn_last_error() and en[0] == 7.0
+    net.close()

@@ -363,3 +363,48 @@ def test_stored_tuning_reapplies(qtn, orc, gpu):
     _check(zb, None, eb, ref, ref_en, 1, "stored tuning")
     a.close()
     bnet.close()
+
+
+@pytest.mark.parametrize("prec,cfg", [
+    (0, dict()), (0, dict(small_width=4)), (0, dict(small_width=4, variant=2, lane_sum_bits=1)),
+    (1, dict(small_width=4, variant=3)), (2, dict(small_width=4, mixed_width=8)),
+    (0, dict(executor=3, small_width=8)), (0, dict(executor=2)), (0, dict(eager=True))])
+def test_angle_batch_matches_single_sets(qtn, orc, gpu, prec, cfg):
+    """Several angle sets in one pass: every set equals its own single-set
+    evaluation bit for bit, and the oracle to the tolerance."""
+    inst = qs.instance(16, 3, 3, 9, 5)
+    e = inst["edges"]
+    gs = np.array([a[0] for a in inst["angles"]])
+    bs = np.array([a[1] for a in inst["angles"]])
+    net = qtn.Network(16, e, gs[0], bs[0], **cfg)
+    net.plan(prec)
+    print(f"angle batch prec={prec} cfg={cfg}", flush=True)
+    zz, en = net.contract_angles(gs, bs)
+    assert zz.shape == (5, len(e)) and en.shape == (5,)
+    for k in range(5):
+        net.set_angles(gs[k], bs[k])
+        z1, _, e1 = net.contract()
+        assert np.array_equal(z1, zz[k]) and e1 == en[k], k
+        ref, ref_en = orc.energy(16, e, gs[k], bs[k], threads=8)
+        _check(zz[k], None, en[k], ref, ref_en, prec, f"set {k}")
+    # a different set count reuses the plan with a new layout
+    zz2, en2 = net.contract_angles(gs[:2], bs[:2])
+    assert np.array_equal(zz2, zz[:2]) and np.array_equal(en2, en[:2])
+    net.close()
+
+
+def test_angle_batch_full_size(qtn, gpu):
+    """N=30 p=4 with the stored oracle angles as one of four sets."""
+    gd = _golden("cfg2")
+    inst = qs.instance(30, 3, 4, 0, 4)
+    gs = np.array([gd["gamma"]] + [a[0] for a in inst["angles"][1:]])
+    bs = np.array([gd["beta"]] + [a[1] for a in inst["angles"][1:]])
+    net = qtn.Network(gd["n"], gd["edges"], gd["gamma"], gd["beta"], order_trials=16)
+    net.plan(0)
+    zz, en = net.contract_angles(gs, bs)
+    _check(zz[0], None, en[0], gd["zz_re"], gd["energy"], 0, "angle batch set 0")
+    for k in range(1, 4):
+        net.set_angles(gs[k], bs[k])
+        z1, _, e1 = net.contract()
+        assert np.array_equal(z1, zz[k]) and e1 == en[k]
+    net.close()
