@@ -29,6 +29,8 @@
 // Matrix form (kVarMfma, complex64).  A group whose operands reduce to two
 // factors over the summed indices is a batched complex matrix product; it
 // runs as three real FP32 products on the matrix cores (3M).
+#include <cstddef>
+
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
@@ -94,12 +96,75 @@ template <> __device__ __forceinline__ float2 ld_elem<float2, true>(const char *
   return make_float2((float)v.x, (float)v.y);
 }
 
+// Descriptor fields are read as 32-bit words: at wave-uniform addresses these
+// become scalar loads, while sub-dword fields would be vector loads on the
+// critical path of every operand.
+__device__ __forceinline__ uint32_t dword(const void *p, int i) {
+  return reinterpret_cast<const uint32_t *>(p)[i];
+}
+static_assert(offsetof(DevOp, level) == 24 && offsetof(DevOp, dt) == 27 &&
+                  offsetof(DevOp, run) == 28,
+              "DevOp word layout");
+__device__ __forceinline__ int op_nruns(const DevOp &o) { return (dword(&o, 6) >> 8) & 0xFFu; }
+__device__ __forceinline__ int op_dt(const DevOp &o) { return dword(&o, 6) >> 24; }
+__device__ __forceinline__ uint32_t op_run(const DevOp &o, int i) {
+  return (dword(&o, 7 + (i >> 1)) >> ((i & 1) * 16)) & 0xFFFFu;
+}
+// Union position of wave-unit bit j from a group's 32-byte unit-bit table.
+__device__ __forceinline__ uint32_t ubit_at(const uint8_t *ub, int j) {
+  return (dword(ub, j >> 2) >> ((j & 3) * 8)) & 0xFFu;
+}
+
+// A group's header unpacked from its descriptor words (wave-uniform values).
+struct GI {
+  int64_t out_off, out_sstride;
+  uint32_t op_begin, n_units;
+  int w, L, n_ops, variant, rls, sl, lk, n_unit, n_step, n_serial, n_step0;
+  int n_ubits, prec, cvt, n_mb, n_nb, n_bb;
+  uint32_t le_lo, le_hi;  // level_end[0..3], [4..7]
+  __device__ int le(int l) const { return ((l < 4 ? le_lo >> (8 * l) : le_hi >> (8 * (l - 4)))) & 0xFF; }
+};
+static_assert(offsetof(DevGroup, w) == 24 && offsetof(DevGroup, rls) == 28 &&
+                  offsetof(DevGroup, n_step) == 32 && offsetof(DevGroup, level_end) == 36 &&
+                  offsetof(DevGroup, n_ubits) == 44 && offsetof(DevGroup, n_nb) == 48,
+              "DevGroup word layout");
+__device__ __forceinline__ GI load_group(const DevGroup *g) {
+  GI G;
+  const uint32_t w0 = dword(g, 0), w1 = dword(g, 1), w2 = dword(g, 2), w3 = dword(g, 3);
+  G.out_off = (int64_t)(((uint64_t)w1 << 32) | w0);
+  G.out_sstride = (int64_t)(((uint64_t)w3 << 32) | w2);
+  G.op_begin = dword(g, 4);
+  G.n_units = dword(g, 5);
+  const uint32_t a = dword(g, 6), b = dword(g, 7), c = dword(g, 8), e = dword(g, 11),
+                 f = dword(g, 12);
+  G.w = a & 0xFF;
+  G.L = (a >> 8) & 0xFF;
+  G.n_ops = (a >> 16) & 0xFF;
+  G.variant = a >> 24;
+  G.rls = b & 0xFF;
+  G.sl = (b >> 8) & 0xFF;
+  G.lk = (b >> 16) & 0xFF;
+  G.n_unit = b >> 24;
+  G.n_step = c & 0xFF;
+  G.n_serial = (c >> 8) & 0xFF;
+  G.n_step0 = (c >> 16) & 0xFF;
+  G.le_lo = dword(g, 9);
+  G.le_hi = dword(g, 10);
+  G.n_ubits = e & 0xFF;
+  G.prec = (e >> 8) & 0xFF;
+  G.cvt = (e >> 16) & 0xFF;
+  G.n_mb = e >> 24;
+  G.n_nb = f & 0xFF;
+  G.n_bb = (f >> 8) & 0xFF;
+  return G;
+}
+
 // pext(x, mask) from the operand's packed runs (wave-uniform loop bounds).
 __device__ __forceinline__ uint32_t pext_runs(uint32_t x, const DevOp &o) {
   uint32_t r = 0;
-  const int nr = o.nruns;
+  const int nr = op_nruns(o);
   for (int i = 0; i < nr; i++) {
-    const uint32_t rr = o.run[i];
+    const uint32_t rr = op_run(o, i);
     const uint32_t src = rr & 31u, len = (rr >> 5) & 63u, dst = rr >> 11;
     r |= ((x >> src) & (uint32_t)((1ull << len) - 1ull)) << dst;
   }
@@ -110,7 +175,7 @@ __device__ __forceinline__ uint32_t pext_runs(uint32_t x, const DevOp &o) {
 __device__ __forceinline__ const char *opnd(const char *data, const DevOp &o, uint32_t set) {
   return data + o.off + (int64_t)set * o.sstride;
 }
-__device__ __forceinline__ char *outp(char *data, const DevGroup &G, uint32_t set) {
+__device__ __forceinline__ char *outp(char *data, const GI &G, uint32_t set) {
   return data + G.out_off + (int64_t)set * G.out_sstride;
 }
 
@@ -118,9 +183,10 @@ __device__ __forceinline__ char *outp(char *data, const DevGroup &G, uint32_t se
 // planner orders the unit bits so that bits some large operand lacks come
 // first, and units that reuse an operand's data run next to each other).
 __device__ __forceinline__ uint32_t unit_bits(uint32_t u, const uint8_t *__restrict__ ubit,
-                                              int n) {
+                                              int n, int first = 0) {
+  // ubit is a group's 4-byte aligned table; bits first..first+n-1 are used
   uint32_t I = 0;
-  for (int j = 0; j < n; j++) I |= ((u >> j) & 1u) << ubit[j];
+  for (int j = 0; j < n; j++) I |= ((u >> j) & 1u) << ubit_at(ubit, first + j);
   return I;
 }
 
@@ -138,7 +204,7 @@ __device__ __forceinline__ uint32_t pext_reg(uint32_t x, uint32_t m) {
 }
 
 template <class T, bool CVT>
-__device__ __forceinline__ void generic_unit(const DevGroup &G, const DevOp *__restrict__ gops,
+__device__ __forceinline__ void generic_unit(const GI &G, const DevOp *__restrict__ gops,
                                              const uint8_t *__restrict__ ubit, char *__restrict__ data,
                                              uint32_t u, int lane, uint32_t set) {
   constexpr int RG = kGenRegBits, NR = 1 << RG;
@@ -150,12 +216,12 @@ __device__ __forceinline__ void generic_unit(const DevGroup &G, const DevOp *__r
     const uint32_t base = pext_runs(I0, o);
     const char *src = opnd(data, o, set);
 #pragma unroll
-    for (int r = 0; r < NR; r++) v[r] = ld_elem<T, CVT>(src, base + pext_reg(r, o.mask), o.dt);
+    for (int r = 0; r < NR; r++) v[r] = ld_elem<T, CVT>(src, base + pext_reg(r, o.mask), op_dt(o));
   }
   // the other leaf operands, kGenBatch at a time: all of their loads are
   // issued before the first multiply, so their latencies overlap
   int k = 1;
-  const int e0 = G.level_end[0];
+  const int e0 = G.le(0);
   for (; k + kGenBatch <= e0; k += kGenBatch) {
     T x[kGenBatch][NR];
 #pragma unroll
@@ -164,7 +230,7 @@ __device__ __forceinline__ void generic_unit(const DevGroup &G, const DevOp *__r
       const uint32_t base = pext_runs(I0, o);
       const char *src = opnd(data, o, set);
 #pragma unroll
-      for (int r = 0; r < NR; r++) x[j][r] = ld_elem<T, CVT>(src, base + pext_reg(r, o.mask), o.dt);
+      for (int r = 0; r < NR; r++) x[j][r] = ld_elem<T, CVT>(src, base + pext_reg(r, o.mask), op_dt(o));
     }
 #pragma unroll
     for (int j = 0; j < kGenBatch; j++)
@@ -177,7 +243,7 @@ __device__ __forceinline__ void generic_unit(const DevGroup &G, const DevOp *__r
     const char *src = opnd(data, o, set);
 #pragma unroll
     for (int r = 0; r < NR; r++)
-      v[r] = cmul(v[r], ld_elem<T, CVT>(src, base + pext_reg(r, o.mask), o.dt));
+      v[r] = cmul(v[r], ld_elem<T, CVT>(src, base + pext_reg(r, o.mask), op_dt(o)));
   }
 #pragma unroll
   for (int s = 0; s < RG; s++) {
@@ -185,13 +251,13 @@ __device__ __forceinline__ void generic_unit(const DevGroup &G, const DevOp *__r
 #pragma unroll
       for (int r = 0; r < (NR >> (s + 1)); r++) v[r] = cadd(v[2 * r], v[2 * r + 1]);
       if (s + 1 < L) {
-        for (; k < G.level_end[s + 1]; k++) {
+        for (; k < G.le(s + 1); k++) {
           const DevOp &o = gops[k];
           const uint32_t base = pext_runs(I0, o);
           const char *src = opnd(data, o, set);
 #pragma unroll
           for (int r = 0; r < (NR >> (s + 1)); r++)
-            v[r] = cmul(v[r], ld_elem<T, CVT>(src, base + pext_reg((uint32_t)r << (s + 1), o.mask), o.dt));
+            v[r] = cmul(v[r], ld_elem<T, CVT>(src, base + pext_reg((uint32_t)r << (s + 1), o.mask), op_dt(o)));
         }
       }
     }
@@ -209,9 +275,9 @@ __device__ __forceinline__ void generic_unit(const DevGroup &G, const DevOp *__r
   for (int s = RG; s < L; s++) {
     acc = cadd(acc, shfl_xor2(acc, 1 << (s - RG)));
     if (s + 1 < L) {
-      for (; k < G.level_end[s + 1]; k++) {
+      for (; k < G.le(s + 1); k++) {
         const DevOp &o = gops[k];
-        acc = cmul(acc, ld_elem<T, CVT>(opnd(data, o, set), pext_runs(I0, o), o.dt));
+        acc = cmul(acc, ld_elem<T, CVT>(opnd(data, o, set), pext_runs(I0, o), op_dt(o)));
       }
     }
   }
@@ -224,7 +290,7 @@ __device__ __forceinline__ void generic_unit(const DevGroup &G, const DevOp *__r
 // ---------------------------------------------------------------- streaming
 
 // Lane parts of every operand of the group: pext of the lane bits.
-__device__ __forceinline__ void stream_setup(const DevGroup &G, const DevOp *__restrict__ gops,
+__device__ __forceinline__ void stream_setup(const GI &G, const DevOp *__restrict__ gops,
                                              uint32_t *s_lane) {
   const uint32_t rls = G.rls, L = G.L;
   for (int e = threadIdx.x; e < G.n_ops * 64; e += blockDim.x) {
@@ -298,7 +364,7 @@ __device__ __forceinline__ T gload_dt(const char *base, uint32_t off, int dt) {
 // one entry per lane and are read with readlane, so a step's loads issue
 // back to back from scalar bases.
 template <class T, bool CVT>
-__device__ __forceinline__ void stream_unit(const DevGroup &G, const DevOp *__restrict__ gops,
+__device__ __forceinline__ void stream_unit(const GI &G, const DevOp *__restrict__ gops,
                                             const int32_t *__restrict__ stab,
                                             const uint8_t *__restrict__ ubit, char *__restrict__ data,
                                             const uint32_t *s_lane, uint32_t u, int lane,
@@ -311,23 +377,23 @@ __device__ __forceinline__ void stream_unit(const DevGroup &G, const DevOp *__re
   T c0 = one, c1 = one;
   for (int k = 0; k < G.n_unit; k++) {
     const DevOp &o = gops[k];
-    const uint32_t ES = esize<T, CVT>(o.dt);
+    const uint32_t ES = esize<T, CVT>(op_dt(o));
     const char *p = uniform_ptr(opnd(data, o, set) + (uint64_t)pext_runs(Iu, o) * ES);
     const uint32_t lb = s_lane[k * 64 + lane] * ES;
-    const T x0 = gload_dt<T, CVT>(p, lb, o.dt);
-    const T x1 = gload_dt<T, CVT>(p, lb + ((o.mask & 1u) ? ES : 0u), o.dt);
+    const T x0 = gload_dt<T, CVT>(p, lb, op_dt(o));
+    const T x1 = gload_dt<T, CVT>(p, lb + ((o.mask & 1u) ? ES : 0u), op_dt(o));
     c0 = cmul(c0, x0);
     c1 = cmul(c1, x1);
   }
   // U(s) for s = lane: product of the uniform-class operands at step s
-  const int ku = G.n_unit + G.n_step, ks = ku + G.level_end[0];
+  const int ku = G.n_unit + G.n_step, ks = ku + G.le(0);
   T U = one;
   for (int k = ku; k < ks; k++) {
     const DevOp &o = gops[k];
-    const uint32_t ES = esize<T, CVT>(o.dt);
+    const uint32_t ES = esize<T, CVT>(op_dt(o));
     const char *p = uniform_ptr(opnd(data, o, set) + (uint64_t)pext_runs(Iu, o) * ES);
     const uint32_t off = lane_step ? (uint32_t)stab[o.stab + lane] * ES : 0u;
-    U = cmul(U, gload_dt<T, CVT>(p, off, o.dt));
+    U = cmul(U, gload_dt<T, CVT>(p, off, op_dt(o)));
   }
   // unrolled step-class operands: scalar base, per-lane byte offset, serial
   // offsets one per lane
@@ -346,8 +412,8 @@ __device__ __forceinline__ void stream_unit(const DevGroup &G, const DevOp *__re
     dt[i] = 0;
     if (i < n_step) {
       const DevOp &o = gops[kb + i];
-      const uint32_t ES = esize<T, CVT>(o.dt);
-      dt[i] = o.dt;
+      const uint32_t ES = esize<T, CVT>(op_dt(o));
+      dt[i] = op_dt(o);
       pb[i] = uniform_ptr(opnd(data, o, set) + (uint64_t)pext_runs(Iu, o) * ES);
       lb[i] = s_lane[(kb + i) * 64 + lane] * ES;
       tb[i] = lane_step ? (uint32_t)stab[o.stab + lane] * ES : 0u;
@@ -355,7 +421,7 @@ __device__ __forceinline__ void stream_unit(const DevGroup &G, const DevOp *__re
       h0b[i] = h0[i] ? ES : 0u;
     }
   }
-  const int ke = ks + G.n_serial - G.level_end[0];  // end of serial-class ops
+  const int ke = ks + G.n_serial - G.le(0);  // end of serial-class ops
   T acc = make_c<T>(0.0, 0.0);
   for (uint32_t s = 0; s < nsteps; s++) {
     T e0[kStepOps], e1[kStepOps];
@@ -380,12 +446,12 @@ __device__ __forceinline__ void stream_unit(const DevGroup &G, const DevOp *__re
     const int k_extra = kb + kStepOps, k_h0_end = kb + G.n_step0;
     for (int k = k_extra; k < k_h0_end; k++) {
       const DevOp &o = gops[k];
-      const uint32_t ES = esize<T, CVT>(o.dt);
+      const uint32_t ES = esize<T, CVT>(op_dt(o));
       const char *p = uniform_ptr(opnd(data, o, set) +
                                   ((uint64_t)pext_runs(Iu, o) + (uint32_t)stab[o.stab + s]) * ES);
       const uint32_t l = s_lane[k * 64 + lane] * ES;
-      v0 = cmul(v0, gload_dt<T, CVT>(p, l, o.dt));
-      v1 = cmul(v1, gload_dt<T, CVT>(p, l + ES, o.dt));
+      v0 = cmul(v0, gload_dt<T, CVT>(p, l, op_dt(o)));
+      v1 = cmul(v1, gload_dt<T, CVT>(p, l + ES, op_dt(o)));
     }
     T x = cadd(v0, v1);  // bit 0 summed in registers
 #pragma unroll
@@ -393,18 +459,18 @@ __device__ __forceinline__ void stream_unit(const DevGroup &G, const DevOp *__re
       if (i < n_step && !h0[i]) x = cmul(x, e0[i]);
     for (int k = max(k_extra, k_h0_end); k < kb + n_step; k++) {
       const DevOp &o = gops[k];
-      const uint32_t ES = esize<T, CVT>(o.dt);
+      const uint32_t ES = esize<T, CVT>(op_dt(o));
       const char *p = uniform_ptr(opnd(data, o, set) +
                                   ((uint64_t)pext_runs(Iu, o) + (uint32_t)stab[o.stab + s]) * ES);
-      x = cmul(x, gload_dt<T, CVT>(p, s_lane[k * 64 + lane] * ES, o.dt));
+      x = cmul(x, gload_dt<T, CVT>(p, s_lane[k * 64 + lane] * ES, op_dt(o)));
     }
     if (sl > 0) x = cmul(x, readlane2(U, s));
     for (int k = ks; k < ke; k++) {
       const DevOp &o = gops[k];
-      const uint32_t ES = esize<T, CVT>(o.dt);
+      const uint32_t ES = esize<T, CVT>(op_dt(o));
       const char *p = uniform_ptr(opnd(data, o, set) +
                                   ((uint64_t)pext_runs(Iu, o) + (uint32_t)stab[o.stab + s]) * ES);
-      x = cmul(x, gload_dt<T, CVT>(p, s_lane[k * 64 + lane] * ES, o.dt));
+      x = cmul(x, gload_dt<T, CVT>(p, s_lane[k * 64 + lane] * ES, op_dt(o)));
     }
     acc = cadd(acc, x);
   }
@@ -431,7 +497,7 @@ __device__ __forceinline__ float2 op_product(const DevOp *__restrict__ gops, int
   float2 v = make_float2(1.0f, 0.0f);
   for (int k = k0; k < k1; k++) {
     const DevOp &o = gops[k];
-    v = cmul(v, ld_elem<float2, CVT>(opnd(data, o, set), pext_runs(I, o), o.dt));
+    v = cmul(v, ld_elem<float2, CVT>(opnd(data, o, set), pext_runs(I, o), op_dt(o)));
   }
   return v;
 }
@@ -445,7 +511,7 @@ __device__ __forceinline__ float2 op_product(const DevOp *__restrict__ gops, int
 // layout: A[i][k] and B[k][j] come from lane i + 16k (j + 16k); lane l holds
 // C[4(l/16) + r][l % 16] in element r.
 template <bool CVT>
-__device__ void mfma_tile(const DevGroup &G, const DevOp *__restrict__ gops,
+__device__ void mfma_tile(const GI &G, const DevOp *__restrict__ gops,
                           const uint8_t *__restrict__ bits, char *__restrict__ data,
                           float2 *lds, uint32_t tile, uint32_t set) {
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -454,10 +520,12 @@ __device__ void mfma_tile(const DevGroup &G, const DevOp *__restrict__ gops,
   const uint32_t mt = (M + kMfmaTM - 1) / kMfmaTM, nt = (N + kMfmaTN - 1) / kMfmaTN;
   const uint32_t bt = tile / (mt * nt), rem = tile % (mt * nt);
   const uint32_t m0 = (rem / nt) * kMfmaTM, n0 = (rem % nt) * kMfmaTN;
-  const uint8_t *mpos = bits, *npos = bits + nM, *bpos = bits + nM + nN;
+  // unit-bit table: m bits, then n bits, then batch bits
+  const int mpos = 0, npos = nM, bpos = nM + nN;
   // m0 and n0 are multiples of the tile sizes, so their union bits and those
   // of a row (col) inside the tile are disjoint
-  const uint32_t Ib = unit_bits(bt, bpos, nB) | unit_bits(m0, mpos, nM) | unit_bits(n0, npos, nN);
+  const uint32_t Ib = unit_bits(bt, bits, nB, bpos) | unit_bits(m0, bits, nM, mpos) |
+                    unit_bits(n0, bits, nN, npos);
   const int mlo = nM < 6 ? nM : 6, nlo = nN < 4 ? nN : 4;
   const uint32_t kc = K >= (uint32_t)kMfmaKC ? (uint32_t)kMfmaKC : (K < 4u ? 4u : K);
   const int na = G.n_unit, nb = G.n_step, no = G.n_serial;
@@ -468,14 +536,14 @@ __device__ void mfma_tile(const DevGroup &G, const DevOp *__restrict__ gops,
       const uint32_t row = e / kc, kk = e % kc, k = k0 + kk;
       float2 v = make_float2(0.0f, 0.0f);
       if (m0 + row < M && k < K)
-        v = op_product<CVT>(gops, 0, na, data, Ib | unit_bits(row, mpos, mlo) | k, set);
+        v = op_product<CVT>(gops, 0, na, data, Ib | unit_bits(row, bits, mlo, mpos) | k, set);
       sA[row * kMfmaLd + kk] = v;
     }
     for (uint32_t e = tid; e < kMfmaTN * kc; e += kBlock) {
       const uint32_t col = e / kc, kk = e % kc, k = k0 + kk;
       float2 v = make_float2(0.0f, 0.0f);
       if (n0 + col < N && k < K)
-        v = op_product<CVT>(gops, na, na + nb, data, Ib | unit_bits(col, npos, nlo) | k, set);
+        v = op_product<CVT>(gops, na, na + nb, data, Ib | unit_bits(col, bits, nlo, npos) | k, set);
       sB[col * kMfmaLd + kk] = v;
     }
     __syncthreads();
@@ -492,15 +560,15 @@ __device__ void mfma_tile(const DevGroup &G, const DevOp *__restrict__ gops,
   float2 *out = (float2 *)outp(data, G, set);
   const uint32_t col = lane & 15;
   if (n0 + col < N) {
-    const uint32_t Ic = Ib | unit_bits(col, npos, nlo);
+    const uint32_t Ic = Ib | unit_bits(col, bits, nlo, npos);
 #pragma unroll
     for (int i = 0; i < 4; i++) {
       const uint32_t row = wave * 16 + 4 * (lane >> 4) + i;
       if (m0 + row < M) {
         float2 v = make_float2(t1[i] - t2[i], t3[i] - t1[i] - t2[i]);
-        const uint32_t I = Ic | unit_bits(row, mpos, mlo);
+        const uint32_t I = Ic | unit_bits(row, bits, mlo, mpos);
         if (no > 0) v = cmul(v, op_product<CVT>(gops, na + nb, na + nb + no, data, I, set));
-        out[I >> L] = v;
+        if ((I >> L) < (1u << (G.w - L))) out[I >> L] = v;
       }
     }
   }
@@ -508,7 +576,7 @@ __device__ void mfma_tile(const DevGroup &G, const DevOp *__restrict__ gops,
 
 // One group's wave units [u0, u1) of angle set `set` over the block's waves,
 // in the group's own precision.
-__device__ __forceinline__ void run_group(const DevGroup &G, int g, const DevOp *__restrict__ ops,
+__device__ __forceinline__ void run_group(const GI &G, int g, const DevOp *__restrict__ ops,
                                           const int32_t *__restrict__ stab,
                                           const uint8_t *__restrict__ uperm, char *__restrict__ data,
                                           uint32_t *s_lane, uint32_t u0, uint32_t u1,
@@ -560,7 +628,7 @@ __global__ __launch_bounds__(kBlock) void k_block_groups(char *__restrict__ data
   const uint32_t set = blockIdx.x / (uint32_t)n_ranges;
   const int2 rg = ranges[range_base + (int)(blockIdx.x % (uint32_t)n_ranges)];
   for (int g = rg.x; g < rg.y; g++) {
-    const DevGroup &G = groups[g];
+    const GI G = load_group(groups + g);
     run_group(G, g, ops, stab, uperm, data, s_lane, 0u, G.n_units, set);
   }
 }
@@ -583,7 +651,7 @@ __global__ __launch_bounds__(kBlock) void k_wide_stream(char *__restrict__ data,
                                                         const uint8_t *__restrict__ uperm, int gid,
                                                         uint32_t n_sets) {
   __shared__ __align__(16) uint32_t s_lane[kStreamMaxOps * 64];
-  const DevGroup &G = groups[gid];
+  const GI G = load_group(groups + gid);
   const DevOp *gops = ops + G.op_begin;
   const int lane = threadIdx.x & 63;
   uint32_t ub, ue;
@@ -607,7 +675,7 @@ __global__ __launch_bounds__(kBlock) void k_wide_generic(char *__restrict__ data
                                                          const int32_t *__restrict__ stab,
                                                          const uint8_t *__restrict__ uperm,
                                                          int gid, uint32_t n_sets) {
-  const DevGroup &G = groups[gid];
+  const GI G = load_group(groups + gid);
   const DevOp *gops = ops + G.op_begin;
   const int lane = threadIdx.x & 63;
   uint32_t ub, ue;
@@ -627,7 +695,7 @@ __global__ __launch_bounds__(kBlock) void k_wide_mfma(char *__restrict__ data,
                                                       const uint8_t *__restrict__ uperm, int gid,
                                                       uint32_t n_sets) {
   __shared__ __align__(16) float2 s_tile[(kMfmaTM + kMfmaTN) * kMfmaLd];
-  const DevGroup &G = groups[gid];
+  const GI G = load_group(groups + gid);
   uint32_t ub, ue;
   wide_range(G.n_units * n_sets, &ub, &ue);
   for (uint32_t f = ub; f < ue; f++) {
@@ -648,7 +716,7 @@ __device__ __forceinline__ void run_item(int4 it, char *__restrict__ data,
   const bool chunk = it.y < 0;
   const int g_end = chunk ? it.x + 1 : it.y;
   for (int g = it.x; g < g_end; g++) {
-    const DevGroup &G = groups[g];
+    const GI G = load_group(groups + g);
     const uint32_t u0 = chunk ? (uint32_t)it.z : 0u;
     const uint32_t u1 = chunk ? min((uint32_t)it.w, G.n_units) : G.n_units;
     run_group(G, g, ops, stab, uperm, data, s_lane, u0, u1, 0u);
