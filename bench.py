@@ -3,9 +3,12 @@
 
 Workload: random 3-regular graph, N=30 (45 edges, one light-cone network per
 edge), QAOA depth p=4 -- the benchmark shape of Sec. II-E -- with seeded
-angle sets gamma ~ U[0, pi), beta ~ U[0, pi/2).  One step is one full energy
-evaluation: angle upload, every bucket of every light cone, the per-edge
-scalars, the FP64 energy and the read-back of |E|+1 doubles.  The plan
+angle sets gamma ~ U[0, pi), beta ~ U[0, pi/2).  One step evaluates
+--angle-batch angle sets (default 32, all of them) in one pass over the plan:
+angle upload, every bucket of every light cone for every set, the per-edge
+scalars, the FP64 energies and their read-back; the reported value counts
+every set's energy.  With --angle-batch 1 a step is one qtn_contract call on
+one angle set.  The plan
 (light cones, orders, merged groups, memory layout) is built once, before the
 timed region, as a caller sweeping angles would.
 
@@ -61,7 +64,11 @@ def save_tune(net, path, report, meta):
 
 
 def run_rows(Q, torch, inst, prec, levels, streams, steps, warmup, autotune=False,
-             tune_file=None, save_tune_file=None, **cfg):
+             tune_file=None, save_tune_file=None, angle_batch=1, **cfg):
+    """Plan (and tune) one network, then time `steps` steps after `warmup`.
+    angle_batch 1: a step is one qtn_contract call on the next angle set;
+    angle_batch K > 1: a step is one qtn_contract_angles call on K angle sets.
+    Returns (network, seconds, plan seconds, last result, evaluations)."""
     n, edges = inst["n"], inst["edges"]
     angles = inst["angles"]
     net = Q.Network(n, edges, *angles[0], max_levels=levels, n_streams=streams, **cfg)
@@ -80,6 +87,23 @@ def run_rows(Q, torch, inst, prec, levels, streams, steps, warmup, autotune=Fals
                           {"n": n, "edges": len(edges), "precision": prec, "levels": levels,
                            "config": {k: v for k, v in cfg.items() if k != "eager"}})
         net.tune_report["seconds"] = time.perf_counter() - t0
+    if angle_batch > 1:
+        import numpy as np
+        sets = [angles[k % len(angles)] for k in range(angle_batch)]
+        gs = np.array([a[0] for a in sets])
+        bs = np.array([a[1] for a in sets])
+        net.angle_sets = (gs, bs)
+        aws = Q.workspace(net.angles_workspace(angle_batch))
+        net._aws = aws
+        for _ in range(warmup):
+            net.contract_angles(gs, bs, aws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        last = None
+        for _ in range(steps):
+            last = net.contract_angles(gs, bs, aws)
+        torch.cuda.synchronize()
+        return net, time.perf_counter() - t0, plan_s, last, steps * angle_batch
     for i in range(warmup):
         net.set_angles(*angles[i % len(angles)])
         net.contract(ws)
@@ -91,7 +115,7 @@ def run_rows(Q, torch, inst, prec, levels, streams, steps, warmup, autotune=Fals
         last = net.contract(ws)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    return net, dt, plan_s, last
+    return net, dt, plan_s, last, steps
 
 
 KERNEL_OF = {  # launch-log (kind, variant) -> kernel symbol
@@ -395,6 +419,8 @@ def main():
                     help="randomized min-fill orders tried per light cone (0 = greedy)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--angle-sets", type=int, default=32)
+    ap.add_argument("--angle-batch", type=int, default=32,
+                    help="angle sets evaluated per step in one pass (1: one call per set)")
     ap.add_argument("--variants", type=int, default=1, help="also time the other rows")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -430,20 +456,40 @@ def main():
                 small_width=args.small_width, mixed_width=args.mixed_width, eager=args.eager)
     tune_file = None if args.retune else (
         args.tune_file or os.path.join(ROOT, "profiles", f"tune_n30p4_{args.precision}.json"))
-    net, dt, plan_s, last = run_rows(Q, torch, inst, prec, args.levels, args.streams,
-                                     args.steps, args.warmup, autotune=bool(args.autotune),
-                                     tune_file=tune_file, save_tune_file=args.save_tune, **kcfg)
+    net, dt, plan_s, last, n_evals = run_rows(
+        Q, torch, inst, prec, args.levels, args.streams, args.steps, args.warmup,
+        autotune=bool(args.autotune), tune_file=tune_file, save_tune_file=args.save_tune,
+        angle_batch=args.angle_batch, **kcfg)
     tune = net.tune_report
-    evals = args.steps / dt
+    evals = n_evals / dt
     stats = net.stats()
-    plan_order_trials = args.order_trials
-    log(f"  {evals:.2f} evals/s, plan {plan_s:.2f} s")
-    # kernel roofline: the same tuned plan, its launches serialized on one
-    # stream so that each launch's HIP event pair brackets that kernel alone
-    net.contract_timed()
-    _, _, timing = net.contract_timed()
-    tag = f"n30p4_{args.precision}"
+    log(f"  {evals:.2f} evals/s ({args.angle_batch} angle sets per step), plan {plan_s:.2f} s")
+    # kernel roofline: the same tuned plan and step, its launches serialized
+    # on one stream so that each launch's HIP event pair brackets that kernel
+    if args.angle_batch > 1:
+        gs, bs = net.angle_sets
+        net.contract_angles(gs, bs, timed=True)
+        _, _, timing = net.contract_angles(gs, bs, timed=True)
+    else:
+        net.contract_timed()
+        _, _, timing = net.contract_timed()
+    tag = f"n30p4_{args.precision}" + (f"_x{args.angle_batch}" if args.angle_batch > 1 else "")
     roof = roofline_of(net.launch_log(), tag)
+    # the same plan, one qtn_contract call per angle set
+    sequential = None
+    if args.angle_batch > 1 and args.variants:
+        ws1 = net.workspace()
+        for i in range(3):
+            net.set_angles(*inst["angles"][i % len(inst["angles"])])
+            net.contract(ws1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.angle_batch):
+            net.set_angles(*inst["angles"][i % len(inst["angles"])])
+            net.contract(ws1)
+        torch.cuda.synchronize()
+        sequential = {"evals_per_s": args.angle_batch / (time.perf_counter() - t0),
+                      "note": "same plan and kernels, one qtn_contract call per angle set"}
     net.close()
     log(f"  roofline {roof['kernel']}: {roof['hbm_gbs']:.0f} GB/s, "
         f"{roof['fp_tflops']:.2f} TFLOP/s")
@@ -455,18 +501,25 @@ def main():
         del src, dst
 
     variants = {}
+    if sequential is not None:
+        variants[f"sequential_{args.precision}"] = sequential
     if args.variants:
-        for name, pr, lv in (("c128_merged", Q.QTN_C128, 8), ("c64_merged", Q.QTN_C64, 8),
-                             ("mixed_merged", Q.QTN_MIXED, 8), ("c128_plain", Q.QTN_C128, 1),
-                             ("c64_plain", Q.QTN_C64, 1)):
-            if pr == prec and lv == args.levels:
+        # merged rows with the main row's angle batch; the bucket-by-bucket
+        # rows (the plain per-bucket path) one call per angle set, as the
+        # paper's backends run
+        for name, pr, lv, ab in (
+                ("c128_merged", Q.QTN_C128, 8, args.angle_batch),
+                ("c64_merged", Q.QTN_C64, 8, args.angle_batch),
+                ("mixed_merged", Q.QTN_MIXED, 8, args.angle_batch),
+                ("c128_plain", Q.QTN_C128, 1, 1), ("c64_plain", Q.QTN_C64, 1, 1)):
+            if pr == prec and lv == args.levels and ab == args.angle_batch:
                 continue
             log(f"variant {name}")
-            vnet, vdt, _, _ = run_rows(Q, torch, inst, pr, lv, args.streams,
-                                       max(3, args.steps // 4), 2,
-                                       autotune=bool(args.autotune), **kcfg)
+            vsteps = max(3, args.steps // 4) if ab == 1 else max(2, args.steps // 8)
+            vnet, vdt, _, _, vev = run_rows(Q, torch, inst, pr, lv, args.streams, vsteps, 2,
+                                            autotune=bool(args.autotune), angle_batch=ab, **kcfg)
             vst = vnet.stats()
-            variants[name] = {"evals_per_s": max(3, args.steps // 4) / vdt,
+            variants[name] = {"evals_per_s": vev / vdt, "angle_sets_per_step": ab,
                               "alg_bytes_per_eval": vst["bytes"],
                               "n_groups": vst["n_groups"]}
             vnet.close()
@@ -511,6 +564,7 @@ def main():
             "streams": args.streams, "variant": args.variant,
             "lane_sum_bits": args.lane_bits, "order_trials": args.order_trials,
             "executor": args.executor, "autotune": bool(args.autotune), "eager": args.eager,
+            "angle_sets_per_step": args.angle_batch,
             "max_width": stats["max_width"],
             "buckets": stats["n_buckets"], "groups": stats["n_groups"],
         },

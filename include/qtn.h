@@ -200,12 +200,16 @@ int qtn_contract_timed(qtn_network *net, void *d_workspace, size_t bytes,
  * per set.  Runs the per-group launch schedule (executor 0, 1 or 3 behaviour)
  * on the network's streams; blocks until the results are on the host.
  * The network's own angles (qtn_set_angles) are not used or changed.
+ *   timing_out   NULL, or: launches serialized on one stream and timed as in
+ *                qtn_contract_timed (fills it and the launch log; bytes and
+ *                flops cover all sets)
  * Errors: QTN_EINVAL (n_sets or angles), QTN_ESTATE, QTN_ENOMEM, QTN_EDEVICE.
  */
 int qtn_angles_workspace(qtn_network *net, int32_t n_sets, size_t *workspace_bytes_out);
 int qtn_contract_angles(qtn_network *net, void *d_workspace, size_t bytes,
                         void *hip_stream, int32_t n_sets, const double *gamma,
-                        const double *beta, double *zz_out, double *energy_out);
+                        const double *beta, double *zz_out, double *energy_out,
+                        qtn_timing *timing_out);
 
 /* One launch of the last qtn_contract_timed call on this network. */
 typedef struct qtn_launch_rec {

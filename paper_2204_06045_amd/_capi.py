@@ -139,7 +139,8 @@ def lib():
         L.qtn_autotune.argtypes = [P, P, ctypes.c_size_t, P, ctypes.POINTER(qtn_tune_report)]
         L.qtn_tune_log.argtypes = [P, i64, ctypes.POINTER(qtn_tune_rec), ctypes.POINTER(i64)]
         L.qtn_angles_workspace.argtypes = [P, i32, ctypes.POINTER(ctypes.c_size_t)]
-        L.qtn_contract_angles.argtypes = [P, P, ctypes.c_size_t, P, i32, pd, pd, pd, pd]
+        L.qtn_contract_angles.argtypes = [P, P, ctypes.c_size_t, P, i32, pd, pd, pd, pd,
+                                          ctypes.POINTER(qtn_timing)]
         L.qtn_tune_picks.argtypes = [P, i64, ctypes.POINTER(qtn_tune_pick), ctypes.POINTER(i64)]
         L.qtn_set_tune_picks.argtypes = [P, ctypes.POINTER(qtn_tune_pick), i64]
         pf = ctypes.POINTER(ctypes.c_float)

@@ -136,10 +136,7 @@ def qtn_contract_timed(net, n_edges, ws, stream=None):
     check(lib().qtn_contract_timed(net, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                                    stream_handle(stream), zz.ctypes.data_as(_pd),
                                    ctypes.byref(en), ctypes.byref(t)))
-    timing = {name: {"ms": t.ms[k], "launches": int(t.launches[k]),
-                     "bytes": t.bytes[k], "flops": t.flops[k]}
-              for k, name in enumerate(_capi.KERNEL_NAMES)}
-    return zz, en.value, timing
+    return zz, en.value, _timing_dict(t)
 
 
 def _net_array(nets):
@@ -214,8 +211,15 @@ def qtn_angles_workspace(net, n_sets):
     return b.value
 
 
-def qtn_contract_angles(net, n_edges, gammas, betas, ws, stream=None):
-    """gammas, betas: [n_sets][p].  Returns (zz [n_sets, n_edges], energies [n_sets])."""
+def _timing_dict(t):
+    return {name: {"ms": t.ms[k], "launches": int(t.launches[k]),
+                   "bytes": t.bytes[k], "flops": t.flops[k]}
+            for k, name in enumerate(_capi.KERNEL_NAMES)}
+
+
+def qtn_contract_angles(net, n_edges, gammas, betas, ws, stream=None, timed=False):
+    """gammas, betas: [n_sets][p].  Returns (zz [n_sets, n_edges], energies
+    [n_sets]), plus the timing dict when timed (launches serialized)."""
     g = np.ascontiguousarray(np.asarray(gammas, dtype=np.float64))
     b = np.ascontiguousarray(np.asarray(betas, dtype=np.float64))
     if g.ndim != 2 or g.shape != b.shape:
@@ -223,11 +227,12 @@ def qtn_contract_angles(net, n_edges, gammas, betas, ws, stream=None):
     n_sets = g.shape[0]
     zz = np.zeros((n_sets, n_edges))
     en = np.zeros(n_sets)
+    t = qtn_timing()
     check(lib().qtn_contract_angles(net, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                                     stream_handle(stream), n_sets, g.ctypes.data_as(_pd),
                                     b.ctypes.data_as(_pd), zz.ctypes.data_as(_pd),
-                                    en.ctypes.data_as(_pd)))
-    return zz, en
+                                    en.ctypes.data_as(_pd), ctypes.byref(t) if timed else None))
+    return (zz, en, _timing_dict(t)) if timed else (zz, en)
 
 
 def qtn_tune_picks(net):
@@ -317,7 +322,7 @@ class Network:
     def angles_workspace(self, n_sets):
         return qtn_angles_workspace(self.h, n_sets)
 
-    def contract_angles(self, gammas, betas, ws=None, stream=None):
+    def contract_angles(self, gammas, betas, ws=None, stream=None, timed=False):
         """Energies of several angle sets in one pass over the plan."""
         if ws is None:
             need = qtn_angles_workspace(self.h, len(gammas))
@@ -325,7 +330,7 @@ class Network:
                 self._aws = None
                 self._aws = workspace(need)
             ws = self._aws
-        return qtn_contract_angles(self.h, self.m, gammas, betas, ws, stream)
+        return qtn_contract_angles(self.h, self.m, gammas, betas, ws, stream, timed)
 
     def tune_picks(self):
         return qtn_tune_picks(self.h)

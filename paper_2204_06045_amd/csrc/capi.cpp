@@ -1130,6 +1130,8 @@ int qtn_set_angles(qtn_network *net, const double *gamma, const double *beta) {
   return QTN_OK;
 }
 
+static int record_timing(qtn_network *net, const Exec &X, const Timer &tm, qtn_timing *timing);
+
 static int contract_impl(qtn_network *net, void *ws, size_t bytes, void *stream, double *zz,
                          double *zz_im, double *energy, qtn_timing *timing) {
   try {
@@ -1140,11 +1142,25 @@ static int contract_impl(qtn_network *net, void *ws, size_t bytes, void *stream,
     std::vector<double> res;
     int rc = run_exec(*net->exec, {net}, ws, bytes, stream, net->n_streams, net->eager, tm, res);
     if (rc) return rc;
+    if (timing && (rc = record_timing(net, *net->exec, tm, timing))) return rc;
+    const int m = net->exec->sched.n_cones;
+    if (zz) std::copy(res.begin(), res.begin() + m, zz);
+    if (zz_im) std::copy(res.begin() + m, res.begin() + 2 * m, zz_im);
+    if (energy) *energy = res[2 * m];
+    return QTN_OK;
+  } catch (const std::bad_alloc &) {
+    return set_err(QTN_ENOMEM, "host allocation failed");
+  }
+}
+
+// The launch log and per-class totals of a timed run of X (bytes and flops
+// cover every angle set of the run).
+static int record_timing(qtn_network *net, const Exec &X, const Timer &tm, qtn_timing *timing) {
     qtn_timing t;
     std::memset(&t, 0, sizeof t);
-    if (timing) {
+    {
       net->launch_log.clear();
-      const Schedule &sc = net->exec->sched;
+      const Schedule &sc = X.sched;
       for (auto &r : tm.recs) {
         float ms = 0;
         QTN_HIP(hipEventElapsedTime(&ms, r.a, r.b));
@@ -1171,10 +1187,10 @@ static int contract_impl(qtn_network *net, void *ws, size_t bytes, void *stream,
         net->launch_log.push_back(lr);
       }
       for (int k = 0; k < QTN_NKERNELS; k++) {
-        t.bytes[k] = net->exec->sched.bytes[k];
-        t.flops[k] = net->exec->sched.flops[k];
+        t.bytes[k] = X.sched.bytes[k] * X.sched.n_sets;
+        t.flops[k] = X.sched.flops[k] * X.sched.n_sets;
       }
-      if (net->exec->persistent) {
+      if (X.persistent) {
         for (int k = 0; k < QTN_K_PERSISTENT; k++) {
           t.bytes[QTN_K_PERSISTENT] += t.bytes[k];
           t.flops[QTN_K_PERSISTENT] += t.flops[k];
@@ -1182,15 +1198,8 @@ static int contract_impl(qtn_network *net, void *ws, size_t bytes, void *stream,
         }
       }
     }
-    const int m = net->exec->sched.n_cones;
-    if (zz) std::copy(res.begin(), res.begin() + m, zz);
-    if (zz_im) std::copy(res.begin() + m, res.begin() + 2 * m, zz_im);
-    if (energy) *energy = res[2 * m];
-    if (timing) *timing = t;
+    *timing = t;
     return QTN_OK;
-  } catch (const std::bad_alloc &) {
-    return set_err(QTN_ENOMEM, "host allocation failed");
-  }
 }
 
 int qtn_contract(qtn_network *net, void *d_workspace, size_t bytes, void *hip_stream,
@@ -1236,7 +1245,7 @@ int qtn_angles_workspace(qtn_network *net, int32_t n_sets, size_t *bytes_out) {
 
 int qtn_contract_angles(qtn_network *net, void *d_workspace, size_t bytes, void *hip_stream,
                         int32_t n_sets, const double *gamma, const double *beta, double *zz_out,
-                        double *energy_out) {
+                        double *energy_out, qtn_timing *timing) {
   try {
     if (!net || !gamma || !beta) return set_err(QTN_EINVAL, "NULL argument");
     if (!net->planned) return set_err(QTN_ESTATE, "qtn_plan has not been called");
@@ -1255,10 +1264,12 @@ int qtn_contract_angles(qtn_network *net, void *d_workspace, size_t bytes, void 
     Exec *ex = angle_exec(net, n_sets, &rc);
     if (!ex) return rc;
     Timer tm;
+    tm.on = timing != nullptr;
     std::vector<double> res;
     rc = run_exec(*ex, {net}, d_workspace, bytes, hip_stream, net->n_streams, net->eager, tm, res,
                   ang.data());
     if (rc) return rc;
+    if (timing && (rc = record_timing(net, *ex, tm, timing))) return rc;
     const int m = (int)net->cones.size(), per = 2 * m + 1;
     for (int k = 0; k < n_sets; k++) {
       if (zz_out) std::copy(res.begin() + (size_t)k * per, res.begin() + (size_t)k * per + m,

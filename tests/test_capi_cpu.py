@@ -277,6 +277,6 @@ def test_angle_batch_workspace_and_validation(qtn):
     en = np.full(1, 7.0)
     rc = lib.qtn_contract_angles(net.h, ctypes.c_void_p(256), 1 << 30, None, 1,
                                  gs.ctypes.data_as(pd), bs.ctypes.data_as(pd), None,
-                                 en.ctypes.data_as(pd))
+                                 en.ctypes.data_as(pd), None)
     assert rc == -1 and "finite" in qtn.qtn_last_error() and en[0] == 7.0
     net.close()

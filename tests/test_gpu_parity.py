@@ -408,3 +408,23 @@ def test_angle_batch_full_size(qtn, gpu):
         z1, _, e1 = net.contract()
         assert np.array_equal(z1, zz[k]) and e1 == en[k]
     net.close()
+
+
+def test_angle_batch_timed_launch_log(qtn, gpu):
+    """Timed angle batches: one serialized launch per scheduled kernel, bytes
+    covering every set."""
+    inst = qs.instance(16, 3, 3, 4, 3)
+    gs = np.array([a[0] for a in inst["angles"]])
+    bs = np.array([a[1] for a in inst["angles"]])
+    net = qtn.Network(16, inst["edges"], gs[0], bs[0], small_width=4)
+    net.plan(0)
+    zz, en, timing = net.contract_angles(gs, bs, timed=True)
+    log = net.launch_log()
+    assert len(log) > 0 and all(r["ms"] >= 0 for r in log)
+    zz1, en1 = net.contract_angles(gs, bs)
+    assert np.array_equal(zz, zz1) and np.array_equal(en, en1)
+    net.contract_timed()
+    single = {k: v["bytes"] for k, v in net.contract_timed()[2].items()}
+    for k, v in timing.items():
+        assert abs(v["bytes"] - 3 * single[k]) <= 1e-6 * max(1.0, v["bytes"])
+    net.close()
