@@ -120,7 +120,7 @@ def run_rows(Q, torch, inst, prec, levels, streams, steps, warmup, autotune=Fals
 
 KERNEL_OF = {  # launch-log (kind, variant) -> kernel symbol
     (1, None): "k_block_groups", (2, 0): "k_wide_generic", (2, 1): "k_wide_stream",
-    (2, 2): "k_wide_mfma", (4, None): "k_persistent",
+    (2, 2): "k_wide_mfma", (2, 3): "k_wide_cells", (4, None): "k_persistent",
 }
 
 
@@ -134,7 +134,10 @@ def kernel_name(rec):
     if rec["variant"] == 2:  # complex64 only
         return f"{base}<{'true' if rec['cvt'] else 'false'}>"
     t = "double2" if rec["prec"] == 0 else "float2"
-    return f"{base}<{t}, {'true' if rec['cvt'] else 'false'}>"
+    cvt = 'true' if rec['cvt'] else 'false'
+    if rec["variant"] == 3:  # one instantiation per cell and serial bit count
+        return f"{base}<{t}, {cvt}, {rec['knob']}, {rec['serial']}>"
+    return f"{base}<{t}, {cvt}>"
 
 
 def source_hash():

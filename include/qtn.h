@@ -218,11 +218,14 @@ typedef struct qtn_launch_rec {
     int32_t n_groups;  /* groups in the launch                            */
     int32_t w, L;      /* union width and summed indices (first group)    */
     int32_t n_ops;     /* operands of the first group                     */
-    int32_t variant;   /* kernel mapping of the first group               */
+    int32_t variant;   /* kernel mapping of the first group: 0 generic,
+                          1 streaming, 2 matrix form, 3 cells              */
     int32_t n_units;   /* wave units of the first group                   */
     int32_t prec;      /* arithmetic of the first group: QTN_C128/QTN_C64 */
     int32_t cvt;       /* 1: some operand of it is stored in the other
                           precision and converted on load                 */
+    int32_t knob;      /* streaming: lane-summed bits; cells: cell bits   */
+    int32_t serial;    /* streaming and cells: serially walked summed bits */
     double ms;         /* HIP-event duration                              */
     double bytes;      /* algorithmic bytes of the launch                 */
     double flops;      /* complex-arithmetic FLOPs of the launch          */
@@ -368,6 +371,7 @@ typedef struct qtn_plan_stats {
     double paper_flops;   /* 8 * sum 2^width (the paper's Sec. II-E count) */
     size_t workspace;     /* device bytes                                 */
     int64_t n_matrix;     /* groups scheduled in matrix form (QTN_VAR_MFMA) */
+    int64_t n_cell;       /* groups scheduled with the cell mapping        */
 } qtn_plan_stats;
 
 int qtn_get_plan_stats(const qtn_network *net, qtn_plan_stats *out);

@@ -68,7 +68,8 @@ class qtn_launch_rec(ctypes.Structure):
                 ("n_groups", ctypes.c_int32), ("w", ctypes.c_int32), ("L", ctypes.c_int32),
                 ("n_ops", ctypes.c_int32), ("variant", ctypes.c_int32),
                 ("n_units", ctypes.c_int32), ("prec", ctypes.c_int32),
-                ("cvt", ctypes.c_int32), ("ms", ctypes.c_double),
+                ("cvt", ctypes.c_int32), ("knob", ctypes.c_int32),
+                ("serial", ctypes.c_int32), ("ms", ctypes.c_double),
                 ("bytes", ctypes.c_double), ("flops", ctypes.c_double)]
 
 
@@ -93,7 +94,8 @@ class qtn_plan_stats(ctypes.Structure):
                 ("n_wide", ctypes.c_int64), ("max_width", ctypes.c_int32),
                 ("width_hist", ctypes.c_int32 * 40), ("bytes", ctypes.c_double),
                 ("flops", ctypes.c_double), ("paper_flops", ctypes.c_double),
-                ("workspace", ctypes.c_size_t), ("n_matrix", ctypes.c_int64)]
+                ("workspace", ctypes.c_size_t), ("n_matrix", ctypes.c_int64),
+                ("n_cell", ctypes.c_int64)]
 
 
 class QtnError(RuntimeError):

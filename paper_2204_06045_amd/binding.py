@@ -167,7 +167,8 @@ def qtn_get_plan_stats(net):
     return {"n_buckets": s.n_buckets, "n_groups": s.n_groups, "n_wide": s.n_wide,
             "max_width": s.max_width, "width_hist": list(s.width_hist),
             "bytes": s.bytes, "flops": s.flops, "paper_flops": s.paper_flops,
-            "workspace": s.workspace, "n_matrix": s.n_matrix}
+            "workspace": s.workspace, "n_matrix": s.n_matrix,
+            "n_cell": s.n_cell}
 
 
 def qtn_plan_order(net, edge):

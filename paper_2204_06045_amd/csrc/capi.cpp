@@ -210,7 +210,8 @@ struct qtn_network {
   int order_trials = 0;   // >1: best of this many randomized min-fill orders
   int executor = 0;       // 0 streams + per-group launches, 1 persistent lockstep
   uint32_t spin_limit = 1u << 22;
-  int variant = 0;        // 0 auto, 1 generic only, 2 streaming where possible
+  int variant = 0;        // 0 auto, 1 generic only, 2 streaming where possible,
+                          // 3 matrix form where possible, 4 cells where possible
   std::vector<LightCone> cones;
   std::vector<std::vector<int>> minfill;
   std::mutex minfill_lock;
@@ -264,22 +265,26 @@ int64_t gate_offset(const Gate &gt, bool transposed, int p) {
 // Candidate kernel configuration the autotuner forces on every wide group.
 struct Force {
   int place;    // -1 keep, 0 workgroup segment, 1 own launch
-  int variant;  // 1 generic, 2 streaming
-  int rls;
+  int variant;  // 1 generic, 2 streaming, 3 matrix form, 4 cells
+  int rls;      // streaming: lane-summed bits; cells: register bits
 };
 
 constexpr int kTuneSingleWidth = 16;
 
 // Configurations measured by the autotuner: every group in its own launch
 // with the generic mapping, with the streaming mapping at 1, 2, 3
-// lane-summed bits, or in matrix form (complex64 groups that have one).
+// lane-summed bits, in matrix form (complex64 groups that have one), or with
+// the cell mapping at 3 or 4 cell bits (groups wide enough for it).
 const std::vector<Force> &tune_candidates() {
-  static const std::vector<Force> c = {{1, 1, 2}, {1, 2, 1}, {1, 2, 2}, {1, 2, 3}, {1, 3, 2}};
+  static const std::vector<Force> c = {{1, 1, 2}, {1, 2, 1}, {1, 2, 2}, {1, 2, 3},
+                                       {1, 3, 2}, {1, 4, 3}, {1, 4, 4}};
   return c;
 }
 
+// persistent: the schedule runs in a persistent executor (every group inside
+// a workgroup, so no group takes the cell mapping).
 int build_schedule(qtn_network *const *nets, int n, Schedule *S, const Force *force = nullptr,
-                   int singleton_width = 0, int n_sets = 1) {
+                   int singleton_width = 0, int n_sets = 1, bool persistent = false) {
   Schedule &s = *S;
   s = Schedule();
   s.n_sets = n_sets;
@@ -377,8 +382,32 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S, const Force *fo
         GemmShape gsh;
         const bool mfma = var_req == 3 && G.prec == 1 && gemm_shape(G, pl, &gsh);
         if (var_req == 3 && !mfma) var_req = 0;
-        // auto: the streaming mapping pays off once a lane walks >= 2 serial bits
-        const bool stream = !mfma && stream_ok && (var_req == 2 || (var_req == 0 && sl >= 2));
+        // cells: lanes on union bits 0..5, cb cell bits in registers (the
+        // summed bits above bit 5, then rb kept bits); own launches only (the
+        // kernel is not part of the workgroup and persistent paths).  Taken
+        // when requested, and by the rule for every own-launch group it fits
+        const int low = std::max(G.L, 6);
+        auto cell_fits = [&](int cbits) {
+          const int r = cbits - std::max(0, G.L - 6);
+          return !is_small && !persistent && (int)G.ops.size() <= 64 &&
+                 cell_lds_words((int)G.ops.size(), cbits) <= kCellMaxLdsWords &&
+                 G.L - 6 <= kCellMaxSerial && r >= 0 && G.w - low >= r;
+        };
+        int cb = 0;
+        bool cell = false;
+        if (var_req == 4) {
+          cb = rls_req >= kCellMinCB && rls_req <= kCellMaxCB ? rls_req : kCellRuleCB;
+          cell = cell_fits(cb);
+          if (!cell) var_req = 0;
+        }
+        if (var_req == 0 && !mfma && cell_fits(kCellRuleCB)) {
+          cb = kCellRuleCB;
+          cell = true;
+        }
+        const int rb = cell ? cb - std::max(0, G.L - 6) : 0;
+        // otherwise the streaming mapping once a lane walks >= 2 serial bits
+        const bool stream =
+            !mfma && !cell && stream_ok && (var_req == 2 || (var_req == 0 && sl >= 2));
         std::vector<int> order(G.ops.size());
         std::vector<int> cls(G.ops.size(), 0);
         for (size_t k = 0; k < G.ops.size(); k++) order[k] = (int)k;
@@ -403,14 +432,38 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S, const Force *fo
           const uint64_t tiles = (1ull << dg.n_bb) * mt * nt;
           if (tiles > 0xFFFFFFFFull) return set_err(QTN_ERANGE, "matrix-form group too large");
           dg.n_units = (uint32_t)tiles;
+        } else if (cell) {
+          dg.variant = kVarCell;
+          dg.rls = (uint8_t)cb;
+          dg.sl = (uint8_t)std::max(0, G.L - 6);
+          dg.lk = (uint8_t)(6 - std::min(G.L, 6));
+          // step operands (with serial bits) first; without serial bits every
+          // operand is one
+          const uint32_t serial_bits = ((1u << G.L) - 1u) & ~63u;
+          for (size_t k = 0; k < G.ops.size(); k++)
+            cls[k] = (!serial_bits || (G.ops[k].mask & serial_bits)) ? kClsStep : kClsUnit;
+          std::stable_sort(order.begin(), order.end(),
+                           [&](int a, int b) { return cls[a] > cls[b]; });
+          int ns = 0;
+          for (int k : order) ns += cls[k] == kClsStep ? 1 : 0;
+          dg.n_step = (uint8_t)ns;
+          dg.n_units = 1u << (G.w - low - rb);
         } else if (stream) {
           dg.variant = kVarStream;
           dg.rls = (uint8_t)rls;
           dg.sl = (uint8_t)sl;
           dg.lk = (uint8_t)(6 - rls);
+          // lane-kept bits: the lowest kept bits, so that the lanes' output
+          // writes are contiguous (positions past the union, in narrow
+          // groups, give idle lanes).  Choosing instead the bits the large
+          // operands lack, so that lanes share operand elements, measured
+          // slower.
+          for (int j = 0; j < dg.lk; j++) dg.lkpos[j] = (uint8_t)(G.L + j);
+          uint32_t lane_kept = 0;
+          for (int j = 0; j < dg.lk; j++)
+            if (dg.lkpos[j] < 32) lane_kept |= 1u << dg.lkpos[j];
           const uint32_t serial_bits = ((1u << G.L) - 1u) & ~((1u << (1 + rls)) - 1u);
-          const uint32_t lane_bits = (((1u << rls) - 1u) << 1) |
-                                     (uint32_t)((((1ull << dg.lk) - 1ull) << G.L) & 0xFFFFFFFFull);
+          const uint32_t lane_bits = (((1u << rls) - 1u) << 1) | lane_kept;
           for (size_t k = 0; k < G.ops.size(); k++) {
             const Operand &o = G.ops[k];
             if (o.level >= 1 + rls)
@@ -465,10 +518,16 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S, const Force *fo
           s.uperm.insert(s.uperm.end(), up, up + 32);
         } else {
           // wave-unit bits, those that large operands lack first (their data
-          // is then reused by neighbouring units of the same block and XCD)
-          const int start = stream ? G.L + dg.lk : kGenRegBits + 6;
+          // is then reused by neighbouring units of the same block and XCD);
+          // cells: the first rb of that order are the register bits (each
+          // value of an operand lacking them serves several cells), first in
+          // the table
+          const int start = stream ? G.L : (cell ? low : kGenRegBits + 6);
           std::vector<std::pair<double, int>> sc;
           for (int b = start; b < G.w; b++) {
+            bool lane = false;
+            for (int j = 0; stream && j < dg.lk; j++) lane |= dg.lkpos[j] == b;
+            if (lane) continue;
             double miss = 0;
             for (const Operand &o : G.ops)
               if (pl.tensors[o.tensor].gate < 0 && !((o.mask >> b) & 1u))
@@ -476,9 +535,39 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S, const Force *fo
             sc.push_back({-miss, b});
           }
           std::stable_sort(sc.begin(), sc.end());
+          std::vector<int> regs;
+          if (cell) {
+            for (int j = 0; j < rb; j++) regs.push_back(sc[j].second);
+            sc.erase(sc.begin(), sc.begin() + rb);
+            // the cell mapping forms an operand's unit offset from its runs
+            // over the unit bits; past kCellURuns of them, ascending order
+            // (at most one run per two unit bits)
+            int worst = 0;
+            for (const Operand &o : G.ops) {
+              int runs = 0, prev = -2;
+              for (size_t j = 0; j < sc.size(); j++) {
+                const int q = sc[j].second;
+                if (!((o.mask >> q) & 1u)) {
+                  prev = -2;
+                  continue;
+                }
+                const int rank = __builtin_popcount(o.mask & ((1u << q) - 1u));
+                if (rank != prev + 1) runs++;
+                prev = rank;
+              }
+              worst = std::max(worst, runs);
+            }
+            if (worst > kCellURuns)
+              std::sort(sc.begin(), sc.end(),
+                        [](const std::pair<double, int> &a, const std::pair<double, int> &b) {
+                          return a.second < b.second;
+                        });
+          }
           uint8_t up[32];
           std::memset(up, 0, sizeof up);
-          for (size_t j = 0; j < sc.size(); j++) up[j] = (uint8_t)sc[j].second;
+          const int first = cell ? rb : 0;
+          for (int j = 0; j < first; j++) up[j] = (uint8_t)regs[j];
+          for (size_t j = 0; j < sc.size(); j++) up[first + j] = (uint8_t)sc[j].second;
           dg.n_ubits = (uint8_t)sc.size();
           s.uperm.insert(s.uperm.end(), up, up + 32);
         }
@@ -511,6 +600,44 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S, const Force *fo
             d.stab = (int32_t)s.stab.size();
             for (uint32_t st = 0; st < (1u << dg.sl); st++)
               s.stab.push_back((int32_t)pext32(st << (1 + dg.rls), o.mask));
+          }
+          if (cell) {
+            // cell offsets (cell c: kept bits c % 2^rb, serial bits c / 2^rb),
+            // then the runs giving the unit part of the index from the unit
+            // number
+            d.stab = (int32_t)s.stab.size();
+            const uint8_t *rp = s.uperm.data() + s.uperm.size() - 32;
+            uint32_t cm = 0;
+            for (int j = 0; j < rb; j++) cm |= ((o.mask >> rp[j]) & 1u) << j;
+            for (int t = 0; t < dg.sl; t++) cm |= ((o.mask >> (6 + t)) & 1u) << (rb + t);
+            for (uint32_t c = 0; c < (1u << cb); c++) {
+              uint32_t I = (c >> rb) << 6;
+              for (int j = 0; j < rb; j++) I |= ((c >> j) & 1u) << rp[j];
+              s.stab.push_back((int32_t)pext32(I, o.mask));
+            }
+            const uint8_t *up = rp + rb;
+            uint16_t ur[kCellURuns];
+            std::memset(ur, 0, sizeof ur);
+            int nur = 0;
+            for (int j = 0; j < dg.n_ubits;) {
+              const int q = up[j];
+              if (!((o.mask >> q) & 1u)) {
+                j++;
+                continue;
+              }
+              const int dst = __builtin_popcount(o.mask & ((1u << q) - 1u));
+              int len = 1;
+              while (j + len < dg.n_ubits && ((o.mask >> up[j + len]) & 1u) &&
+                     __builtin_popcount(o.mask & ((1u << up[j + len]) - 1u)) == dst + len)
+                len++;
+              if (nur == kCellURuns) return set_err(QTN_ERANGE, "cell mapping: unit runs");
+              ur[nur++] = (uint16_t)(j | (len << 5) | (dst << 11));
+              j += len;
+            }
+            dg.n_unit = (uint8_t)std::max<int>(dg.n_unit, nur);
+            for (int w = 0; w < kCellURuns / 2; w++)
+              s.stab.push_back((int32_t)((uint32_t)ur[2 * w] | ((uint32_t)ur[2 * w + 1] << 16)));
+            s.stab.push_back((int32_t)cm);
           }
           if (d.dt != dg.prec) dg.cvt = 1;
           s.ops.push_back(d);
@@ -636,6 +763,10 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S, const Force *fo
   }
   s.bytes[QTN_K_BLOCK] = s.init_bytes;
   s.flops[QTN_K_BLOCK] = s.init_flops;
+  // a wide launch walks the units of every set in one flat 31-bit index
+  for (const DevGroup &g : s.groups)
+    if ((uint64_t)g.n_units * (uint64_t)s.n_sets > 0x7FFFFFFFull)
+      return set_err(QTN_ERANGE, "too many units over the angle sets for one launch");
   for (auto &tk : s.cone_tasks)
     for (auto &t : tk) {
       s.bytes[t.kind] += t.bytes;
@@ -854,9 +985,8 @@ int enqueue(Exec &X, Timer &tm) {
           QTN_HIP(launch_block_groups(s.prec, data, groups, ops, stab, uperm, ranges, t.index, 1, NS,
                                       hs, tm.t0(), tm.t1()));
         else
-          QTN_HIP(launch_wide_group(s.groups[t.index].prec, s.groups[t.index].cvt != 0, t.variant,
-                                    data, groups, ops, stab, uperm, t.index, t.n_units, NS, hs,
-                                    tm.t0(), tm.t1()));
+          QTN_HIP(launch_wide_group(s.groups[t.index], data, groups, ops, stab, uperm, t.index, NS,
+                                    hs, tm.t0(), tm.t1()));
         if ((rc = tm.end(hs, true))) return rc;
       }
     }
@@ -994,7 +1124,7 @@ int qtn_network_build(int32_t n_vertices, int64_t n_edges, const int32_t *edges,
       if (cfg->lane_sum_bits < 0 || cfg->lane_sum_bits > 5)
         return set_err(QTN_EINVAL, "lane_sum_bits must be in 0..5");
       if (cfg->lane_sum_bits) net->lane_sum_bits = cfg->lane_sum_bits;
-      if (cfg->variant < 0 || cfg->variant > 3) return set_err(QTN_EINVAL, "variant must be 0..3");
+      if (cfg->variant < 0 || cfg->variant > 4) return set_err(QTN_EINVAL, "variant must be 0..4");
       net->variant = cfg->variant;
       if (cfg->order_trials < 0 || cfg->order_trials > 4096)
         return set_err(QTN_EINVAL, "order_trials must be in 0..4096");
@@ -1091,7 +1221,8 @@ int qtn_plan(qtn_network *net, const int32_t *const *orders, int32_t precision,
     net->plans.swap(plans);
     net->precision = precision;
     qtn_network *one[1] = {net};
-    int rc = build_schedule(one, 1, &ex->sched);
+    int rc = build_schedule(one, 1, &ex->sched, nullptr, 0, 1,
+                            net->executor == 2 || net->executor == 4);
     if (rc) {
       net->plans.clear();
       net->planned = false;
@@ -1183,6 +1314,8 @@ static int record_timing(qtn_network *net, const Exec &X, const Timer &tm, qtn_t
           lr.n_units = (int32_t)g.n_units;
           lr.prec = g.prec;
           lr.cvt = g.cvt;
+          lr.knob = g.variant == kVarStream || g.variant == kVarCell ? g.rls : 0;
+          lr.serial = g.variant == kVarStream || g.variant == kVarCell ? g.sl : 0;
         }
         net->launch_log.push_back(lr);
       }
@@ -1215,7 +1348,9 @@ static Exec *angle_exec(qtn_network *net, int n_sets, int *rc) {
     return net->angle_exec.get();
   auto ex = std::make_unique<Exec>();
   qtn_network *one[1] = {net};
-  *rc = build_schedule(one, 1, &ex->sched, nullptr, 0, n_sets);
+  // the same kernel mappings as the network's own schedule (so that every
+  // set equals its single-set evaluation), though launched per group
+  *rc = build_schedule(one, 1, &ex->sched, nullptr, 0, n_sets, net->exec->persistent);
   if (*rc) return nullptr;
   // per-group launches (the persistent executors run one set)
   ex->lead_per_cone = net->executor == 3;
@@ -1305,7 +1440,8 @@ static Exec *batch_exec(qtn_network *const *nets, int32_t n, int *rc) {
   auto it = g_batch.find(key);
   if (it != g_batch.end()) return it->second.get();
   auto ex = std::make_unique<Exec>();
-  *rc = build_schedule(nets, n, &ex->sched);
+  *rc = build_schedule(nets, n, &ex->sched, nullptr, 0, 1,
+                       nets[0]->executor != 1 && nets[0]->executor != 3);
   if (*rc) return nullptr;
   // batches default to the persistent executor
   ex->persistent = nets[0]->executor != 1 && nets[0]->executor != 3;
@@ -1398,6 +1534,8 @@ int qtn_autotune(qtn_network *net, void *d_workspace, size_t bytes, void *hip_st
         char *ws = (char *)d_workspace;
         const Schedule &s = ex.sched;
         for (size_t i = 0; i < s.singles.size(); i++) {
+          // the cell mapping only runs in its own launch
+          if (s.groups[s.singles[i]].variant == kVarCell) continue;
           if ((rc = tb.begin(QTN_K_BLOCK, ex.rt.main, s.singles[i], 1, 0, 0, true))) {
             give_back();
             return rc;
@@ -1421,7 +1559,9 @@ int qtn_autotune(qtn_network *net, void *d_workspace, size_t bytes, void *hip_st
         auto key_of = [&](int g) { return std::make_pair(s.group_cone[g], s.group_index[g]); };
         // a candidate only counts for the groups that ran its kernel
         auto ran = [&](int g) {
-          return cands[ci].variant != 3 || s.groups[g].variant == kVarMfma;
+          if (cands[ci].variant == 3) return s.groups[g].variant == kVarMfma;
+          if (cands[ci].variant == 4) return s.groups[g].variant == kVarCell;
+          return true;
         };
         auto slot = [&](int g) -> Meas & {
           return meas.emplace(key_of(g), Meas{{-1, -1, -1, -1, -1, -1, -1, -1},
@@ -1460,8 +1600,15 @@ int qtn_autotune(qtn_network *net, void *d_workspace, size_t bytes, void *hip_st
       const int rls = std::min(G.L - 1, net->lane_sum_bits), sl = G.L - 1 - rls;
       const bool rule_stream = (int)G.ops.size() <= kStreamMaxOps && sl <= kStreamMaxSerial &&
                                sl >= 2 && net->variant != 1;
-      int best = -1;
+      // the rule's own configuration: the cell mapping wherever it ran (own
+      // launches of the per-group executors), else streaming or generic
+      int rule_cell = -1;
       for (int ci = 0; ci < nc; ci++)
+        if (!G.small && !net->exec->persistent && net->variant != 1 && net->variant != 2 &&
+            cands[ci].variant == 4 && cands[ci].rls == kCellRuleCB && t[ci] >= 0)
+          rule_cell = ci;
+      int best = rule_cell;
+      for (int ci = 0; ci < nc && rule_cell < 0; ci++)
         if (cands[ci].variant == (rule_stream ? 2 : 1) && (rule_stream ? cands[ci].rls == rls : true))
           if (t[ci] >= 0) best = ci;
       for (int ci = 0; ci < nc; ci++)
@@ -1481,7 +1628,8 @@ int qtn_autotune(qtn_network *net, void *d_workspace, size_t bytes, void *hip_st
       double mb = -1, ms_stream = -1, ms_mfma = -1;
       for (int ci = 0; ci < nc; ci++) {
         if (m.block[ci] >= 0 && (mb < 0 || m.block[ci] < mb)) mb = m.block[ci];
-        if (cands[ci].variant == 2 && m.wide[ci] >= 0 && (ms_stream < 0 || m.wide[ci] < ms_stream))
+        if ((cands[ci].variant == 2 || cands[ci].variant == 4) && m.wide[ci] >= 0 &&
+            (ms_stream < 0 || m.wide[ci] < ms_stream))
           ms_stream = m.wide[ci];
         if (cands[ci].variant == 3) ms_mfma = m.wide[ci];
       }
@@ -1493,7 +1641,7 @@ int qtn_autotune(qtn_network *net, void *d_workspace, size_t bytes, void *hip_st
     }
     // the tuned schedule replaces the current one, on the same streams
     auto tuned = std::make_unique<Exec>();
-    int rc = build_schedule(one, 1, &tuned->sched);
+    int rc = build_schedule(one, 1, &tuned->sched, nullptr, 0, 1, net->exec->persistent);
     if (rc) {
       give_back();
       return rc;
@@ -1565,7 +1713,7 @@ int qtn_set_tune_picks(qtn_network *net, const qtn_tune_pick *picks, int64_t n) 
         return set_err(QTN_EINVAL, "pick " + std::to_string(i) + " names no group of this plan");
       if (group_shape(net->plans[p.edge].groups[p.group]) != p.shape)
         return set_err(QTN_EINVAL, "pick " + std::to_string(i) + " is for a different group");
-      if (p.place < -1 || p.place > 1 || p.variant < -1 || p.variant > 3 || p.rls < -1 || p.rls > 5)
+      if (p.place < -1 || p.place > 1 || p.variant < -1 || p.variant > 4 || p.rls < -1 || p.rls > 5)
         return set_err(QTN_EINVAL, "pick " + std::to_string(i) + " is out of range");
     }
     for (int64_t i = 0; i < n; i++) {
@@ -1576,7 +1724,7 @@ int qtn_set_tune_picks(qtn_network *net, const qtn_tune_pick *picks, int64_t n) 
     }
     qtn_network *one[1] = {net};
     auto ex = std::make_unique<Exec>();
-    int rc = build_schedule(one, 1, &ex->sched);
+    int rc = build_schedule(one, 1, &ex->sched, nullptr, 0, 1, net->exec->persistent);
     if (rc) return rc;
     ex->rt.take(net->exec->rt);
     ex->persistent = net->exec->persistent;
@@ -1630,7 +1778,10 @@ int qtn_get_plan_stats(const qtn_network *net, qtn_plan_stats *out) {
     st.flops += s.flops[k];
   }
   st.workspace = s.total;
-  for (const DevGroup &g : s.groups) st.n_matrix += g.variant == kVarMfma ? 1 : 0;
+  for (const DevGroup &g : s.groups) {
+    st.n_matrix += g.variant == kVarMfma ? 1 : 0;
+    st.n_cell += g.variant == kVarCell ? 1 : 0;
+  }
   *out = st;
   return QTN_OK;
 }
@@ -1904,12 +2055,14 @@ int qtn_apply_costmodel(qtn_network *net, const qtn_costmodel *cm, void *d_ws, s
       if (G.prec == 1 && p[QTN_VAR_MFMA] < p[best] && gemm_shape(G, *gp[i], nullptr))
         best = QTN_VAR_MFMA;
       counts[best]++;
-      G.pick_variant = best == QTN_VAR_STREAM ? 2 : (best == QTN_VAR_MFMA ? 3 : 1);
-      G.pick_rls = 2;
+      // the streaming family: the cell mapping where it fits, else the
+      // lane-sum streaming mapping (the planner falls back by itself)
+      G.pick_variant = best == QTN_VAR_STREAM ? 4 : (best == QTN_VAR_MFMA ? 3 : 1);
+      G.pick_rls = best == QTN_VAR_STREAM ? kCellRuleCB : 2;
     }
     qtn_network *one[1] = {net};
     auto ex = std::make_unique<Exec>();
-    if ((rc = build_schedule(one, 1, &ex->sched))) return rc;
+    if ((rc = build_schedule(one, 1, &ex->sched, nullptr, 0, 1, net->exec->persistent))) return rc;
     ex->rt.take(net->exec->rt);
     ex->persistent = net->exec->persistent;
     ex->dataflow = net->exec->dataflow;

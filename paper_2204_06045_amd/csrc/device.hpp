@@ -42,7 +42,7 @@ struct DevGroup {       // 64 bytes
   int64_t out_sstride;  // bytes from one angle set's output to the next
   int32_t op_begin;     // first DevOp of the group
   uint32_t n_units;     // wave units
-  uint8_t w, L, n_ops, variant;   // variant: kVarGeneric / kVarStream
+  uint8_t w, L, n_ops, variant;   // variant: kVar*
   uint8_t rls, sl, lk, n_unit;    // streaming: lane-summed bits, serial bits,
                                   // lane-kept bits, kClsUnit op count
   uint8_t n_step, n_serial, n_step0, pad;  // n_step0: step-class ops with bit 0
@@ -54,13 +54,32 @@ struct DevGroup {       // 64 bytes
   uint8_t cvt;          // 1: some operand is stored in the other precision
   uint8_t n_mb, n_nb, n_bb;  // matrix form: m, n and batch bit counts (their
                              // union positions: uperm, m then n then batch)
-  uint8_t pad2[10];
+  uint8_t lkpos[6];     // streaming: union position of each lane-kept bit
+  uint8_t pad2[4];
 };
 
 static_assert(sizeof(DevOp) == 64, "DevOp layout");
 static_assert(sizeof(DevGroup) == 64, "DevGroup layout");
 
-enum Variant : uint8_t { kVarGeneric = 0, kVarStream = 1, kVarMfma = 2 };
+enum Variant : uint8_t { kVarGeneric = 0, kVarStream = 1, kVarMfma = 2, kVarCell = 3 };
+
+// Cell mapping (kVarCell): lanes are union bits 0..5; rls = cell bits CB held
+// in registers per lane: the high sl cell bits are the summed bits 6..L-1
+// (serial), the low CB - sl ones the kept bits at union positions
+// uperm[0..CB - sl) (the unit bits follow in uperm).  Ops [0, n_step) hold
+// serial bits (all ops when sl = 0); n_unit = the most unit-bit runs of any
+// operand.  Each op's stab entry starts its table: 2^CB cell offsets
+// (elements), kCellURuns / 2 words of unit-bit runs (src | len << 5 | dst <<
+// 11, two per word, src counting unit bits; unused runs 0) giving the unit
+// part of its index, then the mask of the cell bits its index holds.
+constexpr int kCellMinCB = 2, kCellMaxCB = 4, kCellRuleCB = 3;
+constexpr int kCellURuns = 16;
+constexpr int kCellMaxSerial = 2;
+// LDS words of a cell group's tables: per operand 2^CB lane tables of 64
+// words and its unit-bit runs.
+constexpr int cell_lds_words(int n_ops, int cb) { return n_ops * ((64 << cb) + kCellURuns / 2); }
+constexpr int cell_table_words(int cb) { return (1 << cb) + kCellURuns / 2 + 1; }
+constexpr int kCellMaxLdsWords = 16384;  // 64 KiB per workgroup
 
 // Matrix form (kVarMfma): ops are [a, ops into At..., b, ops into Bt...,
 // ops into Out...] with n_unit = |At side|, n_step = |Bt side|, n_serial =

@@ -30,6 +30,9 @@
 // factors over the summed indices is a batched complex matrix product; it
 // runs as three real FP32 products on the matrix cores (3M).
 #include <cstddef>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
@@ -122,11 +125,22 @@ struct GI {
   int w, L, n_ops, variant, rls, sl, lk, n_unit, n_step, n_serial, n_step0;
   int n_ubits, prec, cvt, n_mb, n_nb, n_bb;
   uint32_t le_lo, le_hi;  // level_end[0..3], [4..7]
+  uint32_t lk_lo, lk_hi;  // lkpos[0..1], [2..5]
   __device__ int le(int l) const { return ((l < 4 ? le_lo >> (8 * l) : le_hi >> (8 * (l - 4)))) & 0xFF; }
+  // union bits of the lane-kept part of a lane (streaming mapping)
+  __device__ uint32_t lane_kept(uint32_t hi) const {
+    uint32_t I = 0;
+    for (int j = 0; j < lk; j++) {
+      const uint32_t pos = (j < 2 ? lk_lo >> (8 * j) : lk_hi >> (8 * (j - 2))) & 0xFFu;
+      I |= ((hi >> j) & 1u) << pos;
+    }
+    return I;
+  }
 };
 static_assert(offsetof(DevGroup, w) == 24 && offsetof(DevGroup, rls) == 28 &&
                   offsetof(DevGroup, n_step) == 32 && offsetof(DevGroup, level_end) == 36 &&
-                  offsetof(DevGroup, n_ubits) == 44 && offsetof(DevGroup, n_nb) == 48,
+                  offsetof(DevGroup, n_ubits) == 44 && offsetof(DevGroup, n_nb) == 48 &&
+                  offsetof(DevGroup, lkpos) == 50,
               "DevGroup word layout");
 __device__ __forceinline__ GI load_group(const DevGroup *g) {
   GI G;
@@ -156,6 +170,8 @@ __device__ __forceinline__ GI load_group(const DevGroup *g) {
   G.n_mb = e >> 24;
   G.n_nb = f & 0xFF;
   G.n_bb = (f >> 8) & 0xFF;
+  G.lk_lo = f >> 16;
+  G.lk_hi = dword(g, 13);
   return G;
 }
 
@@ -292,11 +308,11 @@ __device__ __forceinline__ void generic_unit(const GI &G, const DevOp *__restric
 // Lane parts of every operand of the group: pext of the lane bits.
 __device__ __forceinline__ void stream_setup(const GI &G, const DevOp *__restrict__ gops,
                                              uint32_t *s_lane) {
-  const uint32_t rls = G.rls, L = G.L;
+  const uint32_t rls = G.rls;
   for (int e = threadIdx.x; e < G.n_ops * 64; e += blockDim.x) {
     const int k = e >> 6, lane = e & 63;
     const uint32_t lo = (uint32_t)lane & ((1u << rls) - 1u), hi = (uint32_t)lane >> rls;
-    s_lane[e] = pext_runs((lo << 1) | (hi << L), gops[k]);
+    s_lane[e] = pext_runs((lo << 1) | G.lane_kept(hi), gops[k]);
   }
 }
 
@@ -477,8 +493,197 @@ __device__ __forceinline__ void stream_unit(const GI &G, const DevOp *__restrict
   // lane-summed bits: butterflies
   for (int b = 0; b < rls; b++) acc = cadd(acc, shfl_xor2(acc, 1 << b));
   if ((lane & ((1 << rls) - 1)) == 0) {
-    const uint32_t o = (Iu >> L) | ((uint32_t)lane >> rls);
+    const uint32_t o = (Iu | G.lane_kept((uint32_t)lane >> rls)) >> L;
     if (o < (1u << (G.w - L))) ((T *)outp(data, G, set))[o] = acc;
+  }
+}
+
+// -------------------------------------------------------------------- cells
+
+// Per-lane operand constants of the cell mapping: lane k holds operand k's
+// (k < n_ops <= 64).
+struct CellLane {
+  uint64_t base;    // address of the operand in angle set 0
+  uint64_t sstride; // bytes between angle sets
+  uint32_t es, dt;  // element bytes in the group's arithmetic, storage type
+  uint32_t cm;      // cell bits the operand's index holds
+};
+
+// Block-wide setup.  LDS: the byte offsets of every operand, cell and lane
+// ([k][c][lane]: lane part plus cell part of the operand's index), then the
+// unit-bit runs of every operand ([k][kCellURuns / 2]).  Registers: the
+// lane's own operand constants.
+template <class T, bool CVT, int NC>
+__device__ __forceinline__ void cell_setup(const GI &G, const DevOp *__restrict__ gops,
+                                           const int32_t *__restrict__ ctab, char *data,
+                                           uint32_t *s_tab, CellLane &cl) {
+  for (int e = threadIdx.x; e < G.n_ops * NC * 64; e += blockDim.x) {
+    const int k = e / (NC * 64), c = (e / 64) % NC, lane = e & 63;
+    const DevOp &o = gops[k];
+    s_tab[e] = (pext_runs((uint32_t)lane, o) + (uint32_t)ctab[o.stab + c]) * esize<T, CVT>(op_dt(o));
+  }
+  uint32_t *s_ur = s_tab + G.n_ops * NC * 64;
+  for (int e = threadIdx.x; e < G.n_ops * (kCellURuns / 2); e += blockDim.x) {
+    const int k = e / (kCellURuns / 2), i = e % (kCellURuns / 2);
+    s_ur[e] = (uint32_t)ctab[gops[k].stab + NC + i];
+  }
+  const int k = min((int)(threadIdx.x & 63), G.n_ops - 1);
+  const DevOp &o = gops[k];
+  cl.dt = (uint32_t)o.dt;
+  cl.es = esize<T, CVT>(cl.dt);
+  cl.base = (uint64_t)(data + o.off);
+  cl.sstride = (uint64_t)o.sstride;
+  cl.cm = (uint32_t)ctab[o.stab + NC + kCellURuns / 2];
+}
+
+// One reduce-scatter step over lane bit t: of the 2 * HALF accumulators the
+// lane keeps the half selected by its bit t, adding the partner lane's copy.
+template <class T, int HALF>
+__device__ __forceinline__ void reduce_scatter_step(T *acc, int lane, int t) {
+  const bool hi = ((lane >> t) & 1) != 0;
+#pragma unroll
+  for (int i = 0; i < HALF; i++) {
+    const T keep = hi ? acc[i + HALF] : acc[i];
+    const T send = hi ? acc[i] : acc[i + HALF];
+    acc[i] = cadd(keep, shfl_xor2(send, 1 << t));
+  }
+}
+
+// Sums the lane-summed bits 0..ls-1 of the 2^RB register accumulators and
+// writes the results: a reduce-scatter over the first q = min(RB, ls) bits
+// (afterwards lane bit t selects half of the cells), butterflies for the rest.
+template <class T, int RB>
+__device__ __forceinline__ void cell_finish(const GI &G, T *acc, const uint8_t *__restrict__ ubit,
+                                            uint32_t Iu, int ls, int lane, T *out) {
+  constexpr int NR = 1 << RB;
+  const int L = G.L, q = min(RB, ls);
+  if (RB >= 1 && ls > 0) reduce_scatter_step<T, (NR >> 1)>(acc, lane, 0);
+  if (RB >= 2 && ls > 1) reduce_scatter_step<T, (NR >> 2)>(acc, lane, 1);
+  if (RB >= 3 && ls > 2) reduce_scatter_step<T, (NR >> 3)>(acc, lane, 2);
+  if (RB >= 4 && ls > 3) reduce_scatter_step<T, (NR >> 4)>(acc, lane, 3);
+  const int nacc = NR >> q;
+  for (int t = q; t < ls; t++) {
+#pragma unroll
+    for (int i = 0; i < NR; i++)
+      if (i < nacc) acc[i] = cadd(acc[i], shfl_xor2(acc[i], 1 << t));
+  }
+  // lanes whose summed bits q..ls-1 are zero hold the results; acc[i] is
+  // register cell i + sum_t (lane bit t) * (NR >> (t + 1))
+  if ((((uint32_t)lane >> q) & ((1u << (ls - q)) - 1u)) == 0) {
+    const uint32_t Ik = Iu | ((uint32_t)lane & ~((1u << ls) - 1u));
+    uint32_t jb = 0;
+    for (int t = 0; t < q; t++) jb += (((uint32_t)lane >> t) & 1u) * (uint32_t)(NR >> (t + 1));
+    const uint32_t nout = 1u << (G.w - L);
+#pragma unroll
+    for (int i = 0; i < NR; i++) {
+      if (i < nacc) {
+        const uint32_t j = jb + (uint32_t)i;
+        uint32_t I = Ik;
+#pragma unroll
+        for (int b = 0; b < RB; b++) I |= ((j >> b) & 1u) << ubit_at(ubit, b);
+        const uint32_t o = I >> L;
+        if (o < nout) out[o] = acc[i];
+      }
+    }
+  }
+}
+
+// acc[c] (c < N; first: set to) times operand k, whose index holds the cell
+// bits CM: only the distinct cells (c & ~CM == 0) are loaded, each value
+// serving every cell that differs from it in bits outside CM.
+template <class T, bool CVT, int NC, int N, int CM>
+__device__ __forceinline__ void cell_op_cm(T *acc, bool first, const char *p, int dt,
+                                           const uint32_t *lt) {
+  T v[N];
+#pragma unroll
+  for (int c = 0; c < N; c++)
+    if ((c & ~CM) == 0) v[c] = gload_dt<T, CVT>(p, lt[c * 64], dt);
+  if (first) {
+#pragma unroll
+    for (int c = 0; c < N; c++) acc[c] = v[c & CM];
+  } else {
+#pragma unroll
+    for (int c = 0; c < N; c++) acc[c] = cmul(acc[c], v[c & CM]);
+  }
+}
+
+// acc[c] (c < N) times operand k (uniform): scalar base from lane k's
+// address, per-lane offsets of each cell from the LDS table.
+template <class T, bool CVT, int NC, int N>
+__device__ __forceinline__ void cell_op(T *acc, bool first, int k, const CellLane &cl,
+                                        uint64_t addr, const uint32_t *s_tab, int lane) {
+  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)addr, k);
+  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(addr >> 32), k);
+  const char *p = (const char *)(((uint64_t)hi << 32) | lo);
+  const int dt = CVT ? (int)__builtin_amdgcn_readlane(cl.dt, k) : 0;
+  const uint32_t cm = __builtin_amdgcn_readlane(cl.cm, k) & (uint32_t)(N - 1);
+  const uint32_t *lt = s_tab + k * NC * 64 + lane;
+#define QTN_CM(m) \
+  case m: cell_op_cm<T, CVT, NC, N, (m) & (N - 1)>(acc, first, p, dt, lt); break;
+  switch (cm) {
+    QTN_CM(0) QTN_CM(1) QTN_CM(2) QTN_CM(3) QTN_CM(4) QTN_CM(5) QTN_CM(6) QTN_CM(7)
+    QTN_CM(8) QTN_CM(9) QTN_CM(10) QTN_CM(11) QTN_CM(12) QTN_CM(13) QTN_CM(14)
+    default: cell_op_cm<T, CVT, NC, N, (15 & (N - 1))>(acc, first, p, dt, lt); break;
+  }
+#undef QTN_CM
+}
+
+// One wave unit of the cell mapping.  The lanes take union bits 0..5, the
+// lowest index bits of the large operands, so one load of an operand by the
+// wave covers whole cache lines.  Each lane holds NC = 2^CB cells: the high
+// SL cell bits are the summed bits 6..L-1 (serial), the low RB = CB - SL
+// cell bits kept bits.  Every point multiplies all operands: the step
+// operands (those with serial bits) in every cell, then the serial cells are
+// summed, then the other operands multiply the 2^RB remaining cells.  The
+// lane-summed bits are reduced last.  Operand addresses for the unit are
+// formed by lane k for operand k.
+template <class T, bool CVT, int CB, int SL>
+__device__ __forceinline__ void cell_unit(const GI &G, const CellLane &cl,
+                                          const uint8_t *__restrict__ ubit, char *__restrict__ data,
+                                          const uint32_t *s_tab, uint32_t u, int lane,
+                                          uint32_t set) {
+  constexpr int NC = 1 << CB, RB = CB - SL, NR = 1 << RB;
+  const int n_step = G.n_step, n_ops = G.n_ops;
+  // lane k: unit part of operand k's index, then its address for this unit
+  const uint32_t *s_ur = s_tab + n_ops * NC * 64 + min(lane, n_ops - 1) * (kCellURuns / 2);
+  uint32_t ub = 0;
+  for (int i = 0; i < G.n_unit; i += 2) {
+    const uint32_t w = s_ur[i >> 1];
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+      const uint32_t rr = (w >> (16 * h)) & 0xFFFFu;  // an unused run is 0
+      const uint32_t src = rr & 31u, len = (rr >> 5) & 63u, dst = rr >> 11;
+      ub |= ((u >> src) & (uint32_t)((1ull << len) - 1ull)) << dst;
+    }
+  }
+  const uint64_t addr = cl.base + (uint64_t)set * cl.sstride + (uint64_t)ub * cl.es;
+  T acc[NC];
+  for (int k = 0; k < n_step; k++) cell_op<T, CVT, NC, NC>(acc, k == 0, k, cl, addr, s_tab, lane);
+  // sum the serial cell bits (the high ones)
+#pragma unroll
+  for (int b = CB - 1; b >= RB; b--) {
+#pragma unroll
+    for (int c = 0; c < (1 << b); c++) acc[c] = cadd(acc[c], acc[c + (1 << b)]);
+  }
+  for (int k = n_step; k < n_ops; k++) cell_op<T, CVT, NC, NR>(acc, false, k, cl, addr, s_tab, lane);
+  const uint32_t Iu = unit_bits(u, ubit, G.n_ubits, RB);
+  cell_finish<T, RB>(G, acc, ubit, Iu, SL > 0 ? 6 : min(G.L, 6), lane, (T *)outp(data, G, set));
+}
+
+// Setup and units [u0, u1) (one per wave, strided) of a cell-mapped group.
+template <class T, bool CVT, int CB, int SL>
+__device__ __forceinline__ void cell_units(const GI &G, const DevOp *__restrict__ gops,
+                                           const int32_t *__restrict__ ctab,
+                                           const uint8_t *__restrict__ ubit, char *__restrict__ data,
+                                           uint32_t *s_tab, uint32_t u0, uint32_t u1,
+                                           uint32_t stride, uint32_t set_units, int lane) {
+  CellLane cl;
+  cell_setup<T, CVT, 1 << CB>(G, gops, ctab, data, s_tab, cl);
+  __syncthreads();
+  // flat unit f: angle set f / set_units, unit f % set_units
+  for (uint32_t f = u0; f < u1; f += stride) {
+    const uint32_t set = f / set_units;
+    cell_unit<T, CVT, CB, SL>(G, cl, ubit, data, s_tab, f - set * set_units, lane, set);
   }
 }
 
@@ -633,14 +838,27 @@ __global__ __launch_bounds__(kBlock) void k_block_groups(char *__restrict__ data
   }
 }
 
-// Blocks are dealt round-robin to the 8 XCDs; renumber them so that each XCD
-// walks one contiguous slice of the union space (its own L2).
-__device__ __forceinline__ void wide_range(uint32_t n_units, uint32_t *ub, uint32_t *ue) {
+// Units of a wide launch.  Blocks are dealt round-robin to the 8 XCDs; each
+// XCD takes one contiguous slice of the flat unit space (its own L2), and the
+// XCD's blocks walk that slice together, one unit per wave and chunk by chunk,
+// so that at any time they work on neighbouring units, which share the data
+// of the operands lacking the low unit bits.  (Each block walking a slice of
+// its own instead spreads the resident blocks over as many distant regions,
+// whose reused data does not fit in the L2 at once.)  The host keeps
+// n_units + the grid's wave count below 2^32.
+struct UnitWalk {
+  uint32_t first, end, stride;
+};
+__device__ __forceinline__ UnitWalk wide_walk(uint32_t n_units, uint32_t nw, uint32_t w) {
   const uint32_t nb = gridDim.x, b = blockIdx.x;
-  const uint32_t lb = (nb % 8u == 0u) ? (b % 8u) * (nb / 8u) + b / 8u : b;
-  const uint32_t per = (n_units + nb - 1) / nb;
-  *ub = lb * per;
-  *ue = min(n_units, *ub + per);
+  const bool xcd = nb % 8u == 0u;
+  const uint32_t nx = xcd ? 8u : 1u, x = xcd ? b % 8u : 0u, j = xcd ? b / 8u : b;
+  const uint32_t per = (n_units + nx - 1) / nx;
+  UnitWalk W;
+  W.end = min(n_units, x * per + per);
+  W.first = x * per + j * nw + w;
+  W.stride = (nb / nx) * nw;
+  return W;
 }
 
 template <class T, bool CVT>
@@ -650,22 +868,39 @@ __global__ __launch_bounds__(kBlock) void k_wide_stream(char *__restrict__ data,
                                                         const int32_t *__restrict__ stab,
                                                         const uint8_t *__restrict__ uperm, int gid,
                                                         uint32_t n_sets) {
-  __shared__ __align__(16) uint32_t s_lane[kStreamMaxOps * 64];
+  // lane tables of the group's operands: n_ops * 64 words, sized at launch
+  extern __shared__ __align__(16) uint32_t s_lane[];
   const GI G = load_group(groups + gid);
   const DevOp *gops = ops + G.op_begin;
   const int lane = threadIdx.x & 63;
-  uint32_t ub, ue;
-  wide_range(G.n_units * n_sets, &ub, &ue);
   const uint32_t nw = blockDim.x >> 6;
   const uint32_t w0 = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const UnitWalk W = wide_walk(G.n_units * n_sets, nw, w0);
   stream_setup(G, gops, s_lane);
   __syncthreads();
   // flat unit f: angle set f / n_units, unit f % n_units
-  for (uint32_t f = ub + w0; f < ue; f += nw) {
+  for (uint32_t f = W.first; f < W.end; f += W.stride) {
     const uint32_t set = f / G.n_units;
     stream_unit<T, CVT>(G, gops, stab, uperm + 32 * gid, data, s_lane, f - set * G.n_units, lane,
                         set);
   }
+}
+
+template <class T, bool CVT, int CB, int SL>
+__global__ __launch_bounds__(kBlock) void k_wide_cells(char *__restrict__ data,
+                                                       const DevGroup *__restrict__ groups,
+                                                       const DevOp *__restrict__ ops,
+                                                       const int32_t *__restrict__ ctab,
+                                                       const uint8_t *__restrict__ uperm, int gid,
+                                                       uint32_t n_sets) {
+  // offset tables of the group's operands, sized at launch
+  extern __shared__ __align__(16) uint32_t s_tab[];
+  const GI G = load_group(groups + gid);
+  const uint32_t nw = blockDim.x >> 6;
+  const uint32_t w0 = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const UnitWalk W = wide_walk(G.n_units * n_sets, nw, w0);
+  cell_units<T, CVT, CB, SL>(G, ops + G.op_begin, ctab, uperm + 32 * gid, data, s_tab, W.first,
+                             W.end, W.stride, G.n_units, threadIdx.x & 63);
 }
 
 template <class T, bool CVT>
@@ -678,11 +913,10 @@ __global__ __launch_bounds__(kBlock) void k_wide_generic(char *__restrict__ data
   const GI G = load_group(groups + gid);
   const DevOp *gops = ops + G.op_begin;
   const int lane = threadIdx.x & 63;
-  uint32_t ub, ue;
-  wide_range(G.n_units * n_sets, &ub, &ue);
   const uint32_t nw = blockDim.x >> 6;
   const uint32_t w0 = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  for (uint32_t f = ub + w0; f < ue; f += nw) {
+  const UnitWalk W = wide_walk(G.n_units * n_sets, nw, w0);
+  for (uint32_t f = W.first; f < W.end; f += W.stride) {
     const uint32_t set = f / G.n_units;
     generic_unit<T, CVT>(G, gops, uperm + 32 * gid, data, f - set * G.n_units, lane, set);
   }
@@ -696,9 +930,8 @@ __global__ __launch_bounds__(kBlock) void k_wide_mfma(char *__restrict__ data,
                                                       uint32_t n_sets) {
   __shared__ __align__(16) float2 s_tile[(kMfmaTM + kMfmaTN) * kMfmaLd];
   const GI G = load_group(groups + gid);
-  uint32_t ub, ue;
-  wide_range(G.n_units * n_sets, &ub, &ue);
-  for (uint32_t f = ub; f < ue; f++) {
+  const UnitWalk W = wide_walk(G.n_units * n_sets, 1, 0);
+  for (uint32_t f = W.first; f < W.end; f += W.stride) {
     const uint32_t set = f / G.n_units;
     mfma_tile<CVT>(G, ops + G.op_begin, uperm + 32 * gid, data, s_tile, f - set * G.n_units, set);
   }
@@ -995,23 +1228,50 @@ __global__ void k_reduce(const char *__restrict__ scalar_base, int64_t scalar_ss
 
 }  // namespace
 
-int wide_blocks(uint32_t n_units) {
-  const uint32_t waves = kBlock / 64;
-  uint32_t b = (n_units + waves - 1) / waves;
-  if (b > 2048) b = 2048;
+// Grid of a wide launch: one wave per unit up to the blocks the device holds
+// at once (all of them resident, so that the blocks of an XCD walk
+// neighbouring units together and share their operand data in its L2), a
+// multiple of the 8 XCDs.  Residency is queried once per kernel, LDS size and
+// device.
+template <class K>
+int wide_grid(K kernel, size_t lds, uint32_t n_units, uint32_t units_per_block = kBlock / 64) {
+  static std::mutex mu;
+  static std::map<std::tuple<const void *, size_t, int>, int> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+  const auto key = std::make_tuple((const void *)kernel, lds, dev);
+  int resident = 0;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+      resident = it->second;
+    } else {
+      int per_cu = 0, n_cu = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, lds) != hipSuccess ||
+          hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        per_cu = n_cu = 0;
+      resident = std::max(1, per_cu) * std::max(1, n_cu);
+      cache[key] = resident;
+    }
+  }
+  uint32_t b = n_units / units_per_block + (n_units % units_per_block ? 1u : 0u);
+  if (b > (uint32_t)resident) b = (uint32_t)resident;
   if (b >= 8) b &= ~7u;
   return (int)(b ? b : 1);
 }
 
 // Launch with optional start/stop events attached to the dispatch itself:
 // they time the kernel alone, without queueing or event-packet overhead.
-#define QTN_LAUNCH(t0, t1, K, grid, block, s, ...)                       \
-  do {                                                                  \
-    if (t0)                                                             \
-      hipExtLaunchKernelGGL(K, grid, block, 0, s, t0, t1, 0, __VA_ARGS__); \
-    else                                                                \
-      hipLaunchKernelGGL(K, grid, block, 0, s, __VA_ARGS__);            \
+#define QTN_LAUNCH_LDS(t0, t1, K, grid, block, lds, s, ...)                  \
+  do {                                                                      \
+    if (t0)                                                                 \
+      hipExtLaunchKernelGGL(K, grid, block, lds, s, t0, t1, 0, __VA_ARGS__); \
+    else                                                                    \
+      hipLaunchKernelGGL(K, grid, block, lds, s, __VA_ARGS__);              \
   } while (0)
+#define QTN_LAUNCH(t0, t1, K, grid, block, s, ...) \
+  QTN_LAUNCH_LDS(t0, t1, K, grid, block, 0, s, __VA_ARGS__)
 
 // Nothing to launch: the timing events still complete (zero duration).
 inline hipError_t no_launch(hipEvent_t t0, hipEvent_t t1, hipStream_t s) {
@@ -1040,44 +1300,77 @@ hipError_t launch_block_groups(int prec, void *data, const DevGroup *groups, con
 }
 
 template <class T, bool CVT>
-void launch_wide_t(int variant, int nb, char *d, const DevGroup *groups, const DevOp *ops,
-                   const int32_t *stab, const uint8_t *uperm, int group, uint32_t n_sets,
-                   hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
-  if (variant == kVarStream)
-    QTN_LAUNCH(t0, t1, (k_wide_stream<T, CVT>), dim3(nb), dim3(kBlock), s, d, groups, ops, stab,
-               uperm, group, n_sets);
-  else
+void launch_wide_t(const DevGroup &hg, uint32_t units, char *d, const DevGroup *groups,
+                   const DevOp *ops, const int32_t *stab, const uint8_t *uperm, int group,
+                   uint32_t n_sets, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
+  if (hg.variant == kVarStream) {
+    const size_t lds = (size_t)hg.n_ops * 64 * sizeof(uint32_t);
+    const int nb = wide_grid(k_wide_stream<T, CVT>, lds, units);
+    QTN_LAUNCH_LDS(t0, t1, (k_wide_stream<T, CVT>), dim3(nb), dim3(kBlock), lds, s, d, groups, ops,
+                   stab, uperm, group, n_sets);
+  } else if (hg.variant == kVarCell) {
+    const size_t lds = cell_lds_words(hg.n_ops, hg.rls) * sizeof(uint32_t);
+#define QTN_CELL_LAUNCH(CB, SL)                                                                  \
+  do {                                                                                           \
+    const int nb = wide_grid(k_wide_cells<T, CVT, CB, SL>, lds, units);                         \
+    QTN_LAUNCH_LDS(t0, t1, (k_wide_cells<T, CVT, CB, SL>), dim3(nb), dim3(kBlock), lds, s, d,   \
+                   groups, ops, stab, uperm, group, n_sets);                                      \
+  } while (0)
+    if (hg.rls == 2 && hg.sl == 0) QTN_CELL_LAUNCH(2, 0);
+    else if (hg.rls == 2 && hg.sl == 1) QTN_CELL_LAUNCH(2, 1);
+    else if (hg.rls == 2) QTN_CELL_LAUNCH(2, 2);
+    else if (hg.rls == 3 && hg.sl == 0) QTN_CELL_LAUNCH(3, 0);
+    else if (hg.rls == 3 && hg.sl == 1) QTN_CELL_LAUNCH(3, 1);
+    else if (hg.rls == 3) QTN_CELL_LAUNCH(3, 2);
+    else if (hg.sl == 0) QTN_CELL_LAUNCH(4, 0);
+    else if (hg.sl == 1) QTN_CELL_LAUNCH(4, 1);
+    else QTN_CELL_LAUNCH(4, 2);
+#undef QTN_CELL_LAUNCH
+  } else {
+    const int nb = wide_grid(k_wide_generic<T, CVT>, 0, units);
     QTN_LAUNCH(t0, t1, (k_wide_generic<T, CVT>), dim3(nb), dim3(kBlock), s, d, groups, ops, stab,
                uperm, group, n_sets);
+  }
 }
 
-hipError_t launch_wide_group(int prec, bool cvt, int variant, void *data, const DevGroup *groups,
+hipError_t launch_wide_group(const DevGroup &hg, void *data, const DevGroup *groups,
                              const DevOp *ops, const int32_t *stab, const uint8_t *uperm,
-                             int group, uint32_t n_units, int n_sets, hipStream_t s,
-                             hipEvent_t t0, hipEvent_t t1) {
-  if (n_sets <= 0 || (uint64_t)n_units * (uint64_t)n_sets > 0xFFFFFFFFull)
+                             int group, int n_sets, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
+  const uint32_t n_units = hg.n_units;
+  // the unit walk needs the flat unit count plus the grid's waves below 2^32
+  if (n_sets <= 0 || (uint64_t)n_units * (uint64_t)n_sets > 0x7FFFFFFFull) return hipErrorInvalidValue;
+  if ((hg.variant == kVarStream || hg.variant == kVarCell) &&
+      (hg.n_ops < 1 || hg.n_ops > kStreamMaxOps))
     return hipErrorInvalidValue;
-  const uint32_t ns = (uint32_t)n_sets;
-  const int nb = wide_blocks(n_units * ns);
+  if (hg.variant == kVarCell && (hg.rls < kCellMinCB || hg.rls > kCellMaxCB || hg.n_ops > 64 ||
+                                 hg.sl > kCellMaxSerial || hg.sl > hg.rls ||
+                                 cell_lds_words(hg.n_ops, hg.rls) > kCellMaxLdsWords))
+    return hipErrorInvalidValue;
+  const uint32_t ns = (uint32_t)n_sets, units = n_units * ns;
   char *d = (char *)data;
-  if (variant == kVarMfma) {
-    if (prec != kPrecC64) return hipErrorInvalidValue;  // complex64 arithmetic only
-    if (cvt)
+  const bool cvt = hg.cvt != 0;
+  if (hg.variant == kVarMfma) {
+    if (hg.prec != kPrecC64) return hipErrorInvalidValue;  // complex64 arithmetic only
+    // a unit is one tile of the whole block
+    if (cvt) {
+      const int nb = wide_grid(k_wide_mfma<true>, 0, units, 1);
       QTN_LAUNCH(t0, t1, k_wide_mfma<true>, dim3(nb), dim3(kBlock), s, d, groups, ops, uperm,
                  group, ns);
-    else
+    } else {
+      const int nb = wide_grid(k_wide_mfma<false>, 0, units, 1);
       QTN_LAUNCH(t0, t1, k_wide_mfma<false>, dim3(nb), dim3(kBlock), s, d, groups, ops, uperm,
                  group, ns);
+    }
     return hipGetLastError();
   }
-  if (prec == kPrecC128 && !cvt)
-    launch_wide_t<double2, false>(variant, nb, d, groups, ops, stab, uperm, group, ns, s, t0, t1);
-  else if (prec == kPrecC128)
-    launch_wide_t<double2, true>(variant, nb, d, groups, ops, stab, uperm, group, ns, s, t0, t1);
+  if (hg.prec == kPrecC128 && !cvt)
+    launch_wide_t<double2, false>(hg, units, d, groups, ops, stab, uperm, group, ns, s, t0, t1);
+  else if (hg.prec == kPrecC128)
+    launch_wide_t<double2, true>(hg, units, d, groups, ops, stab, uperm, group, ns, s, t0, t1);
   else if (!cvt)
-    launch_wide_t<float2, false>(variant, nb, d, groups, ops, stab, uperm, group, ns, s, t0, t1);
+    launch_wide_t<float2, false>(hg, units, d, groups, ops, stab, uperm, group, ns, s, t0, t1);
   else
-    launch_wide_t<float2, true>(variant, nb, d, groups, ops, stab, uperm, group, ns, s, t0, t1);
+    launch_wide_t<float2, true>(hg, units, d, groups, ops, stab, uperm, group, ns, s, t0, t1);
   return hipGetLastError();
 }
 

@@ -38,13 +38,12 @@ hipError_t launch_block_groups(int prec, void *data, const DevGroup *groups,
                                int range_base, int n_blocks, int n_sets, hipStream_t s,
                                hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 
-// One group over the whole grid, with the kernel of its mapping variant, in
-// precision prec; cvt: some operand is stored in the other precision.
-hipError_t launch_wide_group(int prec, bool cvt, int variant, void *data,
-                             const DevGroup *groups, const DevOp *ops,
-                             const int32_t *stab, const uint8_t *uperm, int group,
-                             uint32_t n_units, int n_sets, hipStream_t s,
-                             hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
+// One group over the whole grid, with the kernel of its mapping variant and
+// precision; hg is the host copy of the group's descriptor.
+hipError_t launch_wide_group(const DevGroup &hg, void *data, const DevGroup *groups,
+                             const DevOp *ops, const int32_t *stab, const uint8_t *uperm,
+                             int group, int n_sets, hipStream_t s, hipEvent_t t0 = nullptr,
+                             hipEvent_t t1 = nullptr);
 
 // Clears the control words, then runs every light cone's task list in
 // lockstep inside one persistent launch of n_blocks resident blocks.
@@ -87,7 +86,5 @@ hipError_t launch_reduce(int prec, const void *data, int64_t scalar_off,
                          const int *net_cone_begin, int n_cones, int n_nets, int n_sets,
                          double *res, hipStream_t s);
 
-// Grid size used for a wide group.
-int wide_blocks(uint32_t n_units);
 
 }  // namespace qtn

@@ -126,6 +126,30 @@ def test_matrix_form_scheduled_only_in_complex64(qtn):
     assert counts[1, 3] > counts[2, 3] > 0
 
 
+def test_cell_mapping_scheduling_rules(qtn):
+    """The cell mapping is the rule for own-launch groups it fits; never inside
+    workgroups or the persistent executors, nor when another mapping is
+    requested; more cell bits need wider groups."""
+    inst = qs.instance(30, 3, 4, 0)
+    g, b = inst["angles"][0]
+
+    def cells(**cfg):
+        net = qtn.Network(30, inst["edges"], g, b, **cfg)
+        net.plan(0)
+        st = net.stats()
+        net.close()
+        return st["n_cell"], st["n_wide"]
+
+    n_cell, n_wide = cells()
+    assert 0 < n_cell <= n_wide
+    assert cells(variant=4) == (n_cell, n_wide)
+    assert cells(variant=1)[0] == 0 and cells(variant=2)[0] == 0
+    assert cells(executor=2)[0] == 0 and cells(executor=4)[0] == 0
+    assert cells(variant=4, lane_sum_bits=4)[0] <= cells(variant=4, lane_sum_bits=2)[0]
+    # a workgroup holds every group of width <= small_width
+    assert cells(small_width=32)[0] == 0
+
+
 @pytest.mark.parametrize("edges,msg", [
     ([(0, 0)], "self-loop"),
     ([(0, 1), (1, 0)], "repeated"),

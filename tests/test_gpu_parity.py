@@ -242,12 +242,14 @@ def test_autotune_keeps_parity(qtn, orc, gpu, prec):
     net = qtn.Network(20, inst["edges"], g, b)
     net.plan(prec)
     rep = net.autotune()
-    assert rep["n_candidates"] == 5 and rep["n_groups"] > 0
+    assert rep["n_candidates"] == 7 and rep["n_groups"] > 0
     # the first four candidates time every group; the matrix form only the
-    # complex64 groups that have one
+    # complex64 groups that have one, the cell mapping (3 and 4 cell bits)
+    # the groups wide enough for it
     assert rep["tuned_ms"] <= min(rep["cand_ms"][:4]) * (1 + 1e-9)
     if prec == 0:
         assert rep["cand_ms"][4] == 0 and rep["picks"][4] == 0
+    assert rep["cand_ms"][5] > 0
     feats, ms = net.tune_log()
     assert feats.shape[1] == 16 and len(feats) == len(ms) > 0
     assert np.all(ms[:, 2] > 0)
@@ -302,6 +304,58 @@ def test_matrix_form_parity(qtn, orc, gpu, n, p):
         net.close()
 
 
+@pytest.mark.parametrize("n,p", [(12, 2), (16, 3), (20, 3)])
+def test_cell_mapping_parity(qtn, orc, gpu, n, p):
+    """Cell mapping (lanes on union bits 0..5, kept bits in registers) for
+    every group wide enough for it: own launches, inside workgroups, in the
+    persistent executors, at 2 and 3 register bits, across summed-bit counts
+    below, at and above the six lane bits, in every precision."""
+    inst = qs.instance(n, 3, p, 13)
+    g, b = inst["angles"][0]
+    ref, ref_en = orc.energy(n, inst["edges"], g, b, threads=8)
+    for prec, cfg in [(0, dict(small_width=4)), (0, dict(small_width=4, lane_sum_bits=3)),
+                      (0, dict(small_width=4, max_levels=1)), (0, dict(small_width=4, max_levels=6)),
+                      (0, dict()), (0, dict(small_width=20, lane_sum_bits=3)),
+                      (0, dict(executor=2, small_width=4)), (0, dict(executor=4, small_width=4)),
+                      (1, dict(small_width=4)), (1, dict(small_width=4, lane_sum_bits=3)),
+                      (2, dict(small_width=4, mixed_width=8)),
+                      (2, dict(small_width=4, mixed_width=1, lane_sum_bits=3)),
+                      (0, dict(small_width=4, lane_sum_bits=4)), (1, dict(small_width=4, lane_sum_bits=4)),
+                      (2, dict(small_width=4, mixed_width=8, lane_sum_bits=4))]:
+        print(f"cells n={n} p={p} prec={prec} cfg={cfg}", flush=True)
+        net = qtn.Network(n, inst["edges"], g, b, variant=4, **cfg)
+        net.plan(prec)
+        zz, zi, en = net.contract()
+        _check(zz, zi, en, ref, ref_en, prec, f"cells {cfg}")
+        n_cell = net.stats()["n_cell"]
+        if cfg.get("executor", 0) in (2, 4):
+            assert n_cell == 0  # the persistent executors run no cell groups
+        if n_cell:
+            net.contract_timed()
+            assert any(r["kind"] == 2 and r["variant"] == 3 for r in net.launch_log())
+        elif cfg.get("small_width") == 4 and cfg.get("executor", 0) == 0:
+            assert cfg.get("lane_sum_bits") == 4 and n == 12  # no group wide enough
+        net.close()
+
+
+def test_cell_mapping_angle_batch(qtn, orc, gpu):
+    """Cell mapping over an angle batch: each set equals its single-set run."""
+    inst = qs.instance(20, 3, 3, 21, 3)
+    e = inst["edges"]
+    gs = np.array([a[0] for a in inst["angles"]])
+    bs = np.array([a[1] for a in inst["angles"]])
+    net = qtn.Network(20, e, gs[0], bs[0], variant=4, small_width=4, lane_sum_bits=3)
+    net.plan(0)
+    zz, en = net.contract_angles(gs, bs)
+    for k in range(3):
+        net.set_angles(gs[k], bs[k])
+        z1, _, e1 = net.contract()
+        assert np.array_equal(z1, zz[k]) and e1 == en[k], k
+        ref, ref_en = orc.energy(20, e, gs[k], bs[k], threads=8)
+        _check(zz[k], None, en[k], ref, ref_en, 0, f"cells set {k}")
+    net.close()
+
+
 def _golden(name):
     with open(os.path.join(HERE, "golden", f"{name}_oracle.json")) as f:
         return json.load(f)
@@ -311,7 +365,8 @@ def _golden(name):
     (0, 8, 0, 0, 0), (1, 8, 0, 0, 0), (0, 1, 0, 0, 0), (0, 8, 1, 0, 0), (1, 1, 0, 0, 0),
     (0, 8, 0, 64, 0), (1, 8, 0, 64, 0), (0, 8, 2, 16, 0), (0, 8, 0, 64, 2), (1, 8, 1, 64, 2),
     (0, 8, 0, 64, 3), (2, 8, 0, 64, 0), (2, 8, 0, 64, 2), (1, 8, 3, 64, 0), (2, 8, 3, 64, 0),
-    (0, 8, 0, 64, 4), (1, 8, 3, 64, 4)])
+    (0, 8, 0, 64, 4), (1, 8, 3, 64, 4), (0, 8, 4, 64, 0), (1, 8, 4, 64, 0), (2, 8, 4, 64, 0),
+    (0, 8, 4, 64, 2)])
 def test_cfg2_full_size_against_oracle(qtn, gpu, prec, levels, variant, trials, executor):
     """3-regular N=30, p=4 (Sec. II-E benchmark shape), all 45 light cones."""
     gd = _golden("cfg2")
@@ -324,7 +379,7 @@ def test_cfg2_full_size_against_oracle(qtn, gpu, prec, levels, variant, trials, 
 
 
 @pytest.mark.parametrize("prec,variant,mixed_width", [
-    (0, 0, 0), (1, 0, 0), (2, 0, 18), (2, 3, 18), (1, 3, 0), (2, 3, 12)])
+    (0, 0, 0), (1, 0, 0), (2, 0, 18), (2, 3, 18), (1, 3, 0), (2, 3, 12), (0, 4, 0), (2, 4, 18)])
 def test_cfg4_full_size_against_oracle(qtn, gpu, prec, variant, mixed_width):
     """4-regular N=40, p=3, all 80 light cones; mixed precision runs groups of
     width >= mixed_width in complex64 (matrix form where it applies with
