@@ -437,16 +437,25 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S, const Force *fo
           dg.rls = (uint8_t)cb;
           dg.sl = (uint8_t)std::max(0, G.L - 6);
           dg.lk = (uint8_t)(6 - std::min(G.L, 6));
-          // step operands (with serial bits) first; without serial bits every
-          // operand is one
-          const uint32_t serial_bits = ((1u << G.L) - 1u) & ~63u;
-          for (size_t k = 0; k < G.ops.size(); k++)
-            cls[k] = (!serial_bits || (G.ops[k].mask & serial_bits)) ? kClsStep : kClsUnit;
+          // operands by the first summed bit above the lanes they hold (the
+          // serial cells are summed in that order, each operand multiplying
+          // only the cells still open at its level): bit 6, then bit 7, then
+          // none; without serial bits every operand is at the first level
+          std::vector<int> lev(G.ops.size(), 0);
+          for (size_t k = 0; k < G.ops.size(); k++) {
+            const uint32_t m = G.ops[k].mask;
+            lev[k] = G.L <= 6 ? 0 : ((m >> 6) & 1u) ? 0 : (G.L > 7 && ((m >> 7) & 1u)) ? 1 : 2;
+            cls[k] = lev[k] < 2 ? kClsStep : kClsUnit;
+          }
           std::stable_sort(order.begin(), order.end(),
-                           [&](int a, int b) { return cls[a] > cls[b]; });
-          int ns = 0;
-          for (int k : order) ns += cls[k] == kClsStep ? 1 : 0;
-          dg.n_step = (uint8_t)ns;
+                           [&](int a, int b) { return lev[a] < lev[b]; });
+          int n0 = 0, n1 = 0;
+          for (int k : order) {
+            n0 += lev[k] == 0 ? 1 : 0;
+            n1 += lev[k] == 1 ? 1 : 0;
+          }
+          dg.n_step = (uint8_t)n0;
+          dg.n_serial = (uint8_t)n1;
           dg.n_units = 1u << (G.w - low - rb);
         } else if (stream) {
           dg.variant = kVarStream;
@@ -537,8 +546,33 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S, const Force *fo
           std::stable_sort(sc.begin(), sc.end());
           std::vector<int> regs;
           if (cell) {
-            for (int j = 0; j < rb; j++) regs.push_back(sc[j].second);
-            sc.erase(sc.begin(), sc.begin() + rb);
+            // register bits: one at a time, the kept bit that adds the fewest
+            // loads (an operand is loaded once per distinct value of the cell
+            // bits it holds), ties to the earlier bit of the order above
+            // cell bits held so far: the serial bits still open at the
+            // operand's level
+            std::vector<uint32_t> held(G.ops.size(), 0);
+            for (size_t k = 0; k < G.ops.size(); k++) {
+              const uint32_t m = G.ops[k].mask;
+              const int lv = G.L <= 6 ? 0 : ((m >> 6) & 1u) ? 0 : (G.L > 7 && ((m >> 7) & 1u)) ? 1 : 2;
+              for (int t = lv; t < dg.sl; t++) held[k] += (m >> (6 + t)) & 1u;
+            }
+            for (int j = 0; j < rb; j++) {
+              size_t bi = 0;
+              double best_cost = -1;
+              for (size_t q = 0; q < sc.size(); q++) {
+                double cost = 0;
+                for (size_t k = 0; k < G.ops.size(); k++)
+                  cost += std::ldexp(1.0, (int)held[k] + (int)((G.ops[k].mask >> sc[q].second) & 1u));
+                if (best_cost < 0 || cost < best_cost) {
+                  best_cost = cost;
+                  bi = q;
+                }
+              }
+              for (size_t k = 0; k < G.ops.size(); k++) held[k] += (G.ops[k].mask >> sc[bi].second) & 1u;
+              regs.push_back(sc[bi].second);
+              sc.erase(sc.begin() + bi);
+            }
             // the cell mapping forms an operand's unit offset from its runs
             // over the unit bits; past kCellURuns of them, ascending order
             // (at most one run per two unit bits)
@@ -608,11 +642,15 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S, const Force *fo
             d.stab = (int32_t)s.stab.size();
             const uint8_t *rp = s.uperm.data() + s.uperm.size() - 32;
             uint32_t cm = 0;
+            // serial cell bit rb + t is union bit 6 + sl - 1 - t (bit 6 the
+            // highest cell bit, summed first)
             for (int j = 0; j < rb; j++) cm |= ((o.mask >> rp[j]) & 1u) << j;
-            for (int t = 0; t < dg.sl; t++) cm |= ((o.mask >> (6 + t)) & 1u) << (rb + t);
+            for (int t = 0; t < dg.sl; t++)
+              cm |= ((o.mask >> (6 + dg.sl - 1 - t)) & 1u) << (rb + t);
             for (uint32_t c = 0; c < (1u << cb); c++) {
-              uint32_t I = (c >> rb) << 6;
+              uint32_t I = 0;
               for (int j = 0; j < rb; j++) I |= ((c >> j) & 1u) << rp[j];
+              for (int t = 0; t < dg.sl; t++) I |= ((c >> (rb + t)) & 1u) << (6 + dg.sl - 1 - t);
               s.stab.push_back((int32_t)pext32(I, o.mask));
             }
             const uint8_t *up = rp + rb;

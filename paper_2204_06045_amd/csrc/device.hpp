@@ -65,10 +65,11 @@ enum Variant : uint8_t { kVarGeneric = 0, kVarStream = 1, kVarMfma = 2, kVarCell
 
 // Cell mapping (kVarCell): lanes are union bits 0..5; rls = cell bits CB held
 // in registers per lane: the high sl cell bits are the summed bits 6..L-1
-// (serial), the low CB - sl ones the kept bits at union positions
-// uperm[0..CB - sl) (the unit bits follow in uperm).  Ops [0, n_step) hold
-// serial bits (all ops when sl = 0); n_unit = the most unit-bit runs of any
-// operand.  Each op's stab entry starts its table: 2^CB cell offsets
+// (serial; cell bit CB - 1 - t is union bit 6 + t), the low CB - sl ones the
+// kept bits at union positions uperm[0..CB - sl) (the unit bits follow in
+// uperm).  Ops [0, n_step) hold bit 6 (all ops when sl = 0), the next
+// n_serial hold bit 7 but not 6 (sl = 2), the rest no serial bit; n_unit =
+// the most unit-bit runs of any operand.  Each op's stab entry starts its table: 2^CB cell offsets
 // (elements), kCellURuns / 2 words of unit-bit runs (src | len << 5 | dst <<
 // 11, two per word, src counting unit bits; unused runs 0) giving the unit
 // part of its index, then the mask of the cell bits its index holds.

@@ -631,12 +631,13 @@ __device__ __forceinline__ void cell_op(T *acc, bool first, int k, const CellLan
 // One wave unit of the cell mapping.  The lanes take union bits 0..5, the
 // lowest index bits of the large operands, so one load of an operand by the
 // wave covers whole cache lines.  Each lane holds NC = 2^CB cells: the high
-// SL cell bits are the summed bits 6..L-1 (serial), the low RB = CB - SL
-// cell bits kept bits.  Every point multiplies all operands: the step
-// operands (those with serial bits) in every cell, then the serial cells are
-// summed, then the other operands multiply the 2^RB remaining cells.  The
-// lane-summed bits are reduced last.  Operand addresses for the unit are
-// formed by lane k for operand k.
+// SL cell bits are the summed bits 6..L-1 (serial; bit 6 the highest cell
+// bit), the low RB = CB - SL cell bits kept bits.  Every point multiplies all
+// operands, as bucket elimination orders them: the operands holding bit 6
+// in every cell, then bit 6 is summed, the operands holding bit 7 (but not
+// 6) in the cells left, bit 7 is summed, and the other operands multiply the
+// 2^RB register cells.  The lane-summed bits are reduced last.  Operand
+// addresses for the unit are formed by lane k for operand k.
 template <class T, bool CVT, int CB, int SL>
 __device__ __forceinline__ void cell_unit(const GI &G, const CellLane &cl,
                                           const uint8_t *__restrict__ ubit, char *__restrict__ data,
@@ -658,14 +659,24 @@ __device__ __forceinline__ void cell_unit(const GI &G, const CellLane &cl,
   }
   const uint64_t addr = cl.base + (uint64_t)set * cl.sstride + (uint64_t)ub * cl.es;
   T acc[NC];
+  // operands holding bit 6 (every operand when no bit is serial) in all cells
   for (int k = 0; k < n_step; k++) cell_op<T, CVT, NC, NC>(acc, k == 0, k, cl, addr, s_tab, lane);
-  // sum the serial cell bits (the high ones)
+  if (SL >= 1) {
+    // sum bit 6 (the highest cell bit)
 #pragma unroll
-  for (int b = CB - 1; b >= RB; b--) {
-#pragma unroll
-    for (int c = 0; c < (1 << b); c++) acc[c] = cadd(acc[c], acc[c + (1 << b)]);
+    for (int c = 0; c < NC / 2; c++) acc[c] = cadd(acc[c], acc[c + NC / 2]);
   }
-  for (int k = n_step; k < n_ops; k++) cell_op<T, CVT, NC, NR>(acc, false, k, cl, addr, s_tab, lane);
+  if (SL == 2) {
+    // operands holding bit 7 but not 6, then sum bit 7
+    const int k1 = n_step + G.n_serial;
+    for (int k = n_step; k < k1; k++)
+      cell_op<T, CVT, NC, (SL == 2 ? NC / 2 : 1)>(acc, false, k, cl, addr, s_tab, lane);
+#pragma unroll
+    for (int c = 0; c < NC / 4; c++) acc[c] = cadd(acc[c], acc[c + NC / 4]);
+  }
+  // the operands without serial bits in the register cells
+  for (int k = n_step + (SL == 2 ? G.n_serial : 0); k < n_ops; k++)
+    cell_op<T, CVT, NC, NR>(acc, false, k, cl, addr, s_tab, lane);
   const uint32_t Iu = unit_bits(u, ubit, G.n_ubits, RB);
   cell_finish<T, RB>(G, acc, ubit, Iu, SL > 0 ? 6 : min(G.L, 6), lane, (T *)outp(data, G, set));
 }
