@@ -573,6 +573,22 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S, const Force *fo
               regs.push_back(sc[bi].second);
               sc.erase(sc.begin() + bi);
             }
+            // with serial bits, the operands without them that hold no unit
+            // bit go first: their product over the register cells is formed
+            // once per angle set and reused by every unit (without serial
+            // bits it would span every cell and cost more registers than it
+            // saves)
+            if (dg.sl > 0) {
+              uint32_t unit_mask = 0;
+              for (auto &q : sc) unit_mask |= 1u << q.second;
+              const int last0 = dg.n_step + (dg.sl == 2 ? dg.n_serial : 0);
+              std::stable_partition(order.begin() + last0, order.end(),
+                                    [&](int k) { return (G.ops[k].mask & unit_mask) == 0; });
+              int nfix = 0;
+              for (size_t i = last0; i < order.size(); i++)
+                nfix += (G.ops[order[i]].mask & unit_mask) == 0 ? 1 : 0;
+              dg.n_step0 = (uint8_t)nfix;
+            }
             // the cell mapping forms an operand's unit offset from its runs
             // over the unit bits; past kCellURuns of them, ascending order
             // (at most one run per two unit bits)

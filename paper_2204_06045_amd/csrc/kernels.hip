@@ -641,10 +641,10 @@ __device__ __forceinline__ void cell_op(T *acc, bool first, int k, const CellLan
 template <class T, bool CVT, int CB, int SL>
 __device__ __forceinline__ void cell_unit(const GI &G, const CellLane &cl,
                                           const uint8_t *__restrict__ ubit, char *__restrict__ data,
-                                          const uint32_t *s_tab, uint32_t u, int lane,
+                                          const uint32_t *s_tab, const T *P, uint32_t u, int lane,
                                           uint32_t set) {
   constexpr int NC = 1 << CB, RB = CB - SL, NR = 1 << RB;
-  const int n_step = G.n_step, n_ops = G.n_ops;
+  const int n_step = G.n_step, n_ops = G.n_ops, nfix = G.n_step0;
   // lane k: unit part of operand k's index, then its address for this unit
   const uint32_t *s_ur = s_tab + n_ops * NC * 64 + min(lane, n_ops - 1) * (kCellURuns / 2);
   uint32_t ub = 0;
@@ -660,7 +660,8 @@ __device__ __forceinline__ void cell_unit(const GI &G, const CellLane &cl,
   const uint64_t addr = cl.base + (uint64_t)set * cl.sstride + (uint64_t)ub * cl.es;
   T acc[NC];
   // operands holding bit 6 (every operand when no bit is serial) in all cells
-  for (int k = 0; k < n_step; k++) cell_op<T, CVT, NC, NC>(acc, k == 0, k, cl, addr, s_tab, lane);
+  int k = 0;
+  for (; k < n_step; k++) cell_op<T, CVT, NC, NC>(acc, k == 0, k, cl, addr, s_tab, lane);
   if (SL >= 1) {
     // sum bit 6 (the highest cell bit)
 #pragma unroll
@@ -669,32 +670,54 @@ __device__ __forceinline__ void cell_unit(const GI &G, const CellLane &cl,
   if (SL == 2) {
     // operands holding bit 7 but not 6, then sum bit 7
     const int k1 = n_step + G.n_serial;
-    for (int k = n_step; k < k1; k++)
+    for (k = n_step; k < k1; k++)
       cell_op<T, CVT, NC, (SL == 2 ? NC / 2 : 1)>(acc, false, k, cl, addr, s_tab, lane);
 #pragma unroll
     for (int c = 0; c < NC / 4; c++) acc[c] = cadd(acc[c], acc[c + NC / 4]);
   }
-  // the operands without serial bits in the register cells
-  for (int k = n_step + (SL == 2 ? G.n_serial : 0); k < n_ops; k++)
-    cell_op<T, CVT, NC, NR>(acc, false, k, cl, addr, s_tab, lane);
+  if (SL >= 1) {
+    // the operands without serial bits in the register cells: first the
+    // unit-invariant product, then the others
+    k = n_step + (SL == 2 ? G.n_serial : 0);
+    if (SL >= 1 && nfix > 0) {
+#pragma unroll
+      for (int c = 0; c < NR; c++) acc[c] = cmul(acc[c], P[c]);
+      k += nfix;
+    }
+    for (; k < n_ops; k++) cell_op<T, CVT, NC, NR>(acc, false, k, cl, addr, s_tab, lane);
+  }
   const uint32_t Iu = unit_bits(u, ubit, G.n_ubits, RB);
   cell_finish<T, RB>(G, acc, ubit, Iu, SL > 0 ? 6 : min(G.L, 6), lane, (T *)outp(data, G, set));
 }
 
 // Setup and units [u0, u1) (one per wave, strided) of a cell-mapped group.
+// With serial bits, the product P of the operands without them that hold no
+// unit bit (the first n_step0 of the last level) depends only on the lane, the
+// register cell and the angle set; a wave forms it when its set changes.
 template <class T, bool CVT, int CB, int SL>
 __device__ __forceinline__ void cell_units(const GI &G, const DevOp *__restrict__ gops,
                                            const int32_t *__restrict__ ctab,
                                            const uint8_t *__restrict__ ubit, char *__restrict__ data,
                                            uint32_t *s_tab, uint32_t u0, uint32_t u1,
                                            uint32_t stride, uint32_t set_units, int lane) {
+  constexpr int NC = 1 << CB, NR = 1 << (CB - SL);
   CellLane cl;
-  cell_setup<T, CVT, 1 << CB>(G, gops, ctab, data, s_tab, cl);
+  cell_setup<T, CVT, NC>(G, gops, ctab, data, s_tab, cl);
   __syncthreads();
+  const int nfix = SL > 0 ? G.n_step0 : 0;
+  const int kf = G.n_step + (SL == 2 ? G.n_serial : 0);
+  T P[SL > 0 ? NR : 1];
+  uint32_t pset = 0xFFFFFFFFu;
   // flat unit f: angle set f / set_units, unit f % set_units
   for (uint32_t f = u0; f < u1; f += stride) {
     const uint32_t set = f / set_units;
-    cell_unit<T, CVT, CB, SL>(G, cl, ubit, data, s_tab, f - set * set_units, lane, set);
+    if (SL > 0 && nfix > 0 && set != pset) {
+      const uint64_t a0 = cl.base + (uint64_t)set * cl.sstride;  // no unit part
+      for (int k = kf; k < kf + nfix; k++)
+        cell_op<T, CVT, NC, (SL > 0 ? NR : 1)>(P, k == kf, k, cl, a0, s_tab, lane);
+      pset = set;
+    }
+    cell_unit<T, CVT, CB, SL>(G, cl, ubit, data, s_tab, P, f - set * set_units, lane, set);
   }
 }
 
