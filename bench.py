@@ -77,14 +77,24 @@ def run_rows(Q, torch, inst, prec, levels, streams, steps, warmup, autotune=Fals
     plan_s = time.perf_counter() - t0
     ws = net.workspace()
     net.tune_report = None
+    aws = None
+    if angle_batch > 1:
+        # one workspace for the angle batches and for tuning on them
+        need = net.angles_workspace(angle_batch)
+        if autotune:
+            need = max(need, Q.qtn_tune_angles_workspace(net.h, angle_batch))
+        aws = Q.workspace(need)
     if autotune:
         t0 = time.perf_counter()
         net.tune_report = load_tune(net, tune_file)
         if net.tune_report is None:
-            net.tune_report = net.autotune(ws)
+            # tuned on the workload that is timed: angle batches of this size
+            net.tune_report = (net.autotune(aws, n_sets=angle_batch) if angle_batch > 1
+                               else net.autotune(ws))
             if save_tune_file:
                 save_tune(net, save_tune_file, dict(net.tune_report),
                           {"n": n, "edges": len(edges), "precision": prec, "levels": levels,
+                           "angle_sets": angle_batch,
                            "config": {k: v for k, v in cfg.items() if k != "eager"}})
         net.tune_report["seconds"] = time.perf_counter() - t0
     if angle_batch > 1:
@@ -93,7 +103,6 @@ def run_rows(Q, torch, inst, prec, levels, streams, steps, warmup, autotune=Fals
         gs = np.array([a[0] for a in sets])
         bs = np.array([a[1] for a in sets])
         net.angle_sets = (gs, bs)
-        aws = Q.workspace(net.angles_workspace(angle_batch))
         net._aws = aws
         for _ in range(warmup):
             net.contract_angles(gs, bs, aws)

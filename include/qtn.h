@@ -268,6 +268,20 @@ typedef struct qtn_tune_report {
 int qtn_autotune(qtn_network *net, void *d_workspace, size_t bytes,
                  void *hip_stream, qtn_tune_report *report);
 
+/*
+ * The same autotuner with every candidate run over `n_sets` copies of the
+ * network's current angles in one pass (the launches of qtn_contract_angles),
+ * so that each group keeps the kernel that is fastest for angle batches of
+ * that size; the tuned choices then serve single calls and batches alike.
+ * qtn_tune_angles_workspace stores the workspace bytes it needs (the largest
+ * candidate schedule at that set count).
+ * Errors: QTN_EINVAL (n_sets outside 1..1024), QTN_ESTATE, QTN_ENOMEM (host
+ * allocation, or a workspace smaller than needed), QTN_EDEVICE.
+ */
+int qtn_tune_angles_workspace(qtn_network *net, int32_t n_sets, size_t *workspace_bytes_out);
+int qtn_autotune_angles(qtn_network *net, void *d_workspace, size_t bytes,
+                        void *hip_stream, int32_t n_sets, qtn_tune_report *report);
+
 /* One group's timings from the last qtn_autotune: its 16 shape features and
  * the measured time of each QTN_VAR_* (negative: not measured). */
 typedef struct qtn_tune_rec {

@@ -37,7 +37,8 @@ EXPORTS = (
     "qtn_batch_workspace", "qtn_contract_timed", "qtn_get_plan_stats",
     "qtn_angles_workspace", "qtn_contract_angles",
     "qtn_bucket_widths", "qtn_network_free", "qtn_last_error", "qtn_launch_log",
-    "qtn_plan_order", "qtn_autotune", "qtn_tune_log", "qtn_tune_picks", "qtn_set_tune_picks",
+    "qtn_plan_order", "qtn_autotune", "qtn_tune_angles_workspace", "qtn_autotune_angles",
+    "qtn_tune_log", "qtn_tune_picks", "qtn_set_tune_picks",
     "qtn_costmodel_create", "qtn_costmodel_params", "qtn_costmodel_normalization",
     "qtn_costmodel_workspace", "qtn_costmodel_train", "qtn_costmodel_predict",
     "qtn_costmodel_grad", "qtn_costmodel_adam_step", "qtn_apply_costmodel",
@@ -139,6 +140,9 @@ def lib():
         L.qtn_bucket_widths.argtypes = [P, i64, pi32]
         L.qtn_plan_order.argtypes = [P, i64, pi32]
         L.qtn_autotune.argtypes = [P, P, ctypes.c_size_t, P, ctypes.POINTER(qtn_tune_report)]
+        L.qtn_tune_angles_workspace.argtypes = [P, i32, ctypes.POINTER(ctypes.c_size_t)]
+        L.qtn_autotune_angles.argtypes = [P, P, ctypes.c_size_t, P, i32,
+                                          ctypes.POINTER(qtn_tune_report)]
         L.qtn_tune_log.argtypes = [P, i64, ctypes.POINTER(qtn_tune_rec), ctypes.POINTER(i64)]
         L.qtn_angles_workspace.argtypes = [P, i32, ctypes.POINTER(ctypes.c_size_t)]
         L.qtn_contract_angles.argtypes = [P, P, ctypes.c_size_t, P, i32, pd, pd, pd, pd,

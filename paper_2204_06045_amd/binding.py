@@ -22,7 +22,8 @@ __all__ = [
     "qtn_order_minfill", "qtn_plan", "qtn_set_angles", "qtn_contract",
     "qtn_contract_timed", "qtn_contract_batch", "qtn_batch_workspace",
     "qtn_get_plan_stats", "qtn_bucket_widths", "qtn_network_free",
-    "qtn_last_error", "qtn_launch_log", "qtn_plan_order", "qtn_autotune", "qtn_tune_log",
+    "qtn_last_error", "qtn_launch_log", "qtn_plan_order", "qtn_autotune",
+    "qtn_autotune_angles", "qtn_tune_angles_workspace", "qtn_tune_log",
     "qtn_tune_picks", "qtn_set_tune_picks", "qtn_angles_workspace", "qtn_contract_angles",
     "Network", "CostModel", "qtn_apply_costmodel", "workspace", "stream_handle",
 ]
@@ -206,6 +207,24 @@ def qtn_autotune(net, ws, stream=None):
             "picks": list(r.picks[:nc])}
 
 
+def qtn_tune_angles_workspace(net, n_sets):
+    b = ctypes.c_size_t()
+    check(lib().qtn_tune_angles_workspace(net, int(n_sets), ctypes.byref(b)))
+    return b.value
+
+
+def qtn_autotune_angles(net, ws, n_sets, stream=None):
+    """The autotuner with every candidate run over n_sets copies of the
+    network's angles in one pass.  Returns the report as a dict."""
+    r = qtn_tune_report()
+    check(lib().qtn_autotune_angles(net, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                    stream_handle(stream), int(n_sets), ctypes.byref(r)))
+    nc = r.n_candidates
+    return {"n_groups": r.n_groups, "n_candidates": nc,
+            "cand_ms": list(r.cand_ms[:nc]), "tuned_ms": r.tuned_ms,
+            "picks": list(r.picks[:nc]), "n_sets": int(n_sets)}
+
+
 def qtn_angles_workspace(net, n_sets):
     b = ctypes.c_size_t()
     check(lib().qtn_angles_workspace(net, int(n_sets), ctypes.byref(b)))
@@ -314,8 +333,14 @@ class Network:
     def launch_log(self):
         return qtn_launch_log(self.h)
 
-    def autotune(self, ws=None, stream=None):
-        return qtn_autotune(self.h, ws if ws is not None else self.workspace(), stream)
+    def autotune(self, ws=None, stream=None, n_sets=1):
+        """Measure every candidate kernel configuration and keep the fastest
+        per group; n_sets > 1 measures angle batches of that size."""
+        if n_sets == 1:
+            return qtn_autotune(self.h, ws if ws is not None else self.workspace(), stream)
+        if ws is None:
+            ws = workspace(qtn_tune_angles_workspace(self.h, n_sets))
+        return qtn_autotune_angles(self.h, ws, n_sets, stream)
 
     def tune_log(self):
         return qtn_tune_log(self.h)

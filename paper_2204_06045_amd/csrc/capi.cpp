@@ -1541,14 +1541,47 @@ int qtn_contract_batch(qtn_network *const *nets, int32_t n, void *d_workspace, s
   }
 }
 
-int qtn_autotune(qtn_network *net, void *d_workspace, size_t bytes, void *hip_stream,
-                 qtn_tune_report *report) {
+// Workspace of autotuning over n_sets copies of the network's angles: the
+// largest candidate schedule.
+static int tune_workspace_bytes(qtn_network *net, int n_sets, size_t *bytes) {
+  if (n_sets == 1) {
+    *bytes = net->tune_workspace;
+    return QTN_OK;
+  }
+  qtn_network *one[1] = {net};
+  size_t mx = 0;
+  for (const Force &f : tune_candidates()) {
+    Schedule tmp;
+    const int rc = build_schedule(one, 1, &tmp, &f, kTuneSingleWidth, n_sets);
+    if (rc) return rc;
+    mx = std::max(mx, tmp.total);
+  }
+  *bytes = mx;
+  return QTN_OK;
+}
+
+// The autotuner; every candidate runs over n_sets copies of the network's
+// current angles (n_sets 1: one evaluation).
+static int autotune_sets(qtn_network *net, void *d_workspace, size_t bytes, void *hip_stream,
+                         int n_sets, qtn_tune_report *report) {
   try {
     if (!net) return set_err(QTN_EINVAL, "network is NULL");
     if (!net->planned) return set_err(QTN_ESTATE, "qtn_plan has not been called");
-    if (bytes < net->tune_workspace)
-      return set_err(QTN_ENOMEM, "autotuning needs a workspace of " +
-                                     std::to_string(net->tune_workspace) + " bytes");
+    if (n_sets < 1 || n_sets > kMaxAngleSets)
+      return set_err(QTN_EINVAL, "n_sets must be in 1.." + std::to_string(kMaxAngleSets));
+    size_t need = 0;
+    int wrc = tune_workspace_bytes(net, n_sets, &need);
+    if (wrc) return wrc;
+    if (bytes < need)
+      return set_err(QTN_ENOMEM, "autotuning needs a workspace of " + std::to_string(need) +
+                                     " bytes");
+    // the angles of every set: the network's current ones
+    std::vector<double> set_angles;
+    if (n_sets > 1)
+      for (int k = 0; k < n_sets; k++) {
+        set_angles.insert(set_angles.end(), net->gamma.begin(), net->gamma.end());
+        set_angles.insert(set_angles.end(), net->beta.begin(), net->beta.end());
+      }
     const auto &cands = tune_candidates();
     const int nc = (int)cands.size();
     qtn_network *one[1] = {net};
@@ -1568,7 +1601,7 @@ int qtn_autotune(qtn_network *net, void *d_workspace, size_t bytes, void *hip_st
     constexpr int kPasses = 2;
     for (int pass = 0; pass < kPasses; pass++)
       for (int ci = 0; ci < nc; ci++) {
-        int rc = build_schedule(one, 1, &ex.sched, &cands[ci], kTuneSingleWidth);
+        int rc = build_schedule(one, 1, &ex.sched, &cands[ci], kTuneSingleWidth, n_sets);
         if (rc) {
           give_back();
           return rc;
@@ -1577,7 +1610,8 @@ int qtn_autotune(qtn_network *net, void *d_workspace, size_t bytes, void *hip_st
         Timer tm;
         tm.on = true;
         std::vector<double> res;
-        rc = run_exec(ex, {net}, d_workspace, bytes, hip_stream, 1, true, tm, res);
+        rc = run_exec(ex, {net}, d_workspace, bytes, hip_stream, 1, true, tm, res,
+                      n_sets > 1 ? set_angles.data() : nullptr);
         if (rc) {
           give_back();
           return rc;
@@ -1598,7 +1632,7 @@ int qtn_autotune(qtn_network *net, void *d_workspace, size_t bytes, void *hip_st
               s.prec, ws + s.off_data, (const DevGroup *)(ws + s.off_groups),
               (const DevOp *)(ws + s.off_ops), (const int32_t *)(ws + s.off_stab),
               (const uint8_t *)(ws + s.off_uperm), (const int2 *)(ws + s.off_ranges),
-              s.singles_range0 + (int)i, 1, 1, ex.rt.main, tb.t0(), tb.t1());
+              s.singles_range0 + (int)i, 1, n_sets, ex.rt.main, tb.t0(), tb.t1());
           if (he == hipSuccess) rc = tb.end(ex.rt.main, true);
           if (he != hipSuccess || rc) {
             give_back();
@@ -1792,6 +1826,28 @@ int qtn_set_tune_picks(qtn_network *net, const qtn_tune_pick *picks, int64_t n) 
   } catch (const std::bad_alloc &) {
     return set_err(QTN_ENOMEM, "host allocation failed");
   }
+}
+
+int qtn_autotune(qtn_network *net, void *d_workspace, size_t bytes, void *hip_stream,
+                 qtn_tune_report *report) {
+  return autotune_sets(net, d_workspace, bytes, hip_stream, 1, report);
+}
+
+int qtn_tune_angles_workspace(qtn_network *net, int32_t n_sets, size_t *bytes_out) {
+  try {
+    if (!net || !bytes_out) return set_err(QTN_EINVAL, "NULL argument");
+    if (!net->planned) return set_err(QTN_ESTATE, "qtn_plan has not been called");
+    if (n_sets < 1 || n_sets > kMaxAngleSets)
+      return set_err(QTN_EINVAL, "n_sets must be in 1.." + std::to_string(kMaxAngleSets));
+    return tune_workspace_bytes(net, n_sets, bytes_out);
+  } catch (const std::bad_alloc &) {
+    return set_err(QTN_ENOMEM, "host allocation failed");
+  }
+}
+
+int qtn_autotune_angles(qtn_network *net, void *d_workspace, size_t bytes, void *hip_stream,
+                        int32_t n_sets, qtn_tune_report *report) {
+  return autotune_sets(net, d_workspace, bytes, hip_stream, n_sets, report);
 }
 
 int qtn_tune_log(const qtn_network *net, int64_t cap, qtn_tune_rec *out, int64_t *n_out) {

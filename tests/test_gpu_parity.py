@@ -258,6 +258,32 @@ def test_autotune_keeps_parity(qtn, orc, gpu, prec):
     net.close()
 
 
+def test_autotune_on_angle_batches_keeps_parity(qtn, orc, gpu):
+    """Tuning on angle batches: every candidate runs over 4 copies of the
+    angles; the tuned plan matches the oracle for single calls and batches."""
+    inst = qs.instance(20, 3, 3, 6, 3)
+    e = inst["edges"]
+    gs = np.array([a[0] for a in inst["angles"]])
+    bs = np.array([a[1] for a in inst["angles"]])
+    net = qtn.Network(20, e, gs[0], bs[0], small_width=8)
+    net.plan(0)
+    need = qtn.qtn_tune_angles_workspace(net.h, 4)
+    assert need >= net.angles_workspace(4) > 0
+    with pytest.raises(qtn.QtnError):
+        qtn.qtn_autotune_angles(net.h, qtn.workspace(need // 2), 4)
+    rep = net.autotune(n_sets=4)
+    assert rep["n_candidates"] == 7 and rep["n_groups"] > 0 and rep["n_sets"] == 4
+    assert rep["tuned_ms"] <= min(rep["cand_ms"][:4]) * (1 + 1e-9)
+    zz, en = net.contract_angles(gs, bs)
+    for k in range(3):
+        ref, ref_en = orc.energy(20, e, gs[k], bs[k], threads=8)
+        _check(zz[k], None, en[k], ref, ref_en, 0, f"batch-tuned set {k}")
+        net.set_angles(gs[k], bs[k])
+        z1, _, e1 = net.contract()
+        assert np.array_equal(z1, zz[k]) and e1 == en[k]
+    net.close()
+
+
 @pytest.mark.parametrize("n,p", [(16, 3), (20, 3)])
 def test_mixed_precision(qtn, orc, gpu, n, p):
     """Mixed: groups of union width >= mixed_width in complex64, the rest (and
