@@ -62,11 +62,16 @@ typedef struct qtn_config {
     int32_t eager;       /* 1: launch eagerly instead of replaying a
                             captured HIP graph [0]                          */
     int32_t lane_sum_bits; /* streaming kernel: summed indices spread over
-                            lanes, the rest walked serially per lane [2]  */
-    int32_t variant;     /* 0 auto, 1 generic kernel only, 2 streaming
-                            kernel wherever it applies, 3 matrix form for
-                            every complex64 group that has one (others as
-                            auto) [0]                                       */
+                            lanes, the rest walked serially per lane [2];
+                            with variant 4, the cell mapping's cell bits
+                            (2..4, else 3)                                 */
+    int32_t variant;     /* 0 auto (the cell mapping for own-launch groups
+                            it fits in the per-group launch executors,
+                            else streaming or generic), 1 generic kernel
+                            only, 2 streaming kernel wherever it applies,
+                            3 matrix form for every complex64 group that
+                            has one (others as auto), 4 cell mapping
+                            wherever it applies [0]                         */
     int32_t order_trials; /* >1: plan with the cheapest (sum of 2^width) of
                             the greedy min-fill order and order_trials-1
                             min-fill orders with random tie-breaks [0]     */
@@ -238,7 +243,10 @@ int qtn_launch_log(const qtn_network *net, int64_t cap, qtn_launch_rec *out,
 
 /* Kernel variants a group can run with (cost-model outputs). */
 #define QTN_VAR_BLOCK 0   /* inside one workgroup, many groups per launch  */
-#define QTN_VAR_STREAM 1  /* own launch, streaming mapping (LDS lane
+#define QTN_VAR_STREAM 1  /* own launch, streaming family: the cell mapping
+                             (lanes on the low union bits, register
+                             cells, LDS offset tables, reduce-scatter) or
+                             the lane-sum streaming mapping (LDS lane
                              tables, serial walk, butterflies)           */
 #define QTN_VAR_GENERIC 2 /* own launch, generic register/lane mapping   */
 #define QTN_VAR_MFMA 3    /* matrix form on the matrix cores (complex64
@@ -257,7 +265,8 @@ typedef struct qtn_tune_report {
 /*
  * Autotuner.  Runs the planned evaluation once per candidate configuration
  * (generic mapping; streaming mapping with 1, 2 or 3 lane-summed bits; matrix
- * form, which only complex64 groups that have one take part in), each group in
+ * form, which only complex64 groups that have one take part in; cell mapping
+ * with 3 or 4 cell bits, for the groups wide enough for it), each group in
  * its own launch on one stream and, for groups up to width 16, again alone
  * inside one workgroup, timing every launch with HIP events.  Each group then
  * keeps its fastest configuration for where it runs, and the plan's schedule
@@ -300,8 +309,11 @@ typedef struct qtn_tune_pick {
     int32_t edge;     /* light cone */
     int32_t group;    /* group index inside the light cone's plan */
     int8_t place;     /* 0 inside a workgroup segment, 1 own launch, -1 rule */
-    int8_t variant;   /* 1 generic, 2 streaming, 3 matrix form, -1 rule */
-    int8_t rls;       /* streaming: lane-summed bits, -1 rule */
+    int8_t variant;   /* 1 generic, 2 streaming, 3 matrix form, 4 cells,
+                         -1 rule (a mapping that does not fit the group
+                         falls back to the rule) */
+    int8_t rls;       /* streaming: lane-summed bits; cells: cell bits;
+                         -1 rule */
     int8_t pad;
     uint32_t shape;
 } qtn_tune_pick;
@@ -363,8 +375,10 @@ int qtn_costmodel_adam_step(qtn_costmodel *cm, const float *grad, float lr,
 
 /* Picks, for every group of a planned network that the width rule gives its
  * own launch, the kernel with the lowest predicted time (the matrix form only
- * for complex64 groups that have one) and rebuilds the schedule; groups the
- * rule places inside a workgroup stay there (counted as QTN_VAR_BLOCK).
+ * for complex64 groups that have one; QTN_VAR_STREAM runs as the cell mapping
+ * where it fits, else the lane-sum streaming mapping) and rebuilds the
+ * schedule; groups the rule places inside a workgroup stay there (counted as
+ * QTN_VAR_BLOCK).
  * counts_out [4] or NULL: groups per QTN_VAR_*.  Workspace: the
  * cost-model bytes for as many samples as the network has groups. */
 int qtn_apply_costmodel(qtn_network *net, const qtn_costmodel *cm,

@@ -150,6 +150,25 @@ def test_cell_mapping_scheduling_rules(qtn):
     assert cells(small_width=32)[0] == 0
 
 
+def test_tune_angles_workspace_query(qtn):
+    """Workspace of autotuning on angle batches: grows with the set count, at
+    least the angle-batch workspace; bad set counts and unplanned networks
+    are refused."""
+    inst = qs.instance(20, 3, 3, 6)
+    g, b = inst["angles"][0]
+    net = qtn.Network(20, inst["edges"], g, b)
+    with pytest.raises(qtn.QtnError):
+        qtn.qtn_tune_angles_workspace(net.h, 4)
+    net.plan(0)
+    one = qtn.qtn_tune_angles_workspace(net.h, 1)
+    four = qtn.qtn_tune_angles_workspace(net.h, 4)
+    assert four >= net.angles_workspace(4) > one > 0
+    for bad in (0, 1025):
+        with pytest.raises(qtn.QtnError):
+            qtn.qtn_tune_angles_workspace(net.h, bad)
+    net.close()
+
+
 @pytest.mark.parametrize("edges,msg", [
     ([(0, 0)], "self-loop"),
     ([(0, 1), (1, 0)], "repeated"),
