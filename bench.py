@@ -214,6 +214,45 @@ def roofline_of(log, workload_tag):
             "frac": fp_frac, **common}
 
 
+WIDTH_CLASSES = ((0, 12), (13, 17), (18, 23), (24, 64))
+
+
+def launch_breakdown(log):
+    """Algorithmic GB/s of one timed evaluation per union-width class of the
+    launches (a workgroup launch counts under its first group), the groups
+    per second of the workgroup launches (the small buckets), and, for the
+    matrix-form launches, the three real products' flops (3M: 3 * 2 * 2^w
+    per group) against the FP32 matrix peak."""
+    cls = {}
+    for lo, hi in WIDTH_CLASSES:
+        rs = [r for r in log if lo <= r["w"] <= hi]
+        ms = sum(r["ms"] for r in rs)
+        by = sum(r["bytes"] for r in rs)
+        cls[f"w{lo}-{hi}"] = {"launches": len(rs), "ms": ms,
+                              "gbs": by / ms / 1e6 if ms > 0 else 0.0}
+    blk = [r for r in log if r["kind"] == 1]
+    blk_ms = sum(r["ms"] for r in blk)
+    mm = [r for r in log if r["kind"] == 2 and r["variant"] == 2]
+    mm_ms = sum(r["ms"] for r in mm)
+    mm_flops = sum(6.0 * 2.0 ** r["w"] for r in mm)
+    return {"width_classes": cls,
+            "small_groups_per_s": (sum(r["n_groups"] for r in blk) / blk_ms * 1e3
+                                   if blk_ms > 0 else 0.0),
+            "matrix_form": ({"launches": len(mm), "ms": mm_ms,
+                             "tflops_3m": mm_flops / mm_ms / 1e9,
+                             "frac_fp32_matrix_peak": mm_flops / mm_ms / 1e9 / FP32_PEAK_TFLOPS}
+                            if mm_ms > 0 else None)}
+
+
+def host_facts():
+    """Logical CPUs and RAM of the host the oracle runs on."""
+    try:
+        ram = os.sysconf("SC_PAGE_SIZE") * os.sysconf("SC_PHYS_PAGES")
+    except (ValueError, OSError, AttributeError):
+        ram = None
+    return {"logical_cpus": os.cpu_count(), "ram_bytes": ram}
+
+
 def cpu_baseline(inst, seconds):
     """FP64 oracle on a bounded sample of light cones, scaled by cost."""
     import oracle
@@ -247,6 +286,7 @@ def cpu_baseline(inst, seconds):
     wall = time.perf_counter() - t0
     frac = acc / total
     return {"value": frac / wall, "unit": "evals/s", "cores": threads, "kind": "oracle",
+            "value_1core": rate / total, "host": host_facts(),
             "sample": (f"{len(sample)} of {m} light cones ({100 * frac:.2f}% of the "
                        f"evaluation's sum of 2^width) on {threads} threads in "
                        f"{wall:.1f} s, scaled to one full evaluation by that cost share")}
@@ -269,9 +309,10 @@ def run_batch(Q, torch, steps, warmup, executor=0, autotune=False, order_trials=
     plan_s = time.perf_counter() - t0
     tune_s = 0.0
     if autotune:
-        # tune the 16 networks with the most algorithmic bytes
+        # tune the 8 networks with the most algorithmic bytes (they carry most
+        # of the batch's work; tuning all 64 would take minutes)
         t0 = time.perf_counter()
-        heavy = sorted(nets, key=lambda n: -n.stats()["bytes"])[:16]
+        heavy = sorted(nets, key=lambda n: -n.stats()["bytes"])[:8]
         for net in heavy:
             net.autotune()
         tune_s = time.perf_counter() - t0
@@ -303,6 +344,41 @@ def run_batch(Q, torch, steps, warmup, executor=0, autotune=False, order_trials=
     return row
 
 
+def run_seeds(Q, torch, seeds=(0, 1, 2, 3, 4), angle_batch=32, steps=6, order_trials=64):
+    """The metric's shape on graph seeds 0-4 (the algorithmic bytes vary from
+    graph to graph): per seed, the width of the widest bucket of each light
+    cone (max and median), the evaluation's algorithmic bytes, and evals/s of
+    32-set batches under the width rule (no tuning)."""
+    import numpy as np
+    import qaoa_synth as qs
+    rows = {}
+    for seed in seeds:
+        inst = qs.instance(30, 3, 4, seed, angle_batch)
+        g0, b0 = inst["angles"][0]
+        net = Q.Network(30, inst["edges"], g0, b0, order_trials=order_trials)
+        net.plan(Q.QTN_C128)
+        widths = [max(net.bucket_widths(e)) for e in range(len(inst["edges"]))]
+        gs = np.array([a[0] for a in inst["angles"]])
+        bs = np.array([a[1] for a in inst["angles"]])
+        aws = Q.workspace(net.angles_workspace(angle_batch))
+        for _ in range(2):
+            net.contract_angles(gs, bs, aws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            net.contract_angles(gs, bs, aws)
+        torch.cuda.synchronize()
+        st = net.stats()
+        rows[f"seed{seed}"] = {"evals_per_s": steps * angle_batch / (time.perf_counter() - t0),
+                               "width_max": int(max(widths)),
+                               "width_median": float(np.median(widths)),
+                               "alg_bytes_per_eval": st["bytes"]}
+        del aws
+        net.close()
+        torch.cuda.empty_cache()
+    return rows
+
+
 def run_cfg4(Q, torch, steps=10, autotune=True):
     """4-regular N=40, p=3 (80 light cones): complex128, complex64 and mixed
     precision (groups of width >= 18 in complex64, in matrix form on the
@@ -330,7 +406,10 @@ def run_cfg4(Q, torch, steps=10, autotune=True):
         dt = (time.perf_counter() - t0) / steps
         err = np.abs(zz - ref)
         st = net.stats()
+        net.contract_timed(ws)
+        mf = launch_breakdown(net.launch_log())["matrix_form"]
         rows[name] = {"evals_per_s": 1.0 / dt, "edge_err_max": float(err.max()),
+                      "matrix_form": mf,
                       "edge_err_median": float(np.median(err)),
                       "energy_rel_err": abs(en - gd["energy"]) / abs(gd["energy"]),
                       "alg_bytes_per_eval": st["bytes"], "matrix_groups": st["n_matrix"],
@@ -486,7 +565,9 @@ def main():
         net.contract_timed()
         _, _, timing = net.contract_timed()
     tag = f"n30p4_{args.precision}" + (f"_x{args.angle_batch}" if args.angle_batch > 1 else "")
-    roof = roofline_of(net.launch_log(), tag)
+    main_log = net.launch_log()
+    roof = roofline_of(main_log, tag)
+    breakdown = launch_breakdown(main_log)
     # the same plan, one qtn_contract call per angle set
     sequential = None
     if args.angle_batch > 1 and args.variants:
@@ -544,6 +625,9 @@ def main():
         log("variant costmodel (learned selector vs width rule, held-out graphs)")
         variants["costmodel_c64"] = run_costmodel(Q, torch)
         torch.cuda.empty_cache()
+        log("variant seeds (graph seeds 0-4, width rule, 32-set batches)")
+        variants["seeds_c128"] = run_seeds(Q, torch)
+        torch.cuda.empty_cache()
         log("variant batch64_c64 (persistent)")
         variants["batch64_c64"] = run_batch(Q, torch, 5, 1, executor=0,
                                             autotune=bool(args.autotune))
@@ -583,6 +667,8 @@ def main():
         "alg_bytes_per_eval": stats["bytes"],
         "alg_flops_per_eval": stats["flops"],
         "eval_hbm_gbs": stats["bytes"] * evals / 1e9,
+        "paper_gflops_per_s": stats["paper_flops"] * evals / 1e9,
+        "launch_breakdown": breakdown,
         "plan_seconds": plan_s,
         "autotune": tune,
         "roofline": roof,
