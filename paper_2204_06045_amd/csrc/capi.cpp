@@ -361,7 +361,8 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S, const Force *fo
           const Tensor &t = pl.tensors[o.tensor];
           in_bytes += std::ldexp(1.0, (int)t.vars.size()) * es(t.gate >= 0 ? G.prec : t.prec);
         }
-        // streaming mapping unless the group is too large for its LDS tables
+        // the mapping requested (network config, tuned pick or a tuning
+        // candidate); 0 leaves it to the rule below
         int var_req = net->variant, rls_req = net->lane_sum_bits;
         if (G.pick_variant > 0) {
           var_req = G.pick_variant;
