@@ -379,6 +379,34 @@ def run_seeds(Q, torch, seeds=(0, 1, 2, 3, 4), angle_batch=32, steps=6, order_tr
     return rows
 
 
+def run_gradient(Q, torch, inst, iters=12, lr=0.02, h=1e-4, order_trials=64):
+    """Parameter search on the metric's graph (Sec. II-A): gradient ascent on
+    E(gamma, beta) with the gradient from one batched pass over 4p + 1 angle
+    sets (qtn_energy_gradient), width rule, no tuning.  Reports gradients per
+    second and the energy before and after."""
+    import numpy as np
+    g, b = (np.array(x, dtype=np.float64) for x in inst["angles"][0])
+    net = Q.Network(inst["n"], inst["edges"], g, b, order_trials=order_trials)
+    net.plan(Q.QTN_C128)
+    e0, dg, db = net.energy_gradient(g, b, step=h)  # warm-up (workspace, plan upload)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e = e0
+    for _ in range(iters):
+        e, dg, db = net.energy_gradient(g, b, step=h)
+        g = g + lr * dg
+        b = b + lr * db
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    e_end, _, _ = net.energy_gradient(g, b, step=h)
+    p = len(g)
+    net.close()
+    torch.cuda.empty_cache()
+    return {"gradients_per_s": iters / dt, "energies_per_gradient": 4 * p + 1,
+            "evals_per_s": iters * (4 * p + 1) / dt, "ascent_steps": iters,
+            "learning_rate": lr, "step_h": h, "energy_start": e0, "energy_end": e_end}
+
+
 def run_cfg4(Q, torch, steps=10, autotune=True):
     """4-regular N=40, p=3 (80 light cones): complex128, complex64 and mixed
     precision (groups of width >= 18 in complex64, in matrix form on the
@@ -624,6 +652,9 @@ def main():
         torch.cuda.empty_cache()
         log("variant costmodel (learned selector vs width rule, held-out graphs)")
         variants["costmodel_c64"] = run_costmodel(Q, torch)
+        torch.cuda.empty_cache()
+        log("variant gradient (gradient ascent, 4p + 1 angle sets per gradient)")
+        variants["gradient_c128"] = run_gradient(Q, torch, inst)
         torch.cuda.empty_cache()
         log("variant seeds (graph seeds 0-4, width rule, 32-set batches)")
         variants["seeds_c128"] = run_seeds(Q, torch)

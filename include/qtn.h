@@ -216,6 +216,27 @@ int qtn_contract_angles(qtn_network *net, void *d_workspace, size_t bytes,
                         const double *beta, double *zz_out, double *energy_out,
                         qtn_timing *timing_out);
 
+/*
+ * Energy and its gradient in (gamma, beta) for a parameter search (Sec. II-A:
+ * the energy is maximised over the angles): central differences
+ * dE/dgamma_l = (E(gamma_l + h) - E(gamma_l - h)) / 2h, the same for beta_l,
+ * with the 4p + 1 angle sets (the given angles and each shifted one) evaluated
+ * in one qtn_contract_angles pass on the network's plan.  The network's own
+ * angles (qtn_set_angles) are not changed.
+ *   gamma, beta     [p] radians (host)
+ *   step            h > 0; the truncation error is O(h^2), the rounding error
+ *                   O(eps |E| / h) (about 1e-4 .. 1e-3 in complex128)
+ *   energy_out      E at the given angles
+ *   grad_*_out      [p] (host)
+ * qtn_gradient_workspace stores the workspace bytes (that of 4p + 1 sets).
+ * Errors: as qtn_contract_angles; QTN_EINVAL also for a bad step.
+ */
+int qtn_gradient_workspace(qtn_network *net, size_t *workspace_bytes_out);
+int qtn_energy_gradient(qtn_network *net, void *d_workspace, size_t bytes,
+                        void *hip_stream, const double *gamma, const double *beta,
+                        double step, double *energy_out, double *grad_gamma_out,
+                        double *grad_beta_out);
+
 /* One launch of the last qtn_contract_timed call on this network. */
 typedef struct qtn_launch_rec {
     int32_t kind;      /* QTN_K_* class                                   */

@@ -35,7 +35,8 @@ EXPORTS = (
     "qtn_network_build", "qtn_network_info", "qtn_order_minfill", "qtn_plan",
     "qtn_set_angles", "qtn_contract", "qtn_contract_batch",
     "qtn_batch_workspace", "qtn_contract_timed", "qtn_get_plan_stats",
-    "qtn_angles_workspace", "qtn_contract_angles",
+    "qtn_angles_workspace", "qtn_contract_angles", "qtn_gradient_workspace",
+    "qtn_energy_gradient",
     "qtn_bucket_widths", "qtn_network_free", "qtn_last_error", "qtn_launch_log",
     "qtn_plan_order", "qtn_autotune", "qtn_tune_angles_workspace", "qtn_autotune_angles",
     "qtn_tune_log", "qtn_tune_picks", "qtn_set_tune_picks",
@@ -145,6 +146,9 @@ def lib():
                                           ctypes.POINTER(qtn_tune_report)]
         L.qtn_tune_log.argtypes = [P, i64, ctypes.POINTER(qtn_tune_rec), ctypes.POINTER(i64)]
         L.qtn_angles_workspace.argtypes = [P, i32, ctypes.POINTER(ctypes.c_size_t)]
+        L.qtn_gradient_workspace.argtypes = [P, ctypes.POINTER(ctypes.c_size_t)]
+        L.qtn_energy_gradient.argtypes = [P, P, ctypes.c_size_t, P, pd, pd, ctypes.c_double,
+                                          pd, pd, pd]
         L.qtn_contract_angles.argtypes = [P, P, ctypes.c_size_t, P, i32, pd, pd, pd, pd,
                                           ctypes.POINTER(qtn_timing)]
         L.qtn_tune_picks.argtypes = [P, i64, ctypes.POINTER(qtn_tune_pick), ctypes.POINTER(i64)]

@@ -25,6 +25,7 @@ __all__ = [
     "qtn_last_error", "qtn_launch_log", "qtn_plan_order", "qtn_autotune",
     "qtn_autotune_angles", "qtn_tune_angles_workspace", "qtn_tune_log",
     "qtn_tune_picks", "qtn_set_tune_picks", "qtn_angles_workspace", "qtn_contract_angles",
+    "qtn_gradient_workspace", "qtn_energy_gradient",
     "Network", "CostModel", "qtn_apply_costmodel", "workspace", "stream_handle",
 ]
 
@@ -231,6 +232,31 @@ def qtn_angles_workspace(net, n_sets):
     return b.value
 
 
+def qtn_gradient_workspace(net):
+    b = ctypes.c_size_t()
+    check(lib().qtn_gradient_workspace(net, ctypes.byref(b)))
+    return b.value
+
+
+def qtn_energy_gradient(net, p, gamma, beta, ws, step, stream=None):
+    """Energy and its central-difference gradient in gamma and beta (one
+    batched pass over 4p + 1 angle sets).  Returns (E, dE/dgamma, dE/dbeta)."""
+    import numpy as np
+    g = np.ascontiguousarray(gamma, dtype=np.float64)
+    b = np.ascontiguousarray(beta, dtype=np.float64)
+    if g.shape != (p,) or b.shape != (p,):
+        raise ValueError(f"gamma and beta must have shape ({p},)")
+    e = ctypes.c_double()
+    dg = np.empty(p, dtype=np.float64)
+    db = np.empty(p, dtype=np.float64)
+    pd = ctypes.POINTER(ctypes.c_double)
+    check(lib().qtn_energy_gradient(net, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                    stream_handle(stream), g.ctypes.data_as(pd),
+                                    b.ctypes.data_as(pd), float(step), ctypes.byref(e),
+                                    dg.ctypes.data_as(pd), db.ctypes.data_as(pd)))
+    return e.value, dg, db
+
+
 def _timing_dict(t):
     return {name: {"ms": t.ms[k], "launches": int(t.launches[k]),
                    "bytes": t.bytes[k], "flops": t.flops[k]}
@@ -357,6 +383,17 @@ class Network:
                 self._aws = workspace(need)
             ws = self._aws
         return qtn_contract_angles(self.h, self.m, gammas, betas, ws, stream, timed)
+
+    def energy_gradient(self, gamma, beta, step=1e-4, ws=None, stream=None):
+        """Energy at (gamma, beta) and its gradient, by central differences
+        evaluated in one angle-batched pass."""
+        if ws is None:
+            need = qtn_gradient_workspace(self.h)
+            if self._aws is None or self._aws.numel() < need:
+                self._aws = None
+                self._aws = workspace(need)
+            ws = self._aws
+        return qtn_energy_gradient(self.h, self.p, gamma, beta, ws, step, stream)
 
     def tune_picks(self):
         return qtn_tune_picks(self.h)

@@ -1834,6 +1834,47 @@ int qtn_autotune(qtn_network *net, void *d_workspace, size_t bytes, void *hip_st
   return autotune_sets(net, d_workspace, bytes, hip_stream, 1, report);
 }
 
+int qtn_gradient_workspace(qtn_network *net, size_t *workspace_bytes_out) {
+  if (!net) return set_err(QTN_EINVAL, "NULL argument");
+  return qtn_angles_workspace(net, 4 * net->p + 1, workspace_bytes_out);
+}
+
+int qtn_energy_gradient(qtn_network *net, void *d_workspace, size_t bytes, void *hip_stream,
+                        const double *gamma, const double *beta, double step, double *energy_out,
+                        double *grad_gamma_out, double *grad_beta_out) {
+  try {
+    if (!net || !gamma || !beta || !energy_out || !grad_gamma_out || !grad_beta_out)
+      return set_err(QTN_EINVAL, "NULL argument");
+    if (!(step > 0.0) || !std::isfinite(step))
+      return set_err(QTN_EINVAL, "step must be positive and finite");
+    const int p = net->p, n = 4 * p + 1;
+    // set 0: the angles; then gamma_l + h, gamma_l - h for every l, then the
+    // same for beta_l
+    std::vector<double> g((size_t)n * p), b((size_t)n * p), e(n);
+    for (int k = 0; k < n; k++) {
+      std::copy(gamma, gamma + p, g.begin() + (size_t)k * p);
+      std::copy(beta, beta + p, b.begin() + (size_t)k * p);
+    }
+    for (int l = 0; l < p; l++) {
+      g[(size_t)(1 + 2 * l) * p + l] += step;
+      g[(size_t)(2 + 2 * l) * p + l] -= step;
+      b[(size_t)(1 + 2 * p + 2 * l) * p + l] += step;
+      b[(size_t)(2 + 2 * p + 2 * l) * p + l] -= step;
+    }
+    const int rc = qtn_contract_angles(net, d_workspace, bytes, hip_stream, n, g.data(), b.data(),
+                                       nullptr, e.data(), nullptr);
+    if (rc) return rc;
+    *energy_out = e[0];
+    for (int l = 0; l < p; l++) {
+      grad_gamma_out[l] = (e[1 + 2 * l] - e[2 + 2 * l]) / (2.0 * step);
+      grad_beta_out[l] = (e[1 + 2 * p + 2 * l] - e[2 + 2 * p + 2 * l]) / (2.0 * step);
+    }
+    return QTN_OK;
+  } catch (const std::bad_alloc &) {
+    return set_err(QTN_ENOMEM, "host allocation failed");
+  }
+}
+
 int qtn_tune_angles_workspace(qtn_network *net, int32_t n_sets, size_t *bytes_out) {
   try {
     if (!net || !bytes_out) return set_err(QTN_EINVAL, "NULL argument");

@@ -169,6 +169,21 @@ def test_tune_angles_workspace_query(qtn):
     net.close()
 
 
+def test_gradient_workspace_and_validation(qtn):
+    """The gradient's workspace is that of 4p + 1 angle sets; argument errors
+    are reported before any device work."""
+    inst = qs.instance(12, 3, 2, 1)
+    g, b = inst["angles"][0]
+    net = qtn.Network(12, inst["edges"], g, b)
+    with pytest.raises(qtn.QtnError):
+        qtn.qtn_gradient_workspace(net.h)  # not planned
+    net.plan(0)
+    assert qtn.qtn_gradient_workspace(net.h) == net.angles_workspace(4 * 2 + 1)
+    with pytest.raises(ValueError):
+        qtn.qtn_energy_gradient(net.h, 2, [0.1], [0.2, 0.3], None, 1e-4)
+    net.close()
+
+
 @pytest.mark.parametrize("edges,msg", [
     ([(0, 0)], "self-loop"),
     ([(0, 1), (1, 0)], "repeated"),

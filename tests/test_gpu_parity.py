@@ -100,6 +100,52 @@ def test_repeat_and_new_angles_replay(qtn, orc, gpu):
     net.close()
 
 
+def test_energy_gradient_closed_form_p1(qtn, gpu):
+    """p=1 on the Petersen graph (3-regular, triangle-free): e_uv =
+    -sin(4b) sin(g) cos(g)^2 for every edge, so E = 15/2 + (15/2) sin(4b)
+    sin(g) cos(g)^2 and its derivatives are known in closed form.  The
+    central differences of one batched pass match them to the truncation
+    error."""
+    e = qs.petersen_graph()
+    rng = np.random.default_rng(3)
+    net = qtn.Network(10, e, [0.3], [0.2])
+    net.plan(0)
+    for _ in range(4):
+        g, b = rng.uniform(0, math.pi), rng.uniform(0, math.pi / 2)
+        en, dg, db = net.energy_gradient([g], [b], step=1e-5)
+        c, s_, s4, c4 = math.cos(g), math.sin(g), math.sin(4 * b), math.cos(4 * b)
+        assert abs(en - (7.5 + 7.5 * s4 * s_ * c * c)) < 1e-12
+        assert abs(dg[0] - 7.5 * s4 * c * (c * c - 2 * s_ * s_)) < 1e-7
+        assert abs(db[0] - 30.0 * c4 * s_ * c * c) < 1e-7
+    with pytest.raises(qtn.QtnError):
+        net.energy_gradient([0.3], [0.2], step=0.0)
+    net.close()
+
+
+def test_energy_gradient_matches_oracle_differences(qtn, orc, gpu):
+    """p=3: the GPU gradient equals the same central differences of the FP64
+    oracle's energies at the shifted angles."""
+    inst = qs.instance(14, 3, 3, 8)
+    e = inst["edges"]
+    g, b = (np.asarray(x) for x in inst["angles"][0])
+    net = qtn.Network(14, e, g, b, small_width=4)
+    net.plan(0)
+    h = 1e-4
+    en, dg, db = net.energy_gradient(g, b, step=h)
+    _, ref_en = orc.energy(14, e, g, b, threads=8)
+    assert abs(en - ref_en) <= 1e-10 * abs(ref_en)
+    for l in range(3):
+        for which, grad in ((0, dg), (1, db)):
+            up = [g.copy(), b.copy()]
+            dn = [g.copy(), b.copy()]
+            up[which][l] += h
+            dn[which][l] -= h
+            _, eu = orc.energy(14, e, up[0], up[1], threads=8)
+            _, ed = orc.energy(14, e, dn[0], dn[1], threads=8)
+            assert abs(grad[l] - (eu - ed) / (2 * h)) < 1e-6, (which, l)
+    net.close()
+
+
 def test_edge_cases(qtn, orc, gpu):
     cases = [
         (2, [(0, 1)], 1), (2, [(0, 1)], 3),                      # single edge
