@@ -589,6 +589,15 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S, const Force *fo
               for (size_t i = last0; i < order.size(); i++)
                 nfix += (G.ops[order[i]].mask & unit_mask) == 0 ? 1 : 0;
               dg.n_step0 = (uint8_t)nfix;
+            } else {
+              // without serial bits, the operands holding only lane bits go
+              // first: their product, one value per lane, is formed once per
+              // angle set and multiplies the cells once per unit
+              std::stable_partition(order.begin(), order.end(),
+                                    [&](int k) { return (G.ops[k].mask & ~63u) == 0; });
+              int nfix = 0;
+              for (int k : order) nfix += (G.ops[k].mask & ~63u) == 0 ? 1 : 0;
+              dg.n_step0 = (uint8_t)nfix;
             }
             // the cell mapping forms an operand's unit offset from its runs
             // over the unit bits; past kCellURuns of them, ascending order

@@ -69,8 +69,8 @@ enum Variant : uint8_t { kVarGeneric = 0, kVarStream = 1, kVarMfma = 2, kVarCell
 // kept bits at union positions uperm[0..CB - sl) (the unit bits follow in
 // uperm).  Ops [0, n_step) hold bit 6 (all ops when sl = 0), the next
 // n_serial hold bit 7 but not 6 (sl = 2), the rest no serial bit; the first
-// n_step0 ops of the last of these levels hold no unit bit; n_unit = the most
-// unit-bit runs of any operand.  Each op's stab entry starts its table: 2^CB cell offsets
+// n_step0 ops of the last of these levels hold no unit bit (sl = 0: hold lane
+// bits only); n_unit = the most unit-bit runs of any operand.  Each op's stab entry starts its table: 2^CB cell offsets
 // (elements), kCellURuns / 2 words of unit-bit runs (src | len << 5 | dst <<
 // 11, two per word, src counting unit bits; unused runs 0) giving the unit
 // part of its index, then the mask of the cell bits its index holds.

@@ -659,9 +659,20 @@ __device__ __forceinline__ void cell_unit(const GI &G, const CellLane &cl,
   }
   const uint64_t addr = cl.base + (uint64_t)set * cl.sstride + (uint64_t)ub * cl.es;
   T acc[NC];
-  // operands holding bit 6 (every operand when no bit is serial) in all cells
-  int k = 0;
-  for (; k < n_step; k++) cell_op<T, CVT, NC, NC>(acc, k == 0, k, cl, addr, s_tab, lane);
+  // operands holding bit 6 (every operand when no bit is serial) in all
+  // cells; without serial bits, the first nfix (lane bits only) are the
+  // product P[0] applied last
+  int k = SL == 0 ? nfix : 0;
+  for (const int k0 = k; k < n_step; k++) cell_op<T, CVT, NC, NC>(acc, k == k0, k, cl, addr, s_tab, lane);
+  if (SL == 0 && nfix > 0) {
+    if (nfix == n_step) {
+#pragma unroll
+      for (int c = 0; c < NC; c++) acc[c] = P[0];
+    } else {
+#pragma unroll
+      for (int c = 0; c < NC; c++) acc[c] = cmul(acc[c], P[0]);
+    }
+  }
   if (SL >= 1) {
     // sum bit 6 (the highest cell bit)
 #pragma unroll
@@ -693,7 +704,9 @@ __device__ __forceinline__ void cell_unit(const GI &G, const CellLane &cl,
 // Setup and units [u0, u1) (one per wave, strided) of a cell-mapped group.
 // With serial bits, the product P of the operands without them that hold no
 // unit bit (the first n_step0 of the last level) depends only on the lane, the
-// register cell and the angle set; a wave forms it when its set changes.
+// register cell and the angle set; without serial bits, P[0] is the product
+// of the first n_step0 operands, which hold lane bits only.  A wave forms P
+// when its set changes.
 template <class T, bool CVT, int CB, int SL>
 __device__ __forceinline__ void cell_units(const GI &G, const DevOp *__restrict__ gops,
                                            const int32_t *__restrict__ ctab,
@@ -704,14 +717,14 @@ __device__ __forceinline__ void cell_units(const GI &G, const DevOp *__restrict_
   CellLane cl;
   cell_setup<T, CVT, NC>(G, gops, ctab, data, s_tab, cl);
   __syncthreads();
-  const int nfix = SL > 0 ? G.n_step0 : 0;
-  const int kf = G.n_step + (SL == 2 ? G.n_serial : 0);
+  const int nfix = G.n_step0;
+  const int kf = SL == 0 ? 0 : G.n_step + (SL == 2 ? G.n_serial : 0);
   T P[SL > 0 ? NR : 1];
   uint32_t pset = 0xFFFFFFFFu;
   // flat unit f: angle set f / set_units, unit f % set_units
   for (uint32_t f = u0; f < u1; f += stride) {
     const uint32_t set = f / set_units;
-    if (SL > 0 && nfix > 0 && set != pset) {
+    if (nfix > 0 && set != pset) {
       const uint64_t a0 = cl.base + (uint64_t)set * cl.sstride;  // no unit part
       for (int k = kf; k < kf + nfix; k++)
         cell_op<T, CVT, NC, (SL > 0 ? NR : 1)>(P, k == kf, k, cl, a0, s_tab, lane);
