@@ -421,6 +421,12 @@ typedef struct qtn_plan_stats {
     size_t workspace;     /* device bytes                                 */
     int64_t n_matrix;     /* groups scheduled in matrix form (QTN_VAR_MFMA) */
     int64_t n_cell;       /* groups scheduled with the cell mapping        */
+    int64_t n_stream;     /* groups scheduled with the streaming mapping,
+                           * in own launches or inside workgroup segments */
+    int64_t n_over4g;     /* groups with an operand larger than 4 GiB      */
+    int64_t n_over4g_generic; /* of those, groups run by the generic mapping:
+                           * all of them, as the streaming and cell mappings
+                           * use 32-bit byte offsets within an operand     */
 } qtn_plan_stats;
 
 int qtn_get_plan_stats(const qtn_network *net, qtn_plan_stats *out);

@@ -97,7 +97,8 @@ class qtn_plan_stats(ctypes.Structure):
                 ("width_hist", ctypes.c_int32 * 40), ("bytes", ctypes.c_double),
                 ("flops", ctypes.c_double), ("paper_flops", ctypes.c_double),
                 ("workspace", ctypes.c_size_t), ("n_matrix", ctypes.c_int64),
-                ("n_cell", ctypes.c_int64)]
+                ("n_cell", ctypes.c_int64), ("n_stream", ctypes.c_int64),
+                ("n_over4g", ctypes.c_int64), ("n_over4g_generic", ctypes.c_int64)]
 
 
 class QtnError(RuntimeError):

@@ -170,7 +170,8 @@ def qtn_get_plan_stats(net):
             "max_width": s.max_width, "width_hist": list(s.width_hist),
             "bytes": s.bytes, "flops": s.flops, "paper_flops": s.paper_flops,
             "workspace": s.workspace, "n_matrix": s.n_matrix,
-            "n_cell": s.n_cell}
+            "n_cell": s.n_cell, "n_stream": s.n_stream, "n_over4g": s.n_over4g,
+            "n_over4g_generic": s.n_over4g_generic}
 
 
 def qtn_plan_order(net, edge):

@@ -262,6 +262,22 @@ int64_t gate_offset(const Gate &gt, bool transposed, int p) {
   }
 }
 
+// Bytes of the largest operand of a group (gate tables count in the group's
+// precision).  The streaming and cell mappings address the lane and cell
+// parts of an operand with 32-bit byte offsets, so they take only groups
+// whose operands all fit in 4 GiB; the generic mapping addresses elements
+// with 64-bit indices and takes any group.
+double max_operand_bytes(const Group &G, const ConePlan &pl) {
+  double mx = 0;
+  for (const Operand &o : G.ops) {
+    const Tensor &t = pl.tensors[o.tensor];
+    const int prec = t.gate >= 0 ? G.prec : t.prec;
+    mx = std::max(mx, std::ldexp(prec == 1 ? 8.0 : 16.0, (int)t.vars.size()));
+  }
+  return mx;
+}
+constexpr double kOffset32Bytes = 4294967296.0;
+
 // Candidate kernel configuration the autotuner forces on every wide group.
 struct Force {
   int place;    // -1 keep, 0 workgroup segment, 1 own launch
@@ -377,7 +393,8 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S, const Force *fo
         }
         const int rls = std::min(G.L - 1, rls_req);
         const int sl = G.L - 1 - rls;
-        const bool stream_ok = (int)G.ops.size() <= kStreamMaxOps && sl <= kStreamMaxSerial;
+        const bool off32 = max_operand_bytes(G, pl) <= kOffset32Bytes;
+        const bool stream_ok = (int)G.ops.size() <= kStreamMaxOps && sl <= kStreamMaxSerial && off32;
         // matrix form: complex64 groups in their own launch whose operands
         // reduce to two factors (requested, or picked by tuning)
         GemmShape gsh;
@@ -390,7 +407,7 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S, const Force *fo
         const int low = std::max(G.L, 6);
         auto cell_fits = [&](int cbits) {
           const int r = cbits - std::max(0, G.L - 6);
-          return !is_small && !persistent && (int)G.ops.size() <= 64 &&
+          return !is_small && !persistent && off32 && (int)G.ops.size() <= 64 &&
                  cell_lds_words((int)G.ops.size(), cbits) <= kCellMaxLdsWords &&
                  G.L - 6 <= kCellMaxSerial && r >= 0 && G.w - low >= r;
         };
@@ -1697,7 +1714,8 @@ static int autotune_sets(qtn_network *net, void *d_workspace, size_t bytes, void
       const double *t = G.small ? m.block : m.wide;
       const int rls = std::min(G.L - 1, net->lane_sum_bits), sl = G.L - 1 - rls;
       const bool rule_stream = (int)G.ops.size() <= kStreamMaxOps && sl <= kStreamMaxSerial &&
-                               sl >= 2 && net->variant != 1;
+                               sl >= 2 && net->variant != 1 &&
+                               max_operand_bytes(G, pl) <= kOffset32Bytes;
       // the rule's own configuration: the cell mapping wherever it ran (own
       // launches of the per-group executors), else streaming or generic
       int rule_cell = -1;
@@ -1939,9 +1957,16 @@ int qtn_get_plan_stats(const qtn_network *net, qtn_plan_stats *out) {
     st.flops += s.flops[k];
   }
   st.workspace = s.total;
-  for (const DevGroup &g : s.groups) {
+  for (size_t gi = 0; gi < s.groups.size(); gi++) {
+    const DevGroup &g = s.groups[gi];
     st.n_matrix += g.variant == kVarMfma ? 1 : 0;
     st.n_cell += g.variant == kVarCell ? 1 : 0;
+    st.n_stream += g.variant == kVarStream ? 1 : 0;
+    const ConePlan &pl = net->plans[s.group_cone[gi]];
+    if (max_operand_bytes(pl.groups[s.group_index[gi]], pl) > kOffset32Bytes) {
+      st.n_over4g++;
+      st.n_over4g_generic += g.variant == kVarGeneric ? 1 : 0;
+    }
   }
   *out = st;
   return QTN_OK;

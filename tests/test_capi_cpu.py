@@ -150,6 +150,35 @@ def test_cell_mapping_scheduling_rules(qtn):
     assert cells(small_width=32)[0] == 0
 
 
+def test_operands_over_4gib_take_the_generic_mapping(qtn):
+    """The streaming and cell mappings address within an operand with 32-bit
+    byte offsets, so a group holding an operand above 4 GiB must run the
+    generic mapping (64-bit element indices) whatever mapping is requested.
+    A 5-regular graph of 22 vertices at p=3 plans to width 32; in complex128
+    a few of its groups hold rank-29 operands (8 GiB)."""
+    inst = qs.instance(22, 5, 3, 0)
+    g, b = inst["angles"][0]
+
+    def stats(prec, **cfg):
+        net = qtn.Network(22, inst["edges"], g, b, order_trials=8, **cfg)
+        net.plan(prec)
+        st = net.stats()
+        net.close()
+        return st
+
+    for variant in (0, 2, 4):
+        st = stats(0, variant=variant)
+        assert st["max_width"] >= 30
+        assert st["n_over4g"] > 0
+        assert st["n_over4g_generic"] == st["n_over4g"], variant
+        # the other groups keep the requested mapping
+        assert st["n_cell"] + st["n_stream"] > 0
+    st = stats(1, variant=4)
+    assert st["n_over4g_generic"] == st["n_over4g"]
+    # complex64 halves the operand bytes: no more groups cross the limit
+    assert st["n_over4g"] <= stats(0, variant=4)["n_over4g"]
+
+
 def test_tune_angles_workspace_query(qtn):
     """Workspace of autotuning on angle batches: grows with the set count, at
     least the angle-batch workspace; bad set counts and unplanned networks
