@@ -18,7 +18,9 @@
  * Conventions for every call:
  *   - returns QTN_OK (0) or a negative QTN_E* code; qtn_last_error() gives a
  *     message for the calling thread, valid until its next call;
- *   - no C++ exception crosses this boundary;
+ *   - no C++ exception crosses this boundary: a failed host allocation
+ *     returns QTN_ENOMEM, any other internal exception QTN_EINVAL with a
+ *     message starting "internal error";
  *   - on error, caller-owned output buffers are left untouched;
  *   - arrays passed in are copied; the caller keeps ownership;
  *   - a qtn_network is owned by the library and released by

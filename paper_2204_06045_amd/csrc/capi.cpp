@@ -39,6 +39,21 @@ int set_err(int code, const std::string &msg) {
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// Status of the exception being handled, at the C ABI, which no C++
+// exception crosses: QTN_ENOMEM for a failed host allocation, QTN_EINVAL
+// ("internal error: ...") for anything else.
+int exception_status() {
+  try {
+    throw;
+  } catch (const std::bad_alloc &) {
+    return set_err(QTN_ENOMEM, "host allocation failed");
+  } catch (const std::exception &e) {
+    return set_err(QTN_EINVAL, std::string("internal error: ") + e.what());
+  } catch (...) {
+    return set_err(QTN_EINVAL, "internal error");
+  }
+}
+
 uint32_t pext32(uint32_t x, uint32_t mask) {
   uint32_t r = 0, d = 0;
   for (int b = 0; b < 32; b++)
@@ -1228,6 +1243,8 @@ int qtn_network_build(int32_t n_vertices, int64_t n_edges, const int32_t *edges,
     return set_err(QTN_ENOMEM, "host allocation failed");
   } catch (const std::exception &e) {
     return set_err(QTN_EINVAL, e.what());
+  } catch (...) {
+    return exception_status();
   }
 }
 
@@ -1253,8 +1270,8 @@ int qtn_network_info(const qtn_network *cnet, int64_t edge, int32_t *n_vars, int
     if (n_tensors) *n_tensors = (int32_t)lc.gates.size();
     if (width_minfill) *width_minfill = w;
     return QTN_OK;
-  } catch (const std::bad_alloc &) {
-    return set_err(QTN_ENOMEM, "host allocation failed");
+  } catch (...) {
+    return exception_status();
   }
 }
 
@@ -1267,8 +1284,8 @@ int qtn_order_minfill(const qtn_network *cnet, int64_t edge, int32_t *order_out)
     const auto &o = get_minfill(net, (int)edge);
     std::copy(o.begin(), o.end(), order_out);
     return QTN_OK;
-  } catch (const std::bad_alloc &) {
-    return set_err(QTN_ENOMEM, "host allocation failed");
+  } catch (...) {
+    return exception_status();
   }
 }
 
@@ -1329,8 +1346,8 @@ int qtn_plan(qtn_network *net, const int32_t *const *orders, int32_t precision,
     net->version++;
     if (workspace_bytes_out) *workspace_bytes_out = net->tune_workspace;
     return QTN_OK;
-  } catch (const std::bad_alloc &) {
-    return set_err(QTN_ENOMEM, "host allocation failed");
+  } catch (...) {
+    return exception_status();
   }
 }
 
@@ -1360,8 +1377,8 @@ static int contract_impl(qtn_network *net, void *ws, size_t bytes, void *stream,
     if (zz_im) std::copy(res.begin() + m, res.begin() + 2 * m, zz_im);
     if (energy) *energy = res[2 * m];
     return QTN_OK;
-  } catch (const std::bad_alloc &) {
-    return set_err(QTN_ENOMEM, "host allocation failed");
+  } catch (...) {
+    return exception_status();
   }
 }
 
@@ -1454,8 +1471,8 @@ int qtn_angles_workspace(qtn_network *net, int32_t n_sets, size_t *bytes_out) {
     if (!ex) return rc;
     *bytes_out = ex->sched.total;
     return QTN_OK;
-  } catch (const std::bad_alloc &) {
-    return set_err(QTN_ENOMEM, "host allocation failed");
+  } catch (...) {
+    return exception_status();
   }
 }
 
@@ -1493,8 +1510,8 @@ int qtn_contract_angles(qtn_network *net, void *d_workspace, size_t bytes, void 
       if (energy_out) energy_out[k] = res[(size_t)k * per + 2 * m];
     }
     return QTN_OK;
-  } catch (const std::bad_alloc &) {
-    return set_err(QTN_ENOMEM, "host allocation failed");
+  } catch (...) {
+    return exception_status();
   }
 }
 
@@ -1541,8 +1558,8 @@ int qtn_batch_workspace(qtn_network *const *nets, int32_t n, size_t *workspace_b
     if (!ex) return rc;
     *workspace_bytes_out = ex->sched.total;
     return QTN_OK;
-  } catch (const std::bad_alloc &) {
-    return set_err(QTN_ENOMEM, "host allocation failed");
+  } catch (...) {
+    return exception_status();
   }
 }
 
@@ -1563,8 +1580,8 @@ int qtn_contract_batch(qtn_network *const *nets, int32_t n, void *d_workspace, s
     if (zz_out) std::copy(res.begin(), res.begin() + m, zz_out);
     if (energy_out) std::copy(res.begin() + 2 * m, res.begin() + 2 * m + n, energy_out);
     return QTN_OK;
-  } catch (const std::bad_alloc &) {
-    return set_err(QTN_ENOMEM, "host allocation failed");
+  } catch (...) {
+    return exception_status();
   }
 }
 
@@ -1772,8 +1789,8 @@ static int autotune_sets(qtn_network *net, void *d_workspace, size_t bytes, void
     net->version++;
     if (report) *report = rep;
     return QTN_OK;
-  } catch (const std::bad_alloc &) {
-    return set_err(QTN_ENOMEM, "host allocation failed");
+  } catch (...) {
+    return exception_status();
   }
 }
 
@@ -1851,8 +1868,8 @@ int qtn_set_tune_picks(qtn_network *net, const qtn_tune_pick *picks, int64_t n) 
     net->exec = std::move(ex);
     net->version++;
     return QTN_OK;
-  } catch (const std::bad_alloc &) {
-    return set_err(QTN_ENOMEM, "host allocation failed");
+  } catch (...) {
+    return exception_status();
   }
 }
 
@@ -1897,8 +1914,8 @@ int qtn_energy_gradient(qtn_network *net, void *d_workspace, size_t bytes, void 
       grad_beta_out[l] = (e[1 + 2 * p + 2 * l] - e[2 + 2 * p + 2 * l]) / (2.0 * step);
     }
     return QTN_OK;
-  } catch (const std::bad_alloc &) {
-    return set_err(QTN_ENOMEM, "host allocation failed");
+  } catch (...) {
+    return exception_status();
   }
 }
 
@@ -1909,8 +1926,8 @@ int qtn_tune_angles_workspace(qtn_network *net, int32_t n_sets, size_t *bytes_ou
     if (n_sets < 1 || n_sets > kMaxAngleSets)
       return set_err(QTN_EINVAL, "n_sets must be in 1.." + std::to_string(kMaxAngleSets));
     return tune_workspace_bytes(net, n_sets, bytes_out);
-  } catch (const std::bad_alloc &) {
-    return set_err(QTN_ENOMEM, "host allocation failed");
+  } catch (...) {
+    return exception_status();
   }
 }
 
@@ -2038,8 +2055,8 @@ int qtn_costmodel_create(const float *params, qtn_costmodel **out) {
     }
     *out = cm;
     return QTN_OK;
-  } catch (const std::bad_alloc &) {
-    return set_err(QTN_ENOMEM, "host allocation failed");
+  } catch (...) {
+    return exception_status();
   }
 }
 
@@ -2122,8 +2139,8 @@ int qtn_costmodel_train(qtn_costmodel *cm, const float *x, const double *ms, int
     cm->m2.swap(q2);
     cm->step = step;
     return QTN_OK;
-  } catch (const std::bad_alloc &) {
-    return set_err(QTN_ENOMEM, "host allocation failed");
+  } catch (...) {
+    return exception_status();
   }
 }
 
@@ -2142,8 +2159,8 @@ int qtn_costmodel_predict(const qtn_costmodel *cm, const float *x, int64_t n, vo
     QTN_HIP(hipStreamSynchronize(s));
     std::copy(y.begin(), y.end(), y_out);
     return QTN_OK;
-  } catch (const std::bad_alloc &) {
-    return set_err(QTN_ENOMEM, "host allocation failed");
+  } catch (...) {
+    return exception_status();
   }
 }
 
@@ -2168,8 +2185,8 @@ int qtn_costmodel_grad(const qtn_costmodel *cm, const float *x, const float *t, 
     *loss_out = loss;
     std::copy(g.begin(), g.end(), grad_out);
     return QTN_OK;
-  } catch (const std::bad_alloc &) {
-    return set_err(QTN_ENOMEM, "host allocation failed");
+  } catch (...) {
+    return exception_status();
   }
 }
 
@@ -2196,8 +2213,8 @@ int qtn_costmodel_adam_step(qtn_costmodel *cm, const float *grad, float lr, void
     cm->m2.swap(q2);
     cm->step++;
     return QTN_OK;
-  } catch (const std::bad_alloc &) {
-    return set_err(QTN_ENOMEM, "host allocation failed");
+  } catch (...) {
+    return exception_status();
   }
 }
 
@@ -2259,8 +2276,8 @@ int qtn_apply_costmodel(qtn_network *net, const qtn_costmodel *cm, void *d_ws, s
     net->version++;
     if (counts_out) std::copy(counts, counts + 4, counts_out);
     return QTN_OK;
-  } catch (const std::bad_alloc &) {
-    return set_err(QTN_ENOMEM, "host allocation failed");
+  } catch (...) {
+    return exception_status();
   }
 }
 
