@@ -32,6 +32,13 @@ def test_library_exports_every_declared_symbol(qtn):
     assert set(names) == set(_capi.EXPORTS)
 
 
+def test_free_functions_accept_null(qtn):
+    from paper_2204_06045_amd import _capi
+    lib = _capi.lib()
+    lib.qtn_network_free(None)
+    lib.qtn_costmodel_free(None)
+
+
 def test_minfill_matches_oracle_rule(qtn, orc):
     for n, d, p, seed in [(10, 3, 1, 0), (16, 3, 3, 2), (30, 3, 4, 0), (40, 4, 3, 1)]:
         inst = qs.instance(n, d, p, seed)
