@@ -547,7 +547,7 @@ def main():
                     help="tune the kernel choice per group after planning (stored choices "
                          "from --tune-file when they match the plan, else the autotuner)")
     ap.add_argument("--tune-file", default=None,
-                    help="stored kernel choices to apply (default: profiles/tune_n30p4_<prec>.json)")
+                    help="stored kernel choices to apply (default: paper_2204_06045_amd/tuning/tune_n30p4_<prec>.json)")
     ap.add_argument("--retune", action="store_true", help="ignore stored choices, measure afresh")
     ap.add_argument("--save-tune", default=None, help="write the autotuner's choices here")
     ap.add_argument("--eager", action="store_true",
@@ -574,7 +574,8 @@ def main():
                 order_trials=args.order_trials, executor=args.executor,
                 small_width=args.small_width, mixed_width=args.mixed_width, eager=args.eager)
     tune_file = None if args.retune else (
-        args.tune_file or os.path.join(ROOT, "profiles", f"tune_n30p4_{args.precision}.json"))
+        args.tune_file or os.path.join(ROOT, "paper_2204_06045_amd", "tuning",
+                                       f"tune_n30p4_{args.precision}.json"))
     net, dt, plan_s, last, n_evals = run_rows(
         Q, torch, inst, prec, args.levels, args.streams, args.steps, args.warmup,
         autotune=bool(args.autotune), tune_file=tune_file, save_tune_file=args.save_tune,
