@@ -520,6 +520,31 @@ def test_angle_batch_matches_single_sets(qtn, orc, gpu, prec, cfg):
     net.close()
 
 
+@pytest.mark.parametrize("n_sets", [1, 33, 1024])
+def test_angle_batch_set_counts(qtn, orc, gpu, n_sets):
+    """One set, a count past a power of two, and the largest count accepted
+    (1024), with the cell mapping forced on the wide groups: sampled sets
+    equal their single-set evaluation bit for bit, and the oracle."""
+    inst = qs.instance(12, 3, 2, 21, n_sets)
+    e = inst["edges"]
+    gs = np.array([a[0] for a in inst["angles"]])
+    bs = np.array([a[1] for a in inst["angles"]])
+    net = qtn.Network(12, e, gs[0], bs[0], small_width=4, variant=4)
+    net.plan(0)
+    assert net.stats()["n_cell"] > 0
+    print(f"angle batch n_sets={n_sets}", flush=True)
+    zz, en = net.contract_angles(gs, bs)
+    assert zz.shape == (n_sets, len(e)) and en.shape == (n_sets,)
+    for k in sorted({0, n_sets // 2, n_sets - 1}):
+        net.set_angles(gs[k], bs[k])
+        z1, _, e1 = net.contract()
+        assert np.array_equal(z1, zz[k]) and e1 == en[k], k
+    k = n_sets - 1
+    ref, ref_en = orc.energy(12, e, gs[k], bs[k], threads=8)
+    _check(zz[k], None, en[k], ref, ref_en, 0, f"set {k} of {n_sets}")
+    net.close()
+
+
 def test_angle_batch_full_size(qtn, gpu):
     """N=30 p=4 with the stored oracle angles as one of four sets."""
     gd = _golden("cfg2")
