@@ -449,7 +449,7 @@ def run_cfg4(Q, torch, steps=10, autotune=True):
 
 def run_costmodel(Q, torch, prec=1, epochs=600, lr=3e-3, reps=3):
     """Train the cost model on autotuner timings of N=10 p=1, N=30 p=4 and 16
-    of the batched graphs; judge it by measured time on 32 held-out graphs
+    of the batched graphs; evaluate it by measured time on 32 held-out graphs
     (16 cubic, 16 quartic, N even in [50, 500], p=3) against the width rule."""
     import numpy as np
     import qaoa_synth as qs
