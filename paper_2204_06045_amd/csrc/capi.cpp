@@ -108,6 +108,7 @@ struct Schedule {
   int64_t scalar_off = 0, scalar_sstride = 0;
   int n_sets = 1;  // angle sets evaluated per launch (one copy of the data each)
   std::vector<char> desc_blob;  // bytes [off_desc, off_data)
+  uint64_t serial = 0;          // distinct for every schedule built
   double bytes[QTN_NKERNELS] = {}, flops[QTN_NKERNELS] = {};
   double init_bytes = 0, init_flops = 0;
   // persistent executors: work items in step order; the task (one cone's
@@ -130,7 +131,13 @@ struct Runtime {
   std::vector<hipEvent_t> ev_join;
   double *pinned = nullptr;
   size_t pinned_n = 0;
-  void *ws = nullptr;  // workspace holding the uploaded descriptors
+  void *ws = nullptr;  // workspace the captured graph was recorded for
+  // pinned copy of the schedule's descriptor bytes, uploaded into the
+  // workspace before every evaluation (the workspace contents are the
+  // caller's between calls, and other schedules may share its address)
+  char *pinned_desc = nullptr;
+  size_t pinned_desc_cap = 0, pinned_desc_n = 0;
+  uint64_t desc_serial = 0;  // schedule whose blob the pinned copy holds
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
   int persist_blocks = 0;
@@ -150,7 +157,11 @@ struct Runtime {
     if (main) (void)hipStreamDestroy(main);
     if (pinned) (void)hipHostFree(pinned);
     if (pinned_err) (void)hipHostFree(pinned_err);
+    if (pinned_desc) (void)hipHostFree(pinned_desc);
     pinned_err = nullptr;
+    pinned_desc = nullptr;
+    pinned_desc_cap = pinned_desc_n = 0;
+    desc_serial = 0;
     persist_blocks = 0;
     ev_in = ev_fork = nullptr;
     main = nullptr;
@@ -166,6 +177,8 @@ struct Runtime {
     exec = nullptr;
     graph = nullptr;
     ws = nullptr;
+    desc_serial = 0;
+    pinned_desc_n = 0;
   }
   // Takes over o's streams, events and pinned buffers (o is left empty), for
   // a new schedule of the same network: streams are not torn down and
@@ -183,6 +196,8 @@ struct Runtime {
     pinned_n = o.pinned_n;
     persist_blocks = o.persist_blocks;
     pinned_err = o.pinned_err;
+    pinned_desc = o.pinned_desc;
+    pinned_desc_cap = o.pinned_desc_cap;
     exec = o.exec;
     graph = o.graph;
     o.exec = nullptr;
@@ -192,6 +207,9 @@ struct Runtime {
     o.pinned = nullptr;
     o.pinned_n = 0;
     o.pinned_err = nullptr;
+    o.pinned_desc = nullptr;
+    o.pinned_desc_cap = o.pinned_desc_n = 0;
+    o.desc_serial = 0;
     o.persist_blocks = 0;
     o.ws = nullptr;
     o.device = -1;
@@ -316,8 +334,10 @@ const std::vector<Force> &tune_candidates() {
 // a workgroup, so no group takes the cell mapping).
 int build_schedule(qtn_network *const *nets, int n, Schedule *S, const Force *force = nullptr,
                    int singleton_width = 0, int n_sets = 1, bool persistent = false) {
+  static std::atomic<uint64_t> serial{0};
   Schedule &s = *S;
   s = Schedule();
+  s.serial = ++serial;
   s.n_sets = n_sets;
   s.prec = nets[0]->precision;
   s.scalar_prec = s.prec == kPrecC64 ? 1 : 0;
@@ -1101,7 +1121,9 @@ int enqueue(Exec &X, Timer &tm) {
   return QTN_OK;
 }
 
-// Upload descriptors (once per workspace), angles, run, read back.
+// Upload descriptors and angles, run, read back.  The descriptors go up
+// before every evaluation: between calls the workspace belongs to the caller,
+// who may reuse it for other schedules or other data.
 // set_angles: n_sets * n_angles doubles (per set, per network gamma[p] then
 // beta[p]); NULL: the networks' own angles (one set).
 int run_exec(Exec &X, const std::vector<const qtn_network *> &nets, void *ws, size_t bytes,
@@ -1118,20 +1140,30 @@ int run_exec(Exec &X, const std::vector<const qtn_network *> &nets, void *ws, si
   const int n_res = (2 * s.n_cones + s.n_nets) * s.n_sets;
   int rc = ensure_runtime(rt, n_streams, std::max(n_res, s.n_angles * s.n_sets));
   if (rc) return rc;
+  if (rt.desc_serial != s.serial || rt.pinned_desc_n != s.desc_blob.size()) {
+    if (rt.pinned_desc_cap < s.desc_blob.size()) {
+      if (rt.pinned_desc) QTN_HIP(hipHostFree(rt.pinned_desc));
+      rt.pinned_desc = nullptr;
+      rt.pinned_desc_cap = 0;
+      QTN_HIP(hipHostMalloc((void **)&rt.pinned_desc, s.desc_blob.size(), hipHostMallocDefault));
+      rt.pinned_desc_cap = s.desc_blob.size();
+    }
+    std::memcpy(rt.pinned_desc, s.desc_blob.data(), s.desc_blob.size());
+    rt.pinned_desc_n = s.desc_blob.size();
+    rt.desc_serial = s.serial;
+  }
   QTN_HIP(hipEventRecord(rt.ev_in, (hipStream_t)stream));
   QTN_HIP(hipStreamWaitEvent(rt.main, rt.ev_in, 0));
-  if (rt.ws != ws) {
-    if (rt.exec) {
-      (void)hipGraphExecDestroy(rt.exec);
-      (void)hipGraphDestroy(rt.graph);
-      rt.exec = nullptr;
-      rt.graph = nullptr;
-    }
-    QTN_HIP(hipMemcpyAsync((char *)ws + s.off_desc, s.desc_blob.data(), s.desc_blob.size(),
-                           hipMemcpyHostToDevice, rt.main));
-    QTN_HIP(hipStreamSynchronize(rt.main));
-    rt.ws = ws;
+  if (rt.ws != ws && rt.exec) {
+    // the captured graph holds the old workspace's addresses
+    (void)hipGraphExecDestroy(rt.exec);
+    (void)hipGraphDestroy(rt.graph);
+    rt.exec = nullptr;
+    rt.graph = nullptr;
   }
+  rt.ws = ws;
+  QTN_HIP(hipMemcpyAsync((char *)ws + s.off_desc, rt.pinned_desc, rt.pinned_desc_n,
+                         hipMemcpyHostToDevice, rt.main));
   if (set_angles) {
     std::memcpy(rt.pinned, set_angles, sizeof(double) * s.n_angles * s.n_sets);
   } else {

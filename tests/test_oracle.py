@@ -271,3 +271,57 @@ def test_costmodel_oracle_special_cases(orc):
     nz = np.abs(g) > 1e-3
     assert np.allclose(p1[nz], -0.01 * np.sign(g[nz]), rtol=1e-4)
     assert np.allclose(m1, 0.1 * g) and np.allclose(m2, 0.001 * g * g)
+
+
+def _mlp_numpy_forward(params, x):
+    """The 16-64-64-4 perceptron written out with numpy: parameters in the
+    order W1[16][64], b1[64], W2[64][64], b2[64], W3[64][4], b3[4]."""
+    sizes = [(16, 64), (64,), (64, 64), (64,), (64, 4), (4,)]
+    parts, k = [], 0
+    for s in sizes:
+        n = int(np.prod(s))
+        parts.append(np.asarray(params[k:k + n]).reshape(s))
+        k += n
+    W1, b1, W2, b2, W3, b3 = parts
+    h1 = np.maximum(x @ W1 + b1, 0.0)
+    h2 = np.maximum(h1 @ W2 + b2, 0.0)
+    return h2 @ W3 + b3
+
+
+def test_costmodel_oracle_forward_against_numpy(orc):
+    # random nonzero weights and biases, negative hidden biases included, so
+    # that both hidden ReLUs clip a share of the units
+    r = np.random.default_rng(5)
+    P = orc.mlp_nparams()
+    params = r.standard_normal(P) * 0.4
+    params[16 * 64:16 * 64 + 64] -= 0.3          # b1
+    params[16 * 64 + 64 + 4096:16 * 64 + 128 + 4096] -= 0.3  # b2
+    x = r.standard_normal((37, 16))
+    y = orc.mlp_forward(params, x)
+    ref = _mlp_numpy_forward(params, x)
+    assert np.max(np.abs(y - ref)) < 1e-12 * max(1.0, np.max(np.abs(ref)))
+    # both ReLUs matter on these inputs
+    W1 = params[:1024].reshape(16, 64)
+    assert np.mean(x @ W1 + params[1024:1088] < 0) > 0.2
+
+
+def test_costmodel_oracle_forward_hand_case(orc):
+    # x = 2 e_0.  Layer 1: units 0, 1 get +2, -2 (unit 1 clipped), unit 2
+    # bias -0.5 (clipped), unit 3 bias 0.5.  Layer 2: unit 0 = 3*2 = 6,
+    # unit 1 = 1*h1[1] - 4*0.5 = -2 (clipped), unit 2 = 2*0.5 = 1, unit 4 =
+    # -1*h1[1] = 0 (2 without the first ReLU).  Output: y0 = 0.5*6 + 0.1,
+    # y1 = 1*1 + 0.2, y2 = 7*h2[1] + 0.3 = 0.3 (-13.7 without the second
+    # ReLU), y3 = 1*h2[4] + 0.4 = 0.4.
+    P = orc.mlp_nparams()
+    p = np.zeros(P)
+    W1 = np.zeros((16, 64)); b1 = np.zeros(64)
+    W2 = np.zeros((64, 64)); b2 = np.zeros(64)
+    W3 = np.zeros((64, 4)); b3 = np.array([0.1, 0.2, 0.3, 0.4])
+    W1[0, 0], W1[0, 1] = 1.0, -1.0
+    b1[2], b1[3] = -0.5, 0.5
+    W2[0, 0], W2[1, 1], W2[3, 1], W2[3, 2], W2[1, 4] = 3.0, 1.0, -4.0, 2.0, -1.0
+    W3[0, 0], W3[2, 1], W3[1, 2], W3[4, 3] = 0.5, 1.0, 7.0, 1.0
+    p[:] = np.concatenate([W1.ravel(), b1, W2.ravel(), b2, W3.ravel(), b3])
+    x = np.zeros((1, 16)); x[0, 0] = 2.0
+    y = orc.mlp_forward(p, x)
+    assert np.allclose(y, [[3.1, 1.2, 0.3, 0.4]], atol=1e-15, rtol=0)
