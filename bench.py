@@ -244,6 +244,35 @@ def launch_breakdown(log):
                             if mm_ms > 0 else None)}
 
 
+def golden_check(Q, net, inst, prec, last, angle_batch, seed):
+    """Set 0 of the timed workload against the stored FP64 oracle values
+    (tests/golden/cfg2_oracle.json: graph seed 0, angle set 0), outside the
+    timed region.  Returns the comparison, or None when the workload is not
+    the stored one; exits on a mismatch beyond the tolerance."""
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", "cfg2_oracle.json")
+    with open(path) as f:
+        gd = json.load(f)
+    g0, b0 = inst["angles"][0]
+    if (seed != gd["seed"] or inst["n"] != gd["n"] or inst["p"] != gd["p"]
+            or list(g0) != gd["gamma"] or list(b0) != gd["beta"]):
+        return None
+    if angle_batch > 1:
+        zz, en = np.asarray(last[0])[0], float(np.asarray(last[1])[0])
+    else:
+        net.set_angles(g0, b0)
+        zz, _, en = net.contract()
+    tol = 1e-10 if prec == Q.QTN_C128 else 1e-5
+    de = float(np.max(np.abs(np.asarray(zz) - np.asarray(gd["zz_re"]))))
+    rel = abs(en - gd["energy"]) / abs(gd["energy"])
+    out = {"angle_set": 0, "max_abs_delta_e": de, "energy_rel_err": rel, "tol": tol,
+           "source": os.path.relpath(path, ROOT)}
+    if not (de <= tol and rel <= tol):
+        print(f"bench.py: set 0 differs from the FP64 oracle: {out}", file=sys.stderr)
+        sys.exit(1)
+    return out
+
+
 def host_facts():
     """Logical CPUs and RAM of the host the oracle runs on."""
     try:
@@ -292,6 +321,39 @@ def cpu_baseline(inst, seconds):
                        f"{wall:.1f} s, scaled to one full evaluation by that cost share")}
 
 
+def batch_golden_check(insts, nets, zz, en, master_seed, count):
+    """The last batched call's results against the stored FP64 oracle values
+    (tests/golden/cfg3_oracle.json: every light cone of the graphs the oracle
+    evaluated whole, the widest and the cheapest cones of the others),
+    outside the timed region; exits on a mismatch beyond the complex64
+    tolerance."""
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", "cfg3_oracle.json")
+    with open(path) as f:
+        gd = json.load(f)
+    if gd["master_seed"] != master_seed or gd["count"] != count:
+        return None
+    offs = np.cumsum([0] + [n.m for n in nets])
+    de, rel, n_cones, n_en = 0.0, 0.0, 0, 0
+    for rec in gd["graphs"]:
+        i = rec["index"]
+        it = insts[i]
+        if (it["n"], it["p"], len(it["edges"])) != (rec["n"], rec["p"], rec["m"]):
+            return None
+        z = np.asarray(zz[offs[i]:offs[i + 1]])[np.asarray(rec["edge_ids"])]
+        de = max(de, float(np.max(np.abs(z - np.asarray(rec["zz_re"])))))
+        n_cones += len(rec["edge_ids"])
+        if rec["energy"] is not None:
+            rel = max(rel, abs(float(en[i]) - rec["energy"]) / abs(rec["energy"]))
+            n_en += 1
+    out = {"light_cones_compared": n_cones, "max_abs_delta_e": de, "energies_compared": n_en,
+           "max_energy_rel_err": rel, "tol": 1e-5, "source": os.path.relpath(path, ROOT)}
+    if not (de <= 1e-5 and rel <= 1e-5):
+        print(f"bench.py: batched results differ from the FP64 oracle: {out}", file=sys.stderr)
+        sys.exit(1)
+    return out
+
+
 def run_batch(Q, torch, steps, warmup, executor=0, autotune=False, order_trials=16,
               prec=1, master_seed=2204, count=64):
     """64 random cubic graphs, N uniform over even sizes in [20, 200], p in
@@ -330,6 +392,7 @@ def run_batch(Q, torch, steps, warmup, executor=0, autotune=False, order_trials=
         zz, en = Q.qtn_contract_batch(handles, total, ws)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    parity = batch_golden_check(insts, nets, zz, en, master_seed, count)
     st = [n.stats() for n in nets]
     row = {"graphs": count, "light_cones": total, "calls_per_s": steps / dt,
            "energies_per_s": count * steps / dt, "light_cones_per_s": total * steps / dt,
@@ -338,7 +401,8 @@ def run_batch(Q, torch, steps, warmup, executor=0, autotune=False, order_trials=
            "max_width": max(s["max_width"] for s in st),
            "executor": {0: "persistent lockstep", 2: "persistent lockstep",
                         4: "persistent dataflow"}.get(executor, "launches"),
-           "precision": "c64" if prec == 1 else "c128", "order_trials": order_trials}
+           "precision": "c64" if prec == 1 else "c128", "order_trials": order_trials,
+           "parity_vs_oracle": parity}
     for n in nets:
         n.close()
     return row
@@ -582,6 +646,10 @@ def main():
         angle_batch=args.angle_batch, **kcfg)
     tune = net.tune_report
     evals = n_evals / dt
+    parity = golden_check(Q, net, inst, prec, last, args.angle_batch, args.seed)
+    if parity is not None:
+        log(f"  set 0 vs FP64 oracle: max |delta e| {parity['max_abs_delta_e']:.2e}, "
+            f"|delta E|/E {parity['energy_rel_err']:.2e}")
     stats = net.stats()
     log(f"  {evals:.2f} evals/s ({args.angle_batch} angle sets per step), plan {plan_s:.2f} s")
     # kernel roofline: the same tuned plan and step, its launches serialized
@@ -704,6 +772,7 @@ def main():
         "plan_seconds": plan_s,
         "autotune": tune,
         "roofline": roof,
+        "parity_vs_oracle": parity,
         "kernel_timing": timing,
         "kernel_source_hash": source_hash(),
         "variants": variants,

@@ -580,3 +580,89 @@ def test_angle_batch_timed_launch_log(qtn, gpu):
     for k, v in timing.items():
         assert abs(v["bytes"] - 3 * single[k]) <= 1e-6 * max(1.0, v["bytes"])
     net.close()
+
+
+def test_headline_plan_against_oracle(qtn, gpu):
+    """The benchmark's own plan and step: N=30 p=4 graph seed 0, 8 merged
+    levels, 4 streams, best-of-64 orders, the stored kernel choices, and one
+    32-set angle batch whose set 0 is the stored oracle angle set.  The
+    8-summed-index groups run on the cell mapping with 4 cell bits (2 of
+    them serial summed bits)."""
+    gd = _golden("cfg2")
+    inst = qs.instance(30, 3, 4, 0, 32)
+    gs = np.array([a[0] for a in inst["angles"]])
+    bs = np.array([a[1] for a in inst["angles"]])
+    assert np.array_equal(gs[0], gd["gamma"]) and np.array_equal(bs[0], gd["beta"])
+    net = qtn.Network(30, inst["edges"], gs[0], bs[0], max_levels=8, n_streams=4,
+                      order_trials=64)
+    net.plan(qtn.QTN_C128)
+    root = os.path.dirname(HERE)
+    with open(os.path.join(root, "paper_2204_06045_amd", "tuning", "tune_n30p4_c128.json")) as f:
+        net.set_tune_picks(json.load(f)["picks"])
+    aws = qtn.workspace(net.angles_workspace(32))
+    zz, en = net.contract_angles(gs, bs, aws)
+    _check(zz[0], None, en[0], gd["zz_re"], gd["energy"], 0, "headline set 0")
+    m = len(inst["edges"])
+    assert np.all(np.abs(zz) <= 1 + 1e-12) and np.all((en >= 0) & (en <= m))
+    # the timed pass runs the same launches one at a time and gives the same values
+    zt, et, _ = net.contract_angles(gs, bs, aws, timed=True)
+    assert np.array_equal(zt, zz) and np.array_equal(et, en)
+    log = net.launch_log()
+    assert any(r["kind"] == 2 and r["variant"] == 3 and r["knob"] == 4 and r["serial"] == 2
+               for r in log)
+    net.close()
+
+
+def _batch_golden():
+    """The stored FP64 oracle values of the 64-graph batch and the batch's
+    instances, regenerated from the same seeds (digest-checked)."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("make_golden",
+                                                  os.path.join(HERE, "golden", "make_golden.py"))
+    mg = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mg)
+    gd = _golden("cfg3")
+    insts = qs.batch_instances(gd["master_seed"], gd["count"], gd["n_lo"], gd["n_hi"],
+                               tuple(gd["depths"]), d=gd["d"])
+    for rec in gd["graphs"]:
+        assert mg.instance_digest(insts[rec["index"]]) == rec["digest"], rec["index"]
+    return gd, insts
+
+
+def test_batch64_full_size_against_oracle(qtn, gpu):
+    """The batched workload at full size: 64 cubic graphs (N even in [20,
+    200], p in {2, 3, 4}, 10,155 light cones) planned as the benchmark plans
+    them (best of 16 orders, complex64, persistent lockstep executor), all
+    contracted in one batched call.  Every stored light cone is compared per
+    edge, and every graph the oracle evaluated whole by its energy; the
+    stored cones cover depths 2, 3 and 4 and a cone of width 30."""
+    gd, insts = _batch_golden()
+    nets = []
+    for it in insts:
+        g, b = it["angles"][0]
+        net = qtn.Network(it["n"], it["edges"], g, b, order_trials=16, executor=0)
+        net.plan(qtn.QTN_C64)
+        nets.append(net)
+    handles = [n.h for n in nets]
+    total = sum(n.m for n in nets)
+    assert total == 10155
+    ws = qtn.workspace(qtn.qtn_batch_workspace(handles))
+    print(f"batch64: {total} light cones, workspace {ws.numel() / 2**30:.1f} GiB", flush=True)
+    zz, en = qtn.qtn_contract_batch(handles, total, ws)
+    offs = np.cumsum([0] + [n.m for n in nets])
+    widest, depths, n_edges = 0, set(), 0
+    for rec in gd["graphs"]:
+        i = rec["index"]
+        z = zz[offs[i]:offs[i + 1]]
+        ids = np.asarray(rec["edge_ids"])
+        err = np.max(np.abs(z[ids] - np.asarray(rec["zz_re"])))
+        assert err <= TOL[1], f"graph {i}: max |delta e| {err:.3e}"
+        if rec["energy"] is not None:
+            assert abs(en[i] - rec["energy"]) <= TOL[1] * abs(rec["energy"]), i
+        depths.add(rec["p"])
+        n_edges += len(ids)
+        widest = max(widest, max(max(nets[i].bucket_widths(int(k))) for k in ids))
+    print(f"batch64: {n_edges} light cones compared, widest planned bucket {widest}", flush=True)
+    assert depths == {2, 3, 4} and widest >= 30
+    for n in nets:
+        n.close()
