@@ -439,6 +439,76 @@ int qtn_bucket_widths(const qtn_network *net, int64_t edge, int32_t *widths_out)
 
 void qtn_network_free(qtn_network *net);
 
+/*
+ * One bucket contraction of caller-given tensors (Sec. II-B: the tensors of a
+ * bucket are multiplied over the union of their binary indices and the
+ * bucket index is summed out; with several summed indices, the merged form of
+ * Sec. II-C), with the kernels of the network path.  It isolates the bucket
+ * kernel for synthetic contraction benchmarks (Sec. II-E, Tab. III).
+ *
+ * Indices are binary and named by int32 labels.  The summed labels are the
+ * operand labels that out_labels does not list.  Union order: the summed
+ * labels in ascending value, then out_labels in the order given.  A tensor
+ * of rank r is a dense array of 2^r complex elements (complex128: two
+ * doubles re, im; complex64: two floats) whose element-index bit j is its
+ * j-th label: bit 0 is the least significant.  Each operand must list its
+ * labels in union order (the layout bucket elimination stores tensors in).
+ *   n_ops         1..64 operands
+ *   ranks         [n_ops] ranks, 0..32
+ *   labels        the operands' labels, concatenated ([sum ranks])
+ *   offsets       [n_ops] byte offsets of the operands in the data buffer,
+ *                 multiples of the element size
+ *   n_out, out_labels, out_offset   the output tensor (rank n_out, its
+ *                 labels, its byte offset); it may not overlap an operand
+ *   precision     QTN_C128 or QTN_C64 (every tensor in that precision)
+ *   variant       kernel mapping as qtn_config.variant: 0 the width rule,
+ *                 1 generic, 2 streaming, 3 matrix form (complex64 with two
+ *                 factors), 4 cell mapping; a mapping that does not fit falls
+ *                 back to the rule
+ *   knob          streaming: lane-summed labels; cells: cell bits (2..4);
+ *                 0 the default
+ *   out           receives the plan (host memory, library-owned)
+ * The summed count is 1..8 and the union holds at most 32 labels.
+ * Errors: QTN_EINVAL (labels, offsets, ranks or overlap), QTN_ERANGE (more
+ * than 8 summed labels, more than 32 in the union), QTN_ENOMEM.
+ */
+typedef struct qtn_bucket qtn_bucket;
+int qtn_bucket_plan(int32_t n_ops, const int32_t *ranks, const int32_t *labels,
+                    const int64_t *offsets, int32_t n_out, const int32_t *out_labels,
+                    int64_t out_offset, int32_t precision, int32_t variant, int32_t knob,
+                    qtn_bucket **out);
+
+typedef struct qtn_bucket_info {
+    int32_t w, L, n_ops;    /* union width, summed labels, operands          */
+    int32_t variant;        /* mapping chosen: 0 generic, 1 streaming,
+                               2 matrix form, 3 cells                        */
+    int32_t knob, serial;   /* streaming: lane-summed labels; cells: cell
+                               bits; serially walked summed labels           */
+    int64_t n_units;        /* wave units (matrix form: output tiles)        */
+    double bytes;           /* algorithmic HBM bytes (operands + output)     */
+    double flops;           /* complex-arithmetic FLOPs                      */
+    size_t workspace_bytes; /* device bytes of the descriptors               */
+    int64_t data_bytes;     /* smallest data buffer holding every tensor     */
+} qtn_bucket_info;
+
+int qtn_bucket_get_info(const qtn_bucket *b, qtn_bucket_info *out);
+
+/*
+ * Run a planned bucket on the caller's stream (asynchronous: returns after
+ * the launch is queued).
+ *   d_data       device buffer holding the tensors at the planned offsets,
+ *                at least data_bytes of qtn_bucket_get_info, 256-byte aligned
+ *   d_workspace  device memory of at least workspace_bytes, 256-byte
+ *                aligned; the descriptors are copied into it on the stream,
+ *                so it must stay untouched until the kernel has run
+ * Errors: QTN_EINVAL, QTN_ENOMEM (buffer or workspace too small),
+ *         QTN_EDEVICE.
+ */
+int qtn_bucket_contract(const qtn_bucket *b, void *d_data, size_t data_bytes,
+                        void *d_workspace, size_t ws_bytes, void *hip_stream);
+
+void qtn_bucket_free(qtn_bucket *b);
+
 const char *qtn_last_error(void);
 
 #ifdef __cplusplus

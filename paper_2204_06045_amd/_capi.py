@@ -43,7 +43,8 @@ EXPORTS = (
     "qtn_costmodel_create", "qtn_costmodel_params", "qtn_costmodel_normalization",
     "qtn_costmodel_workspace", "qtn_costmodel_train", "qtn_costmodel_predict",
     "qtn_costmodel_grad", "qtn_costmodel_adam_step", "qtn_apply_costmodel",
-    "qtn_costmodel_free",
+    "qtn_costmodel_free", "qtn_bucket_plan", "qtn_bucket_get_info", "qtn_bucket_contract",
+    "qtn_bucket_free",
 )
 MLP_PARAMS = 5508
 MLP_OUT = 4  # predicted variants: workgroup, streaming, generic, matrix form
@@ -99,6 +100,14 @@ class qtn_plan_stats(ctypes.Structure):
                 ("workspace", ctypes.c_size_t), ("n_matrix", ctypes.c_int64),
                 ("n_cell", ctypes.c_int64), ("n_stream", ctypes.c_int64),
                 ("n_over4g", ctypes.c_int64), ("n_over4g_generic", ctypes.c_int64)]
+
+
+class qtn_bucket_info(ctypes.Structure):
+    _fields_ = [("w", ctypes.c_int32), ("L", ctypes.c_int32), ("n_ops", ctypes.c_int32),
+                ("variant", ctypes.c_int32), ("knob", ctypes.c_int32),
+                ("serial", ctypes.c_int32), ("n_units", ctypes.c_int64),
+                ("bytes", ctypes.c_double), ("flops", ctypes.c_double),
+                ("workspace_bytes", ctypes.c_size_t), ("data_bytes", ctypes.c_int64)]
 
 
 class QtnError(RuntimeError):
@@ -171,8 +180,16 @@ def lib():
                                      ctypes.POINTER(i64)]
         L.qtn_network_free.argtypes = [P]
         L.qtn_network_free.restype = None
+        pi64 = ctypes.POINTER(ctypes.c_int64)
+        L.qtn_bucket_plan.argtypes = [i32, pi32, pi32, pi64, i32, pi32, i64, i32, i32, i32,
+                                      ctypes.POINTER(P)]
+        L.qtn_bucket_get_info.argtypes = [P, ctypes.POINTER(qtn_bucket_info)]
+        L.qtn_bucket_contract.argtypes = [P, P, sz, P, sz, P]
+        L.qtn_bucket_free.argtypes = [P]
+        L.qtn_bucket_free.restype = None
         for name in EXPORTS:
-            if name not in ("qtn_network_free", "qtn_last_error", "qtn_costmodel_free"):
+            if name not in ("qtn_network_free", "qtn_last_error", "qtn_costmodel_free",
+                            "qtn_bucket_free"):
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib

@@ -13,7 +13,8 @@ import numpy as np
 import torch
 
 from . import _capi
-from ._capi import (QTN_C128, QTN_C64, QTN_MIXED, QtnError, check, lib, qtn_config,
+from ._capi import (QTN_C128, QTN_C64, QTN_MIXED, QtnError, check, lib, qtn_bucket_info,
+                    qtn_config,
                     qtn_launch_rec, qtn_plan_stats, qtn_timing, qtn_tune_pick, qtn_tune_rec,
                     qtn_tune_report)
 
@@ -27,6 +28,8 @@ __all__ = [
     "qtn_tune_picks", "qtn_set_tune_picks", "qtn_angles_workspace", "qtn_contract_angles",
     "qtn_gradient_workspace", "qtn_energy_gradient",
     "Network", "CostModel", "qtn_apply_costmodel", "workspace", "stream_handle",
+    "qtn_bucket_plan", "qtn_bucket_get_info", "qtn_bucket_contract", "qtn_bucket_free",
+    "Bucket",
 ]
 
 _pi32 = ctypes.POINTER(ctypes.c_int32)
@@ -532,3 +535,85 @@ def qtn_apply_costmodel(net, cm, stream=None):
     check(lib().qtn_apply_costmodel(net, cm.h, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                                     stream_handle(stream), counts.ctypes.data_as(_pi32)))
     return counts
+
+
+# ------------------------------------------------------------ single bucket
+
+def qtn_bucket_plan(operands, offsets, out_labels, out_offset, precision=QTN_C128, variant=0,
+                    knob=0):
+    """operands: list of label lists (each in union order); offsets: byte
+    offsets of the operands in the data buffer.  Returns the bucket handle."""
+    ranks, rp = _i32([len(o) for o in operands])
+    labs, lp = _i32([x for o in operands for x in o] or [0])
+    offs = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    outl, olp = _i32(list(out_labels) or [0])
+    h = ctypes.c_void_p()
+    check(lib().qtn_bucket_plan(len(operands), rp, lp,
+                                offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                len(out_labels), olp, int(out_offset), precision, variant, knob,
+                                ctypes.byref(h)))
+    return h
+
+
+def qtn_bucket_get_info(b):
+    r = qtn_bucket_info()
+    check(lib().qtn_bucket_get_info(b, ctypes.byref(r)))
+    return {f: getattr(r, f) for f, _ in qtn_bucket_info._fields_}
+
+
+def qtn_bucket_contract(b, data, ws, stream=None):
+    check(lib().qtn_bucket_contract(b, ctypes.c_void_p(data.data_ptr()), data.numel(),
+                                    ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                    stream_handle(stream)))
+
+
+def qtn_bucket_free(b):
+    lib().qtn_bucket_free(b)
+
+
+class Bucket:
+    """One bucket contraction of caller-given tensors (qtn_bucket_*).  The
+    tensors share one device buffer: operand k at offsets[k], the output at
+    out_offset (packed at 256-byte boundaries in operand order when not
+    given)."""
+
+    def __init__(self, operands, out_labels, precision=QTN_C128, variant=0, knob=0,
+                 offsets=None, out_offset=None):
+        es = 8 if precision == QTN_C64 else 16
+        self.operands = [list(o) for o in operands]
+        self.out_labels = list(out_labels)
+        self.precision = precision
+        if offsets is None:
+            offsets, pos = [], 0
+            for o in self.operands:
+                offsets.append(pos)
+                pos += ((es << len(o)) + 255) // 256 * 256
+            out_offset = pos
+        self.offsets = list(offsets)
+        self.out_offset = int(out_offset)
+        self.h = qtn_bucket_plan(self.operands, self.offsets, self.out_labels, self.out_offset,
+                                 precision, variant, knob)
+        self._ws = None
+
+    def info(self):
+        return qtn_bucket_get_info(self.h)
+
+    def workspace(self):
+        if self._ws is None:
+            self._ws = workspace(self.info()["workspace_bytes"])
+        return self._ws
+
+    def contract(self, data, ws=None, stream=None):
+        """Queue the contraction on the stream (asynchronous)."""
+        qtn_bucket_contract(self.h, data, self.workspace() if ws is None else ws, stream)
+
+    def close(self):
+        if self.h:
+            qtn_bucket_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -330,6 +330,388 @@ const std::vector<Force> &tune_candidates() {
   return c;
 }
 
+// Where a group's operands and output live (bytes from the data base) and
+// the kernel configuration requested for it.
+struct GroupEnv {
+  int64_t out_off = 0, out_sstride = 0;   // output (tensor or scalar slot), set 0
+  int64_t arena = 0, arena_sstride = 0;   // intermediates sit at arena + Tensor::offset
+  int64_t table[2] = {-1, -1};            // gate tables: complex128, complex64
+  int64_t table_sstride[2] = {0, 0};
+  const LightCone *lc = nullptr;          // gates of the group's gate operands
+  int p = 0;                              // QAOA depth (gate table layout)
+  int var_req = 0, rls_req = 2;           // mapping requested (0: the width rule)
+  bool is_small = false;                  // runs inside a workgroup segment
+  bool persistent = false;                // the schedule runs in a persistent executor
+};
+
+// Device descriptor of one group: chooses its mapping, appends its operands
+// to s.ops (their tables to s.stab, its unit-bit order to s.uperm) and
+// returns the group record with its algorithmic bytes and flops.
+int describe_group(const Group &G, const ConePlan &pl, const GroupEnv &env, Schedule &s,
+                   DevGroup *dg_out, double *bytes_out, double *flops_out) {
+  auto es = [](int prec) { return prec == 1 ? (int64_t)8 : (int64_t)16; };
+  DevGroup dg;
+  std::memset(&dg, 0, sizeof dg);
+  dg.out_off = env.out_off;
+  dg.out_sstride = env.out_sstride;
+  dg.prec = (uint8_t)G.prec;
+  dg.op_begin = (int32_t)s.ops.size();
+  dg.w = (uint8_t)G.w;
+  dg.L = (uint8_t)G.L;
+  dg.n_ops = (uint8_t)G.ops.size();
+  double in_bytes = 0;
+  std::vector<int> per_level(G.L, 0);
+  for (const Operand &o : G.ops) {
+    per_level[o.level]++;
+    const Tensor &t = pl.tensors[o.tensor];
+    in_bytes += std::ldexp(1.0, (int)t.vars.size()) * es(t.gate >= 0 ? G.prec : t.prec);
+  }
+  int var_req = env.var_req, rls_req = env.rls_req;
+  const bool is_small = env.is_small, persistent = env.persistent;
+  const int rls = std::min(G.L - 1, rls_req);
+  const int sl = G.L - 1 - rls;
+  const bool off32 = max_operand_bytes(G, pl) <= kOffset32Bytes;
+  const bool stream_ok = (int)G.ops.size() <= kStreamMaxOps && sl <= kStreamMaxSerial && off32;
+  // matrix form: complex64 groups in their own launch whose operands
+  // reduce to two factors (requested, or picked by tuning)
+  GemmShape gsh;
+  const bool mfma = var_req == 3 && G.prec == 1 && gemm_shape(G, pl, &gsh);
+  if (var_req == 3 && !mfma) var_req = 0;
+  // cells: lanes on union bits 0..5, cb cell bits in registers (the
+  // summed bits above bit 5, then rb kept bits); own launches only (the
+  // kernel is not part of the workgroup and persistent paths).  Taken
+  // when requested, and by the rule for every own-launch group it fits
+  const int low = std::max(G.L, 6);
+  auto cell_fits = [&](int cbits) {
+    const int r = cbits - std::max(0, G.L - 6);
+    return !is_small && !persistent && off32 && (int)G.ops.size() <= 64 &&
+           cell_lds_words((int)G.ops.size(), cbits) <= kCellMaxLdsWords &&
+           G.L - 6 <= kCellMaxSerial && r >= 0 && G.w - low >= r;
+  };
+  int cb = 0;
+  bool cell = false;
+  if (var_req == 4) {
+    cb = rls_req >= kCellMinCB && rls_req <= kCellMaxCB ? rls_req : kCellRuleCB;
+    cell = cell_fits(cb);
+    if (!cell) var_req = 0;
+  }
+  if (var_req == 0 && !mfma && cell_fits(kCellRuleCB)) {
+    cb = kCellRuleCB;
+    cell = true;
+  }
+  const int rb = cell ? cb - std::max(0, G.L - 6) : 0;
+  // otherwise the streaming mapping once a lane walks >= 2 serial bits
+  const bool stream =
+      !mfma && !cell && stream_ok && (var_req == 2 || (var_req == 0 && sl >= 2));
+  std::vector<int> order(G.ops.size());
+  std::vector<int> cls(G.ops.size(), 0);
+  for (size_t k = 0; k < G.ops.size(); k++) order[k] = (int)k;
+  if (mfma) {
+    dg.variant = kVarMfma;
+    // [a, into At..., b, into Bt..., into Out...]
+    std::vector<int> side[3];
+    side[0].push_back(gsh.a);
+    side[1].push_back(gsh.b);
+    for (int k = 0; k < (int)G.ops.size(); k++)
+      if (k != gsh.a && k != gsh.b) side[gsh.role[k]].push_back(k);
+    order.clear();
+    for (auto &sd : side) order.insert(order.end(), sd.begin(), sd.end());
+    dg.n_unit = (uint8_t)side[0].size();
+    dg.n_step = (uint8_t)side[1].size();
+    dg.n_serial = (uint8_t)side[2].size();
+    dg.n_mb = (uint8_t)gsh.mbits.size();
+    dg.n_nb = (uint8_t)gsh.nbits.size();
+    dg.n_bb = (uint8_t)gsh.bbits.size();
+    const uint64_t mt = ((1ull << dg.n_mb) + kMfmaTM - 1) / kMfmaTM;
+    const uint64_t nt = ((1ull << dg.n_nb) + kMfmaTN - 1) / kMfmaTN;
+    const uint64_t tiles = (1ull << dg.n_bb) * mt * nt;
+    if (tiles > 0xFFFFFFFFull) return set_err(QTN_ERANGE, "matrix-form group too large");
+    dg.n_units = (uint32_t)tiles;
+  } else if (cell) {
+    dg.variant = kVarCell;
+    dg.rls = (uint8_t)cb;
+    dg.sl = (uint8_t)std::max(0, G.L - 6);
+    dg.lk = (uint8_t)(6 - std::min(G.L, 6));
+    // operands by the first summed bit above the lanes they hold (the
+    // serial cells are summed in that order, each operand multiplying
+    // only the cells still open at its level): bit 6, then bit 7, then
+    // none; without serial bits every operand is at the first level
+    std::vector<int> lev(G.ops.size(), 0);
+    for (size_t k = 0; k < G.ops.size(); k++) {
+      const uint32_t m = G.ops[k].mask;
+      lev[k] = G.L <= 6 ? 0 : ((m >> 6) & 1u) ? 0 : (G.L > 7 && ((m >> 7) & 1u)) ? 1 : 2;
+      cls[k] = lev[k] < 2 ? kClsStep : kClsUnit;
+    }
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return lev[a] < lev[b]; });
+    int n0 = 0, n1 = 0;
+    for (int k : order) {
+      n0 += lev[k] == 0 ? 1 : 0;
+      n1 += lev[k] == 1 ? 1 : 0;
+    }
+    dg.n_step = (uint8_t)n0;
+    dg.n_serial = (uint8_t)n1;
+    dg.n_units = 1u << (G.w - low - rb);
+  } else if (stream) {
+    dg.variant = kVarStream;
+    dg.rls = (uint8_t)rls;
+    dg.sl = (uint8_t)sl;
+    dg.lk = (uint8_t)(6 - rls);
+    // lane-kept bits: the lowest kept bits, so that the lanes' output
+    // writes are contiguous (positions past the union, in narrow
+    // groups, give idle lanes).  Choosing instead the bits the large
+    // operands lack, so that lanes share operand elements, measured
+    // slower.
+    for (int j = 0; j < dg.lk; j++) dg.lkpos[j] = (uint8_t)(G.L + j);
+    uint32_t lane_kept = 0;
+    for (int j = 0; j < dg.lk; j++)
+      if (dg.lkpos[j] < 32) lane_kept |= 1u << dg.lkpos[j];
+    const uint32_t serial_bits = ((1u << G.L) - 1u) & ~((1u << (1 + rls)) - 1u);
+    const uint32_t lane_bits = (((1u << rls) - 1u) << 1) | lane_kept;
+    for (size_t k = 0; k < G.ops.size(); k++) {
+      const Operand &o = G.ops[k];
+      if (o.level >= 1 + rls)
+        cls[k] = (o.mask & lane_bits) ? kClsSerial : kClsUniform;
+      else
+        cls[k] = (o.mask & serial_bits) ? kClsStep : kClsUnit;
+    }
+    // step-class operands with bit 0 first: they fill the unrolled slots
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+      if (cls[a] != cls[b]) return cls[a] < cls[b];
+      if (cls[a] == kClsStep) return (G.ops[a].mask & 1u) > (G.ops[b].mask & 1u);
+      return false;
+    });
+    int nu = 0, ns = 0, nun = 0, nse = 0, ns0 = 0;
+    for (int k : order) {
+      if (cls[k] == kClsUnit) nu++;
+      else if (cls[k] == kClsStep) {
+        ns++;
+        ns0 += (G.ops[k].mask & 1u) ? 1 : 0;
+      }
+      else if (cls[k] == kClsUniform) nun++;
+      else nse++;
+    }
+    dg.n_unit = (uint8_t)nu;
+    dg.n_step = (uint8_t)ns;
+    dg.n_step0 = (uint8_t)ns0;
+    dg.n_serial = (uint8_t)(nun + nse);
+    dg.level_end[0] = (uint8_t)nun;
+    const int kept_lanes = G.L + dg.lk;
+    dg.n_units = G.w > kept_lanes ? 1u << (G.w - kept_lanes) : 1u;
+  } else {
+    dg.variant = kVarGeneric;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return G.ops[a].level < G.ops[b].level; });
+    int cum = 0;
+    for (int l = 0; l < kMaxLevels; l++) {
+      if (l < G.L) cum += per_level[l];
+      dg.level_end[l] = (uint8_t)cum;
+    }
+    const int bits = kGenRegBits + 6;
+    dg.n_units = G.w > bits ? 1u << (G.w - bits) : 1u;
+  }
+  if (mfma) {
+    // matrix form: m bits, then n bits, then batch bits
+    uint8_t up[32];
+    std::memset(up, 0, sizeof up);
+    int j = 0;
+    for (int q : gsh.mbits) up[j++] = (uint8_t)q;
+    for (int q : gsh.nbits) up[j++] = (uint8_t)q;
+    for (int q : gsh.bbits) up[j++] = (uint8_t)q;
+    dg.n_ubits = 0;
+    s.uperm.insert(s.uperm.end(), up, up + 32);
+  } else {
+    // wave-unit bits, those that large operands lack first (their data
+    // is then reused by neighbouring units of the same block and XCD);
+    // cells: the first rb of that order are the register bits (each
+    // value of an operand lacking them serves several cells), first in
+    // the table
+    const int start = stream ? G.L : (cell ? low : kGenRegBits + 6);
+    std::vector<std::pair<double, int>> sc;
+    for (int b = start; b < G.w; b++) {
+      bool lane = false;
+      for (int j = 0; stream && j < dg.lk; j++) lane |= dg.lkpos[j] == b;
+      if (lane) continue;
+      double miss = 0;
+      for (const Operand &o : G.ops)
+        if (pl.tensors[o.tensor].gate < 0 && !((o.mask >> b) & 1u))
+          miss += std::ldexp(1.0, (int)pl.tensors[o.tensor].vars.size());
+      sc.push_back({-miss, b});
+    }
+    std::stable_sort(sc.begin(), sc.end());
+    std::vector<int> regs;
+    if (cell) {
+      // register bits: one at a time, the kept bit that adds the fewest
+      // loads (an operand is loaded once per distinct value of the cell
+      // bits it holds), ties to the earlier bit of the order above
+      // cell bits held so far: the serial bits still open at the
+      // operand's level
+      std::vector<uint32_t> held(G.ops.size(), 0);
+      for (size_t k = 0; k < G.ops.size(); k++) {
+        const uint32_t m = G.ops[k].mask;
+        const int lv = G.L <= 6 ? 0 : ((m >> 6) & 1u) ? 0 : (G.L > 7 && ((m >> 7) & 1u)) ? 1 : 2;
+        for (int t = lv; t < dg.sl; t++) held[k] += (m >> (6 + t)) & 1u;
+      }
+      for (int j = 0; j < rb; j++) {
+        size_t bi = 0;
+        double best_cost = -1;
+        for (size_t q = 0; q < sc.size(); q++) {
+          double cost = 0;
+          for (size_t k = 0; k < G.ops.size(); k++)
+            cost += std::ldexp(1.0, (int)held[k] + (int)((G.ops[k].mask >> sc[q].second) & 1u));
+          if (best_cost < 0 || cost < best_cost) {
+            best_cost = cost;
+            bi = q;
+          }
+        }
+        for (size_t k = 0; k < G.ops.size(); k++) held[k] += (G.ops[k].mask >> sc[bi].second) & 1u;
+        regs.push_back(sc[bi].second);
+        sc.erase(sc.begin() + bi);
+      }
+      // with serial bits, the operands without them that hold no unit
+      // bit go first: their product over the register cells is formed
+      // once per angle set and reused by every unit (without serial
+      // bits it would span every cell and cost more registers than it
+      // saves)
+      if (dg.sl > 0) {
+        uint32_t unit_mask = 0;
+        for (auto &q : sc) unit_mask |= 1u << q.second;
+        const int last0 = dg.n_step + (dg.sl == 2 ? dg.n_serial : 0);
+        std::stable_partition(order.begin() + last0, order.end(),
+                              [&](int k) { return (G.ops[k].mask & unit_mask) == 0; });
+        int nfix = 0;
+        for (size_t i = last0; i < order.size(); i++)
+          nfix += (G.ops[order[i]].mask & unit_mask) == 0 ? 1 : 0;
+        dg.n_step0 = (uint8_t)nfix;
+      } else {
+        // without serial bits, the operands holding only lane bits go
+        // first: their product, one value per lane, is formed once per
+        // angle set and multiplies the cells once per unit
+        std::stable_partition(order.begin(), order.end(),
+                              [&](int k) { return (G.ops[k].mask & ~63u) == 0; });
+        int nfix = 0;
+        for (int k : order) nfix += (G.ops[k].mask & ~63u) == 0 ? 1 : 0;
+        dg.n_step0 = (uint8_t)nfix;
+      }
+      // the cell mapping forms an operand's unit offset from its runs
+      // over the unit bits; past kCellURuns of them, ascending order
+      // (at most one run per two unit bits)
+      int worst = 0;
+      for (const Operand &o : G.ops) {
+        int runs = 0, prev = -2;
+        for (size_t j = 0; j < sc.size(); j++) {
+          const int q = sc[j].second;
+          if (!((o.mask >> q) & 1u)) {
+            prev = -2;
+            continue;
+          }
+          const int rank = __builtin_popcount(o.mask & ((1u << q) - 1u));
+          if (rank != prev + 1) runs++;
+          prev = rank;
+        }
+        worst = std::max(worst, runs);
+      }
+      if (worst > kCellURuns)
+        std::sort(sc.begin(), sc.end(),
+                  [](const std::pair<double, int> &a, const std::pair<double, int> &b) {
+                    return a.second < b.second;
+                  });
+    }
+    uint8_t up[32];
+    std::memset(up, 0, sizeof up);
+    const int first = cell ? rb : 0;
+    for (int j = 0; j < first; j++) up[j] = (uint8_t)regs[j];
+    for (size_t j = 0; j < sc.size(); j++) up[first + j] = (uint8_t)sc[j].second;
+    dg.n_ubits = (uint8_t)sc.size();
+    s.uperm.insert(s.uperm.end(), up, up + 32);
+  }
+  for (int k : order) {
+    const Operand &o = G.ops[k];
+    const Tensor &t = pl.tensors[o.tensor];
+    DevOp d;
+    std::memset(&d, 0, sizeof d);
+    if (t.gate >= 0) {
+      // gate operands read the table of the group's own precision
+      d.off = env.table[G.prec] + gate_offset(env.lc->gates[t.gate], t.transposed, env.p) * es(G.prec);
+      d.sstride = env.table_sstride[G.prec];
+      d.dt = (uint8_t)G.prec;
+    } else {
+      d.off = env.arena + t.offset;
+      d.sstride = env.arena_sstride;
+      d.dt = (uint8_t)t.prec;
+    }
+    d.mask = o.mask;
+    d.level = (uint8_t)o.level;
+    uint8_t rs[32], rl[32], rd[32];
+    const int nr = mask_runs(o.mask, rs, rl, rd);
+    if (nr > kOpRuns) return set_err(QTN_ERANGE, "operand index set too fragmented");
+    d.nruns = (uint8_t)nr;
+    for (int r = 0; r < nr; r++)
+      d.run[r] = (uint16_t)(rs[r] | (rl[r] << 5) | (rd[r] << 11));
+    d.cls = (uint8_t)cls[k];
+    d.stab = -1;
+    if (stream && cls[k] != kClsUnit) {
+      d.stab = (int32_t)s.stab.size();
+      for (uint32_t st = 0; st < (1u << dg.sl); st++)
+        s.stab.push_back((int32_t)pext32(st << (1 + dg.rls), o.mask));
+    }
+    if (cell) {
+      // cell offsets (cell c: kept bits c % 2^rb, serial bits c / 2^rb),
+      // then the runs giving the unit part of the index from the unit
+      // number
+      d.stab = (int32_t)s.stab.size();
+      const uint8_t *rp = s.uperm.data() + s.uperm.size() - 32;
+      uint32_t cm = 0;
+      // serial cell bit rb + t is union bit 6 + sl - 1 - t (bit 6 the
+      // highest cell bit, summed first)
+      for (int j = 0; j < rb; j++) cm |= ((o.mask >> rp[j]) & 1u) << j;
+      for (int t = 0; t < dg.sl; t++)
+        cm |= ((o.mask >> (6 + dg.sl - 1 - t)) & 1u) << (rb + t);
+      for (uint32_t c = 0; c < (1u << cb); c++) {
+        uint32_t I = 0;
+        for (int j = 0; j < rb; j++) I |= ((c >> j) & 1u) << rp[j];
+        for (int t = 0; t < dg.sl; t++) I |= ((c >> (rb + t)) & 1u) << (6 + dg.sl - 1 - t);
+        s.stab.push_back((int32_t)pext32(I, o.mask));
+      }
+      const uint8_t *up = rp + rb;
+      uint16_t ur[kCellURuns];
+      std::memset(ur, 0, sizeof ur);
+      int nur = 0;
+      for (int j = 0; j < dg.n_ubits;) {
+        const int q = up[j];
+        if (!((o.mask >> q) & 1u)) {
+          j++;
+          continue;
+        }
+        const int dst = __builtin_popcount(o.mask & ((1u << q) - 1u));
+        int len = 1;
+        while (j + len < dg.n_ubits && ((o.mask >> up[j + len]) & 1u) &&
+               __builtin_popcount(o.mask & ((1u << up[j + len]) - 1u)) == dst + len)
+          len++;
+        if (nur == kCellURuns) return set_err(QTN_ERANGE, "cell mapping: unit runs");
+        ur[nur++] = (uint16_t)(j | (len << 5) | (dst << 11));
+        j += len;
+      }
+      dg.n_unit = (uint8_t)std::max<int>(dg.n_unit, nur);
+      for (int w = 0; w < kCellURuns / 2; w++)
+        s.stab.push_back((int32_t)((uint32_t)ur[2 * w] | ((uint32_t)ur[2 * w + 1] << 16)));
+      s.stab.push_back((int32_t)cm);
+    }
+    if (d.dt != dg.prec) dg.cvt = 1;
+    s.ops.push_back(d);
+  }
+  double gb = in_bytes + es(G.prec) * std::ldexp(1.0, G.w - G.L), gf = 0;
+  for (int l = 0; l < G.L; l++) {
+    int factors = per_level[l] + (l > 0 ? 1 : 0);
+    gf += std::ldexp(1.0, G.w - l) * 6.0 * std::max(0, factors - 1) +
+          std::ldexp(1.0, G.w - l - 1) * 2.0;
+  }
+  *dg_out = dg;
+  *bytes_out = gb;
+  *flops_out = gf;
+  return QTN_OK;
+}
+
 // persistent: the schedule runs in a persistent executor (every group inside
 // a workgroup, so no group takes the cell mapping).
 int build_schedule(qtn_network *const *nets, int n, Schedule *S, const Force *force = nullptr,
@@ -392,378 +774,42 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S, const Force *fo
       };
       for (const Group &G : pl.groups) {
         if (G.ops.size() > 255) return set_err(QTN_ERANGE, "bucket with more than 255 tensors");
-        DevGroup dg;
-        std::memset(&dg, 0, sizeof dg);
         if (G.out_tensor < 0 && G.prec != s.scalar_prec)
           return set_err(QTN_EINVAL, "scalar group precision differs from the scalar slots");
-        dg.out_off = G.out_tensor >= 0
-                         ? arena + pl.tensors[G.out_tensor].offset
-                         : s.scalar_off + (int64_t)(scalar_next + G.scalar_slot) * es(s.scalar_prec);
-        dg.out_sstride = G.out_tensor >= 0 ? arena_sstride : s.scalar_sstride;
-        dg.prec = (uint8_t)G.prec;
-        dg.op_begin = (int32_t)s.ops.size();
-        dg.w = (uint8_t)G.w;
-        dg.L = (uint8_t)G.L;
-        dg.n_ops = (uint8_t)G.ops.size();
-        double in_bytes = 0;
-        std::vector<int> per_level(G.L, 0);
-        for (const Operand &o : G.ops) {
-          per_level[o.level]++;
-          const Tensor &t = pl.tensors[o.tensor];
-          in_bytes += std::ldexp(1.0, (int)t.vars.size()) * es(t.gate >= 0 ? G.prec : t.prec);
+        GroupEnv env;
+        env.out_off = G.out_tensor >= 0
+                          ? arena + pl.tensors[G.out_tensor].offset
+                          : s.scalar_off + (int64_t)(scalar_next + G.scalar_slot) * es(s.scalar_prec);
+        env.out_sstride = G.out_tensor >= 0 ? arena_sstride : s.scalar_sstride;
+        env.arena = arena;
+        env.arena_sstride = arena_sstride;
+        for (int q = 0; q < 2; q++) {
+          env.table[q] = table[q];
+          env.table_sstride[q] = table_sstride[q];
         }
+        env.lc = &lc;
+        env.p = net->p;
         // the mapping requested (network config, tuned pick or a tuning
-        // candidate); 0 leaves it to the rule below
-        int var_req = net->variant, rls_req = net->lane_sum_bits;
+        // candidate); 0 leaves it to the width rule
+        env.var_req = net->variant;
+        env.rls_req = net->lane_sum_bits;
         if (G.pick_variant > 0) {
-          var_req = G.pick_variant;
-          if (G.pick_rls >= 0) rls_req = G.pick_rls;
+          env.var_req = G.pick_variant;
+          if (G.pick_rls >= 0) env.rls_req = G.pick_rls;
         }
         const bool is_small = force && force->place >= 0
                                   ? force->place == 0
                                   : (G.pick_place >= 0 ? G.pick_place == 0 : G.small);
         if (force) {
-          var_req = force->variant;
-          rls_req = force->rls;
+          env.var_req = force->variant;
+          env.rls_req = force->rls;
         }
-        const int rls = std::min(G.L - 1, rls_req);
-        const int sl = G.L - 1 - rls;
-        const bool off32 = max_operand_bytes(G, pl) <= kOffset32Bytes;
-        const bool stream_ok = (int)G.ops.size() <= kStreamMaxOps && sl <= kStreamMaxSerial && off32;
-        // matrix form: complex64 groups in their own launch whose operands
-        // reduce to two factors (requested, or picked by tuning)
-        GemmShape gsh;
-        const bool mfma = var_req == 3 && G.prec == 1 && gemm_shape(G, pl, &gsh);
-        if (var_req == 3 && !mfma) var_req = 0;
-        // cells: lanes on union bits 0..5, cb cell bits in registers (the
-        // summed bits above bit 5, then rb kept bits); own launches only (the
-        // kernel is not part of the workgroup and persistent paths).  Taken
-        // when requested, and by the rule for every own-launch group it fits
-        const int low = std::max(G.L, 6);
-        auto cell_fits = [&](int cbits) {
-          const int r = cbits - std::max(0, G.L - 6);
-          return !is_small && !persistent && off32 && (int)G.ops.size() <= 64 &&
-                 cell_lds_words((int)G.ops.size(), cbits) <= kCellMaxLdsWords &&
-                 G.L - 6 <= kCellMaxSerial && r >= 0 && G.w - low >= r;
-        };
-        int cb = 0;
-        bool cell = false;
-        if (var_req == 4) {
-          cb = rls_req >= kCellMinCB && rls_req <= kCellMaxCB ? rls_req : kCellRuleCB;
-          cell = cell_fits(cb);
-          if (!cell) var_req = 0;
-        }
-        if (var_req == 0 && !mfma && cell_fits(kCellRuleCB)) {
-          cb = kCellRuleCB;
-          cell = true;
-        }
-        const int rb = cell ? cb - std::max(0, G.L - 6) : 0;
-        // otherwise the streaming mapping once a lane walks >= 2 serial bits
-        const bool stream =
-            !mfma && !cell && stream_ok && (var_req == 2 || (var_req == 0 && sl >= 2));
-        std::vector<int> order(G.ops.size());
-        std::vector<int> cls(G.ops.size(), 0);
-        for (size_t k = 0; k < G.ops.size(); k++) order[k] = (int)k;
-        if (mfma) {
-          dg.variant = kVarMfma;
-          // [a, into At..., b, into Bt..., into Out...]
-          std::vector<int> side[3];
-          side[0].push_back(gsh.a);
-          side[1].push_back(gsh.b);
-          for (int k = 0; k < (int)G.ops.size(); k++)
-            if (k != gsh.a && k != gsh.b) side[gsh.role[k]].push_back(k);
-          order.clear();
-          for (auto &sd : side) order.insert(order.end(), sd.begin(), sd.end());
-          dg.n_unit = (uint8_t)side[0].size();
-          dg.n_step = (uint8_t)side[1].size();
-          dg.n_serial = (uint8_t)side[2].size();
-          dg.n_mb = (uint8_t)gsh.mbits.size();
-          dg.n_nb = (uint8_t)gsh.nbits.size();
-          dg.n_bb = (uint8_t)gsh.bbits.size();
-          const uint64_t mt = ((1ull << dg.n_mb) + kMfmaTM - 1) / kMfmaTM;
-          const uint64_t nt = ((1ull << dg.n_nb) + kMfmaTN - 1) / kMfmaTN;
-          const uint64_t tiles = (1ull << dg.n_bb) * mt * nt;
-          if (tiles > 0xFFFFFFFFull) return set_err(QTN_ERANGE, "matrix-form group too large");
-          dg.n_units = (uint32_t)tiles;
-        } else if (cell) {
-          dg.variant = kVarCell;
-          dg.rls = (uint8_t)cb;
-          dg.sl = (uint8_t)std::max(0, G.L - 6);
-          dg.lk = (uint8_t)(6 - std::min(G.L, 6));
-          // operands by the first summed bit above the lanes they hold (the
-          // serial cells are summed in that order, each operand multiplying
-          // only the cells still open at its level): bit 6, then bit 7, then
-          // none; without serial bits every operand is at the first level
-          std::vector<int> lev(G.ops.size(), 0);
-          for (size_t k = 0; k < G.ops.size(); k++) {
-            const uint32_t m = G.ops[k].mask;
-            lev[k] = G.L <= 6 ? 0 : ((m >> 6) & 1u) ? 0 : (G.L > 7 && ((m >> 7) & 1u)) ? 1 : 2;
-            cls[k] = lev[k] < 2 ? kClsStep : kClsUnit;
-          }
-          std::stable_sort(order.begin(), order.end(),
-                           [&](int a, int b) { return lev[a] < lev[b]; });
-          int n0 = 0, n1 = 0;
-          for (int k : order) {
-            n0 += lev[k] == 0 ? 1 : 0;
-            n1 += lev[k] == 1 ? 1 : 0;
-          }
-          dg.n_step = (uint8_t)n0;
-          dg.n_serial = (uint8_t)n1;
-          dg.n_units = 1u << (G.w - low - rb);
-        } else if (stream) {
-          dg.variant = kVarStream;
-          dg.rls = (uint8_t)rls;
-          dg.sl = (uint8_t)sl;
-          dg.lk = (uint8_t)(6 - rls);
-          // lane-kept bits: the lowest kept bits, so that the lanes' output
-          // writes are contiguous (positions past the union, in narrow
-          // groups, give idle lanes).  Choosing instead the bits the large
-          // operands lack, so that lanes share operand elements, measured
-          // slower.
-          for (int j = 0; j < dg.lk; j++) dg.lkpos[j] = (uint8_t)(G.L + j);
-          uint32_t lane_kept = 0;
-          for (int j = 0; j < dg.lk; j++)
-            if (dg.lkpos[j] < 32) lane_kept |= 1u << dg.lkpos[j];
-          const uint32_t serial_bits = ((1u << G.L) - 1u) & ~((1u << (1 + rls)) - 1u);
-          const uint32_t lane_bits = (((1u << rls) - 1u) << 1) | lane_kept;
-          for (size_t k = 0; k < G.ops.size(); k++) {
-            const Operand &o = G.ops[k];
-            if (o.level >= 1 + rls)
-              cls[k] = (o.mask & lane_bits) ? kClsSerial : kClsUniform;
-            else
-              cls[k] = (o.mask & serial_bits) ? kClsStep : kClsUnit;
-          }
-          // step-class operands with bit 0 first: they fill the unrolled slots
-          std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-            if (cls[a] != cls[b]) return cls[a] < cls[b];
-            if (cls[a] == kClsStep) return (G.ops[a].mask & 1u) > (G.ops[b].mask & 1u);
-            return false;
-          });
-          int nu = 0, ns = 0, nun = 0, nse = 0, ns0 = 0;
-          for (int k : order) {
-            if (cls[k] == kClsUnit) nu++;
-            else if (cls[k] == kClsStep) {
-              ns++;
-              ns0 += (G.ops[k].mask & 1u) ? 1 : 0;
-            }
-            else if (cls[k] == kClsUniform) nun++;
-            else nse++;
-          }
-          dg.n_unit = (uint8_t)nu;
-          dg.n_step = (uint8_t)ns;
-          dg.n_step0 = (uint8_t)ns0;
-          dg.n_serial = (uint8_t)(nun + nse);
-          dg.level_end[0] = (uint8_t)nun;
-          const int kept_lanes = G.L + dg.lk;
-          dg.n_units = G.w > kept_lanes ? 1u << (G.w - kept_lanes) : 1u;
-        } else {
-          dg.variant = kVarGeneric;
-          std::stable_sort(order.begin(), order.end(),
-                           [&](int a, int b) { return G.ops[a].level < G.ops[b].level; });
-          int cum = 0;
-          for (int l = 0; l < kMaxLevels; l++) {
-            if (l < G.L) cum += per_level[l];
-            dg.level_end[l] = (uint8_t)cum;
-          }
-          const int bits = kGenRegBits + 6;
-          dg.n_units = G.w > bits ? 1u << (G.w - bits) : 1u;
-        }
-        if (mfma) {
-          // matrix form: m bits, then n bits, then batch bits
-          uint8_t up[32];
-          std::memset(up, 0, sizeof up);
-          int j = 0;
-          for (int q : gsh.mbits) up[j++] = (uint8_t)q;
-          for (int q : gsh.nbits) up[j++] = (uint8_t)q;
-          for (int q : gsh.bbits) up[j++] = (uint8_t)q;
-          dg.n_ubits = 0;
-          s.uperm.insert(s.uperm.end(), up, up + 32);
-        } else {
-          // wave-unit bits, those that large operands lack first (their data
-          // is then reused by neighbouring units of the same block and XCD);
-          // cells: the first rb of that order are the register bits (each
-          // value of an operand lacking them serves several cells), first in
-          // the table
-          const int start = stream ? G.L : (cell ? low : kGenRegBits + 6);
-          std::vector<std::pair<double, int>> sc;
-          for (int b = start; b < G.w; b++) {
-            bool lane = false;
-            for (int j = 0; stream && j < dg.lk; j++) lane |= dg.lkpos[j] == b;
-            if (lane) continue;
-            double miss = 0;
-            for (const Operand &o : G.ops)
-              if (pl.tensors[o.tensor].gate < 0 && !((o.mask >> b) & 1u))
-                miss += std::ldexp(1.0, (int)pl.tensors[o.tensor].vars.size());
-            sc.push_back({-miss, b});
-          }
-          std::stable_sort(sc.begin(), sc.end());
-          std::vector<int> regs;
-          if (cell) {
-            // register bits: one at a time, the kept bit that adds the fewest
-            // loads (an operand is loaded once per distinct value of the cell
-            // bits it holds), ties to the earlier bit of the order above
-            // cell bits held so far: the serial bits still open at the
-            // operand's level
-            std::vector<uint32_t> held(G.ops.size(), 0);
-            for (size_t k = 0; k < G.ops.size(); k++) {
-              const uint32_t m = G.ops[k].mask;
-              const int lv = G.L <= 6 ? 0 : ((m >> 6) & 1u) ? 0 : (G.L > 7 && ((m >> 7) & 1u)) ? 1 : 2;
-              for (int t = lv; t < dg.sl; t++) held[k] += (m >> (6 + t)) & 1u;
-            }
-            for (int j = 0; j < rb; j++) {
-              size_t bi = 0;
-              double best_cost = -1;
-              for (size_t q = 0; q < sc.size(); q++) {
-                double cost = 0;
-                for (size_t k = 0; k < G.ops.size(); k++)
-                  cost += std::ldexp(1.0, (int)held[k] + (int)((G.ops[k].mask >> sc[q].second) & 1u));
-                if (best_cost < 0 || cost < best_cost) {
-                  best_cost = cost;
-                  bi = q;
-                }
-              }
-              for (size_t k = 0; k < G.ops.size(); k++) held[k] += (G.ops[k].mask >> sc[bi].second) & 1u;
-              regs.push_back(sc[bi].second);
-              sc.erase(sc.begin() + bi);
-            }
-            // with serial bits, the operands without them that hold no unit
-            // bit go first: their product over the register cells is formed
-            // once per angle set and reused by every unit (without serial
-            // bits it would span every cell and cost more registers than it
-            // saves)
-            if (dg.sl > 0) {
-              uint32_t unit_mask = 0;
-              for (auto &q : sc) unit_mask |= 1u << q.second;
-              const int last0 = dg.n_step + (dg.sl == 2 ? dg.n_serial : 0);
-              std::stable_partition(order.begin() + last0, order.end(),
-                                    [&](int k) { return (G.ops[k].mask & unit_mask) == 0; });
-              int nfix = 0;
-              for (size_t i = last0; i < order.size(); i++)
-                nfix += (G.ops[order[i]].mask & unit_mask) == 0 ? 1 : 0;
-              dg.n_step0 = (uint8_t)nfix;
-            } else {
-              // without serial bits, the operands holding only lane bits go
-              // first: their product, one value per lane, is formed once per
-              // angle set and multiplies the cells once per unit
-              std::stable_partition(order.begin(), order.end(),
-                                    [&](int k) { return (G.ops[k].mask & ~63u) == 0; });
-              int nfix = 0;
-              for (int k : order) nfix += (G.ops[k].mask & ~63u) == 0 ? 1 : 0;
-              dg.n_step0 = (uint8_t)nfix;
-            }
-            // the cell mapping forms an operand's unit offset from its runs
-            // over the unit bits; past kCellURuns of them, ascending order
-            // (at most one run per two unit bits)
-            int worst = 0;
-            for (const Operand &o : G.ops) {
-              int runs = 0, prev = -2;
-              for (size_t j = 0; j < sc.size(); j++) {
-                const int q = sc[j].second;
-                if (!((o.mask >> q) & 1u)) {
-                  prev = -2;
-                  continue;
-                }
-                const int rank = __builtin_popcount(o.mask & ((1u << q) - 1u));
-                if (rank != prev + 1) runs++;
-                prev = rank;
-              }
-              worst = std::max(worst, runs);
-            }
-            if (worst > kCellURuns)
-              std::sort(sc.begin(), sc.end(),
-                        [](const std::pair<double, int> &a, const std::pair<double, int> &b) {
-                          return a.second < b.second;
-                        });
-          }
-          uint8_t up[32];
-          std::memset(up, 0, sizeof up);
-          const int first = cell ? rb : 0;
-          for (int j = 0; j < first; j++) up[j] = (uint8_t)regs[j];
-          for (size_t j = 0; j < sc.size(); j++) up[first + j] = (uint8_t)sc[j].second;
-          dg.n_ubits = (uint8_t)sc.size();
-          s.uperm.insert(s.uperm.end(), up, up + 32);
-        }
-        for (int k : order) {
-          const Operand &o = G.ops[k];
-          const Tensor &t = pl.tensors[o.tensor];
-          DevOp d;
-          std::memset(&d, 0, sizeof d);
-          if (t.gate >= 0) {
-            // gate operands read the table of the group's own precision
-            d.off = table[G.prec] + gate_offset(lc.gates[t.gate], t.transposed, net->p) * es(G.prec);
-            d.sstride = table_sstride[G.prec];
-            d.dt = (uint8_t)G.prec;
-          } else {
-            d.off = arena + t.offset;
-            d.sstride = arena_sstride;
-            d.dt = (uint8_t)t.prec;
-          }
-          d.mask = o.mask;
-          d.level = (uint8_t)o.level;
-          uint8_t rs[32], rl[32], rd[32];
-          const int nr = mask_runs(o.mask, rs, rl, rd);
-          if (nr > kOpRuns) return set_err(QTN_ERANGE, "operand index set too fragmented");
-          d.nruns = (uint8_t)nr;
-          for (int r = 0; r < nr; r++)
-            d.run[r] = (uint16_t)(rs[r] | (rl[r] << 5) | (rd[r] << 11));
-          d.cls = (uint8_t)cls[k];
-          d.stab = -1;
-          if (stream && cls[k] != kClsUnit) {
-            d.stab = (int32_t)s.stab.size();
-            for (uint32_t st = 0; st < (1u << dg.sl); st++)
-              s.stab.push_back((int32_t)pext32(st << (1 + dg.rls), o.mask));
-          }
-          if (cell) {
-            // cell offsets (cell c: kept bits c % 2^rb, serial bits c / 2^rb),
-            // then the runs giving the unit part of the index from the unit
-            // number
-            d.stab = (int32_t)s.stab.size();
-            const uint8_t *rp = s.uperm.data() + s.uperm.size() - 32;
-            uint32_t cm = 0;
-            // serial cell bit rb + t is union bit 6 + sl - 1 - t (bit 6 the
-            // highest cell bit, summed first)
-            for (int j = 0; j < rb; j++) cm |= ((o.mask >> rp[j]) & 1u) << j;
-            for (int t = 0; t < dg.sl; t++)
-              cm |= ((o.mask >> (6 + dg.sl - 1 - t)) & 1u) << (rb + t);
-            for (uint32_t c = 0; c < (1u << cb); c++) {
-              uint32_t I = 0;
-              for (int j = 0; j < rb; j++) I |= ((c >> j) & 1u) << rp[j];
-              for (int t = 0; t < dg.sl; t++) I |= ((c >> (rb + t)) & 1u) << (6 + dg.sl - 1 - t);
-              s.stab.push_back((int32_t)pext32(I, o.mask));
-            }
-            const uint8_t *up = rp + rb;
-            uint16_t ur[kCellURuns];
-            std::memset(ur, 0, sizeof ur);
-            int nur = 0;
-            for (int j = 0; j < dg.n_ubits;) {
-              const int q = up[j];
-              if (!((o.mask >> q) & 1u)) {
-                j++;
-                continue;
-              }
-              const int dst = __builtin_popcount(o.mask & ((1u << q) - 1u));
-              int len = 1;
-              while (j + len < dg.n_ubits && ((o.mask >> up[j + len]) & 1u) &&
-                     __builtin_popcount(o.mask & ((1u << up[j + len]) - 1u)) == dst + len)
-                len++;
-              if (nur == kCellURuns) return set_err(QTN_ERANGE, "cell mapping: unit runs");
-              ur[nur++] = (uint16_t)(j | (len << 5) | (dst << 11));
-              j += len;
-            }
-            dg.n_unit = (uint8_t)std::max<int>(dg.n_unit, nur);
-            for (int w = 0; w < kCellURuns / 2; w++)
-              s.stab.push_back((int32_t)((uint32_t)ur[2 * w] | ((uint32_t)ur[2 * w + 1] << 16)));
-            s.stab.push_back((int32_t)cm);
-          }
-          if (d.dt != dg.prec) dg.cvt = 1;
-          s.ops.push_back(d);
-        }
-        double gb = in_bytes + es(G.prec) * std::ldexp(1.0, G.w - G.L), gf = 0;
-        for (int l = 0; l < G.L; l++) {
-          int factors = per_level[l] + (l > 0 ? 1 : 0);
-          gf += std::ldexp(1.0, G.w - l) * 6.0 * std::max(0, factors - 1) +
-                std::ldexp(1.0, G.w - l - 1) * 2.0;
-        }
+        env.is_small = is_small;
+        env.persistent = persistent;
+        DevGroup dg;
+        double gb = 0, gf = 0;
+        const int rc = describe_group(G, pl, env, s, &dg, &gb, &gf);
+        if (rc) return rc;
         const int gid = (int)s.groups.size();
         s.groups.push_back(dg);
         s.group_cone.push_back(s.n_cones);
@@ -2029,6 +2075,182 @@ int qtn_plan_order(const qtn_network *net, int64_t edge, int32_t *order_out) {
   std::copy(o.begin(), o.end(), order_out);
   return QTN_OK;
 }
+
+}  // extern "C"
+
+// One bucket contraction of caller-given tensors: a one-group schedule whose
+// descriptors address the caller's data buffer.
+struct qtn_bucket {
+  Schedule s;              // one group; s.desc_blob holds its descriptors
+  DevGroup hg;             // host copy of the group record
+  size_t off_groups = 0, off_ops = 0, off_stab = 0, off_uperm = 0;
+  int64_t data_bytes = 0;  // end of the last tensor in the data buffer
+  double bytes = 0, flops = 0;
+};
+
+namespace {
+
+// Uploads the bucket's descriptors to `desc` (device) and runs its kernel
+// on the caller's data buffer.
+int bucket_run(const qtn_bucket *b, void *d_data, size_t data_bytes, char *desc, hipStream_t st) {
+  if ((int64_t)data_bytes < b->data_bytes)
+    return set_err(QTN_ENOMEM, "data buffer smaller than the bucket's tensors");
+  if (((uintptr_t)d_data & 255u) != 0) return set_err(QTN_EINVAL, "data buffer not 256-byte aligned");
+  QTN_HIP(hipMemcpyAsync(desc, b->s.desc_blob.data(), b->s.desc_blob.size(), hipMemcpyHostToDevice, st));
+  QTN_HIP(launch_wide_group(b->hg, d_data, (const DevGroup *)(desc + b->off_groups),
+                            (const DevOp *)(desc + b->off_ops), (const int32_t *)(desc + b->off_stab),
+                            (const uint8_t *)(desc + b->off_uperm), 0, 1, st));
+  return QTN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int qtn_bucket_plan(int32_t n_ops, const int32_t *ranks, const int32_t *labels,
+                    const int64_t *offsets, int32_t n_out, const int32_t *out_labels,
+                    int64_t out_offset, int32_t precision, int32_t variant, int32_t knob,
+                    qtn_bucket **out) {
+  if (!ranks || !labels || !offsets || !out || (n_out > 0 && !out_labels))
+    return set_err(QTN_EINVAL, "NULL argument");
+  if (n_ops < 1 || n_ops > 64) return set_err(QTN_EINVAL, "n_ops must be in 1..64");
+  if (n_out < 0 || n_out > kMaxWidth) return set_err(QTN_EINVAL, "n_out must be in 0..32");
+  if (precision != QTN_C128 && precision != QTN_C64)
+    return set_err(QTN_EINVAL, "precision must be QTN_C128 or QTN_C64");
+  if (variant < 0 || variant > 4) return set_err(QTN_EINVAL, "variant must be 0..4");
+  try {
+    // union order: the summed labels ascending, then the output labels
+    std::map<int32_t, int> seen;  // label -> union position (-1 until placed)
+    int64_t n_lab = 0;
+    for (int k = 0; k < n_ops; k++) {
+      if (ranks[k] < 0 || ranks[k] > kMaxWidth) return set_err(QTN_EINVAL, "operand rank out of range");
+      for (int j = 0; j < ranks[k]; j++) seen[labels[n_lab + j]] = -1;
+      n_lab += ranks[k];
+    }
+    for (int j = 0; j < n_out; j++) {
+      auto it = seen.find(out_labels[j]);
+      if (it == seen.end()) return set_err(QTN_EINVAL, "output label held by no operand");
+      if (it->second != -1) return set_err(QTN_EINVAL, "repeated output label");
+      it->second = -2;  // kept
+    }
+    int L = 0;
+    for (auto &kv : seen)
+      if (kv.second == -1) kv.second = L++;
+    const int w = L + n_out;
+    if (L < 1) return set_err(QTN_EINVAL, "no summed label: a bucket sums at least one index");
+    if (L > kMaxLevels) return set_err(QTN_ERANGE, "more than 8 summed labels");
+    if (w > kMaxWidth) return set_err(QTN_ERANGE, "union of more than 32 labels");
+    for (int j = 0; j < n_out; j++) seen[out_labels[j]] = L + j;
+    auto qb = std::make_unique<qtn_bucket>();
+    const int64_t es = precision == QTN_C64 ? 8 : 16;
+    ConePlan pl;
+    Group G;
+    G.w = w;
+    G.L = L;
+    G.prec = (int8_t)precision;
+    std::vector<std::pair<int64_t, int64_t>> ranges;  // byte ranges of the inputs
+    n_lab = 0;
+    for (int k = 0; k < n_ops; k++) {
+      uint32_t mask = 0;
+      int prev = -1;
+      for (int j = 0; j < ranks[k]; j++) {
+        const int pos = seen[labels[n_lab + j]];
+        if (pos <= prev)
+          return set_err(QTN_EINVAL, "operand " + std::to_string(k) +
+                                         ": labels repeated or not in union order (summed labels "
+                                         "ascending, then the output labels in order)");
+        prev = pos;
+        mask |= 1u << pos;
+      }
+      n_lab += ranks[k];
+      const int64_t size = es << ranks[k];
+      if (offsets[k] < 0 || offsets[k] % es) return set_err(QTN_EINVAL, "operand offset not aligned");
+      ranges.push_back({offsets[k], offsets[k] + size});
+      qb->data_bytes = std::max(qb->data_bytes, offsets[k] + size);
+      Tensor t;
+      t.vars.assign(ranks[k], 0);
+      t.offset = offsets[k];
+      t.prec = (int8_t)precision;
+      pl.tensors.push_back(t);
+      // level: after the summed labels below the operand's lowest one
+      const uint32_t summed = mask & ((1u << L) - 1u);
+      const int level = summed ? __builtin_ctz(summed) : L - 1;
+      G.ops.push_back({k, mask, level});
+    }
+    std::stable_sort(G.ops.begin(), G.ops.end(),
+                     [](const Operand &a, const Operand &b) { return a.level < b.level; });
+    const int64_t osize = es << n_out;
+    if (out_offset < 0 || out_offset % es) return set_err(QTN_EINVAL, "output offset not aligned");
+    for (auto &r : ranges)
+      if (r.first < out_offset + osize && out_offset < r.second)
+        return set_err(QTN_EINVAL, "output overlaps an operand");
+    qb->data_bytes = std::max(qb->data_bytes, out_offset + osize);
+    Tensor to;
+    to.vars.assign(n_out, 0);
+    to.offset = out_offset;
+    to.prec = (int8_t)precision;
+    pl.tensors.push_back(to);
+    G.out_tensor = n_ops;
+    GroupEnv env;
+    env.out_off = out_offset;
+    env.var_req = variant;
+    env.rls_req = knob > 0 ? knob : (variant == 4 ? kCellRuleCB : 2);
+    Schedule &s = qb->s;
+    int rc = describe_group(G, pl, env, s, &qb->hg, &qb->bytes, &qb->flops);
+    if (rc) return rc;
+    if (qb->hg.n_units == 0 || qb->hg.n_units > 0x7FFFFFFFu)
+      return set_err(QTN_ERANGE, "too many units for one launch");
+    qb->hg.op_begin = 0;
+    s.groups.assign(1, qb->hg);
+    qb->off_groups = 0;
+    qb->off_ops = align_up(sizeof(DevGroup), 256);
+    qb->off_stab = align_up(qb->off_ops + sizeof(DevOp) * s.ops.size(), 256);
+    qb->off_uperm = align_up(qb->off_stab + sizeof(int32_t) * s.stab.size(), 256);
+    s.desc_blob.assign(align_up(qb->off_uperm + s.uperm.size(), 256), 0);
+    std::memcpy(s.desc_blob.data() + qb->off_groups, s.groups.data(), sizeof(DevGroup));
+    std::memcpy(s.desc_blob.data() + qb->off_ops, s.ops.data(), sizeof(DevOp) * s.ops.size());
+    if (!s.stab.empty())
+      std::memcpy(s.desc_blob.data() + qb->off_stab, s.stab.data(), sizeof(int32_t) * s.stab.size());
+    std::memcpy(s.desc_blob.data() + qb->off_uperm, s.uperm.data(), s.uperm.size());
+    *out = qb.release();
+    return QTN_OK;
+  } catch (...) {
+    return exception_status();
+  }
+}
+
+int qtn_bucket_get_info(const qtn_bucket *b, qtn_bucket_info *out) {
+  if (!b || !out) return set_err(QTN_EINVAL, "NULL argument");
+  qtn_bucket_info r;
+  std::memset(&r, 0, sizeof r);
+  r.w = b->hg.w;
+  r.L = b->hg.L;
+  r.n_ops = b->hg.n_ops;
+  r.variant = b->hg.variant;
+  r.knob = b->hg.variant == kVarStream || b->hg.variant == kVarCell ? b->hg.rls : 0;
+  r.serial = b->hg.variant == kVarStream || b->hg.variant == kVarCell ? b->hg.sl : 0;
+  r.n_units = b->hg.n_units;
+  r.bytes = b->bytes;
+  r.flops = b->flops;
+  r.workspace_bytes = b->s.desc_blob.size();
+  r.data_bytes = b->data_bytes;
+  *out = r;
+  return QTN_OK;
+}
+
+int qtn_bucket_contract(const qtn_bucket *b, void *d_data, size_t data_bytes, void *d_workspace,
+                        size_t ws_bytes, void *hip_stream) {
+  if (!b || !d_data || !d_workspace) return set_err(QTN_EINVAL, "NULL argument");
+  if (ws_bytes < b->s.desc_blob.size()) return set_err(QTN_ENOMEM, "workspace too small");
+  if (((uintptr_t)d_workspace & 255u) != 0) return set_err(QTN_EINVAL, "workspace not 256-byte aligned");
+  try {
+    return bucket_run(b, d_data, data_bytes, (char *)d_workspace, (hipStream_t)hip_stream);
+  } catch (...) {
+    return exception_status();
+  }
+}
+
+void qtn_bucket_free(qtn_bucket *b) { delete b; }
 
 int qtn_bucket_widths(const qtn_network *net, int64_t edge, int32_t *widths_out) {
   if (!net || !widths_out) return set_err(QTN_EINVAL, "NULL argument");

@@ -37,6 +37,7 @@ def test_free_functions_accept_null(qtn):
     lib = _capi.lib()
     lib.qtn_network_free(None)
     lib.qtn_costmodel_free(None)
+    lib.qtn_bucket_free(None)
 
 
 def test_minfill_matches_oracle_rule(qtn, orc):
@@ -374,3 +375,46 @@ def test_angle_batch_workspace_and_validation(qtn):
                                  en.ctypes.data_as(pd), None)
     assert rc == -1 and "finite" in qtn.qtn_last_error() and en[0] == 7.0
     net.close()
+
+
+def test_bucket_plan_shapes_and_validation(qtn):
+    """Single-bucket plans (no launch): union order, widths, algorithmic
+    bytes and flops, mapping choice, and every rejected input."""
+    # abcd,bcdf->acf with 2-bit indices: 4 summed labels (b, d), 6 kept
+    a, b, c, d, f = ([2 * i, 2 * i + 1] for i in range(5))
+    bk = qtn.Bucket([b + d + a + c, b + d + c + f], a + c + f)
+    info = bk.info()
+    assert (info["w"], info["L"], info["n_ops"]) == (10, 4, 2)
+    assert info["bytes"] == 16 * (2 ** 8 + 2 ** 8 + 2 ** 6)
+    # level 0: 2^10 products (6 flops) and 2^9 adds (2); levels 1..3: adds only
+    assert info["flops"] == 2 ** 10 * 6 + sum(2 ** (10 - l - 1) * 2 for l in range(4))
+    assert info["data_bytes"] == 2 * 4096 + 1024 and info["workspace_bytes"] % 256 == 0
+    bk.close()
+    # a wide bucket takes the cell mapping under the width rule; forcing the
+    # generic mapping is honoured
+    ops = [list(range(0, 20)), [0, 1] + list(range(20, 26))]
+    assert qtn.Bucket(ops, list(range(2, 26))).info()["variant"] == 3
+    assert qtn.Bucket(ops, list(range(2, 26)), variant=1).info()["variant"] == 0
+    # the matrix form only in complex64
+    mm = [[0, 1, 2, 3, 4, 5], [0, 1, 2, 6, 7, 8]]
+    assert qtn.Bucket(mm, [3, 4, 5, 6, 7, 8], precision=qtn.QTN_C64, variant=3).info()["variant"] == 2
+    assert qtn.Bucket(mm, [3, 4, 5, 6, 7, 8], precision=qtn.QTN_C128, variant=3).info()["variant"] != 2
+    bad = [
+        (([[0, 1]], [0, 1]), "no summed"),            # nothing summed
+        (([[0, 1, 2], [1, 2, 3]], [0, 3]), "union order"),
+        (([[0, 0]], []), "union order"),              # repeated label
+        (([[0, 1]], [2]), "no operand"),
+        (([[0, 1]], [1, 1]), "repeated output"),
+        (([list(range(9)) + [9]], [9]), "8 summed"),
+        (([list(range(33))], list(range(1, 33))), "rank"),
+    ]
+    for (ops, out), msg in bad:
+        with pytest.raises(qtn.QtnError) as ei:
+            qtn.Bucket(ops, out)
+        assert msg in str(ei.value), (ops, out, str(ei.value))
+    with pytest.raises(qtn.QtnError, match="overlaps"):
+        qtn.Bucket([[0, 1], [0, 2]], [1, 2], offsets=[0, 256], out_offset=256)
+    with pytest.raises(qtn.QtnError, match="aligned"):
+        qtn.Bucket([[0, 1], [0, 2]], [1, 2], offsets=[8, 512], out_offset=1024)
+    with pytest.raises(qtn.QtnError, match="precision"):
+        qtn.Bucket([[0, 1]], [1], precision=qtn.QTN_MIXED)
