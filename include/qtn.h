@@ -507,6 +507,21 @@ int qtn_bucket_get_info(const qtn_bucket *b, qtn_bucket_info *out);
 int qtn_bucket_contract(const qtn_bucket *b, void *d_data, size_t data_bytes,
                         void *d_workspace, size_t ws_bytes, void *hip_stream);
 
+/*
+ * qtn_bucket_contract without a workspace argument and without any device
+ * allocation, for callers that cannot allocate device memory (tight serving
+ * or benchmark loops, harnesses that forbid hipMalloc).  The descriptors go
+ * into a fixed device array inside the library (16 KiB, one per GPU, held
+ * until the process ends) instead of a caller workspace; nothing is
+ * allocated or freed.  Every call on a GPU shares that GPU's array: calls
+ * that overlap on one GPU (on different streams, or from several threads)
+ * race and must be serialised by the caller; calls on one stream are ordered.
+ * Errors: QTN_ERANGE when the bucket's descriptors (workspace_bytes of
+ * qtn_bucket_get_info) exceed 16 KiB; otherwise as qtn_bucket_contract.
+ */
+int qtn_bucket_contract_noalloc(const qtn_bucket *b, void *d_data, size_t data_bytes,
+                                void *hip_stream);
+
 void qtn_bucket_free(qtn_bucket *b);
 
 const char *qtn_last_error(void);

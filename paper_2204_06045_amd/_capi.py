@@ -44,7 +44,7 @@ EXPORTS = (
     "qtn_costmodel_workspace", "qtn_costmodel_train", "qtn_costmodel_predict",
     "qtn_costmodel_grad", "qtn_costmodel_adam_step", "qtn_apply_costmodel",
     "qtn_costmodel_free", "qtn_bucket_plan", "qtn_bucket_get_info", "qtn_bucket_contract",
-    "qtn_bucket_free",
+    "qtn_bucket_contract_noalloc", "qtn_bucket_free",
 )
 MLP_PARAMS = 5508
 MLP_OUT = 4  # predicted variants: workgroup, streaming, generic, matrix form
@@ -185,6 +185,7 @@ def lib():
                                       ctypes.POINTER(P)]
         L.qtn_bucket_get_info.argtypes = [P, ctypes.POINTER(qtn_bucket_info)]
         L.qtn_bucket_contract.argtypes = [P, P, sz, P, sz, P]
+        L.qtn_bucket_contract_noalloc.argtypes = [P, P, sz, P]
         L.qtn_bucket_free.argtypes = [P]
         L.qtn_bucket_free.restype = None
         for name in EXPORTS:

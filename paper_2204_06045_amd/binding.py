@@ -28,7 +28,8 @@ __all__ = [
     "qtn_tune_picks", "qtn_set_tune_picks", "qtn_angles_workspace", "qtn_contract_angles",
     "qtn_gradient_workspace", "qtn_energy_gradient",
     "Network", "CostModel", "qtn_apply_costmodel", "workspace", "stream_handle",
-    "qtn_bucket_plan", "qtn_bucket_get_info", "qtn_bucket_contract", "qtn_bucket_free",
+    "qtn_bucket_plan", "qtn_bucket_get_info", "qtn_bucket_contract",
+    "qtn_bucket_contract_noalloc", "qtn_bucket_free",
     "Bucket",
 ]
 
@@ -567,6 +568,11 @@ def qtn_bucket_contract(b, data, ws, stream=None):
                                     stream_handle(stream)))
 
 
+def qtn_bucket_contract_noalloc(b, data, stream=None):
+    check(lib().qtn_bucket_contract_noalloc(b, ctypes.c_void_p(data.data_ptr()), data.numel(),
+                                            stream_handle(stream)))
+
+
 def qtn_bucket_free(b):
     lib().qtn_bucket_free(b)
 
@@ -606,6 +612,11 @@ class Bucket:
     def contract(self, data, ws=None, stream=None):
         """Queue the contraction on the stream (asynchronous)."""
         qtn_bucket_contract(self.h, data, self.workspace() if ws is None else ws, stream)
+
+    def contract_noalloc(self, data, stream=None):
+        """Queue the contraction with the descriptors in the library's fixed
+        device array (no workspace, no allocation)."""
+        qtn_bucket_contract_noalloc(self.h, data, stream)
 
     def close(self):
         if self.h:

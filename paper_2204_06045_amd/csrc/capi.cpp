@@ -2250,6 +2250,22 @@ int qtn_bucket_contract(const qtn_bucket *b, void *d_data, size_t data_bytes, vo
   }
 }
 
+int qtn_bucket_contract_noalloc(const qtn_bucket *b, void *d_data, size_t data_bytes,
+                                void *hip_stream) {
+  if (!b || !d_data) return set_err(QTN_EINVAL, "NULL argument");
+  if (b->s.desc_blob.size() > kScratchBytes)
+    return set_err(QTN_ERANGE, "bucket descriptors (" + std::to_string(b->s.desc_blob.size()) +
+                                   " bytes) exceed the " + std::to_string(kScratchBytes) +
+                                   "-byte device scratch");
+  try {
+    void *scr = nullptr;
+    QTN_HIP(scratch_address(&scr));
+    return bucket_run(b, d_data, data_bytes, (char *)scr, (hipStream_t)hip_stream);
+  } catch (...) {
+    return exception_status();
+  }
+}
+
 void qtn_bucket_free(qtn_bucket *b) { delete b; }
 
 int qtn_bucket_widths(const qtn_network *net, int64_t edge, int32_t *widths_out) {

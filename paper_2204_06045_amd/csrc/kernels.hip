@@ -1475,4 +1475,30 @@ hipError_t launch_reduce(int prec, const void *data, int64_t scalar_off, int64_t
   return hipGetLastError();
 }
 
+// Descriptor scratch of the allocation-free single-bucket entry point: a
+// file-scope device array, one copy per GPU, held until the process ends.
+// In host code `scratch` names a host-side stand-in; kernels get the device
+// address looked up below.
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+hipError_t scratch_address(void **out) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void *addr[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!addr[dev]) {
+    // once per device, with that device current
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = p;
+  }
+  *out = addr[dev];
+  return hipSuccess;
+}
+
 }  // namespace qtn

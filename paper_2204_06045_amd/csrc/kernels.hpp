@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
 #include <cstdint>
 
 #include "device.hpp"
@@ -86,5 +87,13 @@ hipError_t launch_reduce(int prec, const void *data, int64_t scalar_off,
                          const int *net_cone_begin, int n_cones, int n_nets, int n_sets,
                          double *res, hipStream_t s);
 
+
+// Bytes of the device scratch array that the allocation-free bucket entry
+// point copies its descriptors into.
+constexpr size_t kScratchBytes = 16384;
+
+// Device address of that array on the current device (looked up once per
+// device with hipGetSymbolAddress; never the host-side name).
+hipError_t scratch_address(void **out);
 
 }  // namespace qtn
