@@ -282,43 +282,39 @@ def host_facts():
     return {"logical_cpus": os.cpu_count(), "ram_bytes": ram}
 
 
-def cpu_baseline(inst, seconds):
-    """FP64 oracle on a bounded sample of light cones, scaled by cost."""
+def cpu_baseline(inst, threads=None):
+    """One whole evaluation of the FP64 oracle on the host cores: every light
+    cone of angle set 0, one oracle call per cone on a pool of host threads
+    (heaviest cones first), timed as a whole (the multi-core rate) and cone
+    by cone (the sum of the per-cone times is one core's time for the
+    evaluation).  Nothing is sampled or scaled."""
+    import concurrent.futures as cf
+
     import oracle
     n, edges, p = inst["n"], inst["edges"], inst["p"]
     g, b = inst["angles"][0]
     m = len(edges)
-    cost = [sum(2.0 ** int(w) for w in oracle.edge_widths(n, edges, k, p) if w)
-            for k in range(m)]
-    total = sum(cost)
-    cheapest = min(range(m), key=lambda k: cost[k])
+    threads = threads or max(1, min(os.cpu_count() or 1, 16))
+    cost = [sum(2.0 ** int(w) for w in oracle.edge_widths(n, edges, k, p) if w) for k in range(m)]
+    order = sorted(range(m), key=lambda k: -cost[k])
+
+    def one(k):
+        t0 = time.perf_counter()
+        z, _ = oracle.energy(n, edges, g, b, threads=1, edge_list=[k])
+        return k, z[0], time.perf_counter() - t0
+
     t0 = time.perf_counter()
-    oracle.energy(n, edges, g, b, threads=1, edge_list=[cheapest])
-    rate = cost[cheapest] / max(time.perf_counter() - t0, 1e-6)  # ops/s/thread
-    threads = max(1, min(os.cpu_count() or 1, 16))
-    import qaoa_synth as qs
-    r = qs.Rng(2024)
-    order = list(range(m))
-    for i in range(m - 1, 0, -1):
-        j = r.below(i + 1)
-        order[i], order[j] = order[j], order[i]
-    sample, acc = [], 0.0
-    for k in order:
-        if cost[k] / rate > seconds / 2:
-            continue
-        if acc + cost[k] > seconds * rate * threads and sample:
-            break
-        sample.append(k)
-        acc += cost[k]
-    t0 = time.perf_counter()
-    oracle.energy(n, edges, g, b, threads=threads, edge_list=sample)
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        done = list(ex.map(one, order))
     wall = time.perf_counter() - t0
-    frac = acc / total
-    return {"value": frac / wall, "unit": "evals/s", "cores": threads, "kind": "oracle",
-            "value_1core": rate / total, "host": host_facts(),
-            "sample": (f"{len(sample)} of {m} light cones ({100 * frac:.2f}% of the "
-                       f"evaluation's sum of 2^width) on {threads} threads in "
-                       f"{wall:.1f} s, scaled to one full evaluation by that cost share")}
+    per_cone = sum(d[2] for d in done)
+    energy = 0.5 * m - 0.5 * sum(d[1].real for d in done)
+    return {"value": 1.0 / wall, "unit": "evals/s", "cores": threads, "kind": "oracle",
+            "value_1core": 1.0 / per_cone, "host": host_facts(), "energy": float(energy),
+            "sample": (f"one whole evaluation: all {m} light cones of angle set 0, one "
+                       f"single-threaded oracle call per cone on {threads} host threads, "
+                       f"{wall:.1f} s wall; value_1core = 1 / the sum of the per-cone times "
+                       f"({per_cone:.1f} s)")}
 
 
 def batch_golden_check(insts, nets, zz, en, master_seed, count):
@@ -584,6 +580,77 @@ def run_costmodel(Q, torch, prec=1, epochs=600, lr=3e-3, reps=3):
             "precision": "c64" if prec == 1 else "c128"}
 
 
+def run_micro(Q, torch, reps=5, n_random=8, seed=2204):
+    """Single-bucket probes of the bucket kernels (Sec. II-E synthetic
+    benchmarks, Tab. III), each one bucket of binary indices on the network
+    path's kernels (qtn_bucket_*): matrix products (k summed labels), the
+    fixed abcd,bcdf->acf contraction (each index 2^4 as 4 labels) and random
+    two-operand contractions of 16..25 distinct labels with 1..8 summed.
+    Kernel time from events attached to the dispatch, the median of `reps`
+    runs after one warm-up; inputs seeded normal values.  Each row carries
+    algorithmic GB/s, true and paper-convention (8 * 2^labels) flop rates and
+    the fraction of the roof its arithmetic intensity implies."""
+    import numpy as np
+    import qaoa_synth as qs
+
+    def probe(ops, out, prec, variant=0):
+        b = Q.Bucket(ops, out, precision=prec, variant=variant)
+        info = b.info()
+        data = torch.empty(info["data_bytes"], dtype=torch.uint8, device="cuda")
+        g = torch.Generator(device="cuda")
+        g.manual_seed(seed)
+        data.view(torch.float64 if prec == Q.QTN_C128 else torch.float32).normal_(generator=g)
+        b.contract_timed(data)
+        ms = float(np.median([b.contract_timed(data) for _ in range(reps)]))
+        b.close()
+        del data
+        gbs = info["bytes"] / ms / 1e6
+        tflops = info["flops"] / ms / 1e9
+        # complex64 matrix form runs on the FP32 matrix cores; the rest on
+        # FP64 (complex128) or FP32 (complex64) vector ALUs
+        fpeak = FP64_PEAK_TFLOPS if prec == Q.QTN_C128 else FP32_PEAK_TFLOPS
+        bound = "hbm" if info["flops"] / info["bytes"] < fpeak * 1e12 / (HBM_PEAK_GBS * 1e9) else "alu"
+        frac = gbs / HBM_PEAK_GBS if bound == "hbm" else tflops / fpeak
+        return {"w": info["w"], "L": info["L"], "mapping": ["generic", "streaming", "matrix form",
+                                                            "cells"][info["variant"]],
+                "kernel_ms": ms, "gbs": gbs, "tflops": tflops,
+                "paper_gflops": 8.0 * 2.0 ** info["w"] / ms / 1e6,
+                "bound": bound, "frac": frac}
+
+    rows = {}
+    for name, prec in (("c128", Q.QTN_C128), ("c64", Q.QTN_C64)):
+        k = list(range(8))
+        for mb, nb in ((8, 8), (11, 12)):
+            m_ = list(range(8, 8 + mb))
+            n_ = list(range(8 + mb, 8 + mb + nb))
+            shape = f"{1 << mb}x{1 << nb}x256"
+            rows[f"matmul_{shape}_{name}"] = probe([k + m_, k + n_], m_ + n_, prec)
+            if prec == Q.QTN_C64:
+                rows[f"matmul_{shape}_{name}_matrix_form"] = probe([k + m_, k + n_], m_ + n_, prec,
+                                                                    variant=3)
+        a, bb, c, d, f = ([4 * i + j for j in range(4)] for i in range(5))
+        rows[f"tncontract_fixed_n16_{name}"] = probe([bb + d + a + c, bb + d + c + f], a + c + f, prec)
+        r = qs.Rng(seed)
+        rnd = []
+        for _ in range(n_random):
+            n_lab = 16 + r.below(10)
+            n_sum = 1 + r.below(8)
+            summed = list(range(n_sum))
+            kept = list(range(n_sum, n_lab))
+            # each kept label in one operand or both; every summed label in both
+            side = [r.below(3) for _ in kept]
+            A = summed + [l for l, sd in zip(kept, side) if sd != 1]
+            B = summed + [l for l, sd in zip(kept, side) if sd != 0]
+            rnd.append(probe([A, B], kept, prec))
+        rows[f"tncontract_random_{name}"] = {
+            "cases": n_random, "labels": [x["w"] for x in rnd],
+            "median_gbs": float(np.median([x["gbs"] for x in rnd])),
+            "median_frac": float(np.median([x["frac"] for x in rnd])),
+            "median_paper_gflops": float(np.median([x["paper_gflops"] for x in rnd])),
+            "rows": rnd}
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -605,7 +672,8 @@ def main():
     ap.add_argument("--angle-batch", type=int, default=32,
                     help="angle sets evaluated per step in one pass (1: one call per set)")
     ap.add_argument("--variants", type=int, default=1, help="also time the other rows")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="host threads of the oracle baseline (0: all, at most 16)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", type=int, default=1,
                     help="tune the kernel choice per group after planning (stored choices "
@@ -728,6 +796,9 @@ def main():
         log("variant seeds (graph seeds 0-4, width rule, 32-set batches)")
         variants["seeds_c128"] = run_seeds(Q, torch)
         torch.cuda.empty_cache()
+        log("variant micro (single-bucket probes)")
+        variants["micro"] = run_micro(Q, torch)
+        torch.cuda.empty_cache()
         log("variant batch64_c64 (persistent)")
         variants["batch64_c64"] = run_batch(Q, torch, 5, 1, executor=0,
                                             autotune=bool(args.autotune))
@@ -736,7 +807,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        cpu = cpu_baseline(inst, args.cpu_seconds)
+        cpu = cpu_baseline(inst, args.cpu_threads or None)
 
     line = {
         "metric": METRIC,
