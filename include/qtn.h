@@ -88,7 +88,14 @@ typedef struct qtn_config {
     int32_t spin_limit;  /* persistent executors: polls before a barrier or
                             dependency wait gives up with QTN_EDEVICE [2^22] */
     int32_t mixed_width; /* QTN_MIXED: narrowest group run in complex64 [18] */
-    int32_t reserved[5];
+    int32_t slice_width; /* >0: index slicing for every light cone whose
+                            widest bucket exceeds this width: up to 10 of its
+                            variables are fixed (greedily, from its widest
+                            bucket, until the width fits or nothing more can
+                            be fixed), each value combination (a slice) is
+                            contracted in turn on one arena and e_jk is the
+                            FP64 sum of the slices' scalars; 0 off [0]      */
+    int32_t reserved[4];
 } qtn_config;
 
 /*
@@ -429,9 +436,17 @@ typedef struct qtn_plan_stats {
     int64_t n_over4g_generic; /* of those, groups run by the generic mapping:
                            * all of them, as the streaming and cell mappings
                            * use 32-bit byte offsets within an operand     */
+    int64_t n_sliced;     /* light cones planned with index slicing          */
+    int64_t n_slices;     /* slices over all light cones (1 per unsliced one) */
 } qtn_plan_stats;
 
 int qtn_get_plan_stats(const qtn_network *net, qtn_plan_stats *out);
+
+/* Variables of one light cone fixed by index slicing (slice bit k is
+ * vars_out[k]); *n_out receives their count (0: not sliced).  vars_out holds
+ * up to `cap` entries (10 suffice). */
+int qtn_slice_vars(const qtn_network *net, int64_t edge, int32_t cap, int32_t *vars_out,
+                   int32_t *n_out);
 
 /* Width of each bucket of one light cone in the planned order, indexed by
  * elimination position (0 for an empty bucket).  widths_out [n_vars]. */
@@ -506,6 +521,13 @@ int qtn_bucket_get_info(const qtn_bucket *b, qtn_bucket_info *out);
  */
 int qtn_bucket_contract(const qtn_bucket *b, void *d_data, size_t data_bytes,
                         void *d_workspace, size_t ws_bytes, void *hip_stream);
+
+/* qtn_bucket_contract with start and stop events attached to the kernel's
+ * dispatch: blocks until the kernel has run and stores its duration in
+ * milliseconds (the descriptor upload is not included). */
+int qtn_bucket_contract_timed(qtn_bucket *b, void *d_data, size_t data_bytes,
+                              void *d_workspace, size_t ws_bytes, void *hip_stream,
+                              double *kernel_ms);
 
 /*
  * qtn_bucket_contract without a workspace argument and without any device

@@ -37,14 +37,14 @@ EXPORTS = (
     "qtn_batch_workspace", "qtn_contract_timed", "qtn_get_plan_stats",
     "qtn_angles_workspace", "qtn_contract_angles", "qtn_gradient_workspace",
     "qtn_energy_gradient",
-    "qtn_bucket_widths", "qtn_network_free", "qtn_last_error", "qtn_launch_log",
+    "qtn_bucket_widths", "qtn_slice_vars", "qtn_network_free", "qtn_last_error", "qtn_launch_log",
     "qtn_plan_order", "qtn_autotune", "qtn_tune_angles_workspace", "qtn_autotune_angles",
     "qtn_tune_log", "qtn_tune_picks", "qtn_set_tune_picks",
     "qtn_costmodel_create", "qtn_costmodel_params", "qtn_costmodel_normalization",
     "qtn_costmodel_workspace", "qtn_costmodel_train", "qtn_costmodel_predict",
     "qtn_costmodel_grad", "qtn_costmodel_adam_step", "qtn_apply_costmodel",
     "qtn_costmodel_free", "qtn_bucket_plan", "qtn_bucket_get_info", "qtn_bucket_contract",
-    "qtn_bucket_contract_noalloc", "qtn_bucket_free",
+    "qtn_bucket_contract_noalloc", "qtn_bucket_contract_timed", "qtn_bucket_free",
 )
 MLP_PARAMS = 5508
 MLP_OUT = 4  # predicted variants: workgroup, streaming, generic, matrix form
@@ -56,7 +56,8 @@ class qtn_config(ctypes.Structure):
                 ("eager", ctypes.c_int32), ("lane_sum_bits", ctypes.c_int32),
                 ("variant", ctypes.c_int32), ("order_trials", ctypes.c_int32),
                 ("executor", ctypes.c_int32), ("spin_limit", ctypes.c_int32),
-                ("mixed_width", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("mixed_width", ctypes.c_int32), ("slice_width", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 class qtn_timing(ctypes.Structure):
@@ -99,7 +100,8 @@ class qtn_plan_stats(ctypes.Structure):
                 ("flops", ctypes.c_double), ("paper_flops", ctypes.c_double),
                 ("workspace", ctypes.c_size_t), ("n_matrix", ctypes.c_int64),
                 ("n_cell", ctypes.c_int64), ("n_stream", ctypes.c_int64),
-                ("n_over4g", ctypes.c_int64), ("n_over4g_generic", ctypes.c_int64)]
+                ("n_over4g", ctypes.c_int64), ("n_over4g_generic", ctypes.c_int64),
+                ("n_sliced", ctypes.c_int64), ("n_slices", ctypes.c_int64)]
 
 
 class qtn_bucket_info(ctypes.Structure):
@@ -149,6 +151,7 @@ def lib():
                                          ctypes.POINTER(qtn_timing)]
         L.qtn_get_plan_stats.argtypes = [P, ctypes.POINTER(qtn_plan_stats)]
         L.qtn_bucket_widths.argtypes = [P, i64, pi32]
+        L.qtn_slice_vars.argtypes = [P, i64, i32, pi32, pi32]
         L.qtn_plan_order.argtypes = [P, i64, pi32]
         L.qtn_autotune.argtypes = [P, P, ctypes.c_size_t, P, ctypes.POINTER(qtn_tune_report)]
         L.qtn_tune_angles_workspace.argtypes = [P, i32, ctypes.POINTER(ctypes.c_size_t)]
@@ -186,6 +189,7 @@ def lib():
         L.qtn_bucket_get_info.argtypes = [P, ctypes.POINTER(qtn_bucket_info)]
         L.qtn_bucket_contract.argtypes = [P, P, sz, P, sz, P]
         L.qtn_bucket_contract_noalloc.argtypes = [P, P, sz, P]
+        L.qtn_bucket_contract_timed.argtypes = [P, P, sz, P, sz, P, pd]
         L.qtn_bucket_free.argtypes = [P]
         L.qtn_bucket_free.restype = None
         for name in EXPORTS:

@@ -22,14 +22,14 @@ __all__ = [
     "QTN_C128", "QTN_C64", "QTN_MIXED", "QtnError", "qtn_network_build", "qtn_network_info",
     "qtn_order_minfill", "qtn_plan", "qtn_set_angles", "qtn_contract",
     "qtn_contract_timed", "qtn_contract_batch", "qtn_batch_workspace",
-    "qtn_get_plan_stats", "qtn_bucket_widths", "qtn_network_free",
+    "qtn_get_plan_stats", "qtn_bucket_widths", "qtn_slice_vars", "qtn_network_free",
     "qtn_last_error", "qtn_launch_log", "qtn_plan_order", "qtn_autotune",
     "qtn_autotune_angles", "qtn_tune_angles_workspace", "qtn_tune_log",
     "qtn_tune_picks", "qtn_set_tune_picks", "qtn_angles_workspace", "qtn_contract_angles",
     "qtn_gradient_workspace", "qtn_energy_gradient",
     "Network", "CostModel", "qtn_apply_costmodel", "workspace", "stream_handle",
     "qtn_bucket_plan", "qtn_bucket_get_info", "qtn_bucket_contract",
-    "qtn_bucket_contract_noalloc", "qtn_bucket_free",
+    "qtn_bucket_contract_noalloc", "qtn_bucket_contract_timed", "qtn_bucket_free",
     "Bucket",
 ]
 
@@ -54,7 +54,7 @@ def qtn_last_error() -> str:
 def qtn_network_build(n_vertices, edges, gamma, beta, max_levels=0,
                       small_width=0, max_width=0, n_streams=0, eager=False,
                       lane_sum_bits=0, variant=0, order_trials=0, executor=0,
-                      spin_limit=0, mixed_width=0):
+                      spin_limit=0, mixed_width=0, slice_width=0):
     """Returns an opaque handle (int)."""
     e, ep = _i32(edges)
     g, gp = _f64(gamma)
@@ -63,7 +63,7 @@ def qtn_network_build(n_vertices, edges, gamma, beta, max_levels=0,
         raise ValueError("gamma and beta differ in length")
     cfg = qtn_config(max_levels, small_width, max_width, n_streams, int(eager),
                      lane_sum_bits, variant, order_trials, executor, spin_limit,
-                     mixed_width)
+                     mixed_width, slice_width)
     h = ctypes.c_void_p()
     check(lib().qtn_network_build(int(n_vertices), len(e) // 2, ep, len(g), gp,
                                   bp, ctypes.byref(cfg), ctypes.byref(h)))
@@ -175,7 +175,8 @@ def qtn_get_plan_stats(net):
             "bytes": s.bytes, "flops": s.flops, "paper_flops": s.paper_flops,
             "workspace": s.workspace, "n_matrix": s.n_matrix,
             "n_cell": s.n_cell, "n_stream": s.n_stream, "n_over4g": s.n_over4g,
-            "n_over4g_generic": s.n_over4g_generic}
+            "n_over4g_generic": s.n_over4g_generic, "n_sliced": s.n_sliced,
+            "n_slices": s.n_slices}
 
 
 def qtn_plan_order(net, edge):
@@ -190,6 +191,14 @@ def qtn_bucket_widths(net, edge):
     out, op = _i32(np.zeros(nv))
     check(lib().qtn_bucket_widths(net, edge, op))
     return out
+
+
+def qtn_slice_vars(net, edge):
+    """Variables fixed by index slicing in one light cone (slice bit order)."""
+    out, op = _i32(np.zeros(16))
+    n = ctypes.c_int32()
+    check(lib().qtn_slice_vars(net, edge, 16, op, ctypes.byref(n)))
+    return out[:n.value]
 
 
 def qtn_launch_log(net):
@@ -409,6 +418,9 @@ class Network:
     def plan_order(self, edge):
         return qtn_plan_order(self.h, edge)
 
+    def slice_vars(self, edge):
+        return qtn_slice_vars(self.h, edge)
+
     def bucket_widths(self, edge):
         return qtn_bucket_widths(self.h, edge)
 
@@ -568,6 +580,15 @@ def qtn_bucket_contract(b, data, ws, stream=None):
                                     stream_handle(stream)))
 
 
+def qtn_bucket_contract_timed(b, data, ws, stream=None):
+    """Runs the bucket and returns its kernel's duration in milliseconds."""
+    ms = ctypes.c_double()
+    check(lib().qtn_bucket_contract_timed(b, ctypes.c_void_p(data.data_ptr()), data.numel(),
+                                          ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                          stream_handle(stream), ctypes.byref(ms)))
+    return ms.value
+
+
 def qtn_bucket_contract_noalloc(b, data, stream=None):
     check(lib().qtn_bucket_contract_noalloc(b, ctypes.c_void_p(data.data_ptr()), data.numel(),
                                             stream_handle(stream)))
@@ -612,6 +633,11 @@ class Bucket:
     def contract(self, data, ws=None, stream=None):
         """Queue the contraction on the stream (asynchronous)."""
         qtn_bucket_contract(self.h, data, self.workspace() if ws is None else ws, stream)
+
+    def contract_timed(self, data, ws=None, stream=None):
+        """Run once and return the kernel's duration in milliseconds."""
+        return qtn_bucket_contract_timed(self.h, data, self.workspace() if ws is None else ws,
+                                         stream)
 
     def contract_noalloc(self, data, stream=None):
         """Queue the contraction with the descriptors in the library's fixed

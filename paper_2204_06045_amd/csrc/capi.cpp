@@ -95,6 +95,7 @@ struct Schedule {
   std::vector<DevOp> ops;
   std::vector<int2> ranges;  // first n_cones: each cone's leading small groups
   std::vector<int> csb, ncb;
+  std::vector<int> cns;       // slices per light cone (index slicing; 1: none)
   std::vector<FillDesc> fills;
   std::vector<int32_t> stab;  // serial-offset tables of streaming operands
   std::vector<uint8_t> uperm; // 32 bytes per group: union bit of each unit bit
@@ -104,7 +105,7 @@ struct Schedule {
   std::vector<std::vector<Task>> cone_tasks;  // after the leading small groups
   int n_cones = 0, n_nets = 0, n_angles = 0;
   size_t off_res = 0, off_angles = 0, off_desc = 0, off_fills = 0, off_groups = 0,
-         off_ops = 0, off_stab = 0, off_uperm = 0, off_ranges = 0, off_csb = 0, off_ncb = 0, off_data = 0, total = 0;
+         off_ops = 0, off_stab = 0, off_uperm = 0, off_ranges = 0, off_csb = 0, off_ncb = 0, off_cns = 0, off_data = 0, total = 0;
   int64_t scalar_off = 0, scalar_sstride = 0;
   int n_sets = 1;  // angle sets evaluated per launch (one copy of the data each)
   std::vector<char> desc_blob;  // bytes [off_desc, off_data)
@@ -283,8 +284,12 @@ const std::vector<int> &get_minfill(qtn_network *net, int e) {
   return net->minfill[e];
 }
 
-int64_t gate_offset(const Gate &gt, bool transposed, int p) {
-  const int t = transposed ? 4 : 0;
+// Element offset of a gate's values in the gate table.  A gate cut by index
+// slicing reads the block whose bit 0 is its remaining axis, at the row of
+// the fixed axis's value (bit cut_slot of the slice number).
+int64_t gate_offset(const Gate &gt, bool transposed, int p, uint32_t slice = 0) {
+  int t = transposed ? 4 : 0;
+  if (gt.cut >= 0) t = (gt.cut == 1 ? 4 : 0) + 2 * (int)((slice >> gt.cut_slot) & 1u);
   switch (gt.kind) {
     case kH: return 32LL * p;
     case kZ: return 32LL * p + 2;
@@ -337,7 +342,8 @@ struct GroupEnv {
   int64_t arena = 0, arena_sstride = 0;   // intermediates sit at arena + Tensor::offset
   int64_t table[2] = {-1, -1};            // gate tables: complex128, complex64
   int64_t table_sstride[2] = {0, 0};
-  const LightCone *lc = nullptr;          // gates of the group's gate operands
+  const std::vector<Gate> *gates = nullptr;  // gates of the group's gate operands
+  uint32_t slice = 0;                     // index slicing: the slice's number
   int p = 0;                              // QAOA depth (gate table layout)
   int var_req = 0, rls_req = 2;           // mapping requested (0: the width rule)
   bool is_small = false;                  // runs inside a workgroup segment
@@ -632,7 +638,8 @@ int describe_group(const Group &G, const ConePlan &pl, const GroupEnv &env, Sche
     std::memset(&d, 0, sizeof d);
     if (t.gate >= 0) {
       // gate operands read the table of the group's own precision
-      d.off = env.table[G.prec] + gate_offset(env.lc->gates[t.gate], t.transposed, env.p) * es(G.prec);
+      d.off = env.table[G.prec] +
+              gate_offset((*env.gates)[t.gate], t.transposed, env.p, env.slice) * es(G.prec);
       d.sstride = env.table_sstride[G.prec];
       d.dt = (uint8_t)G.prec;
     } else {
@@ -745,7 +752,7 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S, const Force *fo
     }
     s.fills.push_back(f);
     s.n_angles += 2 * nets[i]->p;
-    for (auto &pl : nets[i]->plans) n_scalars += pl.n_scalars;
+    for (auto &pl : nets[i]->plans) n_scalars += pl.n_scalars * pl.n_slices;
   }
   s.scalar_off = data;
   s.scalar_sstride = al(n_scalars * es(s.scalar_prec));
@@ -758,10 +765,11 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S, const Force *fo
     const int64_t table_sstride[2] = {s.fills[i].sstride128, s.fills[i].sstride64};
     for (size_t c = 0; c < net->plans.size(); c++) {
       const ConePlan &pl = net->plans[c];
-      const LightCone &lc = net->cones[c];
+      const std::vector<Gate> &gates = pl.gates.empty() ? net->cones[c].gates : pl.gates;
       const int64_t arena = data, arena_sstride = al(pl.arena_bytes);
       data += n_sets * arena_sstride;
       s.csb.push_back(scalar_next);
+      s.cns.push_back(pl.n_slices);
       std::vector<Task> tasks;
       int open_begin = -1;
       double seg_bytes = 0, seg_flops = 0;
@@ -772,6 +780,9 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S, const Force *fo
         open_begin = -1;
         seg_bytes = seg_flops = 0;
       };
+      // index slicing: the groups run once per slice, in order, on the one
+      // arena; slice k's scalars take slots k * n_scalars onwards
+      for (int slice = 0; slice < pl.n_slices; slice++)
       for (const Group &G : pl.groups) {
         if (G.ops.size() > 255) return set_err(QTN_ERANGE, "bucket with more than 255 tensors");
         if (G.out_tensor < 0 && G.prec != s.scalar_prec)
@@ -779,7 +790,8 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S, const Force *fo
         GroupEnv env;
         env.out_off = G.out_tensor >= 0
                           ? arena + pl.tensors[G.out_tensor].offset
-                          : s.scalar_off + (int64_t)(scalar_next + G.scalar_slot) * es(s.scalar_prec);
+                          : s.scalar_off + (int64_t)(scalar_next + slice * pl.n_scalars + G.scalar_slot) *
+                                               es(s.scalar_prec);
         env.out_sstride = G.out_tensor >= 0 ? arena_sstride : s.scalar_sstride;
         env.arena = arena;
         env.arena_sstride = arena_sstride;
@@ -787,7 +799,8 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S, const Force *fo
           env.table[q] = table[q];
           env.table_sstride[q] = table_sstride[q];
         }
-        env.lc = &lc;
+        env.gates = &gates;
+        env.slice = (uint32_t)slice;
         env.p = net->p;
         // the mapping requested (network config, tuned pick or a tuning
         // candidate); 0 leaves it to the width rule
@@ -825,7 +838,7 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S, const Force *fo
         }
       }
       close_segment((int)s.groups.size());
-      scalar_next += pl.n_scalars;
+      scalar_next += pl.n_scalars * pl.n_slices;
       s.cone_tasks.push_back(std::move(tasks));
       s.n_cones++;
     }
@@ -947,7 +960,8 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S, const Force *fo
   s.off_ranges = align_up(s.off_uperm + s.uperm.size(), 256);
   s.off_csb = align_up(s.off_ranges + sizeof(int2) * s.ranges.size(), 256);
   s.off_ncb = align_up(s.off_csb + sizeof(int) * s.csb.size(), 256);
-  s.off_items = align_up(s.off_ncb + sizeof(int) * s.ncb.size(), 256);
+  s.off_cns = align_up(s.off_ncb + sizeof(int) * s.ncb.size(), 256);
+  s.off_items = align_up(s.off_cns + sizeof(int) * s.cns.size(), 256);
   s.off_steps = align_up(s.off_items + sizeof(int4) * s.items.size(), 256);
   s.off_item_task = align_up(s.off_steps + sizeof(int) * s.step_begin.size(), 256);
   s.off_task_next = align_up(s.off_item_task + sizeof(int) * s.item_task.size(), 256);
@@ -969,6 +983,7 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S, const Force *fo
   put(s.off_ranges, s.ranges.data(), sizeof(int2) * s.ranges.size());
   put(s.off_csb, s.csb.data(), sizeof(int) * s.csb.size());
   put(s.off_ncb, s.ncb.data(), sizeof(int) * s.ncb.size());
+  put(s.off_cns, s.cns.data(), sizeof(int) * s.cns.size());
   put(s.off_items, s.items.data(), sizeof(int4) * s.items.size());
   put(s.off_steps, s.step_begin.data(), sizeof(int) * s.step_begin.size());
   put(s.off_item_task, s.item_task.data(), sizeof(int) * s.item_task.size());
@@ -1161,7 +1176,8 @@ int enqueue(Exec &X, Timer &tm) {
   if ((rc = tm.begin(QTN_K_REDUCE, rt.main))) return rc;
   QTN_HIP(launch_reduce(s.scalar_prec == 1 ? kPrecC64 : kPrecC128, data, s.scalar_off,
                         s.scalar_sstride, (const int *)(ws + s.off_csb),
-                        (const int *)(ws + s.off_ncb), s.n_cones, s.n_nets, NS,
+                        (const int *)(ws + s.off_ncb), (const int *)(ws + s.off_cns), s.n_cones,
+                        s.n_nets, NS,
                         (double *)(ws + s.off_res), rt.main));
   if ((rc = tm.end(rt.main))) return rc;
   return QTN_OK;
@@ -1309,6 +1325,9 @@ int qtn_network_build(int32_t n_vertices, int64_t n_edges, const int32_t *edges,
       if (cfg->mixed_width < 0 || cfg->mixed_width > 32)
         return set_err(QTN_EINVAL, "mixed_width must be in 0..32");
       if (cfg->mixed_width > 0) net->opt.mixed_width = cfg->mixed_width;
+      if (cfg->slice_width < 0 || cfg->slice_width > kMaxWidth)
+        return set_err(QTN_EINVAL, "slice_width must be in 0..32");
+      net->opt.slice_width = cfg->slice_width;
     }
     const int m = (int)n_edges;
     net->cones.resize(m);
@@ -1379,14 +1398,37 @@ int qtn_plan(qtn_network *net, const int32_t *const *orders, int32_t precision,
     PlanOptions o = net->opt;
     o.precision = precision;
     parallel_for(m, [&](int e) {
+      const LightCone &lc = net->cones[e];
+      const bool given = orders && orders[e];
       std::vector<int> ord;
-      if (orders && orders[e])
-        ord.assign(orders[e], orders[e] + net->cones[e].n_vars);
+      if (given)
+        ord.assign(orders[e], orders[e] + lc.n_vars);
       else if (net->order_trials > 1)
-        ord = search_order(net->cones[e], net->order_trials);
+        ord = search_order(lc, net->order_trials);
       else
         ord = get_minfill(net, e);
-      errs[e] = plan_cone(net->cones[e], ord, o, &plans[e]);
+      if (o.slice_width > 0 && order_width(lc, ord) > o.slice_width) {
+        // index slicing: fix variables until the widest bucket fits the cap,
+        // then plan the restricted light cone (a caller's order still applies:
+        // the fixed variables are left with empty buckets)
+        std::vector<int> cord;
+        const std::vector<int> sv =
+            choose_slices(lc, o.slice_width, kMaxSliceVars, net->order_trials, &cord);
+        LightCone sc = lc;
+        for (size_t k = 0; k < sv.size(); k++) sc = slice_cone(sc, sv[k], (int)k);
+        if (!given) {
+          // the full order search, unless it is wider than the order the
+          // choice of slices reached
+          ord = net->order_trials > 1 ? search_order(sc, net->order_trials) : minfill_order(sc);
+          if (order_width(sc, ord) > std::max(o.slice_width, order_width(sc, cord))) ord = cord;
+        }
+        errs[e] = plan_cone(sc, ord, o, &plans[e]);
+        plans[e].slice_vars = sv;
+        plans[e].n_slices = 1 << sv.size();
+        plans[e].gates = sc.gates;
+        return;
+      }
+      errs[e] = plan_cone(lc, ord, o, &plans[e]);
     });
     for (int e = 0; e < m; e++)
       if (!errs[e].empty()) {
@@ -2044,7 +2086,9 @@ int qtn_get_plan_stats(const qtn_network *net, qtn_plan_stats *out) {
     st.max_width = std::max(st.max_width, pl.max_width);
     for (int w : pl.bucket_width)
       if (w > 0 && w < 40) st.width_hist[w]++;
-    st.paper_flops += pl.paper_flops;
+    st.paper_flops += pl.paper_flops * pl.n_slices;
+    st.n_sliced += pl.n_slices > 1 ? 1 : 0;
+    st.n_slices += pl.n_slices;
   }
   const Schedule &s = net->exec->sched;
   for (int k = 0; k < QTN_NKERNELS; k++) {
@@ -2067,6 +2111,17 @@ int qtn_get_plan_stats(const qtn_network *net, qtn_plan_stats *out) {
   return QTN_OK;
 }
 
+int qtn_slice_vars(const qtn_network *net, int64_t edge, int32_t cap, int32_t *vars_out,
+                   int32_t *n_out) {
+  if (!net || !n_out || (cap > 0 && !vars_out)) return set_err(QTN_EINVAL, "NULL argument");
+  if (!net->planned) return set_err(QTN_ESTATE, "qtn_plan has not been called");
+  if (edge < 0 || edge >= (int64_t)net->plans.size()) return set_err(QTN_EINVAL, "edge out of range");
+  const auto &sv = net->plans[edge].slice_vars;
+  for (int k = 0; k < (int)sv.size() && k < cap; k++) vars_out[k] = sv[k];
+  *n_out = (int32_t)sv.size();
+  return QTN_OK;
+}
+
 int qtn_plan_order(const qtn_network *net, int64_t edge, int32_t *order_out) {
   if (!net || !order_out) return set_err(QTN_EINVAL, "NULL argument");
   if (!net->planned) return set_err(QTN_ESTATE, "qtn_plan has not been called");
@@ -2086,20 +2141,27 @@ struct qtn_bucket {
   size_t off_groups = 0, off_ops = 0, off_stab = 0, off_uperm = 0;
   int64_t data_bytes = 0;  // end of the last tensor in the data buffer
   double bytes = 0, flops = 0;
+  hipEvent_t ev[2] = {nullptr, nullptr};  // timed runs: start/stop of the dispatch
+  ~qtn_bucket() {
+    for (hipEvent_t &e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
 };
 
 namespace {
 
 // Uploads the bucket's descriptors to `desc` (device) and runs its kernel
 // on the caller's data buffer.
-int bucket_run(const qtn_bucket *b, void *d_data, size_t data_bytes, char *desc, hipStream_t st) {
+// t0, t1: events attached to the kernel's dispatch (timed runs), or null.
+int bucket_run(const qtn_bucket *b, void *d_data, size_t data_bytes, char *desc, hipStream_t st,
+               hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr) {
   if ((int64_t)data_bytes < b->data_bytes)
     return set_err(QTN_ENOMEM, "data buffer smaller than the bucket's tensors");
   if (((uintptr_t)d_data & 255u) != 0) return set_err(QTN_EINVAL, "data buffer not 256-byte aligned");
   QTN_HIP(hipMemcpyAsync(desc, b->s.desc_blob.data(), b->s.desc_blob.size(), hipMemcpyHostToDevice, st));
   QTN_HIP(launch_wide_group(b->hg, d_data, (const DevGroup *)(desc + b->off_groups),
                             (const DevOp *)(desc + b->off_ops), (const int32_t *)(desc + b->off_stab),
-                            (const uint8_t *)(desc + b->off_uperm), 0, 1, st));
+                            (const uint8_t *)(desc + b->off_uperm), 0, 1, st, t0, t1));
   return QTN_OK;
 }
 
@@ -2245,6 +2307,27 @@ int qtn_bucket_contract(const qtn_bucket *b, void *d_data, size_t data_bytes, vo
   if (((uintptr_t)d_workspace & 255u) != 0) return set_err(QTN_EINVAL, "workspace not 256-byte aligned");
   try {
     return bucket_run(b, d_data, data_bytes, (char *)d_workspace, (hipStream_t)hip_stream);
+  } catch (...) {
+    return exception_status();
+  }
+}
+
+int qtn_bucket_contract_timed(qtn_bucket *b, void *d_data, size_t data_bytes, void *d_workspace,
+                              size_t ws_bytes, void *hip_stream, double *kernel_ms) {
+  if (!b || !d_data || !d_workspace || !kernel_ms) return set_err(QTN_EINVAL, "NULL argument");
+  if (ws_bytes < b->s.desc_blob.size()) return set_err(QTN_ENOMEM, "workspace too small");
+  if (((uintptr_t)d_workspace & 255u) != 0) return set_err(QTN_EINVAL, "workspace not 256-byte aligned");
+  try {
+    for (hipEvent_t &e : b->ev)
+      if (!e) QTN_HIP(hipEventCreate(&e));
+    const int rc = bucket_run(b, d_data, data_bytes, (char *)d_workspace, (hipStream_t)hip_stream,
+                              b->ev[0], b->ev[1]);
+    if (rc) return rc;
+    QTN_HIP(hipEventSynchronize(b->ev[1]));
+    float ms = 0;
+    QTN_HIP(hipEventElapsedTime(&ms, b->ev[0], b->ev[1]));
+    *kernel_ms = ms;
+    return QTN_OK;
   } catch (...) {
     return exception_status();
   }

@@ -1246,20 +1246,34 @@ __global__ void k_fill(char *__restrict__ data, const double *__restrict__ angle
 // after those of set s - 1, its results 2 n_cones + n_nets doubles after.
 template <class T>
 __global__ void k_reduce(const char *__restrict__ scalar_base, int64_t scalar_sstride,
-                         const int *__restrict__ csb, const int *__restrict__ ncb, int n_cones,
-                         int n_nets, double *__restrict__ res_base) {
+                         const int *__restrict__ csb, const int *__restrict__ ncb,
+                         const int *__restrict__ cns, int n_cones, int n_nets,
+                         double *__restrict__ res_base) {
   const T *scalars = (const T *)(scalar_base + blockIdx.x * scalar_sstride);
   double *res = res_base + (int64_t)blockIdx.x * (2 * n_cones + n_nets);
   for (int c = threadIdx.x; c < n_cones; c += blockDim.x) {
-    double re = 1.0, im = 0.0;
-    for (int s = csb[c]; s < csb[c + 1]; s++) {
-      const double2 z = to_d(scalars[s]);
-      const double nr = re * z.x - im * z.y, ni = re * z.y + im * z.x;
-      re = nr;
-      im = ni;
+    // the cone's slots split into cns[c] runs, one per slice (index
+    // slicing); e_jk is the sum over slices of each run's product
+    const int n_sl = cns[c], per = (csb[c + 1] - csb[c]) / n_sl;
+    double sre = 0.0, sim = 0.0;
+    for (int k = 0; k < n_sl; k++) {
+      double re = 1.0, im = 0.0;
+      for (int s = csb[c] + k * per; s < csb[c] + (k + 1) * per; s++) {
+        const double2 z = to_d(scalars[s]);
+        const double nr = re * z.x - im * z.y, ni = re * z.y + im * z.x;
+        re = nr;
+        im = ni;
+      }
+      if (n_sl == 1) {
+        sre = re;
+        sim = im;
+      } else {
+        sre += re;
+        sim += im;
+      }
     }
-    res[c] = re;
-    res[n_cones + c] = im;
+    res[c] = sre;
+    res[n_cones + c] = sim;
   }
   __syncthreads();
   for (int n = threadIdx.x; n < n_nets; n += blockDim.x) {
@@ -1463,15 +1477,15 @@ int persistent_blocks(int prec, int n_cu) {
 }
 
 hipError_t launch_reduce(int prec, const void *data, int64_t scalar_off, int64_t scalar_sstride,
-                         const int *csb, const int *ncb, int n_cones, int n_nets, int n_sets,
-                         double *res, hipStream_t s) {
+                         const int *csb, const int *ncb, const int *cns, int n_cones, int n_nets,
+                         int n_sets, double *res, hipStream_t s) {
   const char *sc = (const char *)data + scalar_off;
   if (prec == kPrecC64)
     hipLaunchKernelGGL(k_reduce<float2>, dim3(n_sets), dim3(256), 0, s, sc, scalar_sstride, csb,
-                       ncb, n_cones, n_nets, res);
+                       ncb, cns, n_cones, n_nets, res);
   else
     hipLaunchKernelGGL(k_reduce<double2>, dim3(n_sets), dim3(256), 0, s, sc, scalar_sstride, csb,
-                       ncb, n_cones, n_nets, res);
+                       ncb, cns, n_cones, n_nets, res);
   return hipGetLastError();
 }
 

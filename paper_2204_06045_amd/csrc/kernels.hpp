@@ -79,13 +79,15 @@ int persistent_blocks(int prec, int n_cu);
 // All offsets in descriptors are bytes from the data base `data`.
 // launch_reduce: scalars stored as complex64 when prec is kPrecC64, else as
 // complex128, starting scalar_off bytes into data.
-// Per light cone: product of its scalar slots -> e_jk (FP64); per network:
+// Per light cone: product of its scalar slots -> e_jk (FP64); with index
+// slicing (cone_slices[c] > 1) the slots split into that many equal runs, one
+// per slice, and e_jk is the sum of the runs' products; per network:
 // E = |E|/2 - 1/2 sum Re e_jk with Neumaier compensation.
 // res: per angle set [n_cones] Re, [n_cones] Im, [n_nets] energies.
 hipError_t launch_reduce(int prec, const void *data, int64_t scalar_off,
                          int64_t scalar_sstride, const int *cone_scalar_begin,
-                         const int *net_cone_begin, int n_cones, int n_nets, int n_sets,
-                         double *res, hipStream_t s);
+                         const int *net_cone_begin, const int *cone_slices, int n_cones,
+                         int n_nets, int n_sets, double *res, hipStream_t s);
 
 
 // Bytes of the device scratch array that the allocation-free bucket entry

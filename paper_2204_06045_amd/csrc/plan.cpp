@@ -243,6 +243,103 @@ double order_cost(const LightCone &lc, const std::vector<int> &order) {
   return cost;
 }
 
+int order_width(const LightCone &lc, const std::vector<int> &order, std::vector<int> *widest) {
+  const int n = lc.n_vars;
+  std::vector<int> pos(n);
+  for (int i = 0; i < n; i++) pos[order[i]] = i;
+  std::vector<std::vector<int>> bucket(n);
+  auto place = [&](const std::vector<int> &vars) {
+    int b = n;
+    for (int v : vars) b = std::min(b, pos[v]);
+    bucket[b].insert(bucket[b].end(), vars.begin(), vars.end());
+  };
+  for (const Gate &g : lc.gates) {
+    std::vector<int> v = {g.var[0]};
+    if (g.rank == 2) v.push_back(g.var[1]);
+    place(v);
+  }
+  int best = 0;
+  std::vector<char> mark(n, 0);
+  std::vector<int> u;
+  for (int i = 0; i < n; i++) {
+    if (bucket[i].empty()) continue;
+    u.clear();
+    for (int v : bucket[i])
+      if (!mark[v]) {
+        mark[v] = 1;
+        u.push_back(v);
+      }
+    for (int v : u) mark[v] = 0;
+    if ((int)u.size() > best) {
+      best = (int)u.size();
+      if (widest) *widest = u;
+    }
+    std::vector<int> rest;
+    for (int v : u)
+      if (v != order[i]) rest.push_back(v);
+    if (!rest.empty()) place(rest);
+  }
+  return best;
+}
+
+LightCone slice_cone(const LightCone &lc, int var, int slot) {
+  LightCone out = lc;
+  for (Gate &g : out.gates) {
+    if (g.rank != 2 || (g.var[0] != var && g.var[1] != var)) continue;
+    const int axis = g.var[0] == var ? 0 : 1;
+    g.cut = (int8_t)axis;
+    g.cut_slot = (int8_t)slot;
+    g.var[0] = g.var[1 - axis];
+    g.var[1] = -1;
+    g.rank = 1;
+  }
+  return out;
+}
+
+std::vector<int> choose_slices(const LightCone &lc, int cap, int max_vars, int trials,
+                               std::vector<int> *order_out) {
+  std::vector<int> fixed;
+  LightCone cur = lc;
+  auto order_of = [&](const LightCone &c) {
+    return trials > 1 ? search_order(c, std::min(trials, 8)) : minfill_order(c);
+  };
+  std::vector<int> widest, best_order = order_of(cur);
+  int w = order_width(cur, best_order, &widest);
+  while (w > cap && (int)fixed.size() < max_vars) {
+    // a variable can be fixed when every gate holding it has rank 2
+    std::vector<char> ok(cur.n_vars, 1);
+    for (const Gate &g : cur.gates)
+      if (g.rank == 1) ok[g.var[0]] = 0;
+    for (int v : fixed) ok[v] = 0;
+    int best = -1, best_w = 0;
+    double best_cost = 0;
+    std::vector<int> best_widest, cand_order;
+    for (int v : widest) {
+      if (!ok[v]) continue;
+      const LightCone t = slice_cone(cur, v, (int)fixed.size());
+      const std::vector<int> o = order_of(t);
+      std::vector<int> wv;
+      const int tw = order_width(t, o, &wv);
+      const double tc = order_cost(t, o);
+      if (best < 0 || tw < best_w || (tw == best_w && tc < best_cost)) {
+        best = v;
+        best_w = tw;
+        best_cost = tc;
+        best_widest = wv;
+        cand_order = o;
+      }
+    }
+    if (best < 0) break;  // nothing in the widest bucket can be fixed
+    cur = slice_cone(cur, best, (int)fixed.size());
+    fixed.push_back(best);
+    w = best_w;
+    widest = best_widest;
+    best_order = cand_order;
+  }
+  if (order_out) *order_out = best_order;
+  return fixed;
+}
+
 std::vector<int> search_order(const LightCone &lc, int trials) {
   std::vector<int> best = minfill_order(lc, 0);
   double best_cost = order_cost(lc, best);

@@ -32,6 +32,12 @@ struct Gate {
   int8_t layer;  // 0-based QAOA layer of P/Pc/R/Rc
   int8_t rank;
   int32_t var[2];
+  // Index slicing: a rank-2 gate one of whose variables is fixed.  `cut` is
+  // the fixed axis of the original gate (0 or 1); the gate is then stored as
+  // rank 1 over the other variable (var[0]), and the fixed value is bit
+  // `cut_slot` of the slice number.  -1: not cut.
+  int8_t cut = -1;
+  int8_t cut_slot = -1;
 };
 
 struct LightCone {
@@ -58,6 +64,27 @@ std::vector<int> minfill_order(const LightCone &lc, uint64_t seed = 0);
 
 // Sum over buckets of 2^width for an order (index sets only).
 double order_cost(const LightCone &lc, const std::vector<int> &order);
+
+// Width of the widest bucket for an order; `widest` (optional) receives the
+// variables of that bucket's union.
+int order_width(const LightCone &lc, const std::vector<int> &order,
+                std::vector<int> *widest = nullptr);
+
+// Index slicing (the network's scalar is the sum, over the 2^s values of s
+// fixed variables, of the scalars of the networks with those variables
+// fixed): the light cone with variable `var` fixed, as slice bit `slot`.
+// Every gate holding `var` must be rank 2; it becomes rank 1 (Gate::cut).
+LightCone slice_cone(const LightCone &lc, int var, int slot);
+
+// Variables to fix so that the widest bucket is at most `cap`: greedily,
+// the variable of the current widest bucket whose fixing gives the
+// narrowest (then cheapest) min-fill plan, at most `max_vars` of them.
+// Only variables held by rank-2 gates alone, and sharing no gate with an
+// already fixed one, are fixed (so every gate keeps an index).  Returns the
+// variables in slot order and, in order_out, the order of the restricted
+// light cone that reached the last width; the caller checks that width.
+std::vector<int> choose_slices(const LightCone &lc, int cap, int max_vars, int trials,
+                               std::vector<int> *order_out = nullptr);
 
 // The cheapest (by order_cost) of the greedy order and trials-1 randomized
 // min-fill orders.
@@ -98,6 +125,13 @@ struct Group {
 
 
 struct ConePlan {
+  // index slicing: the plan is of the light cone with slice_vars fixed; its
+  // groups run once per slice (n_slices = 2^|slice_vars|) and the cone's
+  // scalar is the sum of the slices' scalars.  gates: that light cone's gates
+  // (empty when nothing is sliced: the original cone's gates apply)
+  std::vector<int> slice_vars;
+  int n_slices = 1;
+  std::vector<Gate> gates;
   std::vector<int> order;
   std::vector<int> bucket_width;   // by elimination position, 0 if empty
   int max_width = 0;
@@ -131,7 +165,10 @@ bool gemm_shape(const Group &G, const ConePlan &pl, GemmShape *gs);
 constexpr int kNumFeatures = 16;
 void group_features(const Group &G, const ConePlan &pl, int precision, float *f);
 
+constexpr int kMaxSliceVars = 10;  // at most 1024 slices per light cone
+
 struct PlanOptions {
+  int slice_width = 0;   // >0: fix variables of light cones wider than this
   int max_levels = kMaxLevels;
   int small_width = 12;
   int max_width = kMaxWidth;

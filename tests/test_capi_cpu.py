@@ -418,3 +418,54 @@ def test_bucket_plan_shapes_and_validation(qtn):
         qtn.Bucket([[0, 1], [0, 2]], [1, 2], offsets=[8, 512], out_offset=1024)
     with pytest.raises(qtn.QtnError, match="precision"):
         qtn.Bucket([[0, 1]], [1], precision=qtn.QTN_MIXED)
+
+
+@pytest.mark.parametrize("cap,trials", [(24, 0), (22, 16), (10, 0)])
+def test_slice_plan(qtn, cap, trials):
+    """Index slicing: every light cone wider than the cap is planned with
+    variables fixed; its widest bucket then fits the cap, the fixed
+    variables are distinct and leave empty buckets, and the slice count and
+    the per-evaluation bytes cover every slice."""
+    n, p = (30, 4) if cap > 10 else (14, 3)
+    inst = qs.instance(n, 3, p, 0)
+    g, b = inst["angles"][0]
+    plain = qtn.Network(n, inst["edges"], g, b, order_trials=trials)
+    plain.plan(0)
+    net = qtn.Network(n, inst["edges"], g, b, order_trials=trials, slice_width=cap)
+    net.plan(0)
+    st, st0 = net.stats(), plain.stats()
+    assert st0["max_width"] > cap and st["max_width"] <= cap
+    n_sliced, n_slices = 0, 0
+    for e in range(len(inst["edges"])):
+        sv = list(net.slice_vars(e))
+        nv, _, _ = net.info(e)
+        assert len(set(sv)) == len(sv) <= 10 and all(0 <= v < nv for v in sv)
+        widths = net.bucket_widths(e)
+        order = list(net.plan_order(e))
+        for v in sv:
+            assert widths[order.index(v)] == 0  # a fixed variable has no bucket
+        if sv:
+            n_sliced += 1
+            assert max(plain.bucket_widths(e)) > cap or trials > 0
+        n_slices += 1 << len(sv)
+    assert st["n_sliced"] == n_sliced > 0 and st["n_slices"] == n_slices
+    assert st["workspace"] < st0["workspace"]
+    net.close()
+    plain.close()
+
+
+def test_slice_width_validation(qtn):
+    # a cap below what fixing variables can reach is met as far as it can be
+    inst = qs.instance(14, 3, 3, 0)
+    net = qtn.Network(14, inst["edges"], *inst["angles"][0], slice_width=4)
+    net.plan(0)
+    st = net.stats()
+    assert 4 < st["max_width"] and st["n_sliced"] > 0
+    net.close()
+    inst = qs.instance(10, 3, 1, 0)
+    with pytest.raises(qtn.QtnError):
+        qtn.Network(10, inst["edges"], *inst["angles"][0], slice_width=33)
+    net = qtn.Network(10, inst["edges"], *inst["angles"][0], slice_width=30)
+    net.plan(0)
+    assert net.stats()["n_sliced"] == 0 and net.stats()["n_slices"] == len(inst["edges"])
+    net.close()

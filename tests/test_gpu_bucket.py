@@ -167,3 +167,20 @@ def test_bucket_errors_leave_output(qtn, gpu):
     with pytest.raises(qtn.QtnError):
         b.contract(data, ws=torch.zeros(16, dtype=torch.uint8, device="cuda"))
     b.close()
+
+
+def test_timed_run_matches_plain_run(qtn, orc, gpu):
+    """The timed entry point runs the same kernel (bit-identical output) and
+    reports a positive kernel duration."""
+    rng = np.random.default_rng(11)
+    b = qtn.Bucket([list(range(18)), [0, 1, 2] + list(range(18, 24))], list(range(3, 24)))
+    data, host = _device_data(qtn, b, rng, 0)
+    b.contract(data)
+    torch.cuda.synchronize()
+    n = 1 << len(b.out_labels)
+    first = data[b.out_offset:b.out_offset + 16 * n].clone()
+    data[b.out_offset:b.out_offset + 16 * n].zero_()
+    ms = b.contract_timed(data)
+    assert ms > 0
+    assert torch.equal(first, data[b.out_offset:b.out_offset + 16 * n])
+    b.close()

@@ -666,3 +666,49 @@ def test_batch64_full_size_against_oracle(qtn, gpu):
     assert depths == {2, 3, 4} and widest >= 30
     for n in nets:
         n.close()
+
+
+@pytest.mark.parametrize("prec,cap,cfg", [
+    (0, 24, dict()), (0, 22, dict(order_trials=16)), (1, 24, dict()), (2, 24, dict()),
+    (0, 24, dict(executor=2)), (0, 24, dict(executor=4)), (0, 24, dict(variant=4)),
+    (0, 20, dict(order_trials=16, n_streams=1))])
+def test_cfg2_sliced_against_oracle(qtn, gpu, prec, cap, cfg):
+    """Index slicing at full size: N=30 p=4 with every light cone wider than
+    the cap contracted slice by slice on one arena, the slices' scalars
+    summed in FP64, against the unsliced oracle values."""
+    gd = _golden("cfg2")
+    print(f"cfg2 sliced prec={prec} cap={cap} cfg={cfg}", flush=True)
+    net = qtn.Network(gd["n"], gd["edges"], gd["gamma"], gd["beta"], slice_width=cap, **cfg)
+    net.plan(prec)
+    st = net.stats()
+    assert st["n_sliced"] > 0 and st["max_width"] <= cap
+    zz, zi, en = net.contract()
+    _check(zz, zi, en, gd["zz_re"], gd["energy"], prec, f"sliced cap {cap} {cfg}")
+    if cfg.get("executor", 0) == 0:
+        # an angle batch whose set 0 is the stored set matches the single call
+        inst = qs.instance(30, 3, 4, 0, 3)
+        gs = np.array([gd["gamma"]] + [a[0] for a in inst["angles"][1:]])
+        bs = np.array([gd["beta"]] + [a[1] for a in inst["angles"][1:]])
+        za, ea = net.contract_angles(gs, bs)
+        assert np.array_equal(za[0], zz) and ea[0] == en
+    net.close()
+
+
+@pytest.mark.parametrize("n,p", [(12, 2), (14, 3), (16, 3)])
+def test_sliced_small_graphs_all_configs(qtn, orc, gpu, n, p):
+    """Aggressive slicing (caps of 6 to 10: up to 10 fixed variables, 1024
+    slices per light cone) under every executor and precision."""
+    inst = qs.instance(n, 3, p, 19)
+    g, b = inst["angles"][0]
+    ref, ref_en = orc.energy(n, inst["edges"], g, b, threads=8)
+    for prec, cfg in [(0, dict(slice_width=8)), (0, dict(slice_width=7, small_width=4)),
+                      (1, dict(slice_width=8)), (2, dict(slice_width=8, mixed_width=4)),
+                      (0, dict(slice_width=8, executor=2)), (0, dict(slice_width=7, executor=4)),
+                      (0, dict(slice_width=10, variant=1, small_width=4)),
+                      (0, dict(slice_width=8, max_levels=1)), (1, dict(slice_width=8, variant=3))]:
+        print(f"sliced n={n} p={p} prec={prec} cfg={cfg}", flush=True)
+        net = qtn.Network(n, inst["edges"], g, b, **cfg)
+        net.plan(prec)
+        zz, zi, en = net.contract()
+        _check(zz, zi, en, ref, ref_en, prec, f"sliced {cfg}")
+        net.close()
