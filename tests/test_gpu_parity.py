@@ -582,22 +582,25 @@ def test_angle_batch_timed_launch_log(qtn, gpu):
     net.close()
 
 
-def test_headline_plan_against_oracle(qtn, gpu):
-    """The benchmark's own plan and step: N=30 p=4 graph seed 0, 8 merged
-    levels, 4 streams, best-of-64 orders, the stored kernel choices, and one
-    32-set angle batch whose set 0 is the stored oracle angle set.  The
-    8-summed-index groups run on the cell mapping with 4 cell bits (2 of
-    them serial summed bits)."""
+@pytest.mark.parametrize("slice_width,tune", [(24, "tune_n30p4_c128_s24.json"),
+                                              (0, "tune_n30p4_c128.json")])
+def test_headline_plan_against_oracle(qtn, gpu, slice_width, tune):
+    """The benchmark's own plans and step: N=30 p=4 graph seed 0, 8 merged
+    levels, 4 streams, best-of-64 orders, index slicing at width 24 (the
+    headline) or none, the stored kernel choices, and one 32-set angle batch
+    whose set 0 is the stored oracle angle set.  The 8-summed-index groups
+    run on the cell mapping with 4 cell bits (2 of them serial summed bits)."""
     gd = _golden("cfg2")
     inst = qs.instance(30, 3, 4, 0, 32)
     gs = np.array([a[0] for a in inst["angles"]])
     bs = np.array([a[1] for a in inst["angles"]])
     assert np.array_equal(gs[0], gd["gamma"]) and np.array_equal(bs[0], gd["beta"])
     net = qtn.Network(30, inst["edges"], gs[0], bs[0], max_levels=8, n_streams=4,
-                      order_trials=64)
+                      order_trials=64, slice_width=slice_width)
     net.plan(qtn.QTN_C128)
+    assert (net.stats()["n_sliced"] > 0) == (slice_width > 0)
     root = os.path.dirname(HERE)
-    with open(os.path.join(root, "paper_2204_06045_amd", "tuning", "tune_n30p4_c128.json")) as f:
+    with open(os.path.join(root, "paper_2204_06045_amd", "tuning", tune)) as f:
         net.set_tune_picks(json.load(f)["picks"])
     aws = qtn.workspace(net.angles_workspace(32))
     zz, en = net.contract_angles(gs, bs, aws)
