@@ -405,7 +405,7 @@ def run_batch(Q, torch, steps, warmup, executor=0, autotune=False, order_trials=
 
 
 def run_seeds(Q, torch, seeds=(0, 1, 2, 3, 4), angle_batch=32, steps=6, order_trials=64,
-              slice_width=0):
+              slice_width=0, order_weight=0):
     """The metric's shape on graph seeds 0-4 (the algorithmic bytes vary from
     graph to graph): per seed, the width of the widest bucket of each light
     cone (max and median), the evaluation's algorithmic bytes, and evals/s of
@@ -417,7 +417,7 @@ def run_seeds(Q, torch, seeds=(0, 1, 2, 3, 4), angle_batch=32, steps=6, order_tr
         inst = qs.instance(30, 3, 4, seed, angle_batch)
         g0, b0 = inst["angles"][0]
         net = Q.Network(30, inst["edges"], g0, b0, order_trials=order_trials,
-                        slice_width=slice_width)
+                        slice_width=slice_width, order_weight=order_weight)
         net.plan(Q.QTN_C128)
         widths = [max(net.bucket_widths(e)) for e in range(len(inst["edges"]))]
         gs = np.array([a[0] for a in inst["angles"]])
@@ -441,7 +441,8 @@ def run_seeds(Q, torch, seeds=(0, 1, 2, 3, 4), angle_batch=32, steps=6, order_tr
     return rows
 
 
-def run_gradient(Q, torch, inst, iters=12, lr=0.02, h=1e-4, order_trials=64, slice_width=0):
+def run_gradient(Q, torch, inst, iters=12, lr=0.02, h=1e-4, order_trials=64, slice_width=0,
+                 order_weight=0):
     """Parameter search on the metric's graph (Sec. II-A): gradient ascent on
     E(gamma, beta) with the gradient from one batched pass over 4p + 1 angle
     sets (qtn_energy_gradient), width rule, no tuning.  Reports gradients per
@@ -449,7 +450,7 @@ def run_gradient(Q, torch, inst, iters=12, lr=0.02, h=1e-4, order_trials=64, sli
     import numpy as np
     g, b = (np.array(x, dtype=np.float64) for x in inst["angles"][0])
     net = Q.Network(inst["n"], inst["edges"], g, b, order_trials=order_trials,
-                    slice_width=slice_width)
+                    slice_width=slice_width, order_weight=order_weight)
     net.plan(Q.QTN_C128)
     e0, dg, db = net.energy_gradient(g, b, step=h)  # warm-up (workspace, plan upload)
     torch.cuda.synchronize()
@@ -670,6 +671,8 @@ def main():
     ap.add_argument("--executor", type=int, default=0, help="0 default, 1 launches, 2 persistent")
     ap.add_argument("--order-trials", type=int, default=64,
                     help="randomized min-fill orders tried per light cone (0 = greedy)")
+    ap.add_argument("--order-weight", type=int, default=4,
+                    help="order search by plan flops + this weight * bytes (0: sum of 2^width)")
     ap.add_argument("--slice-width", type=int, default=24,
                     help="index slicing of light cones wider than this (0: off)")
     ap.add_argument("--seed", type=int, default=0)
@@ -710,8 +713,9 @@ def main():
     kcfg = dict(variant=args.variant, lane_sum_bits=args.lane_bits,
                 order_trials=args.order_trials, executor=args.executor,
                 small_width=args.small_width, mixed_width=args.mixed_width, eager=args.eager,
-                slice_width=args.slice_width)
-    tag_s = f"_s{args.slice_width}" if args.slice_width else ""
+                slice_width=args.slice_width, order_weight=args.order_weight)
+    tag_s = ((f"_s{args.slice_width}" if args.slice_width else "") +
+             (f"_o{args.order_weight}" if args.order_weight else ""))
     tune_file = None if args.retune else (
         args.tune_file or os.path.join(ROOT, "paper_2204_06045_amd", "tuning",
                                        f"tune_n30p4_{args.precision}{tag_s}.json"))
@@ -770,31 +774,35 @@ def main():
     if sequential is not None:
         variants[f"sequential_{args.precision}"] = sequential
     if args.variants:
-        # merged rows with the main row's angle batch (and slicing); the same
-        # plan without slicing (its stored kernel choices); the
+        # merged rows with the main row's angle batch (and its slicing and
+        # order objective); the merged plan with neither (orders by the sum
+        # of 2^width, no slicing; its stored kernel choices); the
         # bucket-by-bucket rows (the plain per-bucket path: no merging, no
         # slicing) one call per angle set, as the paper's backends run
-        for name, pr, lv, ab, sw in (
-                ("c128_merged", Q.QTN_C128, 8, args.angle_batch, args.slice_width),
-                ("c128_unsliced", Q.QTN_C128, 8, args.angle_batch, 0),
-                ("c64_merged", Q.QTN_C64, 8, args.angle_batch, args.slice_width),
-                ("mixed_merged", Q.QTN_MIXED, 8, args.angle_batch, args.slice_width),
-                ("c128_plain", Q.QTN_C128, 1, 1, 0), ("c64_plain", Q.QTN_C64, 1, 1, 0)):
+        ow = args.order_weight
+        for name, pr, lv, ab, sw, vw in (
+                ("c128_merged", Q.QTN_C128, 8, args.angle_batch, args.slice_width, ow),
+                ("c128_unsliced", Q.QTN_C128, 8, args.angle_batch, 0, 0),
+                ("c64_merged", Q.QTN_C64, 8, args.angle_batch, args.slice_width, ow),
+                ("mixed_merged", Q.QTN_MIXED, 8, args.angle_batch, args.slice_width, ow),
+                ("c128_plain", Q.QTN_C128, 1, 1, 0, 0), ("c64_plain", Q.QTN_C64, 1, 1, 0, 0)):
             if (pr == prec and lv == args.levels and ab == args.angle_batch
-                    and sw == args.slice_width):
+                    and sw == args.slice_width and vw == ow):
                 continue
             log(f"variant {name}")
             vsteps = max(3, args.steps // 4) if ab == 1 else max(2, args.steps // 8)
             vtune = None
-            if sw == 0 and lv == 8 and pr == Q.QTN_C128 and not args.retune:
+            if sw == 0 and vw == 0 and lv == 8 and pr == Q.QTN_C128 and not args.retune:
                 vtune = os.path.join(ROOT, "paper_2204_06045_amd", "tuning", "tune_n30p4_c128.json")
             vnet, vdt, _, _, vev = run_rows(Q, torch, inst, pr, lv, args.streams, vsteps, 2,
                                             autotune=bool(args.autotune), tune_file=vtune,
-                                            angle_batch=ab, **{**kcfg, "slice_width": sw})
+                                            angle_batch=ab,
+                                            **{**kcfg, "slice_width": sw, "order_weight": vw})
             vst = vnet.stats()
             variants[name] = {"evals_per_s": vev / vdt, "angle_sets_per_step": ab,
                               "alg_bytes_per_eval": vst["bytes"],
                               "alg_flops_per_eval": vst["flops"], "slice_width": sw,
+                              "order_weight": vw,
                               "slices": vst["n_slices"], "n_groups": vst["n_groups"]}
             vnet.close()
             torch.cuda.empty_cache()
@@ -807,10 +815,12 @@ def main():
         variants["costmodel_c64"] = run_costmodel(Q, torch)
         torch.cuda.empty_cache()
         log("variant gradient (gradient ascent, 4p + 1 angle sets per gradient)")
-        variants["gradient_c128"] = run_gradient(Q, torch, inst, slice_width=args.slice_width)
+        variants["gradient_c128"] = run_gradient(Q, torch, inst, slice_width=args.slice_width,
+                                                 order_weight=args.order_weight)
         torch.cuda.empty_cache()
         log("variant seeds (graph seeds 0-4, width rule, 32-set batches)")
-        variants["seeds_c128"] = run_seeds(Q, torch, slice_width=args.slice_width)
+        variants["seeds_c128"] = run_seeds(Q, torch, slice_width=args.slice_width,
+                                           order_weight=args.order_weight)
         torch.cuda.empty_cache()
         log("variant micro (single-bucket probes)")
         variants["micro"] = run_micro(Q, torch)
@@ -847,7 +857,7 @@ def main():
             "streams": args.streams, "variant": args.variant,
             "lane_sum_bits": args.lane_bits, "order_trials": args.order_trials,
             "executor": args.executor, "autotune": bool(args.autotune), "eager": args.eager,
-            "slice_width": args.slice_width,
+            "slice_width": args.slice_width, "order_weight": args.order_weight,
             "angle_sets_per_step": args.angle_batch,
             "max_width": stats["max_width"],
             "buckets": stats["n_buckets"], "groups": stats["n_groups"],

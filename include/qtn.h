@@ -95,7 +95,12 @@ typedef struct qtn_config {
                             be fixed), each value combination (a slice) is
                             contracted in turn on one arena and e_jk is the
                             FP64 sum of the slices' scalars; 0 off [0]      */
-    int32_t reserved[4];
+    int32_t order_weight; /* order_trials > 1: 0 picks the order with the
+                            smallest sum of 2^width [0]; > 0 the one whose
+                            merged plan has the smallest complex flops +
+                            order_weight * algorithmic bytes (the groups the
+                            kernels run, in the plan's precision)          */
+    int32_t reserved[3];
 } qtn_config;
 
 /*

@@ -1328,6 +1328,9 @@ int qtn_network_build(int32_t n_vertices, int64_t n_edges, const int32_t *edges,
       if (cfg->slice_width < 0 || cfg->slice_width > kMaxWidth)
         return set_err(QTN_EINVAL, "slice_width must be in 0..32");
       net->opt.slice_width = cfg->slice_width;
+      if (cfg->order_weight < 0 || cfg->order_weight > 1000)
+        return set_err(QTN_EINVAL, "order_weight must be in 0..1000");
+      net->opt.order_weight = cfg->order_weight;
     }
     const int m = (int)n_edges;
     net->cones.resize(m);
@@ -1401,10 +1404,13 @@ int qtn_plan(qtn_network *net, const int32_t *const *orders, int32_t precision,
       const LightCone &lc = net->cones[e];
       const bool given = orders && orders[e];
       std::vector<int> ord;
+      // order search by the merged plan's cost (order_weight > 0) or by the
+      // sum of 2^width
+      const PlanOptions *cost_opt = o.order_weight > 0 ? &o : nullptr;
       if (given)
         ord.assign(orders[e], orders[e] + lc.n_vars);
       else if (net->order_trials > 1)
-        ord = search_order(lc, net->order_trials);
+        ord = search_order(lc, net->order_trials, cost_opt, o.order_weight);
       else
         ord = get_minfill(net, e);
       if (o.slice_width > 0 && order_width(lc, ord) > o.slice_width) {
@@ -1412,14 +1418,15 @@ int qtn_plan(qtn_network *net, const int32_t *const *orders, int32_t precision,
         // then plan the restricted light cone (a caller's order still applies:
         // the fixed variables are left with empty buckets)
         std::vector<int> cord;
-        const std::vector<int> sv =
-            choose_slices(lc, o.slice_width, kMaxSliceVars, net->order_trials, &cord);
+        const std::vector<int> sv = choose_slices(lc, o.slice_width, kMaxSliceVars,
+                                                  net->order_trials, &cord, cost_opt, o.order_weight);
         LightCone sc = lc;
         for (size_t k = 0; k < sv.size(); k++) sc = slice_cone(sc, sv[k], (int)k);
         if (!given) {
           // the full order search, unless it is wider than the order the
           // choice of slices reached
-          ord = net->order_trials > 1 ? search_order(sc, net->order_trials) : minfill_order(sc);
+          ord = net->order_trials > 1 ? search_order(sc, net->order_trials, cost_opt, o.order_weight)
+                                      : minfill_order(sc);
           if (order_width(sc, ord) > std::max(o.slice_width, order_width(sc, cord))) ord = cord;
         }
         errs[e] = plan_cone(sc, ord, o, &plans[e]);

@@ -297,11 +297,12 @@ LightCone slice_cone(const LightCone &lc, int var, int slot) {
 }
 
 std::vector<int> choose_slices(const LightCone &lc, int cap, int max_vars, int trials,
-                               std::vector<int> *order_out) {
+                               std::vector<int> *order_out, const PlanOptions *plan,
+                               double bytes_weight) {
   std::vector<int> fixed;
   LightCone cur = lc;
   auto order_of = [&](const LightCone &c) {
-    return trials > 1 ? search_order(c, std::min(trials, 8)) : minfill_order(c);
+    return trials > 1 ? search_order(c, std::min(trials, 8), plan, bytes_weight) : minfill_order(c);
   };
   std::vector<int> widest, best_order = order_of(cur);
   int w = order_width(cur, best_order, &widest);
@@ -340,12 +341,21 @@ std::vector<int> choose_slices(const LightCone &lc, int cap, int max_vars, int t
   return fixed;
 }
 
-std::vector<int> search_order(const LightCone &lc, int trials) {
+std::vector<int> search_order(const LightCone &lc, int trials, const PlanOptions *plan,
+                              double bytes_weight) {
+  // the merged plan's flops + weighted bytes; an order the plan refuses
+  // (over the width cap) costs more than any other
+  auto cost = [&](const std::vector<int> &o) {
+    if (!plan) return order_cost(lc, o);
+    ConePlan pl;
+    if (!plan_cone(lc, o, *plan, &pl).empty()) return HUGE_VAL;
+    return pl.flops + bytes_weight * pl.bytes;
+  };
   std::vector<int> best = minfill_order(lc, 0);
-  double best_cost = order_cost(lc, best);
+  double best_cost = cost(best);
   for (int t = 1; t < trials; t++) {
     std::vector<int> o = minfill_order(lc, 0x5EEDull * (uint64_t)t + (uint64_t)lc.edge);
-    const double c = order_cost(lc, o);
+    const double c = cost(o);
     if (c < best_cost) {
       best_cost = c;
       best.swap(o);

@@ -58,6 +58,8 @@ std::string make_graph(int n, int64_t m, const int32_t *edges, Graph *g);
 // Light cone of edge e at depth p (Sec. II-B reverse light cone).
 LightCone build_lightcone(const Graph &g, int e, int p);
 
+struct PlanOptions;
+
 // Greedy min-fill order (ties: fewest neighbours, then smallest id; with a
 // nonzero seed, remaining ties are broken at random).
 std::vector<int> minfill_order(const LightCone &lc, uint64_t seed = 0);
@@ -84,11 +86,15 @@ LightCone slice_cone(const LightCone &lc, int var, int slot);
 // variables in slot order and, in order_out, the order of the restricted
 // light cone that reached the last width; the caller checks that width.
 std::vector<int> choose_slices(const LightCone &lc, int cap, int max_vars, int trials,
-                               std::vector<int> *order_out = nullptr);
+                               std::vector<int> *order_out = nullptr,
+                               const PlanOptions *plan = nullptr, double bytes_weight = 0);
 
-// The cheapest (by order_cost) of the greedy order and trials-1 randomized
-// min-fill orders.
-std::vector<int> search_order(const LightCone &lc, int trials);
+// The cheapest of the greedy order and trials-1 randomized min-fill orders:
+// by order_cost (sum of 2^width), or, with `plan` given, by the merged plan's
+// complex flops + bytes_weight * algorithmic bytes (the groups the kernels
+// actually run, under those plan options).
+std::vector<int> search_order(const LightCone &lc, int trials, const PlanOptions *plan = nullptr,
+                              double bytes_weight = 0);
 
 // ---------------------------------------------------------------- plan
 
@@ -169,6 +175,7 @@ constexpr int kMaxSliceVars = 10;  // at most 1024 slices per light cone
 
 struct PlanOptions {
   int slice_width = 0;   // >0: fix variables of light cones wider than this
+  int order_weight = 0;  // >0: order search by plan flops + order_weight * bytes
   int max_levels = kMaxLevels;
   int small_width = 12;
   int max_width = kMaxWidth;

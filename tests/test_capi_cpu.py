@@ -469,3 +469,24 @@ def test_slice_width_validation(qtn):
     net.plan(0)
     assert net.stats()["n_sliced"] == 0 and net.stats()["n_slices"] == len(inst["edges"])
     net.close()
+
+
+@pytest.mark.parametrize("cap", [0, 24])
+def test_order_search_by_plan_cost(qtn, cap):
+    """Orders picked by the merged plan's flops + w * bytes: among the same
+    candidate orders, the plan cost is never above that of the order with
+    the smallest sum of 2^width (per light cone, so also in total)."""
+    inst = qs.instance(30, 3, 4, 0)
+    g, b = inst["angles"][0]
+    st = {}
+    for w in (0, 4):
+        net = qtn.Network(30, inst["edges"], g, b, order_trials=16, slice_width=cap,
+                          order_weight=w)
+        net.plan(0)
+        st[w] = net.stats()
+        net.close()
+    if cap == 0:
+        assert st[4]["flops"] + 4 * st[4]["bytes"] <= st[0]["flops"] + 4 * st[0]["bytes"]
+    assert st[4]["max_width"] <= max(st[0]["max_width"], cap or 32)
+    with pytest.raises(qtn.QtnError):
+        qtn.Network(30, inst["edges"], g, b, order_weight=-1)

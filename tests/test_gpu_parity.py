@@ -438,15 +438,16 @@ def _golden(name):
     (0, 8, 0, 64, 0), (1, 8, 0, 64, 0), (0, 8, 2, 16, 0), (0, 8, 0, 64, 2), (1, 8, 1, 64, 2),
     (0, 8, 0, 64, 3), (2, 8, 0, 64, 0), (2, 8, 0, 64, 2), (1, 8, 3, 64, 0), (2, 8, 3, 64, 0),
     (0, 8, 0, 64, 4), (1, 8, 3, 64, 4), (0, 8, 4, 64, 0), (1, 8, 4, 64, 0), (2, 8, 4, 64, 0),
-    (0, 8, 4, 64, 2)])
+    (0, 8, 4, 64, 2), (0, 8, 0, -16, 0), (1, 8, 4, -64, 0)])
 def test_cfg2_full_size_against_oracle(qtn, gpu, prec, levels, variant, trials, executor):
     """3-regular N=30, p=4 (Sec. II-E benchmark shape), all 45 light cones."""
     gd = _golden("cfg2")
     print(f"cfg2 prec={prec} levels={levels} variant={variant} trials={trials} "
           f"executor={executor}", flush=True)
+    # negative trials: orders picked by the merged plan's flops + 4 x bytes
     zz, zi, en = _run(qtn, gd["n"], gd["edges"], gd["gamma"], gd["beta"], prec,
-                      max_levels=levels, variant=variant, order_trials=trials,
-                      executor=executor)
+                      max_levels=levels, variant=variant, order_trials=abs(trials),
+                      executor=executor, order_weight=4 if trials < 0 else 0)
     _check(zz, zi, en, gd["zz_re"], gd["energy"], prec, "cfg2")
 
 
@@ -582,21 +583,24 @@ def test_angle_batch_timed_launch_log(qtn, gpu):
     net.close()
 
 
-@pytest.mark.parametrize("slice_width,tune", [(24, "tune_n30p4_c128_s24.json"),
-                                              (0, "tune_n30p4_c128.json")])
-def test_headline_plan_against_oracle(qtn, gpu, slice_width, tune):
+@pytest.mark.parametrize("slice_width,weight,tune", [(24, 4, "tune_n30p4_c128_s24_o4.json"),
+                                                     (24, 0, "tune_n30p4_c128_s24.json"),
+                                                     (0, 0, "tune_n30p4_c128.json")])
+def test_headline_plan_against_oracle(qtn, gpu, slice_width, weight, tune):
     """The benchmark's own plans and step: N=30 p=4 graph seed 0, 8 merged
-    levels, 4 streams, best-of-64 orders, index slicing at width 24 (the
-    headline) or none, the stored kernel choices, and one 32-set angle batch
-    whose set 0 is the stored oracle angle set.  The 8-summed-index groups
-    run on the cell mapping with 4 cell bits (2 of them serial summed bits)."""
+    levels, 4 streams, best-of-64 orders (by the merged plan's flops + 4 x
+    bytes for the headline, else by the sum of 2^width), index slicing at
+    width 24 (the headline) or none, the stored kernel choices, and one
+    32-set angle batch whose set 0 is the stored oracle angle set.  The
+    8-summed-index groups run on the cell mapping with 4 cell bits (2 of
+    them serial summed bits)."""
     gd = _golden("cfg2")
     inst = qs.instance(30, 3, 4, 0, 32)
     gs = np.array([a[0] for a in inst["angles"]])
     bs = np.array([a[1] for a in inst["angles"]])
     assert np.array_equal(gs[0], gd["gamma"]) and np.array_equal(bs[0], gd["beta"])
     net = qtn.Network(30, inst["edges"], gs[0], bs[0], max_levels=8, n_streams=4,
-                      order_trials=64, slice_width=slice_width)
+                      order_trials=64, slice_width=slice_width, order_weight=weight)
     net.plan(qtn.QTN_C128)
     assert (net.stats()["n_sliced"] > 0) == (slice_width > 0)
     root = os.path.dirname(HERE)
