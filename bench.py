@@ -350,10 +350,14 @@ def batch_golden_check(insts, nets, zz, en, master_seed, count):
     return out
 
 
-def run_batch(Q, torch, steps, warmup, executor=0, autotune=False, order_trials=16,
-              prec=1, master_seed=2204, count=64):
+def run_batch(Q, torch, steps, warmup, executor=5, autotune=False, order_trials=64,
+              prec=1, master_seed=2204, count=64, slice_width=0, order_weight=4,
+              hybrid_width=24):
     """64 random cubic graphs, N uniform over even sizes in [20, 200], p in
-    {2, 3, 4}; all light cones of all graphs in one batched call."""
+    {2, 3, 4}; all light cones of all graphs in one batched call: the hybrid
+    executor (cones up to width `hybrid_width` in one persistent lockstep
+    launch, the wider ones by per-group launches after it), orders by the
+    merged plan's flops + 4 x bytes."""
     import qaoa_synth as qs
     insts = qs.batch_instances(master_seed, count, 20, 200, (2, 3, 4), d=3)
     t0 = time.perf_counter()
@@ -361,7 +365,8 @@ def run_batch(Q, torch, steps, warmup, executor=0, autotune=False, order_trials=
     for it in insts:
         g, b = it["angles"][0]
         net = Q.Network(it["n"], it["edges"], g, b, order_trials=order_trials,
-                        executor=executor)
+                        executor=executor, slice_width=slice_width, order_weight=order_weight,
+                        hybrid_width=hybrid_width)
         net.plan(prec)
         nets.append(net)
     plan_s = time.perf_counter() - t0
@@ -396,8 +401,12 @@ def run_batch(Q, torch, steps, warmup, executor=0, autotune=False, order_trials=
            "alg_bytes_per_call": sum(s["bytes"] for s in st),
            "max_width": max(s["max_width"] for s in st),
            "executor": {0: "persistent lockstep", 2: "persistent lockstep",
-                        4: "persistent dataflow"}.get(executor, "launches"),
+                        4: "persistent dataflow",
+                        5: f"hybrid: persistent lockstep for cones up to width {hybrid_width}, "
+                           "per-group launches for the wider ones"}.get(executor, "launches"),
            "precision": "c64" if prec == 1 else "c128", "order_trials": order_trials,
+           "slice_width": slice_width, "order_weight": order_weight,
+           "slices": sum(s["n_slices"] for s in st),
            "parity_vs_oracle": parity}
     for n in nets:
         n.close()
@@ -825,9 +834,12 @@ def main():
         log("variant micro (single-bucket probes)")
         variants["micro"] = run_micro(Q, torch)
         torch.cuda.empty_cache()
-        log("variant batch64_c64 (persistent)")
-        variants["batch64_c64"] = run_batch(Q, torch, 5, 1, executor=0,
-                                            autotune=bool(args.autotune))
+        log("variant batch64_c64 (hybrid executor)")
+        variants["batch64_c64"] = run_batch(Q, torch, 5, 1, autotune=bool(args.autotune))
+        torch.cuda.empty_cache()
+        log("variant batch64_c64_lockstep (every cone in the persistent lockstep launch)")
+        variants["batch64_c64_lockstep"] = run_batch(Q, torch, 5, 1, executor=0, order_trials=16,
+                                                     order_weight=0, autotune=False)
         torch.cuda.empty_cache()
 
     cpu = None

@@ -84,7 +84,10 @@ typedef struct qtn_config {
                             leading small groups launched on that cone's
                             stream, 4 one persistent dataflow launch (work
                             items wait only for the previous task of their
-                            own light cone)                                */
+                            own light cone), 5 hybrid: one persistent
+                            lockstep launch for the light cones, then
+                            per-group launches for the heavy ones
+                            (hybrid_width)                                 */
     int32_t spin_limit;  /* persistent executors: polls before a barrier or
                             dependency wait gives up with QTN_EDEVICE [2^22] */
     int32_t mixed_width; /* QTN_MIXED: narrowest group run in complex64 [18] */
@@ -100,7 +103,12 @@ typedef struct qtn_config {
                             merged plan has the smallest complex flops +
                             order_weight * algorithmic bytes (the groups the
                             kernels run, in the plan's precision)          */
-    int32_t reserved[3];
+    int32_t hybrid_width; /* executor 5: light cones whose widest bucket is
+                            at most this run in one persistent lockstep
+                            launch, the others after it by per-group
+                            launches (cell mapping allowed) on the side
+                            streams [20]                                   */
+    int32_t reserved[2];
 } qtn_config;
 
 /*

@@ -57,7 +57,8 @@ class qtn_config(ctypes.Structure):
                 ("variant", ctypes.c_int32), ("order_trials", ctypes.c_int32),
                 ("executor", ctypes.c_int32), ("spin_limit", ctypes.c_int32),
                 ("mixed_width", ctypes.c_int32), ("slice_width", ctypes.c_int32),
-                ("order_weight", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("order_weight", ctypes.c_int32), ("hybrid_width", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class qtn_timing(ctypes.Structure):

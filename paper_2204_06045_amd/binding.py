@@ -54,7 +54,8 @@ def qtn_last_error() -> str:
 def qtn_network_build(n_vertices, edges, gamma, beta, max_levels=0,
                       small_width=0, max_width=0, n_streams=0, eager=False,
                       lane_sum_bits=0, variant=0, order_trials=0, executor=0,
-                      spin_limit=0, mixed_width=0, slice_width=0, order_weight=0):
+                      spin_limit=0, mixed_width=0, slice_width=0, order_weight=0,
+                      hybrid_width=0):
     """Returns an opaque handle (int)."""
     e, ep = _i32(edges)
     g, gp = _f64(gamma)
@@ -63,7 +64,7 @@ def qtn_network_build(n_vertices, edges, gamma, beta, max_levels=0,
         raise ValueError("gamma and beta differ in length")
     cfg = qtn_config(max_levels, small_width, max_width, n_streams, int(eager),
                      lane_sum_bits, variant, order_trials, executor, spin_limit,
-                     mixed_width, slice_width, order_weight)
+                     mixed_width, slice_width, order_weight, hybrid_width)
     h = ctypes.c_void_p()
     check(lib().qtn_network_build(int(n_vertices), len(e) // 2, ep, len(g), gp,
                                   bp, ctypes.byref(cfg), ctypes.byref(h)))

@@ -96,6 +96,10 @@ struct Schedule {
   std::vector<int2> ranges;  // first n_cones: each cone's leading small groups
   std::vector<int> csb, ncb;
   std::vector<int> cns;       // slices per light cone (index slicing; 1: none)
+  // hybrid executor: cones run by per-group launches beside the persistent
+  // launch (their groups may take the cell mapping); per-cone lead bytes
+  std::vector<char> cone_heavy;
+  std::vector<double> lead_bytes, lead_flops;
   std::vector<FillDesc> fills;
   std::vector<int32_t> stab;  // serial-offset tables of streaming operands
   std::vector<uint8_t> uperm; // 32 bytes per group: union bit of each unit bit
@@ -227,6 +231,7 @@ struct Exec {
   Runtime rt;
   bool persistent = false;
   bool dataflow = false;  // persistent: per-task dependencies instead of lockstep
+  bool hybrid = false;    // persistent lockstep for light cones, launches for heavy ones
   bool lead_per_cone = false;
   uint32_t spin_limit = 1u << 22;
 };
@@ -242,6 +247,7 @@ struct qtn_network {
   bool eager = false;
   int lane_sum_bits = 2;  // streaming: summed bits spread over lanes
   int order_trials = 0;   // >1: best of this many randomized min-fill orders
+  int hybrid_width = 20;  // executor 5: cones with a bucket wider than this are heavy
   int executor = 0;       // 0 streams + per-group launches, 1 persistent lockstep
   uint32_t spin_limit = 1u << 22;
   int variant = 0;        // 0 auto, 1 generic only, 2 streaming where possible,
@@ -770,6 +776,10 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S, const Force *fo
       data += n_sets * arena_sstride;
       s.csb.push_back(scalar_next);
       s.cns.push_back(pl.n_slices);
+      // hybrid executor (executor 5): a cone with a bucket wider than the
+      // network's hybrid width runs by per-group launches
+      const bool heavy = persistent && net->executor == 5 && pl.max_width > net->hybrid_width;
+      s.cone_heavy.push_back(heavy ? 1 : 0);
       std::vector<Task> tasks;
       int open_begin = -1;
       double seg_bytes = 0, seg_flops = 0;
@@ -818,7 +828,7 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S, const Force *fo
           env.rls_req = force->rls;
         }
         env.is_small = is_small;
-        env.persistent = persistent;
+        env.persistent = persistent && !heavy;
         DevGroup dg;
         double gb = 0, gf = 0;
         const int rc = describe_group(G, pl, env, s, &dg, &gb, &gf);
@@ -849,10 +859,14 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S, const Force *fo
   std::vector<int2> lead(s.n_cones, make_int2(0, 0));
   for (int c = 0; c < s.n_cones; c++) {
     auto &tk = s.cone_tasks[c];
+    s.lead_bytes.push_back(0);
+    s.lead_flops.push_back(0);
     if (!tk.empty() && tk[0].kind == QTN_K_BLOCK) {
       lead[c] = s.ranges[tk[0].index];
       s.init_bytes += tk[0].bytes;
       s.init_flops += tk[0].flops;
+      s.lead_bytes[c] = tk[0].bytes;
+      s.lead_flops[c] = tk[0].flops;
       tk.erase(tk.begin());
     }
   }
@@ -879,6 +893,7 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S, const Force *fo
     std::vector<std::vector<int4>> per_step;
     std::vector<std::vector<int>> per_step_task;
     for (int cn : corder) {
+      if (s.cone_heavy[cn]) continue;  // run by launches beside the persistent kernel
       int j = 0, prev = -1;
       auto put = [&](const int4 &it, int task) {
         if ((int)per_step.size() <= j) {
@@ -1090,12 +1105,31 @@ int enqueue(Exec &X, Timer &tm) {
   const int NS = s.n_sets;  // launch records carry the bytes of every set
   if (X.persistent) {
     if (NS != 1) return set_err(QTN_EINVAL, "the persistent executors run one angle set");
+    bool any_heavy = false;
+    for (char h : s.cone_heavy) any_heavy |= h != 0;
+    // the persistent launch runs alone: its grid barriers need every block
+    // resident, which kernels running beside it could prevent (measured: with
+    // the heavy cones' launches started beside a full-size persistent grid, a
+    // barrier wait ran past its bound)
     const int nb = rt.persist_blocks;
     if (nb < 1) return set_err(QTN_EDEVICE, "persistent kernel does not fit on the device");
     double b_all = 0, f_all = 0;
     for (int k = 0; k < QTN_NKERNELS; k++) {
       b_all += s.bytes[k];
       f_all += s.flops[k];
+    }
+    const int K = tm.on ? 1 : (int)rt.side.size();
+    if (X.hybrid && any_heavy) {
+      // the heavy cones' share is not the persistent launch's
+      for (int c = 0; c < s.n_cones; c++)
+        if (s.cone_heavy[c]) {
+          b_all -= s.lead_bytes[c];
+          f_all -= s.lead_flops[c];
+          for (auto &t : s.cone_tasks[c]) {
+            b_all -= t.bytes;
+            f_all -= t.flops;
+          }
+        }
     }
     if ((rc = tm.begin(QTN_K_PERSISTENT, rt.main, 0, (int)s.groups.size(), b_all, f_all, true)))
       return rc;
@@ -1113,6 +1147,52 @@ int enqueue(Exec &X, Timer &tm) {
                                 s.n_steps, (uint32_t *)(ws + s.off_ctl), s.n_ctl, nb, X.spin_limit,
                                 rt.main, tm.t0(), tm.t1()));
     if ((rc = tm.end(rt.main, true))) return rc;
+    if (X.hybrid && any_heavy) {
+      // after the persistent launch: the heavy cones, each cone's leading
+      // segment and tasks in order on one side stream, heaviest first, dealt
+      // to the least loaded stream
+      QTN_HIP(hipEventRecord(rt.ev_fork, rt.main));
+      for (int i = 0; i < K; i++) QTN_HIP(hipStreamWaitEvent(rt.side[i], rt.ev_fork, 0));
+      std::vector<int> order;
+      std::vector<double> cost(s.n_cones, 0);
+      for (int c = 0; c < s.n_cones; c++)
+        if (s.cone_heavy[c]) {
+          order.push_back(c);
+          cost[c] = s.lead_bytes[c];
+          for (auto &t : s.cone_tasks[c]) cost[c] += t.bytes;
+        }
+      std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+      std::vector<double> load(K, 0);
+      for (int c : order) {
+        const int st = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[st] += cost[c];
+        hipStream_t hs = rt.side[st];
+        if (s.ranges[c].y > s.ranges[c].x) {
+          if ((rc = tm.begin(QTN_K_BLOCK, hs, s.ranges[c].x, s.ranges[c].y - s.ranges[c].x,
+                             s.lead_bytes[c], s.lead_flops[c], true)))
+            return rc;
+          QTN_HIP(launch_block_groups(s.prec, data, groups, ops, stab, uperm, ranges, c, 1, NS, hs,
+                                      tm.t0(), tm.t1()));
+          if ((rc = tm.end(hs, true))) return rc;
+        }
+        for (auto &t : s.cone_tasks[c]) {
+          const int g0 = t.kind == QTN_K_BLOCK ? s.ranges[t.index].x : t.index;
+          const int ng = t.kind == QTN_K_BLOCK ? s.ranges[t.index].y - s.ranges[t.index].x : 1;
+          if ((rc = tm.begin(t.kind, hs, g0, ng, t.bytes, t.flops, true))) return rc;
+          if (t.kind == QTN_K_BLOCK)
+            QTN_HIP(launch_block_groups(s.prec, data, groups, ops, stab, uperm, ranges, t.index, 1,
+                                        NS, hs, tm.t0(), tm.t1()));
+          else
+            QTN_HIP(launch_wide_group(s.groups[t.index], data, groups, ops, stab, uperm, t.index,
+                                      NS, hs, tm.t0(), tm.t1()));
+          if ((rc = tm.end(hs, true))) return rc;
+        }
+      }
+      for (int i = 0; i < K; i++) {
+        QTN_HIP(hipEventRecord(rt.ev_join[i], rt.side[i]));
+        QTN_HIP(hipStreamWaitEvent(rt.main, rt.ev_join[i], 0));
+      }
+    }
   } else {
   // leading small segments: one launch for every cone before the fork, or
   // (lead_per_cone) each cone's own one-block launch on its stream
@@ -1319,7 +1399,7 @@ int qtn_network_build(int32_t n_vertices, int64_t n_edges, const int32_t *edges,
       if (cfg->order_trials < 0 || cfg->order_trials > 4096)
         return set_err(QTN_EINVAL, "order_trials must be in 0..4096");
       net->order_trials = cfg->order_trials;
-      if (cfg->executor < 0 || cfg->executor > 4) return set_err(QTN_EINVAL, "executor must be 0..4");
+      if (cfg->executor < 0 || cfg->executor > 5) return set_err(QTN_EINVAL, "executor must be 0..5");
       net->executor = cfg->executor;
       if (cfg->spin_limit > 0) net->spin_limit = (uint32_t)cfg->spin_limit;
       if (cfg->mixed_width < 0 || cfg->mixed_width > 32)
@@ -1331,6 +1411,9 @@ int qtn_network_build(int32_t n_vertices, int64_t n_edges, const int32_t *edges,
       if (cfg->order_weight < 0 || cfg->order_weight > 1000)
         return set_err(QTN_EINVAL, "order_weight must be in 0..1000");
       net->opt.order_weight = cfg->order_weight;
+      if (cfg->hybrid_width < 0 || cfg->hybrid_width > kMaxWidth)
+        return set_err(QTN_EINVAL, "hybrid_width must be in 0..32");
+      if (cfg->hybrid_width > 0) net->hybrid_width = cfg->hybrid_width;
     }
     const int m = (int)n_edges;
     net->cones.resize(m);
@@ -1447,14 +1530,15 @@ int qtn_plan(qtn_network *net, const int32_t *const *orders, int32_t precision,
     net->precision = precision;
     qtn_network *one[1] = {net};
     int rc = build_schedule(one, 1, &ex->sched, nullptr, 0, 1,
-                            net->executor == 2 || net->executor == 4);
+                            net->executor == 2 || net->executor == 4 || net->executor == 5);
     if (rc) {
       net->plans.clear();
       net->planned = false;
       return rc;
     }
     drop_batches_with(net);
-    ex->persistent = net->executor == 2 || net->executor == 4;
+    ex->persistent = net->executor == 2 || net->executor == 4 || net->executor == 5;
+    ex->hybrid = net->executor == 5;
     ex->dataflow = net->executor == 4;
     ex->lead_per_cone = net->executor == 3;
     {
@@ -1671,6 +1755,7 @@ static Exec *batch_exec(qtn_network *const *nets, int32_t n, int *rc) {
   // batches default to the persistent executor
   ex->persistent = nets[0]->executor != 1 && nets[0]->executor != 3;
   ex->dataflow = nets[0]->executor == 4;
+  ex->hybrid = nets[0]->executor == 5;
   ex->spin_limit = nets[0]->spin_limit;
   Exec *raw = ex.get();
   g_batch[key] = std::move(ex);
@@ -1907,6 +1992,7 @@ static int autotune_sets(qtn_network *net, void *d_workspace, size_t bytes, void
       return rc;
     }
     tuned->persistent = net->exec->persistent;
+    tuned->hybrid = net->exec->hybrid;
     tuned->dataflow = net->exec->dataflow;
     tuned->lead_per_cone = net->exec->lead_per_cone;
     tuned->spin_limit = net->exec->spin_limit;
@@ -1988,6 +2074,7 @@ int qtn_set_tune_picks(qtn_network *net, const qtn_tune_pick *picks, int64_t n) 
     if (rc) return rc;
     ex->rt.take(net->exec->rt);
     ex->persistent = net->exec->persistent;
+    ex->hybrid = net->exec->hybrid;
     ex->dataflow = net->exec->dataflow;
     ex->lead_per_cone = net->exec->lead_per_cone;
     ex->spin_limit = net->exec->spin_limit;
@@ -2628,6 +2715,7 @@ int qtn_apply_costmodel(qtn_network *net, const qtn_costmodel *cm, void *d_ws, s
     if ((rc = build_schedule(one, 1, &ex->sched, nullptr, 0, 1, net->exec->persistent))) return rc;
     ex->rt.take(net->exec->rt);
     ex->persistent = net->exec->persistent;
+    ex->hybrid = net->exec->hybrid;
     ex->dataflow = net->exec->dataflow;
     ex->lead_per_cone = net->exec->lead_per_cone;
     ex->spin_limit = net->exec->spin_limit;

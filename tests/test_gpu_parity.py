@@ -74,7 +74,9 @@ def test_small_graphs_all_configs(qtn, orc, gpu, n, p, prec):
                 dict(executor=2), dict(executor=2, small_width=4),
                 dict(executor=2, max_levels=1, variant=1), dict(executor=3),
                 dict(executor=3, n_streams=2, small_width=8), dict(executor=4),
-                dict(executor=4, small_width=4), dict(executor=4, max_levels=1, variant=1)]:
+                dict(executor=4, small_width=4), dict(executor=4, max_levels=1, variant=1),
+                dict(executor=5, hybrid_width=8), dict(executor=5, hybrid_width=8, small_width=4),
+                dict(executor=5, hybrid_width=1)]:
         print(f"n={n} p={p} prec={prec} cfg={cfg}", flush=True)
         zz, zi, en = _run(qtn, n, inst["edges"], g, b, prec, **cfg)
         _check(zz, zi, en, ref, ref_en, prec, str(cfg))
@@ -261,11 +263,12 @@ def test_batch_persistent_and_streams_agree(qtn, orc, gpu):
         g, b = it["angles"][0]
         print(f"oracle n={it['n']} p={it['p']}", flush=True)
         refs.append(orc.energy(it["n"], it["edges"], g, b, threads=8))
-    for executor in (0, 1, 4):
+    for executor in (0, 1, 4, 5):
         nets = []
         for it in insts:
             g, b = it["angles"][0]
-            net = qtn.Network(it["n"], it["edges"], g, b, executor=executor, order_trials=4)
+            net = qtn.Network(it["n"], it["edges"], g, b, executor=executor, order_trials=4,
+                              hybrid_width=12 if executor == 5 else 0)
             net.plan(0)
             nets.append(net)
         print(f"batch executor={executor}", flush=True)
@@ -438,7 +441,7 @@ def _golden(name):
     (0, 8, 0, 64, 0), (1, 8, 0, 64, 0), (0, 8, 2, 16, 0), (0, 8, 0, 64, 2), (1, 8, 1, 64, 2),
     (0, 8, 0, 64, 3), (2, 8, 0, 64, 0), (2, 8, 0, 64, 2), (1, 8, 3, 64, 0), (2, 8, 3, 64, 0),
     (0, 8, 0, 64, 4), (1, 8, 3, 64, 4), (0, 8, 4, 64, 0), (1, 8, 4, 64, 0), (2, 8, 4, 64, 0),
-    (0, 8, 4, 64, 2), (0, 8, 0, -16, 0), (1, 8, 4, -64, 0)])
+    (0, 8, 4, 64, 2), (0, 8, 0, -16, 0), (1, 8, 4, -64, 0), (0, 8, 0, 64, 5), (1, 8, 0, 16, 5)])
 def test_cfg2_full_size_against_oracle(qtn, gpu, prec, levels, variant, trials, executor):
     """3-regular N=30, p=4 (Sec. II-E benchmark shape), all 45 light cones."""
     gd = _golden("cfg2")
@@ -636,25 +639,29 @@ def _batch_golden():
     return gd, insts
 
 
-def test_batch64_full_size_against_oracle(qtn, gpu):
+@pytest.mark.parametrize("executor", [0, 5])
+def test_batch64_full_size_against_oracle(qtn, gpu, executor):
     """The batched workload at full size: 64 cubic graphs (N even in [20,
     200], p in {2, 3, 4}, 10,155 light cones) planned as the benchmark plans
     them (best of 16 orders, complex64, persistent lockstep executor), all
     contracted in one batched call.  Every stored light cone is compared per
     edge, and every graph the oracle evaluated whole by its energy; the
-    stored cones cover depths 2, 3 and 4 and a cone of width 30."""
+    stored cones cover depths 2, 3 and 4 and a cone of width 30.  Executor 0
+    runs every cone in the persistent lockstep launch, executor 5 the cones
+    wider than 20 by per-group launches after it."""
     gd, insts = _batch_golden()
     nets = []
     for it in insts:
         g, b = it["angles"][0]
-        net = qtn.Network(it["n"], it["edges"], g, b, order_trials=16, executor=0)
+        net = qtn.Network(it["n"], it["edges"], g, b, order_trials=16, executor=executor)
         net.plan(qtn.QTN_C64)
         nets.append(net)
     handles = [n.h for n in nets]
     total = sum(n.m for n in nets)
     assert total == 10155
     ws = qtn.workspace(qtn.qtn_batch_workspace(handles))
-    print(f"batch64: {total} light cones, workspace {ws.numel() / 2**30:.1f} GiB", flush=True)
+    print(f"batch64 executor {executor}: {total} light cones, workspace "
+          f"{ws.numel() / 2**30:.1f} GiB", flush=True)
     zz, en = qtn.qtn_contract_batch(handles, total, ws)
     offs = np.cumsum([0] + [n.m for n in nets])
     widest, depths, n_edges = 0, set(), 0
@@ -719,3 +726,21 @@ def test_sliced_small_graphs_all_configs(qtn, orc, gpu, n, p):
         zz, zi, en = net.contract()
         _check(zz, zi, en, ref, ref_en, prec, f"sliced {cfg}")
         net.close()
+
+
+def test_hybrid_executor_timed_run(qtn, orc, gpu):
+    """The hybrid executor's timed run (launches serialized) gives the same
+    results as its graph replay and records a persistent launch and the
+    heavy cones' own launches."""
+    inst = qs.instance(16, 3, 3, 23)
+    g, b = inst["angles"][0]
+    ref, ref_en = orc.energy(16, inst["edges"], g, b, threads=8)
+    net = qtn.Network(16, inst["edges"], g, b, executor=5, hybrid_width=9)
+    net.plan(0)
+    zz, zi, en = net.contract()
+    _check(zz, zi, en, ref, ref_en, 0, "hybrid")
+    zt, et, timing = net.contract_timed()
+    assert np.allclose(zt, zz, rtol=0, atol=1e-13) and abs(et - en) < 1e-12
+    kinds = {r["kind"] for r in net.launch_log()}
+    assert 4 in kinds and 2 in kinds
+    net.close()
