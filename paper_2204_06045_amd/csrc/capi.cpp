@@ -386,8 +386,12 @@ int describe_group(const Group &G, const ConePlan &pl, const GroupEnv &env, Sche
   const bool stream_ok = (int)G.ops.size() <= kStreamMaxOps && sl <= kStreamMaxSerial && off32;
   // matrix form: complex64 groups in their own launch whose operands
   // reduce to two factors (requested, or picked by tuning)
+  // matrix form: groups that split into two sides (gemm_shape), requested or
+  // picked by tuning; complex128 tiles take more LDS than the workgroup and
+  // persistent kernels hold, so complex128 groups take it in own launches only
   GemmShape gsh;
-  const bool mfma = var_req == 3 && G.prec == 1 && gemm_shape(G, pl, &gsh);
+  const bool mfma = var_req == 3 && (G.prec == 1 || (!is_small && !persistent)) &&
+                    gemm_shape(G, pl, &gsh);
   if (var_req == 3 && !mfma) var_req = 0;
   // cells: lanes on union bits 0..5, cb cell bits in registers (the
   // summed bits above bit 5, then rb kept bits); own launches only (the
@@ -420,25 +424,33 @@ int describe_group(const Group &G, const ConePlan &pl, const GroupEnv &env, Sche
   for (size_t k = 0; k < G.ops.size(); k++) order[k] = (int)k;
   if (mfma) {
     dg.variant = kVarMfma;
-    // [a, into At..., b, into Bt..., into Out...]
-    std::vector<int> side[3];
-    side[0].push_back(gsh.a);
-    side[1].push_back(gsh.b);
-    for (int k = 0; k < (int)G.ops.size(); k++)
-      if (k != gsh.a && k != gsh.b) side[gsh.role[k]].push_back(k);
+    // [side A..., side B...]
+    std::vector<int> side[2];
+    for (int k = 0; k < (int)G.ops.size(); k++) side[gsh.role[k]].push_back(k);
     order.clear();
     for (auto &sd : side) order.insert(order.end(), sd.begin(), sd.end());
     dg.n_unit = (uint8_t)side[0].size();
     dg.n_step = (uint8_t)side[1].size();
-    dg.n_serial = (uint8_t)side[2].size();
+    dg.n_serial = 0;
     dg.n_mb = (uint8_t)gsh.mbits.size();
     dg.n_nb = (uint8_t)gsh.nbits.size();
     dg.n_bb = (uint8_t)gsh.bbits.size();
-    const uint64_t mt = ((1ull << dg.n_mb) + kMfmaTM - 1) / kMfmaTM;
-    const uint64_t nt = ((1ull << dg.n_nb) + kMfmaTN - 1) / kMfmaTN;
+    const uint64_t mt = ((1ull << dg.n_mb) + kMmTM - 1) / kMmTM;
+    const uint64_t nt = ((1ull << dg.n_nb) + kMmTN - 1) / kMmTN;
     const uint64_t tiles = (1ull << dg.n_bb) * mt * nt;
     if (tiles > 0xFFFFFFFFull) return set_err(QTN_ERANGE, "matrix-form group too large");
     dg.n_units = (uint32_t)tiles;
+    // the tile's rows and columns: union bits of the lowest 6 m (n) bits
+    dg.gtab = (int32_t)s.stab.size();
+    for (int pass = 0; pass < 2; pass++) {
+      const std::vector<int> &bl = pass == 0 ? gsh.mbits : gsh.nbits;
+      const int lim = pass == 0 ? kMmTM : kMmTN;
+      for (int r = 0; r < lim; r++) {
+        uint32_t I = 0;
+        for (int j = 0; j < (int)bl.size() && j < 6; j++) I |= (uint32_t)((r >> j) & 1) << bl[j];
+        s.stab.push_back((int32_t)I);
+      }
+    }
   } else if (cell) {
     dg.variant = kVarCell;
     dg.rls = (uint8_t)cb;
@@ -709,6 +721,18 @@ int describe_group(const Group &G, const ConePlan &pl, const GroupEnv &env, Sche
       for (int w = 0; w < kCellURuns / 2; w++)
         s.stab.push_back((int32_t)((uint32_t)ur[2 * w] | ((uint32_t)ur[2 * w + 1] << 16)));
       s.stab.push_back((int32_t)cm);
+    }
+    if (mfma) {
+      // the operand's element offsets of the tile's rows (side A) or
+      // columns (side B), then of the summed indices
+      d.stab = (int32_t)s.stab.size();
+      const int sd = gsh.role[k];
+      const int lim = sd == 0 ? kMmTM : kMmTN;
+      const int32_t *rows = s.stab.data() + dg.gtab + (sd == 0 ? 0 : kMmTM);
+      std::vector<int32_t> tab(lim + (1 << G.L));
+      for (int r = 0; r < lim; r++) tab[r] = (int32_t)pext32((uint32_t)rows[r], o.mask);
+      for (int kk = 0; kk < (1 << G.L); kk++) tab[lim + kk] = (int32_t)pext32((uint32_t)kk, o.mask);
+      s.stab.insert(s.stab.end(), tab.begin(), tab.end());
     }
     if (d.dt != dg.prec) dg.cvt = 1;
     s.ops.push_back(d);

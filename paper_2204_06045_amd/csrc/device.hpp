@@ -55,7 +55,7 @@ struct DevGroup {       // 64 bytes
   uint8_t n_mb, n_nb, n_bb;  // matrix form: m, n and batch bit counts (their
                              // union positions: uperm, m then n then batch)
   uint8_t lkpos[6];     // streaming: union position of each lane-kept bit
-  uint8_t pad2[4];
+  int32_t gtab;         // matrix form: first entry of the group's row/column table
 };
 
 static_assert(sizeof(DevOp) == 64, "DevOp layout");
@@ -83,11 +83,14 @@ constexpr int cell_lds_words(int n_ops, int cb) { return n_ops * ((64 << cb) + k
 constexpr int cell_table_words(int cb) { return (1 << cb) + kCellURuns / 2 + 1; }
 constexpr int kCellMaxLdsWords = 16384;  // 64 KiB per workgroup
 
-// Matrix form (kVarMfma): ops are [a, ops into At..., b, ops into Bt...,
-// ops into Out...] with n_unit = |At side|, n_step = |Bt side|, n_serial =
-// |Out side|.  A work unit is one 64 x 16 (m x n) output tile of one batch
-// index; a whole workgroup computes it.
-constexpr int kMfmaTM = 64, kMfmaTN = 16, kMfmaKC = 32, kMfmaLd = kMfmaKC + 1;
+// Matrix form (kVarMfma): ops are [side A..., side B...] with n_unit = |side
+// A|, n_step = |side B|.  A work unit is one kMmTM x kMmTN (m x n) output
+// tile of one batch index; a whole workgroup computes it, kMmKC summed
+// indices per LDS chunk.  Tables (int32, in the stab area): the group's at
+// gtab, kMmTM union-bit words for the tile's rows then kMmTN for its columns;
+// each operand's at its stab, kMmTM row (side A) or kMmTN column (side B)
+// element offsets, then 2^L offsets of the summed indices.
+constexpr int kMmTM = 64, kMmTN = 64, kMmKC = 16, kMmMaxOps = 64;
 
 // Generic mapping: 2 register bits and 6 lane bits per wave unit.
 constexpr int kGenRegBits = 2;

@@ -124,6 +124,7 @@ struct GI {
   uint32_t op_begin, n_units;
   int w, L, n_ops, variant, rls, sl, lk, n_unit, n_step, n_serial, n_step0;
   int n_ubits, prec, cvt, n_mb, n_nb, n_bb;
+  int32_t gtab;           // matrix form: the group's row and column table
   uint32_t le_lo, le_hi;  // level_end[0..3], [4..7]
   uint32_t lk_lo, lk_hi;  // lkpos[0..1], [2..5]
   __device__ int le(int l) const { return ((l < 4 ? le_lo >> (8 * l) : le_hi >> (8 * (l - 4)))) & 0xFF; }
@@ -140,7 +141,7 @@ struct GI {
 static_assert(offsetof(DevGroup, w) == 24 && offsetof(DevGroup, rls) == 28 &&
                   offsetof(DevGroup, n_step) == 32 && offsetof(DevGroup, level_end) == 36 &&
                   offsetof(DevGroup, n_ubits) == 44 && offsetof(DevGroup, n_nb) == 48 &&
-                  offsetof(DevGroup, lkpos) == 50,
+                  offsetof(DevGroup, lkpos) == 50 && offsetof(DevGroup, gtab) == 56,
               "DevGroup word layout");
 __device__ __forceinline__ GI load_group(const DevGroup *g) {
   GI G;
@@ -172,6 +173,7 @@ __device__ __forceinline__ GI load_group(const DevGroup *g) {
   G.n_bb = (f >> 8) & 0xFF;
   G.lk_lo = f >> 16;
   G.lk_hi = dword(g, 13);
+  G.gtab = (int32_t)dword(g, 14);
   return G;
 }
 
@@ -737,91 +739,152 @@ __device__ __forceinline__ void cell_units(const GI &G, const DevOp *__restrict_
 // ------------------------------------------------------------ matrix form
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-static_assert((kMfmaTM + kMfmaTN) * kMfmaLd * 8 <= kStreamMaxOps * 64 * 4,
-              "matrix tiles must fit the streaming LDS tables");
-
-// Product of operands [k0, k1) at union index I, in complex64.
-template <bool CVT>
-__device__ __forceinline__ float2 op_product(const DevOp *__restrict__ gops, int k0, int k1,
-                                             const char *__restrict__ data, uint32_t I,
-                                             uint32_t set) {
-  float2 v = make_float2(1.0f, 0.0f);
-  for (int k = k0; k < k1; k++) {
-    const DevOp &o = gops[k];
-    v = cmul(v, ld_elem<float2, CVT>(opnd(data, o, set), pext_runs(I, o), op_dt(o)));
-  }
-  return v;
+// Matrix cores, one 16 x 16 x 4 real product (A 16 x 4, B 4 x 16, one value
+// per lane: A[i][k] from lane i + 16k, B[k][j] from lane j + 16k), FP64 for
+// complex128 and FP32 for complex64 groups.  Output element r of lane l is
+// C[row][l % 16] with row (l / 16) + 4r (FP64) or 4 (l / 16) + r (FP32).
+__device__ __forceinline__ f64x4 mm_step(double a, double b, f64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
+__device__ __forceinline__ f32x4 mm_step(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+template <class T> struct MmTypes;
+template <> struct MmTypes<double2> {
+  typedef double R;
+  typedef f64x4 V;
+  __device__ static int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+template <> struct MmTypes<float2> {
+  typedef float R;
+  typedef f32x4 V;
+  __device__ static int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
 
-// One 64 x 16 output tile of a matrix-form group, with the whole workgroup.
-// Per chunk of 32 summed indices, At (64 x 32) and Bt (16 x 32) are gathered
-// into LDS with their absorbed operands multiplied in; then three real
-// products run on the matrix cores (3M: T1 = Ar Br, T2 = Ai Bi,
-// T3 = (Ar + Ai)(Br + Bi); Re = T1 - T2, Im = T3 - T1 - T2), accumulated in
-// FP32.  Wave v owns tile rows 16v..16v+15.  v_mfma_f32_16x16x4_f32 lane
-// layout: A[i][k] and B[k][j] come from lane i + 16k (j + 16k); lane l holds
-// C[4(l/16) + r][l % 16] in element r.
-template <bool CVT>
-__device__ void mfma_tile(const GI &G, const DevOp *__restrict__ gops,
-                          const uint8_t *__restrict__ bits, char *__restrict__ data,
-                          float2 *lds, uint32_t tile, uint32_t set) {
+// LDS bytes of a matrix-form tile in arithmetic type T: the operands' tile
+// bases (kMmMaxOps words, padded to 256 bytes), the A chunk
+// [kMmTM][kMmKC + 1] and the B chunk [kMmKC][kMmTN + 1].
+template <class T> constexpr int mm_lds_bytes() {
+  return 256 + (kMmTM * (kMmKC + 1) + kMmKC * (kMmTN + 1)) * (int)sizeof(T);
+}
+static_assert(kMmMaxOps * 4 <= 256, "matrix-form operand bases");
+static_assert(mm_lds_bytes<float2>() <= kStreamMaxOps * 64 * 4,
+              "complex64 matrix tiles must fit the workgroup kernels' LDS");
+
+// One kMmTM x kMmTN output tile of a matrix-form group, with the whole
+// workgroup:
+//   out[bt, m, n] = sum_k At[bt, m, k] Bt[bt, k, n],
+// At (Bt) the product of the group's side-A (side-B) operands, k over the L
+// summed union bits.  Per chunk of kMmKC summed indices both factors are
+// gathered into LDS: thread t takes k = t % 16 (the lowest union bits, so
+// that threads with neighbouring k read neighbouring elements) and rows or
+// columns t / 16 + 16j; an operand's element offset is its tile base plus
+// table entries for the row (or column) and for k (planner-built pext
+// tables).  Then wave v multiplies its 16 rows into four 16 x 16 column
+// blocks: four real products per complex product, accumulated in the
+// group's precision.  Operands: [side A..., side B...]; G.gtab holds the
+// union bits of the tile's rows (kMmTM words) and columns (kMmTN words);
+// operand k's table (at its stab) holds kMmTM row (side A) or kMmTN column
+// (side B) offsets, then 2^L summed-index offsets.  Unit bits (uperm): m
+// bits, then n bits, then batch bits.
+template <class T, bool CVT>
+__device__ void mm_tile(const GI &G, const DevOp *__restrict__ gops, const int32_t *__restrict__ stab,
+                        const uint8_t *__restrict__ bits, char *__restrict__ data, char *lds,
+                        uint32_t tile, uint32_t set) {
+  typedef typename MmTypes<T>::R R;
+  typedef typename MmTypes<T>::V V;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int nM = G.n_mb, nN = G.n_nb, nB = G.n_bb, L = G.L;
   const uint32_t M = 1u << nM, N = 1u << nN, K = 1u << L;
-  const uint32_t mt = (M + kMfmaTM - 1) / kMfmaTM, nt = (N + kMfmaTN - 1) / kMfmaTN;
+  const uint32_t mt = (M + kMmTM - 1) / kMmTM, nt = (N + kMmTN - 1) / kMmTN;
   const uint32_t bt = tile / (mt * nt), rem = tile % (mt * nt);
-  const uint32_t m0 = (rem / nt) * kMfmaTM, n0 = (rem % nt) * kMfmaTN;
-  // unit-bit table: m bits, then n bits, then batch bits
-  const int mpos = 0, npos = nM, bpos = nM + nN;
-  // m0 and n0 are multiples of the tile sizes, so their union bits and those
-  // of a row (col) inside the tile are disjoint
-  const uint32_t Ib = unit_bits(bt, bits, nB, bpos) | unit_bits(m0, bits, nM, mpos) |
-                    unit_bits(n0, bits, nN, npos);
-  const int mlo = nM < 6 ? nM : 6, nlo = nN < 4 ? nN : 4;
-  const uint32_t kc = K >= (uint32_t)kMfmaKC ? (uint32_t)kMfmaKC : (K < 4u ? 4u : K);
-  const int na = G.n_unit, nb = G.n_step, no = G.n_serial;
-  float2 *sA = lds, *sB = lds + kMfmaTM * kMfmaLd;
-  f32x4 t1 = {0.0f, 0.0f, 0.0f, 0.0f}, t2 = t1, t3 = t1;
-  for (uint32_t k0 = 0; k0 < K; k0 += kc) {
-    for (uint32_t e = tid; e < kMfmaTM * kc; e += kBlock) {
-      const uint32_t row = e / kc, kk = e % kc, k = k0 + kk;
-      float2 v = make_float2(0.0f, 0.0f);
-      if (m0 + row < M && k < K)
-        v = op_product<CVT>(gops, 0, na, data, Ib | unit_bits(row, bits, mlo, mpos) | k, set);
-      sA[row * kMfmaLd + kk] = v;
+  const uint32_t mi = rem / nt, ni = rem % nt;
+  const uint32_t m0 = mi * kMmTM, n0 = ni * kMmTN;
+  // union bits of the tile: batch bits, and the m (n) bits above the
+  // in-tile ones (a tile spans the lowest 6 m bits and 6 n bits)
+  const int mlo = nM < 6 ? nM : 6, nlo = nN < 6 ? nN : 6;
+  const uint32_t Ib = unit_bits(bt, bits, nB, nM + nN) | unit_bits(mi, bits, nM - mlo, mlo) |
+                      unit_bits(ni, bits, nN - nlo, nM + nlo);
+  const int na = G.n_unit, nb = G.n_step;
+  const int32_t *mu = stab + G.gtab, *nu = mu + kMmTM;
+  uint32_t *base = (uint32_t *)lds;  // each operand's element offset at the tile's union bits
+  T *sA = (T *)(lds + 256), *sB = sA + kMmTM * (kMmKC + 1);
+  if (tid < na + nb) base[tid] = pext_runs(Ib, gops[tid]);
+  __syncthreads();
+  V cr[4], ci[4];
+#pragma unroll
+  for (int s = 0; s < 4; s++)
+#pragma unroll
+    for (int r = 0; r < 4; r++) cr[s][r] = ci[s][r] = (R)0;
+  const int kl = tid & 15, rl = tid >> 4;  // k, and the first row / column, of this thread
+  for (uint32_t k0 = 0; k0 < K; k0 += kMmKC) {
+    const uint32_t k = k0 + (uint32_t)kl;
+    // side A: rows rl + 16j
+#pragma unroll
+    for (int j = 0; j < kMmTM / 16; j++) {
+      const int row = rl + 16 * j;
+      T v = make_c<T>(0.0, 0.0);
+      if (m0 + (uint32_t)row < M && k < K) {
+        v = make_c<T>(1.0, 0.0);
+        for (int q = 0; q < na; q++) {
+          const DevOp &o = gops[q];
+          const int32_t *t = stab + o.stab;
+          const uint32_t e = base[q] + (uint32_t)t[row] + (uint32_t)t[kMmTM + k];
+          v = cmul(v, ld_elem<T, CVT>(opnd(data, o, set), e, op_dt(o)));
+        }
+      }
+      sA[row * (kMmKC + 1) + kl] = v;
     }
-    for (uint32_t e = tid; e < kMfmaTN * kc; e += kBlock) {
-      const uint32_t col = e / kc, kk = e % kc, k = k0 + kk;
-      float2 v = make_float2(0.0f, 0.0f);
-      if (n0 + col < N && k < K)
-        v = op_product<CVT>(gops, na, na + nb, data, Ib | unit_bits(col, bits, nlo, npos) | k, set);
-      sB[col * kMfmaLd + kk] = v;
+    // side B: columns rl + 16j
+#pragma unroll
+    for (int j = 0; j < kMmTN / 16; j++) {
+      const int col = rl + 16 * j;
+      T v = make_c<T>(0.0, 0.0);
+      if (n0 + (uint32_t)col < N && k < K) {
+        v = make_c<T>(1.0, 0.0);
+        for (int q = na; q < na + nb; q++) {
+          const DevOp &o = gops[q];
+          const int32_t *t = stab + o.stab;
+          const uint32_t e = base[q] + (uint32_t)t[col] + (uint32_t)t[kMmTN + k];
+          v = cmul(v, ld_elem<T, CVT>(opnd(data, o, set), e, op_dt(o)));
+        }
+      }
+      sB[kl * (kMmTN + 1) + col] = v;
     }
     __syncthreads();
-    const float2 *ra = sA + (wave * 16 + (lane & 15)) * kMfmaLd + (lane >> 4);
-    const float2 *rb = sB + (lane & 15) * kMfmaLd + (lane >> 4);
-    for (uint32_t kk = 0; kk < kc; kk += 4) {
-      const float2 a = ra[kk], b = rb[kk];
-      t1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, t1, 0, 0, 0);
-      t2 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, t2, 0, 0, 0);
-      t3 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x + a.y, b.x + b.y, t3, 0, 0, 0);
+#pragma unroll
+    for (int kk = 0; kk < kMmKC; kk += 4) {
+      const T a = sA[(wave * 16 + (lane & 15)) * (kMmKC + 1) + kk + (lane >> 4)];
+      const R ar = (R)a.x, ai = (R)a.y, nai = -ai;
+#pragma unroll
+      for (int s = 0; s < 4; s++) {
+        const T b = sB[(kk + (lane >> 4)) * (kMmTN + 1) + 16 * s + (lane & 15)];
+        const R br = (R)b.x, bi = (R)b.y;
+        cr[s] = mm_step(ar, br, cr[s]);
+        cr[s] = mm_step(nai, bi, cr[s]);
+        ci[s] = mm_step(ar, bi, ci[s]);
+        ci[s] = mm_step(ai, br, ci[s]);
+      }
     }
     __syncthreads();
   }
-  float2 *out = (float2 *)outp(data, G, set);
-  const uint32_t col = lane & 15;
-  if (n0 + col < N) {
-    const uint32_t Ic = Ib | unit_bits(col, bits, nlo, npos);
+  T *out = (T *)outp(data, G, set);
+  const uint32_t nout = 1u << (G.w - L);
 #pragma unroll
-    for (int i = 0; i < 4; i++) {
-      const uint32_t row = wave * 16 + 4 * (lane >> 4) + i;
-      if (m0 + row < M) {
-        float2 v = make_float2(t1[i] - t2[i], t3[i] - t1[i] - t2[i]);
-        const uint32_t I = Ic | unit_bits(row, bits, mlo, mpos);
-        if (no > 0) v = cmul(v, op_product<CVT>(gops, na + nb, na + nb + no, data, I, set));
-        if ((I >> L) < (1u << (G.w - L))) out[I >> L] = v;
-      }
+  for (int s = 0; s < 4; s++) {
+    const int col = 16 * s + (lane & 15);
+    if (n0 + (uint32_t)col >= N) continue;
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+      const int row = wave * 16 + MmTypes<T>::row(lane, r);
+      if (m0 + (uint32_t)row >= M) continue;
+      const uint32_t o = (Ib | (uint32_t)mu[row] | (uint32_t)nu[col]) >> L;
+      T v;
+      v.x = cr[s][r];
+      v.y = ci[s][r];
+      if (o < nout) out[o] = v;
     }
   }
 }
@@ -848,13 +911,14 @@ __device__ __forceinline__ void run_group(const GI &G, int g, const DevOp *__res
       for (uint32_t u = u0 + wave; u < u1; u += nw) F<float2, true>(__VA_ARGS__);   \
   } while (0)
   if (G.variant == kVarMfma) {
-    // matrix form: a unit is one output tile, computed by the whole block
+    // matrix form (complex64 inside workgroups): a unit is one output tile,
+    // computed by the whole block
     if (G.cvt)
       for (uint32_t u = u0; u < u1; u++)
-        mfma_tile<true>(G, gops, ub, data, (float2 *)s_lane, u, set);
+        mm_tile<float2, true>(G, gops, stab, ub, data, (char *)s_lane, u, set);
     else
       for (uint32_t u = u0; u < u1; u++)
-        mfma_tile<false>(G, gops, ub, data, (float2 *)s_lane, u, set);
+        mm_tile<float2, false>(G, gops, stab, ub, data, (char *)s_lane, u, set);
   } else if (G.variant == kVarStream) {
     stream_setup(G, gops, s_lane);
     __syncthreads();
@@ -969,18 +1033,20 @@ __global__ __launch_bounds__(kBlock) void k_wide_generic(char *__restrict__ data
   }
 }
 
-template <bool CVT>
+template <class T, bool CVT>
 __global__ __launch_bounds__(kBlock) void k_wide_mfma(char *__restrict__ data,
                                                       const DevGroup *__restrict__ groups,
                                                       const DevOp *__restrict__ ops,
+                                                      const int32_t *__restrict__ stab,
                                                       const uint8_t *__restrict__ uperm, int gid,
                                                       uint32_t n_sets) {
-  __shared__ __align__(16) float2 s_tile[(kMfmaTM + kMfmaTN) * kMfmaLd];
+  __shared__ __align__(16) char s_tile[mm_lds_bytes<T>()];
   const GI G = load_group(groups + gid);
   const UnitWalk W = wide_walk(G.n_units * n_sets, 1, 0);
   for (uint32_t f = W.first; f < W.end; f += W.stride) {
     const uint32_t set = f / G.n_units;
-    mfma_tile<CVT>(G, ops + G.op_begin, uperm + 32 * gid, data, s_tile, f - set * G.n_units, set);
+    mm_tile<T, CVT>(G, ops + G.op_begin, stab, uperm + 32 * gid, data, s_tile,
+                    f - set * G.n_units, set);
   }
 }
 
@@ -1411,17 +1477,18 @@ hipError_t launch_wide_group(const DevGroup &hg, void *data, const DevGroup *gro
   char *d = (char *)data;
   const bool cvt = hg.cvt != 0;
   if (hg.variant == kVarMfma) {
-    if (hg.prec != kPrecC64) return hipErrorInvalidValue;  // complex64 arithmetic only
     // a unit is one tile of the whole block
-    if (cvt) {
-      const int nb = wide_grid(k_wide_mfma<true>, 0, units, 1);
-      QTN_LAUNCH(t0, t1, k_wide_mfma<true>, dim3(nb), dim3(kBlock), s, d, groups, ops, uperm,
-                 group, ns);
-    } else {
-      const int nb = wide_grid(k_wide_mfma<false>, 0, units, 1);
-      QTN_LAUNCH(t0, t1, k_wide_mfma<false>, dim3(nb), dim3(kBlock), s, d, groups, ops, uperm,
-                 group, ns);
-    }
+#define QTN_MM_LAUNCH(T, C)                                                                 \
+  do {                                                                                     \
+    const int nb = wide_grid(k_wide_mfma<T, C>, 0, units, 1);                              \
+    QTN_LAUNCH(t0, t1, (k_wide_mfma<T, C>), dim3(nb), dim3(kBlock), s, d, groups, ops, stab, \
+               uperm, group, ns);                                                          \
+  } while (0)
+    if (hg.prec == kPrecC128 && !cvt) QTN_MM_LAUNCH(double2, false);
+    else if (hg.prec == kPrecC128) QTN_MM_LAUNCH(double2, true);
+    else if (!cvt) QTN_MM_LAUNCH(float2, false);
+    else QTN_MM_LAUNCH(float2, true);
+#undef QTN_MM_LAUNCH
     return hipGetLastError();
   }
   if (hg.prec == kPrecC128 && !cvt)

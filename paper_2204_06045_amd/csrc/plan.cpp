@@ -410,62 +410,62 @@ void group_features(const Group &G, const ConePlan &pl, int precision, float *f)
 
 bool gemm_shape(const Group &G, const ConePlan &pl, GemmShape *gs) {
   const int n = (int)G.ops.size();
-  if (n < 2 || G.w > 31) return false;
+  if (n < 2 || n > 64 || G.w > 31) return false;
   const uint32_t summed = (1u << G.L) - 1u, all = (1u << G.w) - 1u, kept = all & ~summed;
-  std::vector<int> by_rank(n);
-  for (int k = 0; k < n; k++) by_rank[k] = k;
   auto rank = [&](int k) { return (int)pl.tensors[G.ops[k].tensor].vars.size(); };
-  std::stable_sort(by_rank.begin(), by_rank.end(), [&](int x, int y) { return rank(x) > rank(y); });
-  bool found = false;
-  GemmShape best;
-  int best_m = -1;
-  // a: the largest operand; b: each other operand in order of rank
-  const int a = by_rank[0];
-  for (int bi = 1; bi < n; bi++) {
-    const int b = by_rank[bi];
-    const uint32_t ma = G.ops[a].mask, mb = G.ops[b].mask;
-    GemmShape s;
-    s.a = a;
-    s.b = b;
-    s.role.assign(n, 0);
-    bool ok = true;
-    for (int k = 0; k < n && ok; k++) {
-      const uint32_t mk = G.ops[k].mask;
-      if (k == a || (k != b && (mk & ~ma) == 0)) s.role[k] = 0;
-      else if (k == b || (mk & ~mb) == 0) s.role[k] = 1;
-      else if ((mk & ~kept) == 0) s.role[k] = 2;
-      else ok = false;
-    }
-    if (!ok) continue;
-    for (int q = G.L; q < G.w; q++) {
-      const bool in_a = (ma >> q) & 1u, in_b = (mb >> q) & 1u;
-      if (in_a && in_b) s.bbits.push_back(q);
-      else if (in_b) s.nbits.push_back(q);
-      else s.mbits.push_back(q);
-    }
-    if (s.nbits.size() > s.mbits.size()) {
-      // b has more private kept bits: swap the roles of a and b
-      std::swap(s.a, s.b);
-      for (auto &r : s.role)
-        if (r < 2) r = (int8_t)(1 - r);
-      std::vector<int> mb2, nb2;
-      for (int q = G.L; q < G.w; q++) {
-        const bool in_a = (G.ops[s.a].mask >> q) & 1u, in_b = (G.ops[s.b].mask >> q) & 1u;
-        if (in_a && in_b) continue;
-        if (in_b) nb2.push_back(q);
-        else mb2.push_back(q);
-      }
-      s.mbits.swap(mb2);
-      s.nbits.swap(nb2);
-    }
-    if ((int)s.mbits.size() > best_m) {
-      best_m = (int)s.mbits.size();
-      best = s;
-      found = true;
+  // side A: the largest operand; side B: the operand with the most kept bits
+  // side A lacks (ties: the larger one)
+  int a = 0;
+  for (int k = 1; k < n; k++)
+    if (rank(k) > rank(a)) a = k;
+  int b = -1, best = -1;
+  for (int k = 0; k < n; k++) {
+    if (k == a) continue;
+    const int priv = __builtin_popcount(G.ops[k].mask & kept & ~G.ops[a].mask);
+    if (priv > best || (priv == best && rank(k) > rank(b))) {
+      best = priv;
+      b = k;
     }
   }
-  if (found && gs) *gs = best;
-  return found;
+  GemmShape s;
+  s.a = a;
+  s.b = b;
+  s.role.assign(n, 0);
+  s.role[b] = 1;
+  uint32_t ma = G.ops[a].mask, mb = G.ops[b].mask;
+  // the rest, largest first: into a side that holds all their bits (side A
+  // first), else into the side that gains the fewest kept bits, so that the
+  // kept bits private to each side (the m and n dimensions) stay many
+  std::vector<int> rest;
+  for (int k = 0; k < n; k++)
+    if (k != a && k != b) rest.push_back(k);
+  std::stable_sort(rest.begin(), rest.end(), [&](int x, int y) { return rank(x) > rank(y); });
+  for (int k : rest) {
+    const uint32_t mk = G.ops[k].mask;
+    int side;
+    if ((mk & ~ma) == 0) side = 0;
+    else if ((mk & ~mb) == 0) side = 1;
+    else side = __builtin_popcount(mk & kept & ~ma) <= __builtin_popcount(mk & kept & ~mb) ? 0 : 1;
+    s.role[k] = (int8_t)side;
+    (side == 0 ? ma : mb) |= mk;
+  }
+  for (int q = G.L; q < G.w; q++) {
+    const bool in_a = (ma >> q) & 1u, in_b = (mb >> q) & 1u;
+    if (in_a && in_b) s.bbits.push_back(q);
+    else if (in_b) s.nbits.push_back(q);
+    else s.mbits.push_back(q);
+  }
+  if (s.nbits.size() > s.mbits.size()) {
+    // more private kept bits on side B: swap the sides
+    std::swap(s.a, s.b);
+    for (auto &r : s.role) r = (int8_t)(1 - r);
+    s.mbits.swap(s.nbits);
+  }
+  (void)kept;
+  // at least one full 16-wide block of the matrix cores each way
+  if (s.nbits.size() < 4) return false;
+  if (gs) *gs = s;
+  return true;
 }
 
 int mask_runs(uint32_t mask, uint8_t *src, uint8_t *len, uint8_t *dst) {

@@ -150,21 +150,23 @@ struct ConePlan {
 };
 
 // Matrix form of a group.  The merged contraction of Sec. II-C is a batched
-// complex matrix product when two operands a and b cover every other operand
-// that carries a summed index:
-//   out[bt, m, n] = Out[bt, m, n] * sum_k At[bt, m, k] Bt[bt, k, n]
-// At (Bt) is operand a (b) times the operands whose indices it covers; Out is
-// the product of the operands that carry kept indices only.  k runs over the
-// L summed union bits (0..L-1); m over kept bits of a alone (and kept bits of
-// neither, broadcast); n over kept bits of b alone; bt over kept bits of both.
+// complex matrix product once the group's operands are split into two sides:
+//   out[bt, m, n] = sum_k At[bt, m, k] Bt[bt, k, n]
+// At (Bt) is the product of the side-A (side-B) operands; k runs over the L
+// summed union bits (0..L-1); m over kept bits held on side A only, n over
+// kept bits held on side B only, bt over kept bits held on both.  Every split
+// is exact; the matrix cores pay off when m and n are both wide, so the split
+// keeps each side's private kept bits many.
 struct GemmShape {
-  int a = -1, b = -1;            // operand positions in Group::ops
-  std::vector<int8_t> role;      // per operand: 0 into At, 1 into Bt, 2 into Out
+  int a = -1, b = -1;            // the two operands the sides are built around
+  std::vector<int8_t> role;      // per operand: 0 side A, 1 side B
   std::vector<int> mbits, nbits, bbits;  // union bit positions, low to high
 };
 
-// The matrix form of G, or false when G has none.  Of the valid choices the
-// one with the most rows per batch (m bits) is taken, with |m| >= |n|.
+// The matrix form of G, or false when G has none worth running: fewer than
+// two operands, more than 64, or fewer than 4 n bits (one 16-wide block of
+// the matrix cores).  Side A is built around the largest operand, side B
+// around the one with the most kept bits side A lacks; |m| >= |n|.
 bool gemm_shape(const Group &G, const ConePlan &pl, GemmShape *gs);
 
 // 16 shape features of a group, for timing records and the cost model.

@@ -118,20 +118,27 @@ def test_mixed_plan_bytes_between_c64_and_c128(qtn):
     net.close()
 
 
-def test_matrix_form_scheduled_only_in_complex64(qtn):
+def test_matrix_form_scheduling(qtn):
+    """The matrix form runs only when requested (or tuned), for groups that
+    split into two sides with at least 4 n bits: own launches in every
+    precision, inside workgroups and the persistent executors only in
+    complex64 (complex128 tiles need more LDS than those kernels hold)."""
     inst = qs.instance(30, 3, 4, 0)
     g, b = inst["angles"][0]
     counts = {}
     for prec in (0, 1, 2):
         for variant in (0, 3):
-            net = qtn.Network(30, inst["edges"], g, b, variant=variant, mixed_width=16)
-            net.plan(prec)
-            counts[prec, variant] = net.stats()["n_matrix"]
-            net.close()
-    # requested only: never by the default rule, never in complex128 groups
-    assert counts[0, 0] == counts[1, 0] == counts[2, 0] == 0
-    assert counts[0, 3] == 0
-    assert counts[1, 3] > counts[2, 3] > 0
+            for executor in (0, 2):
+                net = qtn.Network(30, inst["edges"], g, b, variant=variant, mixed_width=16,
+                                  executor=executor)
+                net.plan(prec)
+                counts[prec, variant, executor] = net.stats()["n_matrix"]
+                net.close()
+    assert all(counts[p, 0, e] == 0 for p in (0, 1, 2) for e in (0, 2))
+    assert counts[0, 3, 0] > 0 and counts[1, 3, 0] > 0 and counts[2, 3, 0] > 0
+    # the persistent executor: complex64 groups only
+    assert counts[0, 3, 2] == 0 and counts[1, 3, 2] > 0
+    assert counts[1, 3, 0] >= counts[2, 3, 2]
 
 
 def test_cell_mapping_scheduling_rules(qtn):
@@ -396,9 +403,12 @@ def test_bucket_plan_shapes_and_validation(qtn):
     assert qtn.Bucket(ops, list(range(2, 26))).info()["variant"] == 3
     assert qtn.Bucket(ops, list(range(2, 26)), variant=1).info()["variant"] == 0
     # the matrix form only in complex64
-    mm = [[0, 1, 2, 3, 4, 5], [0, 1, 2, 6, 7, 8]]
-    assert qtn.Bucket(mm, [3, 4, 5, 6, 7, 8], precision=qtn.QTN_C64, variant=3).info()["variant"] == 2
-    assert qtn.Bucket(mm, [3, 4, 5, 6, 7, 8], precision=qtn.QTN_C128, variant=3).info()["variant"] != 2
+    mm = [[0, 1, 2, 3, 4, 5, 6, 7], [0, 1, 2, 8, 9, 10, 11]]
+    for prec in (qtn.QTN_C64, qtn.QTN_C128):
+        assert qtn.Bucket(mm, list(range(3, 12)), precision=prec, variant=3).info()["variant"] == 2
+    # fewer than 4 kept labels private to the smaller side: no matrix form
+    mm3 = [[0, 1, 2, 3, 4, 5], [0, 1, 2, 6, 7, 8]]
+    assert qtn.Bucket(mm3, [3, 4, 5, 6, 7, 8], precision=qtn.QTN_C64, variant=3).info()["variant"] != 2
     bad = [
         (([[0, 1]], [0, 1]), "no summed"),            # nothing summed
         (([[0, 1, 2], [1, 2, 3]], [0, 3]), "union order"),

@@ -353,18 +353,21 @@ def test_mixed_precision(qtn, orc, gpu, n, p):
     assert np.array_equal(full[0], same[0]) and full[2] == same[2]
 
 
-@pytest.mark.parametrize("n,p", [(12, 2), (16, 3), (20, 3)])
+@pytest.mark.parametrize("n,p", [(14, 3), (16, 3), (20, 3)])
 def test_matrix_form_parity(qtn, orc, gpu, n, p):
-    """Matrix form (3M on the matrix cores, FP32) for every complex64 group
-    that has one, in its own launch, inside workgroups and in the persistent
-    executor."""
+    """Matrix form (four real products per complex product on the matrix
+    cores) for every group that has one: complex64 (FP32) in its own launch,
+    inside workgroups and in the persistent executors; complex128 (FP64) in
+    own launches."""
     inst = qs.instance(n, 3, p, 5)
     g, b = inst["angles"][0]
     ref, ref_en = orc.energy(n, inst["edges"], g, b, threads=8)
     for prec, cfg in [(1, dict(small_width=4)), (1, dict()), (1, dict(small_width=4, max_levels=1)),
                       (1, dict(small_width=4, max_levels=2)), (1, dict(executor=2, small_width=4)),
                       (1, dict(executor=4, small_width=4)),
-                      (2, dict(small_width=4, mixed_width=6)), (2, dict(mixed_width=1))]:
+                      (2, dict(small_width=4, mixed_width=6)), (2, dict(mixed_width=1)),
+                      (0, dict()), (0, dict(small_width=4, max_levels=2)),
+                      (2, dict(mixed_width=30))]:
         print(f"matrix form n={n} p={p} prec={prec} cfg={cfg}", flush=True)
         net = qtn.Network(n, inst["edges"], g, b, variant=3, **cfg)
         net.plan(prec)
