@@ -140,12 +140,12 @@ def kernel_name(rec):
         return None
     if rec["kind"] != 2:  # one instantiation serves every precision
         return base
-    if rec["variant"] == 2:  # complex64 only
-        return f"{base}<{'true' if rec['cvt'] else 'false'}>"
     t = "double2" if rec["prec"] == 0 else "float2"
     cvt = 'true' if rec['cvt'] else 'false'
     if rec["variant"] == 3:  # one instantiation per cell and serial bit count
         return f"{base}<{t}, {cvt}, {rec['knob']}, {rec['serial']}>"
+    if rec["variant"] == 2:  # one instantiation per column-block count
+        return f"{base}<{t}, {cvt}, {rec['knob']}>"
     return f"{base}<{t}, {cvt}>"
 
 
@@ -217,12 +217,13 @@ def roofline_of(log, workload_tag):
 WIDTH_CLASSES = ((0, 12), (13, 17), (18, 23), (24, 64))
 
 
-def launch_breakdown(log):
-    """Algorithmic GB/s of one timed evaluation per union-width class of the
-    launches (a workgroup launch counts under its first group), the groups
-    per second of the workgroup launches (the small buckets), and, for the
-    matrix-form launches, the three real products' flops (3M: 3 * 2 * 2^w
-    per group) against the FP32 matrix peak."""
+def launch_breakdown(log, n_sets=1):
+    """Algorithmic GB/s of one timed evaluation (n_sets angle sets) per
+    union-width class of the launches (a workgroup launch counts under its
+    first group), the groups per second of the workgroup launches (the small
+    buckets), and, for the matrix-form launches, the matrix cores' flops
+    (four real products, 8 * 2^w per group and angle set) against the matrix
+    peak of their precision."""
     cls = {}
     for lo, hi in WIDTH_CLASSES:
         rs = [r for r in log if lo <= r["w"] <= hi]
@@ -234,13 +235,17 @@ def launch_breakdown(log):
     blk_ms = sum(r["ms"] for r in blk)
     mm = [r for r in log if r["kind"] == 2 and r["variant"] == 2]
     mm_ms = sum(r["ms"] for r in mm)
-    mm_flops = sum(6.0 * 2.0 ** r["w"] for r in mm)
+    # matrix-core work: 2^w complex multiply-adds per angle set, four real
+    # products (8 real FLOPs) each, at the group's precision
+    mm_flops = sum(8.0 * 2.0 ** r["w"] * n_sets for r in mm)
+    mm_peak = (FP64_PEAK_TFLOPS if all(r["prec"] == 0 for r in mm) else FP32_PEAK_TFLOPS)
     return {"width_classes": cls,
             "small_groups_per_s": (sum(r["n_groups"] for r in blk) / blk_ms * 1e3
                                    if blk_ms > 0 else 0.0),
             "matrix_form": ({"launches": len(mm), "ms": mm_ms,
-                             "tflops_3m": mm_flops / mm_ms / 1e9,
-                             "frac_fp32_matrix_peak": mm_flops / mm_ms / 1e9 / FP32_PEAK_TFLOPS}
+                             "matrix_tflops": mm_flops / mm_ms / 1e9,
+                             "peak_tflops": mm_peak,
+                             "frac_matrix_peak": mm_flops / mm_ms / 1e9 / mm_peak}
                             if mm_ms > 0 else None)}
 
 
@@ -619,16 +624,20 @@ def run_micro(Q, torch, reps=5, n_random=8, seed=2204):
         del data
         gbs = info["bytes"] / ms / 1e6
         tflops = info["flops"] / ms / 1e9
-        # complex64 matrix form runs on the FP32 matrix cores; the rest on
-        # FP64 (complex128) or FP32 (complex64) vector ALUs
+        # FP64 (complex128) or FP32 (complex64) arithmetic: the vector ALUs,
+        # or in matrix form the matrix cores of the same precision, whose
+        # work is four real products (8 real FLOPs) per union point
         fpeak = FP64_PEAK_TFLOPS if prec == Q.QTN_C128 else FP32_PEAK_TFLOPS
+        row = {"w": info["w"], "L": info["L"], "mapping": ["generic", "streaming", "matrix form",
+                                                           "cells"][info["variant"]],
+               "kernel_ms": ms, "gbs": gbs, "tflops": tflops,
+               "paper_gflops": 8.0 * 2.0 ** info["w"] / ms / 1e6}
+        if info["variant"] == 2:
+            mt = 8.0 * 2.0 ** info["w"] / ms / 1e9
+            return {**row, "matrix_tflops": mt, "bound": "mfma", "frac": mt / fpeak}
         bound = "hbm" if info["flops"] / info["bytes"] < fpeak * 1e12 / (HBM_PEAK_GBS * 1e9) else "alu"
         frac = gbs / HBM_PEAK_GBS if bound == "hbm" else tflops / fpeak
-        return {"w": info["w"], "L": info["L"], "mapping": ["generic", "streaming", "matrix form",
-                                                            "cells"][info["variant"]],
-                "kernel_ms": ms, "gbs": gbs, "tflops": tflops,
-                "paper_gflops": 8.0 * 2.0 ** info["w"] / ms / 1e6,
-                "bound": bound, "frac": frac}
+        return {**row, "bound": bound, "frac": frac}
 
     rows = {}
     for name, prec in (("c128", Q.QTN_C128), ("c64", Q.QTN_C64)):
@@ -638,9 +647,8 @@ def run_micro(Q, torch, reps=5, n_random=8, seed=2204):
             n_ = list(range(8 + mb, 8 + mb + nb))
             shape = f"{1 << mb}x{1 << nb}x256"
             rows[f"matmul_{shape}_{name}"] = probe([k + m_, k + n_], m_ + n_, prec)
-            if prec == Q.QTN_C64:
-                rows[f"matmul_{shape}_{name}_matrix_form"] = probe([k + m_, k + n_], m_ + n_, prec,
-                                                                    variant=3)
+            rows[f"matmul_{shape}_{name}_matrix_form"] = probe([k + m_, k + n_], m_ + n_, prec,
+                                                                variant=3)
         a, bb, c, d, f = ([4 * i + j for j in range(4)] for i in range(5))
         rows[f"tncontract_fixed_n16_{name}"] = probe([bb + d + a + c, bb + d + c + f], a + c + f, prec)
         r = qs.Rng(seed)
@@ -753,7 +761,7 @@ def main():
            (f"_x{args.angle_batch}" if args.angle_batch > 1 else ""))
     main_log = net.launch_log()
     roof = roofline_of(main_log, tag)
-    breakdown = launch_breakdown(main_log)
+    breakdown = launch_breakdown(main_log, args.angle_batch)
     # the same plan, one qtn_contract call per angle set
     sequential = None
     if args.angle_batch > 1 and args.variants:

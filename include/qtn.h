@@ -272,7 +272,8 @@ typedef struct qtn_launch_rec {
     int32_t prec;      /* arithmetic of the first group: QTN_C128/QTN_C64 */
     int32_t cvt;       /* 1: some operand of it is stored in the other
                           precision and converted on load                 */
-    int32_t knob;      /* streaming: lane-summed bits; cells: cell bits   */
+    int32_t knob;      /* streaming: lane-summed bits; cells: cell bits;
+                          matrix form: 16-column blocks per tile        */
     int32_t serial;    /* streaming and cells: serially walked summed bits */
     double ms;         /* HIP-event duration                              */
     double bytes;      /* algorithmic bytes of the launch                 */

@@ -333,7 +333,7 @@ constexpr int kTuneSingleWidth = 16;
 
 // Configurations measured by the autotuner: every group in its own launch
 // with the generic mapping, with the streaming mapping at 1, 2, 3
-// lane-summed bits, in matrix form (complex64 groups that have one), or with
+// lane-summed bits, in matrix form (groups that have one), or with
 // the cell mapping at 3 or 4 cell bits (groups wide enough for it).
 const std::vector<Force> &tune_candidates() {
   static const std::vector<Force> c = {{1, 1, 2}, {1, 2, 1}, {1, 2, 2}, {1, 2, 3},
@@ -435,8 +435,11 @@ int describe_group(const Group &G, const ConePlan &pl, const GroupEnv &env, Sche
     dg.n_mb = (uint8_t)gsh.mbits.size();
     dg.n_nb = (uint8_t)gsh.nbits.size();
     dg.n_bb = (uint8_t)gsh.bbits.size();
+    // column blocks of 16 per tile: as many as the n range fills (n >= 4 bits)
+    dg.rls = (uint8_t)(dg.n_nb >= 6 ? 4 : (dg.n_nb == 5 ? 2 : 1));
+    const uint64_t tn = 16ull * dg.rls;
     const uint64_t mt = ((1ull << dg.n_mb) + kMmTM - 1) / kMmTM;
-    const uint64_t nt = ((1ull << dg.n_nb) + kMmTN - 1) / kMmTN;
+    const uint64_t nt = ((1ull << dg.n_nb) + tn - 1) / tn;
     const uint64_t tiles = (1ull << dg.n_bb) * mt * nt;
     if (tiles > 0xFFFFFFFFull) return set_err(QTN_ERANGE, "matrix-form group too large");
     dg.n_units = (uint32_t)tiles;
@@ -1647,7 +1650,7 @@ static int record_timing(qtn_network *net, const Exec &X, const Timer &tm, qtn_t
           lr.n_units = (int32_t)g.n_units;
           lr.prec = g.prec;
           lr.cvt = g.cvt;
-          lr.knob = g.variant == kVarStream || g.variant == kVarCell ? g.rls : 0;
+          lr.knob = g.variant == kVarStream || g.variant == kVarCell || g.variant == kVarMfma ? g.rls : 0;
           lr.serial = g.variant == kVarStream || g.variant == kVarCell ? g.sl : 0;
         }
         net->launch_log.push_back(lr);
@@ -1902,8 +1905,10 @@ static int autotune_sets(qtn_network *net, void *d_workspace, size_t bytes, void
         char *ws = (char *)d_workspace;
         const Schedule &s = ex.sched;
         for (size_t i = 0; i < s.singles.size(); i++) {
-          // the cell mapping only runs in its own launch
-          if (s.groups[s.singles[i]].variant == kVarCell) continue;
+          // the cell mapping, and the complex128 matrix form, only run in
+          // their own launch
+          const DevGroup &dg = s.groups[s.singles[i]];
+          if (dg.variant == kVarCell || (dg.variant == kVarMfma && dg.prec == 0)) continue;
           if ((rc = tb.begin(QTN_K_BLOCK, ex.rt.main, s.singles[i], 1, 0, 0, true))) {
             give_back();
             return rc;
@@ -2407,7 +2412,7 @@ int qtn_bucket_get_info(const qtn_bucket *b, qtn_bucket_info *out) {
   r.L = b->hg.L;
   r.n_ops = b->hg.n_ops;
   r.variant = b->hg.variant;
-  r.knob = b->hg.variant == kVarStream || b->hg.variant == kVarCell ? b->hg.rls : 0;
+  r.knob = b->hg.variant == kVarStream || b->hg.variant == kVarCell || b->hg.variant == kVarMfma ? b->hg.rls : 0;
   r.serial = b->hg.variant == kVarStream || b->hg.variant == kVarCell ? b->hg.sl : 0;
   r.n_units = b->hg.n_units;
   r.bytes = b->bytes;

@@ -84,12 +84,13 @@ constexpr int cell_table_words(int cb) { return (1 << cb) + kCellURuns / 2 + 1; 
 constexpr int kCellMaxLdsWords = 16384;  // 64 KiB per workgroup
 
 // Matrix form (kVarMfma): ops are [side A..., side B...] with n_unit = |side
-// A|, n_step = |side B|.  A work unit is one kMmTM x kMmTN (m x n) output
-// tile of one batch index; a whole workgroup computes it, kMmKC summed
-// indices per LDS chunk.  Tables (int32, in the stab area): the group's at
-// gtab, kMmTM union-bit words for the tile's rows then kMmTN for its columns;
-// each operand's at its stab, kMmTM row (side A) or kMmTN column (side B)
-// element offsets, then 2^L offsets of the summed indices.
+// A|, n_step = |side B|.  A work unit is one kMmTM x 16 rls (m x n) output
+// tile of one batch index (rls: column blocks, 1, 2 or 4, the most the n
+// range fills); a whole workgroup computes it, at most kMmKC summed indices
+// per LDS chunk.  Tables (int32, in the stab area): the group's at gtab,
+// kMmTM union-bit words for the tile's rows then kMmTN for its columns; each
+// operand's at its stab, kMmTM row (side A) or kMmTN column (side B) element
+// offsets, then 2^L offsets of the summed indices.
 constexpr int kMmTM = 64, kMmTN = 64, kMmKC = 16, kMmMaxOps = 64;
 
 // Generic mapping: 2 register bits and 6 lane bits per wave unit.

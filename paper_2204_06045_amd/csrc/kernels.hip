@@ -763,48 +763,53 @@ template <> struct MmTypes<float2> {
   __device__ static int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
-// LDS bytes of a matrix-form tile in arithmetic type T: the operands' tile
-// bases (kMmMaxOps words, padded to 256 bytes), the A chunk
-// [kMmTM][kMmKC + 1] and the B chunk [kMmKC][kMmTN + 1].
-template <class T> constexpr int mm_lds_bytes() {
-  return 256 + (kMmTM * (kMmKC + 1) + kMmKC * (kMmTN + 1)) * (int)sizeof(T);
+// LDS bytes of a matrix-form tile in arithmetic type T with NCB 16-column
+// blocks: the operands' tile bases (kMmMaxOps words, padded to 256 bytes),
+// the A chunk [kMmTM][kMmKC + 1] and the B chunk [kMmKC][16 NCB + 1].
+template <class T, int NCB> constexpr int mm_lds_bytes() {
+  return 256 + (kMmTM * (kMmKC + 1) + kMmKC * (16 * NCB + 1)) * (int)sizeof(T);
 }
 static_assert(kMmMaxOps * 4 <= 256, "matrix-form operand bases");
-static_assert(mm_lds_bytes<float2>() <= kStreamMaxOps * 64 * 4,
+static_assert(mm_lds_bytes<float2, 4>() <= kStreamMaxOps * 64 * 4,
               "complex64 matrix tiles must fit the workgroup kernels' LDS");
 
-// One kMmTM x kMmTN output tile of a matrix-form group, with the whole
+// One kMmTM x 16 NCB output tile of a matrix-form group, with the whole
 // workgroup:
 //   out[bt, m, n] = sum_k At[bt, m, k] Bt[bt, k, n],
 // At (Bt) the product of the group's side-A (side-B) operands, k over the L
-// summed union bits.  Per chunk of kMmKC summed indices both factors are
-// gathered into LDS: thread t takes k = t % 16 (the lowest union bits, so
-// that threads with neighbouring k read neighbouring elements) and rows or
-// columns t / 16 + 16j; an operand's element offset is its tile base plus
-// table entries for the row (or column) and for k (planner-built pext
-// tables).  Then wave v multiplies its 16 rows into four 16 x 16 column
-// blocks: four real products per complex product, accumulated in the
-// group's precision.  Operands: [side A..., side B...]; G.gtab holds the
-// union bits of the tile's rows (kMmTM words) and columns (kMmTN words);
-// operand k's table (at its stab) holds kMmTM row (side A) or kMmTN column
-// (side B) offsets, then 2^L summed-index offsets.  Unit bits (uperm): m
-// bits, then n bits, then batch bits.
-template <class T, bool CVT>
+// summed union bits.  Per chunk of KC = min(max(2^L, 4), kMmKC) summed
+// indices both factors are gathered into LDS: thread t takes k = t % KC (the
+// lowest union bits, so that threads with neighbouring k read neighbouring
+// elements) and the rows (columns) t / KC + (256 / KC) j.  An operand's
+// element offset is its tile base plus table entries for the row (column)
+// and for k; both tables are pext images of disjoint bit sets, so an entry
+// splits into a per-thread part (row and k below the pass and chunk sizes)
+// and parts uniform over the block (the pass and the chunk).  Then wave v
+// multiplies its 16 rows into NCB 16 x 16 column blocks: four real products
+// per complex product, accumulated in the group's precision.  Operands:
+// [side A..., side B...]; G.gtab holds the union bits of the tile's rows
+// (kMmTM words) and columns (kMmTN words, the first 16 NCB used); operand
+// k's table (at its stab) holds kMmTM row (side A) or kMmTN column (side B)
+// offsets, then 2^L summed-index offsets.  Unit bits (uperm): m bits, then n
+// bits, then batch bits.
+template <class T, bool CVT, int NCB>
 __device__ void mm_tile(const GI &G, const DevOp *__restrict__ gops, const int32_t *__restrict__ stab,
                         const uint8_t *__restrict__ bits, char *__restrict__ data, char *lds,
                         uint32_t tile, uint32_t set) {
   typedef typename MmTypes<T>::R R;
   typedef typename MmTypes<T>::V V;
+  constexpr int TN = 16 * NCB, TNB = NCB == 1 ? 4 : (NCB == 2 ? 5 : 6);
+  constexpr int AP = kMmTM * kMmKC / 256;  // most side-A passes (KC = kMmKC)
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int nM = G.n_mb, nN = G.n_nb, nB = G.n_bb, L = G.L;
   const uint32_t M = 1u << nM, N = 1u << nN, K = 1u << L;
-  const uint32_t mt = (M + kMmTM - 1) / kMmTM, nt = (N + kMmTN - 1) / kMmTN;
+  const uint32_t mt = (M + kMmTM - 1) / kMmTM, nt = (N + TN - 1) / TN;
   const uint32_t bt = tile / (mt * nt), rem = tile % (mt * nt);
   const uint32_t mi = rem / nt, ni = rem % nt;
-  const uint32_t m0 = mi * kMmTM, n0 = ni * kMmTN;
+  const uint32_t m0 = mi * kMmTM, n0 = ni * TN;
   // union bits of the tile: batch bits, and the m (n) bits above the
-  // in-tile ones (a tile spans the lowest 6 m bits and 6 n bits)
-  const int mlo = nM < 6 ? nM : 6, nlo = nN < 6 ? nN : 6;
+  // in-tile ones (a tile spans the lowest 6 m bits and TNB n bits)
+  const int mlo = nM < 6 ? nM : 6, nlo = nN < TNB ? nN : TNB;
   const uint32_t Ib = unit_bits(bt, bits, nB, nM + nN) | unit_bits(mi, bits, nM - mlo, mlo) |
                       unit_bits(ni, bits, nN - nlo, nM + nlo);
   const int na = G.n_unit, nb = G.n_step;
@@ -813,54 +818,73 @@ __device__ void mm_tile(const GI &G, const DevOp *__restrict__ gops, const int32
   T *sA = (T *)(lds + 256), *sB = sA + kMmTM * (kMmKC + 1);
   if (tid < na + nb) base[tid] = pext_runs(Ib, gops[tid]);
   __syncthreads();
-  V cr[4], ci[4];
+  V cr[NCB], ci[NCB];
 #pragma unroll
-  for (int s = 0; s < 4; s++)
+  for (int s = 0; s < NCB; s++)
 #pragma unroll
     for (int r = 0; r < 4; r++) cr[s][r] = ci[s][r] = (R)0;
-  const int kl = tid & 15, rl = tid >> 4;  // k, and the first row / column, of this thread
-  for (uint32_t k0 = 0; k0 < K; k0 += kMmKC) {
+  // chunk size KC = 2^kb, passes of RP = 256 / KC rows (columns)
+  const int kb = L < 2 ? 2 : (L > 4 ? 4 : L), KC = 1 << kb, RP = 256 >> kb;
+  const int kl = tid & (KC - 1), rl = tid >> kb;
+  const int pa = kMmTM / RP, pb = (TN + RP - 1) / RP;
+  const int klt = (uint32_t)kl < K ? kl : 0;  // table index of kl (2^L < KC: padding)
+  for (uint32_t k0 = 0; k0 < K; k0 += (uint32_t)KC) {
     const uint32_t k = k0 + (uint32_t)kl;
-    // side A: rows rl + 16j
+    // side A: rows rl + RP j
+    T va[AP];
+    bool oka[AP];
 #pragma unroll
-    for (int j = 0; j < kMmTM / 16; j++) {
-      const int row = rl + 16 * j;
-      T v = make_c<T>(0.0, 0.0);
-      if (m0 + (uint32_t)row < M && k < K) {
-        v = make_c<T>(1.0, 0.0);
-        for (int q = 0; q < na; q++) {
-          const DevOp &o = gops[q];
-          const int32_t *t = stab + o.stab;
-          const uint32_t e = base[q] + (uint32_t)t[row] + (uint32_t)t[kMmTM + k];
-          v = cmul(v, ld_elem<T, CVT>(opnd(data, o, set), e, op_dt(o)));
-        }
-      }
-      sA[row * (kMmKC + 1) + kl] = v;
+    for (int j = 0; j < AP; j++) {
+      oka[j] = j < pa && m0 + (uint32_t)(rl + RP * j) < M && k < K;
+      va[j] = make_c<T>(1.0, 0.0);
     }
-    // side B: columns rl + 16j
+    for (int q = 0; q < na; q++) {
+      const DevOp &o = gops[q];
+      const int32_t *t = stab + o.stab;
+      const char *p = opnd(data, o, set);
+      const int dt = op_dt(o);
+      const uint32_t e0 = base[q] + (uint32_t)t[rl] + (uint32_t)t[kMmTM + klt] +
+                          (uint32_t)t[kMmTM + k0];
 #pragma unroll
-    for (int j = 0; j < kMmTN / 16; j++) {
-      const int col = rl + 16 * j;
-      T v = make_c<T>(0.0, 0.0);
-      if (n0 + (uint32_t)col < N && k < K) {
-        v = make_c<T>(1.0, 0.0);
-        for (int q = na; q < na + nb; q++) {
-          const DevOp &o = gops[q];
-          const int32_t *t = stab + o.stab;
-          const uint32_t e = base[q] + (uint32_t)t[col] + (uint32_t)t[kMmTN + k];
-          v = cmul(v, ld_elem<T, CVT>(opnd(data, o, set), e, op_dt(o)));
-        }
-      }
-      sB[kl * (kMmTN + 1) + col] = v;
+      for (int j = 0; j < AP; j++)
+        if (oka[j]) va[j] = cmul(va[j], ld_elem<T, CVT>(p, e0 + (uint32_t)t[RP * j], dt));
+    }
+#pragma unroll
+    for (int j = 0; j < AP; j++)
+      if (j < pa) sA[(rl + RP * j) * (kMmKC + 1) + kl] = oka[j] ? va[j] : make_c<T>(0.0, 0.0);
+    // side B: columns rl + RP j
+    T vb[NCB];
+    bool okb[NCB];
+#pragma unroll
+    for (int j = 0; j < NCB; j++) {
+      const int col = rl + RP * j;
+      okb[j] = j < pb && col < TN && n0 + (uint32_t)col < N && k < K;
+      vb[j] = make_c<T>(1.0, 0.0);
+    }
+    for (int q = na; q < na + nb; q++) {
+      const DevOp &o = gops[q];
+      const int32_t *t = stab + o.stab;
+      const char *p = opnd(data, o, set);
+      const int dt = op_dt(o);
+      const int c0 = rl < TN ? rl : 0;
+      const uint32_t e0 = base[q] + (uint32_t)t[c0] + (uint32_t)t[kMmTN + klt] +
+                          (uint32_t)t[kMmTN + k0];
+#pragma unroll
+      for (int j = 0; j < NCB; j++)
+        if (okb[j]) vb[j] = cmul(vb[j], ld_elem<T, CVT>(p, e0 + (uint32_t)t[RP * j], dt));
+    }
+#pragma unroll
+    for (int j = 0; j < NCB; j++) {
+      const int col = rl + RP * j;
+      if (j < pb && col < TN) sB[kl * (TN + 1) + col] = okb[j] ? vb[j] : make_c<T>(0.0, 0.0);
     }
     __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < kMmKC; kk += 4) {
+    for (int kk = 0; kk < KC; kk += 4) {
       const T a = sA[(wave * 16 + (lane & 15)) * (kMmKC + 1) + kk + (lane >> 4)];
       const R ar = (R)a.x, ai = (R)a.y, nai = -ai;
 #pragma unroll
-      for (int s = 0; s < 4; s++) {
-        const T b = sB[(kk + (lane >> 4)) * (kMmTN + 1) + 16 * s + (lane & 15)];
+      for (int s = 0; s < NCB; s++) {
+        const T b = sB[(kk + (lane >> 4)) * (TN + 1) + 16 * s + (lane & 15)];
         const R br = (R)b.x, bi = (R)b.y;
         cr[s] = mm_step(ar, br, cr[s]);
         cr[s] = mm_step(nai, bi, cr[s]);
@@ -873,7 +897,7 @@ __device__ void mm_tile(const GI &G, const DevOp *__restrict__ gops, const int32
   T *out = (T *)outp(data, G, set);
   const uint32_t nout = 1u << (G.w - L);
 #pragma unroll
-  for (int s = 0; s < 4; s++) {
+  for (int s = 0; s < NCB; s++) {
     const int col = 16 * s + (lane & 15);
     if (n0 + (uint32_t)col >= N) continue;
 #pragma unroll
@@ -887,6 +911,17 @@ __device__ void mm_tile(const GI &G, const DevOp *__restrict__ gops, const int32
       if (o < nout) out[o] = v;
     }
   }
+}
+
+// A matrix-form tile with the group's column-block count (G.rls: 1, 2, 4).
+template <class T, bool CVT>
+__device__ __forceinline__ void mm_tile_any(const GI &G, const DevOp *__restrict__ gops,
+                                            const int32_t *__restrict__ stab,
+                                            const uint8_t *__restrict__ bits, char *__restrict__ data,
+                                            char *lds, uint32_t tile, uint32_t set) {
+  if (G.rls == 1) mm_tile<T, CVT, 1>(G, gops, stab, bits, data, lds, tile, set);
+  else if (G.rls == 2) mm_tile<T, CVT, 2>(G, gops, stab, bits, data, lds, tile, set);
+  else mm_tile<T, CVT, 4>(G, gops, stab, bits, data, lds, tile, set);
 }
 
 // One group's wave units [u0, u1) of angle set `set` over the block's waves,
@@ -915,10 +950,10 @@ __device__ __forceinline__ void run_group(const GI &G, int g, const DevOp *__res
     // computed by the whole block
     if (G.cvt)
       for (uint32_t u = u0; u < u1; u++)
-        mm_tile<float2, true>(G, gops, stab, ub, data, (char *)s_lane, u, set);
+        mm_tile_any<float2, true>(G, gops, stab, ub, data, (char *)s_lane, u, set);
     else
       for (uint32_t u = u0; u < u1; u++)
-        mm_tile<float2, false>(G, gops, stab, ub, data, (char *)s_lane, u, set);
+        mm_tile_any<float2, false>(G, gops, stab, ub, data, (char *)s_lane, u, set);
   } else if (G.variant == kVarStream) {
     stream_setup(G, gops, s_lane);
     __syncthreads();
@@ -1033,20 +1068,20 @@ __global__ __launch_bounds__(kBlock) void k_wide_generic(char *__restrict__ data
   }
 }
 
-template <class T, bool CVT>
+template <class T, bool CVT, int NCB>
 __global__ __launch_bounds__(kBlock) void k_wide_mfma(char *__restrict__ data,
                                                       const DevGroup *__restrict__ groups,
                                                       const DevOp *__restrict__ ops,
                                                       const int32_t *__restrict__ stab,
                                                       const uint8_t *__restrict__ uperm, int gid,
                                                       uint32_t n_sets) {
-  __shared__ __align__(16) char s_tile[mm_lds_bytes<T>()];
+  __shared__ __align__(16) char s_tile[mm_lds_bytes<T, NCB>()];
   const GI G = load_group(groups + gid);
   const UnitWalk W = wide_walk(G.n_units * n_sets, 1, 0);
   for (uint32_t f = W.first; f < W.end; f += W.stride) {
     const uint32_t set = f / G.n_units;
-    mm_tile<T, CVT>(G, ops + G.op_begin, stab, uperm + 32 * gid, data, s_tile,
-                    f - set * G.n_units, set);
+    mm_tile<T, CVT, NCB>(G, ops + G.op_begin, stab, uperm + 32 * gid, data, s_tile,
+                         f - set * G.n_units, set);
   }
 }
 
@@ -1478,17 +1513,24 @@ hipError_t launch_wide_group(const DevGroup &hg, void *data, const DevGroup *gro
   const bool cvt = hg.cvt != 0;
   if (hg.variant == kVarMfma) {
     // a unit is one tile of the whole block
-#define QTN_MM_LAUNCH(T, C)                                                                 \
-  do {                                                                                     \
-    const int nb = wide_grid(k_wide_mfma<T, C>, 0, units, 1);                              \
-    QTN_LAUNCH(t0, t1, (k_wide_mfma<T, C>), dim3(nb), dim3(kBlock), s, d, groups, ops, stab, \
-               uperm, group, ns);                                                          \
+#define QTN_MM_LAUNCH3(T, C, NCB)                                                             \
+  do {                                                                                       \
+    const int nb = wide_grid(k_wide_mfma<T, C, NCB>, 0, units, 1);                           \
+    QTN_LAUNCH(t0, t1, (k_wide_mfma<T, C, NCB>), dim3(nb), dim3(kBlock), s, d, groups, ops,   \
+               stab, uperm, group, ns);                                                      \
+  } while (0)
+#define QTN_MM_LAUNCH(T, C)                                   \
+  do {                                                        \
+    if (hg.rls == 1) QTN_MM_LAUNCH3(T, C, 1);                 \
+    else if (hg.rls == 2) QTN_MM_LAUNCH3(T, C, 2);            \
+    else QTN_MM_LAUNCH3(T, C, 4);                             \
   } while (0)
     if (hg.prec == kPrecC128 && !cvt) QTN_MM_LAUNCH(double2, false);
     else if (hg.prec == kPrecC128) QTN_MM_LAUNCH(double2, true);
     else if (!cvt) QTN_MM_LAUNCH(float2, false);
     else QTN_MM_LAUNCH(float2, true);
 #undef QTN_MM_LAUNCH
+#undef QTN_MM_LAUNCH3
     return hipGetLastError();
   }
   if (hg.prec == kPrecC128 && !cvt)

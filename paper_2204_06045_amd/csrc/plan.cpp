@@ -461,7 +461,13 @@ bool gemm_shape(const Group &G, const ConePlan &pl, GemmShape *gs) {
     for (auto &r : s.role) r = (int8_t)(1 - r);
     s.mbits.swap(s.nbits);
   }
-  (void)kept;
+  // an operand with no m or n bit (only batch and summed bits) fits either
+  // side: side B, whose factor has fewer entries (N <= M)
+  uint32_t mn = 0;
+  for (int q : s.mbits) mn |= 1u << q;
+  for (int q : s.nbits) mn |= 1u << q;
+  for (int k = 0; k < n; k++)
+    if (k != s.a && k != s.b && (G.ops[k].mask & mn) == 0) s.role[k] = 1;
   // at least one full 16-wide block of the matrix cores each way
   if (s.nbits.size() < 4) return false;
   if (gs) *gs = s;
