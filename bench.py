@@ -711,6 +711,9 @@ def main():
                     help="launch eagerly instead of replaying the captured HIP graph")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 1 GiB device copy (byte-counter calibration)")
+    ap.add_argument("--micro", action="store_true",
+                    help="only the single-bucket probes (matrix products, fixed and random "
+                         "contractions): one JSON line of their rows")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -724,6 +727,9 @@ def main():
     import qaoa_synth as qs
 
     torch.cuda.set_device(0)
+    if args.micro:
+        print(json.dumps({"micro": run_micro(Q, torch)}))
+        return
     inst = qs.instance(30, 3, 4, args.seed, args.angle_sets)
     prec = {"c128": Q.QTN_C128, "c64": Q.QTN_C64, "mixed": Q.QTN_MIXED}[args.precision]
     log(f"main row: {args.precision} levels={args.levels} streams={args.streams}")
