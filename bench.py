@@ -222,7 +222,7 @@ def launch_breakdown(log, n_sets=1):
     union-width class of the launches (a workgroup launch counts under its
     first group), the groups per second of the workgroup launches (the small
     buckets), and, for the matrix-form launches, the matrix cores' flops
-    (four real products, 8 * 2^w per group and angle set) against the matrix
+    (3M: three real products, 6 * 2^w per group and angle set) against the matrix
     peak of their precision."""
     cls = {}
     for lo, hi in WIDTH_CLASSES:
@@ -235,9 +235,9 @@ def launch_breakdown(log, n_sets=1):
     blk_ms = sum(r["ms"] for r in blk)
     mm = [r for r in log if r["kind"] == 2 and r["variant"] == 2]
     mm_ms = sum(r["ms"] for r in mm)
-    # matrix-core work: 2^w complex multiply-adds per angle set, four real
-    # products (8 real FLOPs) each, at the group's precision
-    mm_flops = sum(8.0 * 2.0 ** r["w"] * n_sets for r in mm)
+    # matrix-core work: 2^w complex multiply-adds per angle set, three real
+    # products (3M, 6 real FLOPs) each, at the group's precision
+    mm_flops = sum(6.0 * 2.0 ** r["w"] * n_sets for r in mm)
     mm_peak = (FP64_PEAK_TFLOPS if all(r["prec"] == 0 for r in mm) else FP32_PEAK_TFLOPS)
     return {"width_classes": cls,
             "small_groups_per_s": (sum(r["n_groups"] for r in blk) / blk_ms * 1e3
@@ -626,14 +626,14 @@ def run_micro(Q, torch, reps=5, n_random=8, seed=2204):
         tflops = info["flops"] / ms / 1e9
         # FP64 (complex128) or FP32 (complex64) arithmetic: the vector ALUs,
         # or in matrix form the matrix cores of the same precision, whose
-        # work is four real products (8 real FLOPs) per union point
+        # work is three real products (3M, 6 real FLOPs) per union point
         fpeak = FP64_PEAK_TFLOPS if prec == Q.QTN_C128 else FP32_PEAK_TFLOPS
         row = {"w": info["w"], "L": info["L"], "mapping": ["generic", "streaming", "matrix form",
                                                            "cells"][info["variant"]],
                "kernel_ms": ms, "gbs": gbs, "tflops": tflops,
                "paper_gflops": 8.0 * 2.0 ** info["w"] / ms / 1e6}
         if info["variant"] == 2:
-            mt = 8.0 * 2.0 ** info["w"] / ms / 1e9
+            mt = 6.0 * 2.0 ** info["w"] / ms / 1e9
             return {**row, "matrix_tflops": mt, "bound": "mfma", "frac": mt / fpeak}
         bound = "hbm" if info["flops"] / info["bytes"] < fpeak * 1e12 / (HBM_PEAK_GBS * 1e9) else "alu"
         frac = gbs / HBM_PEAK_GBS if bound == "hbm" else tflops / fpeak

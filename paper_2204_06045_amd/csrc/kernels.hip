@@ -26,9 +26,10 @@
 // level in hierarchical order with register adds and lane butterflies.  Used
 // for groups with more operands than the streaming LDS tables hold.
 //
-// Matrix form (kVarMfma, complex64).  A group whose operands reduce to two
-// factors over the summed indices is a batched complex matrix product; it
-// runs as three real FP32 products on the matrix cores (3M).
+// Matrix form (kVarMfma).  A group whose operands split into two sides is a
+// batched complex matrix product of the sides' factors; it runs as three real
+// products on the matrix cores (3M), FP32 for complex64 and FP64 for
+// complex128 groups.
 #include <cstddef>
 #include <map>
 #include <mutex>
@@ -785,8 +786,8 @@ static_assert(mm_lds_bytes<float2, 4>() <= kStreamMaxOps * 64 * 4,
 // and for k; both tables are pext images of disjoint bit sets, so an entry
 // splits into a per-thread part (row and k below the pass and chunk sizes)
 // and parts uniform over the block (the pass and the chunk).  Then wave v
-// multiplies its 16 rows into NCB 16 x 16 column blocks: four real products
-// per complex product, accumulated in the group's precision.  Operands:
+// multiplies its 16 rows into NCB 16 x 16 column blocks: three real products
+// per complex product (3M), accumulated in the group's precision.  Operands:
 // [side A..., side B...]; G.gtab holds the union bits of the tile's rows
 // (kMmTM words) and columns (kMmTN words, the first 16 NCB used); operand
 // k's table (at its stab) holds kMmTM row (side A) or kMmTN column (side B)
@@ -818,11 +819,13 @@ __device__ void mm_tile(const GI &G, const DevOp *__restrict__ gops, const int32
   T *sA = (T *)(lds + 256), *sB = sA + kMmTM * (kMmKC + 1);
   if (tid < na + nb) base[tid] = pext_runs(Ib, gops[tid]);
   __syncthreads();
-  V cr[NCB], ci[NCB];
+  // 3M: t1 = sum Ar Br, t2 = sum Ai Bi, t3 = sum (Ar + Ai)(Br + Bi); then
+  // Re = t1 - t2, Im = t3 - t1 - t2
+  V t1[NCB], t2[NCB], t3[NCB];
 #pragma unroll
   for (int s = 0; s < NCB; s++)
 #pragma unroll
-    for (int r = 0; r < 4; r++) cr[s][r] = ci[s][r] = (R)0;
+    for (int r = 0; r < 4; r++) t1[s][r] = t2[s][r] = t3[s][r] = (R)0;
   // chunk size KC = 2^kb, passes of RP = 256 / KC rows (columns)
   const int kb = L < 2 ? 2 : (L > 4 ? 4 : L), KC = 1 << kb, RP = 256 >> kb;
   const int kl = tid & (KC - 1), rl = tid >> kb;
@@ -881,15 +884,14 @@ __device__ void mm_tile(const GI &G, const DevOp *__restrict__ gops, const int32
     __syncthreads();
     for (int kk = 0; kk < KC; kk += 4) {
       const T a = sA[(wave * 16 + (lane & 15)) * (kMmKC + 1) + kk + (lane >> 4)];
-      const R ar = (R)a.x, ai = (R)a.y, nai = -ai;
+      const R ar = (R)a.x, ai = (R)a.y, as = ar + ai;
 #pragma unroll
       for (int s = 0; s < NCB; s++) {
         const T b = sB[(kk + (lane >> 4)) * (TN + 1) + 16 * s + (lane & 15)];
         const R br = (R)b.x, bi = (R)b.y;
-        cr[s] = mm_step(ar, br, cr[s]);
-        cr[s] = mm_step(nai, bi, cr[s]);
-        ci[s] = mm_step(ar, bi, ci[s]);
-        ci[s] = mm_step(ai, br, ci[s]);
+        t1[s] = mm_step(ar, br, t1[s]);
+        t2[s] = mm_step(ai, bi, t2[s]);
+        t3[s] = mm_step(as, br + bi, t3[s]);
       }
     }
     __syncthreads();
@@ -899,17 +901,22 @@ __device__ void mm_tile(const GI &G, const DevOp *__restrict__ gops, const int32
 #pragma unroll
   for (int s = 0; s < NCB; s++) {
     const int col = 16 * s + (lane & 15);
-    if (n0 + (uint32_t)col >= N) continue;
+    const bool okc = n0 + (uint32_t)col < N;
 #pragma unroll
     for (int r = 0; r < 4; r++) {
-      const int row = wave * 16 + MmTypes<T>::row(lane, r);
-      if (m0 + (uint32_t)row >= M) continue;
-      const uint32_t o = (Ib | (uint32_t)mu[row] | (uint32_t)nu[col]) >> L;
+      // combined in every lane, stored where the row and column exist
       T v;
-      v.x = cr[s][r];
-      v.y = ci[s][r];
-      if (o < nout) out[o] = v;
+      v.x = t1[s][r] - t2[s][r];
+      v.y = t3[s][r] - t1[s][r] - t2[s][r];
+      const int row = wave * 16 + MmTypes<T>::row(lane, r);
+      if (okc && m0 + (uint32_t)row < M) {
+        const uint32_t o = (Ib | (uint32_t)mu[row] | (uint32_t)nu[col]) >> L;
+        if (o < nout) out[o] = v;
+      }
     }
+    // one column block at a time: keeps the accumulators that are read out
+    // into vector registers to one block's worth
+    __builtin_amdgcn_sched_barrier(0);
   }
 }
 
@@ -1068,8 +1075,15 @@ __global__ __launch_bounds__(kBlock) void k_wide_generic(char *__restrict__ data
   }
 }
 
+// Waves per SIMD the matrix-form kernel is compiled for: three accumulator
+// sets of NCB blocks (3M) fill many registers, and left alone the compiler
+// spends more on staging than this occupancy allows.
+template <class T, int NCB> constexpr int mm_waves() {
+  return sizeof(T) == 8 ? (NCB == 4 ? 4 : 5) : (NCB == 4 ? 3 : 4);
+}
+
 template <class T, bool CVT, int NCB>
-__global__ __launch_bounds__(kBlock) void k_wide_mfma(char *__restrict__ data,
+__global__ __launch_bounds__(kBlock, (mm_waves<T, NCB>())) void k_wide_mfma(char *__restrict__ data,
                                                       const DevGroup *__restrict__ groups,
                                                       const DevOp *__restrict__ ops,
                                                       const int32_t *__restrict__ stab,

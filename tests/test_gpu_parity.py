@@ -355,7 +355,7 @@ def test_mixed_precision(qtn, orc, gpu, n, p):
 
 @pytest.mark.parametrize("n,p", [(14, 3), (16, 3), (20, 3)])
 def test_matrix_form_parity(qtn, orc, gpu, n, p):
-    """Matrix form (four real products per complex product on the matrix
+    """Matrix form (3M: three real products per complex product on the matrix
     cores) for every group that has one: complex64 (FP32) in its own launch,
     inside workgroups and in the persistent executors; complex128 (FP64) in
     own launches."""
