@@ -485,11 +485,11 @@ def run_gradient(Q, torch, inst, iters=12, lr=0.02, h=1e-4, order_trials=64, sli
             "learning_rate": lr, "step_h": h, "energy_start": e0, "energy_end": e_end}
 
 
-def run_cfg4(Q, torch, steps=10, autotune=True):
+def run_cfg4(Q, torch, steps=10, autotune=True, only=None):
     """4-regular N=40, p=3 (80 light cones): complex128, complex64 and mixed
     precision (groups of width >= 18 in complex64, in matrix form on the
     matrix cores where a group reshapes), each with its per-edge error
-    against the stored FP64 oracle values."""
+    against the stored FP64 oracle values.  `only`: one row's name."""
     import numpy as np
     with open(os.path.join(ROOT, "tests", "golden", "cfg4_oracle.json")) as f:
         gd = json.load(f)
@@ -497,6 +497,8 @@ def run_cfg4(Q, torch, steps=10, autotune=True):
     rows = {}
     for name, prec, variant in (("c128", Q.QTN_C128, 0), ("c64", Q.QTN_C64, 0),
                                 ("mixed", Q.QTN_MIXED, 0), ("mixed_matrix", Q.QTN_MIXED, 3)):
+        if only is not None and name != only:
+            continue
         net = Q.Network(gd["n"], gd["edges"], gd["gamma"], gd["beta"], order_trials=16,
                         variant=variant)
         net.plan(prec)
@@ -711,6 +713,9 @@ def main():
                     help="launch eagerly instead of replaying the captured HIP graph")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 1 GiB device copy (byte-counter calibration)")
+    ap.add_argument("--cfg4", nargs="?", const="all", default=None,
+                    choices=("all", "c128", "c64", "mixed", "mixed_matrix"),
+                    help="only the 4-regular N=40 p=3 rows (or one of them): one JSON line")
     ap.add_argument("--micro", action="store_true",
                     help="only the single-bucket probes (matrix products, fixed and random "
                          "contractions): one JSON line of their rows")
@@ -729,6 +734,10 @@ def main():
     torch.cuda.set_device(0)
     if args.micro:
         print(json.dumps({"micro": run_micro(Q, torch)}))
+        return
+    if args.cfg4:
+        print(json.dumps({"n40d4p3": run_cfg4(Q, torch, autotune=bool(args.autotune),
+                                              only=None if args.cfg4 == "all" else args.cfg4)}))
         return
     inst = qs.instance(30, 3, 4, args.seed, args.angle_sets)
     prec = {"c128": Q.QTN_C128, "c64": Q.QTN_C64, "mixed": Q.QTN_MIXED}[args.precision]
