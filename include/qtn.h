@@ -293,8 +293,8 @@ int qtn_launch_log(const qtn_network *net, int64_t cap, qtn_launch_rec *out,
                              the lane-sum streaming mapping (LDS lane
                              tables, serial walk, butterflies)           */
 #define QTN_VAR_GENERIC 2 /* own launch, generic register/lane mapping   */
-#define QTN_VAR_MFMA 3    /* matrix form on the matrix cores (complex64
-                             groups whose operands reduce to two factors) */
+#define QTN_VAR_MFMA 3    /* matrix form on the matrix cores (groups whose
+                             operands split into two sides)               */
 
 typedef struct qtn_tune_report {
     int32_t n_groups;     /* own-launch groups tuned                        */
@@ -309,8 +309,8 @@ typedef struct qtn_tune_report {
 /*
  * Autotuner.  Runs the planned evaluation once per candidate configuration
  * (generic mapping; streaming mapping with 1, 2 or 3 lane-summed bits; matrix
- * form, which only complex64 groups that have one take part in; cell mapping
- * with 3 or 4 cell bits, for the groups wide enough for it), each group in
+ * form, which only the groups that have one take part in; cell mapping with
+ * 3 or 4 cell bits, for the groups wide enough for it), each group in
  * its own launch on one stream and, for groups up to width 16, again alone
  * inside one workgroup, timing every launch with HIP events.  Each group then
  * keeps its fastest configuration for where it runs, and the plan's schedule

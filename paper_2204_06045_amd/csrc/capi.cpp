@@ -334,7 +334,8 @@ constexpr int kTuneSingleWidth = 16;
 // Configurations measured by the autotuner: every group in its own launch
 // with the generic mapping, with the streaming mapping at 1, 2, 3
 // lane-summed bits, in matrix form (groups that have one), or with
-// the cell mapping at 3 or 4 cell bits (groups wide enough for it).
+// the cell mapping at 3 or 4 cell bits (groups wide enough for it; 2 cell
+// bits were measured too and never won on the N=30 p=4 network).
 const std::vector<Force> &tune_candidates() {
   static const std::vector<Force> c = {{1, 1, 2}, {1, 2, 1}, {1, 2, 2}, {1, 2, 3},
                                        {1, 3, 2}, {1, 4, 3}, {1, 4, 4}};
