@@ -565,30 +565,40 @@ def run_costmodel(Q, torch, prec=1, epochs=600, lr=3e-3, reps=3):
     torch.cuda.empty_cache()
     rr = qs.Rng(5000)
     fallback_ms = learned_ms = 0.0
+    gains = []
     picks = np.zeros(4, dtype=np.int64)
     for i in range(32):
         d = 3 if i < 16 else 4
         sizes = [n for n in range(50, 501) if (n * d) % 2 == 0]
         n = sizes[rr.below(len(sizes))]
         inst = qs.instance(n, d, 3, 7000 + i)
-        net = Q.Network(n, inst["edges"], *inst["angles"][0], order_trials=4)
-        net.plan(prec)
-        ws = net.workspace()
-        for mode in ("fallback", "learned"):
-            if mode == "learned":
-                picks += Q.qtn_apply_costmodel(net.h, cm)
-            net.contract(ws)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(reps):
+        # the same plan twice: width rule, and the model's picks; timed in
+        # alternation so that drift hits both alike
+        fb = Q.Network(n, inst["edges"], *inst["angles"][0], order_trials=4)
+        fb.plan(prec)
+        ln = Q.Network(n, inst["edges"], *inst["angles"][0], order_trials=4)
+        ln.plan(prec)
+        picks += Q.qtn_apply_costmodel(ln.h, cm)
+        wf, wl = fb.workspace(), ln.workspace()
+        fb.contract(wf)
+        ln.contract(wl)
+        tf = tl = 0.0
+        for _ in range(reps):
+            for net, ws in ((fb, wf), (ln, wl)):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
                 net.contract(ws)
-            torch.cuda.synchronize()
-            dt = 1e3 * (time.perf_counter() - t0) / reps
-            if mode == "fallback":
-                fallback_ms += dt
-            else:
-                learned_ms += dt
-        net.close()
+                torch.cuda.synchronize()
+                dt = 1e3 * (time.perf_counter() - t0)
+                if net is fb:
+                    tf += dt
+                else:
+                    tl += dt
+        fallback_ms += tf / reps
+        learned_ms += tl / reps
+        gains.append(tf / tl)
+        fb.close()
+        ln.close()
         torch.cuda.empty_cache()
     cm.close()
     return {"train_samples": int(len(x)), "collect_seconds": collect_s,
@@ -596,6 +606,8 @@ def run_costmodel(Q, torch, prec=1, epochs=600, lr=3e-3, reps=3):
             "loss_last": float(hist[-1]), "heldout_graphs": 32,
             "fallback_ms_per_pass": fallback_ms, "learned_ms_per_pass": learned_ms,
             "gain": fallback_ms / learned_ms if learned_ms > 0 else None,
+            "gain_per_graph": {"min": float(min(gains)), "median": float(np.median(gains)),
+                               "max": float(max(gains))},
             "picks_block_stream_generic_mfma": [int(v) for v in picks],
             "precision": "c64" if prec == 1 else "c128"}
 

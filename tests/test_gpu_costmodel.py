@@ -89,3 +89,75 @@ def test_costmodel_selection_keeps_parity(qtn, orc, gpu):
     assert abs(en - ref_en) / abs(ref_en) <= 1e-10
     net.close()
     cm.close()
+
+
+def _time_contract(net, ws, reps):
+    import torch
+    import time
+    net.contract(ws)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        net.contract(ws)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    return float(np.median(ts))
+
+
+def test_trained_selector_gains_over_width_rule(qtn, gpu):
+    """What the trained network gains: trained on autotuner timings of nine
+    networks, it picks each group's kernel on six held-out graphs (N in
+    [100, 300], degree 3 and 4, p=3), and the evaluation is timed (median of
+    repeats, the two selections interleaved per graph) against the width-rule
+    fallback on the same plan.  The summed time ratio is printed; the learned
+    selection must be at least 3% faster (the bench row measures it on 32
+    held-out graphs)."""
+    feats, times = [], []
+    for it in qs.batch_instances(2204, 64, 20, 200, (2, 3, 4), d=3)[:8]:
+        net = qtn.Network(it["n"], it["edges"], *it["angles"][0], order_trials=8)
+        net.plan(1)
+        net.autotune()
+        f, m = net.tune_log()
+        feats.append(f)
+        times.append(m)
+        net.close()
+    it = qs.instance(30, 3, 4, 0)
+    net = qtn.Network(30, it["edges"], *it["angles"][0], order_trials=16)
+    net.plan(1)
+    net.autotune()
+    f, m = net.tune_log()
+    feats.append(f)
+    times.append(m)
+    net.close()
+    cm = qtn.CostModel(_rand_params(4242, 0.15))
+    hist = cm.train(np.concatenate(feats), np.concatenate(times), 600, 3e-3)
+    assert hist[-1] < hist[0]
+    rr = qs.Rng(5100)
+    fb_total = ln_total = 0.0
+    gains = []
+    for i in range(6):
+        d = 3 if i % 2 == 0 else 4
+        sizes = [n for n in range(100, 301) if (n * d) % 2 == 0]
+        n = sizes[rr.below(len(sizes))]
+        inst = qs.instance(n, d, 3, 7100 + i)
+        fb = qtn.Network(n, inst["edges"], *inst["angles"][0], order_trials=4)
+        fb.plan(1)
+        ln = qtn.Network(n, inst["edges"], *inst["angles"][0], order_trials=4)
+        ln.plan(1)
+        qtn.qtn_apply_costmodel(ln.h, cm)
+        wf, wl = fb.workspace(), ln.workspace()
+        tf = tl = 0.0
+        for _ in range(3):
+            tf += _time_contract(fb, wf, 5)
+            tl += _time_contract(ln, wl, 5)
+        fb_total += tf
+        ln_total += tl
+        gains.append(tf / tl)
+        fb.close()
+        ln.close()
+    cm.close()
+    gain = fb_total / ln_total
+    print(f"trained selector vs width rule on 6 held-out graphs: {gain:.3f}x "
+          f"(per graph {', '.join(f'{g:.2f}' for g in gains)})", flush=True)
+    assert gain >= 1.03
