@@ -35,8 +35,12 @@ def test_noalloc_matches_workspace_entry_point(qtn, orc, gpu):
     big = qtn.Bucket([list(range(0, 22)), [0, 1, 2, 3] + list(range(22, 28))],
                      list(range(4, 28)))
     small = qtn.Bucket([[0, 1, 2, 3], [0, 4, 5]], [1, 2, 3, 4, 5])
-    assert big.info()["w"] == 28 and small.info()["w"] == 6
-    for b in (big, small):  # the second call: a smaller input
+    # a 64 x 64 x 16 matrix product in matrix form (its row, column and
+    # summed-index tables travel in the descriptors too)
+    mm = qtn.Bucket([[0, 1, 2, 3] + list(range(4, 10)), [0, 1, 2, 3] + list(range(10, 16))],
+                    list(range(4, 16)), variant=3)
+    assert big.info()["w"] == 28 and small.info()["w"] == 6 and mm.info()["variant"] == 2
+    for b in (big, mm, small):  # each call on a smaller input than the one before
         print(f"noalloc bucket w={b.info()['w']} L={b.info()['L']} "
               f"variant={b.info()['variant']}", flush=True)
         data, host = _fill(b, rng)
@@ -49,9 +53,10 @@ def test_noalloc_matches_workspace_entry_point(qtn, orc, gpu):
         b.contract(data)
         torch.cuda.synchronize()
         assert np.array_equal(got, _out(b, data))
-        if b is small:
+        if b is not big:
             tensors = [(l[::-1], x.reshape((2,) * len(l))) for l, x in zip(b.operands, host)]
-            ref = np.asarray(orc.contract_bucket(tensors, [0], b.out_labels[::-1])).ravel()
+            summed = sorted({l for o in b.operands for l in o} - set(b.out_labels))
+            ref = np.asarray(orc.contract_bucket(tensors, summed, b.out_labels[::-1])).ravel()
             assert np.max(np.abs(got - ref)) <= 1e-10 * max(1.0, np.max(np.abs(ref)))
         else:
             # sampled outputs of the wide bucket against plain sums on the host
@@ -64,6 +69,7 @@ def test_noalloc_matches_workspace_entry_point(qtn, orc, gpu):
                     s += A[ia] * B[ib]
                 assert abs(got[o] - s) <= 1e-10 * max(1.0, abs(s))
     big.close()
+    mm.close()
     small.close()
 
 
