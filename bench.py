@@ -239,13 +239,25 @@ def launch_breakdown(log, n_sets=1):
     # products (3M, 6 real FLOPs) each, at the group's precision
     mm_flops = sum(6.0 * 2.0 ** r["w"] * n_sets for r in mm)
     mm_peak = (FP64_PEAK_TFLOPS if all(r["prec"] == 0 for r in mm) else FP32_PEAK_TFLOPS)
+    # each launch against the bound its arithmetic intensity implies: the
+    # time its bytes take at the HBM peak or its matrix work at the matrix
+    # peak of its precision, whichever is longer
+    bound_ms, n_hbm = 0.0, 0
+    for r in mm:
+        pk = FP64_PEAK_TFLOPS if r["prec"] == 0 else FP32_PEAK_TFLOPS
+        t_hbm = r["bytes"] / (HBM_PEAK_GBS * 1e6)
+        t_mm = 6.0 * 2.0 ** r["w"] * n_sets / (pk * 1e9)
+        bound_ms += max(t_hbm, t_mm)
+        n_hbm += t_hbm >= t_mm
     return {"width_classes": cls,
             "small_groups_per_s": (sum(r["n_groups"] for r in blk) / blk_ms * 1e3
                                    if blk_ms > 0 else 0.0),
             "matrix_form": ({"launches": len(mm), "ms": mm_ms,
                              "matrix_tflops": mm_flops / mm_ms / 1e9,
                              "peak_tflops": mm_peak,
-                             "frac_matrix_peak": mm_flops / mm_ms / 1e9 / mm_peak}
+                             "frac_matrix_peak": mm_flops / mm_ms / 1e9 / mm_peak,
+                             "hbm_bound_launches": n_hbm,
+                             "frac_of_bound": bound_ms / mm_ms}
                             if mm_ms > 0 else None)}
 
 
@@ -647,8 +659,11 @@ def run_micro(Q, torch, reps=5, n_random=8, seed=2204):
                "kernel_ms": ms, "gbs": gbs, "tflops": tflops,
                "paper_gflops": 8.0 * 2.0 ** info["w"] / ms / 1e6}
         if info["variant"] == 2:
+            # against the bound its intensity implies (3M matrix work vs bytes)
             mt = 6.0 * 2.0 ** info["w"] / ms / 1e9
-            return {**row, "matrix_tflops": mt, "bound": "mfma", "frac": mt / fpeak}
+            hbm = 6.0 * 2.0 ** info["w"] / info["bytes"] < fpeak * 1e12 / (HBM_PEAK_GBS * 1e9)
+            return {**row, "matrix_tflops": mt, "bound": "hbm" if hbm else "mfma",
+                    "frac": gbs / HBM_PEAK_GBS if hbm else mt / fpeak}
         bound = "hbm" if info["flops"] / info["bytes"] < fpeak * 1e12 / (HBM_PEAK_GBS * 1e9) else "alu"
         frac = gbs / HBM_PEAK_GBS if bound == "hbm" else tflops / fpeak
         return {**row, "bound": bound, "frac": frac}
