@@ -71,9 +71,11 @@ typedef struct qtn_config {
                             it fits in the per-group launch executors,
                             else streaming or generic), 1 generic kernel
                             only, 2 streaming kernel wherever it applies,
-                            3 matrix form for every complex64 group that
-                            has one (others as auto), 4 cell mapping
-                            wherever it applies [0]                         */
+                            3 matrix form for every group that has one
+                            (complex128 in own launches; complex64 also in
+                            workgroups and the persistent executors;
+                            others as auto), 4 cell mapping wherever it
+                            applies [0]                                     */
     int32_t order_trials; /* >1: plan with the cheapest (sum of 2^width) of
                             the greedy min-fill order and order_trials-1
                             min-fill orders with random tie-breaks [0]     */
@@ -491,9 +493,10 @@ void qtn_network_free(qtn_network *net);
  *                 labels, its byte offset); it may not overlap an operand
  *   precision     QTN_C128 or QTN_C64 (every tensor in that precision)
  *   variant       kernel mapping as qtn_config.variant: 0 the width rule,
- *                 1 generic, 2 streaming, 3 matrix form (complex64 with two
- *                 factors), 4 cell mapping; a mapping that does not fit falls
- *                 back to the rule
+ *                 1 generic, 2 streaming, 3 matrix form (operands that split
+ *                 into two sides with at least 4 labels private to each), 4
+ *                 cell mapping; a mapping that does not fit falls back to the
+ *                 rule
  *   knob          streaming: lane-summed labels; cells: cell bits (2..4);
  *                 0 the default
  *   out           receives the plan (host memory, library-owned)
