@@ -385,8 +385,6 @@ int describe_group(const Group &G, const ConePlan &pl, const GroupEnv &env, Sche
   const int sl = G.L - 1 - rls;
   const bool off32 = max_operand_bytes(G, pl) <= kOffset32Bytes;
   const bool stream_ok = (int)G.ops.size() <= kStreamMaxOps && sl <= kStreamMaxSerial && off32;
-  // matrix form: complex64 groups in their own launch whose operands
-  // reduce to two factors (requested, or picked by tuning)
   // matrix form: groups that split into two sides (gemm_shape), requested or
   // picked by tuning; complex128 tiles take more LDS than the workgroup and
   // persistent kernels hold, so complex128 groups take it in own launches only
