@@ -434,8 +434,10 @@ int describe_group(const Group &G, const ConePlan &pl, const GroupEnv &env, Sche
     dg.n_mb = (uint8_t)gsh.mbits.size();
     dg.n_nb = (uint8_t)gsh.nbits.size();
     dg.n_bb = (uint8_t)gsh.bbits.size();
-    // column blocks of 16 per tile: as many as the n range fills (n >= 4 bits)
-    dg.rls = (uint8_t)(dg.n_nb >= 6 ? 4 : (dg.n_nb == 5 ? 2 : 1));
+    // column blocks of 16 per tile: as many as the n range fills (n >= 4
+    // bits) in own launches; one inside workgroups and the persistent
+    // executors, whose kernels are compiled for that form only
+    dg.rls = (uint8_t)(is_small || persistent ? 1 : (dg.n_nb >= 6 ? 4 : (dg.n_nb == 5 ? 2 : 1)));
     const uint64_t tn = 16ull * dg.rls;
     const uint64_t mt = ((1ull << dg.n_mb) + kMmTM - 1) / kMmTM;
     const uint64_t nt = ((1ull << dg.n_nb) + tn - 1) / tn;
@@ -1904,10 +1906,11 @@ static int autotune_sets(qtn_network *net, void *d_workspace, size_t bytes, void
         char *ws = (char *)d_workspace;
         const Schedule &s = ex.sched;
         for (size_t i = 0; i < s.singles.size(); i++) {
-          // the cell mapping, and the complex128 matrix form, only run in
-          // their own launch
+          // the cell mapping, the complex128 matrix form and matrix-form
+          // tiles wider than one column block only run in their own launch
           const DevGroup &dg = s.groups[s.singles[i]];
-          if (dg.variant == kVarCell || (dg.variant == kVarMfma && dg.prec == 0)) continue;
+          if (dg.variant == kVarCell || (dg.variant == kVarMfma && (dg.prec == 0 || dg.rls != 1)))
+            continue;
           if ((rc = tb.begin(QTN_K_BLOCK, ex.rt.main, s.singles[i], 1, 0, 0, true))) {
             give_back();
             return rc;

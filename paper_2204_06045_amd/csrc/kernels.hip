@@ -920,17 +920,6 @@ __device__ void mm_tile(const GI &G, const DevOp *__restrict__ gops, const int32
   }
 }
 
-// A matrix-form tile with the group's column-block count (G.rls: 1, 2, 4).
-template <class T, bool CVT>
-__device__ __forceinline__ void mm_tile_any(const GI &G, const DevOp *__restrict__ gops,
-                                            const int32_t *__restrict__ stab,
-                                            const uint8_t *__restrict__ bits, char *__restrict__ data,
-                                            char *lds, uint32_t tile, uint32_t set) {
-  if (G.rls == 1) mm_tile<T, CVT, 1>(G, gops, stab, bits, data, lds, tile, set);
-  else if (G.rls == 2) mm_tile<T, CVT, 2>(G, gops, stab, bits, data, lds, tile, set);
-  else mm_tile<T, CVT, 4>(G, gops, stab, bits, data, lds, tile, set);
-}
-
 // One group's wave units [u0, u1) of angle set `set` over the block's waves,
 // in the group's own precision.
 __device__ __forceinline__ void run_group(const GI &G, int g, const DevOp *__restrict__ ops,
@@ -953,14 +942,15 @@ __device__ __forceinline__ void run_group(const GI &G, int g, const DevOp *__res
       for (uint32_t u = u0 + wave; u < u1; u += nw) F<float2, true>(__VA_ARGS__);   \
   } while (0)
   if (G.variant == kVarMfma) {
-    // matrix form (complex64 inside workgroups): a unit is one output tile,
-    // computed by the whole block
+    // matrix form (complex64 inside workgroups): a unit is one 64 x 16
+    // output tile, computed by the whole block (one column block per wave
+    // keeps the accumulators, and so these kernels' registers, few)
     if (G.cvt)
       for (uint32_t u = u0; u < u1; u++)
-        mm_tile_any<float2, true>(G, gops, stab, ub, data, (char *)s_lane, u, set);
+        mm_tile<float2, true, 1>(G, gops, stab, ub, data, (char *)s_lane, u, set);
     else
       for (uint32_t u = u0; u < u1; u++)
-        mm_tile_any<float2, false>(G, gops, stab, ub, data, (char *)s_lane, u, set);
+        mm_tile<float2, false, 1>(G, gops, stab, ub, data, (char *)s_lane, u, set);
   } else if (G.variant == kVarStream) {
     stream_setup(G, gops, s_lane);
     __syncthreads();
