@@ -501,18 +501,25 @@ def run_cfg4(Q, torch, steps=10, autotune=True, only=None):
     """4-regular N=40, p=3 (80 light cones): complex128, complex64 and mixed
     precision (groups of width >= 18 in complex64, in matrix form on the
     matrix cores where a group reshapes), each with its per-edge error
-    against the stored FP64 oracle values.  `only`: one row's name."""
+    against the stored FP64 oracle values; then complex128 and mixed with
+    the headline's plan options (slicing at 26).  `only`: one row's name."""
     import numpy as np
     with open(os.path.join(ROOT, "tests", "golden", "cfg4_oracle.json")) as f:
         gd = json.load(f)
     ref = np.asarray(gd["zz_re"])
     rows = {}
-    for name, prec, variant in (("c128", Q.QTN_C128, 0), ("c64", Q.QTN_C64, 0),
-                                ("mixed", Q.QTN_MIXED, 0), ("mixed_matrix", Q.QTN_MIXED, 3)):
+    # the last two rows: the headline's plan options (best of 64 orders by
+    # plan cost, slicing of cones wider than 26)
+    for name, prec, variant, plan in (
+            ("c128", Q.QTN_C128, 0, {}), ("c64", Q.QTN_C64, 0, {}),
+            ("mixed", Q.QTN_MIXED, 0, {}), ("mixed_matrix", Q.QTN_MIXED, 3, {}),
+            ("c128_sliced26", Q.QTN_C128, 0, dict(order_trials=64, slice_width=26, order_weight=4)),
+            ("mixed_sliced26", Q.QTN_MIXED, 0,
+             dict(order_trials=64, slice_width=26, order_weight=4))):
         if only is not None and name != only:
             continue
-        net = Q.Network(gd["n"], gd["edges"], gd["gamma"], gd["beta"], order_trials=16,
-                        variant=variant)
+        net = Q.Network(gd["n"], gd["edges"], gd["gamma"], gd["beta"],
+                        **{"order_trials": 16, "variant": variant, **plan})
         net.plan(prec)
         ws = net.workspace()
         if autotune:
@@ -741,7 +748,8 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 1 GiB device copy (byte-counter calibration)")
     ap.add_argument("--cfg4", nargs="?", const="all", default=None,
-                    choices=("all", "c128", "c64", "mixed", "mixed_matrix"),
+                    choices=("all", "c128", "c64", "mixed", "mixed_matrix", "c128_sliced26",
+                             "mixed_sliced26"),
                     help="only the 4-regular N=40 p=3 rows (or one of them): one JSON line")
     ap.add_argument("--micro", action="store_true",
                     help="only the single-bucket probes (matrix products, fixed and random "

@@ -472,6 +472,26 @@ def test_cfg4_full_size_against_oracle(qtn, gpu, prec, variant, mixed_width):
     _check(zz, zi, en, gd["zz_re"], gd["energy"], prec, "cfg4")
 
 
+@pytest.mark.parametrize("prec", [0, 2])
+def test_cfg4_sliced_against_oracle(qtn, gpu, prec):
+    """4-regular N=40, p=3 with the headline's plan options: best of 64 orders
+    by plan flops + 4 x bytes, light cones wider than 26 sliced (their slices'
+    scalars summed in FP64), tuned; per edge against the unsliced FP64 oracle
+    values."""
+    gd = _golden("cfg4")
+    net = qtn.Network(gd["n"], gd["edges"], gd["gamma"], gd["beta"], order_trials=64,
+                      slice_width=26, order_weight=4)
+    net.plan(prec)
+    st = net.stats()
+    print(f"cfg4 sliced at 26, prec={prec}: max width {st['max_width']}, "
+          f"{st['n_sliced']} cones sliced", flush=True)
+    assert st["max_width"] <= 26 and st["n_sliced"] > 0
+    net.autotune()
+    zz, zi, en = net.contract()
+    _check(zz, zi, en, gd["zz_re"], gd["energy"], prec, "cfg4 sliced")
+    net.close()
+
+
 def test_stored_tuning_reapplies(qtn, orc, gpu):
     """Choices measured on one network reapplied to a fresh plan of the same
     graph give the same schedule and results."""
