@@ -434,8 +434,9 @@ def run_seeds(Q, torch, seeds=(0, 1, 2, 3, 4), angle_batch=32, steps=6, order_tr
               slice_width=0, order_weight=0):
     """The metric's shape on graph seeds 0-4 (the algorithmic bytes vary from
     graph to graph): per seed, the width of the widest bucket of each light
-    cone (max and median), the evaluation's algorithmic bytes, and evals/s of
-    32-set batches under the width rule (no tuning)."""
+    cone (max and median), the histogram of bucket widths, the evaluation's
+    algorithmic bytes, and evals/s of 32-set batches under the width rule (no
+    tuning)."""
     import numpy as np
     import qaoa_synth as qs
     rows = {}
@@ -460,6 +461,9 @@ def run_seeds(Q, torch, seeds=(0, 1, 2, 3, 4), angle_batch=32, steps=6, order_tr
         rows[f"seed{seed}"] = {"evals_per_s": steps * angle_batch / (time.perf_counter() - t0),
                                "width_max": int(max(widths)),
                                "width_median": float(np.median(widths)),
+                               # buckets per width (the planned light cones)
+                               "width_hist": {str(w): int(c) for w, c in enumerate(st["width_hist"])
+                                              if c},
                                "alg_bytes_per_eval": st["bytes"]}
         del aws
         net.close()
