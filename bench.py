@@ -369,12 +369,14 @@ def batch_golden_check(insts, nets, zz, en, master_seed, count):
 
 def run_batch(Q, torch, steps, warmup, executor=5, autotune=False, order_trials=64,
               prec=1, master_seed=2204, count=64, slice_width=0, order_weight=4,
-              hybrid_width=24):
+              hybrid_width=24, cost_model=None):
     """64 random cubic graphs, N uniform over even sizes in [20, 200], p in
     {2, 3, 4}; all light cones of all graphs in one batched call: the hybrid
     executor (cones up to width `hybrid_width` in one persistent lockstep
     launch, the wider ones by per-group launches after it), orders by the
-    merged plan's flops + 4 x bytes."""
+    merged plan's flops + 4 x bytes.  With autotune: the 8 networks with the
+    most algorithmic bytes are tuned, and the trained cost model (cost_model)
+    picks the kernels of the others."""
     import qaoa_synth as qs
     insts = qs.batch_instances(master_seed, count, 20, 200, (2, 3, 4), d=3)
     t0 = time.perf_counter()
@@ -395,6 +397,10 @@ def run_batch(Q, torch, steps, warmup, executor=5, autotune=False, order_trials=
         heavy = sorted(nets, key=lambda n: -n.stats()["bytes"])[:8]
         for net in heavy:
             net.autotune()
+        if cost_model is not None:
+            for net in nets:
+                if all(net is not h for h in heavy):
+                    Q.qtn_apply_costmodel(net.h, cost_model)
         tune_s = time.perf_counter() - t0
         for net in nets:
             net._ws = None
@@ -421,6 +427,10 @@ def run_batch(Q, torch, steps, warmup, executor=5, autotune=False, order_trials=
                         4: "persistent dataflow",
                         5: f"hybrid: persistent lockstep for cones up to width {hybrid_width}, "
                            "per-group launches for the wider ones"}.get(executor, "launches"),
+           "kernel_choice": ("the 8 networks with the most bytes tuned, the others by the "
+                             "learned cost model" if autotune and cost_model is not None else
+                             "the 8 networks with the most bytes tuned, the others by the width "
+                             "rule" if autotune else "width rule"),
            "precision": "c64" if prec == 1 else "c128", "order_trials": order_trials,
            "slice_width": slice_width, "order_weight": order_weight,
            "slices": sum(s["n_slices"] for s in st),
@@ -623,7 +633,6 @@ def run_costmodel(Q, torch, prec=1, epochs=600, lr=3e-3, reps=3):
         fb.close()
         ln.close()
         torch.cuda.empty_cache()
-    cm.close()
     return {"train_samples": int(len(x)), "collect_seconds": collect_s,
             "train_seconds": train_s, "epochs": epochs, "loss_first": float(hist[0]),
             "loss_last": float(hist[-1]), "heldout_graphs": 32,
@@ -632,7 +641,8 @@ def run_costmodel(Q, torch, prec=1, epochs=600, lr=3e-3, reps=3):
             "gain_per_graph": {"min": float(min(gains)), "median": float(np.median(gains)),
                                "max": float(max(gains))},
             "picks_block_stream_generic_mfma": [int(v) for v in picks],
-            "precision": "c64" if prec == 1 else "c128"}
+            "precision": "c64" if prec == 1 else "c128",
+            "_model": cm}
 
 
 def run_micro(Q, torch, reps=5, n_random=8, seed=2204):
@@ -884,6 +894,7 @@ def main():
         torch.cuda.empty_cache()
         log("variant costmodel (learned selector vs width rule, held-out graphs)")
         variants["costmodel_c64"] = run_costmodel(Q, torch)
+        cost_model = variants["costmodel_c64"].pop("_model")
         torch.cuda.empty_cache()
         log("variant gradient (gradient ascent, 4p + 1 angle sets per gradient)")
         variants["gradient_c128"] = run_gradient(Q, torch, inst, slice_width=args.slice_width,
@@ -897,7 +908,9 @@ def main():
         variants["micro"] = run_micro(Q, torch)
         torch.cuda.empty_cache()
         log("variant batch64_c64 (hybrid executor)")
-        variants["batch64_c64"] = run_batch(Q, torch, 5, 1, autotune=bool(args.autotune))
+        variants["batch64_c64"] = run_batch(Q, torch, 5, 1, autotune=bool(args.autotune),
+                                            cost_model=cost_model)
+        cost_model.close()
         torch.cuda.empty_cache()
         log("variant batch64_c64_lockstep (every cone in the persistent lockstep launch)")
         variants["batch64_c64_lockstep"] = run_batch(Q, torch, 5, 1, executor=0, order_trials=16,
