@@ -149,9 +149,10 @@ def test_matrix_product(qtn, orc, gpu, prec, variant, m):
                                                (8, 9, 4, 0), (6, 4, 8, 3), (2, 12, 7, 0)])
 def test_matrix_form_shapes(qtn, orc, gpu, prec, n_sum, n_m, n_n, n_b):
     """Matrix-form buckets: several operands per side, labels shared by both
-    sides (batch), summed ranges shorter than and several times one LDS chunk
-    (16), and m / n ranges that are not multiples of the 64 x 64 tile.  The
-    operands interleave summed and kept labels in union order."""
+    sides (batch), an operand with batch and summed labels only, summed
+    ranges shorter than and several times one LDS chunk (16), and m / n
+    ranges that are not multiples of the 64 x 64 tile.  The operands
+    interleave summed and kept labels in union order."""
     r = qs.Rng(4000 + 100 * n_sum + 10 * n_m + n_n)
     labels = list(range(n_sum + n_m + n_n + n_b))
     perm = labels[n_sum:]
@@ -166,6 +167,9 @@ def test_matrix_form_shapes(qtn, orc, gpu, prec, n_sum, n_m, n_n, n_b):
     a_small = sorted(ks[-1:] + mm[:2])
     b_small = sorted(ks[:1] + nn[-3:] + bb[:1])
     ops = [a_main, b_main, a_small, b_small]
+    if bb:
+        # summed and batch labels only: either side holds it (placed on side B)
+        ops.append(sorted(ks[:2] + bb))
     b = qtn.Bucket(ops, sorted(perm), precision=prec, variant=3)
     info = _run_check(qtn, orc, b, np.random.default_rng(n_sum * 31 + n_m), prec,
                       f"matrix form sum={n_sum} m={n_m} n={n_n} b={n_b}")
