@@ -768,6 +768,9 @@ def main():
     ap.add_argument("--micro", action="store_true",
                     help="only the single-bucket probes (matrix products, fixed and random "
                          "contractions): one JSON line of their rows")
+    ap.add_argument("--batch", action="store_true",
+                    help="only the 64-graph batch row (hybrid executor; with --autotune 0 "
+                         "every kernel by the width rule): one JSON line")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -783,6 +786,11 @@ def main():
     torch.cuda.set_device(0)
     if args.micro:
         print(json.dumps({"micro": run_micro(Q, torch)}))
+        return
+    if args.batch:
+        print(json.dumps({"batch64_c64": run_batch(Q, torch, max(1, args.steps // 8),
+                                                   min(args.warmup, 2),
+                                                   autotune=bool(args.autotune))}))
         return
     if args.cfg4:
         print(json.dumps({"n40d4p3": run_cfg4(Q, torch, autotune=bool(args.autotune),
