@@ -109,7 +109,9 @@ typedef struct qtn_config {
                             at most this run in one persistent lockstep
                             launch, the others after it by per-group
                             launches (cell mapping allowed) on the side
-                            streams [20]                                   */
+                            streams; their leading small groups, which
+                            need no other group, run in the persistent
+                            launch's first step [20]                       */
     int32_t reserved[2];
 } qtn_config;
 

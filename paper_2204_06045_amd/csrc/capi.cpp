@@ -96,10 +96,10 @@ struct Schedule {
   std::vector<int2> ranges;  // first n_cones: each cone's leading small groups
   std::vector<int> csb, ncb;
   std::vector<int> cns;       // slices per light cone (index slicing; 1: none)
-  // hybrid executor: cones run by per-group launches beside the persistent
-  // launch (their groups may take the cell mapping); per-cone lead bytes
+  // hybrid executor: cones whose groups after the leading segment run by
+  // per-group launches after the persistent launch (they may take the cell
+  // mapping)
   std::vector<char> cone_heavy;
-  std::vector<double> lead_bytes, lead_flops;
   std::vector<FillDesc> fills;
   std::vector<int32_t> stab;  // serial-offset tables of streaming operands
   std::vector<uint8_t> uperm; // 32 bytes per group: union bit of each unit bit
@@ -887,14 +887,10 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S, const Force *fo
   std::vector<int2> lead(s.n_cones, make_int2(0, 0));
   for (int c = 0; c < s.n_cones; c++) {
     auto &tk = s.cone_tasks[c];
-    s.lead_bytes.push_back(0);
-    s.lead_flops.push_back(0);
     if (!tk.empty() && tk[0].kind == QTN_K_BLOCK) {
       lead[c] = s.ranges[tk[0].index];
       s.init_bytes += tk[0].bytes;
       s.init_flops += tk[0].flops;
-      s.lead_bytes[c] = tk[0].bytes;
-      s.lead_flops[c] = tk[0].flops;
       tk.erase(tk.begin());
     }
   }
@@ -921,7 +917,9 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S, const Force *fo
     std::vector<std::vector<int4>> per_step;
     std::vector<std::vector<int>> per_step_task;
     for (int cn : corder) {
-      if (s.cone_heavy[cn]) continue;  // run by launches beside the persistent kernel
+      // a heavy cone runs by launches after the persistent kernel; its
+      // leading segment, which needs nothing, is a first-step item
+      const bool heavy = s.cone_heavy[cn] != 0;
       int j = 0, prev = -1;
       auto put = [&](const int4 &it, int task) {
         if ((int)per_step.size() <= j) {
@@ -943,6 +941,7 @@ int build_schedule(qtn_network *const *nets, int n, Schedule *S, const Force *fo
         s.task_need[tk]++;
         j++;
       }
+      if (heavy) continue;
       for (const Task &t : s.cone_tasks[cn]) {
         const int tk = new_task();
         if (t.kind == QTN_K_BLOCK) {
@@ -1151,8 +1150,6 @@ int enqueue(Exec &X, Timer &tm) {
       // the heavy cones' share is not the persistent launch's
       for (int c = 0; c < s.n_cones; c++)
         if (s.cone_heavy[c]) {
-          b_all -= s.lead_bytes[c];
-          f_all -= s.lead_flops[c];
           for (auto &t : s.cone_tasks[c]) {
             b_all -= t.bytes;
             f_all -= t.flops;
@@ -1176,9 +1173,9 @@ int enqueue(Exec &X, Timer &tm) {
                                 rt.main, tm.t0(), tm.t1()));
     if ((rc = tm.end(rt.main, true))) return rc;
     if (X.hybrid && any_heavy) {
-      // after the persistent launch: the heavy cones, each cone's leading
-      // segment and tasks in order on one side stream, heaviest first, dealt
-      // to the least loaded stream
+      // after the persistent launch (which ran their leading segments): the
+      // heavy cones, each cone's tasks in order on one side stream, heaviest
+      // first, dealt to the least loaded stream
       QTN_HIP(hipEventRecord(rt.ev_fork, rt.main));
       for (int i = 0; i < K; i++) QTN_HIP(hipStreamWaitEvent(rt.side[i], rt.ev_fork, 0));
       std::vector<int> order;
@@ -1186,7 +1183,6 @@ int enqueue(Exec &X, Timer &tm) {
       for (int c = 0; c < s.n_cones; c++)
         if (s.cone_heavy[c]) {
           order.push_back(c);
-          cost[c] = s.lead_bytes[c];
           for (auto &t : s.cone_tasks[c]) cost[c] += t.bytes;
         }
       std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
@@ -1195,14 +1191,6 @@ int enqueue(Exec &X, Timer &tm) {
         const int st = (int)(std::min_element(load.begin(), load.end()) - load.begin());
         load[st] += cost[c];
         hipStream_t hs = rt.side[st];
-        if (s.ranges[c].y > s.ranges[c].x) {
-          if ((rc = tm.begin(QTN_K_BLOCK, hs, s.ranges[c].x, s.ranges[c].y - s.ranges[c].x,
-                             s.lead_bytes[c], s.lead_flops[c], true)))
-            return rc;
-          QTN_HIP(launch_block_groups(s.prec, data, groups, ops, stab, uperm, ranges, c, 1, NS, hs,
-                                      tm.t0(), tm.t1()));
-          if ((rc = tm.end(hs, true))) return rc;
-        }
         for (auto &t : s.cone_tasks[c]) {
           const int g0 = t.kind == QTN_K_BLOCK ? s.ranges[t.index].x : t.index;
           const int ng = t.kind == QTN_K_BLOCK ? s.ranges[t.index].y - s.ranges[t.index].x : 1;
