@@ -375,8 +375,9 @@ def run_batch(Q, torch, steps, warmup, executor=5, autotune=False, order_trials=
     executor (cones up to width `hybrid_width` in one persistent lockstep
     launch, the wider ones by per-group launches after it), orders by the
     merged plan's flops + 4 x bytes.  With autotune: the 8 networks with the
-    most algorithmic bytes are tuned, and the trained cost model (cost_model)
-    picks the kernels of the others."""
+    most algorithmic bytes are tuned, the trained cost model (cost_model)
+    picks the kernels of the others, and the batched call's persistent grid
+    and step item order are searched."""
     import qaoa_synth as qs
     insts = qs.batch_instances(master_seed, count, 20, 200, (2, 3, 4), d=3)
     t0 = time.perf_counter()
@@ -408,6 +409,12 @@ def run_batch(Q, torch, steps, warmup, executor=5, autotune=False, order_trials=
     handles = [n.h for n in nets]
     ws = Q.workspace(Q.qtn_batch_workspace(handles))
     total = sum(n.m for n in nets)
+    sched_tune = None
+    if autotune:
+        # persistent grid and step item order of the batched call
+        t0 = time.perf_counter()
+        sched_tune = Q.qtn_autotune_batch(handles, ws)
+        tune_s += time.perf_counter() - t0
     for _ in range(warmup):
         Q.qtn_contract_batch(handles, total, ws)
     torch.cuda.synchronize()
@@ -434,6 +441,7 @@ def run_batch(Q, torch, steps, warmup, executor=5, autotune=False, order_trials=
            "precision": "c64" if prec == 1 else "c128", "order_trials": order_trials,
            "slice_width": slice_width, "order_weight": order_weight,
            "slices": sum(s["n_slices"] for s in st),
+           "schedule_tune": sched_tune,
            "parity_vs_oracle": parity}
     for n in nets:
         n.close()

@@ -197,6 +197,32 @@ int qtn_contract_batch(qtn_network *const *nets, int32_t n, void *d_workspace,
 int qtn_batch_workspace(qtn_network *const *nets, int32_t n,
                         size_t *workspace_bytes_out);
 
+/* Schedule search for a batched call (the small-bucket overhead of a batch
+ * of networks, Sec. III-C): the persistent lockstep launch's grid (all
+ * resident blocks, three quarters or half of them, in whole rounds over the
+ * 8 XCDs) and the order of the work items inside each lockstep step (the
+ * costliest light cone's first, or reversed).  Each of the 6 configurations
+ * runs qtn_contract_batch 4 times on d_workspace; the best of the last 3
+ * host-clock call times is its time.  The configuration built first is
+ * kept unless another is more than 3% faster.  The choice stays with this
+ * list of networks (the schedule that later qtn_contract_batch calls on the
+ * same networks, unplanned since, reuse).  Results are the same in every
+ * configuration: each item computes the same values, whichever block runs it.
+ *   nets, n, d_workspace, bytes, hip_stream: as for qtn_contract_batch
+ *   report  filled if not NULL
+ * QTN_ESTATE unless the networks use executor 0, 2 or 5 (the lockstep and
+ * hybrid forms); errors of the calls as for qtn_contract_batch. */
+typedef struct qtn_batch_tune_report {
+    int32_t n_candidates;   /* configurations measured (6)                */
+    int32_t pick;           /* the one kept                               */
+    int32_t grid_blocks[8]; /* persistent grid of each                    */
+    int32_t item_order[8];  /* 0 costliest cone's items first, 1 reversed */
+    double ms[8];           /* best call time of each (milliseconds)      */
+} qtn_batch_tune_report;
+
+int qtn_autotune_batch(qtn_network *const *nets, int32_t n, void *d_workspace,
+                       size_t bytes, void *hip_stream, qtn_batch_tune_report *report);
+
 /* Per-kernel-class timing of one eager evaluation, for the roofline report. */
 #define QTN_NKERNELS 5
 #define QTN_K_FILL 0       /* gate-table fill from the angles            */

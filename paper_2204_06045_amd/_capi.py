@@ -34,7 +34,7 @@ KERNEL_NAMES = ("fill", "block", "wide", "reduce", "persistent")
 EXPORTS = (
     "qtn_network_build", "qtn_network_info", "qtn_order_minfill", "qtn_plan",
     "qtn_set_angles", "qtn_contract", "qtn_contract_batch",
-    "qtn_batch_workspace", "qtn_contract_timed", "qtn_get_plan_stats",
+    "qtn_batch_workspace", "qtn_autotune_batch", "qtn_contract_timed", "qtn_get_plan_stats",
     "qtn_angles_workspace", "qtn_contract_angles", "qtn_gradient_workspace",
     "qtn_energy_gradient",
     "qtn_bucket_widths", "qtn_slice_vars", "qtn_network_free", "qtn_last_error", "qtn_launch_log",
@@ -82,6 +82,12 @@ class qtn_tune_report(ctypes.Structure):
     _fields_ = [("n_groups", ctypes.c_int32), ("n_candidates", ctypes.c_int32),
                 ("cand_ms", ctypes.c_double * 8), ("tuned_ms", ctypes.c_double),
                 ("picks", ctypes.c_int32 * 8)]
+
+
+class qtn_batch_tune_report(ctypes.Structure):
+    _fields_ = [("n_candidates", ctypes.c_int32), ("pick", ctypes.c_int32),
+                ("grid_blocks", ctypes.c_int32 * 8), ("item_order", ctypes.c_int32 * 8),
+                ("ms", ctypes.c_double * 8)]
 
 
 class qtn_tune_pick(ctypes.Structure):
@@ -148,6 +154,8 @@ def lib():
                                          P, pd, pd]
         L.qtn_batch_workspace.argtypes = [ctypes.POINTER(P), i32,
                                           ctypes.POINTER(ctypes.c_size_t)]
+        L.qtn_autotune_batch.argtypes = [ctypes.POINTER(P), i32, P, ctypes.c_size_t, P,
+                                         ctypes.POINTER(qtn_batch_tune_report)]
         L.qtn_contract_timed.argtypes = [P, P, ctypes.c_size_t, P, pd, pd,
                                          ctypes.POINTER(qtn_timing)]
         L.qtn_get_plan_stats.argtypes = [P, ctypes.POINTER(qtn_plan_stats)]

@@ -14,14 +14,14 @@ import torch
 
 from . import _capi
 from ._capi import (QTN_C128, QTN_C64, QTN_MIXED, QtnError, check, lib, qtn_bucket_info,
-                    qtn_config,
+                    qtn_batch_tune_report, qtn_config,
                     qtn_launch_rec, qtn_plan_stats, qtn_timing, qtn_tune_pick, qtn_tune_rec,
                     qtn_tune_report)
 
 __all__ = [
     "QTN_C128", "QTN_C64", "QTN_MIXED", "QtnError", "qtn_network_build", "qtn_network_info",
     "qtn_order_minfill", "qtn_plan", "qtn_set_angles", "qtn_contract",
-    "qtn_contract_timed", "qtn_contract_batch", "qtn_batch_workspace",
+    "qtn_contract_timed", "qtn_contract_batch", "qtn_batch_workspace", "qtn_autotune_batch",
     "qtn_get_plan_stats", "qtn_bucket_widths", "qtn_slice_vars", "qtn_network_free",
     "qtn_last_error", "qtn_launch_log", "qtn_plan_order", "qtn_autotune",
     "qtn_autotune_angles", "qtn_tune_angles_workspace", "qtn_tune_log",
@@ -166,6 +166,17 @@ def qtn_contract_batch(nets, total_edges, ws, stream=None):
                                    stream_handle(stream), zz.ctypes.data_as(_pd),
                                    en.ctypes.data_as(_pd)))
     return zz, en
+
+
+def qtn_autotune_batch(nets, ws, stream=None):
+    """Persistent grid and step item order of the batched call; returns the
+    measured configurations and the one kept."""
+    r = qtn_batch_tune_report()
+    check(lib().qtn_autotune_batch(_net_array(nets), len(nets), ctypes.c_void_p(ws.data_ptr()),
+                                   ws.numel(), stream_handle(stream), ctypes.byref(r)))
+    n = r.n_candidates
+    return {"n_candidates": n, "pick": r.pick, "grid_blocks": list(r.grid_blocks[:n]),
+            "item_order": list(r.item_order[:n]), "ms": list(r.ms[:n])}
 
 
 def qtn_get_plan_stats(net):

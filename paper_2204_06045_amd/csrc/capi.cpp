@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -114,6 +115,7 @@ struct Schedule {
   int n_sets = 1;  // angle sets evaluated per launch (one copy of the data each)
   std::vector<char> desc_blob;  // bytes [off_desc, off_data)
   uint64_t serial = 0;          // distinct for every schedule built
+  int item_order = 0;           // lockstep steps: 0 costliest cone's items first, 1 reversed
   double bytes[QTN_NKERNELS] = {}, flops[QTN_NKERNELS] = {};
   double init_bytes = 0, init_flops = 0;
   // persistent executors: work items in step order; the task (one cone's
@@ -234,7 +236,10 @@ struct Exec {
   bool hybrid = false;    // persistent lockstep for light cones, launches for heavy ones
   bool lead_per_cone = false;
   uint32_t spin_limit = 1u << 22;
+  int grid_quarters = 4;  // persistent grid: this many quarters of the resident blocks
 };
+
+std::atomic<uint64_t> g_sched_serial{0};  // Schedule::serial source
 
 }  // namespace
 
@@ -757,10 +762,9 @@ int describe_group(const Group &G, const ConePlan &pl, const GroupEnv &env, Sche
 // a workgroup, so no group takes the cell mapping).
 int build_schedule(qtn_network *const *nets, int n, Schedule *S, const Force *force = nullptr,
                    int singleton_width = 0, int n_sets = 1, bool persistent = false) {
-  static std::atomic<uint64_t> serial{0};
   Schedule &s = *S;
   s = Schedule();
-  s.serial = ++serial;
+  s.serial = ++g_sched_serial;
   s.n_sets = n_sets;
   s.prec = nets[0]->precision;
   s.scalar_prec = s.prec == kPrecC64 ? 1 : 0;
@@ -1113,6 +1117,42 @@ struct Timer {
 };
 
 // Every launch of one evaluation, on rt.main and the side streams.
+// Blocks of the persistent launch: all that are resident at once, or the
+// tuned share of them (whole rounds over the 8 XCDs, at least 8).
+int persist_grid(const Exec &X) {
+  const int full = X.rt.persist_blocks;
+  if (X.grid_quarters >= 4 || full <= 8) return full;
+  const int nb = full * X.grid_quarters / 4;
+  return std::max(8, nb - nb % 8);
+}
+
+// Orders the items inside every lockstep step: 0 the costliest light cone's
+// first (as built), 1 reversed.  The blob's copies are rewritten and the
+// schedule takes a new serial, so the next run uploads them.
+void set_item_order(Schedule &s, int order) {
+  if (order == s.item_order) return;
+  for (int j = 0; j < s.n_steps; j++) {
+    std::reverse(s.items.begin() + s.step_begin[j], s.items.begin() + s.step_begin[j + 1]);
+    std::reverse(s.item_task.begin() + s.step_begin[j],
+                 s.item_task.begin() + s.step_begin[j + 1]);
+  }
+  if (!s.items.empty())
+    std::memcpy(s.desc_blob.data() + (s.off_items - s.off_desc), s.items.data(),
+                sizeof(int4) * s.items.size());
+  if (!s.item_task.empty())
+    std::memcpy(s.desc_blob.data() + (s.off_item_task - s.off_desc), s.item_task.data(),
+                sizeof(int) * s.item_task.size());
+  s.item_order = order;
+  s.serial = ++g_sched_serial;
+}
+
+void drop_graph(Runtime &rt) {
+  if (rt.exec) (void)hipGraphExecDestroy(rt.exec);
+  if (rt.graph) (void)hipGraphDestroy(rt.graph);
+  rt.exec = nullptr;
+  rt.graph = nullptr;
+}
+
 int enqueue(Exec &X, Timer &tm) {
   Schedule &s = X.sched;
   Runtime &rt = X.rt;
@@ -1138,7 +1178,7 @@ int enqueue(Exec &X, Timer &tm) {
     // resident, which kernels running beside it could prevent (measured: with
     // the heavy cones' launches started beside a full-size persistent grid, a
     // barrier wait ran past its bound)
-    const int nb = rt.persist_blocks;
+    const int nb = persist_grid(X);
     if (nb < 1) return set_err(QTN_EDEVICE, "persistent kernel does not fit on the device");
     double b_all = 0, f_all = 0;
     for (int k = 0; k < QTN_NKERNELS; k++) {
@@ -1312,13 +1352,8 @@ int run_exec(Exec &X, const std::vector<const qtn_network *> &nets, void *ws, si
   }
   QTN_HIP(hipEventRecord(rt.ev_in, (hipStream_t)stream));
   QTN_HIP(hipStreamWaitEvent(rt.main, rt.ev_in, 0));
-  if (rt.ws != ws && rt.exec) {
-    // the captured graph holds the old workspace's addresses
-    (void)hipGraphExecDestroy(rt.exec);
-    (void)hipGraphDestroy(rt.graph);
-    rt.exec = nullptr;
-    rt.graph = nullptr;
-  }
+  // the captured graph holds the old workspace's addresses
+  if (rt.ws != ws) drop_graph(rt);
   rt.ws = ws;
   QTN_HIP(hipMemcpyAsync((char *)ws + s.off_desc, rt.pinned_desc, rt.pinned_desc_n,
                          hipMemcpyHostToDevice, rt.main));
@@ -1807,6 +1842,71 @@ int qtn_contract_batch(qtn_network *const *nets, int32_t n, void *d_workspace, s
     const int m = ex->sched.n_cones;
     if (zz_out) std::copy(res.begin(), res.begin() + m, zz_out);
     if (energy_out) std::copy(res.begin() + 2 * m, res.begin() + 2 * m + n, energy_out);
+    return QTN_OK;
+  } catch (...) {
+    return exception_status();
+  }
+}
+
+int qtn_autotune_batch(qtn_network *const *nets, int32_t n, void *d_workspace, size_t bytes,
+                       void *hip_stream, qtn_batch_tune_report *report) {
+  try {
+    if (!nets || n < 1) return set_err(QTN_EINVAL, "bad batch arguments");
+    int rc = QTN_OK;
+    Exec *ex = batch_exec(nets, n, &rc);
+    if (!ex) return rc;
+    if (!ex->persistent || ex->dataflow)
+      return set_err(QTN_ESTATE, "batch autotuning needs the persistent lockstep or hybrid executor");
+    std::vector<const qtn_network *> list(nets, nets + n);
+    struct Cand {
+      int quarters, order;
+    };
+    std::vector<Cand> cands;
+    for (int order = 0; order < 2; order++)
+      for (int q : {4, 3, 2}) cands.push_back({q, order});
+    auto apply = [&](const Cand &c) {
+      ex->grid_quarters = c.quarters;
+      set_item_order(ex->sched, c.order);
+      drop_graph(ex->rt);
+    };
+    std::vector<double> best(cands.size(), 1e300);
+    std::vector<int> grid(cands.size(), 0);
+    for (size_t i = 0; i < cands.size(); i++) {
+      apply(cands[i]);
+      // the first call captures the graph (or warms up): not timed
+      for (int r = 0; r < 4; r++) {
+        Timer tm;
+        std::vector<double> res;
+        const auto t0 = std::chrono::steady_clock::now();
+        rc = run_exec(*ex, list, d_workspace, bytes, hip_stream, nets[0]->n_streams,
+                      nets[0]->eager, tm, res);
+        const auto t1 = std::chrono::steady_clock::now();
+        if (rc) {
+          apply(cands[0]);
+          return rc;
+        }
+        if (r > 0) best[i] = std::min(best[i], std::chrono::duration<double, std::milli>(t1 - t0).count());
+      }
+      grid[i] = persist_grid(*ex);
+    }
+    // the built configuration unless another is more than 3% faster
+    size_t pick = 0;
+    for (size_t i = 1; i < cands.size(); i++)
+      if (best[i] < best[pick]) pick = i;
+    if (best[0] <= 1.03 * best[pick]) pick = 0;
+    apply(cands[pick]);
+    if (report) {
+      qtn_batch_tune_report r;
+      std::memset(&r, 0, sizeof r);
+      r.n_candidates = (int32_t)cands.size();
+      r.pick = (int32_t)pick;
+      for (size_t i = 0; i < cands.size(); i++) {
+        r.grid_blocks[i] = grid[i];
+        r.item_order[i] = cands[i].order;
+        r.ms[i] = best[i];
+      }
+      *report = r;
+    }
     return QTN_OK;
   } catch (...) {
     return exception_status();

@@ -283,6 +283,52 @@ def test_batch_persistent_and_streams_agree(qtn, orc, gpu):
             n.close()
 
 
+@pytest.mark.parametrize("executor", [0, 5])
+def test_batch_autotune_keeps_results(qtn, orc, gpu, executor):
+    """The batched call's schedule search (persistent grid of all, three
+    quarters or half of the resident blocks; step items costliest cone first
+    or reversed) gives bit-identical results in the configuration it keeps,
+    and on the oracle's values; the launch executors have no such search."""
+    insts = qs.batch_instances(7, 5, 12, 36, (2, 3), d=3)
+    nets = []
+    for it in insts:
+        g, b = it["angles"][0]
+        net = qtn.Network(it["n"], it["edges"], g, b, executor=executor, order_trials=4,
+                          hybrid_width=12 if executor == 5 else 0)
+        net.plan(0)
+        nets.append(net)
+    handles = [n.h for n in nets]
+    total = sum(n.m for n in nets)
+    ws = qtn.workspace(qtn.qtn_batch_workspace(handles))
+    print(f"batch autotune executor={executor}", flush=True)
+    zz0, en0 = qtn.qtn_contract_batch(handles, total, ws)
+    rep = qtn.qtn_autotune_batch(handles, ws)
+    assert rep["n_candidates"] == 6 and 0 <= rep["pick"] < 6
+    assert rep["item_order"] == [0, 0, 0, 1, 1, 1]
+    gb = rep["grid_blocks"]
+    assert gb[0] == gb[3] and gb[0] >= gb[1] >= gb[2] >= 8
+    assert all(g % 8 == 0 for g in gb[1:3]) and all(m > 0 for m in rep["ms"])
+    zz1, en1 = qtn.qtn_contract_batch(handles, total, ws)
+    assert np.array_equal(zz0, zz1) and np.array_equal(en0, en1)
+    off = 0
+    for i, (it, net) in enumerate(zip(insts, nets)):
+        g, b = it["angles"][0]
+        rz, re_ = orc.energy(it["n"], it["edges"], g, b, threads=8)
+        _check(zz1[off:off + net.m], None, en1[i], rz, re_, 0, f"tuned batch {executor}")
+        off += net.m
+    for n in nets:
+        n.close()
+    # launch executors: no persistent grid to tune
+    it = insts[0]
+    net = qtn.Network(it["n"], it["edges"], *it["angles"][0], executor=1)
+    net.plan(0)
+    ws1 = qtn.workspace(qtn.qtn_batch_workspace([net.h]))
+    with pytest.raises(qtn.QtnError) as ei:
+        qtn.qtn_autotune_batch([net.h], ws1)
+    assert "persistent" in str(ei.value)
+    net.close()
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 def test_autotune_keeps_parity(qtn, orc, gpu, prec):
     inst = qs.instance(20, 3, 3, 4)
