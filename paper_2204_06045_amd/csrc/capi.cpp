@@ -1116,7 +1116,6 @@ struct Timer {
   }
 };
 
-// Every launch of one evaluation, on rt.main and the side streams.
 // Blocks of the persistent launch: all that are resident at once, or the
 // tuned share of them (whole rounds over the 8 XCDs, at least 8).
 int persist_grid(const Exec &X) {
@@ -1153,6 +1152,7 @@ void drop_graph(Runtime &rt) {
   rt.graph = nullptr;
 }
 
+// Every launch of one evaluation, on rt.main and the side streams.
 int enqueue(Exec &X, Timer &tm) {
   Schedule &s = X.sched;
   Runtime &rt = X.rt;
