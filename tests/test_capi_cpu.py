@@ -384,6 +384,25 @@ def test_angle_batch_workspace_and_validation(qtn):
     net.close()
 
 
+def test_batch_autotune_validation(qtn):
+    """The batched-call schedule search refuses, before any device work, a
+    NULL list and networks whose batch runs per-group launches or the
+    dataflow executor (no lockstep steps to order)."""
+    from paper_2204_06045_amd import _capi
+    lib = _capi.lib()
+    rc = lib.qtn_autotune_batch(None, 0, ctypes.c_void_p(256), 1 << 20, None, None)
+    assert rc == -1
+    inst = qs.instance(12, 3, 2, 1)
+    g, b = inst["angles"][0]
+    for executor in (1, 3, 4):
+        net = qtn.Network(12, inst["edges"], g, b, executor=executor)
+        net.plan(qtn.QTN_C128)
+        arr = (ctypes.c_void_p * 1)(net.h)
+        rc = lib.qtn_autotune_batch(arr, 1, ctypes.c_void_p(256), 1 << 30, None, None)
+        assert rc == -5 and "lockstep" in qtn.qtn_last_error(), executor
+        net.close()
+
+
 def test_bucket_plan_shapes_and_validation(qtn):
     """Single-bucket plans (no launch): union order, widths, algorithmic
     bytes and flops, mapping choice, and every rejected input."""
