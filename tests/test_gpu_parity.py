@@ -716,7 +716,8 @@ def test_batch64_full_size_against_oracle(qtn, gpu, executor):
     edge, and every graph the oracle evaluated whole by its energy; the
     stored cones cover depths 2, 3 and 4 and a cone of width 30.  Executor 0
     runs every cone in the persistent lockstep launch, executor 5 the cones
-    wider than 20 by per-group launches after it."""
+    wider than 20 by per-group launches after it; after the batched call's
+    schedule search the results are unchanged bit for bit."""
     gd, insts = _batch_golden()
     nets = []
     for it in insts:
@@ -746,6 +747,12 @@ def test_batch64_full_size_against_oracle(qtn, gpu, executor):
         widest = max(widest, max(max(nets[i].bucket_widths(int(k))) for k in ids))
     print(f"batch64: {n_edges} light cones compared, widest planned bucket {widest}", flush=True)
     assert depths == {2, 3, 4} and widest >= 30
+    # the batched call's schedule search (grid, step item order) keeps every
+    # result bit for bit in the configuration it keeps
+    rep = qtn.qtn_autotune_batch(handles, ws)
+    print(f"batch64 schedule search: pick {rep['pick']}, grids {rep['grid_blocks']}", flush=True)
+    zz2, en2 = qtn.qtn_contract_batch(handles, total, ws)
+    assert np.array_equal(zz, zz2) and np.array_equal(en, en2)
     for n in nets:
         n.close()
 
